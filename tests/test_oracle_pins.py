@@ -1,0 +1,302 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test names the passage it follows.  None of them compares the oracle
+with itself through a retyped formula: they use exact integrals, closed-form
+counts, printed table values, identities of the weak form, brute force and
+exact reproduction of polynomial solutions.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hdg
+from oracle.quadrature import segment_rule, triangle_rule
+from paper_2302_10917_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- quadrature
+@pytest.mark.parametrize("k", [2, 4, 6])
+def test_triangle_rule_exact_on_monomials(k):
+    # int_T xi^a eta^b = a! b! / (a+b+2)!  on the unit reference triangle
+    xi, eta, w = triangle_rule(k)
+    for a in range(2 * k):
+        for b in range(2 * k - a):
+            exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+            assert abs(np.sum(w * xi ** a * eta ** b) - exact) <= 1e-15 + 1e-13 * exact
+
+
+@pytest.mark.parametrize("k", [2, 5])
+def test_segment_rule_exact(k):
+    t, w = segment_rule(k)
+    for a in range(2 * k):
+        assert abs(np.sum(w * t ** a) - 1.0 / (a + 1)) < 1e-15
+
+
+# ---------------------------------------------------------------- counts
+def test_paper_3d_dof_tables_follow_c0_macro_spaces():
+    """The printed 3D dof tables are reproduced by C0 piecewise-P_p spaces on
+    macro-elements of m^3 tetrahedra (section 3.2): local dofs
+    N/m^3 * (d+1) * C(mp+3, 3) and global dofs F * C(mp+2, 2) with one face
+    count F per mesh, independent of p (complexity tables 1-2)."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_dof_tables.json")))
+    t = g["global_by_p"]
+    for key, m in (("m1", 1), ("m2", 2)):
+        faces = {v // math.comb(m * p + 2, 2) for v, p in zip(t[key], t["p"])}
+        assert all(v % math.comb(m * p + 2, 2) == 0 for v, p in zip(t[key], t["p"]))
+        assert len(faces) == 1, faces
+    o = g["overall_size_p2"]
+    for key, m in (("m1", 1), ("m2", 2), ("m4", 4)):
+        for ne, loc, glo in zip(o["n_elements"], o["local"][key], o["global"][key]):
+            assert ne % m ** 3 == 0
+            assert loc == ne // m ** 3 * 4 * math.comb(m * 2 + 3, 3)
+            assert glo % math.comb(m * 2 + 2, 2) == 0
+            assert glo // math.comb(m * 2 + 2, 2) <= 4 * ne // m ** 3
+    s = g["macro_size_p2"]
+    for key, m in (("m2", 2), ("m4", 4), ("m8", 8)):
+        for ne, glo in zip(s["n_elements"], s["global"][key]):
+            assert glo % math.comb(m * 2 + 2, 2) == 0
+            assert glo // math.comb(m * 2 + 2, 2) <= 4 * ne // m ** 3
+
+
+@pytest.mark.parametrize("n,r,p", [(2, 1, 2), (3, 0, 1), (4, 2, 3)])
+def test_oracle_counts_match_closed_forms(n, r, p):
+    """2D counts: N = 2 n^2 macros, D = 3n^2 - 2n interior faces (face count
+    of the complexity tables, A_2 = B_2 = 1), 4n boundary faces,
+    Q = C(mp+2, 2) lattice nodes, mp+1 trace nodes per face."""
+    xy, tri = inputs.structured_mesh(n)
+    topo = hdg.Topology(xy, tri, r, p)
+    m = 2 ** r
+    assert topo.n_macro == 2 * n * n
+    assert int(topo.interior.sum()) == 3 * n * n - 2 * n
+    assert int((~topo.interior).sum()) == 4 * n
+    assert all(q == math.comb(m * p + 2, 2) for q in topo.Q)
+    assert topo.n_trace == (3 * n * n - 2 * n) * (m * p + 1)
+    assert len(hdg.sub_triangles(m, p)) == m * m
+
+
+# ---------------------------------------------------------------- blocks
+def _blocks(p=2, r=1, kappa=0.7, beta=(1.0, 0.5), tau=1.0, jitter=0.15):
+    xy, tri = inputs.structured_mesh(2, jitter=jitter, seed=11)
+    o = hdg.Oracle(xy, tri, r, p, kappa, beta, tau)
+    return o, o.blocks(3)
+
+
+def test_H_equals_E_transpose():
+    """Integration by parts inside the C0 macro space: the q-columns of the w
+    rows, -(phi_j, d phi_i)_K + <phi_j n, phi_i>_dK, equal (d phi_j, phi_i)_K,
+    i.e. E^T.  Pins boundary normals and boundary masses against the volume
+    terms of A(U, V) (section 3.2)."""
+    o, b = _blocks()
+    Q = int(o.topo.Q[3])
+    kap = o.kappa[3]
+    assert np.allclose(b.A[2 * Q:, :Q] / kap, b.Ex.T, atol=1e-14)
+    assert np.allclose(b.A[2 * Q:, Q:2 * Q] / kap, b.Ey.T, atol=1e-14)
+
+
+def test_energy_identity():
+    """A(U, V) with V = (kappa q, u) equals kappa ||q||^2 + <(tau - a.n/2) u, u>_dK
+    for divergence-free a (integration by parts of the forms of section 3.2)."""
+    o, b = _blocks(p=3, r=1)
+    Q = int(o.topo.Q[3])
+    kap, tau = o.kappa[3], o.tau
+    rng = np.random.default_rng(0)
+    U = rng.standard_normal(3 * Q)
+    V = np.concatenate([kap * U[:Q], kap * U[Q:2 * Q], U[2 * Q:]])
+    lhs = V @ b.A @ U
+    u = U[2 * Q:]
+    qq = U[:Q] @ b.M @ U[:Q] + U[Q:2 * Q] @ b.M @ U[Q:2 * Q]
+    bnd = 0.0
+    for k in range(3):
+        an = o.beta @ b.normals[k]
+        # <u, u>_{F_k}: G_k restricted to the u trace, via the face mass
+        G = b.G[k]
+        MF = hdg.face_mass(o.topo, int(o.topo.macro_face[3, k]))
+        ut = np.linalg.solve(MF, G.T @ u)       # trace of u on F_k lies in M(F)
+        bnd += (tau - 0.5 * an) * ut @ MF @ ut
+    assert abs(lhs - (kap * qq + bnd)) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_zero_diagonal_in_uu_block_interior_nodes():
+    """For divergence-free a the u-u entry of any node off the macro boundary
+    is -(a phi_i, grad phi_i) = 0: LU needs pivoting."""
+    o, b = _blocks(p=2, r=2)
+    P, Q = int(o.topo.P[3]), int(o.topo.Q[3])
+    lat = o.topo.lattice(3)
+    diag = np.diag(b.A)[2 * Q:]
+    for n, (i, j) in enumerate(lat):
+        if i > 0 and j > 0 and i + j < P:
+            assert abs(diag[n]) < 1e-14
+    assert np.max(np.abs(diag)) > 1e-3
+
+
+def test_face_block_D():
+    """D_F = sum_K <(a.n_K - tau) mu, mu>_F = -2 tau M_F on interior faces
+    (normals of the two sides cancel for constant a)."""
+    o, _ = _blocks()
+    for f in range(o.topo.n_faces):
+        if o.topo.interior[f]:
+            assert np.allclose(o.D_face(f), -2 * o.tau * hdg.face_mass(o.topo, f), atol=1e-15)
+            assert np.all(np.linalg.eigvalsh(-o.D_face(f)) > 0)
+
+
+def test_partition_of_unity_and_nodal_delta():
+    xy, tri = inputs.structured_mesh(1)
+    topo = hdg.Topology(xy, tri, 1, 3)
+    corners, lat = hdg.sub_triangles(2, 3)[3]          # a down sub-triangle
+    idx = hdg.lattice_index(6)
+    nodes = topo.node_xy(0)[idx[lat[:, 0], lat[:, 1]]]
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(0.0, 0.2, size=(7, 2))
+    phi, dx, dy = hdg.lagrange_2d(nodes, 3, nodes[:, 0], nodes[:, 1])
+    assert np.allclose(phi, np.eye(10), atol=1e-12)
+    phi, dx, dy = hdg.lagrange_2d(nodes, 3, pts[:, 0], pts[:, 1])
+    assert np.allclose(phi.sum(1), 1.0) and np.allclose(dx.sum(1), 0.0, atol=1e-10)
+
+
+# ---------------------------------------------------------------- whole method
+@pytest.mark.parametrize("p,r", [(1, 0), (1, 2), (2, 1), (3, 1), (2, 2)])
+def test_polynomial_reproduction(p, r):
+    """u in P_p, q = -grad u, f = a.grad u - kappa lap u: the exact solution
+    lies in the discrete spaces, so consistency of the weak form (section 3.1)
+    and uniqueness give it back to rounding."""
+    xy, tri = inputs.structured_mesh(2, jitter=0.1, seed=2)
+    ex = inputs.polynomial(p, 0.6, (1.0, -0.5), seed=p + 10 * r)
+    o = hdg.Oracle(xy, tri, r, p, 0.6, (1.0, -0.5), 1.0)
+    f, g = o.sample(ex)
+    lam, U, lamD = o.solve(f, g)
+    eu, eq = o.l2_errors(U, ex)
+    assert eu < 1e-11 and eq < 1e-10
+    ut = ex.u(*o.topo.boundary_qp_xy().T)
+    lam_exact = np.concatenate([ex.u(*o.topo.trace_xy(fc).T)
+                                for fc in range(o.topo.n_faces) if o.topo.interior[fc]])
+    assert np.allclose(lam, lam_exact, atol=1e-11)
+    assert np.allclose(g, ut)
+
+
+def test_polynomial_reproduction_nonmatching_levels():
+    """Uneven r per macro: the trace takes the finer level on each face
+    (local refinement paragraph of section 4), so reproduction still holds."""
+    xy, tri = inputs.structured_mesh(3, jitter=0.15, seed=7)
+    r = inputs.random_levels(len(tri), (0, 1, 2), seed=3)
+    ex = inputs.polynomial(2, 0.3, (1.0, -0.5), seed=5)
+    o = hdg.Oracle(xy, tri, r, 2, 0.3, (1.0, -0.5), 1.0)
+    f, g = o.sample(ex)
+    lam, U, _ = o.solve(f, g)
+    eu, eq = o.l2_errors(U, ex)
+    assert eu < 1e-11 and eq < 1e-10
+
+
+@pytest.mark.parametrize("p,r,n", [(2, 1, 2), (3, 1, 2), (1, 2, 2)])
+def test_brute_force_matches_condensation(p, r, n):
+    """Static condensation (eqs. global_problem / local_problem) against a
+    dense solve of the unhybridised block system (eq. D)."""
+    xy, tri = inputs.structured_mesh(n)
+    ex = inputs.sin_sin(1.0, (1.0, 1.0))
+    o = hdg.Oracle(xy, tri, r, p, 1.0, (1.0, 1.0), 1.0)
+    f, g = o.sample(ex)
+    lam, U, _ = o.solve(f, g)
+    lb, Ub, _ = o.brute_force(f, g)
+    scale = max(np.abs(lb).max(), max(np.abs(u).max() for u in Ub))
+    assert np.abs(lam - lb).max() < 1e-12 * scale
+    assert max(np.abs(a - b).max() for a, b in zip(U, Ub)) < 1e-12 * scale
+
+
+def test_apply_matches_assembled_operator():
+    """Steps 1-4 of the matrix-free algorithm (section 3.3.2) against the
+    assembled S, and the D^-1 preconditioned form against D^-1 S."""
+    xy, tri = inputs.structured_mesh(2, jitter=0.1, seed=4)
+    o = hdg.Oracle(xy, tri, 1, 2, 0.5, (0.3, 1.0), 1.0)
+    f, g = o.sample(inputs.exp_sin(0.5, (0.3, 1.0)))
+    S, fhat, _ = o.condensed(f, g)
+    lam = inputs.random_vector(o.topo.n_trace, seed=1)
+    assert np.allclose(o.apply(lam), S @ lam, atol=1e-13)
+    assert np.allclose(o.apply(lam, precondition=True), o.precondition(S @ lam), atol=1e-12)
+
+
+def test_worked_example_structure():
+    """The two-macro example of section 3.3.2: one interface carries the only
+    unknown trace; steps 1-3 are local to each macro and step 4 sums exactly
+    two macro contributions on that face."""
+    xy, tri = inputs.two_macro_mesh()
+    o = hdg.Oracle(xy, tri, 0, 1, 1.0, (1.0, 1.0), 1.0)
+    assert o.topo.n_trace == 2 and int(o.topo.interior.sum()) == 1
+    f_int = int(np.flatnonzero(o.topo.interior)[0])
+    assert len(o.topo.face_incid[f_int]) == 2
+    lam = np.array([0.3, -1.2])
+    c0 = o.macro_contribution(0, lam)[f_int]
+    c1 = o.macro_contribution(1, lam)[f_int]
+    assert np.allclose(o.apply(lam), o.D_face(f_int) @ lam - c0 - c1, atol=1e-15)
+
+
+def test_operator_sparsity_follows_shared_macros():
+    xy, tri = inputs.structured_mesh(3)
+    o = hdg.Oracle(xy, tri, 1, 1, 1.0, (1.0, 0.0), 1.0)
+    f, g = o.sample(inputs.sin_sin(1.0, (1.0, 0.0)))
+    S, _, _ = o.condensed(f, g)
+    S = S.toarray()
+    topo = o.topo
+    owner = {}
+    for fc in range(topo.n_faces):
+        if topo.interior[fc]:
+            for t in range(topo.trace_off[fc], topo.trace_off[fc] + topo.face_nodes[fc]):
+                owner[t] = {K for K, _ in topo.face_incid[fc]}
+    for i in range(topo.n_trace):
+        for j in range(topo.n_trace):
+            if not (owner[i] & owner[j]):
+                assert S[i, j] == 0.0
+
+
+def test_conservation_and_transmission():
+    """Testing eq. pde with w = 1 (macro conservation) and eq. transmission
+    with mu = 1 (weak flux continuity) gives zero residuals."""
+    xy, tri = inputs.structured_mesh(3, jitter=0.1, seed=9)
+    ex = inputs.exp_sin(0.1, (1.0, 0.5))
+    o = hdg.Oracle(xy, tri, 1, 2, 0.1, (1.0, 0.5), 1.0)
+    f, g = o.sample(ex)
+    lam, U, lamD = o.solve(f, g)
+    assert np.abs(o.flux_balance(U, lam, lamD, f)).max() < 1e-12
+    assert np.abs(o.transmission_residual(U, lam)).max() < 1e-12
+
+
+def test_dirichlet_projection_reproduces_trace_space_and_is_l2_optimal():
+    """P o P = P (section 2.3): data already in M(F) is returned unchanged;
+    for general data the projection error is orthogonal to M(F)."""
+    xy, tri = inputs.structured_mesh(2)
+    o = hdg.Oracle(xy, tri, 1, 2, 1.0, (1.0, 1.0), 1.0)
+    topo = o.topo
+    # a piecewise-quadratic (per trace segment) function: a global quadratic in x, y
+    g_fn = lambda x, y: 1.0 + 2 * x - y + 3 * x * y - x * x
+    bxy = topo.boundary_qp_xy()
+    lamD = o.dirichlet_trace(g_fn(bxy[:, 0], bxy[:, 1]))
+    for f, v in lamD.items():
+        nodes = topo.trace_xy(f)
+        assert np.allclose(v, g_fn(nodes[:, 0], nodes[:, 1]), atol=1e-13)
+    lamD = o.dirichlet_trace(np.exp(bxy[:, 0]) * np.sin(3 * bxy[:, 1]))
+    for f, v in lamD.items():
+        t, w = topo.boundary_qp(f)
+        A, B = topo.xy[topo.face_verts[f]]
+        pts = A + np.outer(t, B - A)
+        g = np.exp(pts[:, 0]) * np.sin(3 * pts[:, 1])
+        nF = int(topo.face_nodes[f])
+        t_nodes = np.linspace(0, 1, nF)
+        # evaluate the projection at the sampling points segment by segment
+        vals = np.zeros_like(t)
+        mus = np.zeros((t.size, nF))
+        kb = topo.p + 2
+        for c in range(2 ** int(topo.face_level[f])):
+            lr = np.arange(c * topo.p, c * topo.p + topo.p + 1)
+            sl = slice(c * kb, (c + 1) * kb)
+            mus[sl][:, lr] = hdg.lagrange_1d(t_nodes[lr], t[sl])
+        vals = mus @ v
+        assert np.abs(mus.T @ (w * (g - vals))).max() < 1e-14
+
+
+def test_oracle_rejects_clockwise():
+    xy, tri = inputs.structured_mesh(1)
+    with pytest.raises(ValueError):
+        hdg.Topology(xy, tri[:, ::-1], 1, 1)
