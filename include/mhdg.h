@@ -1,0 +1,198 @@
+/*
+ * mhdg.h -- C ABI of the MI355X macro-element HDG local-problem library.
+ *
+ * The library implements the data-parallel hot path of the macro-element
+ * hybridized DG method for steady advection-diffusion in 2D
+ *   div(a u + kappa q) = f,  q = -grad u  in Omega,  u = g_D on dOmega
+ * (paper section 2.1, eqs. C21/C22) on triangular macro-elements K, each
+ * uniformly subdivided into 4^r triangles carrying continuous piecewise-P_p
+ * q and u (section 3.2), coupled only through the trace lambda on macro faces
+ * with the LDG-H flux a lambda + kappa q + tau (u - lambda) n (section 3.1).
+ *
+ *   factor_local            assemble A_K and LU-factor it in place
+ *                           (section 3.3.2, remark on the in-place LU)
+ *   apply_trace_operator    S lambda = D lambda - sum_K C_K A_K^-1 B_K lambda_K,
+ *                           steps 1-4 of the matrix-free algorithm, optionally
+ *                           left-preconditioned by D^-1 (section 6.1)
+ *   solve                   GMRES on the global problem (eq. global_problem)
+ *   recover_local           A_K U_K = R_K - B_K lambda_K (eq. local_problem)
+ *                           plus the transmission residual C U + D lambda
+ *
+ * Conventions (the same written specification is implemented independently
+ * by the CPU oracle used in the tests):
+ *   - macro lattice node (i, j), i + j <= P = 2^r p, sits at
+ *     X0 + (i/P)(X1 - X0) + (j/P)(X2 - X0), node index j(P+1) - j(j-1)/2 + i;
+ *     Q = (P+1)(P+2)/2 nodes; local unknowns U_K = [q_x(Q), q_y(Q), u(Q)],
+ *     N_K = 3Q;
+ *   - faces are the unique macro edges sorted by (low vertex id, high vertex
+ *     id); a face's level is the max of its macros' levels and it carries
+ *     n_F = 2^{r_F} p + 1 trace nodes at A + t/(n_F-1) (B - A), A the
+ *     lower-id vertex;
+ *   - the global trace vector (length n_trace) lists interior faces in that
+ *     order; boundary faces are Dirichlet and are eliminated;
+ *   - f is given at the macro lattice nodes (macro-contiguous, n_nodes
+ *     values): its interpolant in W(K) is the load;
+ *   - g_D is given at p+2 Gauss-Legendre points on each of the 2^{r_F}
+ *     segments of every boundary face (faces in sorted order, segments and
+ *     points in increasing t): the Dirichlet trace is its L2 projection onto
+ *     M(F) (section 2.3) by that quadrature;
+ *   - local solutions U are returned macro-contiguous (n_local values).
+ *
+ * Memory and ownership: the caller owns every pointer.  Device memory for
+ * factors and scratch comes from caller workspaces sized by mhdg_query();
+ * the handle keeps pointers into the factor workspace from factor_local
+ * until the next factor_local or mhdg_destroy.  The handle itself owns only
+ * host metadata.  Device pointers are plain device addresses (for example
+ * from a torch tensor); "stream" is a hipStream_t passed as void*
+ * (NULL = the null stream).  Calls are asynchronous on that stream, except
+ * setup (host only), factor_local (synchronises once to check pivots) and
+ * solve (synchronises each iteration to run the Arnoldi recurrences).
+ *
+ * Errors: every call returns an mhdg_status; nothing throws across the ABI.
+ * mhdg_last_error() gives a message for the last failing call on a handle.
+ * Handles are not thread-safe.
+ */
+#ifndef MHDG_H_
+#define MHDG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MHDG_OK = 0,
+  MHDG_ERR_INVALID_ARG = 1,   /* NULL pointer, size out of range, bad option  */
+  MHDG_ERR_MESH = 2,          /* clockwise/degenerate triangle, bad connectivity */
+  MHDG_ERR_SINGULAR = 3,      /* an exactly zero pivot in some A_K            */
+  MHDG_ERR_NOT_CONVERGED = 4, /* GMRES hit max_iter before rtol               */
+  MHDG_ERR_WORKSPACE = 5,     /* workspace smaller than mhdg_query reports    */
+  MHDG_ERR_HIP = 6,           /* a HIP runtime call failed                    */
+  MHDG_ERR_STATE = 7          /* e.g. apply before factor_local               */
+} mhdg_status;
+
+typedef enum {
+  MHDG_FP64 = 0,              /* FP64 factors (the plain form)                 */
+  MHDG_FP32 = 1               /* FP32 factors on MFMA, FP64 refinement         */
+} mhdg_precision;
+
+/* flags for apply_trace_operator / local_solve */
+enum {
+  MHDG_PRECONDITION = 1,      /* return D^-1 S lambda instead of S lambda      */
+  MHDG_TRANSPOSE = 2          /* use A_K^-T (adjoint solves)                   */
+};
+
+typedef struct mhdg_mesh mhdg_mesh;
+
+typedef struct {
+  int64_t n_macro;            /* macro-elements                               */
+  int64_t n_faces;            /* all macro faces                              */
+  int64_t n_interior_faces;
+  int64_t n_trace;            /* global unknowns: sum of n_F, interior faces   */
+  int64_t n_nodes;            /* sum over macros of Q                          */
+  int64_t n_local;            /* sum over macros of N_K = 3Q                   */
+  int64_t n_bnd_points;       /* Dirichlet sampling points                     */
+  int32_t p;
+  int32_t max_level;
+  int64_t max_local;          /* max N_K                                       */
+  size_t factor_ws_bytes;     /* workspace for factor_local at this precision  */
+  size_t solve_ws_bytes;      /* workspace for solve at this restart length    */
+} mhdg_sizes;
+
+typedef struct {
+  double rtol;                /* stop when ||D^-1 r|| <= rtol ||D^-1 f^||      */
+  int32_t restart;            /* Krylov length per cycle (>= 1)                */
+  int32_t max_iter;           /* total iterations                              */
+  int32_t zero_guess;         /* 1: start from lambda = 0; 0: use lam on entry */
+} mhdg_solve_opts;
+
+typedef struct {
+  int32_t iterations;
+  int32_t status;             /* mhdg_status of the solve                      */
+  double rel_res_prec;        /* final ||D^-1 (f^ - S lam)|| / ||D^-1 f^||     */
+  double rel_res_true;        /* final ||f^ - S lam|| / ||f^||                 */
+  double t_rhs_ms, t_gmres_ms;
+  int32_t n_applies;
+} mhdg_solve_info;
+
+/* Build the host-side macro mesh: faces, levels, orientation, numbering and
+ * the reference templates.  xy[n_vertices][2] (host, f64), tri[n_macro][3]
+ * (host, i32, counter-clockwise), level[n_macro] (host, i32, 0..5; NULL means
+ * every macro has level `uniform_level`), p in 1..4.
+ * Errors: INVALID_ARG (NULL, p or level out of range, vertex id out of range),
+ * MESH (clockwise/degenerate triangle, an edge shared by more than 2 macros).
+ * On error *out is NULL. */
+mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t n_macro,
+                                  const int32_t* tri, const int32_t* level, int32_t uniform_level,
+                                  int32_t p, mhdg_mesh** out);
+
+/* Sizes and workspace requirements for a precision and GMRES restart length. */
+mhdg_status mhdg_query(const mhdg_mesh* mesh, int32_t precision, int32_t restart, mhdg_sizes* out);
+
+/* Host copies of the sampling points: node_xy[n_nodes][2] (macro lattice
+ * nodes, where f is sampled) and bnd_xy[n_bnd_points][2] (Dirichlet points).
+ * Either pointer may be NULL. */
+mhdg_status mhdg_sample_points(const mhdg_mesh* mesh, double* node_xy, double* bnd_xy);
+
+/* Assemble every A_K (section 3.2 forms: blocks [[M,0,-E^x],[0,M,-E^y],
+ * [kappa H^x, kappa H^y, K]]) and factor it in place with partial row
+ * pivoting (ties to the smallest row), in the requested precision.
+ * kappa: device f64[n_macro]; a = (beta_x, beta_y) constant; tau > 0.
+ * ws: device workspace of at least factor_ws_bytes (mhdg_query with the
+ * same precision); it must stay allocated while the handle uses it.
+ * Errors: INVALID_ARG, WORKSPACE, SINGULAR (first macro in last_error), HIP. */
+mhdg_status mhdg_factor_local(mhdg_mesh* mesh, const double* kappa, double beta_x, double beta_y,
+                              double tau, int32_t precision, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* Copy macro e's assembled (flags=0) local matrix A_e, row-major N_e x N_e,
+ * into dst (device f64).  Re-assembles it from the templates; no factor
+ * state is touched.  For tests of the assembly. */
+mhdg_status mhdg_local_matrix(mhdg_mesh* mesh, int64_t e, double* dst, void* stream);
+
+/* out = S lam, or D^-1 S lam with MHDG_PRECONDITION, with MHDG_TRANSPOSE the
+ * transposed operator S^T lam (or D^-T S^T lam).  lam, out: device
+ * f64[n_trace], must not alias.  Errors: STATE before factor_local. */
+mhdg_status mhdg_apply_trace_operator(mhdg_mesh* mesh, const double* lam, double* out,
+                                      int32_t flags, void* stream);
+
+/* y_K = A_K^-1 x_K (or A_K^-T x_K with MHDG_TRANSPOSE) for every macro with
+ * the stored factors (step 2).  x, y: device f64[n_local], may alias. */
+mhdg_status mhdg_local_solve(mhdg_mesh* mesh, const double* x, double* y, int32_t flags,
+                             void* stream);
+
+/* Right-hand side of the global problem, f^ = -sum_K C_K A_K^-1 R_K, with
+ * R_K built from f (device f64[n_nodes]) and g_D (device f64[n_bnd_points]);
+ * fhat: device f64[n_trace] (D^-1 f^ with MHDG_PRECONDITION).  Keeps R_K in
+ * the factor workspace for recover_local. */
+mhdg_status mhdg_rhs(mhdg_mesh* mesh, const double* f_nodes, const double* g_bnd, double* fhat,
+                     int32_t flags, void* stream);
+
+/* Solve S lam = f^ by GMRES(restart) left-preconditioned with D^-1, all
+ * vector work in FP64 on the device.  Calls mhdg_rhs first.  lam: device
+ * f64[n_trace] (initial guess unless opts->zero_guess, then the solution).
+ * ws: device workspace of at least solve_ws_bytes (mhdg_query with the same
+ * restart).  info (host) may be NULL.  Returns NOT_CONVERGED if max_iter
+ * was reached (lam then holds the last iterate). */
+mhdg_status mhdg_solve(mhdg_mesh* mesh, const double* f_nodes, const double* g_bnd,
+                       const mhdg_solve_opts* opts, double* lam, void* ws, size_t ws_bytes,
+                       mhdg_solve_info* info, void* stream);
+
+/* Local recovery U_K = A_K^-1 (R_K - B_K lam_K) into qu (device
+ * f64[n_local]) and, if flux_res is not NULL, the transmission residual
+ * sum_K C_K U_K + D_F lam_F per interior trace dof (device f64[n_trace]).
+ * Needs mhdg_rhs (or solve) to have run since factor_local. */
+mhdg_status mhdg_recover_local(mhdg_mesh* mesh, const double* lam, double* qu, double* flux_res,
+                               void* stream);
+
+void mhdg_destroy(mhdg_mesh* mesh);
+const char* mhdg_last_error(const mhdg_mesh* mesh);
+const char* mhdg_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHDG_H_ */

@@ -486,6 +486,8 @@ class Oracle:
             vals.append(Se.ravel())
             R = self.local_rhs(K, f_nodal, lamD)
             np.add.at(fhat, gidx, -Ci @ sla.lu_solve(lu, R))
+        if not vals:            # a mesh without interior faces has no trace unknowns
+            return sp.csc_matrix((n, n)), fhat, lamD
         S = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                           shape=(n, n)).tocsc()
         return S, fhat, lamD

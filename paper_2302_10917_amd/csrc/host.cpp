@@ -1,0 +1,928 @@
+// Host side of the macro-element HDG library: mesh setup (faces, levels,
+// orientation, numbering), exact reference templates, workspace layout, the
+// GMRES driver and the C ABI declared in include/mhdg.h.
+#include "../../include/mhdg.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace mhdg;
+
+struct mhdg_mesh {
+  int32_t p = 1;
+  int64_t n_vertices = 0, n_macro = 0;
+  std::vector<double> xy;
+  std::vector<int32_t> tri, level;
+  // faces
+  int64_t n_faces = 0, n_int = 0, n_bnd = 0;
+  std::vector<MacroInfo> macros;
+  std::vector<FaceInfo> faces;
+  std::vector<BndFaceInfo> bfaces;
+  std::vector<int32_t> order;     // macro processing order (largest first)
+  int64_t n_trace = 0, n_nodes = 0, n_local = 0, n_bnd_points = 0, n_slots = 0, n_lamD = 0;
+  int32_t max_level = 0, max_N = 0;
+  // templates
+  Templates T{};
+  std::vector<double> tmpl;       // blob (int tables stored bit-wise in doubles' space)
+  // factor state
+  bool factored = false, have_rhs = false;
+  int precision = MHDG_FP64;
+  double bx = 0, by = 0, tau = 1;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  FactorLayout L{};
+  std::string err;
+};
+
+namespace {
+
+mhdg_status fail(mhdg_mesh* m, mhdg_status s, const std::string& msg) {
+  if (m) m->err = msg;
+  return s;
+}
+
+#define HIP_TRY(m, call)                                                         \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(m, MHDG_ERR_HIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- small dense LA
+// In-place inverse of an n x n row-major matrix by Gauss-Jordan with partial
+// pivoting.  Used only for tiny Vandermonde and 1D mass matrices.
+bool invert(std::vector<double>& a, int n) {
+  std::vector<double> inv(n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r * n + c]) > std::fabs(a[piv * n + c])) piv = r;
+    if (a[piv * n + c] == 0.0) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[c * n + k], a[piv * n + k]);
+        std::swap(inv[c * n + k], inv[piv * n + k]);
+      }
+    double d = 1.0 / a[c * n + c];
+    for (int k = 0; k < n; ++k) { a[c * n + k] *= d; inv[c * n + k] *= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = a[r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) { a[r * n + k] -= f * a[c * n + k]; inv[r * n + k] -= f * inv[c * n + k]; }
+    }
+  }
+  a.swap(inv);
+  return true;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1] by Newton iteration on the
+// Legendre polynomial from its three-term recurrence.
+void gauss_legendre01(int k, std::vector<double>& t, std::vector<double>& w) {
+  t.assign(k, 0.0);
+  w.assign(k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (k + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int n = 2; n <= k; ++n) {
+        double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (k == 1) { p1 = x; p0 = 1.0; }
+      dp = k * (x * p1 - p0) / (x * x - 1.0);
+      double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int n = 2; n <= k; ++n) {
+      double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (k == 1) { p1 = x; p0 = 1.0; }
+    dp = k * (x * p1 - p0) / (x * x - 1.0);
+    // ascending order in t
+    t[k - 1 - i] = 0.5 * (x + 1.0);
+    w[k - 1 - i] = 1.0 / ((1.0 - x * x) * dp * dp);  // = 2/((1-x^2)P'^2) scaled by 1/2
+  }
+}
+
+// 1D Lagrange basis on nodes a/p, a = 0..p, evaluated at tau.
+void lagrange1d(int p, double tau, double* out) {
+  for (int a = 0; a <= p; ++a) {
+    double v = 1.0;
+    for (int b = 0; b <= p; ++b)
+      if (b != a) v *= (tau - double(b) / p) / (double(a - b) / p);
+    out[a] = v;
+  }
+}
+
+// Silvester's product form of the equispaced Lagrange basis: the node with
+// barycentric multi-index (i, j, k), i + j + k = p, has basis
+// R_i(l1) R_j(l2) R_k(l3), R_n(z) = prod_{a<n} (p z - a)/(a + 1).
+static void silvester(int p, int n, double z, double& val, double& der) {
+  val = 1.0;
+  der = 0.0;
+  for (int a = 0; a < n; ++a) {
+    double f = (p * z - a) / (a + 1);
+    der = der * f + val * p / (a + 1);
+    val *= f;
+  }
+}
+
+// Reference P_p triangle matrices on {xi, eta >= 0, xi + eta <= 1} with
+// equispaced nodes (s/p, t/p), t outer: mass Mt[i][j] = (psi_j, psi_i) and
+// Et[k][i][j] = (psi_j, d_k psi_i).  Integrated exactly (degree 2p) by a
+// collapsed Gauss-Legendre product rule with p+2 points per direction
+// (xi = (1+a)(1-b)/4, eta = (1+b)/2, weight (1-b)/8).
+void reference_triangle(int p, std::vector<double>& Mt, std::vector<double> Et[2]) {
+  std::vector<std::pair<int, int>> loc;
+  for (int t = 0; t <= p; ++t)
+    for (int s = 0; s <= p - t; ++s) loc.push_back({s, t});
+  const int n = (int)loc.size();
+  std::vector<double> t01, w01;
+  gauss_legendre01(p + 2, t01, w01);
+  Mt.assign(n * n, 0.0);
+  Et[0].assign(n * n, 0.0);
+  Et[1].assign(n * n, 0.0);
+  std::vector<double> v(n), dx(n), dy(n);
+  for (size_t qa = 0; qa < t01.size(); ++qa)
+    for (size_t qb = 0; qb < t01.size(); ++qb) {
+      const double a = 2 * t01[qa] - 1, b = 2 * t01[qb] - 1;
+      const double xi = (1 + a) * (1 - b) / 4, eta = (1 + b) / 2;
+      const double w = 4 * w01[qa] * w01[qb] * (1 - b) / 8;
+      const double l1 = 1 - xi - eta;
+      for (int m = 0; m < n; ++m) {
+        const int j = loc[m].first, k = loc[m].second, i = p - j - k;
+        double r1, d1, r2, d2, r3, d3;
+        silvester(p, i, l1, r1, d1);
+        silvester(p, j, xi, r2, d2);
+        silvester(p, k, eta, r3, d3);
+        v[m] = r1 * r2 * r3;
+        dx[m] = r1 * d2 * r3 - d1 * r2 * r3;   // d/dxi  = d/dl2 - d/dl1
+        dy[m] = r1 * r2 * d3 - d1 * r2 * r3;   // d/deta = d/dl3 - d/dl1
+      }
+      for (int ii = 0; ii < n; ++ii)
+        for (int jj = 0; jj < n; ++jj) {
+          Mt[ii * n + jj] += w * v[ii] * v[jj];
+          Et[0][ii * n + jj] += w * v[jj] * dx[ii];
+          Et[1][ii * n + jj] += w * v[jj] * dy[ii];
+        }
+    }
+}
+
+// 1D continuous P_p mass matrix on [0,1] split into 2^r equal segments.
+std::vector<double> mass1d(int p, int r) {
+  int m = 1 << r, P = m * p;
+  std::vector<double> t, w;
+  gauss_legendre01(p + 2, t, w);
+  std::vector<double> M((P + 1) * (P + 1), 0.0);
+  std::vector<double> phi(p + 1);
+  for (int c = 0; c < m; ++c)
+    for (size_t q = 0; q < t.size(); ++q) {
+      lagrange1d(p, t[q], phi.data());
+      for (int a = 0; a <= p; ++a)
+        for (int b = 0; b <= p; ++b) M[(c * p + a) * (P + 1) + c * p + b] += w[q] / m * phi[a] * phi[b];
+    }
+  return M;
+}
+
+// Prolongation of the level-rc continuous P_p space to level rf >= rc:
+// Pi[l][s] = phi_s(t_l), exact for piecewise polynomials.
+std::vector<double> prolong1d(int p, int rc, int rf) {
+  int mc = 1 << rc, Pc = mc * p, Pf = (1 << rf) * p;
+  std::vector<double> Pi((Pf + 1) * (Pc + 1), 0.0);
+  std::vector<double> phi(p + 1);
+  for (int l = 0; l <= Pf; ++l) {
+    double t = double(l) / Pf;
+    int c = std::min(int(std::floor(t * mc)), mc - 1);
+    double tau = t * mc - c;
+    lagrange1d(p, tau, phi.data());
+    for (int a = 0; a <= p; ++a) Pi[l * (Pc + 1) + c * p + a] = phi[a];
+  }
+  return Pi;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- templates
+static void build_templates(mhdg_mesh* M) {
+  const int p = M->p;
+  std::vector<bool> present(kMaxLevel + 1, false);
+  for (auto r : M->level) present[r] = true;
+  // faces may carry levels present only through max()
+  for (auto& f : M->faces) present[f.level] = true;
+  std::vector<double>& B = M->tmpl;
+  B.clear();
+  auto take = [&](size_t n) { size_t o = B.size(); B.resize(o + ((n + 31) / 32) * 32, 0.0); return (int64_t)o; };
+  std::vector<double> Mt, Et[2];
+  reference_triangle(p, Mt, Et);
+  const int nl = (p + 1) * (p + 2) / 2;
+  Templates& T = M->T;
+  T.p = p;
+  for (int r = 0; r <= kMaxLevel; ++r) {
+    LevelTemplates& L = T.lev[r];
+    L.present = present[r] ? 1 : 0;
+    const int m = 1 << r, P = m * p, Q = (P + 1) * (P + 2) / 2;
+    L.P = P; L.Q = Q; L.N = 3 * Q;
+    for (int k = 0; k <= kMaxLevel; ++k) L.T1[k] = -1;
+    if (!present[r]) continue;
+    auto idx = [&](int i, int j) { return j * (P + 1) - j * (j - 1) / 2 + i; };
+    L.Mhat = take(size_t(Q) * Q);
+    L.E0 = take(size_t(Q) * Q);
+    L.E1 = take(size_t(Q) * Q);
+    double* Mh = &B[L.Mhat];
+    double* E0 = &B[L.E0];
+    double* E1 = &B[L.E1];
+    std::vector<std::pair<int, int>> loc;
+    for (int t = 0; t <= p; ++t)
+      for (int s = 0; s <= p - t; ++s) loc.push_back({s, t});
+    // up sub-triangles: node (s,t) -> (ap+s, bp+t); map x = (a + xi)/m
+    // down sub-triangles: node (s,t) -> ((a+1)p-s, (b+1)p-t); map x = (a+1 - xi)/m
+    for (int pass = 0; pass < 2; ++pass) {
+      int bmax = pass == 0 ? m : m - 1;
+      for (int b = 0; b < bmax; ++b)
+        for (int a = 0; a < bmax - b; ++a) {
+          std::vector<int> g(nl);
+          for (int n = 0; n < nl; ++n) {
+            int s = loc[n].first, t = loc[n].second;
+            g[n] = pass == 0 ? idx(a * p + s, b * p + t) : idx((a + 1) * p - s, (b + 1) * p - t);
+          }
+          const double sm = 1.0 / (double(m) * m), se = (pass == 0 ? 1.0 : -1.0) / m;
+          for (int i = 0; i < nl; ++i)
+            for (int j = 0; j < nl; ++j) {
+              size_t o = size_t(g[i]) * Q + g[j];
+              Mh[o] += sm * Mt[i * nl + j];
+              E0[o] += se * Et[0][i * nl + j];
+              E1[o] += se * Et[1][i * nl + j];
+            }
+        }
+    }
+    // 1D masses
+    std::vector<double> M1 = mass1d(p, r), M1i = M1;
+    invert(M1i, P + 1);
+    L.M1 = take(M1.size());
+    std::copy(M1.begin(), M1.end(), B.begin() + L.M1);
+    L.M1inv = take(M1i.size());
+    std::copy(M1i.begin(), M1i.end(), B.begin() + L.M1inv);
+    // edge tables (int32 stored in the double blob)
+    L.edge_node = take((3 * (P + 1) + 1) / 2);
+    int32_t* en = reinterpret_cast<int32_t*>(&B[L.edge_node]);
+    for (int s = 0; s <= P; ++s) {
+      en[0 * (P + 1) + s] = idx(s, 0);          // edge 0: j = 0, from X0 to X1
+      en[1 * (P + 1) + s] = idx(P - s, s);      // edge 1: i + j = P, from X1 to X2
+      en[2 * (P + 1) + s] = idx(0, P - s);      // edge 2: i = 0, from X2 to X0
+    }
+    L.node_epos = take((3 * Q + 1) / 2);
+    int32_t* ep = reinterpret_cast<int32_t*>(&B[L.node_epos]);
+    for (int j = 0; j <= P; ++j)
+      for (int i = 0; i <= P - j; ++i) {
+        int n = idx(i, j);
+        ep[3 * n + 0] = j == 0 ? i : -1;
+        ep[3 * n + 1] = i + j == P ? j : -1;
+        ep[3 * n + 2] = i == 0 ? P - j : -1;
+      }
+  }
+  // coupling of a level-r macro edge with a level-rf trace: T1 = (M1(rf) Pi)^T
+  for (int r = 0; r <= kMaxLevel; ++r) {
+    if (!present[r]) continue;
+    for (int rf = r; rf <= kMaxLevel; ++rf) {
+      if (!present[rf]) continue;
+      const int Pc = (1 << r) * p, Pf = (1 << rf) * p;
+      std::vector<double> M1f = mass1d(p, rf), Pi = prolong1d(p, r, rf);
+      int64_t o = take(size_t(Pc + 1) * (Pf + 1));
+      T.lev[r].T1[rf] = o;
+      for (int s = 0; s <= Pc; ++s)
+        for (int l = 0; l <= Pf; ++l) {
+          double v = 0;
+          for (int l2 = 0; l2 <= Pf; ++l2) v += M1f[l * (Pf + 1) + l2] * Pi[l2 * (Pc + 1) + s];
+          B[o + size_t(s) * (Pf + 1) + l] = v;
+        }
+    }
+  }
+  // Dirichlet sampling basis: trace basis at kb Gauss-Legendre points of a segment
+  T.kb = p + 2;
+  std::vector<double> t, w;
+  gauss_legendre01(T.kb, t, w);
+  T.dir_basis = take(size_t(p + 1) * T.kb);
+  T.dir_w = take(T.kb);
+  std::vector<double> phi(p + 1);
+  for (int q = 0; q < T.kb; ++q) {
+    lagrange1d(p, t[q], phi.data());
+    for (int a = 0; a <= p; ++a) B[T.dir_basis + a * T.kb + q] = phi[a];
+    B[T.dir_w + q] = w[q];
+  }
+}
+
+// ---------------------------------------------------------------- layout
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
+  FactorLayout L{};
+  size_t o = 0;
+  L.meta = o;   o = align_up(o + M->macros.size() * sizeof(MacroInfo));
+  L.faces = o;  o = align_up(o + M->faces.size() * sizeof(FaceInfo));
+  L.bfaces = o; o = align_up(o + M->bfaces.size() * sizeof(BndFaceInfo));
+  L.tmpl = o;   o = align_up(o + M->tmpl.size() * sizeof(double));
+  L.perm = o;   o = align_up(o + size_t(M->n_local) * sizeof(int32_t));
+  L.status = o; o = align_up(o + size_t(M->n_macro) * sizeof(int32_t));
+  L.R = o;      o = align_up(o + size_t(M->n_local) * sizeof(double));
+  L.slots = o;  o = align_up(o + size_t(M->n_slots) * sizeof(double));
+  L.lamD = o;   o = align_up(o + size_t(std::max<int64_t>(M->n_lamD, 1)) * sizeof(double));
+  L.factors = o;
+  size_t es = precision == MHDG_FP32 ? 4 : 8;
+  size_t nf = 0;
+  for (auto& mi : M->macros) nf += size_t(mi.N) * mi.N;
+  (void)es;
+  o = align_up(o + nf * es);
+  L.total = o;
+  return L;
+}
+
+static size_t solve_bytes(const mhdg_mesh* M, int restart) {
+  size_t n = size_t(M->n_trace);
+  size_t vecs = size_t(restart + 1) + 6;  // Krylov basis + w, r, fhat, pfhat, tmp, x0
+  size_t nblk = size_t(dots_nblk(M->n_trace));
+  return align_up(vecs * align_up(n * sizeof(double))) +
+         align_up(nblk * size_t(restart + 2) * sizeof(double)) + align_up(size_t(restart + 2) * 8) * 2;
+}
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+const char* mhdg_status_string(int32_t s) {
+  switch (s) {
+    case MHDG_OK: return "ok";
+    case MHDG_ERR_INVALID_ARG: return "invalid argument";
+    case MHDG_ERR_MESH: return "invalid mesh";
+    case MHDG_ERR_SINGULAR: return "singular local matrix";
+    case MHDG_ERR_NOT_CONVERGED: return "not converged";
+    case MHDG_ERR_WORKSPACE: return "workspace too small";
+    case MHDG_ERR_HIP: return "HIP error";
+    case MHDG_ERR_STATE: return "invalid call order";
+  }
+  return "unknown status";
+}
+
+const char* mhdg_last_error(const mhdg_mesh* m) { return m ? m->err.c_str() : "null handle"; }
+
+void mhdg_destroy(mhdg_mesh* m) { delete m; }
+
+mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t n_macro,
+                                  const int32_t* tri, const int32_t* level, int32_t uniform_level,
+                                  int32_t p, mhdg_mesh** out) {
+  if (!out) return MHDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!xy || !tri || n_vertices < 3 || n_macro < 1 || p < 1 || p > 4) return MHDG_ERR_INVALID_ARG;
+  if (!level && (uniform_level < 0 || uniform_level > kMaxLevel)) return MHDG_ERR_INVALID_ARG;
+  if (n_macro > (int64_t(1) << 28)) return MHDG_ERR_INVALID_ARG;
+  mhdg_mesh* M = new mhdg_mesh();
+  M->p = p;
+  M->n_vertices = n_vertices;
+  M->n_macro = n_macro;
+  M->xy.assign(xy, xy + 2 * n_vertices);
+  M->tri.assign(tri, tri + 3 * n_macro);
+  M->level.resize(n_macro);
+  for (int64_t e = 0; e < n_macro; ++e) {
+    int r = level ? level[e] : uniform_level;
+    if (r < 0 || r > kMaxLevel) { delete M; return MHDG_ERR_INVALID_ARG; }
+    M->level[e] = r;
+    for (int k = 0; k < 3; ++k)
+      if (tri[3 * e + k] < 0 || tri[3 * e + k] >= n_vertices) { delete M; return MHDG_ERR_INVALID_ARG; }
+    M->max_level = std::max(M->max_level, r);
+  }
+  // orientation / degeneracy
+  M->macros.resize(n_macro);
+  for (int64_t e = 0; e < n_macro; ++e) {
+    const int32_t* t = &tri[3 * e];
+    if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2]) { delete M; return MHDG_ERR_MESH; }
+    double x0 = xy[2 * t[0]], y0 = xy[2 * t[0] + 1];
+    double e1x = xy[2 * t[1]] - x0, e1y = xy[2 * t[1] + 1] - y0;
+    double e2x = xy[2 * t[2]] - x0, e2y = xy[2 * t[2] + 1] - y0;
+    double det = e1x * e2y - e1y * e2x;
+    if (!(det > 0.0) || !std::isfinite(det)) { delete M; return MHDG_ERR_MESH; }
+    MacroInfo& mi = M->macros[e];
+    std::memset(&mi, 0, sizeof(mi));
+    // J = [e1 e2] (columns); G = J^-1
+    mi.G[0] = e2y / det;  mi.G[1] = -e2x / det;
+    mi.G[2] = -e1y / det; mi.G[3] = e1x / det;
+    mi.dJ = det;
+    for (int k = 0; k < 3; ++k) {
+      int a = t[k], b = t[(k + 1) % 3];
+      double tx = xy[2 * b] - xy[2 * a], ty = xy[2 * b + 1] - xy[2 * a + 1];
+      double Lk = std::sqrt(tx * tx + ty * ty);
+      mi.len[k] = Lk;
+      mi.nrm[2 * k] = ty / Lk;
+      mi.nrm[2 * k + 1] = -tx / Lk;
+    }
+    int r = M->level[e];
+    mi.level = r;
+    mi.P = (1 << r) * p;
+    mi.Q = (mi.P + 1) * (mi.P + 2) / 2;
+    mi.N = 3 * mi.Q;
+    M->max_N = std::max(M->max_N, mi.N);
+  }
+  // faces: unique edges sorted by (low, high)
+  std::vector<std::array<int64_t, 4>> edges;  // low, high, macro, k
+  edges.reserve(3 * n_macro);
+  for (int64_t e = 0; e < n_macro; ++e)
+    for (int k = 0; k < 3; ++k) {
+      int64_t a = tri[3 * e + k], b = tri[3 * e + (k + 1) % 3];
+      edges.push_back({std::min(a, b), std::max(a, b), e, k});
+    }
+  std::sort(edges.begin(), edges.end());
+  struct FaceTmp { int64_t lo, hi; int64_t mac[2]; int k[2]; int cnt; };
+  std::vector<FaceTmp> ft;
+  for (size_t i = 0; i < edges.size();) {
+    size_t j = i;
+    while (j < edges.size() && edges[j][0] == edges[i][0] && edges[j][1] == edges[i][1]) ++j;
+    if (j - i > 2) { delete M; return MHDG_ERR_MESH; }
+    FaceTmp f{edges[i][0], edges[i][1], {edges[i][2], -1}, {int(edges[i][3]), -1}, int(j - i)};
+    if (j - i == 2) {
+      f.mac[1] = edges[i + 1][2];
+      f.k[1] = int(edges[i + 1][3]);
+      // a shared edge must be traversed in opposite directions (conforming, consistently oriented)
+      int64_t e0 = f.mac[0], e1 = f.mac[1];
+      int d0 = tri[3 * e0 + f.k[0]] < tri[3 * e0 + (f.k[0] + 1) % 3];
+      int d1 = tri[3 * e1 + f.k[1]] < tri[3 * e1 + (f.k[1] + 1) % 3];
+      if (d0 == d1) { delete M; return MHDG_ERR_MESH; }
+    }
+    ft.push_back(f);
+    i = j;
+  }
+  M->n_faces = (int64_t)ft.size();
+  int64_t tr = 0, gb = 0, ld = 0;
+  for (size_t fi = 0; fi < ft.size(); ++fi) {
+    FaceTmp& f = ft[fi];
+    int lev = M->level[f.mac[0]];
+    if (f.cnt == 2) lev = std::max(lev, M->level[f.mac[1]]);
+    int nF = (1 << lev) * p + 1;
+    double dx = xy[2 * f.hi] - xy[2 * f.lo], dy = xy[2 * f.hi + 1] - xy[2 * f.lo + 1];
+    double len = std::sqrt(dx * dx + dy * dy);
+    for (int s = 0; s < f.cnt; ++s) {
+      MacroInfo& mi = M->macros[f.mac[s]];
+      int k = f.k[s];
+      mi.face[k] = (int32_t)fi;
+      mi.orient[k] = tri[3 * f.mac[s] + k] < tri[3 * f.mac[s] + (k + 1) % 3] ? 1 : -1;
+      mi.flevel[k] = lev;
+      mi.tr_off[k] = -1;
+      mi.bnd_face[k] = -1;
+      mi.slot_off[k] = -1;
+    }
+    if (f.cnt == 2) {
+      FaceInfo fi2{};
+      fi2.len = len;
+      fi2.tr_off = (int32_t)tr;
+      fi2.nF = nF;
+      fi2.level = lev;
+      int a = f.mac[0] < f.mac[1] ? 0 : 1;
+      for (int s = 0; s < 2; ++s) {
+        MacroInfo& mi = M->macros[f.mac[s]];
+        mi.tr_off[f.k[s]] = (int32_t)tr;
+      }
+      // slots assigned below; remember macro/edge pairs
+      fi2.slot[0] = f.mac[a] * 3 + f.k[a];
+      fi2.slot[1] = f.mac[1 - a] * 3 + f.k[1 - a];
+      M->faces.push_back(fi2);
+      tr += nF;
+    } else {
+      BndFaceInfo b{};
+      b.len = len;
+      b.g_off = gb;
+      b.lam_off = ld;
+      b.nF = nF;
+      b.level = lev;
+      M->macros[f.mac[0]].bnd_face[f.k[0]] = (int32_t)M->bfaces.size();
+      M->bfaces.push_back(b);
+      gb += int64_t(1 << lev) * (p + 2);
+      ld += nF;
+    }
+  }
+  M->n_int = (int64_t)M->faces.size();
+  M->n_bnd = (int64_t)M->bfaces.size();
+  M->n_trace = tr;
+  M->n_bnd_points = gb;
+  M->n_lamD = ld;
+  // offsets
+  int64_t lo = 0, no = 0, so = 0;
+  for (int64_t e = 0; e < n_macro; ++e) {
+    MacroInfo& mi = M->macros[e];
+    mi.loc_off = lo;
+    mi.node_off = no;
+    lo += mi.N;
+    no += mi.Q;
+    for (int k = 0; k < 3; ++k)
+      if (mi.tr_off[k] >= 0) {
+        mi.slot_off[k] = so;
+        so += (1 << mi.flevel[k]) * p + 1;
+      }
+  }
+  M->n_local = lo;
+  M->n_nodes = no;
+  M->n_slots = so;
+  for (auto& f : M->faces) {
+    int64_t e0 = f.slot[0] / 3, k0 = f.slot[0] % 3, e1 = f.slot[1] / 3, k1 = f.slot[1] % 3;
+    f.slot[0] = M->macros[e0].slot_off[k0];
+    f.slot[1] = M->macros[e1].slot_off[k1];
+  }
+  // processing order: largest local size first (stable), factor offsets in that order
+  M->order.resize(n_macro);
+  for (int64_t e = 0; e < n_macro; ++e) M->order[e] = (int32_t)e;
+  std::stable_sort(M->order.begin(), M->order.end(),
+                   [&](int32_t a, int32_t b) { return M->macros[a].N > M->macros[b].N; });
+  int64_t fo = 0;
+  for (int64_t e = 0; e < n_macro; ++e) {
+    MacroInfo& mi = M->macros[e];
+    mi.fac_off = fo;
+    fo += int64_t(mi.N) * mi.N;
+    fo = (fo + 63) & ~int64_t(63);
+  }
+  build_templates(M);
+  *out = M;
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, mhdg_sizes* out) {
+  if (!M || !out || restart < 1 || (precision != MHDG_FP64 && precision != MHDG_FP32))
+    return MHDG_ERR_INVALID_ARG;
+  out->n_macro = M->n_macro;
+  out->n_faces = M->n_faces;
+  out->n_interior_faces = M->n_int;
+  out->n_trace = M->n_trace;
+  out->n_nodes = M->n_nodes;
+  out->n_local = M->n_local;
+  out->n_bnd_points = M->n_bnd_points;
+  out->p = M->p;
+  out->max_level = M->max_level;
+  out->max_local = M->max_N;
+  FactorLayout L = factor_layout(M, precision);
+  // factor block offsets are padded to 64 elements per macro
+  size_t es = precision == MHDG_FP32 ? 4 : 8;
+  const MacroInfo& last = M->macros.back();
+  size_t nf = size_t(last.fac_off) + size_t(last.N) * last.N;
+  out->factor_ws_bytes = align_up(L.factors + nf * es);
+  out->solve_ws_bytes = solve_bytes(M, restart);
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_sample_points(const mhdg_mesh* M, double* node_xy, double* bnd_xy) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (node_xy) {
+    int64_t o = 0;
+    for (int64_t e = 0; e < M->n_macro; ++e) {
+      const MacroInfo& mi = M->macros[e];
+      const int32_t* t = &M->tri[3 * e];
+      double x0 = M->xy[2 * t[0]], y0 = M->xy[2 * t[0] + 1];
+      double e1x = M->xy[2 * t[1]] - x0, e1y = M->xy[2 * t[1] + 1] - y0;
+      double e2x = M->xy[2 * t[2]] - x0, e2y = M->xy[2 * t[2] + 1] - y0;
+      for (int j = 0; j <= mi.P; ++j)
+        for (int i = 0; i <= mi.P - j; ++i) {
+          double a = double(i) / mi.P, b = double(j) / mi.P;
+          node_xy[2 * o] = x0 + a * e1x + b * e2x;
+          node_xy[2 * o + 1] = y0 + a * e1y + b * e2y;
+          ++o;
+        }
+    }
+  }
+  if (bnd_xy) {
+    std::vector<double> t, w;
+    gauss_legendre01(M->p + 2, t, w);
+    // boundary faces in sorted order = order of bfaces
+    std::vector<std::pair<int64_t, int64_t>> fv(M->n_faces);
+    for (int64_t e = 0; e < M->n_macro; ++e)
+      for (int k = 0; k < 3; ++k) {
+        int64_t a = M->tri[3 * e + k], b = M->tri[3 * e + (k + 1) % 3];
+        fv[M->macros[e].face[k]] = {std::min(a, b), std::max(a, b)};
+      }
+    std::vector<int32_t> bface_of(M->n_faces, -1);
+    for (int64_t e = 0; e < M->n_macro; ++e)
+      for (int k = 0; k < 3; ++k)
+        if (M->macros[e].bnd_face[k] >= 0) bface_of[M->macros[e].face[k]] = M->macros[e].bnd_face[k];
+    for (int64_t f = 0; f < M->n_faces; ++f) {
+      if (bface_of[f] < 0) continue;
+      const BndFaceInfo& b = M->bfaces[bface_of[f]];
+      double ax = M->xy[2 * fv[f].first], ay = M->xy[2 * fv[f].first + 1];
+      double bx = M->xy[2 * fv[f].second], by = M->xy[2 * fv[f].second + 1];
+      int npc = 1 << b.level;
+      int64_t o = b.g_off;
+      for (int c = 0; c < npc; ++c)
+        for (size_t q = 0; q < t.size(); ++q) {
+          double s = (c + t[q]) / npc;
+          bnd_xy[2 * o] = ax + s * (bx - ax);
+          bnd_xy[2 * o + 1] = ay + s * (by - ay);
+          ++o;
+        }
+    }
+  }
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_factor_local(mhdg_mesh* M, const double* kappa, double beta_x, double beta_y,
+                              double tau, int32_t precision, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!kappa || !ws || !(tau > 0.0) || !std::isfinite(beta_x) || !std::isfinite(beta_y))
+    return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: null pointer or tau <= 0");
+  if (precision != MHDG_FP64 && precision != MHDG_FP32)
+    return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: unknown precision");
+  mhdg_sizes sz;
+  mhdg_query(M, precision, 1, &sz);
+  if (ws_bytes < sz.factor_ws_bytes)
+    return fail(M, MHDG_ERR_WORKSPACE, "factor_local: workspace smaller than mhdg_query reports");
+  hipStream_t s = (hipStream_t)stream;
+  M->factored = false;
+  M->have_rhs = false;
+  M->precision = precision;
+  M->bx = beta_x; M->by = beta_y; M->tau = tau;
+  M->ws = (char*)ws;
+  M->ws_bytes = ws_bytes;
+  M->L = factor_layout(M, precision);
+  FactorLayout& L = M->L;
+  char* w = M->ws;
+  HIP_TRY(M, hipMemcpyAsync(w + L.meta, M->macros.data(), M->macros.size() * sizeof(MacroInfo),
+                            hipMemcpyHostToDevice, s));
+  if (!M->faces.empty())
+    HIP_TRY(M, hipMemcpyAsync(w + L.faces, M->faces.data(), M->faces.size() * sizeof(FaceInfo),
+                              hipMemcpyHostToDevice, s));
+  if (!M->bfaces.empty())
+    HIP_TRY(M, hipMemcpyAsync(w + L.bfaces, M->bfaces.data(), M->bfaces.size() * sizeof(BndFaceInfo),
+                              hipMemcpyHostToDevice, s));
+  HIP_TRY(M, hipMemcpyAsync(w + L.tmpl, M->tmpl.data(), M->tmpl.size() * sizeof(double),
+                            hipMemcpyHostToDevice, s));
+  // the macro order lives after the permutation vector region: reuse status region size n_macro
+  MacroInfo* info = (MacroInfo*)(w + L.meta);
+  HIP_TRY(M, launch_set_kappa(info, kappa, M->n_macro, s));
+  HIP_TRY(M, launch_assemble(w + L.factors, precision, info, nullptr, M->n_macro,
+                             (const double*)(w + L.tmpl), M->T, beta_x, beta_y, tau, s));
+  HIP_TRY(M, launch_lu(w + L.factors, precision, info, nullptr, M->n_macro, M->max_N,
+                       (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+  std::vector<int32_t> st(M->n_macro);
+  HIP_TRY(M, hipMemcpyAsync(st.data(), w + L.status, st.size() * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(M, hipStreamSynchronize(s));
+  for (int64_t e = 0; e < M->n_macro; ++e)
+    if (st[e] != 0) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "factor_local: zero pivot in macro %lld at column %d",
+               (long long)e, st[e] - 1);
+      return fail(M, MHDG_ERR_SINGULAR, buf);
+    }
+  M->factored = true;
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_local_matrix(mhdg_mesh* M, int64_t e, double* dst, void* stream) {
+  if (!M || !dst || e < 0 || e >= M->n_macro) return MHDG_ERR_INVALID_ARG;
+  if (!M->ws) return fail(M, MHDG_ERR_STATE, "local_matrix: call factor_local first");
+  FactorLayout& L = M->L;
+  HIP_TRY(M, launch_extract_matrix((const MacroInfo*)(M->ws + L.meta), e,
+                                   (const double*)(M->ws + L.tmpl), M->T, M->bx, M->by, M->tau,
+                                   dst, (hipStream_t)stream));
+  return MHDG_OK;
+}
+
+static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const double* lam,
+                                   const double* xin, double* yout, hipStream_t s) {
+  FactorLayout& L = M->L;
+  char* w = M->ws;
+  HIP_TRY(M, launch_macro_solve(mode, transpose, w + L.factors, M->precision,
+                                (const MacroInfo*)(w + L.meta), nullptr, M->n_macro, M->max_N,
+                                (const int32_t*)(w + L.perm), (const double*)(w + L.tmpl), M->T,
+                                M->bx, M->by, M->tau, lam, xin, yout, (double*)(w + L.slots), s));
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
+                                      void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->factored) return fail(M, MHDG_ERR_STATE, "apply: call factor_local first");
+  if ((!lam || !out) && M->n_trace > 0) return fail(M, MHDG_ERR_INVALID_ARG, "apply: null vector");
+  if (lam == out && M->n_trace > 0) return fail(M, MHDG_ERR_INVALID_ARG, "apply: lam and out alias");
+  if (flags & MHDG_TRANSPOSE) return fail(M, MHDG_ERR_INVALID_ARG, "apply: transpose not built");
+  if (M->n_trace == 0) return MHDG_OK;
+  hipStream_t s = (hipStream_t)stream;
+  mhdg_status st = run_macro_solve(M, MODE_APPLY, 0, lam, nullptr, nullptr, s);
+  if (st) return st;
+  FactorLayout& L = M->L;
+  HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
+                                 (const FaceInfo*)(M->ws + L.faces), M->n_int,
+                                 (const double*)(M->ws + L.tmpl), M->T, M->tau, lam,
+                                 (const double*)(M->ws + L.slots), out, s));
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_local_solve(mhdg_mesh* M, const double* x, double* y, int32_t flags, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->factored) return fail(M, MHDG_ERR_STATE, "local_solve: call factor_local first");
+  if (!x || !y) return fail(M, MHDG_ERR_INVALID_ARG, "local_solve: null vector");
+  if (flags & MHDG_TRANSPOSE) return fail(M, MHDG_ERR_INVALID_ARG, "local_solve: transpose not built");
+  return run_macro_solve(M, MODE_LOCAL, 0, nullptr, x, y, (hipStream_t)stream);
+}
+
+mhdg_status mhdg_rhs(mhdg_mesh* M, const double* f_nodes, const double* g_bnd, double* fhat,
+                     int32_t flags, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->factored) return fail(M, MHDG_ERR_STATE, "rhs: call factor_local first");
+  if (!f_nodes || (!g_bnd && M->n_bnd_points > 0) || (!fhat && M->n_trace > 0))
+    return fail(M, MHDG_ERR_INVALID_ARG, "rhs: null vector");
+  hipStream_t s = (hipStream_t)stream;
+  FactorLayout& L = M->L;
+  char* w = M->ws;
+  const double* tm = (const double*)(w + L.tmpl);
+  if (M->n_bnd > 0)
+    HIP_TRY(M, launch_dirichlet((const BndFaceInfo*)(w + L.bfaces), M->n_bnd, tm, M->T, g_bnd,
+                                (double*)(w + L.lamD), s));
+  HIP_TRY(M, launch_local_rhs((const MacroInfo*)(w + L.meta), M->n_macro,
+                              (const BndFaceInfo*)(w + L.bfaces), tm, M->T, f_nodes,
+                              (const double*)(w + L.lamD), M->bx, M->by, M->tau,
+                              (double*)(w + L.R), s));
+  M->have_rhs = true;
+  if (M->n_trace == 0) return MHDG_OK;
+  mhdg_status st = run_macro_solve(M, MODE_RHS, 0, nullptr, (const double*)(w + L.R), nullptr, s);
+  if (st) return st;
+  HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_RHS : FACE_RHS,
+                                 (const FaceInfo*)(w + L.faces), M->n_int, tm, M->T, M->tau,
+                                 nullptr, (const double*)(w + L.slots), fhat, s));
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_recover_local(mhdg_mesh* M, const double* lam, double* qu, double* flux_res,
+                               void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->factored || !M->have_rhs)
+    return fail(M, MHDG_ERR_STATE, "recover_local: call factor_local and rhs/solve first");
+  if (!qu || (!lam && M->n_trace > 0)) return fail(M, MHDG_ERR_INVALID_ARG, "recover_local: null vector");
+  hipStream_t s = (hipStream_t)stream;
+  FactorLayout& L = M->L;
+  mhdg_status st = run_macro_solve(M, MODE_RECOVER, 0, lam, (const double*)(M->ws + L.R), qu, s);
+  if (st) return st;
+  if (flux_res && M->n_trace > 0)
+    HIP_TRY(M, launch_face_combine(FACE_RESID, (const FaceInfo*)(M->ws + L.faces), M->n_int,
+                                   (const double*)(M->ws + L.tmpl), M->T, M->tau, lam,
+                                   (const double*)(M->ws + L.slots), flux_res, s));
+  return MHDG_OK;
+}
+
+// ---------------------------------------------------------------- GMRES
+// Left-preconditioned restarted GMRES with classical Gram-Schmidt applied
+// twice (CGS2); all vectors and inner products in FP64 on the device, the
+// (restart+1) x restart Hessenberg least-squares problem by Givens rotations
+// on the host.
+mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
+                       const mhdg_solve_opts* o, double* lam, void* ws, size_t ws_bytes,
+                       mhdg_solve_info* info, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!o || !lam || !ws || o->restart < 1 || o->max_iter < 0 || !(o->rtol >= 0.0))
+    return fail(M, MHDG_ERR_INVALID_ARG, "solve: bad options or null pointer");
+  if (!M->factored) return fail(M, MHDG_ERR_STATE, "solve: call factor_local first");
+  if (ws_bytes < solve_bytes(M, o->restart))
+    return fail(M, MHDG_ERR_WORKSPACE, "solve: workspace smaller than mhdg_query reports");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = M->n_trace;
+  const int R = o->restart;
+  auto t0 = std::chrono::steady_clock::now();
+  char* w = (char*)ws;
+  size_t vb = align_up(size_t(n) * sizeof(double));
+  double* V = (double*)w;                         // (R+1) vectors, leading dim vb/8
+  const int64_t ld = int64_t(vb / sizeof(double));
+  double* wv = (double*)(w + vb * (R + 1));
+  double* rv = (double*)(w + vb * (R + 2));
+  double* fh = (double*)(w + vb * (R + 3));
+  double* pf = (double*)(w + vb * (R + 4));
+  double* tv = (double*)(w + vb * (R + 5));
+  size_t off = align_up(vb * (R + 7));
+  const int nblk = dots_nblk(n);
+  double* partial = (double*)(w + off);
+  off += align_up(size_t(nblk) * (R + 2) * sizeof(double));
+  double* hdev = (double*)(w + off);
+  off += align_up(size_t(R + 2) * 8);
+  double* ydev = (double*)(w + off);
+
+  mhdg_solve_info inf{};
+  // f^ and D^-1 f^
+  mhdg_status st = mhdg_rhs(M, f_nodes, g_bnd, fh, 0, stream);
+  if (st) return st;
+  if (n == 0) {
+    if (info) *info = inf;
+    return MHDG_OK;
+  }
+  st = mhdg_rhs(M, f_nodes, g_bnd, pf, MHDG_PRECONDITION, stream);
+  if (st) return st;
+  auto t1 = std::chrono::steady_clock::now();
+  inf.t_rhs_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+
+  auto dot = [&](const double* a, const double* b, double* host) -> mhdg_status {
+    HIP_TRY(M, launch_dots(a, ld, 1, b, n, partial, nblk, hdev, s));
+    HIP_TRY(M, hipMemcpyAsync(host, hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(M, hipStreamSynchronize(s));
+    return MHDG_OK;
+  };
+  double bnorm2 = 0;
+  if ((st = dot(pf, pf, &bnorm2))) return st;
+  const double bnorm = std::sqrt(bnorm2);
+  if (o->zero_guess) HIP_TRY(M, hipMemsetAsync(lam, 0, n * sizeof(double), s));
+  if (bnorm == 0.0) {
+    HIP_TRY(M, hipMemsetAsync(lam, 0, n * sizeof(double), s));
+    HIP_TRY(M, hipStreamSynchronize(s));
+    if (info) *info = inf;
+    return MHDG_OK;
+  }
+  std::vector<double> H((R + 1) * R), cs(R), sn(R), g(R + 1), h(R + 2), y(R);
+  int it = 0;
+  double rel = 1.0;
+  bool converged = false;
+  int applies = 0;
+  while (true) {
+    // r = D^-1 f^ - D^-1 S lam
+    if ((st = mhdg_apply_trace_operator(M, lam, tv, MHDG_PRECONDITION, stream))) return st;
+    ++applies;
+    HIP_TRY(M, launch_scale_copy(1.0, pf, rv, n, s));
+    HIP_TRY(M, launch_axpby(-1.0, tv, 1.0, rv, n, s));
+    double rn2;
+    if ((st = dot(rv, rv, &rn2))) return st;
+    double beta = std::sqrt(rn2);
+    rel = beta / bnorm;
+    if (rel <= o->rtol || it >= o->max_iter) { converged = rel <= o->rtol; break; }
+    HIP_TRY(M, launch_scale_copy(1.0 / beta, rv, V, n, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < R && it < o->max_iter; ++j) {
+      ++it;
+      if ((st = mhdg_apply_trace_operator(M, V + j * ld, wv, MHDG_PRECONDITION, stream))) return st;
+      ++applies;
+      // CGS2
+      for (int pass = 0; pass < 2; ++pass) {
+        HIP_TRY(M, launch_dots(V, ld, j + 1, wv, n, partial, nblk, hdev, s));
+        HIP_TRY(M, launch_gemv_sub(V, ld, j + 1, hdev, wv, n, -1.0, s));
+        HIP_TRY(M, hipMemcpyAsync(h.data(), hdev,
+                                  (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(M, hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) H[i * R + j] = (pass ? H[i * R + j] : 0.0) + h[i];
+      }
+      double hn2;
+      if ((st = dot(wv, wv, &hn2))) return st;
+      double hn = std::sqrt(hn2);
+      H[(j + 1) * R + j] = hn;
+      if (hn > 0) HIP_TRY(M, launch_scale_copy(1.0 / hn, wv, V + (j + 1) * ld, n, s));
+      // apply previous rotations, then a new one
+      for (int i = 0; i < j; ++i) {
+        double a = H[i * R + j], b = H[(i + 1) * R + j];
+        H[i * R + j] = cs[i] * a + sn[i] * b;
+        H[(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+      }
+      double a = H[j * R + j], b = H[(j + 1) * R + j];
+      double rr = std::hypot(a, b);
+      cs[j] = rr == 0 ? 1.0 : a / rr;
+      sn[j] = rr == 0 ? 0.0 : b / rr;
+      H[j * R + j] = rr;
+      H[(j + 1) * R + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      rel = std::fabs(g[j + 1]) / bnorm;
+      if (rel <= o->rtol || hn == 0.0) { ++j; break; }
+    }
+    // y = H^-1 g, lam += V y
+    for (int i = j - 1; i >= 0; --i) {
+      double v = g[i];
+      for (int k = i + 1; k < j; ++k) v -= H[i * R + k] * y[k];
+      y[i] = v / H[i * R + i];
+    }
+    HIP_TRY(M, hipMemcpyAsync(ydev, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(M, launch_gemv_sub(V, ld, j, ydev, lam, n, 1.0, s));
+    HIP_TRY(M, hipStreamSynchronize(s));
+  }
+  // true residual ||f^ - S lam|| / ||f^||
+  if ((st = mhdg_apply_trace_operator(M, lam, tv, 0, stream))) return st;
+  ++applies;
+  HIP_TRY(M, launch_scale_copy(1.0, fh, rv, n, s));
+  HIP_TRY(M, launch_axpby(-1.0, tv, 1.0, rv, n, s));
+  double tr2, f2;
+  if ((st = dot(rv, rv, &tr2))) return st;
+  if ((st = dot(fh, fh, &f2))) return st;
+  auto t2 = std::chrono::steady_clock::now();
+  inf.iterations = it;
+  inf.rel_res_prec = rel;
+  inf.rel_res_true = f2 > 0 ? std::sqrt(tr2 / f2) : 0.0;
+  inf.t_gmres_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+  inf.n_applies = applies;
+  inf.status = converged ? MHDG_OK : MHDG_ERR_NOT_CONVERGED;
+  if (info) *info = inf;
+  if (!converged) return fail(M, MHDG_ERR_NOT_CONVERGED, "solve: max_iter reached");
+  return MHDG_OK;
+}
+
+}  // extern "C"

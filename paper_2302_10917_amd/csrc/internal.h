@@ -1,0 +1,113 @@
+// Internal declarations shared by the host driver (host.cpp) and the HIP
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mhdg {
+
+constexpr int kMaxLevel = 5;
+
+// Per-macro data, built on the host at setup and copied into the factor
+// workspace by factor_local.  All doubles first so the layout has no holes.
+struct MacroInfo {
+  double G[4];        // inverse Jacobian of the macro map, G[k*2+d] = d xi_k / d x_d
+  double dJ;          // |det J| (twice the area)
+  double len[3];      // edge lengths, edge k from vertex k to vertex k+1
+  double nrm[6];      // outward unit normals (nx, ny) per edge
+  double kappa;       // filled on the device from the caller's kappa array
+  int64_t fac_off;    // element offset of this macro's factor block
+  int64_t loc_off;    // offset into n_local vectors
+  int64_t node_off;   // offset into n_nodes vectors
+  int64_t slot_off[3];// offset of the (macro, edge) contribution slot, -1 on boundary
+  int32_t face[3];    // face id (sorted order)
+  int32_t orient[3];  // +1 if the local edge runs like the canonical face direction
+  int32_t tr_off[3];  // global trace offset of an interior face, else -1
+  int32_t bnd_face[3];// index into BndFaceInfo for a boundary face, else -1
+  int32_t flevel[3];  // face level
+  int32_t level;      // macro level r
+  int32_t N;          // local size 3Q
+  int32_t Q;
+  int32_t P;          // 2^r p
+  int32_t pad;
+};
+
+struct FaceInfo {     // interior faces
+  double len;
+  int64_t slot[2];    // slots of the two macros (lower macro id first)
+  int32_t tr_off;
+  int32_t nF;
+  int32_t level;
+  int32_t pad;
+};
+
+struct BndFaceInfo {  // boundary (Dirichlet) faces
+  double len;
+  int64_t g_off;      // offset of its samples in the g_D array
+  int64_t lam_off;    // offset of its projected trace in the Dirichlet trace array
+  int32_t nF;
+  int32_t level;
+};
+
+// Offsets (in doubles / ints, from the template blob base) per level.
+struct LevelTemplates {
+  int64_t Mhat, E0, E1;     // Q x Q reference macro mass and derivative matrices
+  int64_t M1, M1inv;        // (P+1)^2 1D trace mass on [0,1] and its inverse
+  int64_t edge_node;        // int32 [3][P+1]: lattice node at local edge position s
+  int64_t node_epos;        // int32 [Q][3]: position along local edge k, or -1
+  int64_t T1[kMaxLevel + 1];// (P+1) x (P_F+1): int phi_s mu_l over [0,1], face level F >= r
+  int32_t present, Q, P, N;
+};
+
+struct Templates {
+  LevelTemplates lev[kMaxLevel + 1];
+  int64_t dir_basis;        // (p+1) x kb: trace basis at the Dirichlet points of a segment
+  int64_t dir_w;            // kb weights on [0,1]
+  int32_t p, kb;
+};
+
+// Device workspace layout for factor_local / apply / rhs / recover.
+struct FactorLayout {
+  size_t meta, faces, bfaces, tmpl, perm, status, R, slots, lamD, factors, total;
+};
+
+enum SolveMode { MODE_APPLY = 0, MODE_RHS = 1, MODE_RECOVER = 2, MODE_LOCAL = 3 };
+
+// ---- kernel launchers (kernels.hip) ----
+hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, hipStream_t s);
+hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, const int32_t* order,
+                           int64_t n, const double* tmpl, const Templates& T, double bx, double by,
+                           double tau, hipStream_t s);
+hipError_t launch_lu(void* fac, int precision, const MacroInfo* info, const int32_t* order,
+                     int64_t n, int max_N, int32_t* perm, int32_t* status, hipStream_t s);
+hipError_t launch_dirichlet(const BndFaceInfo* bf, int64_t nbf, const double* tmpl,
+                            const Templates& T, const double* g, double* lamD, hipStream_t s);
+hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
+                            const double* tmpl, const Templates& T, const double* f,
+                            const double* lamD, double bx, double by, double tau, double* R,
+                            hipStream_t s);
+hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int precision,
+                              const MacroInfo* info, const int32_t* order, int64_t n, int max_N,
+                              const int32_t* perm, const double* tmpl, const Templates& T,
+                              double bx, double by, double tau, const double* lam,
+                              const double* xin, double* yout, double* slots, hipStream_t s);
+hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const double* tmpl,
+                               const Templates& T, double tau, const double* lam,
+                               const double* slots, double* out, hipStream_t s);
+hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double* tmpl,
+                                 const Templates& T, double bx, double by, double tau,
+                                 double* dst, hipStream_t s);
+// face_combine modes
+enum FaceMode { FACE_S = 0, FACE_PREC_S = 1, FACE_RHS = 2, FACE_PREC_RHS = 3, FACE_RESID = 4 };
+
+// GMRES vector kernels
+hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, int64_t n,
+                       double* partial, int nblk, double* out, hipStream_t s);
+hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double* h, double* w,
+                           int64_t n, double sign, hipStream_t s);
+hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+hipError_t launch_scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);
+int dots_nblk(int64_t n);
+
+}  // namespace mhdg

@@ -1,0 +1,746 @@
+// HIP kernels (gfx950) of the macro-element HDG local-problem path.
+//
+//   assemble      A_K from the exact reference templates, scaled by the macro's
+//                 affine map, kappa_K, a and tau (forms of paper section 3.2)
+//   lu            in-place LU with partial row pivoting, one workgroup per macro;
+//                 register-resident pivoted panels, MFMA trailing updates
+//                 (the in-place factorisation of the remark in section 3.3.2)
+//   macro_solve   steps 1-3 of the matrix-free algorithm for one macro per
+//                 wavefront: gather lambda_K, x = B_K lambda_K, y = A_K^-1 x,
+//                 v^ = C_K y into a per-(macro, edge) slot; also the local
+//                 right-hand side solve and the local recovery (eq. local_problem)
+//   face_combine  step 4 per interior face: D_F lambda - v^_1 - v^_2, or with
+//                 the D^-1 preconditioner lambda - D_F^-1 (v^_1 + v^_2)
+//   dirichlet     L2 projection of g_D onto the boundary trace spaces
+//   vector ops    deterministic two-pass dot products and Krylov updates
+#include "internal.h"
+
+namespace mhdg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ const int32_t* ints(const double* base, int64_t off) {
+  return reinterpret_cast<const int32_t*>(base + off);
+}
+
+// ------------------------------------------------------------------ assembly
+struct EntryCtx {
+  const double* Mh;
+  const double* E0;
+  const double* E1;
+  const double* M1;
+  const int32_t* epos;
+  double G[4], dJ, len[3], kappa, bx, by, tau;
+  int Q, P;
+};
+
+__device__ __forceinline__ EntryCtx make_ctx(const MacroInfo& mi, const double* tm,
+                                             const Templates& T, double bx, double by,
+                                             double tau) {
+  EntryCtx c;
+  const LevelTemplates& L = T.lev[mi.level];
+  c.Mh = tm + L.Mhat;
+  c.E0 = tm + L.E0;
+  c.E1 = tm + L.E1;
+  c.M1 = tm + L.M1;
+  c.epos = ints(tm, L.node_epos);
+  for (int k = 0; k < 4; ++k) c.G[k] = mi.G[k];
+  c.dJ = mi.dJ;
+  for (int k = 0; k < 3; ++k) c.len[k] = mi.len[k];
+  c.kappa = mi.kappa;
+  c.bx = bx;
+  c.by = by;
+  c.tau = tau;
+  c.Q = mi.Q;
+  c.P = mi.P;
+  return c;
+}
+
+// E^d_ij = (phi_j, d_d phi_i)_K = |det J| sum_k G[k][d] Ehat^k_ij
+__device__ __forceinline__ double Ed(const EntryCtx& c, int d, int i, int j) {
+  const size_t o = size_t(i) * c.Q + j;
+  return c.dJ * (c.G[d] * c.E0[o] + c.G[2 + d] * c.E1[o]);
+}
+
+// boundary mass <phi_j, phi_i>_dK from the 1D trace mass on each edge
+__device__ __forceinline__ double Mb(const EntryCtx& c, int i, int j) {
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int si = c.epos[3 * i + k], sj = c.epos[3 * j + k];
+    if (si >= 0 && sj >= 0) v += c.len[k] * c.M1[size_t(si) * (c.P + 1) + sj];
+  }
+  return v;
+}
+
+// Entry (r, c) of A_K = [[M, 0, -E^x], [0, M, -E^y], [kappa H^x, kappa H^y, K]]
+// with H^d = (E^d)^T (integration by parts inside the continuous macro space)
+// and K = -(a_x E^x + a_y E^y) + tau Mb.
+__device__ double a_entry(const EntryCtx& c, int r, int col) {
+  const int Q = c.Q;
+  const int rb = r / Q, i = r - rb * Q, cb = col / Q, j = col - cb * Q;
+  switch (rb * 3 + cb) {
+    case 0: case 4: return c.dJ * c.Mh[size_t(i) * Q + j];
+    case 1: case 3: return 0.0;
+    case 2: return -Ed(c, 0, i, j);
+    case 5: return -Ed(c, 1, i, j);
+    case 6: return c.kappa * Ed(c, 0, j, i);
+    case 7: return c.kappa * Ed(c, 1, j, i);
+    default: return -(c.bx * Ed(c, 0, i, j) + c.by * Ed(c, 1, i, j)) + c.tau * Mb(c, i, j);
+  }
+}
+
+__global__ void set_kappa_kernel(MacroInfo* info, const double* kappa, int64_t n) {
+  int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (e < n) info[e].kappa = kappa[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void assemble_kernel(T* fac, const MacroInfo* __restrict__ info,
+                                                       const double* __restrict__ tm, Templates Tp,
+                                                       double bx, double by, double tau) {
+  const MacroInfo& mi = info[blockIdx.x];
+  const int N = mi.N;
+  const int rows_per = 8;
+  const int r0 = blockIdx.y * rows_per;
+  if (r0 >= N) return;
+  EntryCtx c = make_ctx(mi, tm, Tp, bx, by, tau);
+  T* A = fac + mi.fac_off;
+  const int r1 = min(N, r0 + rows_per);
+  for (int r = r0; r < r1; ++r)
+    for (int col = threadIdx.x; col < N; col += blockDim.x)
+      A[size_t(r) * N + col] = (T)a_entry(c, r, col);
+}
+
+__global__ void extract_kernel(const MacroInfo* info, int64_t e, const double* tm, Templates Tp,
+                               double bx, double by, double tau, double* dst) {
+  const MacroInfo& mi = info[e];
+  EntryCtx c = make_ctx(mi, tm, Tp, bx, by, tau);
+  const int N = mi.N;
+  const int r = blockIdx.x;
+  if (r >= N) return;
+  for (int col = threadIdx.x; col < N; col += blockDim.x) dst[size_t(r) * N + col] = a_entry(c, r, col);
+}
+
+// ------------------------------------------------------------------ LU
+template <typename T> struct Mfma;
+// 16x16x4 MFMA tiles: lane l holds A[l%16][l/16] and B[l/16][l%16]; the
+// accumulator element v of lane l is D[drow(l/16, v)][l%16] (row order
+// measured on gfx950 for each instruction).
+template <> struct Mfma<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int g, int v) { return g + 4 * v; }
+};
+template <> struct Mfma<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int g, int v) { return 4 * g + v; }
+};
+
+// One workgroup of NT threads factors one macro's N x N row-major block in
+// place: PA = LU with partial pivoting (largest |a|, ties to the smallest
+// row).  Panels of NB columns are held in registers (thread t owns rows
+// k0 + t + q NT); the pivot search is a wavefront max-reduction followed by a
+// cross-wave reduction in LDS; the trailing update runs on MFMA 16x16x4 tiles.
+// perm[i] receives the original row of factor row i; status = first zero
+// pivot column + 1, or 0.
+template <typename T, int NT, int RPT>
+__global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restrict__ info,
+                                                int32_t* perm_all, int32_t* status) {
+  constexpr int NB = 16;
+  constexpr int NW = NT / 64;
+  const MacroInfo& mi = info[blockIdx.x];
+  const int N = mi.N;
+  T* A = fac + mi.fac_off;
+  int32_t* perm = perm_all + mi.loc_off;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+
+  __shared__ double s_red_v[NW];
+  __shared__ int s_red_i[NW];
+  __shared__ T s_row[NB];
+  __shared__ T s_swap[2][NB];
+  __shared__ T s_L11[NB * NB];
+  __shared__ int s_piv[NB];
+  __shared__ int s_status;
+
+  for (int i = tid; i < N; i += NT) perm[i] = i;
+  if (tid == 0) s_status = 0;
+  __syncthreads();
+
+  T pr[RPT][NB];
+  for (int k0 = 0; k0 < N; k0 += NB) {
+    const int nb = min(NB, N - k0);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = k0 + tid + q * NT;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        pr[q][c] = (row < N && c < nb) ? A[size_t(row) * N + k0 + c] : T(0);
+    }
+    // ---- panel factorisation
+    for (int j = 0; j < nb; ++j) {
+      const int col = k0 + j;
+      double best = -1.0;
+      int bidx = 0x7fffffff;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int row = k0 + tid + q * NT;
+        double v = -1.0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c == j) v = fabs((double)pr[q][c]);
+        if (row >= col && row < N && v > best) { best = v; bidx = row; }
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        double ov = __shfl_xor(best, o, 64);
+        int oi = __shfl_xor(bidx, o, 64);
+        if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+      }
+      if (lane == 0) { s_red_v[wid] = best; s_red_i[wid] = bidx; }
+      __syncthreads();
+      best = s_red_v[0];
+      bidx = s_red_i[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        double ov = s_red_v[w];
+        int oi = s_red_i[w];
+        if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+      }
+      const int prow = bidx;
+      const int own_c = (col - k0) % NT, slot_c = (col - k0) / NT;
+      const int own_p = (prow - k0) % NT, slot_p = (prow - k0) / NT;
+      if (prow != col) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          if (tid == own_p && q == slot_p)
+            for (int c = 0; c < NB; ++c) s_swap[0][c] = pr[q][c];
+          if (tid == own_c && q == slot_c)
+            for (int c = 0; c < NB; ++c) s_swap[1][c] = pr[q][c];
+        }
+      }
+      __syncthreads();
+      if (prow != col) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          if (tid == own_c && q == slot_c)
+            for (int c = 0; c < NB; ++c) pr[q][c] = s_swap[0][c];
+          if (tid == own_p && q == slot_p)
+            for (int c = 0; c < NB; ++c) pr[q][c] = s_swap[1][c];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (tid == own_c && q == slot_c)
+          for (int c = 0; c < NB; ++c) s_row[c] = pr[q][c];
+      if (tid == 0) {
+        s_piv[j] = prow;
+        if (best == 0.0 && s_status == 0) s_status = col + 1;
+      }
+      __syncthreads();
+      if (best != 0.0) {
+        const T piv = s_row[j];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int row = k0 + tid + q * NT;
+          if (row > col && row < N) {
+            T l = T(0);
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+              if (c == j) { l = pr[q][c] / piv; pr[q][c] = l; }
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+              if (c > j) pr[q][c] -= l * s_row[c];
+          }
+        }
+      }
+    }
+    // ---- write the panel back; keep L11 in LDS
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = k0 + tid + q * NT;
+      if (row < N) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c < nb) A[size_t(row) * N + k0 + c] = pr[q][c];
+        if (row < k0 + nb)
+          for (int c = 0; c < NB; ++c) s_L11[(row - k0) * NB + c] = pr[q][c];
+      }
+    }
+    __syncthreads();
+    // ---- row interchanges outside the panel, in pivot order
+    for (int c = tid; c < N; c += NT) {
+      if (c >= k0 && c < k0 + nb) continue;
+      for (int j = 0; j < nb; ++j) {
+        const int prow = s_piv[j], col = k0 + j;
+        if (prow != col) {
+          T a = A[size_t(col) * N + c], b = A[size_t(prow) * N + c];
+          A[size_t(col) * N + c] = b;
+          A[size_t(prow) * N + c] = a;
+        }
+      }
+    }
+    if (tid == 0)
+      for (int j = 0; j < nb; ++j) {
+        const int prow = s_piv[j], col = k0 + j;
+        if (prow != col) { int t = perm[col]; perm[col] = perm[prow]; perm[prow] = t; }
+      }
+    __syncthreads();
+    if (k0 + nb >= N) break;
+    // ---- U12 = L11^-1 A12
+    for (int c = k0 + nb + tid; c < N; c += NT) {
+      T v[NB];
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) v[jj] = jj < nb ? A[size_t(k0 + jj) * N + c] : T(0);
+#pragma unroll
+      for (int jj = 1; jj < NB; ++jj)
+#pragma unroll
+        for (int ii = 0; ii < jj; ++ii) v[jj] -= s_L11[jj * NB + ii] * v[ii];
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj)
+        if (jj < nb) A[size_t(k0 + jj) * N + c] = v[jj];
+    }
+    __syncthreads();
+    // ---- A22 -= L21 U12 on MFMA 16x16x4 tiles
+    {
+      const int base = k0 + nb;
+      const int nt = (N - base + 15) / 16;
+      const int li = lane & 15, lk = lane >> 4;
+      for (int rt = wid; rt < nt; rt += NW) {
+        const int r0 = base + 16 * rt;
+        T a[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = 4 * s + lk, row = r0 + li;
+          a[s] = (row < N && k < nb) ? -A[size_t(row) * N + k0 + k] : T(0);
+        }
+        for (int ct = 0; ct < nt; ++ct) {
+          const int c0 = base + 16 * ct;
+          const int colc = c0 + li;
+          T b[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + lk;
+            b[s] = (k < nb && colc < N) ? A[size_t(k0 + k) * N + colc] : T(0);
+          }
+          typename Mfma<T>::acc acc;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = r0 + Mfma<T>::drow(lk, v);
+            acc[v] = (row < N && colc < N) ? A[size_t(row) * N + colc] : T(0);
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc = Mfma<T>::run(a[s], b[s], acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = r0 + Mfma<T>::drow(lk, v);
+            if (row < N && colc < N) A[size_t(row) * N + colc] = acc[v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) status[blockIdx.x] = s_status;
+}
+
+// ------------------------------------------------------------------ per-macro solves
+// x += sgn * B_k lam_F for local edge k (step 1): rows v_x, v_y, w of the
+// boundary nodes of edge k receive n_x g, n_y g, (a.n - tau) g with
+// g_s = |F| sum_l T1[s][l] lam_l (T1 couples the level-r edge space with
+// the face's trace space, both in the face's canonical direction).
+__device__ void edge_B(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
+                       const double* lamF, double sgn, double bx, double by, double tau, double* x) {
+  const LevelTemplates& L = Tp.lev[mi.level];
+  const int P = mi.P, Q = mi.Q, fl = mi.flevel[k];
+  const int nF = (1 << fl) * Tp.p + 1;
+  const double* T1 = tm + L.T1[fl];
+  const int32_t* en = ints(tm, L.edge_node);
+  const double nx = mi.nrm[2 * k], ny = mi.nrm[2 * k + 1];
+  const double an = bx * nx + by * ny - tau;
+  for (int s = threadIdx.x; s <= P; s += blockDim.x) {
+    const int sc = mi.orient[k] > 0 ? s : P - s;
+    double g = 0.0;
+    for (int l = 0; l < nF; ++l) g += T1[size_t(sc) * nF + l] * lamF[l];
+    g *= sgn * mi.len[k];
+    const int node = en[k * (P + 1) + s];
+    x[node] += nx * g;
+    x[Q + node] += ny * g;
+    x[2 * Q + node] += an * g;
+  }
+}
+
+// out_l = (C_k z)_l = |F| sum_s T1[s][l] (kappa n.q + tau u)(node s) (step 3)
+__device__ void edge_C(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
+                       const double* z, double tau, double* out) {
+  const LevelTemplates& L = Tp.lev[mi.level];
+  const int P = mi.P, Q = mi.Q, fl = mi.flevel[k];
+  const int nF = (1 << fl) * Tp.p + 1;
+  const double* T1 = tm + L.T1[fl];
+  const int32_t* en = ints(tm, L.edge_node);
+  const double kx = mi.kappa * mi.nrm[2 * k], ky = mi.kappa * mi.nrm[2 * k + 1];
+  for (int l = threadIdx.x; l < nF; l += blockDim.x) {
+    double v = 0.0;
+    for (int sc = 0; sc <= P; ++sc) {
+      const int s = mi.orient[k] > 0 ? sc : P - sc;
+      const int node = en[k * (P + 1) + s];
+      v += T1[size_t(sc) * nF + l] * (kx * z[node] + ky * z[Q + node] + tau * z[2 * Q + node]);
+    }
+    out[l] = mi.len[k] * v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void macro_solve_kernel(int mode, const T* __restrict__ fac,
+                                                         const MacroInfo* __restrict__ info,
+                                                         const int32_t* __restrict__ perm_all,
+                                                         const double* __restrict__ tm, Templates Tp,
+                                                         double bx, double by, double tau,
+                                                         const double* __restrict__ lam,
+                                                         const double* __restrict__ xin,
+                                                         double* __restrict__ yout,
+                                                         double* __restrict__ slots) {
+  extern __shared__ double sm[];
+  const MacroInfo& mi = info[blockIdx.x];
+  const int N = mi.N, lane = threadIdx.x;
+  double* x = sm;
+  double* y = sm + N;
+  const T* A = fac + mi.fac_off;
+  const int32_t* perm = perm_all + mi.loc_off;
+  // ---- right-hand side
+  if (mode == MODE_APPLY) {
+    for (int i = lane; i < N; i += 64) x[i] = 0.0;
+  } else {
+    for (int i = lane; i < N; i += 64) x[i] = xin[mi.loc_off + i];
+  }
+  __syncthreads();
+  if (mode == MODE_APPLY || mode == MODE_RECOVER) {
+    const double sgn = mode == MODE_APPLY ? 1.0 : -1.0;
+    for (int k = 0; k < 3; ++k) {
+      if (mi.tr_off[k] >= 0) edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], sgn, bx, by, tau, x);
+      __syncthreads();
+    }
+  }
+  // ---- pivoting, forward and backward substitution (step 2)
+  for (int i = lane; i < N; i += 64) y[i] = x[perm[i]];
+  __syncthreads();
+  for (int i = 1; i < N; ++i) {
+    const T* row = A + size_t(i) * N;
+    double acc = 0.0;
+    for (int j = lane; j < i; j += 64) acc += (double)row[j] * y[j];
+    acc = wave_sum(acc);
+    if (lane == 0) y[i] -= acc;
+    __syncthreads();
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    const T* row = A + size_t(i) * N;
+    double acc = 0.0;
+    for (int j = i + 1 + lane; j < N; j += 64) acc += (double)row[j] * y[j];
+    acc = wave_sum(acc);
+    if (lane == 0) y[i] = (y[i] - acc) / (double)row[i];
+    __syncthreads();
+  }
+  // ---- outputs
+  if (mode == MODE_RECOVER || mode == MODE_LOCAL)
+    for (int i = lane; i < N; i += 64) yout[mi.loc_off + i] = y[i];
+  if (mode != MODE_LOCAL)
+    for (int k = 0; k < 3; ++k)
+      if (mi.tr_off[k] >= 0) edge_C(mi, k, tm, Tp, y, tau, slots + mi.slot_off[k]);
+}
+
+// ------------------------------------------------------------------ step 4
+__global__ __launch_bounds__(64) void face_combine_kernel(int mode, const FaceInfo* __restrict__ fi,
+                                                          const double* __restrict__ tm, Templates Tp,
+                                                          double tau, const double* __restrict__ lam,
+                                                          const double* __restrict__ slots,
+                                                          double* __restrict__ out) {
+  __shared__ double v[(1 << kMaxLevel) * 4 + 1];
+  __shared__ double lf[(1 << kMaxLevel) * 4 + 1];
+  const FaceInfo& f = fi[blockIdx.x];
+  const int nF = f.nF;
+  const LevelTemplates& L = Tp.lev[f.level];
+  for (int l = threadIdx.x; l < nF; l += 64) {
+    v[l] = slots[f.slot[0] + l] + slots[f.slot[1] + l];
+    lf[l] = lam ? lam[f.tr_off + l] : 0.0;
+  }
+  __syncthreads();
+  const double* M1 = tm + L.M1;
+  const double* Mi = tm + L.M1inv;
+  for (int l = threadIdx.x; l < nF; l += 64) {
+    double r;
+    if (mode == FACE_S || mode == FACE_RESID) {
+      double d = 0.0;  // D_F lam = -2 tau |F| M1 lam
+      for (int k = 0; k < nF; ++k) d += M1[size_t(l) * nF + k] * lf[k];
+      d *= -2.0 * tau * f.len;
+      r = mode == FACE_S ? d - v[l] : d + v[l];
+    } else if (mode == FACE_RHS) {
+      r = -v[l];
+    } else {
+      double d = 0.0;  // -D_F^-1 v = M1^-1 v / (2 tau |F|)
+      for (int k = 0; k < nF; ++k) d += Mi[size_t(l) * nF + k] * v[k];
+      d /= 2.0 * tau * f.len;
+      r = mode == FACE_PREC_S ? lf[l] + d : d;
+    }
+    out[f.tr_off + l] = r;
+  }
+}
+
+// ------------------------------------------------------------------ data
+// lam_D = M1^-1 b, b_l = sum over segments and sampling points of
+// (w_q / npc) g_q mu_l(t_q): the L2 projection of g_D onto M(F).
+__global__ __launch_bounds__(64) void dirichlet_kernel(const BndFaceInfo* __restrict__ bf,
+                                                       const double* __restrict__ tm, Templates Tp,
+                                                       const double* __restrict__ g,
+                                                       double* __restrict__ lamD) {
+  __shared__ double b[(1 << kMaxLevel) * 4 + 1];
+  const BndFaceInfo& f = bf[blockIdx.x];
+  const int p = Tp.p, kb = Tp.kb, nF = f.nF, npc = 1 << f.level;
+  const double* phi = tm + Tp.dir_basis;
+  const double* w = tm + Tp.dir_w;
+  for (int l = threadIdx.x; l < nF; l += 64) {
+    double acc = 0.0;
+    // node l belongs to segment l/p (local a = l%p) and, if l%p == 0, to segment l/p - 1 (a = p)
+    const int c1 = l / p, a1 = l % p;
+    if (c1 < npc)
+      for (int q = 0; q < kb; ++q) acc += w[q] * g[f.g_off + c1 * kb + q] * phi[a1 * kb + q];
+    if (a1 == 0 && c1 > 0)
+      for (int q = 0; q < kb; ++q) acc += w[q] * g[f.g_off + (c1 - 1) * kb + q] * phi[p * kb + q];
+    b[l] = acc / npc;
+  }
+  __syncthreads();
+  const double* Mi = tm + Tp.lev[f.level].M1inv;
+  for (int l = threadIdx.x; l < nF; l += 64) {
+    double acc = 0.0;
+    for (int k = 0; k < nF; ++k) acc += Mi[size_t(l) * nF + k] * b[k];
+    lamD[f.lam_off + l] = acc;
+  }
+}
+
+// R_K = [0; 0; |det J| Mhat f_K] - sum over Dirichlet edges of B_k lam_D
+__global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restrict__ info,
+                                                       const BndFaceInfo* __restrict__ bf,
+                                                       const double* __restrict__ tm, Templates Tp,
+                                                       const double* __restrict__ f,
+                                                       const double* __restrict__ lamD, double bx,
+                                                       double by, double tau, double* __restrict__ R) {
+  extern __shared__ double x[];
+  const MacroInfo& mi = info[blockIdx.x];
+  const int N = mi.N, Q = mi.Q;
+  const double* Mh = tm + Tp.lev[mi.level].Mhat;
+  const double* fK = f + mi.node_off;
+  for (int i = threadIdx.x; i < N; i += 64) {
+    double v = 0.0;
+    if (i >= 2 * Q) {
+      const int ii = i - 2 * Q;
+      for (int j = 0; j < Q; ++j) v += Mh[size_t(ii) * Q + j] * fK[j];
+      v *= mi.dJ;
+    }
+    x[i] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < 3; ++k) {
+    if (mi.bnd_face[k] >= 0)
+      edge_B(mi, k, tm, Tp, lamD + bf[mi.bnd_face[k]].lam_off, -1.0, bx, by, tau, x);
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < N; i += 64) R[mi.loc_off + i] = x[i];
+}
+
+// ------------------------------------------------------------------ vector ops
+int dots_nblk(int64_t n) {
+  int64_t b = (n + 4095) / 4096;
+  return (int)(b < 1 ? 1 : (b > 512 ? 512 : b));
+}
+
+__global__ __launch_bounds__(256) void dots_partial_kernel(const double* __restrict__ V, int64_t ld,
+                                                           int ncols, const double* __restrict__ w,
+                                                           int64_t n, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int nblk = gridDim.x;
+  for (int c = 0; c < ncols; ++c) {
+    const double* v = V + c * ld;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * int64_t(256) + threadIdx.x; i < n; i += int64_t(nblk) * 256)
+      acc += v[i] * w[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[c * nblk + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(64) void dots_final_kernel(const double* __restrict__ partial, int nblk,
+                                                        double* __restrict__ out) {
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) acc += partial[c * nblk + b];
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) out[c] = acc;
+}
+
+__global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ld, int ncols,
+                                const double* __restrict__ h, double* __restrict__ w, int64_t n,
+                                double sign) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int c = 0; c < ncols; ++c) acc += V[c * ld + i] * h[c];
+  w[i] += sign * acc;
+}
+
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y,
+                             int64_t n) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void scale_copy_kernel(double a, const double* __restrict__ x, double* __restrict__ y,
+                                  int64_t n) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(set_kappa_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, info, kappa, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, const int32_t*,
+                           int64_t n, const double* tmpl, const Templates& T, double bx, double by,
+                           double tau, hipStream_t s) {
+  int maxN = 0;
+  for (int r = 0; r <= kMaxLevel; ++r)
+    if (T.lev[r].present) maxN = maxN > T.lev[r].N ? maxN : T.lev[r].N;
+  dim3 grid((unsigned)n, (unsigned)((maxN + 7) / 8));
+  if (precision == 1)
+    hipLaunchKernelGGL(assemble_kernel<float>, grid, dim3(256), 0, s, (float*)fac, info, tmpl, T,
+                       bx, by, tau);
+  else
+    hipLaunchKernelGGL(assemble_kernel<double>, grid, dim3(256), 0, s, (double*)fac, info, tmpl, T,
+                       bx, by, tau);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t lu_dispatch(T* fac, const MacroInfo* info, int64_t n, int maxN, int32_t* perm,
+                              int32_t* status, hipStream_t s) {
+  if (maxN <= 256)
+    hipLaunchKernelGGL((lu_kernel<T, 256, 1>), dim3((unsigned)n), dim3(256), 0, s, fac, info, perm, status);
+  else if (maxN <= 1024)
+    hipLaunchKernelGGL((lu_kernel<T, 256, 4>), dim3((unsigned)n), dim3(256), 0, s, fac, info, perm, status);
+  else if (maxN <= 4096)
+    hipLaunchKernelGGL((lu_kernel<T, 1024, 4>), dim3((unsigned)n), dim3(1024), 0, s, fac, info, perm, status);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_lu(void* fac, int precision, const MacroInfo* info, const int32_t*, int64_t n,
+                     int maxN, int32_t* perm, int32_t* status, hipStream_t s) {
+  if (precision == 1) return lu_dispatch((float*)fac, info, n, maxN, perm, status, s);
+  return lu_dispatch((double*)fac, info, n, maxN, perm, status, s);
+}
+
+hipError_t launch_dirichlet(const BndFaceInfo* bf, int64_t nbf, const double* tmpl,
+                            const Templates& T, const double* g, double* lamD, hipStream_t s) {
+  hipLaunchKernelGGL(dirichlet_kernel, dim3((unsigned)nbf), dim3(64), 0, s, bf, tmpl, T, g, lamD);
+  return hipGetLastError();
+}
+
+static int max_present_N(const Templates& T) {
+  int maxN = 0;
+  for (int r = 0; r <= kMaxLevel; ++r)
+    if (T.lev[r].present && T.lev[r].N > maxN) maxN = T.lev[r].N;
+  return maxN;
+}
+
+hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
+                            const double* tmpl, const Templates& T, const double* f,
+                            const double* lamD, double bx, double by, double tau, double* R,
+                            hipStream_t s) {
+  size_t lds = size_t(max_present_N(T)) * sizeof(double);
+  hipLaunchKernelGGL(local_rhs_kernel, dim3((unsigned)n), dim3(64), lds, s, info, bf, tmpl, T, f,
+                     lamD, bx, by, tau, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int precision,
+                              const MacroInfo* info, const int32_t*, int64_t n, int max_N,
+                              const int32_t* perm, const double* tmpl, const Templates& T,
+                              double bx, double by, double tau, const double* lam,
+                              const double* xin, double* yout, double* slots, hipStream_t s) {
+  (void)transpose;
+  size_t lds = size_t(2) * max_N * sizeof(double);
+  if (precision == 1)
+    hipLaunchKernelGGL(macro_solve_kernel<float>, dim3((unsigned)n), dim3(64), lds, s, mode,
+                       (const float*)fac, info, perm, tmpl, T, bx, by, tau, lam, xin, yout, slots);
+  else
+    hipLaunchKernelGGL(macro_solve_kernel<double>, dim3((unsigned)n), dim3(64), lds, s, mode,
+                       (const double*)fac, info, perm, tmpl, T, bx, by, tau, lam, xin, yout, slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const double* tmpl,
+                               const Templates& T, double tau, const double* lam,
+                               const double* slots, double* out, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(face_combine_kernel, dim3((unsigned)nf), dim3(64), 0, s, mode, fi, tmpl, T,
+                     tau, lam, slots, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double* tmpl,
+                                 const Templates& T, double bx, double by, double tau,
+                                 double* dst, hipStream_t s) {
+  // the row count is the macro's N; launch max_N rows and let extra rows exit
+  int maxN = max_present_N(T);
+  hipLaunchKernelGGL(extract_kernel, dim3((unsigned)maxN), dim3(256), 0, s, info, e, tmpl, T, bx,
+                     by, tau, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, int64_t n,
+                       double* partial, int nblk, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk), dim3(256), 0, s, V, ld, ncols, w, n, partial);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(ncols), dim3(64), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double* h, double* w,
+                           int64_t n, double sign, hipStream_t s) {
+  if (ncols == 0) return hipSuccess;
+  hipLaunchKernelGGL(gemv_sub_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, V, ld, ncols, h,
+                     w, n, sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, x, y, n);
+  return hipGetLastError();
+}
+
+}  // namespace mhdg

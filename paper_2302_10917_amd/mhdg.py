@@ -1,0 +1,221 @@
+"""Thin Python binding of libmhdg.so (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels; PyTorch only
+provides device memory (the workspaces and vectors) and the stream.  The
+method names follow the C ABI in include/mhdg.h.  If the library is missing
+the binding raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhdg.so")
+
+MHDG_FP64, MHDG_FP32 = 0, 1
+MHDG_PRECONDITION, MHDG_TRANSPOSE = 1, 2
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "MESH", 3: "SINGULAR", 4: "NOT_CONVERGED",
+          5: "WORKSPACE", 6: "HIP", 7: "STATE"}
+
+ABI_SYMBOLS = [
+    "mhdg_setup_macro_mesh", "mhdg_query", "mhdg_sample_points", "mhdg_factor_local",
+    "mhdg_local_matrix", "mhdg_apply_trace_operator", "mhdg_local_solve", "mhdg_rhs",
+    "mhdg_solve", "mhdg_recover_local", "mhdg_destroy", "mhdg_last_error",
+    "mhdg_status_string",
+]
+
+
+class MhdgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("n_macro", ctypes.c_int64), ("n_faces", ctypes.c_int64),
+                ("n_interior_faces", ctypes.c_int64), ("n_trace", ctypes.c_int64),
+                ("n_nodes", ctypes.c_int64), ("n_local", ctypes.c_int64),
+                ("n_bnd_points", ctypes.c_int64), ("p", ctypes.c_int32),
+                ("max_level", ctypes.c_int32), ("max_local", ctypes.c_int64),
+                ("factor_ws_bytes", ctypes.c_size_t), ("solve_ws_bytes", ctypes.c_size_t)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("zero_guess", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel_res_prec", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("t_rhs_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
+                ("n_applies", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmhdg.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() "
+                          "(the HIP library is required, there is no fallback)")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                          ctypes.c_size_t)
+    sig = {
+        "mhdg_setup_macro_mesh": [I64, P, I64, P, P, I32, I32, ctypes.POINTER(P)],
+        "mhdg_query": [P, I32, I32, ctypes.POINTER(Sizes)],
+        "mhdg_sample_points": [P, P, P],
+        "mhdg_factor_local": [P, P, D, D, D, I32, P, SZ, P],
+        "mhdg_local_matrix": [P, I64, P, P],
+        "mhdg_apply_trace_operator": [P, P, P, I32, P],
+        "mhdg_local_solve": [P, P, P, I32, P],
+        "mhdg_rhs": [P, P, P, P, I32, P],
+        "mhdg_solve": [P, P, P, ctypes.POINTER(SolveOpts), P, P, SZ, ctypes.POINTER(SolveInfo), P],
+        "mhdg_recover_local": [P, P, P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.mhdg_destroy.argtypes = [P]
+    lib.mhdg_destroy.restype = None
+    lib.mhdg_last_error.argtypes = [P]
+    lib.mhdg_last_error.restype = ctypes.c_char_p
+    lib.mhdg_status_string.argtypes = [I32]
+    lib.mhdg_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    """Device or host address of a torch tensor / numpy array (None -> NULL)."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class MacroMesh:
+    """Handle of a macro mesh on the library side, plus the torch workspaces
+    that hold its factors (kept alive for as long as the handle uses them)."""
+
+    def __init__(self, xy, tri, level, p: int):
+        lib = load_library()
+        self._lib = lib
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        if np.ndim(level) == 0:
+            lev_arr, uniform = None, int(level)
+        else:
+            lev_arr, uniform = np.ascontiguousarray(level, dtype=np.int32), 0
+        h = ctypes.c_void_p()
+        st = lib.mhdg_setup_macro_mesh(xy.shape[0], xy.ctypes.data, tri.shape[0], tri.ctypes.data,
+                                       None if lev_arr is None else lev_arr.ctypes.data, uniform,
+                                       int(p), ctypes.byref(h))
+        if st != 0:
+            raise MhdgError(st, "setup_macro_mesh rejected the mesh")
+        self.h = h
+        self.factor_ws = None
+        self.solve_ws = None
+        self.sizes = self.query()
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self._lib.mhdg_destroy(h)
+            self.h = None
+
+    def _check(self, st, what):
+        if st != 0:
+            msg = self._lib.mhdg_last_error(self.h).decode()
+            raise MhdgError(st, f"{what}: {msg}")
+
+    # ---- C ABI calls ---------------------------------------------------
+    def query(self, precision=MHDG_FP64, restart=30) -> Sizes:
+        s = Sizes()
+        self._check(self._lib.mhdg_query(self.h, precision, restart, ctypes.byref(s)), "query")
+        return s
+
+    def sample_points(self):
+        s = self.sizes
+        node = np.zeros((s.n_nodes, 2))
+        bnd = np.zeros((max(s.n_bnd_points, 1), 2))
+        self._check(self._lib.mhdg_sample_points(self.h, node.ctypes.data, bnd.ctypes.data),
+                    "sample_points")
+        return node, bnd[:s.n_bnd_points]
+
+    def factor_local(self, kappa, beta, tau=1.0, precision=MHDG_FP64, stream=None):
+        import torch
+        s = self.query(precision)
+        if self.factor_ws is None or self.factor_ws.numel() < s.factor_ws_bytes:
+            self.factor_ws = None
+            self.factor_ws = torch.empty(s.factor_ws_bytes, dtype=torch.uint8, device="cuda")
+        kap = torch.as_tensor(kappa, dtype=torch.float64, device="cuda")
+        if kap.ndim == 0:
+            kap = kap.expand(s.n_macro)
+        kap = kap.contiguous()
+        self._kappa = kap
+        self._check(self._lib.mhdg_factor_local(self.h, _ptr(kap), float(beta[0]), float(beta[1]),
+                                                float(tau), precision, _ptr(self.factor_ws),
+                                                self.factor_ws.numel(), _stream(stream)),
+                    "factor_local")
+
+    def local_matrix(self, e, out, stream=None):
+        self._check(self._lib.mhdg_local_matrix(self.h, int(e), _ptr(out), _stream(stream)),
+                    "local_matrix")
+
+    def apply_trace_operator(self, lam, out, flags=0, stream=None):
+        self._check(self._lib.mhdg_apply_trace_operator(self.h, _ptr(lam), _ptr(out), flags,
+                                                        _stream(stream)), "apply_trace_operator")
+
+    def local_solve(self, x, y, flags=0, stream=None):
+        self._check(self._lib.mhdg_local_solve(self.h, _ptr(x), _ptr(y), flags, _stream(stream)),
+                    "local_solve")
+
+    def rhs(self, f_nodes, g_bnd, fhat, flags=0, stream=None):
+        self._check(self._lib.mhdg_rhs(self.h, _ptr(f_nodes), _ptr(g_bnd), _ptr(fhat), flags,
+                                       _stream(stream)), "rhs")
+
+    def solve(self, f_nodes, g_bnd, lam, rtol=1e-10, restart=30, max_iter=10000, zero_guess=True,
+              stream=None, check=True):
+        import torch
+        s = self.query(MHDG_FP64, restart)
+        if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
+            self.solve_ws = None
+            self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
+        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1 if zero_guess else 0)
+        info = SolveInfo()
+        st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
+                                  _ptr(self.solve_ws), self.solve_ws.numel(), ctypes.byref(info),
+                                  _stream(stream))
+        if check:
+            self._check(st, "solve")
+        return info
+
+    def recover_local(self, lam, qu, flux_res=None, stream=None):
+        self._check(self._lib.mhdg_recover_local(self.h, _ptr(lam), _ptr(qu), _ptr(flux_res),
+                                                 _stream(stream)), "recover_local")
+
+
+def setup_macro_mesh(xy, tri, level, p) -> MacroMesh:
+    return MacroMesh(xy, tri, level, p)

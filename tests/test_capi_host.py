@@ -1,0 +1,139 @@
+"""Host-side tests of the C ABI: the library loads, exports every symbol the
+header declares, validates meshes, and its host-only calls (setup, query,
+sample points) agree with closed forms and with the oracle's independent
+topology.  No GPU compute is called here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import hdg
+from paper_2302_10917_amd import inputs, mhdg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    try:
+        return mhdg.load_library()
+    except ImportError as e:
+        pytest.fail(f"library not built: {e}")
+
+
+def test_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "mhdg.h")).read()
+    declared = set(re.findall(r"\b(mhdg_[a-z_]+)\s*\(", header))
+    assert declared == set(mhdg.ABI_SYMBOLS)
+    lib = _lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = _lib()
+    assert lib.mhdg_status_string(0) == b"ok"
+    assert lib.mhdg_status_string(4) == b"not converged"
+
+
+@pytest.mark.parametrize("n,r,p", [(2, 1, 2), (4, 3, 3), (3, 0, 1), (8, 2, 2)])
+def test_sizes_match_closed_forms(n, r, p):
+    xy, tri = inputs.structured_mesh(n)
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    s = m.sizes
+    P = 2 ** r * p
+    Q = (P + 1) * (P + 2) // 2
+    assert s.n_macro == 2 * n * n
+    assert s.n_interior_faces == 3 * n * n - 2 * n
+    assert s.n_faces == 3 * n * n - 2 * n + 4 * n
+    assert s.n_trace == (3 * n * n - 2 * n) * (P + 1)
+    assert s.n_nodes == 2 * n * n * Q
+    assert s.n_local == 6 * n * n * Q
+    assert s.max_local == 3 * Q
+    assert s.n_bnd_points == 4 * n * 2 ** r * (p + 2)
+    s32 = m.query(mhdg.MHDG_FP32)
+    assert s32.factor_ws_bytes < s.factor_ws_bytes
+    assert s.factor_ws_bytes >= 2 * n * n * (3 * Q) ** 2 * 8
+
+
+def test_config_sizes_of_the_benchmarks():
+    """The plain-at-scale mesh: 8192 macros, r = 3, p = 3 -> N_K = 975, 25 trace
+    nodes per face, 12,160 interior faces, 304,000 trace unknowns."""
+    xy, tri = inputs.structured_mesh(64)
+    s = mhdg.MacroMesh(xy, tri, 3, 3).sizes
+    assert (s.n_macro, s.max_local, s.n_interior_faces, s.n_trace) == (8192, 975, 12160, 304000)
+
+
+@pytest.mark.parametrize("jitter,levels", [(0.0, 1), (0.12, "mixed")])
+def test_sample_points_agree_with_oracle(jitter, levels):
+    xy, tri = inputs.structured_mesh(3, jitter=jitter, seed=5)
+    r = inputs.random_levels(len(tri), (0, 1, 2), seed=1) if levels == "mixed" else levels
+    m = mhdg.MacroMesh(xy, tri, r, 2)
+    node, bnd = m.sample_points()
+    topo = hdg.Topology(xy, tri, r, 2)
+    assert np.allclose(node, topo.all_node_xy(), atol=1e-15)
+    assert np.allclose(bnd, topo.boundary_qp_xy(), atol=1e-15)
+    assert m.sizes.n_trace == topo.n_trace
+
+
+def _setup(xy, tri, level=None, uniform=1, p=2):
+    lib = _lib()
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    lv = None if level is None else np.ascontiguousarray(level, dtype=np.int32)
+    h = ctypes.c_void_p()
+    st = lib.mhdg_setup_macro_mesh(xy.shape[0], xy.ctypes.data, tri.shape[0], tri.ctypes.data,
+                                   None if lv is None else lv.ctypes.data, uniform, p,
+                                   ctypes.byref(h))
+    if st == 0:
+        lib.mhdg_destroy(h)
+    else:
+        assert not h.value
+    return st
+
+
+def test_setup_error_codes():
+    xy, tri = inputs.structured_mesh(2)
+    assert _setup(xy, tri) == 0
+    assert _setup(xy, tri[:, ::-1]) == 2                     # clockwise
+    bad = tri.copy()
+    bad[0, 1] = bad[0, 0]
+    assert _setup(xy, bad) == 2                              # degenerate
+    assert _setup(xy, tri, p=0) == 1
+    assert _setup(xy, tri, p=5) == 1
+    assert _setup(xy, tri, uniform=6) == 1
+    assert _setup(xy, tri, level=np.full(len(tri), 7)) == 1
+    oob = tri.copy()
+    oob[1, 2] = 999
+    assert _setup(xy, oob) == 1
+    # three triangles on one edge
+    xy3 = np.array([[0, 0], [1, 0], [0.5, 1], [0.5, -1], [0.5, 0.5]], float)
+    tri3 = np.array([[0, 1, 2], [1, 0, 3], [0, 1, 4]])
+    assert _setup(xy3, tri3) == 2
+
+
+def test_calls_before_factor_are_rejected():
+    lib = _lib()
+    xy, tri = inputs.structured_mesh(2)
+    m = mhdg.MacroMesh(xy, tri, 1, 2)
+    st = lib.mhdg_apply_trace_operator(m.h, None, None, 0, None)
+    assert st == 7
+    assert b"factor_local" in lib.mhdg_last_error(m.h)
+    st = lib.mhdg_recover_local(m.h, None, None, None, None)
+    assert st == 7
+
+
+def test_gauss_legendre_points_match_library_quadrature():
+    """The library's Dirichlet points are p+2 Gauss-Legendre points per
+    segment: check their positions on a unit boundary face against the
+    closed form roots of the Legendre polynomial of degree 3 (p = 1)."""
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    tri = np.array([[0, 1, 2]])
+    m = mhdg.MacroMesh(xy, tri, 0, 1)
+    _, bnd = m.sample_points()
+    # face (0,1): y = 0, x = (1 + x_k)/2 with x_k = 0, +-sqrt(3/5)
+    t = np.sort(bnd[:3, 0])
+    expect = np.sort(0.5 * (1 + np.array([-math.sqrt(0.6), 0.0, math.sqrt(0.6)])))
+    assert np.allclose(t, expect, atol=1e-15)
