@@ -1,0 +1,231 @@
+"""Benchmark of the macro-element HDG hot path on one MI355X.
+
+A step is one pass of the whole hot path over the plain-FP64-at-scale
+workload: factor_local (assemble + pivoted LU of every A_K), solve (right-hand
+side, then GMRES on the trace system to a 1e-10 preconditioned relative
+residual) and recover_local.  Inputs (mesh metadata, kappa, f and g_D
+samples) are resident in HBM before the timed region.
+
+Workload (default): unit square, 64 x 64 squares -> 8192 macro-triangles,
+r = 3 (64 sub-triangles each), p = 3, kappa = 1e-2, a = (1, 0.5), tau = 1,
+manufactured u = exp(x) sin(2 pi y); N_K = 975, 304,000 trace unknowns.
+
+Prints one JSON line.  `value` is trace-operator applies per second over the
+whole timed job (all applies made by the K steps divided by their wall time,
+factorisation and orthogonalisation included); the roofline object is for
+the dominant kernel, the per-macro streaming solve of the trace operator,
+timed live with HIP events on its stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "trace-operator applies/s + solve time to 1e-10 res: tuned form vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: n, r, p, kappa, beta, manufactured solution
+    "plain_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5), sol="exp_sin"),
+    "plain_fp64_8macro_r1_p2": dict(n=2, r=1, p=2, kappa=1.0, beta=(1.0, 1.0), sol="sin_sin"),
+}
+
+
+def apply_bytes(m) -> float:
+    """Algorithmic HBM bytes of one launch of the apply's per-macro solve:
+    every stored LU entry once (8 N_K^2), the pivot vector (4 N_K), the
+    gathered trace and the written contribution slots (2 x 8 x 2 n_trace)."""
+    s = m.sizes
+    n_e = s.max_local  # uniform level: every macro has N_K = max_local
+    return float(s.n_macro) * (8.0 * n_e * n_e + 4.0 * n_e) + 32.0 * s.n_trace
+
+
+def cpu_baseline(xy, tri, w, lam_seed=1, n_sample=16, budget_s=15.0):
+    """The oracle (scipy LU + lu_solve per macro) applying the trace operator
+    on a bounded sample of macros, scaled to the full mesh."""
+    from oracle import hdg
+    from paper_2302_10917_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    orc = hdg.Oracle(xy, tri, w["r"], w["p"], w["kappa"], w["beta"], 1.0)
+    n_macro = orc.topo.n_macro
+    sample = np.unique(np.linspace(0, n_macro - 1, min(n_sample, n_macro)).astype(int))
+    lam = inputs.random_vector(orc.topo.n_trace, seed=lam_seed)
+    t0 = time.perf_counter()
+    for K in sample:
+        orc.lu(int(K))
+    t_setup = time.perf_counter() - t0
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        for K in sample:
+            orc.macro_contribution(int(K), lam)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s or reps >= 2000:
+            break
+    t = (time.perf_counter() - t0) / reps
+    per_apply = t * n_macro / len(sample)
+    return {"value": 1.0 / per_apply, "unit": "applies/s", "cores": cores, "kind": "oracle",
+            "sample": (f"steps 1-3 (x = B lam, lu_solve, C y) on {len(sample)} of {n_macro} "
+                       f"macros, {reps} repetitions, scaled by {n_macro / len(sample):.0f}; "
+                       f"assembly + lu_factor of the sample took {t_setup:.1f} s and is excluded"),
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="plain_fp64_8192macro_r3_p3", choices=list(WORKLOADS))
+    ap.add_argument("--restart", type=int, default=100)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=20000,
+                    help="GMRES iteration cap (a short cap is for counter runs only)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run a plain 1 GiB read + 1 GiB write "
+                         "elementwise kernel (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2302_10917_amd import inputs, mhdg
+
+    w = WORKLOADS[args.workload]
+    xy, tri = inputs.structured_mesh(w["n"])
+    ex = getattr(inputs, w["sol"])(w["kappa"], w["beta"])
+    m = mhdg.MacroMesh(xy, tri, w["r"], w["p"])
+    s = m.sizes
+    node, bnd = m.sample_points()
+    dev = "cuda"
+    f = torch.as_tensor(ex.f(node[:, 0], node[:, 1]), device=dev)
+    g = torch.as_tensor(ex.u(bnd[:, 0], bnd[:, 1]), device=dev)
+    kappa = torch.full((s.n_macro,), w["kappa"], dtype=torch.float64, device=dev)
+    lam = torch.zeros(s.n_trace, dtype=torch.float64, device=dev)
+    qu = torch.empty(s.n_local, dtype=torch.float64, device=dev)
+    print(f"[bench] {args.workload}: {s.n_macro} macros, N_K={s.max_local}, "
+          f"n_trace={s.n_trace}", file=sys.stderr, flush=True)
+
+    infos = []
+
+    def step():
+        m.factor_local(kappa, w["beta"], 1.0)
+        info = m.solve(f, g, lam, rtol=args.rtol, restart=args.restart, max_iter=args.max_iter,
+                       check=args.max_iter >= 20000)
+        m.recover_local(lam, qu)
+        infos.append(info.as_dict())
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i}: {infos[-1]['iterations']} iterations, "
+              f"{infos[-1]['t_gmres_ms']:.0f} ms GMRES", file=sys.stderr, flush=True)
+    infos.clear()
+    m.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        print(f"[bench] step {i}: {infos[-1]['iterations']} iterations, rel res "
+              f"{infos[-1]['rel_res_prec']:.2e} (true {infos[-1]['rel_res_true']:.2e})",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = m.profile(False)
+    elapsed = t1 - t0
+    applies = sum(i["n_applies"] for i in infos)
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # pure operator throughput (outside the timed steps)
+    lam_r = torch.as_tensor(inputs.random_vector(s.n_trace, seed=1), device=dev)
+    out = torch.empty_like(lam_r)
+    m.apply_trace_operator(lam_r, out, mhdg.MHDG_PRECONDITION)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.apply_reps):
+        m.apply_trace_operator(lam_r, out, mhdg.MHDG_PRECONDITION)
+    torch.cuda.synchronize()
+    apply_only = args.apply_reps / (time.perf_counter() - ta)
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # discretisation error of the solution (sanity: the manufactured solution)
+    Q = s.n_nodes // s.n_macro
+    u_h = qu.view(s.n_macro, 3, Q)[:, 2, :].reshape(-1).cpu().numpy()
+    u_err = float(np.abs(u_h - ex.u(node[:, 0], node[:, 1])).max())
+
+    ams = kt["apply_macro_solve"]
+    avg_ms = ams["ms"] / max(ams["count"], 1)
+    nbytes = apply_bytes(m)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    lu = kt["lu"]
+    result = {
+        "metric": METRIC,
+        "value": applies / elapsed,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_macro": s.n_macro, "r": w["r"], "p": w["p"],
+                   "N_K": s.max_local, "n_trace": s.n_trace, "kappa": w["kappa"],
+                   "beta": list(w["beta"]), "tau": 1.0, "rtol": args.rtol,
+                   "gmres_restart": args.restart, "form": "plain_fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "macro_solve_kernel<double> (apply steps 1-3)",
+                     "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
+                     "launches": ams["count"]},
+        "time_to_solve_s": ms_per_step / 1e3,
+        "iterations": [i["iterations"] for i in infos],
+        "rel_res_prec": [i["rel_res_prec"] for i in infos],
+        "rel_res_true": [i["rel_res_true"] for i in infos],
+        "apply_only_per_s": apply_only,
+        "kernel_ms": {k: v["ms"] / max(args.steps, 1) for k, v in kt.items()},
+        "lu_tflops": (s.n_macro * (2.0 / 3.0) * s.max_local ** 3) / (lu["ms"] / max(lu["count"], 1)
+                                                                      * 1e-3) / 1e12 if lu["count"] else None,
+        "u_max_err_vs_exact": u_err,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(xy, tri, w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -187,6 +187,18 @@ mhdg_status mhdg_solve(mhdg_mesh* mesh, const double* f_nodes, const double* g_b
 mhdg_status mhdg_recover_local(mhdg_mesh* mesh, const double* lam, double* qu, double* flux_res,
                                void* stream);
 
+/* Per-kernel timing of the hot path, for measurement.  enable = 1 clears
+ * the counters and brackets every later launch of the listed kernels with
+ * HIP events recorded on the launch stream; enable = 0 stops recording,
+ * waits for the recorded events and fills *out (may be NULL).  Index:
+ * 0 assemble, 1 lu, 2 macro solve of apply_trace_operator (steps 1-3),
+ * 3 face combine (step 4), 4 macro solve of rhs/recover/local_solve. */
+typedef struct {
+  int32_t count[5];
+  double ms[5];
+} mhdg_kernel_times;
+mhdg_status mhdg_profile(mhdg_mesh* mesh, int32_t enable, mhdg_kernel_times* out);
+
 void mhdg_destroy(mhdg_mesh* mesh);
 const char* mhdg_last_error(const mhdg_mesh* mesh);
 const char* mhdg_status_string(int32_t status);

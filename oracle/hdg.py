@@ -388,6 +388,14 @@ class Oracle:
             self._cache[K] = b
         return b
 
+    def lu(self, K):
+        """Partial-pivoting LU of A_K, computed once and reused (the in-place
+        factorisation remark of section 3.3.2)."""
+        b = self.blocks(K)
+        if getattr(b, "lu", None) is None:
+            b.lu = sla.lu_factor(b.A)
+        return b.lu
+
     def D_face(self, f):
         """D_F = sum over the macros of F of <(a.n_K - tau) mu_j, mu_l>_F."""
         topo = self.topo
@@ -472,7 +480,7 @@ class Oracle:
                 vals.append(D.ravel())
         for K in range(topo.n_macro):
             b = self.blocks(K)
-            lu = sla.lu_factor(b.A)
+            lu = self.lu(K)
             icols = self._interior_cols(K)
             if not icols:
                 continue
@@ -515,7 +523,7 @@ class Oracle:
             rhs = self.local_rhs(K, f_nodal, lamD)
             for k, o, nF in self._interior_cols(K):
                 rhs = rhs - b.B[k] @ lam[o:o + nF]
-            U.append(sla.lu_solve(sla.lu_factor(b.A), rhs))
+            U.append(sla.lu_solve(self.lu(K), rhs))
         return U
 
     # -- O12: the trace operator, steps 1-4 of the matrix-free algorithm ------
@@ -527,7 +535,7 @@ class Oracle:
         if not icols:
             return {}
         x = sum(b.B[k] @ lam[o:o + nF] for k, o, nF in icols)
-        y = sla.lu_solve(sla.lu_factor(b.A), x)
+        y = sla.lu_solve(self.lu(K), x)
         return {int(self.topo.macro_face[K, k]): b.C[k] @ y for k, _, _ in icols}
 
     def apply(self, lam, precondition=False, faces=None):
@@ -569,8 +577,7 @@ class Oracle:
 
     def local_solve(self, K, x, transpose=False):
         """A_K^-1 x (or A_K^-T x) with partial-pivoting LU."""
-        lu = sla.lu_factor(self.blocks(K).A)
-        return sla.lu_solve(lu, x, trans=1 if transpose else 0)
+        return sla.lu_solve(self.lu(K), x, trans=1 if transpose else 0)
 
     # -- O11: brute force on the unhybridised system ---------------------------
     def brute_force(self, f_nodal, g_bnd):

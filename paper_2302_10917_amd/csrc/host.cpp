@@ -40,7 +40,34 @@ struct mhdg_mesh {
   size_t ws_bytes = 0;
   FactorLayout L{};
   std::string err;
+  // kernel timing (mhdg_profile)
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+  ~mhdg_mesh() {
+    for (auto& v : ev)
+      for (auto& p : v) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
+  }
 };
+
+namespace {
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  mhdg_mesh* m;
+  int k;
+  hipStream_t s;
+  hipEvent_t b = nullptr, e = nullptr;
+  ProfScope(mhdg_mesh* m_, int k_, hipStream_t s_) : m(m_), k(k_), s(s_) {
+    if (!m->prof) return;
+    if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) { b = e = nullptr; return; }
+    (void)hipEventRecord(b, s);
+  }
+  ~ProfScope() {
+    if (!b) return;
+    (void)hipEventRecord(e, s);
+    m->ev[k].push_back({b, e});
+  }
+};
+}  // namespace
 
 namespace {
 
@@ -555,6 +582,27 @@ mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t 
   return MHDG_OK;
 }
 
+mhdg_status mhdg_profile(mhdg_mesh* M, int32_t enable, mhdg_kernel_times* out) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (out) std::memset(out, 0, sizeof(*out));
+  for (int k = 0; k < 5; ++k) {
+    for (auto& p : M->ev[k]) {
+      if (!enable && out) {
+        HIP_TRY(M, hipEventSynchronize(p.second));
+        float ms = 0.f;
+        HIP_TRY(M, hipEventElapsedTime(&ms, p.first, p.second));
+        out->count[k] += 1;
+        out->ms[k] += ms;
+      }
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+    M->ev[k].clear();
+  }
+  M->prof = enable != 0;
+  return MHDG_OK;
+}
+
 mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, mhdg_sizes* out) {
   if (!M || !out || restart < 1 || (precision != MHDG_FP64 && precision != MHDG_FP32))
     return MHDG_ERR_INVALID_ARG;
@@ -665,10 +713,16 @@ mhdg_status mhdg_factor_local(mhdg_mesh* M, const double* kappa, double beta_x, 
   // the macro order lives after the permutation vector region: reuse status region size n_macro
   MacroInfo* info = (MacroInfo*)(w + L.meta);
   HIP_TRY(M, launch_set_kappa(info, kappa, M->n_macro, s));
-  HIP_TRY(M, launch_assemble(w + L.factors, precision, info, nullptr, M->n_macro,
-                             (const double*)(w + L.tmpl), M->T, beta_x, beta_y, tau, s));
-  HIP_TRY(M, launch_lu(w + L.factors, precision, info, nullptr, M->n_macro, M->max_N,
-                       (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+  {
+    ProfScope ps(M, 0, s);
+    HIP_TRY(M, launch_assemble(w + L.factors, precision, info, nullptr, M->n_macro,
+                               (const double*)(w + L.tmpl), M->T, beta_x, beta_y, tau, s));
+  }
+  {
+    ProfScope ps(M, 1, s);
+    HIP_TRY(M, launch_lu(w + L.factors, precision, info, nullptr, M->n_macro, M->max_N,
+                         (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+  }
   std::vector<int32_t> st(M->n_macro);
   HIP_TRY(M, hipMemcpyAsync(st.data(), w + L.status, st.size() * sizeof(int32_t),
                             hipMemcpyDeviceToHost, s));
@@ -698,6 +752,7 @@ static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const 
                                    const double* xin, double* yout, hipStream_t s) {
   FactorLayout& L = M->L;
   char* w = M->ws;
+  ProfScope ps(M, mode == MODE_APPLY ? 2 : 4, s);
   HIP_TRY(M, launch_macro_solve(mode, transpose, w + L.factors, M->precision,
                                 (const MacroInfo*)(w + L.meta), nullptr, M->n_macro, M->max_N,
                                 (const int32_t*)(w + L.perm), (const double*)(w + L.tmpl), M->T,
@@ -717,6 +772,7 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* o
   mhdg_status st = run_macro_solve(M, MODE_APPLY, 0, lam, nullptr, nullptr, s);
   if (st) return st;
   FactorLayout& L = M->L;
+  ProfScope ps(M, 3, s);
   HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
                                  (const FaceInfo*)(M->ws + L.faces), M->n_int,
                                  (const double*)(M->ws + L.tmpl), M->T, M->tau, lam,

@@ -25,7 +25,7 @@ ABI_SYMBOLS = [
     "mhdg_setup_macro_mesh", "mhdg_query", "mhdg_sample_points", "mhdg_factor_local",
     "mhdg_local_matrix", "mhdg_apply_trace_operator", "mhdg_local_solve", "mhdg_rhs",
     "mhdg_solve", "mhdg_recover_local", "mhdg_destroy", "mhdg_last_error",
-    "mhdg_status_string",
+    "mhdg_status_string", "mhdg_profile",
 ]
 
 
@@ -47,6 +47,15 @@ class Sizes(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("zero_guess", ctypes.c_int32)]
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32 * 5), ("ms", ctypes.c_double * 5)]
+    NAMES = ("assemble", "lu", "apply_macro_solve", "face_combine", "other_macro_solve")
+
+    def as_dict(self):
+        return {n: {"count": int(self.count[i]), "ms": float(self.ms[i])}
+                for i, n in enumerate(self.NAMES)}
 
 
 class SolveInfo(ctypes.Structure):
@@ -84,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "mhdg_rhs": [P, P, P, P, I32, P],
         "mhdg_solve": [P, P, P, ctypes.POINTER(SolveOpts), P, P, SZ, ctypes.POINTER(SolveInfo), P],
         "mhdg_recover_local": [P, P, P, P, P],
+        "mhdg_profile": [P, I32, ctypes.POINTER(KernelTimes)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -211,6 +221,13 @@ class MacroMesh:
         if check:
             self._check(st, "solve")
         return info
+
+    def profile(self, enable: bool):
+        """Start (True) or stop (False) per-kernel event timing; stop returns
+        the accumulated counts and milliseconds per kernel class."""
+        kt = KernelTimes()
+        self._check(self._lib.mhdg_profile(self.h, 1 if enable else 0, ctypes.byref(kt)), "profile")
+        return None if enable else kt.as_dict()
 
     def recover_local(self, lam, qu, flux_res=None, stream=None):
         self._check(self._lib.mhdg_recover_local(self.h, _ptr(lam), _ptr(qu), _ptr(flux_res),
