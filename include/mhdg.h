@@ -120,8 +120,9 @@ typedef struct {
 /* Build the host-side macro mesh: faces, levels, orientation, numbering and
  * the reference templates.  xy[n_vertices][2] (host, f64), tri[n_macro][3]
  * (host, i32, counter-clockwise), level[n_macro] (host, i32, 0..5; NULL means
- * every macro has level `uniform_level`), p in 1..4.
- * Errors: INVALID_ARG (NULL, p or level out of range, vertex id out of range),
+ * every macro has level `uniform_level`), p in 1..4, local size
+ * N_K = 3 (2^r p + 1)(2^r p + 2)/2 <= 4096.
+ * Errors: INVALID_ARG (NULL, p, level or N_K out of range, vertex id out of range),
  * MESH (clockwise/degenerate triangle, an edge shared by more than 2 macros).
  * On error *out is NULL. */
 mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t n_macro,

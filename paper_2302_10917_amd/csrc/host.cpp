@@ -313,6 +313,12 @@ static void build_templates(mhdg_mesh* M) {
       en[1 * (P + 1) + s] = idx(P - s, s);      // edge 1: i + j = P, from X1 to X2
       en[2 * (P + 1) + s] = idx(0, P - s);      // edge 2: i = 0, from X2 to X0
     }
+    L.bnd_index = take((Q + 1) / 2);
+    en = reinterpret_cast<int32_t*>(&B[L.edge_node]);   // take() may have moved the blob
+    int32_t* bi = reinterpret_cast<int32_t*>(&B[L.bnd_index]);
+    for (int n = 0; n < Q; ++n) bi[n] = -1;
+    for (int k = 0; k < 3; ++k)
+      for (int s = 0; s < P; ++s) bi[en[k * (P + 1) + s]] = k * P + s;
     L.node_epos = take((3 * Q + 1) / 2);
     int32_t* ep = reinterpret_cast<int32_t*>(&B[L.node_epos]);
     for (int j = 0; j <= P; ++j)
@@ -427,6 +433,10 @@ mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t 
     int r = level ? level[e] : uniform_level;
     if (r < 0 || r > kMaxLevel) { delete M; return MHDG_ERR_INVALID_ARG; }
     M->level[e] = r;
+    {
+      const int P = (1 << r) * p;
+      if (3 * (P + 1) * (P + 2) / 2 > 4096) { delete M; return MHDG_ERR_INVALID_ARG; }
+    }
     for (int k = 0; k < 3; ++k)
       if (tri[3 * e + k] < 0 || tri[3 * e + k] >= n_vertices) { delete M; return MHDG_ERR_INVALID_ARG; }
     M->max_level = std::max(M->max_level, r);

@@ -56,6 +56,8 @@ struct LevelTemplates {
   int64_t M1, M1inv;        // (P+1)^2 1D trace mass on [0,1] and its inverse
   int64_t edge_node;        // int32 [3][P+1]: lattice node at local edge position s
   int64_t node_epos;        // int32 [Q][3]: position along local edge k, or -1
+  int64_t bnd_index;        // int32 [Q]: position b in the macro boundary loop (edge k,
+                            // position s < P -> kP + s), or -1 for nodes off the boundary
   int64_t T1[kMaxLevel + 1];// (P+1) x (P_F+1): int phi_s mu_l over [0,1], face level F >= r
   int32_t present, Q, P, N;
 };

@@ -14,6 +14,7 @@
 //   dirichlet     L2 projection of g_D onto the boundary trace spaces
 //   vector ops    deterministic two-pass dot products and Krylov updates
 #include "internal.h"
+#include "macro_solve.h"
 
 namespace mhdg {
 
@@ -155,7 +156,8 @@ template <> struct Mfma<float> {
 // k0 + t + q NT); the pivot search is a wavefront max-reduction followed by a
 // cross-wave reduction in LDS; the trailing update runs on MFMA 16x16x4 tiles.
 // perm[i] receives the original row of factor row i; status = first zero
-// pivot column + 1, or 0.
+// pivot column + 1, or 0.  On exit L (unit lower) and U are stored
+// column-major in the block: element (i, j) at j * N + i.
 template <typename T, int NT, int RPT>
 __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restrict__ info,
                                                 int32_t* perm_all, int32_t* status) {
@@ -353,111 +355,34 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
     }
     __syncthreads();
   }
+  // ---- store the factors column-major (in-place transpose by 32 x 32 tile pairs):
+  // the triangular solves then read one contiguous column per step.
+  __syncthreads();
+  {
+    __shared__ T t0[32][33];
+    __shared__ T t1[32][33];
+    const int nt = (N + 31) / 32;
+    for (int I = 0; I < nt; ++I)
+      for (int J = I; J < nt; ++J) {
+        for (int e = tid; e < 1024; e += NT) {
+          const int a = e >> 5, b = e & 31;
+          const int r = 32 * I + a, c = 32 * J + b;
+          t0[a][b] = (r < N && c < N) ? A[size_t(r) * N + c] : T(0);
+          const int r2 = 32 * J + a, c2 = 32 * I + b;
+          t1[a][b] = (r2 < N && c2 < N) ? A[size_t(r2) * N + c2] : T(0);
+        }
+        __syncthreads();
+        for (int e = tid; e < 1024; e += NT) {
+          const int a = e >> 5, b = e & 31;
+          const int r = 32 * I + a, c = 32 * J + b;
+          if (r < N && c < N) A[size_t(r) * N + c] = t1[b][a];
+          const int r2 = 32 * J + a, c2 = 32 * I + b;
+          if (r2 < N && c2 < N) A[size_t(r2) * N + c2] = t0[b][a];
+        }
+        __syncthreads();
+      }
+  }
   if (tid == 0) status[blockIdx.x] = s_status;
-}
-
-// ------------------------------------------------------------------ per-macro solves
-// x += sgn * B_k lam_F for local edge k (step 1): rows v_x, v_y, w of the
-// boundary nodes of edge k receive n_x g, n_y g, (a.n - tau) g with
-// g_s = |F| sum_l T1[s][l] lam_l (T1 couples the level-r edge space with
-// the face's trace space, both in the face's canonical direction).
-__device__ void edge_B(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
-                       const double* lamF, double sgn, double bx, double by, double tau, double* x) {
-  const LevelTemplates& L = Tp.lev[mi.level];
-  const int P = mi.P, Q = mi.Q, fl = mi.flevel[k];
-  const int nF = (1 << fl) * Tp.p + 1;
-  const double* T1 = tm + L.T1[fl];
-  const int32_t* en = ints(tm, L.edge_node);
-  const double nx = mi.nrm[2 * k], ny = mi.nrm[2 * k + 1];
-  const double an = bx * nx + by * ny - tau;
-  for (int s = threadIdx.x; s <= P; s += blockDim.x) {
-    const int sc = mi.orient[k] > 0 ? s : P - s;
-    double g = 0.0;
-    for (int l = 0; l < nF; ++l) g += T1[size_t(sc) * nF + l] * lamF[l];
-    g *= sgn * mi.len[k];
-    const int node = en[k * (P + 1) + s];
-    x[node] += nx * g;
-    x[Q + node] += ny * g;
-    x[2 * Q + node] += an * g;
-  }
-}
-
-// out_l = (C_k z)_l = |F| sum_s T1[s][l] (kappa n.q + tau u)(node s) (step 3)
-__device__ void edge_C(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
-                       const double* z, double tau, double* out) {
-  const LevelTemplates& L = Tp.lev[mi.level];
-  const int P = mi.P, Q = mi.Q, fl = mi.flevel[k];
-  const int nF = (1 << fl) * Tp.p + 1;
-  const double* T1 = tm + L.T1[fl];
-  const int32_t* en = ints(tm, L.edge_node);
-  const double kx = mi.kappa * mi.nrm[2 * k], ky = mi.kappa * mi.nrm[2 * k + 1];
-  for (int l = threadIdx.x; l < nF; l += blockDim.x) {
-    double v = 0.0;
-    for (int sc = 0; sc <= P; ++sc) {
-      const int s = mi.orient[k] > 0 ? sc : P - sc;
-      const int node = en[k * (P + 1) + s];
-      v += T1[size_t(sc) * nF + l] * (kx * z[node] + ky * z[Q + node] + tau * z[2 * Q + node]);
-    }
-    out[l] = mi.len[k] * v;
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(64) void macro_solve_kernel(int mode, const T* __restrict__ fac,
-                                                         const MacroInfo* __restrict__ info,
-                                                         const int32_t* __restrict__ perm_all,
-                                                         const double* __restrict__ tm, Templates Tp,
-                                                         double bx, double by, double tau,
-                                                         const double* __restrict__ lam,
-                                                         const double* __restrict__ xin,
-                                                         double* __restrict__ yout,
-                                                         double* __restrict__ slots) {
-  extern __shared__ double sm[];
-  const MacroInfo& mi = info[blockIdx.x];
-  const int N = mi.N, lane = threadIdx.x;
-  double* x = sm;
-  double* y = sm + N;
-  const T* A = fac + mi.fac_off;
-  const int32_t* perm = perm_all + mi.loc_off;
-  // ---- right-hand side
-  if (mode == MODE_APPLY) {
-    for (int i = lane; i < N; i += 64) x[i] = 0.0;
-  } else {
-    for (int i = lane; i < N; i += 64) x[i] = xin[mi.loc_off + i];
-  }
-  __syncthreads();
-  if (mode == MODE_APPLY || mode == MODE_RECOVER) {
-    const double sgn = mode == MODE_APPLY ? 1.0 : -1.0;
-    for (int k = 0; k < 3; ++k) {
-      if (mi.tr_off[k] >= 0) edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], sgn, bx, by, tau, x);
-      __syncthreads();
-    }
-  }
-  // ---- pivoting, forward and backward substitution (step 2)
-  for (int i = lane; i < N; i += 64) y[i] = x[perm[i]];
-  __syncthreads();
-  for (int i = 1; i < N; ++i) {
-    const T* row = A + size_t(i) * N;
-    double acc = 0.0;
-    for (int j = lane; j < i; j += 64) acc += (double)row[j] * y[j];
-    acc = wave_sum(acc);
-    if (lane == 0) y[i] -= acc;
-    __syncthreads();
-  }
-  for (int i = N - 1; i >= 0; --i) {
-    const T* row = A + size_t(i) * N;
-    double acc = 0.0;
-    for (int j = i + 1 + lane; j < N; j += 64) acc += (double)row[j] * y[j];
-    acc = wave_sum(acc);
-    if (lane == 0) y[i] = (y[i] - acc) / (double)row[i];
-    __syncthreads();
-  }
-  // ---- outputs
-  if (mode == MODE_RECOVER || mode == MODE_LOCAL)
-    for (int i = lane; i < N; i += 64) yout[mi.loc_off + i] = y[i];
-  if (mode != MODE_LOCAL)
-    for (int k = 0; k < 3; ++k)
-      if (mi.tr_off[k] >= 0) edge_C(mi, k, tm, Tp, y, tau, slots + mi.slot_off[k]);
 }
 
 // ------------------------------------------------------------------ step 4
@@ -550,11 +475,22 @@ __global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restri
     x[i] = v;
   }
   __syncthreads();
+  // Dirichlet columns of B_K, accumulated in compact boundary form then added
+  const int P = mi.P, NBD = 3 * P;
+  double* xc = x + N;
+  for (int i = threadIdx.x; i < 3 * NBD; i += 64) xc[i] = 0.0;
+  __syncthreads();
   for (int k = 0; k < 3; ++k) {
     if (mi.bnd_face[k] >= 0)
-      edge_B(mi, k, tm, Tp, lamD + bf[mi.bnd_face[k]].lam_off, -1.0, bx, by, tau, x);
+      edge_B(mi, k, tm, Tp, lamD + bf[mi.bnd_face[k]].lam_off, -1.0, bx, by, tau, xc);
     __syncthreads();
   }
+  const int32_t* en = ints(tm, Tp.lev[mi.level].edge_node);
+  for (int b = threadIdx.x; b < NBD; b += 64) {
+    const int node = en[(b / P) * (P + 1) + b % P];
+    for (int f = 0; f < 3; ++f) x[f * Q + node] += xc[f * NBD + b];
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < N; i += 64) R[mi.loc_off + i] = x[i];
 }
 
@@ -677,10 +613,44 @@ hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo*
                             const double* tmpl, const Templates& T, const double* f,
                             const double* lamD, double bx, double by, double tau, double* R,
                             hipStream_t s) {
-  size_t lds = size_t(max_present_N(T)) * sizeof(double);
+  int maxP = 0;
+  for (int r = 0; r <= kMaxLevel; ++r)
+    if (T.lev[r].present && T.lev[r].P > maxP) maxP = T.lev[r].P;
+  size_t lds = size_t(max_present_N(T) + 9 * maxP) * sizeof(double);
   hipLaunchKernelGGL(local_rhs_kernel, dim3((unsigned)n), dim3(64), lds, s, info, bf, tmpl, T, f,
                      lamD, bx, by, tau, R);
   return hipGetLastError();
+}
+
+// instantiated in solve_nq_*.hip
+#define MS_DECL(T_, Q_)                                                                        \
+  extern template void macro_solve_launch<T_, Q_>(int, const void*, const MacroInfo*, int64_t,  \
+                                                  size_t, const int32_t*, const double*,        \
+                                                  const Templates&, double, double, double,     \
+                                                  const double*, const double*, double*,        \
+                                                  double*, hipStream_t);
+#define MS_DECL2(Q_) MS_DECL(double, Q_) MS_DECL(float, Q_)
+MS_DECL2(1) MS_DECL2(2) MS_DECL2(3) MS_DECL2(5) MS_DECL2(8) MS_DECL2(16) MS_DECL2(27)
+MS_DECL2(58)
+#undef MS_DECL2
+#undef MS_DECL
+
+template <typename T>
+static hipError_t macro_solve_dispatch(int nq, int mode, const void* fac, const MacroInfo* info,
+                                       int64_t n, size_t lds, const int32_t* perm,
+                                       const double* tmpl, const Templates& Tp, double bx,
+                                       double by, double tau, const double* lam,
+                                       const double* xin, double* yout, double* slots,
+                                       hipStream_t s) {
+#define MS_CASE(Q_)                                                                         \
+  if (nq <= Q_) {                                                                           \
+    macro_solve_launch<T, Q_>(mode, fac, info, n, lds, perm, tmpl, Tp, bx, by, tau, lam, xin, \
+                              yout, slots, s);                                              \
+    return hipGetLastError();                                                               \
+  }
+  MS_CASE(1) MS_CASE(2) MS_CASE(3) MS_CASE(5) MS_CASE(8) MS_CASE(16) MS_CASE(27) MS_CASE(58)
+#undef MS_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int precision,
@@ -689,14 +659,16 @@ hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int prec
                               double bx, double by, double tau, const double* lam,
                               const double* xin, double* yout, double* slots, hipStream_t s) {
   (void)transpose;
-  size_t lds = size_t(2) * max_N * sizeof(double);
+  int maxP = 0;
+  for (int r = 0; r <= kMaxLevel; ++r)
+    if (T.lev[r].present && T.lev[r].P > maxP) maxP = T.lev[r].P;
+  const size_t lds = size_t(18) * maxP * sizeof(double);
+  const int nq = (max_N + 63) / 64;
   if (precision == 1)
-    hipLaunchKernelGGL(macro_solve_kernel<float>, dim3((unsigned)n), dim3(64), lds, s, mode,
-                       (const float*)fac, info, perm, tmpl, T, bx, by, tau, lam, xin, yout, slots);
-  else
-    hipLaunchKernelGGL(macro_solve_kernel<double>, dim3((unsigned)n), dim3(64), lds, s, mode,
-                       (const double*)fac, info, perm, tmpl, T, bx, by, tau, lam, xin, yout, slots);
-  return hipGetLastError();
+    return macro_solve_dispatch<float>(nq, mode, fac, info, n, lds, perm, tmpl, T, bx, by, tau,
+                                       lam, xin, yout, slots, s);
+  return macro_solve_dispatch<double>(nq, mode, fac, info, n, lds, perm, tmpl, T, bx, by, tau,
+                                      lam, xin, yout, slots, s);
 }
 
 hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const double* tmpl,
