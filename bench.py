@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plain_fp64_8192macro_r3_p3", choices=list(WORKLOADS))
-    ap.add_argument("--restart", type=int, default=100)
+    ap.add_argument("--restart", type=int, default=2000)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -495,30 +495,37 @@ __global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restri
 }
 
 // ------------------------------------------------------------------ vector ops
+// Row chunks of the Krylov vectors handled by one partial dot product.
+constexpr int kDotChunk = 8192;
+
 int dots_nblk(int64_t n) {
-  int64_t b = (n + 4095) / 4096;
-  return (int)(b < 1 ? 1 : (b > 512 ? 512 : b));
+  int64_t b = (n + kDotChunk - 1) / kDotChunk;
+  return (int)(b < 1 ? 1 : b);
 }
 
+// partial[c * nblk + blk] = sum over row chunk blk of V[c][i] w[i]: one
+// wavefront per (column, chunk), coalesced loads, a fixed-order reduction.
 __global__ __launch_bounds__(256) void dots_partial_kernel(const double* __restrict__ V, int64_t ld,
                                                            int ncols, const double* __restrict__ w,
                                                            int64_t n, double* __restrict__ partial) {
-  __shared__ double red[256];
   const int nblk = gridDim.x;
-  for (int c = 0; c < ncols; ++c) {
-    const double* v = V + c * ld;
-    double acc = 0.0;
-    for (int64_t i = blockIdx.x * int64_t(256) + threadIdx.x; i < n; i += int64_t(nblk) * 256)
-      acc += v[i] * w[i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[c * nblk + blockIdx.x] = red[0];
-    __syncthreads();
+  const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= ncols) return;
+  const double* v = V + c * ld;
+  const int64_t i0 = int64_t(blockIdx.x) * kDotChunk;
+  const int64_t i1 = i0 + kDotChunk < n ? i0 + kDotChunk : n;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t i = i0 + lane;
+  for (; i + 192 < i1; i += 256) {
+    a0 += v[i] * w[i];
+    a1 += v[i + 64] * w[i + 64];
+    a2 += v[i + 128] * w[i + 128];
+    a3 += v[i + 192] * w[i + 192];
   }
+  for (; i < i1; i += 64) a0 += v[i] * w[i];
+  const double acc = wave_sum((a0 + a1) + (a2 + a3));
+  if (lane == 0) partial[c * nblk + blockIdx.x] = acc;
 }
 
 __global__ __launch_bounds__(64) void dots_final_kernel(const double* __restrict__ partial, int nblk,
@@ -535,9 +542,16 @@ __global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ld, int nc
                                 double sign) {
   int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (i >= n) return;
-  double acc = 0.0;
-  for (int c = 0; c < ncols; ++c) acc += V[c * ld + i] * h[c];
-  w[i] += sign * acc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int c = 0;
+  for (; c + 3 < ncols; c += 4) {
+    a0 += V[c * ld + i] * h[c];
+    a1 += V[(c + 1) * ld + i] * h[c + 1];
+    a2 += V[(c + 2) * ld + i] * h[c + 2];
+    a3 += V[(c + 3) * ld + i] * h[c + 3];
+  }
+  for (; c < ncols; ++c) a0 += V[c * ld + i] * h[c];
+  w[i] += sign * ((a0 + a1) + (a2 + a3));
 }
 
 __global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y,
@@ -692,7 +706,8 @@ hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double*
 
 hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, int64_t n,
                        double* partial, int nblk, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk), dim3(256), 0, s, V, ld, ncols, w, n, partial);
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk, (ncols + 3) / 4), dim3(256), 0, s, V, ld, ncols,
+                     w, n, partial);
   hipLaunchKernelGGL(dots_final_kernel, dim3(ncols), dim3(64), 0, s, partial, nblk, out);
   return hipGetLastError();
 }

@@ -73,8 +73,12 @@ __device__ inline void edge_C(const MacroInfo& mi, int k, const double* tm, cons
 // each step broadcasts one solved entry (readlane) and updates the remaining
 // entries with one contiguous column of L or U, so the loads of a column do
 // not wait on any reduction and the factor streams from HBM exactly once.
+// Resident wavefronts per SIMD the register budget is sized for: all macros
+// of a large mesh should be resident at once (8 waves/SIMD = 64 VGPRs).
+template <int NQ> struct SolveOccupancy { static constexpr int waves = NQ <= 16 ? 8 : (NQ <= 27 ? 4 : 2); };
+
 template <typename T, int NQ>
-__global__ __launch_bounds__(64) void macro_solve_kernel(int mode, const T* __restrict__ fac,
+__global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_kernel(int mode, const T* __restrict__ fac,
                                                          const MacroInfo* __restrict__ info,
                                                          const int32_t* __restrict__ perm_all,
                                                          const double* __restrict__ tm, Templates Tp,
