@@ -180,6 +180,17 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # reference: a plain streaming read of 16 GiB on this device (context for the roofline)
+    buf = torch.ones(1 << 31, dtype=torch.float64, device=dev)
+    torch.sum(buf)
+    torch.cuda.synchronize()
+    tr = time.perf_counter()
+    for _ in range(5):
+        torch.sum(buf)
+    torch.cuda.synchronize()
+    stream_gbs = 5 * buf.numel() * 8 / (time.perf_counter() - tr) / 1e9
+    del buf
+
     # discretisation error of the solution (sanity: the manufactured solution)
     Q = s.n_nodes // s.n_macro
     u_h = qu.view(s.n_macro, 3, Q)[:, 2, :].reshape(-1).cpu().numpy()
@@ -217,6 +228,7 @@ def main():
         "rel_res_prec": [i["rel_res_prec"] for i in infos],
         "rel_res_true": [i["rel_res_true"] for i in infos],
         "apply_only_per_s": apply_only,
+        "stream_read_gbs": stream_gbs,
         "kernel_ms": {k: v["ms"] / max(args.steps, 1) for k, v in kt.items()},
         "lu_tflops": (s.n_macro * (2.0 / 3.0) * s.max_local ** 3) / (lu["ms"] / max(lu["count"], 1)
                                                                       * 1e-3) / 1e12 if lu["count"] else None,

@@ -630,7 +630,10 @@ mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, m
   // factor block offsets are padded to 64 elements per macro
   size_t es = precision == MHDG_FP32 ? 4 : 8;
   const MacroInfo& last = M->macros.back();
-  size_t nf = size_t(last.fac_off) + size_t(last.N) * last.N;
+  // guard tail: the column-streaming solve reads whole 64-row chunks (up to
+  // 64 x 64 rows) past a column start; reads past a block land in the next
+  // block or in this tail and are discarded
+  size_t nf = size_t(last.fac_off) + size_t(last.N) * last.N + kFactorGuard;
   out->factor_ws_bytes = align_up(L.factors + nf * es);
   out->solve_ws_bytes = solve_bytes(M, restart);
   return MHDG_OK;

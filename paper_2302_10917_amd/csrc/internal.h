@@ -8,6 +8,7 @@
 namespace mhdg {
 
 constexpr int kMaxLevel = 5;
+constexpr int kFactorGuard = 64 * 64;  // elements of readable padding after the last factor block
 
 // Per-macro data, built on the host at setup and copied into the factor
 // workspace by factor_local.  All doubles first so the layout has no holes.

@@ -75,6 +75,7 @@ __device__ inline void edge_C(const MacroInfo& mi, int k, const double* tm, cons
 // not wait on any reduction and the factor streams from HBM exactly once.
 // Resident wavefronts per SIMD the register budget is sized for: all macros
 // of a large mesh should be resident at once (8 waves/SIMD = 64 VGPRs).
+constexpr int kLoadGroup = 8;
 template <int NQ> struct SolveOccupancy { static constexpr int waves = NQ <= 16 ? 8 : (NQ <= 27 ? 4 : 2); };
 
 template <typename T, int NQ>
@@ -128,10 +129,30 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
       const int j = 64 * q + jj;
       const double yj = readlane_d(y[q], jj);
       const T* col = A + size_t(j) * N;
+      // loads are unconditional and issued in groups of kLoadGroup chunks, so a
+      // column costs one or two memory latencies and the in-flight values fit
+      // the register budget.  Rows past N land in the next macro's block or in
+      // the workspace's guard tail; values outside the triangle are discarded
+      // by the select.
 #pragma unroll
-      for (int qq = q; qq < NQ; ++qq) {
-        const int r = lane + 64 * qq;
-        if (r > j && r < N) y[qq] -= (double)col[r] * yj;
+      for (int g = q; g < NQ; g += kLoadGroup) {
+        double a[kLoadGroup];
+#pragma unroll
+        for (int t = 0; t < kLoadGroup; ++t) {
+          const int r = lane + 64 * (g + t);
+          // lanes outside the triangle of the first chunk, and past N in the
+          // last chunk, re-read a row whose cache line is fetched anyway
+          int rr = r;
+          if (g + t == q) rr = r > j ? r : j + 1;
+          if (g + t == NQ - 1) rr = rr < N ? rr : N - 1;
+          a[t] = (g + t < NQ) ? (double)col[rr] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kLoadGroup; ++t) {
+          const int r = lane + 64 * (g + t);
+          if (g + t < NQ) y[g + t] -= ((r > j && r < N) ? a[t] : 0.0) * yj;
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
@@ -145,9 +166,21 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
       const double zj = readlane_d(y[q], jj) / (double)col[j];
       if (lane == jj) y[q] = zj;
 #pragma unroll
-      for (int qq = 0; qq <= q; ++qq) {
-        const int r = lane + 64 * qq;
-        if (r < j) y[qq] -= (double)col[r] * zj;
+      for (int g = 0; g <= q; g += kLoadGroup) {
+        double a[kLoadGroup];
+#pragma unroll
+        for (int t = 0; t < kLoadGroup; ++t) {
+          const int r = lane + 64 * (g + t);
+          int rr = r;
+          if (g + t == q) rr = r < j ? r : (j > 0 ? j - 1 : 0);
+          a[t] = (g + t <= q) ? (double)col[rr] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kLoadGroup; ++t) {
+          const int r = lane + 64 * (g + t);
+          if (g + t <= q) y[g + t] -= (r < j ? a[t] : 0.0) * zj;
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
