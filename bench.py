@@ -33,19 +33,27 @@ METRIC = "trace-operator applies/s + solve time to 1e-10 res: tuned form vs plai
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    # name: n, r, p, kappa, beta, manufactured solution
-    "plain_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5), sol="exp_sin"),
-    "plain_fp64_8macro_r1_p2": dict(n=2, r=1, p=2, kappa=1.0, beta=(1.0, 1.0), sol="sin_sin"),
+    # name: n, r, p, kappa, beta, manufactured solution, factor precision
+    "plain_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5), sol="exp_sin",
+                                       precision="fp64"),
+    "plain_fp64_8macro_r1_p2": dict(n=2, r=1, p=2, kappa=1.0, beta=(1.0, 1.0), sol="sin_sin",
+                                    precision="fp64"),
+    # precision configuration: same mesh, kappa = 1e-3, FP32 factors + FP64 refinement
+    "fp32ir_8192macro_r3_p3_kappa1e-3": dict(n=64, r=3, p=3, kappa=1e-3, beta=(1.0, 0.5),
+                                             sol="exp_sin", precision="fp32"),
+    "plain_fp64_8192macro_r3_p3_kappa1e-3": dict(n=64, r=3, p=3, kappa=1e-3, beta=(1.0, 0.5),
+                                                 sol="exp_sin", precision="fp64"),
 }
 
 
-def apply_bytes(m) -> float:
+def apply_bytes(m, elem_bytes=8) -> float:
     """Algorithmic HBM bytes of one launch of the apply's per-macro solve:
-    every stored LU entry once (8 N_K^2), the pivot vector (4 N_K), the
-    gathered trace and the written contribution slots (2 x 8 x 2 n_trace)."""
+    every stored LU entry once (b N_K^2, b = 8 for FP64 factors, 4 for FP32),
+    the pivot vector (4 N_K), the gathered trace and the written contribution
+    slots (2 x 8 x 2 n_trace)."""
     s = m.sizes
     n_e = s.max_local  # uniform level: every macro has N_K = max_local
-    return float(s.n_macro) * (8.0 * n_e * n_e + 4.0 * n_e) + 32.0 * s.n_trace
+    return float(s.n_macro) * (elem_bytes * n_e * n_e + 4.0 * n_e) + 32.0 * s.n_trace
 
 
 def cpu_baseline(xy, tri, w, lam_seed=1, n_sample=16, budget_s=15.0):
@@ -101,6 +109,11 @@ def main():
     ap.add_argument("--workload", default="plain_fp64_8192macro_r3_p3", choices=list(WORKLOADS))
     ap.add_argument("--restart", type=int, default=2000)
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--inner-rtol", type=float, default=1e-5,
+                    help="inner GMRES tolerance per refinement step (FP32 factors)")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="after the timed steps, solve again with FP64 factors and report the "
+                         "relative differences of lambda, q and u")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=20000,
@@ -133,11 +146,14 @@ def main():
           f"n_trace={s.n_trace}", file=sys.stderr, flush=True)
 
     infos = []
+    Q = s.n_nodes // s.n_macro
+
+    prec = mhdg.MHDG_FP32 if w["precision"] == "fp32" else mhdg.MHDG_FP64
 
     def step():
-        m.factor_local(kappa, w["beta"], 1.0)
+        m.factor_local(kappa, w["beta"], 1.0, precision=prec)
         info = m.solve(f, g, lam, rtol=args.rtol, restart=args.restart, max_iter=args.max_iter,
-                       check=args.max_iter >= 20000)
+                       check=args.max_iter >= 20000, inner_rtol=args.inner_rtol)
         m.recover_local(lam, qu)
         infos.append(info.as_dict())
 
@@ -162,6 +178,7 @@ def main():
     applies = sum(i["n_applies"] for i in infos)
     ms_per_step = 1e3 * elapsed / args.steps
 
+    print("[bench] timed steps done; operator-only throughput", file=sys.stderr, flush=True)
     # pure operator throughput (outside the timed steps)
     lam_r = torch.as_tensor(inputs.random_vector(s.n_trace, seed=1), device=dev)
     out = torch.empty_like(lam_r)
@@ -192,13 +209,28 @@ def main():
     del buf
 
     # discretisation error of the solution (sanity: the manufactured solution)
-    Q = s.n_nodes // s.n_macro
     u_h = qu.view(s.n_macro, 3, Q)[:, 2, :].reshape(-1).cpu().numpy()
     u_err = float(np.abs(u_h - ex.u(node[:, 0], node[:, 1])).max())
 
+    cmp = None
+    if args.compare_fp64 and prec != mhdg.MHDG_FP64:
+        print("[bench] reference solve with FP64 factors (rtol 1e-12)", file=sys.stderr, flush=True)
+        lam_lp, qu_lp = lam.clone(), qu.clone()
+        m.factor_local(kappa, w["beta"], 1.0, precision=mhdg.MHDG_FP64)
+        ref = m.solve(f, g, lam, rtol=1e-12, restart=args.restart, max_iter=args.max_iter)
+        print(f"[bench] reference: {ref.iterations} iterations", file=sys.stderr, flush=True)
+        m.recover_local(lam, qu)
+        qv, qv_lp = qu.view(s.n_macro, 3, Q), qu_lp.view(s.n_macro, 3, Q)
+
+        def rd(a, b_):
+            return float(torch.linalg.norm(a - b_) / torch.linalg.norm(b_))
+        cmp = {"reference": "FP64 factors, GMRES rtol 1e-13",
+               "lambda": rd(lam_lp, lam), "q": rd(qv_lp[:, :2], qv[:, :2]),
+               "u": rd(qv_lp[:, 2], qv[:, 2])}
+
     ams = kt["apply_macro_solve"]
     avg_ms = ams["ms"] / max(ams["count"], 1)
-    nbytes = apply_bytes(m)
+    nbytes = apply_bytes(m, 4 if prec == mhdg.MHDG_FP32 else 8)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     lu = kt["lu"]
     result = {
@@ -212,19 +244,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == mhdg.MHDG_FP64 else "f32 factors, f64 refinement",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_macro": s.n_macro, "r": w["r"], "p": w["p"],
                    "N_K": s.max_local, "n_trace": s.n_trace, "kappa": w["kappa"],
                    "beta": list(w["beta"]), "tau": 1.0, "rtol": args.rtol,
-                   "gmres_restart": args.restart, "form": "plain_fp64"},
+                   "gmres_restart": args.restart,
+                   "form": "plain_fp64" if prec == mhdg.MHDG_FP64 else "fp32_factors_fp64_ir"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "macro_solve_kernel<double> (apply steps 1-3)",
+                     "kernel": ("macro_solve_kernel<double>" if prec == mhdg.MHDG_FP64
+                                else "macro_solve_kernel<float>") + " (apply steps 1-3)",
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
                      "launches": ams["count"]},
         "time_to_solve_s": ms_per_step / 1e3,
         "iterations": [i["iterations"] for i in infos],
+        "outer_iterations": [i["outer_iterations"] for i in infos],
+        "applies_per_solve": [i["n_applies"] for i in infos],
+        "vs_fp64": cmp,
         "rel_res_prec": [i["rel_res_prec"] for i in infos],
         "rel_res_true": [i["rel_res_true"] for i in infos],
         "apply_only_per_s": apply_only,

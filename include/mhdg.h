@@ -104,17 +104,24 @@ typedef struct {
 typedef struct {
   double rtol;                /* stop when ||D^-1 r|| <= rtol ||D^-1 f^||      */
   int32_t restart;            /* Krylov length per cycle (>= 1)                */
-  int32_t max_iter;           /* total iterations                              */
+  int32_t max_iter;           /* total (inner) GMRES iterations                */
   int32_t zero_guess;         /* 1: start from lambda = 0; 0: use lam on entry */
+  int32_t max_outer;          /* reduced-precision factors: refinement steps (0: 30) */
+  double inner_rtol;          /* reduced-precision factors: inner GMRES relative
+                                 tolerance per refinement step (0: 1e-5)      */
 } mhdg_solve_opts;
 
 typedef struct {
-  int32_t iterations;
+  int32_t iterations;         /* GMRES iterations (all inner solves)           */
   int32_t status;             /* mhdg_status of the solve                      */
-  double rel_res_prec;        /* final ||D^-1 (f^ - S lam)|| / ||D^-1 f^||     */
-  double rel_res_true;        /* final ||f^ - S lam|| / ||f^||                 */
+  double rel_res_prec;        /* final ||D^-1 (f^ - S lam)|| / ||D^-1 f^||; with
+                                 reduced-precision factors the FP64 residual of
+                                 the whole system condensed onto the trace     */
+  double rel_res_true;        /* final ||f^ - S lam|| / ||f^|| (FP64 factors;
+                                 -1 with reduced-precision factors)            */
   double t_rhs_ms, t_gmres_ms;
-  int32_t n_applies;
+  int32_t n_applies;          /* operator applies + per-macro solve passes     */
+  int32_t outer_iterations;   /* refinement steps (reduced-precision factors)  */
 } mhdg_solve_info;
 
 /* Build the host-side macro mesh: faces, levels, orientation, numbering and
@@ -172,7 +179,12 @@ mhdg_status mhdg_rhs(mhdg_mesh* mesh, const double* f_nodes, const double* g_bnd
                      int32_t flags, void* stream);
 
 /* Solve S lam = f^ by GMRES(restart) left-preconditioned with D^-1, all
- * vector work in FP64 on the device.  Calls mhdg_rhs first.  lam: device
+ * vector work in FP64 on the device.  Calls mhdg_rhs first.  When the
+ * factors are FP32 the solve is an FP64 iterative refinement of the whole
+ * hybridised system: the residual (R - A U - B lam, -(C U + D lam)) is formed
+ * matrix-free in FP64 and each correction solves the condensed system with
+ * the FP32 factors (inner GMRES to opts->inner_rtol), until the condensed
+ * FP64 residual is below rtol relative to its initial value.  lam: device
  * f64[n_trace] (initial guess unless opts->zero_guess, then the solution).
  * ws: device workspace of at least solve_ws_bytes (mhdg_query with the same
  * restart).  info (host) may be NULL.  Returns NOT_CONVERGED if max_iter
@@ -182,7 +194,8 @@ mhdg_status mhdg_solve(mhdg_mesh* mesh, const double* f_nodes, const double* g_b
                        mhdg_solve_info* info, void* stream);
 
 /* Local recovery U_K = A_K^-1 (R_K - B_K lam_K) into qu (device
- * f64[n_local]) and, if flux_res is not NULL, the transmission residual
+ * f64[n_local]; with FP32 factors refined in FP64 until the local residual
+ * stops decreasing) and, if flux_res is not NULL, the transmission residual
  * sum_K C_K U_K + D_F lam_F per interior trace dof (device f64[n_trace]).
  * Needs mhdg_rhs (or solve) to have run since factor_local. */
 mhdg_status mhdg_recover_local(mhdg_mesh* mesh, const double* lam, double* qu, double* flux_res,

@@ -271,6 +271,8 @@ static void build_templates(mhdg_mesh* M) {
     L.Mhat = take(size_t(Q) * Q);
     L.E0 = take(size_t(Q) * Q);
     L.E1 = take(size_t(Q) * Q);
+    L.E0T = take(size_t(Q) * Q);
+    L.E1T = take(size_t(Q) * Q);
     double* Mh = &B[L.Mhat];
     double* E0 = &B[L.E0];
     double* E1 = &B[L.E1];
@@ -298,6 +300,11 @@ static void build_templates(mhdg_mesh* M) {
             }
         }
     }
+    for (int a = 0; a < Q; ++a)
+      for (int b = 0; b < Q; ++b) {
+        B[L.E0T + size_t(b) * Q + a] = E0[size_t(a) * Q + b];
+        B[L.E1T + size_t(b) * Q + a] = E1[size_t(a) * Q + b];
+      }
     // 1D masses
     std::vector<double> M1 = mass1d(p, r), M1i = M1;
     invert(M1i, P + 1);
@@ -375,6 +382,8 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   L.R = o;      o = align_up(o + size_t(M->n_local) * sizeof(double));
   L.slots = o;  o = align_up(o + size_t(M->n_slots) * sizeof(double));
   L.lamD = o;   o = align_up(o + size_t(std::max<int64_t>(M->n_lamD, 1)) * sizeof(double));
+  L.work1 = o;  o = align_up(o + size_t(M->n_local) * sizeof(double));
+  L.work2 = o;  o = align_up(o + size_t(M->n_local) * sizeof(double));
   L.factors = o;
   size_t es = precision == MHDG_FP32 ? 4 : 8;
   size_t nf = 0;
@@ -385,13 +394,124 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   return L;
 }
 
-static size_t solve_bytes(const mhdg_mesh* M, int restart) {
-  size_t n = size_t(M->n_trace);
-  size_t vecs = size_t(restart + 1) + 6;  // Krylov basis + w, r, fhat, pfhat, tmp, x0
-  size_t nblk = size_t(dots_nblk(M->n_trace));
-  return align_up(vecs * align_up(n * sizeof(double))) +
-         align_up(nblk * size_t(restart + 2) * sizeof(double)) + align_up(size_t(restart + 2) * 8) * 2;
+static size_t solve_bytes_impl(const mhdg_mesh* M, int R);
+static size_t solve_bytes(const mhdg_mesh* M, int restart) { return solve_bytes_impl(M, restart); }
+
+// ---------------------------------------------------------------- GMRES
+namespace {
+
+// Device vectors of one solve, carved from the caller's solve workspace.
+struct Gm {
+  int64_t n = 0, ld = 0;
+  int nblk = 1;
+  double *V = nullptr, *wv = nullptr, *rv = nullptr, *tv = nullptr, *fh = nullptr, *pf = nullptr;
+  double *partial = nullptr, *hdev = nullptr, *ydev = nullptr;
+  double *U = nullptr, *dl = nullptr, *cl = nullptr;  // precision-refinement state
+};
+
+mhdg_status dot(mhdg_mesh* M, Gm& G, const double* a, const double* b, double* host, hipStream_t s) {
+  HIP_TRY(M, launch_dots(a, G.ld, 1, b, G.n, G.partial, G.nblk, G.hdev, s));
+  HIP_TRY(M, hipMemcpyAsync(host, G.hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(M, hipStreamSynchronize(s));
+  return MHDG_OK;
 }
+
+// Left-preconditioned restarted GMRES on D^-1 S x = b (b already
+// preconditioned) with classical Gram-Schmidt applied twice (CGS2); all
+// vectors and inner products in FP64 on the device, the Hessenberg
+// least-squares problem by Givens rotations on the host.  Stops when
+// ||b - D^-1 S x|| <= rtol * bref.  x holds the initial guess.
+mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, double bref, double* x, double rtol,
+                  int R, int max_iter, int& iters, double& rel, int& applies, bool& converged,
+                  hipStream_t s) {
+  const int64_t n = G.n, ld = G.ld;
+  mhdg_status st;
+  std::vector<double> H((R + 1) * R), cs(R), sn(R), g(R + 1), h(R + 2), y(R);
+  iters = 0;
+  converged = false;
+  while (true) {
+    if ((st = mhdg_apply_trace_operator(M, x, G.tv, MHDG_PRECONDITION, s))) return st;
+    ++applies;
+    HIP_TRY(M, launch_scale_copy(1.0, b, G.rv, n, s));
+    HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, n, s));
+    double rn2;
+    if ((st = dot(M, G, G.rv, G.rv, &rn2, s))) return st;
+    const double beta = std::sqrt(rn2);
+    rel = beta / bref;
+    if (rel <= rtol || iters >= max_iter) { converged = rel <= rtol; return MHDG_OK; }
+    HIP_TRY(M, launch_scale_copy(1.0 / beta, G.rv, G.V, n, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < R && iters < max_iter; ++j) {
+      ++iters;
+      if ((st = mhdg_apply_trace_operator(M, G.V + j * ld, G.wv, MHDG_PRECONDITION, s))) return st;
+      ++applies;
+      for (int pass = 0; pass < 2; ++pass) {
+        HIP_TRY(M, launch_dots(G.V, ld, j + 1, G.wv, n, G.partial, G.nblk, G.hdev, s));
+        HIP_TRY(M, launch_gemv_sub(G.V, ld, j + 1, G.hdev, G.wv, n, -1.0, s));
+        HIP_TRY(M, hipMemcpyAsync(h.data(), G.hdev, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(M, hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) H[i * R + j] = (pass ? H[i * R + j] : 0.0) + h[i];
+      }
+      double hn2;
+      if ((st = dot(M, G, G.wv, G.wv, &hn2, s))) return st;
+      const double hn = std::sqrt(hn2);
+      H[(j + 1) * R + j] = hn;
+      if (hn > 0) HIP_TRY(M, launch_scale_copy(1.0 / hn, G.wv, G.V + (j + 1) * ld, n, s));
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i * R + j], bb = H[(i + 1) * R + j];
+        H[i * R + j] = cs[i] * a + sn[i] * bb;
+        H[(i + 1) * R + j] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = H[j * R + j], bb = H[(j + 1) * R + j];
+      const double rr = std::hypot(a, bb);
+      cs[j] = rr == 0 ? 1.0 : a / rr;
+      sn[j] = rr == 0 ? 0.0 : bb / rr;
+      H[j * R + j] = rr;
+      H[(j + 1) * R + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      rel = std::fabs(g[j + 1]) / bref;
+      if (rel <= rtol || hn == 0.0) { ++j; break; }
+    }
+    for (int i = j - 1; i >= 0; --i) {
+      double v = g[i];
+      for (int k = i + 1; k < j; ++k) v -= H[i * R + k] * y[k];
+      y[i] = v / H[i * R + i];
+    }
+    HIP_TRY(M, hipMemcpyAsync(G.ydev, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(M, launch_gemv_sub(G.V, ld, j, G.ydev, x, n, 1.0, s));
+    HIP_TRY(M, hipStreamSynchronize(s));
+  }
+}
+
+mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
+  G.n = M->n_trace;
+  char* w = (char*)ws;
+  const size_t vb = align_up(size_t(G.n) * sizeof(double));
+  G.ld = int64_t(vb / sizeof(double));
+  G.V = (double*)w;
+  G.wv = (double*)(w + vb * (R + 1));
+  G.rv = (double*)(w + vb * (R + 2));
+  G.fh = (double*)(w + vb * (R + 3));
+  G.pf = (double*)(w + vb * (R + 4));
+  G.tv = (double*)(w + vb * (R + 5));
+  G.dl = (double*)(w + vb * (R + 6));
+  G.cl = (double*)(w + vb * (R + 7));
+  size_t off = align_up(vb * (R + 8));
+  G.nblk = dots_nblk(G.n);
+  G.partial = (double*)(w + off);
+  off += align_up(size_t(G.nblk) * (R + 2) * sizeof(double));
+  G.hdev = (double*)(w + off);
+  off += align_up(size_t(R + 2) * 8);
+  G.ydev = (double*)(w + off);
+  off += align_up(size_t(R + 2) * 8);
+  G.U = (double*)(w + off);
+  return MHDG_OK;
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------- C ABI
 extern "C" {
@@ -838,6 +958,43 @@ mhdg_status mhdg_recover_local(mhdg_mesh* M, const double* lam, double* qu, doub
   FactorLayout& L = M->L;
   mhdg_status st = run_macro_solve(M, MODE_RECOVER, 0, lam, (const double*)(M->ws + L.R), qu, s);
   if (st) return st;
+  if (M->precision != MHDG_FP64) {
+    // local iterative refinement: r = R - A U - B lam in FP64 (matrix-free),
+    // U += A~^-1 r with the low-precision factors, until r stops decreasing
+    char* fw = M->ws;
+    const double* tm = (const double*)(fw + L.tmpl);
+    const MacroInfo* info_d = (const MacroInfo*)(fw + L.meta);
+    double* r = (double*)(fw + L.work1);
+    double* d = (double*)(fw + L.work2);
+    const int64_t nl = M->n_local;
+    Gm G;
+    G.n = nl;
+    G.ld = nl;
+    G.nblk = dots_nblk(nl);
+    // scratch for the norms: the tail of work2 is not needed for them, use slots
+    std::vector<double> hbuf(1);
+    double prev = -1.0;
+    for (int sweep = 0; sweep < 12; ++sweep) {
+      HIP_TRY(M, launch_local_residual(info_d, M->n_macro, tm, M->T, M->bx, M->by, M->tau,
+                                       (const double*)(fw + L.R), qu, lam, r, s));
+      // ||r||: partial sums in d (nblk doubles), result in d[nblk]
+      G.partial = d;
+      G.hdev = d + G.nblk;
+      double rn2;
+      if ((st = dot(M, G, r, r, &rn2, s))) return st;
+      const double rn = std::sqrt(rn2);
+      if (rn == 0.0 || (prev >= 0.0 && rn > 0.5 * prev)) break;
+      prev = rn;
+      if ((st = run_macro_solve(M, MODE_LOCAL, 0, nullptr, r, d, s))) return st;
+      HIP_TRY(M, launch_axpby(1.0, d, 1.0, qu, nl, s));
+    }
+    if (flux_res && M->n_trace > 0) {
+      HIP_TRY(M, launch_boundary_C(info_d, M->n_macro, tm, M->T, M->tau, qu, (double*)(fw + L.slots), s));
+      HIP_TRY(M, launch_face_combine(FACE_RESID, (const FaceInfo*)(fw + L.faces), M->n_int, tm,
+                                     M->T, M->tau, lam, (const double*)(fw + L.slots), flux_res, s));
+    }
+    return MHDG_OK;
+  }
   if (flux_res && M->n_trace > 0)
     HIP_TRY(M, launch_face_combine(FACE_RESID, (const FaceInfo*)(M->ws + L.faces), M->n_int,
                                    (const double*)(M->ws + L.tmpl), M->T, M->tau, lam,
@@ -845,11 +1002,14 @@ mhdg_status mhdg_recover_local(mhdg_mesh* M, const double* lam, double* qu, doub
   return MHDG_OK;
 }
 
-// ---------------------------------------------------------------- GMRES
-// Left-preconditioned restarted GMRES with classical Gram-Schmidt applied
-// twice (CGS2); all vectors and inner products in FP64 on the device, the
-// (restart+1) x restart Hessenberg least-squares problem by Givens rotations
-// on the host.
+
+static size_t solve_bytes_impl(const mhdg_mesh* M, int R) {
+  const size_t vb = align_up(size_t(M->n_trace) * sizeof(double));
+  const size_t nblk = size_t(dots_nblk(M->n_trace));
+  return align_up(vb * (R + 8)) + align_up(nblk * size_t(R + 2) * sizeof(double)) +
+         2 * align_up(size_t(R + 2) * 8) + align_up(size_t(M->n_local) * sizeof(double));
+}
+
 mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
                        const mhdg_solve_opts* o, double* lam, void* ws, size_t ws_bytes,
                        mhdg_solve_info* info, void* stream) {
@@ -857,137 +1017,131 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   if (!o || !lam || !ws || o->restart < 1 || o->max_iter < 0 || !(o->rtol >= 0.0))
     return fail(M, MHDG_ERR_INVALID_ARG, "solve: bad options or null pointer");
   if (!M->factored) return fail(M, MHDG_ERR_STATE, "solve: call factor_local first");
-  if (ws_bytes < solve_bytes(M, o->restart))
+  if (ws_bytes < solve_bytes_impl(M, o->restart))
     return fail(M, MHDG_ERR_WORKSPACE, "solve: workspace smaller than mhdg_query reports");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = M->n_trace;
   const int R = o->restart;
   auto t0 = std::chrono::steady_clock::now();
-  char* w = (char*)ws;
-  size_t vb = align_up(size_t(n) * sizeof(double));
-  double* V = (double*)w;                         // (R+1) vectors, leading dim vb/8
-  const int64_t ld = int64_t(vb / sizeof(double));
-  double* wv = (double*)(w + vb * (R + 1));
-  double* rv = (double*)(w + vb * (R + 2));
-  double* fh = (double*)(w + vb * (R + 3));
-  double* pf = (double*)(w + vb * (R + 4));
-  double* tv = (double*)(w + vb * (R + 5));
-  size_t off = align_up(vb * (R + 7));
-  const int nblk = dots_nblk(n);
-  double* partial = (double*)(w + off);
-  off += align_up(size_t(nblk) * (R + 2) * sizeof(double));
-  double* hdev = (double*)(w + off);
-  off += align_up(size_t(R + 2) * 8);
-  double* ydev = (double*)(w + off);
-
+  Gm G;
+  carve(M, ws, R, G);
   mhdg_solve_info inf{};
-  // f^ and D^-1 f^
-  mhdg_status st = mhdg_rhs(M, f_nodes, g_bnd, fh, 0, stream);
-  if (st) return st;
+  mhdg_status st;
+  FactorLayout& L = M->L;
+  char* fw = M->ws;
+  const double* tm = (const double*)(fw + L.tmpl);
+  const MacroInfo* info_d = (const MacroInfo*)(fw + L.meta);
+  const FaceInfo* faces_d = (const FaceInfo*)(fw + L.faces);
+  // f^ (and R_K, kept in the factor workspace) and D^-1 f^
+  if ((st = mhdg_rhs(M, f_nodes, g_bnd, G.fh, 0, stream))) return st;
   if (n == 0) {
     if (info) *info = inf;
     return MHDG_OK;
   }
-  st = mhdg_rhs(M, f_nodes, g_bnd, pf, MHDG_PRECONDITION, stream);
-  if (st) return st;
+  if ((st = mhdg_rhs(M, f_nodes, g_bnd, G.pf, MHDG_PRECONDITION, stream))) return st;
+  inf.n_applies = 2;
   auto t1 = std::chrono::steady_clock::now();
   inf.t_rhs_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-
-  auto dot = [&](const double* a, const double* b, double* host) -> mhdg_status {
-    HIP_TRY(M, launch_dots(a, ld, 1, b, n, partial, nblk, hdev, s));
-    HIP_TRY(M, hipMemcpyAsync(host, hdev, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(M, hipStreamSynchronize(s));
-    return MHDG_OK;
-  };
-  double bnorm2 = 0;
-  if ((st = dot(pf, pf, &bnorm2))) return st;
-  const double bnorm = std::sqrt(bnorm2);
   if (o->zero_guess) HIP_TRY(M, hipMemsetAsync(lam, 0, n * sizeof(double), s));
-  if (bnorm == 0.0) {
-    HIP_TRY(M, hipMemsetAsync(lam, 0, n * sizeof(double), s));
-    HIP_TRY(M, hipStreamSynchronize(s));
-    if (info) *info = inf;
-    return MHDG_OK;
-  }
-  std::vector<double> H((R + 1) * R), cs(R), sn(R), g(R + 1), h(R + 2), y(R);
-  int it = 0;
-  double rel = 1.0;
   bool converged = false;
-  int applies = 0;
-  while (true) {
-    // r = D^-1 f^ - D^-1 S lam
-    if ((st = mhdg_apply_trace_operator(M, lam, tv, MHDG_PRECONDITION, stream))) return st;
-    ++applies;
-    HIP_TRY(M, launch_scale_copy(1.0, pf, rv, n, s));
-    HIP_TRY(M, launch_axpby(-1.0, tv, 1.0, rv, n, s));
-    double rn2;
-    if ((st = dot(rv, rv, &rn2))) return st;
-    double beta = std::sqrt(rn2);
-    rel = beta / bnorm;
-    if (rel <= o->rtol || it >= o->max_iter) { converged = rel <= o->rtol; break; }
-    HIP_TRY(M, launch_scale_copy(1.0 / beta, rv, V, n, s));
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int j = 0;
-    for (; j < R && it < o->max_iter; ++j) {
-      ++it;
-      if ((st = mhdg_apply_trace_operator(M, V + j * ld, wv, MHDG_PRECONDITION, stream))) return st;
-      ++applies;
-      // CGS2
-      for (int pass = 0; pass < 2; ++pass) {
-        HIP_TRY(M, launch_dots(V, ld, j + 1, wv, n, partial, nblk, hdev, s));
-        HIP_TRY(M, launch_gemv_sub(V, ld, j + 1, hdev, wv, n, -1.0, s));
-        HIP_TRY(M, hipMemcpyAsync(h.data(), hdev,
-                                  (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(M, hipStreamSynchronize(s));
-        for (int i = 0; i <= j; ++i) H[i * R + j] = (pass ? H[i * R + j] : 0.0) + h[i];
-      }
-      double hn2;
-      if ((st = dot(wv, wv, &hn2))) return st;
-      double hn = std::sqrt(hn2);
-      H[(j + 1) * R + j] = hn;
-      if (hn > 0) HIP_TRY(M, launch_scale_copy(1.0 / hn, wv, V + (j + 1) * ld, n, s));
-      // apply previous rotations, then a new one
-      for (int i = 0; i < j; ++i) {
-        double a = H[i * R + j], b = H[(i + 1) * R + j];
-        H[i * R + j] = cs[i] * a + sn[i] * b;
-        H[(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
-      }
-      double a = H[j * R + j], b = H[(j + 1) * R + j];
-      double rr = std::hypot(a, b);
-      cs[j] = rr == 0 ? 1.0 : a / rr;
-      sn[j] = rr == 0 ? 0.0 : b / rr;
-      H[j * R + j] = rr;
-      H[(j + 1) * R + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      rel = std::fabs(g[j + 1]) / bnorm;
-      if (rel <= o->rtol || hn == 0.0) { ++j; break; }
+  double rel = 0.0;
+  if (M->precision == MHDG_FP64) {
+    // ---- plain form: GMRES on D^-1 S lam = D^-1 f^
+    double b2;
+    if ((st = dot(M, G, G.pf, G.pf, &b2, s))) return st;
+    const double bnorm = std::sqrt(b2);
+    if (bnorm == 0.0) {
+      HIP_TRY(M, hipMemsetAsync(lam, 0, n * sizeof(double), s));
+      converged = true;
+    } else {
+      int it = 0;
+      if ((st = gmres(M, G, G.pf, bnorm, lam, o->rtol, R, o->max_iter, it, rel, inf.n_applies,
+                      converged, s)))
+        return st;
+      inf.iterations = it;
     }
-    // y = H^-1 g, lam += V y
-    for (int i = j - 1; i >= 0; --i) {
-      double v = g[i];
-      for (int k = i + 1; k < j; ++k) v -= H[i * R + k] * y[k];
-      y[i] = v / H[i * R + i];
+    // true residual ||f^ - S lam|| / ||f^||
+    if ((st = mhdg_apply_trace_operator(M, lam, G.tv, 0, stream))) return st;
+    ++inf.n_applies;
+    HIP_TRY(M, launch_scale_copy(1.0, G.fh, G.rv, n, s));
+    HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, n, s));
+    double tr2, f2;
+    if ((st = dot(M, G, G.rv, G.rv, &tr2, s))) return st;
+    if ((st = dot(M, G, G.fh, G.fh, &f2, s))) return st;
+    inf.rel_res_true = f2 > 0 ? std::sqrt(tr2 / f2) : 0.0;
+    inf.rel_res_prec = rel;
+  } else {
+    // ---- reduced-precision factors: iterative refinement of the whole
+    // hybridised system in FP64.  The residual (r_U, r_lam) = (R - A U - B lam,
+    // -(C U + D lam)) is formed matrix-free in FP64; the correction solves the
+    // condensed system with the stored low-precision factors (inner GMRES on
+    // D^-1 S~ dlam = D^-1 (r_lam - sum C A~^-1 r_U), then dU = A~^-1 (r_U - B dlam)).
+    double* rU = (double*)(fw + L.work1);
+    const int64_t nl = M->n_local;
+    HIP_TRY(M, hipMemsetAsync(G.U, 0, nl * sizeof(double), s));
+    if (!o->zero_guess) {
+      // start U from the low-precision local solve for the given lam
+      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, nullptr,
+                                    M->n_macro, M->max_N, (const int32_t*)(fw + L.perm), tm, M->T,
+                                    M->bx, M->by, M->tau, lam, (const double*)(fw + L.R), G.U,
+                                    (double*)(fw + L.slots), s));
     }
-    HIP_TRY(M, hipMemcpyAsync(ydev, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_TRY(M, launch_gemv_sub(V, ld, j, ydev, lam, n, 1.0, s));
-    HIP_TRY(M, hipStreamSynchronize(s));
+    const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
+    const int max_outer = o->max_outer > 0 ? o->max_outer : 30;
+    double rho0 = 0.0;
+    int outer = 0, it_total = 0;
+    for (;; ++outer) {
+      // FP64 residual of the full system
+      HIP_TRY(M, launch_local_residual(info_d, M->n_macro, tm, M->T, M->bx, M->by, M->tau,
+                                       (const double*)(fw + L.R), G.U, lam, rU, s));
+      HIP_TRY(M, launch_boundary_C(info_d, M->n_macro, tm, M->T, M->tau, G.U, (double*)(fw + L.slots), s));
+      HIP_TRY(M, launch_face_combine(FACE_RESID, faces_d, M->n_int, tm, M->T, M->tau, lam,
+                                     (const double*)(fw + L.slots), G.cl, s));      // C U + D lam
+      // condensed right-hand side b = D^-1 (r_lam - sum C A~^-1 r_U)
+      HIP_TRY(M, launch_macro_solve(MODE_RHS, 0, fw + L.factors, M->precision, info_d, nullptr,
+                                    M->n_macro, M->max_N, (const int32_t*)(fw + L.perm), tm, M->T,
+                                    M->bx, M->by, M->tau, nullptr, rU, nullptr,
+                                    (double*)(fw + L.slots), s));
+      ++inf.n_applies;
+      HIP_TRY(M, launch_face_combine(FACE_PREC_RHS, faces_d, M->n_int, tm, M->T, M->tau, nullptr,
+                                     (const double*)(fw + L.slots), G.rv, s));      // -D^-1 sum C A~^-1 r_U
+      HIP_TRY(M, launch_face_combine(FACE_DINV, faces_d, M->n_int, tm, M->T, M->tau, G.cl,
+                                     nullptr, G.tv, s));                            // D^-1 (C U + D lam)
+      HIP_TRY(M, launch_scale_copy(1.0, G.rv, G.wv, n, s));
+      HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.wv, n, s));                       // b in wv
+      double b2;
+      if ((st = dot(M, G, G.wv, G.wv, &b2, s))) return st;
+      const double rho = std::sqrt(b2);
+      if (outer == 0) rho0 = rho;
+      rel = rho0 > 0 ? rho / rho0 : 0.0;
+      if (rho0 == 0.0 || rel <= o->rtol) { converged = true; break; }
+      if (outer >= max_outer || it_total >= o->max_iter) break;
+      // inner solve to a relative tolerance no tighter than needed for the target
+      const double eta = std::max(inner_rtol, 0.3 * o->rtol / std::max(rel, 1e-300));
+      HIP_TRY(M, launch_scale_copy(1.0, G.wv, G.fh, n, s));                        // keep b: GMRES uses V/wv
+      HIP_TRY(M, hipMemsetAsync(G.dl, 0, n * sizeof(double), s));
+      int it = 0;
+      double irel = 0;
+      bool iconv = false;
+      if ((st = gmres(M, G, G.fh, rho, G.dl, eta, R, o->max_iter - it_total, it, irel,
+                      inf.n_applies, iconv, s)))
+        return st;
+      it_total += it;
+      // dU = A~^-1 (r_U - B dlam); U += dU; lam += dlam
+      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, nullptr,
+                                    M->n_macro, M->max_N, (const int32_t*)(fw + L.perm), tm, M->T,
+                                    M->bx, M->by, M->tau, G.dl, rU, rU, (double*)(fw + L.slots), s));
+      ++inf.n_applies;
+      HIP_TRY(M, launch_axpby(1.0, rU, 1.0, G.U, nl, s));
+      HIP_TRY(M, launch_axpby(1.0, G.dl, 1.0, lam, n, s));
+    }
+    inf.iterations = it_total;
+    inf.outer_iterations = outer;
+    inf.rel_res_prec = rel;
+    inf.rel_res_true = -1.0;   // needs FP64 factors; see rel_res_prec (FP64 residual, condensed)
   }
-  // true residual ||f^ - S lam|| / ||f^||
-  if ((st = mhdg_apply_trace_operator(M, lam, tv, 0, stream))) return st;
-  ++applies;
-  HIP_TRY(M, launch_scale_copy(1.0, fh, rv, n, s));
-  HIP_TRY(M, launch_axpby(-1.0, tv, 1.0, rv, n, s));
-  double tr2, f2;
-  if ((st = dot(rv, rv, &tr2))) return st;
-  if ((st = dot(fh, fh, &f2))) return st;
   auto t2 = std::chrono::steady_clock::now();
-  inf.iterations = it;
-  inf.rel_res_prec = rel;
-  inf.rel_res_true = f2 > 0 ? std::sqrt(tr2 / f2) : 0.0;
   inf.t_gmres_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
-  inf.n_applies = applies;
   inf.status = converged ? MHDG_OK : MHDG_ERR_NOT_CONVERGED;
   if (info) *info = inf;
   if (!converged) return fail(M, MHDG_ERR_NOT_CONVERGED, "solve: max_iter reached");

@@ -54,6 +54,7 @@ struct BndFaceInfo {  // boundary (Dirichlet) faces
 // Offsets (in doubles / ints, from the template blob base) per level.
 struct LevelTemplates {
   int64_t Mhat, E0, E1;     // Q x Q reference macro mass and derivative matrices
+  int64_t E0T, E1T;         // their transposes (coalesced column access)
   int64_t M1, M1inv;        // (P+1)^2 1D trace mass on [0,1] and its inverse
   int64_t edge_node;        // int32 [3][P+1]: lattice node at local edge position s
   int64_t node_epos;        // int32 [Q][3]: position along local edge k, or -1
@@ -72,10 +73,18 @@ struct Templates {
 
 // Device workspace layout for factor_local / apply / rhs / recover.
 struct FactorLayout {
-  size_t meta, faces, bfaces, tmpl, perm, status, R, slots, lamD, factors, total;
+  size_t meta, faces, bfaces, tmpl, perm, status, R, slots, lamD, work1, work2, factors, total;
 };
 
 enum SolveMode { MODE_APPLY = 0, MODE_RHS = 1, MODE_RECOVER = 2, MODE_LOCAL = 3 };
+
+hipError_t launch_local_residual(const MacroInfo* info, int64_t n, const double* tmpl,
+                                 const Templates& T, double bx, double by, double tau,
+                                 const double* R, const double* U, const double* lam,
+                                 double* out, hipStream_t s);
+hipError_t launch_boundary_C(const MacroInfo* info, int64_t n, const double* tmpl,
+                             const Templates& T, double tau, const double* U, double* slots,
+                             hipStream_t s);
 
 // ---- kernel launchers (kernels.hip) ----
 hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, hipStream_t s);
@@ -102,7 +111,8 @@ hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double*
                                  const Templates& T, double bx, double by, double tau,
                                  double* dst, hipStream_t s);
 // face_combine modes
-enum FaceMode { FACE_S = 0, FACE_PREC_S = 1, FACE_RHS = 2, FACE_PREC_RHS = 3, FACE_RESID = 4 };
+enum FaceMode { FACE_S = 0, FACE_PREC_S = 1, FACE_RHS = 2, FACE_PREC_RHS = 3, FACE_RESID = 4,
+                FACE_DINV = 5 /* out = D_F^-1 lam (slots unused) */ };
 
 // GMRES vector kernels
 hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, int64_t n,

@@ -397,7 +397,7 @@ __global__ __launch_bounds__(64) void face_combine_kernel(int mode, const FaceIn
   const int nF = f.nF;
   const LevelTemplates& L = Tp.lev[f.level];
   for (int l = threadIdx.x; l < nF; l += 64) {
-    v[l] = slots[f.slot[0] + l] + slots[f.slot[1] + l];
+    v[l] = mode == FACE_DINV ? 0.0 : slots[f.slot[0] + l] + slots[f.slot[1] + l];
     lf[l] = lam ? lam[f.tr_off + l] : 0.0;
   }
   __syncthreads();
@@ -412,6 +412,10 @@ __global__ __launch_bounds__(64) void face_combine_kernel(int mode, const FaceIn
       r = mode == FACE_S ? d - v[l] : d + v[l];
     } else if (mode == FACE_RHS) {
       r = -v[l];
+    } else if (mode == FACE_DINV) {
+      double d = 0.0;  // D_F^-1 lam = -M1^-1 lam / (2 tau |F|)
+      for (int k = 0; k < nF; ++k) d += Mi[size_t(l) * nF + k] * lf[k];
+      r = -d / (2.0 * tau * f.len);
     } else {
       double d = 0.0;  // -D_F^-1 v = M1^-1 v / (2 tau |F|)
       for (int k = 0; k < nF; ++k) d += Mi[size_t(l) * nF + k] * v[k];
@@ -492,6 +496,97 @@ __global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restri
   }
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += 64) R[mi.loc_off + i] = x[i];
+}
+
+// ------------------------------------------------------------------ FP64 residual of the local rows
+// out_K = R_K - A_K U_K - B_K lam_K in FP64, matrix-free: with the reference
+// templates (Mhat symmetric, E^k and their transposes) the three block rows are
+//   v_x: |J| Mhat q_x - E^x u,   v_y: |J| Mhat q_y - E^y u,
+//   w:   kappa (E^x^T q_x + E^y^T q_y) - (a_x E^x + a_y E^y) u + tau Mb u,
+// E^d = |J| sum_k G[k][d] Ehat^k.  lam may be NULL (no trace term).
+__global__ __launch_bounds__(256) void local_residual_kernel(
+    const MacroInfo* __restrict__ info, const double* __restrict__ tm, Templates Tp, double bx,
+    double by, double tau, const double* __restrict__ R, const double* __restrict__ U,
+    const double* __restrict__ lam, double* __restrict__ out) {
+  extern __shared__ double sh[];
+  const MacroInfo& mi = info[blockIdx.x];
+  const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P;
+  const LevelTemplates& L = Tp.lev[mi.level];
+  double* u = sh;
+  double* xc = sh + N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) u[i] = U[mi.loc_off + i];
+  for (int i = threadIdx.x; i < 3 * NBD; i += blockDim.x) xc[i] = 0.0;
+  __syncthreads();
+  if (lam)
+    for (int k = 0; k < 3; ++k) {
+      if (mi.tr_off[k] >= 0) edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], 1.0, bx, by, tau, xc);
+      __syncthreads();
+    }
+  const double* Mh = tm + L.Mhat;
+  const double* E0 = tm + L.E0;
+  const double* E1 = tm + L.E1;
+  const double* E0T = tm + L.E0T;
+  const double* E1T = tm + L.E1T;
+  const double* M1 = tm + L.M1;
+  const int32_t* ep = ints(tm, L.node_epos);
+  const int32_t* en = ints(tm, L.edge_node);
+  const int32_t* bidx = ints(tm, L.bnd_index);
+  const double dJ = mi.dJ, g0 = mi.G[0], g1 = mi.G[1], g2 = mi.G[2], g3 = mi.G[3];
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) {
+    double mqx = 0, mqy = 0, e0u = 0, e1u = 0, e0x = 0, e1x = 0, e0y = 0, e1y = 0;
+    for (int j = 0; j < Q; ++j) {
+      const size_t o = size_t(j) * Q + i;
+      const double qx = u[j], qy = u[Q + j], uu = u[2 * Q + j];
+      const double m = Mh[o], a0 = E0T[o], a1 = E1T[o], b0 = E0[o], b1 = E1[o];
+      mqx += m * qx;
+      mqy += m * qy;
+      e0u += a0 * uu;     // (Ehat^0 u)_i
+      e1u += a1 * uu;
+      e0x += b0 * qx;     // (Ehat^0^T q_x)_i
+      e1x += b1 * qx;
+      e0y += b0 * qy;
+      e1y += b1 * qy;
+    }
+    const double Exu = dJ * (g0 * e0u + g2 * e1u), Eyu = dJ * (g1 * e0u + g3 * e1u);
+    const double ExTqx = dJ * (g0 * e0x + g2 * e1x), EyTqy = dJ * (g1 * e0y + g3 * e1y);
+    double mbu = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const int si = ep[3 * i + k];
+      if (si < 0) continue;
+      const int lo = si - Tp.p > 0 ? si - Tp.p : 0, hi = si + Tp.p < P ? si + Tp.p : P;
+      double acc = 0.0;
+      for (int s2 = lo; s2 <= hi; ++s2) acc += M1[size_t(si) * (P + 1) + s2] * u[2 * Q + en[k * (P + 1) + s2]];
+      mbu += mi.len[k] * acc;
+    }
+    double av[3];
+    av[0] = dJ * mqx - Exu;
+    av[1] = dJ * mqy - Eyu;
+    av[2] = mi.kappa * (ExTqx + EyTqy) - (bx * Exu + by * Eyu) + tau * mbu;
+    const int b = bidx[i];
+    for (int f = 0; f < 3; ++f) {
+      double r = R[mi.loc_off + f * Q + i] - av[f];
+      if (b >= 0) r -= xc[f * NBD + b];
+      out[mi.loc_off + f * Q + i] = r;
+    }
+  }
+}
+
+// slots of macro K <- C_K U_K (step 3 applied to a given local vector)
+__global__ __launch_bounds__(64) void boundary_C_kernel(const MacroInfo* __restrict__ info,
+                                                        const double* __restrict__ tm, Templates Tp,
+                                                        double tau, const double* __restrict__ U,
+                                                        double* __restrict__ slots) {
+  extern __shared__ double zc[];
+  const MacroInfo& mi = info[blockIdx.x];
+  const int Q = mi.Q, P = mi.P, NBD = 3 * P;
+  const int32_t* en = ints(tm, Tp.lev[mi.level].edge_node);
+  for (int b = threadIdx.x; b < NBD; b += 64) {
+    const int node = en[(b / P) * (P + 1) + b % P];
+    for (int f = 0; f < 3; ++f) zc[f * NBD + b] = U[mi.loc_off + f * Q + node];
+  }
+  __syncthreads();
+  for (int k = 0; k < 3; ++k)
+    if (mi.tr_off[k] >= 0) edge_C(mi, k, tm, Tp, zc, tau, slots + mi.slot_off[k]);
 }
 
 // ------------------------------------------------------------------ vector ops
@@ -701,6 +796,32 @@ hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double*
   int maxN = max_present_N(T);
   hipLaunchKernelGGL(extract_kernel, dim3((unsigned)maxN), dim3(256), 0, s, info, e, tmpl, T, bx,
                      by, tau, dst);
+  return hipGetLastError();
+}
+
+static int max_present_P(const Templates& T) {
+  int maxP = 0;
+  for (int r = 0; r <= kMaxLevel; ++r)
+    if (T.lev[r].present && T.lev[r].P > maxP) maxP = T.lev[r].P;
+  return maxP;
+}
+
+hipError_t launch_local_residual(const MacroInfo* info, int64_t n, const double* tmpl,
+                                 const Templates& T, double bx, double by, double tau,
+                                 const double* R, const double* U, const double* lam,
+                                 double* out, hipStream_t s) {
+  size_t lds = size_t(max_present_N(T) + 9 * max_present_P(T)) * sizeof(double);
+  hipLaunchKernelGGL(local_residual_kernel, dim3((unsigned)n), dim3(256), lds, s, info, tmpl, T,
+                     bx, by, tau, R, U, lam, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary_C(const MacroInfo* info, int64_t n, const double* tmpl,
+                             const Templates& T, double tau, const double* U, double* slots,
+                             hipStream_t s) {
+  size_t lds = size_t(9 * max_present_P(T)) * sizeof(double);
+  hipLaunchKernelGGL(boundary_C_kernel, dim3((unsigned)n), dim3(64), lds, s, info, tmpl, T, tau, U,
+                     slots);
   return hipGetLastError();
 }
 

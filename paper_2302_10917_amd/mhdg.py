@@ -46,7 +46,8 @@ class Sizes(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32),
-                ("max_iter", ctypes.c_int32), ("zero_guess", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("zero_guess", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -62,7 +63,7 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_res_prec", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("t_rhs_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
-                ("n_applies", ctypes.c_int32)]
+                ("n_applies", ctypes.c_int32), ("outer_iterations", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -147,6 +148,7 @@ class MacroMesh:
         self.h = h
         self.factor_ws = None
         self.solve_ws = None
+        self.precision = MHDG_FP64
         self.sizes = self.query()
 
     def __del__(self):
@@ -185,6 +187,7 @@ class MacroMesh:
             kap = kap.expand(s.n_macro)
         kap = kap.contiguous()
         self._kappa = kap
+        self.precision = precision
         self._check(self._lib.mhdg_factor_local(self.h, _ptr(kap), float(beta[0]), float(beta[1]),
                                                 float(tau), precision, _ptr(self.factor_ws),
                                                 self.factor_ws.numel(), _stream(stream)),
@@ -207,13 +210,14 @@ class MacroMesh:
                                        _stream(stream)), "rhs")
 
     def solve(self, f_nodes, g_bnd, lam, rtol=1e-10, restart=30, max_iter=10000, zero_guess=True,
-              stream=None, check=True):
+              stream=None, check=True, inner_rtol=0.0, max_outer=0):
         import torch
-        s = self.query(MHDG_FP64, restart)
+        s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
-        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1 if zero_guess else 0)
+        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1 if zero_guess else 0,
+                         int(max_outer), float(inner_rtol))
         info = SolveInfo()
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
                                   _ptr(self.solve_ws), self.solve_ws.numel(), ctypes.byref(info),
