@@ -160,9 +160,10 @@ mhdg_status mhdg_factor_local(mhdg_mesh* mesh, const double* kappa, double beta_
  * state is touched.  For tests of the assembly. */
 mhdg_status mhdg_local_matrix(mhdg_mesh* mesh, int64_t e, double* dst, void* stream);
 
-/* out = S lam, or D^-1 S lam with MHDG_PRECONDITION, with MHDG_TRANSPOSE the
- * transposed operator S^T lam (or D^-T S^T lam).  lam, out: device
- * f64[n_trace], must not alias.  Errors: STATE before factor_local. */
+/* out = S lam, or D^-1 S lam with MHDG_PRECONDITION; with MHDG_TRANSPOSE the
+ * transposed operator S^T lam (or D^-1 S^T lam; D is symmetric), FP64
+ * factors only.  lam, out: device f64[n_trace], must not alias.
+ * Errors: STATE before factor_local. */
 mhdg_status mhdg_apply_trace_operator(mhdg_mesh* mesh, const double* lam, double* out,
                                       int32_t flags, void* stream);
 
@@ -200,6 +201,26 @@ mhdg_status mhdg_solve(mhdg_mesh* mesh, const double* f_nodes, const double* g_b
  * Needs mhdg_rhs (or solve) to have run since factor_local. */
 mhdg_status mhdg_recover_local(mhdg_mesh* mesh, const double* lam, double* qu, double* flux_res,
                                void* stream);
+
+/* out_K = M_K v_K for every macro and each of the three fields (M_K the
+ * macro mass matrix (phi_j, phi_i)_K); v, out: device f64[n_local], not
+ * aliased.  Gives L2 inner products of local fields, e.g. for objectives. */
+mhdg_status mhdg_mass_apply(mhdg_mesh* mesh, const double* v, double* out, void* stream);
+
+/* Adjoint of a solved problem for an objective J(U) with gradient dJ_dU
+ * (device f64[n_local]) at the solution (lam from solve, qu from
+ * recover_local): solves K^T Psi = dJ/dX for the hybridised system by static
+ * condensation with the stored FP64 LU factors (GMRES on D^-1 S^T to
+ * opts->rtol, then psi_K = A_K^-T (g_K - C_K^T psi_lam)) and returns
+ *   dJ_dkappa[n_macro] = dJ/dkappa_K = -Psi^T dK/dkappa_K X   (device f64)
+ *   dJ_dbeta[2]        = dJ/da_d = Psi^T (dF/da_d - dK/da_d X)   (device f64)
+ * plus psi_lam (device f64[n_trace]) and psi_U (device f64[n_local]).  f is
+ * held fixed.  ws: the solve workspace (mhdg_query with the same restart).
+ * Errors: STATE without solve or with FP32 factors, NOT_CONVERGED. */
+mhdg_status mhdg_adjoint(mhdg_mesh* mesh, const double* lam, const double* qu, const double* dJ_dU,
+                         const mhdg_solve_opts* opts, double* psi_lam, double* psi_U,
+                         double* dJ_dkappa, double* dJ_dbeta, void* ws, size_t ws_bytes,
+                         mhdg_solve_info* info, void* stream);
 
 /* Per-kernel timing of the hot path, for measurement.  enable = 1 clears
  * the counters and brackets every later launch of the listed kernels with

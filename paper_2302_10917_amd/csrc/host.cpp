@@ -404,6 +404,7 @@ namespace {
 struct Gm {
   int64_t n = 0, ld = 0;
   int nblk = 1;
+  int32_t op_flags = MHDG_PRECONDITION;   // MHDG_TRANSPOSE added for adjoint solves
   double *V = nullptr, *wv = nullptr, *rv = nullptr, *tv = nullptr, *fh = nullptr, *pf = nullptr;
   double *partial = nullptr, *hdev = nullptr, *ydev = nullptr;
   double *U = nullptr, *dl = nullptr, *cl = nullptr;  // precision-refinement state
@@ -430,7 +431,7 @@ mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, double bref, double* x, 
   iters = 0;
   converged = false;
   while (true) {
-    if ((st = mhdg_apply_trace_operator(M, x, G.tv, MHDG_PRECONDITION, s))) return st;
+    if ((st = mhdg_apply_trace_operator(M, x, G.tv, G.op_flags, s))) return st;
     ++applies;
     HIP_TRY(M, launch_scale_copy(1.0, b, G.rv, n, s));
     HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, n, s));
@@ -445,7 +446,7 @@ mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, double bref, double* x, 
     int j = 0;
     for (; j < R && iters < max_iter; ++j) {
       ++iters;
-      if ((st = mhdg_apply_trace_operator(M, G.V + j * ld, G.wv, MHDG_PRECONDITION, s))) return st;
+      if ((st = mhdg_apply_trace_operator(M, G.V + j * ld, G.wv, G.op_flags, s))) return st;
       ++applies;
       for (int pass = 0; pass < 2; ++pass) {
         HIP_TRY(M, launch_dots(G.V, ld, j + 1, G.wv, n, G.partial, G.nblk, G.hdev, s));
@@ -899,10 +900,12 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* o
   if (!M->factored) return fail(M, MHDG_ERR_STATE, "apply: call factor_local first");
   if ((!lam || !out) && M->n_trace > 0) return fail(M, MHDG_ERR_INVALID_ARG, "apply: null vector");
   if (lam == out && M->n_trace > 0) return fail(M, MHDG_ERR_INVALID_ARG, "apply: lam and out alias");
-  if (flags & MHDG_TRANSPOSE) return fail(M, MHDG_ERR_INVALID_ARG, "apply: transpose not built");
+  const int tr = (flags & MHDG_TRANSPOSE) ? 1 : 0;
+  if (tr && M->precision != MHDG_FP64)
+    return fail(M, MHDG_ERR_STATE, "apply: the transposed operator needs FP64 factors");
   if (M->n_trace == 0) return MHDG_OK;
   hipStream_t s = (hipStream_t)stream;
-  mhdg_status st = run_macro_solve(M, MODE_APPLY, 0, lam, nullptr, nullptr, s);
+  mhdg_status st = run_macro_solve(M, MODE_APPLY, tr, lam, nullptr, nullptr, s);
   if (st) return st;
   FactorLayout& L = M->L;
   ProfScope ps(M, 3, s);
@@ -917,8 +920,10 @@ mhdg_status mhdg_local_solve(mhdg_mesh* M, const double* x, double* y, int32_t f
   if (!M) return MHDG_ERR_INVALID_ARG;
   if (!M->factored) return fail(M, MHDG_ERR_STATE, "local_solve: call factor_local first");
   if (!x || !y) return fail(M, MHDG_ERR_INVALID_ARG, "local_solve: null vector");
-  if (flags & MHDG_TRANSPOSE) return fail(M, MHDG_ERR_INVALID_ARG, "local_solve: transpose not built");
-  return run_macro_solve(M, MODE_LOCAL, 0, nullptr, x, y, (hipStream_t)stream);
+  const int tr = (flags & MHDG_TRANSPOSE) ? 1 : 0;
+  if (tr && M->precision != MHDG_FP64)
+    return fail(M, MHDG_ERR_STATE, "local_solve: transposed solves need FP64 factors");
+  return run_macro_solve(M, MODE_LOCAL, tr, nullptr, x, y, (hipStream_t)stream);
 }
 
 mhdg_status mhdg_rhs(mhdg_mesh* M, const double* f_nodes, const double* g_bnd, double* fhat,
@@ -1145,6 +1150,76 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   inf.status = converged ? MHDG_OK : MHDG_ERR_NOT_CONVERGED;
   if (info) *info = inf;
   if (!converged) return fail(M, MHDG_ERR_NOT_CONVERGED, "solve: max_iter reached");
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_mass_apply(mhdg_mesh* M, const double* v, double* out, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->ws) return fail(M, MHDG_ERR_STATE, "mass_apply: call factor_local first");
+  if (!v || !out || v == out) return fail(M, MHDG_ERR_INVALID_ARG, "mass_apply: bad vectors");
+  FactorLayout& L = M->L;
+  HIP_TRY(M, launch_mass((const MacroInfo*)(M->ws + L.meta), M->n_macro,
+                         (const double*)(M->ws + L.tmpl), M->T, v, out, (hipStream_t)stream));
+  return MHDG_OK;
+}
+
+// Adjoint: K^T Psi = dJ/dX with X = (U, lam), condensed onto the trace:
+// S^T psi_lam = -sum_K B_K^T A_K^-T g_K (GMRES left-preconditioned with
+// D^-1; D is symmetric), psi_K = A_K^-T (g_K - C_K^T psi_lam), both with the
+// stored LU factors; then dJ/dtheta = Psi^T (dF/dtheta - dK/dtheta X).
+mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, const double* dJ_dU,
+                         const mhdg_solve_opts* o, double* psi_lam, double* psi_U,
+                         double* dJ_dkappa, double* dJ_dbeta, void* ws, size_t ws_bytes,
+                         mhdg_solve_info* info, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!o || !qu || !dJ_dU || !psi_U || !dJ_dkappa || !dJ_dbeta || !ws || o->restart < 1 ||
+      (M->n_trace > 0 && (!lam || !psi_lam)))
+    return fail(M, MHDG_ERR_INVALID_ARG, "adjoint: bad options or null pointer");
+  if (!M->factored || !M->have_rhs)
+    return fail(M, MHDG_ERR_STATE, "adjoint: call factor_local and solve first");
+  if (M->precision != MHDG_FP64)
+    return fail(M, MHDG_ERR_STATE, "adjoint: needs FP64 factors");
+  if (ws_bytes < solve_bytes_impl(M, o->restart))
+    return fail(M, MHDG_ERR_WORKSPACE, "adjoint: workspace smaller than mhdg_query reports");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = M->n_trace;
+  Gm G;
+  carve(M, ws, o->restart, G);
+  G.op_flags = MHDG_PRECONDITION | MHDG_TRANSPOSE;
+  FactorLayout& L = M->L;
+  char* fw = M->ws;
+  const double* tm = (const double*)(fw + L.tmpl);
+  const MacroInfo* info_d = (const MacroInfo*)(fw + L.meta);
+  const FaceInfo* faces_d = (const FaceInfo*)(fw + L.faces);
+  mhdg_solve_info inf{};
+  mhdg_status st;
+  bool converged = true;
+  if (n > 0) {
+    // right-hand side D^-1 b, b = -sum B^T A^-T g
+    if ((st = run_macro_solve(M, MODE_RHS, 1, nullptr, dJ_dU, nullptr, s))) return st;
+    HIP_TRY(M, launch_face_combine(FACE_PREC_RHS, faces_d, M->n_int, tm, M->T, M->tau, nullptr,
+                                   (const double*)(fw + L.slots), G.pf, s));
+    inf.n_applies = 1;
+    double b2;
+    if ((st = dot(M, G, G.pf, G.pf, &b2, s))) return st;
+    HIP_TRY(M, hipMemsetAsync(psi_lam, 0, n * sizeof(double), s));
+    if (b2 > 0) {
+      double rel = 0;
+      if ((st = gmres(M, G, G.pf, std::sqrt(b2), psi_lam, o->rtol, o->restart, o->max_iter,
+                      inf.iterations, rel, inf.n_applies, converged, s)))
+        return st;
+      inf.rel_res_prec = rel;
+    }
+  }
+  // psi_U = A^-T (g - C^T psi_lam)
+  if ((st = run_macro_solve(M, MODE_RECOVER, 1, psi_lam, dJ_dU, psi_U, s))) return st;
+  ++inf.n_applies;
+  HIP_TRY(M, launch_adjoint_contract(info_d, M->n_macro, (const BndFaceInfo*)(fw + L.bfaces), tm,
+                                     M->T, qu, psi_U, lam, psi_lam, (const double*)(fw + L.lamD),
+                                     dJ_dkappa, (double*)(fw + L.work1), dJ_dbeta, s));
+  inf.status = converged ? MHDG_OK : MHDG_ERR_NOT_CONVERGED;
+  if (info) *info = inf;
+  if (!converged) return fail(M, MHDG_ERR_NOT_CONVERGED, "adjoint: max_iter reached");
   return MHDG_OK;
 }
 

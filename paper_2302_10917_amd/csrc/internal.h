@@ -82,6 +82,13 @@ hipError_t launch_local_residual(const MacroInfo* info, int64_t n, const double*
                                  const Templates& T, double bx, double by, double tau,
                                  const double* R, const double* U, const double* lam,
                                  double* out, hipStream_t s);
+hipError_t launch_adjoint_contract(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
+                                   const double* tmpl, const Templates& T, const double* U,
+                                   const double* Psi, const double* lam, const double* psi_lam,
+                                   const double* lamD, double* dkappa, double* dbeta_part,
+                                   double* dbeta, hipStream_t s);
+hipError_t launch_mass(const MacroInfo* info, int64_t n, const double* tmpl, const Templates& T,
+                       const double* v, double* out, hipStream_t s);
 hipError_t launch_boundary_C(const MacroInfo* info, int64_t n, const double* tmpl,
                              const Templates& T, double tau, const double* U, double* slots,
                              hipStream_t s);

@@ -589,6 +589,136 @@ __global__ __launch_bounds__(64) void boundary_C_kernel(const MacroInfo* __restr
     if (mi.tr_off[k] >= 0) edge_C(mi, k, tm, Tp, zc, tau, slots + mi.slot_off[k]);
 }
 
+// ------------------------------------------------------------------ adjoint contractions
+// For macro K with forward solution U = (q_x, q_y, u), local adjoint
+// Psi = (psi_x, psi_y, psi_w), trace adjoint psi_lam and traces lam_k on its
+// edges (interior: global trace, Dirichlet: projected data):
+//   dJ/dkappa_K = -[psi_w^T (E^x^T q_x + E^y^T q_y) + sum_{interior k} psi_lam,k^T G_k^T (n_x q_x + n_y q_y)]
+//   dJ/da_d (macro part) = psi_w^T E^d u - n_d sum_k lam_k^T G_k^T psi_w
+// (A_K and C_K are affine in kappa_K; A_K through -(a.E) u and B_K through
+// (a.n - tau) are affine in a; D_F does not depend on a, f and tau are fixed).
+__global__ __launch_bounds__(256) void adjoint_contract_kernel(
+    const MacroInfo* __restrict__ info, const BndFaceInfo* __restrict__ bf,
+    const double* __restrict__ tm, Templates Tp, const double* __restrict__ U,
+    const double* __restrict__ Psi, const double* __restrict__ lam,
+    const double* __restrict__ psi_lam, const double* __restrict__ lamD,
+    double* __restrict__ dkappa, double* __restrict__ dbeta_part) {
+  extern __shared__ double sh[];
+  __shared__ double red[3][256];
+  const MacroInfo& mi = info[blockIdx.x];
+  const int N = mi.N, Q = mi.Q, P = mi.P;
+  const LevelTemplates& L = Tp.lev[mi.level];
+  double* u = sh;
+  double* ps = sh + N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    u[i] = U[mi.loc_off + i];
+    ps[i] = Psi[mi.loc_off + i];
+  }
+  __syncthreads();
+  const double* E0 = tm + L.E0;
+  const double* E1 = tm + L.E1;
+  const double* E0T = tm + L.E0T;
+  const double* E1T = tm + L.E1T;
+  const double dJ = mi.dJ, g0 = mi.G[0], g1 = mi.G[1], g2 = mi.G[2], g3 = mi.G[3];
+  double ak = 0.0, abx = 0.0, aby = 0.0;
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) {
+    double e0x = 0, e1x = 0, e0y = 0, e1y = 0, e0u = 0, e1u = 0;
+    for (int j = 0; j < Q; ++j) {
+      const size_t o = size_t(j) * Q + i;
+      const double b0 = E0[o], b1 = E1[o], a0 = E0T[o], a1 = E1T[o];
+      e0x += b0 * u[j];
+      e1x += b1 * u[j];
+      e0y += b0 * u[Q + j];
+      e1y += b1 * u[Q + j];
+      e0u += a0 * u[2 * Q + j];
+      e1u += a1 * u[2 * Q + j];
+    }
+    const double pw = ps[2 * Q + i];
+    ak += pw * dJ * ((g0 * e0x + g2 * e1x) + (g1 * e0y + g3 * e1y));
+    abx += pw * dJ * (g0 * e0u + g2 * e1u);
+    aby += pw * dJ * (g1 * e0u + g3 * e1u);
+  }
+  // edge terms
+  const int32_t* en = ints(tm, L.edge_node);
+  for (int k = 0; k < 3; ++k) {
+    const int fl = mi.flevel[k];
+    const int nF = (1 << fl) * Tp.p + 1;
+    const double* T1 = tm + L.T1[fl];
+    const double nx = mi.nrm[2 * k], ny = mi.nrm[2 * k + 1];
+    const bool interior = mi.tr_off[k] >= 0;
+    const double* lk = interior ? lam + mi.tr_off[k] : lamD + bf[mi.bnd_face[k]].lam_off;
+    for (int l = threadIdx.x; l < nF; l += blockDim.x) {
+      double gq = 0.0, gw = 0.0;
+      for (int sc = 0; sc <= P; ++sc) {
+        const int s = mi.orient[k] > 0 ? sc : P - sc;
+        const int node = en[k * (P + 1) + s];
+        const double t = T1[size_t(sc) * nF + l];
+        gq += t * (nx * u[node] + ny * u[Q + node]);
+        gw += t * ps[2 * Q + node];
+      }
+      gq *= mi.len[k];
+      gw *= mi.len[k];
+      if (interior) ak += psi_lam[mi.tr_off[k] + l] * gq;
+      abx -= nx * lk[l] * gw;
+      aby -= ny * lk[l] * gw;
+    }
+  }
+  red[0][threadIdx.x] = ak;
+  red[1][threadIdx.x] = abx;
+  red[2][threadIdx.x] = aby;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    dkappa[blockIdx.x] = -red[0][0];
+    dbeta_part[2 * blockIdx.x] = red[1][0];
+    dbeta_part[2 * blockIdx.x + 1] = red[2][0];
+  }
+}
+
+// out[c] = sum_K part[stride K + c] in a fixed order (c < stride)
+__global__ __launch_bounds__(256) void strided_sum_kernel(const double* __restrict__ part, int64_t n,
+                                                          int stride, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t K = threadIdx.x; K < n; K += 256) acc += part[K * stride + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// out_K,f = M_K v_K,f for the three fields (M_K = |det J| Mhat, the macro mass matrix)
+__global__ __launch_bounds__(256) void mass_kernel(const MacroInfo* __restrict__ info,
+                                                   const double* __restrict__ tm, Templates Tp,
+                                                   const double* __restrict__ v, double* __restrict__ out) {
+  extern __shared__ double sh[];
+  const MacroInfo& mi = info[blockIdx.x];
+  const int N = mi.N, Q = mi.Q;
+  const double* Mh = tm + Tp.lev[mi.level].Mhat;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) sh[i] = v[mi.loc_off + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) {
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int j = 0; j < Q; ++j) {
+      const double m = Mh[size_t(j) * Q + i];
+      a0 += m * sh[j];
+      a1 += m * sh[Q + j];
+      a2 += m * sh[2 * Q + j];
+    }
+    out[mi.loc_off + i] = mi.dJ * a0;
+    out[mi.loc_off + Q + i] = mi.dJ * a1;
+    out[mi.loc_off + 2 * Q + i] = mi.dJ * a2;
+  }
+}
+
 // ------------------------------------------------------------------ vector ops
 // Row chunks of the Krylov vectors handled by one partial dot product.
 constexpr int kDotChunk = 8192;
@@ -743,6 +873,30 @@ MS_DECL2(1) MS_DECL2(2) MS_DECL2(3) MS_DECL2(5) MS_DECL2(8) MS_DECL2(16) MS_DECL
 MS_DECL2(58)
 #undef MS_DECL2
 #undef MS_DECL
+#define MST_DECL(Q_)                                                                           \
+  extern template void macro_solve_t_launch<Q_>(int, const void*, const MacroInfo*, int64_t,    \
+                                                size_t, const int32_t*, const double*,          \
+                                                const Templates&, double, double, double,       \
+                                                const double*, const double*, double*, double*, \
+                                                hipStream_t);
+MST_DECL(1) MST_DECL(2) MST_DECL(3) MST_DECL(5) MST_DECL(8) MST_DECL(16) MST_DECL(27) MST_DECL(58)
+#undef MST_DECL
+
+static hipError_t macro_solve_t_dispatch(int nq, int mode, const void* fac, const MacroInfo* info,
+                                         int64_t n, size_t lds, const int32_t* perm,
+                                         const double* tmpl, const Templates& Tp, double bx,
+                                         double by, double tau, const double* mu, const double* xin,
+                                         double* yout, double* slots, hipStream_t s) {
+#define MST_CASE(Q_)                                                                           \
+  if (nq <= Q_) {                                                                              \
+    macro_solve_t_launch<Q_>(mode, fac, info, n, lds, perm, tmpl, Tp, bx, by, tau, mu, xin,    \
+                             yout, slots, s);                                                  \
+    return hipGetLastError();                                                                  \
+  }
+  MST_CASE(1) MST_CASE(2) MST_CASE(3) MST_CASE(5) MST_CASE(8) MST_CASE(16) MST_CASE(27) MST_CASE(58)
+#undef MST_CASE
+  return hipErrorInvalidValue;
+}
 
 template <typename T>
 static hipError_t macro_solve_dispatch(int nq, int mode, const void* fac, const MacroInfo* info,
@@ -767,12 +921,16 @@ hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int prec
                               const int32_t* perm, const double* tmpl, const Templates& T,
                               double bx, double by, double tau, const double* lam,
                               const double* xin, double* yout, double* slots, hipStream_t s) {
-  (void)transpose;
   int maxP = 0;
   for (int r = 0; r <= kMaxLevel; ++r)
     if (T.lev[r].present && T.lev[r].P > maxP) maxP = T.lev[r].P;
   const size_t lds = size_t(18) * maxP * sizeof(double);
   const int nq = (max_N + 63) / 64;
+  if (transpose) {
+    if (precision != 0) return hipErrorInvalidValue;
+    return macro_solve_t_dispatch(nq, mode, fac, info, n, lds, perm, tmpl, T, bx, by, tau, lam, xin,
+                                  yout, slots, s);
+  }
   if (precision == 1)
     return macro_solve_dispatch<float>(nq, mode, fac, info, n, lds, perm, tmpl, T, bx, by, tau,
                                        lam, xin, yout, slots, s);
@@ -822,6 +980,25 @@ hipError_t launch_boundary_C(const MacroInfo* info, int64_t n, const double* tmp
   size_t lds = size_t(9 * max_present_P(T)) * sizeof(double);
   hipLaunchKernelGGL(boundary_C_kernel, dim3((unsigned)n), dim3(64), lds, s, info, tmpl, T, tau, U,
                      slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_contract(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
+                                   const double* tmpl, const Templates& T, const double* U,
+                                   const double* Psi, const double* lam, const double* psi_lam,
+                                   const double* lamD, double* dkappa, double* dbeta_part,
+                                   double* dbeta, hipStream_t s) {
+  size_t lds = size_t(2 * max_present_N(T)) * sizeof(double);
+  hipLaunchKernelGGL(adjoint_contract_kernel, dim3((unsigned)n), dim3(256), lds, s, info, bf, tmpl,
+                     T, U, Psi, lam, psi_lam, lamD, dkappa, dbeta_part);
+  hipLaunchKernelGGL(strided_sum_kernel, dim3(2), dim3(256), 0, s, dbeta_part, n, 2, dbeta);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass(const MacroInfo* info, int64_t n, const double* tmpl, const Templates& T,
+                       const double* v, double* out, hipStream_t s) {
+  size_t lds = size_t(max_present_N(T)) * sizeof(double);
+  hipLaunchKernelGGL(mass_kernel, dim3((unsigned)n), dim3(256), lds, s, info, tmpl, T, v, out);
   return hipGetLastError();
 }
 

@@ -15,6 +15,12 @@ __device__ __forceinline__ const int32_t* ints_(const double* base, int64_t off)
 // Boundary entries of a macro's local vectors are kept compactly: field f
 // (q_x, q_y, u), boundary position b = kP + s (edge k, position s < P along
 // it), index f * 3P + b.  Only these rows of x = B lam and of C y are nonzero.
+__device__ __forceinline__ double wave_sum_(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ int bpos(int k, int s, int P) { return s < P ? k * P + s : ((k + 1) % 3) * P; }
 
 __device__ __forceinline__ double readlane_d(double v, int l) {
@@ -24,47 +30,70 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// xc += sgn * B_k lam_F (step 1): the rows v_x, v_y, w of the boundary nodes
-// of edge k receive n_x g, n_y g, (a.n - tau) g with g_s = |F| sum_l
-// T1[s][l] lam_l, T1 coupling the level-r edge space with the face's trace
-// space, both in the face's canonical direction.
-__device__ inline void edge_B(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
-                       const double* lamF, double sgn, double bx, double by, double tau,
-                       double* xc) {
+// Boundary-row couplings of local edge k.  With G[i][l] = <mu_l, phi_i>_F =
+// |F| T1[s][l] (T1 couples the level-r edge space with the face's trace
+// space, both in the face's canonical direction, s the canonical position of
+// boundary node i) every trace coupling of the method has the form
+//   scatter: x[f][b(i)] += sgn c_f sum_l G[i][l] v_l      (B v: c = (n_x, n_y, a.n - tau);
+//                                                         C^T v: c = (kappa n_x, kappa n_y, tau))
+//   gather:  out_l = sum_i G[i][l] (c_0 z_0 + c_1 z_1 + c_2 z_2)(i)
+//                                                        (C z: c = (kappa n_x, kappa n_y, tau);
+//                                                         B^T z: c = (n_x, n_y, a.n - tau))
+struct EdgeCoef { double c0, c1, c2; };
+
+__device__ __forceinline__ EdgeCoef coef_B(const MacroInfo& mi, int k, double bx, double by, double tau) {
+  const double nx = mi.nrm[2 * k], ny = mi.nrm[2 * k + 1];
+  return {nx, ny, bx * nx + by * ny - tau};
+}
+__device__ __forceinline__ EdgeCoef coef_C(const MacroInfo& mi, int k, double tau) {
+  return {mi.kappa * mi.nrm[2 * k], mi.kappa * mi.nrm[2 * k + 1], tau};
+}
+
+__device__ inline void edge_scatter(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
+                                    const double* vF, double sgn, EdgeCoef c, double* xc) {
   const LevelTemplates& L = Tp.lev[mi.level];
   const int P = mi.P, NBD = 3 * P, fl = mi.flevel[k];
   const int nF = (1 << fl) * Tp.p + 1;
   const double* T1 = tm + L.T1[fl];
-  const double nx = mi.nrm[2 * k], ny = mi.nrm[2 * k + 1];
-  const double an = bx * nx + by * ny - tau;
   for (int s = threadIdx.x; s <= P; s += blockDim.x) {
     const int sc = mi.orient[k] > 0 ? s : P - s;
     double g = 0.0;
-    for (int l = 0; l < nF; ++l) g += T1[size_t(sc) * nF + l] * lamF[l];
+    for (int l = 0; l < nF; ++l) g += T1[size_t(sc) * nF + l] * vF[l];
     g *= sgn * mi.len[k];
     const int b = bpos(k, s, P);
-    xc[b] += nx * g;
-    xc[NBD + b] += ny * g;
-    xc[2 * NBD + b] += an * g;
+    xc[b] += c.c0 * g;
+    xc[NBD + b] += c.c1 * g;
+    xc[2 * NBD + b] += c.c2 * g;
   }
 }
 
-// out_l = (C_k z)_l = |F| sum_s T1[s][l] (kappa n.q + tau u)(boundary node s) (step 3)
-__device__ inline void edge_C(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
-                       const double* zc, double tau, double* out) {
+__device__ inline void edge_gather(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
+                                   const double* zc, EdgeCoef c, double* out) {
   const LevelTemplates& L = Tp.lev[mi.level];
   const int P = mi.P, NBD = 3 * P, fl = mi.flevel[k];
   const int nF = (1 << fl) * Tp.p + 1;
   const double* T1 = tm + L.T1[fl];
-  const double kx = mi.kappa * mi.nrm[2 * k], ky = mi.kappa * mi.nrm[2 * k + 1];
   for (int l = threadIdx.x; l < nF; l += blockDim.x) {
     double v = 0.0;
     for (int sc = 0; sc <= P; ++sc) {
       const int b = bpos(k, mi.orient[k] > 0 ? sc : P - sc, P);
-      v += T1[size_t(sc) * nF + l] * (kx * zc[b] + ky * zc[NBD + b] + tau * zc[2 * NBD + b]);
+      v += T1[size_t(sc) * nF + l] * (c.c0 * zc[b] + c.c1 * zc[NBD + b] + c.c2 * zc[2 * NBD + b]);
     }
     out[l] = mi.len[k] * v;
   }
+}
+
+// xc += sgn * B_k lam_F (step 1)
+__device__ inline void edge_B(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
+                              const double* lamF, double sgn, double bx, double by, double tau,
+                              double* xc) {
+  edge_scatter(mi, k, tm, Tp, lamF, sgn, coef_B(mi, k, bx, by, tau), xc);
+}
+
+// out = C_k z (step 3)
+__device__ inline void edge_C(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
+                              const double* zc, double tau, double* out) {
+  edge_gather(mi, k, tm, Tp, zc, coef_C(mi, k, tau), out);
 }
 
 // One wavefront per macro.  The permuted right-hand side and then the
@@ -206,6 +235,124 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
     for (int k = 0; k < 3; ++k)
       if (mi.tr_off[k] >= 0) edge_C(mi, k, tm, Tp, zc, tau, slots + mi.slot_off[k]);
   }
+}
+
+// Transposed per-macro solve y = A^-T x (adjoint), one wavefront per macro.
+// With P A = L U held column-major: U^T w = x uses column i of U for row i
+// of the forward sweep, L^T v = w column i of L for the backward sweep (each
+// a dot product over contiguous memory and one wavefront reduction), then
+// z[perm[i]] = v[i].  Modes as the forward solve, with C^T in place of B on
+// input and B^T in place of C on output.
+template <typename T, int NQ>
+__global__ __launch_bounds__(64) void macro_solve_t_kernel(
+    int mode, const T* __restrict__ fac, const MacroInfo* __restrict__ info,
+    const int32_t* __restrict__ perm_all, const double* __restrict__ tm, Templates Tp, double bx,
+    double by, double tau, const double* __restrict__ mu, const double* xin, double* yout,
+    double* __restrict__ slots) {
+  extern __shared__ double sm[];
+  const MacroInfo& mi = info[blockIdx.x];
+  const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P, lane = threadIdx.x;
+  double* xc = sm;
+  double* zc = sm + 3 * NBD;
+  const int32_t* bidx = ints_(tm, Tp.lev[mi.level].bnd_index);
+  const T* A = fac + mi.fac_off;
+  const int32_t* perm = perm_all + mi.loc_off;
+  const bool with_Ct = mode == MODE_APPLY || mode == MODE_RECOVER;
+  if (with_Ct) {
+    for (int i = lane; i < 3 * NBD; i += 64) xc[i] = 0.0;
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+      if (mi.tr_off[k] >= 0)
+        edge_scatter(mi, k, tm, Tp, mu + mi.tr_off[k], mode == MODE_APPLY ? 1.0 : -1.0,
+                     coef_C(mi, k, tau), xc);
+      __syncthreads();
+    }
+  }
+  double y[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    double v = 0.0;
+    if (i < N) {
+      if (mode != MODE_APPLY) v = xin[mi.loc_off + i];
+      if (with_Ct) {
+        const int f = i / Q;
+        const int b = bidx[i - f * Q];
+        if (b >= 0) v += xc[f * NBD + b];
+      }
+    }
+    y[q] = v;
+  }
+  // ---- U^T w = x
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int jend = min(64, N - 64 * q);
+    for (int jj = 0; jj < jend; ++jj) {
+      const int i = 64 * q + jj;
+      const T* col = A + size_t(i) * N;
+      double part = 0.0;
+#pragma unroll
+      for (int t = 0; t <= q; ++t) {
+        const int r = lane + 64 * t;
+        const double a = (double)col[r];
+        part += (r < i ? a : 0.0) * y[t];
+      }
+      const double tot = wave_sum_(part);
+      const double wi = (readlane_d(y[q], jj) - tot) / (double)col[i];
+      if (lane == jj) y[q] = wi;
+    }
+  }
+  // ---- L^T v = w
+#pragma unroll
+  for (int q = NQ - 1; q >= 0; --q) {
+    const int jend = min(64, N - 64 * q);
+    for (int jj = jend - 1; jj >= 0; --jj) {
+      const int i = 64 * q + jj;
+      const T* col = A + size_t(i) * N;
+      double part = 0.0;
+#pragma unroll
+      for (int t = q; t < NQ; ++t) {
+        const int r = lane + 64 * t;
+        const double a = (double)col[r];
+        part += ((r > i && r < N) ? a : 0.0) * y[t];
+      }
+      const double tot = wave_sum_(part);
+      const double vi = readlane_d(y[q], jj) - tot;
+      if (lane == jj) y[q] = vi;
+    }
+  }
+  // ---- z[perm[i]] = v[i]; outputs
+  if (mode == MODE_RECOVER || mode == MODE_LOCAL) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      if (i < N) yout[mi.loc_off + perm[i]] = y[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      if (i < N) {
+        const int r = perm[i];
+        const int f = r / Q;
+        const int b = bidx[r - f * Q];
+        if (b >= 0) zc[f * NBD + b] = y[q];
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < 3; ++k)
+      if (mi.tr_off[k] >= 0)
+        edge_gather(mi, k, tm, Tp, zc, coef_B(mi, k, bx, by, tau), slots + mi.slot_off[k]);
+  }
+}
+
+template <int NQ>
+void macro_solve_t_launch(int mode, const void* fac, const MacroInfo* info, int64_t n, size_t lds,
+                          const int32_t* perm, const double* tmpl, const Templates& Tp, double bx,
+                          double by, double tau, const double* mu, const double* xin, double* yout,
+                          double* slots, hipStream_t s) {
+  hipLaunchKernelGGL((macro_solve_t_kernel<double, NQ>), dim3((unsigned)n), dim3(64), lds, s, mode,
+                     (const double*)fac, info, perm, tmpl, Tp, bx, by, tau, mu, xin, yout, slots);
 }
 
 template <typename T, int NQ>

@@ -25,7 +25,7 @@ ABI_SYMBOLS = [
     "mhdg_setup_macro_mesh", "mhdg_query", "mhdg_sample_points", "mhdg_factor_local",
     "mhdg_local_matrix", "mhdg_apply_trace_operator", "mhdg_local_solve", "mhdg_rhs",
     "mhdg_solve", "mhdg_recover_local", "mhdg_destroy", "mhdg_last_error",
-    "mhdg_status_string", "mhdg_profile",
+    "mhdg_status_string", "mhdg_profile", "mhdg_mass_apply", "mhdg_adjoint",
 ]
 
 
@@ -95,6 +95,9 @@ def load_library(path: str = LIB_PATH):
         "mhdg_solve": [P, P, P, ctypes.POINTER(SolveOpts), P, P, SZ, ctypes.POINTER(SolveInfo), P],
         "mhdg_recover_local": [P, P, P, P, P],
         "mhdg_profile": [P, I32, ctypes.POINTER(KernelTimes)],
+        "mhdg_mass_apply": [P, P, P, P],
+        "mhdg_adjoint": [P, P, P, P, ctypes.POINTER(SolveOpts), P, P, P, P, P, SZ,
+                         ctypes.POINTER(SolveInfo), P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -224,6 +227,26 @@ class MacroMesh:
                                   _stream(stream))
         if check:
             self._check(st, "solve")
+        return info
+
+    def mass_apply(self, v, out, stream=None):
+        self._check(self._lib.mhdg_mass_apply(self.h, _ptr(v), _ptr(out), _stream(stream)),
+                    "mass_apply")
+
+    def adjoint(self, lam, qu, dJ_dU, psi_lam, psi_U, dJ_dkappa, dJ_dbeta, rtol=1e-12,
+                restart=300, max_iter=20000, stream=None):
+        import torch
+        s = self.query(self.precision, restart)
+        if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
+            self.solve_ws = None
+            self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
+        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0)
+        info = SolveInfo()
+        self._check(self._lib.mhdg_adjoint(self.h, _ptr(lam), _ptr(qu), _ptr(dJ_dU),
+                                           ctypes.byref(opts), _ptr(psi_lam), _ptr(psi_U),
+                                           _ptr(dJ_dkappa), _ptr(dJ_dbeta), _ptr(self.solve_ws),
+                                           self.solve_ws.numel(), ctypes.byref(info),
+                                           _stream(stream)), "adjoint")
         return info
 
     def profile(self, enable: bool):

@@ -1,0 +1,135 @@
+"""GPU parity of the transposed operator and the hand-written adjoint.
+
+Transposed applies and A^-T solves against the oracle (relative 1e-10);
+dJ/dkappa and dJ/dbeta against the oracle adjoint (relative 1e-8, both sides
+solving to tight tolerances) and against central finite differences of the
+GPU forward solve (relative 1e-5: the FD truncation and solve tolerance
+bound it); the torch.autograd path end to end.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from oracle import hdg
+from paper_2302_10917_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_10917_amd import autograd as ad  # noqa: E402
+from paper_2302_10917_amd import mhdg  # noqa: E402
+
+DEV = "cuda"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _problem(n=2, r=1, p=2, jitter=0.1):
+    xy, tri = inputs.structured_mesh(n, jitter=jitter, seed=3)
+    kappa = inputs.lognormal_kappa(len(tri), 0.5, seed=5)
+    beta = np.array([1.0, 1.0])
+    return xy, tri, r, p, kappa, beta
+
+
+@pytest.mark.parametrize("spec", [(2, 1, 2), (3, 2, 3), (2, 3, 3)])
+def test_transposed_apply_and_local_solve(spec):
+    n, r, p = spec
+    xy, tri, r, p, kappa, beta = _problem(n, r, p)
+    orc = hdg.Oracle(xy, tri, r, p, kappa, beta, 1.0)
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    m.factor_local(gpu(kappa), beta, 1.0)
+    ex = inputs.exp_sin(1.0, beta)
+    fo, go = orc.sample(ex)
+    S, _, _ = orc.condensed(fo, go)
+    lam = inputs.random_vector(orc.topo.n_trace, seed=4)
+    out = torch.empty(orc.topo.n_trace, dtype=torch.float64, device=DEV)
+    m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_TRANSPOSE)
+    assert rel(host(out), S.T @ lam) <= 1e-10
+    m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_TRANSPOSE | mhdg.MHDG_PRECONDITION)
+    assert rel(host(out), orc.precondition(S.T @ lam)) <= 1e-10
+    x = inputs.random_vector(int(orc.topo.local_off[-1]), seed=6)
+    y = torch.empty(len(x), dtype=torch.float64, device=DEV)
+    m.local_solve(gpu(x), y, mhdg.MHDG_TRANSPOSE)
+    yh = host(y)
+    for K in range(orc.topo.n_macro):
+        lo, hi = orc.topo.local_off[K], orc.topo.local_off[K + 1]
+        assert rel(yh[lo:hi], orc.local_solve(K, x[lo:hi], transpose=True)) <= 1e-10
+
+
+def _u_obs(xy, tri, r, p, kappa, beta, ex, m):
+    """u_obs: the GPU solution for kappa exp(0.1 eta) (FE field, local layout)."""
+    eta = np.random.default_rng(55).standard_normal(len(tri))
+    node, bnd = m.sample_points()
+    f = gpu(ex.f(node[:, 0], node[:, 1]))
+    g = gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+    with torch.no_grad():
+        qu_obs = ad.solve(gpu(kappa * np.exp(0.1 * eta)), torch.tensor(beta), m, f, g)
+    return qu_obs.clone(), f, g
+
+
+def test_adjoint_matches_oracle_adjoint():
+    xy, tri, r, p, kappa, beta = _problem(2, 1, 2)
+    ex = inputs.exp_sin(1.0, (1.0, 1.0))
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    qu_obs, f, g = _u_obs(xy, tri, r, p, kappa, beta, ex, m)
+    k = gpu(kappa).requires_grad_(True)
+    b = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
+    qu = ad.solve(k, b, m, f, g)
+    J = ad.l2_misfit(m, qu, qu_obs)
+    J.backward()
+    # oracle adjoint with the same u_obs field
+    orc = hdg.Oracle(xy, tri, r, p, kappa, beta, 1.0)
+    Q = int(orc.topo.Q[0])
+    uo = host(qu_obs).reshape(len(tri), 3, Q)[:, 2, :]
+    fo, go = orc.sample(ex)
+    Jo, dko, dbo, _, _, _, _ = oadj.gradient(orc, fo, go, [uo[K] for K in range(len(tri))])
+    assert abs(J.item() - Jo) <= 1e-9 * abs(Jo)
+    assert rel(host(k.grad), dko) <= 1e-8
+    assert rel(b.grad.numpy(), dbo) <= 1e-8
+
+
+def test_adjoint_matches_central_differences_on_gpu():
+    """Differentiation workload shape (r = 2, p = 2, log-normal kappa, a = (1, 1),
+    f fixed, g_D = 0) on a 4x4-square mesh."""
+    xy, tri, r, p, kappa, beta = _problem(4, 2, 2, jitter=0.0)
+    ex = inputs.sin_sin(1.0, (1.0, 1.0))
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    qu_obs, f, g = _u_obs(xy, tri, r, p, kappa, beta, ex, m)
+    k = gpu(kappa).requires_grad_(True)
+    b = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
+    J = ad.l2_misfit(m, ad.solve(k, b, m, f, g, 1e-13), qu_obs)
+    J.backward()
+    dk, db = host(k.grad), b.grad.numpy()
+
+    def Jof(kap, bet):
+        with torch.no_grad():
+            qu = ad.solve(gpu(kap), torch.tensor(bet), m, f, g, 1e-13)
+            return ad.l2_misfit(m, qu, qu_obs).item()
+
+    h = 1e-5
+    for K in (0, 7, 19, len(tri) - 1):
+        kp, km = kappa.copy(), kappa.copy()
+        kp[K] *= 1 + h
+        km[K] *= 1 - h
+        fd = (Jof(kp, beta) - Jof(km, beta)) / (2 * h * kappa[K])
+        assert abs(fd - dk[K]) <= 1e-5 * abs(fd) + 1e-9 * abs(J.item()), (K, fd, dk[K])
+    for d in range(2):
+        bp, bm = beta.copy(), beta.copy()
+        bp[d] += h
+        bm[d] -= h
+        fd = (Jof(kappa, bp) - Jof(kappa, bm)) / (2 * h)
+        assert abs(fd - db[d]) <= 1e-5 * abs(fd) + 1e-9 * abs(J.item()), (d, fd, db[d])
