@@ -43,6 +43,11 @@ WORKLOADS = {
                                              sol="exp_sin", precision="fp32"),
     "plain_fp64_8192macro_r3_p3_kappa1e-3": dict(n=64, r=3, p=3, kappa=1e-3, beta=(1.0, 0.5),
                                                  sol="exp_sin", precision="fp64"),
+    # differentiation configuration: 128 x 128 squares (32,768 macros), r = 2, p = 2,
+    # kappa_K = exp(0.5 xi_K) (seed 5), a = (1, 1), f fixed (u = sin sin with kappa = 1,
+    # a = (1, 1)), g_D = 0; J = ||u_h - u_obs||^2, u_obs for kappa exp(0.1 eta) (seed 55)
+    "adjoint_32768macro_r2_p2": dict(n=128, r=2, p=2, kappa=None, beta=(1.0, 1.0), sol="sin_sin",
+                                     precision="fp64", form="adjoint", restart=8000, rtol=1e-9),
 }
 
 
@@ -107,10 +112,16 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plain_fp64_8192macro_r3_p3", choices=list(WORKLOADS))
-    ap.add_argument("--restart", type=int, default=2000)
-    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--restart", type=int, default=None,
+                    help="GMRES Krylov length (default: 2000, 8000 for the differentiation workload)")
+    ap.add_argument("--rtol", type=float, default=None,
+                    help="GMRES relative tolerance (default 1e-10; 1e-9 for the differentiation "
+                         "workload, whose 440,064-unknown trace system stalls near 1e-10)")
     ap.add_argument("--inner-rtol", type=float, default=1e-5,
                     help="inner GMRES tolerance per refinement step (FP32 factors)")
+    ap.add_argument("--fd-check", action="store_true",
+                    help="differentiation workload: central differences of J on sampled kappa_K "
+                         "and on both advection components, against the adjoint gradient")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="after the timed steps, solve again with FP64 factors and report the "
                          "relative differences of lambda, q and u")
@@ -131,6 +142,12 @@ def main():
     from paper_2302_10917_amd import inputs, mhdg
 
     w = WORKLOADS[args.workload]
+    if args.restart is None:
+        args.restart = w.get("restart", 2000)
+    if args.rtol is None:
+        args.rtol = w.get("rtol", 1e-10)
+    if w.get("form") == "adjoint":
+        return bench_adjoint(args, w)
     xy, tri = inputs.structured_mesh(w["n"])
     ex = getattr(inputs, w["sol"])(w["kappa"], w["beta"])
     m = mhdg.MacroMesh(xy, tri, w["r"], w["p"])
@@ -273,6 +290,113 @@ def main():
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(xy, tri, w)
+    print(json.dumps(result), flush=True)
+
+
+def bench_adjoint(args, w):
+    """One step = forward solve (factor_local + solve + recover_local) plus the
+    objective and its adjoint gradient (mhdg_adjoint behind torch.autograd)."""
+    import torch
+    from paper_2302_10917_amd import autograd as ad
+    from paper_2302_10917_amd import inputs, mhdg
+
+    xy, tri = inputs.structured_mesh(w["n"])
+    n_macro = len(tri)
+    m = mhdg.MacroMesh(xy, tri, w["r"], w["p"])
+    s = m.sizes
+    node, bnd = m.sample_points()
+    ex = inputs.sin_sin(1.0, (1.0, 1.0))
+    dev = "cuda"
+    f = torch.as_tensor(ex.f(node[:, 0], node[:, 1]), device=dev)
+    g = torch.as_tensor(ex.u(bnd[:, 0], bnd[:, 1]), device=dev)
+    kappa = inputs.lognormal_kappa(n_macro, 0.5, seed=5)
+    eta = np.random.default_rng(55).standard_normal(n_macro)
+    beta = torch.tensor(w["beta"], dtype=torch.float64)
+    print(f"[bench] {args.workload}: {n_macro} macros, N_K={s.max_local}, n_trace={s.n_trace}",
+          file=sys.stderr, flush=True)
+    with torch.no_grad():
+        qu_obs = ad.solve(torch.as_tensor(kappa * np.exp(0.1 * eta), device=dev), beta, m, f, g,
+                          args.rtol, args.restart).clone()
+    print(f"[bench] u_obs solved: {m.last_solve_info['iterations']} iterations", file=sys.stderr,
+          flush=True)
+    infos = []
+
+    def step():
+        k = torch.as_tensor(kappa, device=dev).requires_grad_(True)
+        b = beta.clone().requires_grad_(True)
+        J = ad.l2_misfit(m, ad.solve(k, b, m, f, g, args.rtol, args.restart), qu_obs)
+        fwd = dict(m.last_solve_info)
+        J.backward()
+        infos.append((fwd, dict(m.last_adjoint_info)))
+        return J.item(), k.grad, b.grad
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+    infos.clear()
+    m.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        J, dk, db = step()
+        print(f"[bench] step {i}: forward {infos[-1][0]['iterations']} it, adjoint "
+              f"{infos[-1][1]['iterations']} it, J = {J:.6e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = m.profile(False)
+    applies = sum(a["n_applies"] + b_["n_applies"] for a, b_ in infos)
+    fd = None
+    if args.fd_check:
+        print("[bench] central differences (outside the timed region)", file=sys.stderr, flush=True)
+
+        def Jof(kap, bet):
+            with torch.no_grad():
+                qu = ad.solve(torch.as_tensor(kap, device=dev), torch.tensor(bet), m, f, g,
+                              args.rtol, args.restart)
+                return ad.l2_misfit(m, qu, qu_obs).item()
+        # J is smooth in kappa_K: a relative step of 1e-3 keeps the central-difference
+        # truncation small while lifting the J difference above the solve tolerance
+        h, hk = 1e-5, 1e-3
+        dkh = dk.cpu().numpy()
+        fd = {"step_beta": h, "step_kappa_rel": hk, "kappa": [], "beta": []}
+        for K in (int(np.argmax(np.abs(dkh))), n_macro // 3):
+            kp, km = kappa.copy(), kappa.copy()
+            kp[K] *= 1 + hk
+            km[K] *= 1 - hk
+            v = (Jof(kp, w["beta"]) - Jof(km, w["beta"])) / (2 * hk * kappa[K])
+            fd["kappa"].append({"macro": K, "fd": v, "adjoint": float(dkh[K]),
+                                "rel_diff": abs(v - dkh[K]) / abs(v)})
+            print(f"[bench] fd kappa_{K}: {fd['kappa'][-1]}", file=sys.stderr, flush=True)
+        for d in range(2):
+            bp, bm = list(w["beta"]), list(w["beta"])
+            bp[d] += h
+            bm[d] -= h
+            v = (Jof(kappa, bp) - Jof(kappa, bm)) / (2 * h)
+            fd["beta"].append({"d": d, "fd": v, "adjoint": float(db[d]),
+                               "rel_diff": abs(v - float(db[d])) / abs(v)})
+            print(f"[bench] fd beta_{d}: {fd['beta'][-1]}", file=sys.stderr, flush=True)
+    ams = kt["apply_macro_solve"]
+    avg_ms = ams["ms"] / max(ams["count"], 1)
+    nbytes = apply_bytes(m, 8)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC, "value": applies / elapsed, "unit": "applies/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_macro": n_macro, "r": w["r"], "p": w["p"],
+                   "N_K": s.max_local, "n_trace": s.n_trace, "kappa": "lognormal sigma 0.5 seed 5",
+                   "beta": list(w["beta"]), "tau": 1.0, "rtol": args.rtol,
+                   "gmres_restart": args.restart, "form": "forward + adjoint gradient"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "macro_solve_kernel<double> (forward apply steps 1-3)",
+                     "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms, "launches": ams["count"]},
+        "forward_iterations": [a["iterations"] for a, _ in infos],
+        "adjoint_iterations": [b_["iterations"] for _, b_ in infos],
+        "kernel_ms": {k: v["ms"] / max(args.steps, 1) for k, v in kt.items()},
+        "J": J, "dJ_dbeta": [float(x) for x in db], "fd_check": fd,
+    }
     print(json.dumps(result), flush=True)
 
 

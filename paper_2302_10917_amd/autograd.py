@@ -30,7 +30,7 @@ def _forward(mesh, kappa, beta, f, g, rtol, restart):
     s = mesh.sizes
     mesh.factor_local(kappa.detach(), (float(beta[0]), float(beta[1])), 1.0)
     lam = torch.zeros(s.n_trace, dtype=torch.float64, device="cuda")
-    mesh.solve(f, g, lam, rtol=rtol, restart=restart, max_iter=50000)
+    mesh.solve(f, g, lam, rtol=rtol, restart=restart, max_iter=max(50000, 2 * restart))
     qu = torch.empty(s.n_local, dtype=torch.float64, device="cuda")
     mesh.recover_local(lam, qu)
     if not hasattr(mesh, "_ad_state"):

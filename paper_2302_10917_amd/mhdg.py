@@ -225,6 +225,7 @@ class MacroMesh:
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
                                   _ptr(self.solve_ws), self.solve_ws.numel(), ctypes.byref(info),
                                   _stream(stream))
+        self.last_solve_info = info.as_dict()
         if check:
             self._check(st, "solve")
         return info
@@ -247,6 +248,7 @@ class MacroMesh:
                                            _ptr(dJ_dkappa), _ptr(dJ_dbeta), _ptr(self.solve_ws),
                                            self.solve_ws.numel(), ctypes.byref(info),
                                            _stream(stream)), "adjoint")
+        self.last_adjoint_info = info.as_dict()
         return info
 
     def profile(self, enable: bool):
