@@ -46,19 +46,36 @@ WORKLOADS = {
     # differentiation configuration: 128 x 128 squares (32,768 macros), r = 2, p = 2,
     # kappa_K = exp(0.5 xi_K) (seed 5), a = (1, 1), f fixed (u = sin sin with kappa = 1,
     # a = (1, 1)), g_D = 0; J = ||u_h - u_obs||^2, u_obs for kappa exp(0.1 eta) (seed 55)
+    # batching configuration, one coefficient instance at a time: 8192 macros with r drawn
+    # from {1,2,3,4} (seed 3), p = 3, instance i of 64 (kappa log-uniform [1e-3, 1],
+    # a random direction, |a| in [0.5, 2], seed 33), u = exp(x) sin(2 pi y) data
+    "mixed_r1to4_8192macro_p3_inst0": dict(n=64, r="mixed", p=3, kappa=None, beta=None,
+                                           sol="exp_sin", precision="fp64", instance=0),
     "adjoint_32768macro_r2_p2": dict(n=128, r=2, p=2, kappa=None, beta=(1.0, 1.0), sol="sin_sin",
                                      precision="fp64", form="adjoint", restart=8000, rtol=1e-9),
 }
 
 
-def apply_bytes(m, elem_bytes=8) -> float:
-    """Algorithmic HBM bytes of one launch of the apply's per-macro solve:
-    every stored LU entry once (b N_K^2, b = 8 for FP64 factors, 4 for FP32),
-    the pivot vector (4 N_K), the gathered trace and the written contribution
-    slots (2 x 8 x 2 n_trace)."""
+def apply_bytes(m, elem_bytes=8, levels=None, p=None) -> float:
+    """Algorithmic HBM bytes of one apply's per-macro solves: every stored LU
+    entry once (b N_K^2, b = 8 for FP64 factors, 4 for FP32), the pivot vector
+    (4 N_K), the gathered trace and the written contribution slots (about
+    2 x 8 x 2 n_trace)."""
     s = m.sizes
-    n_e = s.max_local  # uniform level: every macro has N_K = max_local
-    return float(s.n_macro) * (elem_bytes * n_e * n_e + 4.0 * n_e) + 32.0 * s.n_trace
+    if levels is None:
+        n_e = np.full(s.n_macro, float(s.max_local))
+    else:
+        P = (2 ** np.asarray(levels, dtype=np.int64)) * p
+        n_e = 3.0 * (P + 1) * (P + 2) / 2
+    return float(np.sum(elem_bytes * n_e * n_e + 4.0 * n_e)) + 32.0 * s.n_trace
+
+
+def lu_flops(w, s):
+    """(2/3) N_K^3 summed over macros."""
+    if np.ndim(w["r"]) == 0:
+        return s.n_macro * (2.0 / 3.0) * float(s.max_local) ** 3
+    P = (2 ** np.asarray(w["r"], dtype=np.int64)) * w["p"]
+    return float(np.sum((2.0 / 3.0) * (3.0 * (P + 1) * (P + 2) / 2) ** 3))
 
 
 def cpu_baseline(xy, tri, w, lam_seed=1, n_sample=16, budget_s=15.0):
@@ -141,7 +158,7 @@ def main():
     import torch
     from paper_2302_10917_amd import inputs, mhdg
 
-    w = WORKLOADS[args.workload]
+    w = dict(WORKLOADS[args.workload])
     if args.restart is None:
         args.restart = w.get("restart", 2000)
     if args.rtol is None:
@@ -149,6 +166,11 @@ def main():
     if w.get("form") == "adjoint":
         return bench_adjoint(args, w)
     xy, tri = inputs.structured_mesh(w["n"])
+    if w["r"] == "mixed":
+        w["r"] = inputs.random_levels(len(tri), (1, 2, 3, 4), seed=3)
+        kap_i, beta_i = inputs.coefficient_instances(64, seed=33)
+        w["kappa"] = float(kap_i[w["instance"]])
+        w["beta"] = tuple(float(x) for x in beta_i[w["instance"]])
     ex = getattr(inputs, w["sol"])(w["kappa"], w["beta"])
     m = mhdg.MacroMesh(xy, tri, w["r"], w["p"])
     s = m.sizes
@@ -226,8 +248,11 @@ def main():
     del buf
 
     # discretisation error of the solution (sanity: the manufactured solution)
-    u_h = qu.view(s.n_macro, 3, Q)[:, 2, :].reshape(-1).cpu().numpy()
-    u_err = float(np.abs(u_h - ex.u(node[:, 0], node[:, 1])).max())
+    if np.ndim(w["r"]) == 0:
+        u_h = qu.view(s.n_macro, 3, Q)[:, 2, :].reshape(-1).cpu().numpy()
+        u_err = float(np.abs(u_h - ex.u(node[:, 0], node[:, 1])).max())
+    else:
+        u_err = None
 
     cmp = None
     if args.compare_fp64 and prec != mhdg.MHDG_FP64:
@@ -247,7 +272,8 @@ def main():
 
     ams = kt["apply_macro_solve"]
     avg_ms = ams["ms"] / max(ams["count"], 1)
-    nbytes = apply_bytes(m, 4 if prec == mhdg.MHDG_FP32 else 8)
+    nbytes = apply_bytes(m, 4 if prec == mhdg.MHDG_FP32 else 8,
+                         None if np.ndim(w["r"]) == 0 else w["r"], w["p"])
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     lu = kt["lu"]
     result = {
@@ -263,7 +289,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == mhdg.MHDG_FP64 else "f32 factors, f64 refinement",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_macro": s.n_macro, "r": w["r"], "p": w["p"],
+        "config": {"workload": args.workload, "n_macro": s.n_macro,
+                   "r": w["r"] if np.ndim(w["r"]) == 0 else "U{1,2,3,4} seed 3", "p": w["p"],
                    "N_K": s.max_local, "n_trace": s.n_trace, "kappa": w["kappa"],
                    "beta": list(w["beta"]), "tau": 1.0, "rtol": args.rtol,
                    "gmres_restart": args.restart,
@@ -284,8 +311,8 @@ def main():
         "apply_only_per_s": apply_only,
         "stream_read_gbs": stream_gbs,
         "kernel_ms": {k: v["ms"] / max(args.steps, 1) for k, v in kt.items()},
-        "lu_tflops": (s.n_macro * (2.0 / 3.0) * s.max_local ** 3) / (lu["ms"] / max(lu["count"], 1)
-                                                                      * 1e-3) / 1e12 if lu["count"] else None,
+        "lu_tflops": lu_flops(w, s) / (lu["ms"] / max(lu["count"], 1) * 1e-3) / 1e12
+        if lu["count"] else None,
         "u_max_err_vs_exact": u_err,
     }
     if not args.no_cpu_baseline:

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -26,7 +27,8 @@ struct mhdg_mesh {
   std::vector<MacroInfo> macros;
   std::vector<FaceInfo> faces;
   std::vector<BndFaceInfo> bfaces;
-  std::vector<int32_t> order;     // macro processing order (largest first)
+  std::vector<int32_t> order;     // macro processing order (largest local size first)
+  std::vector<SizeClass> classes; // contiguous runs of equal local size in that order
   int64_t n_trace = 0, n_nodes = 0, n_local = 0, n_bnd_points = 0, n_slots = 0, n_lamD = 0;
   int32_t max_level = 0, max_N = 0;
   // templates
@@ -377,6 +379,7 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   L.faces = o;  o = align_up(o + M->faces.size() * sizeof(FaceInfo));
   L.bfaces = o; o = align_up(o + M->bfaces.size() * sizeof(BndFaceInfo));
   L.tmpl = o;   o = align_up(o + M->tmpl.size() * sizeof(double));
+  L.order = o;  o = align_up(o + size_t(M->n_macro) * sizeof(int32_t));
   L.perm = o;   o = align_up(o + size_t(M->n_local) * sizeof(int32_t));
   L.status = o; o = align_up(o + size_t(M->n_macro) * sizeof(int32_t));
   L.R = o;      o = align_up(o + size_t(M->n_local) * sizeof(double));
@@ -399,6 +402,13 @@ static size_t solve_bytes(const mhdg_mesh* M, int restart) { return solve_bytes_
 
 // ---------------------------------------------------------------- GMRES
 namespace {
+
+// MHDG_PROGRESS=k in the environment prints the GMRES residual every k
+// iterations to stderr (long solves on large meshes).
+const int g_progress = [] {
+  const char* e = std::getenv("MHDG_PROGRESS");
+  return e ? std::max(0, std::atoi(e)) : 0;
+}();
 
 // Device vectors of one solve, carved from the caller's solve workspace.
 struct Gm {
@@ -474,6 +484,10 @@ mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, double bref, double* x, 
       g[j + 1] = -sn[j] * g[j];
       g[j] = cs[j] * g[j];
       rel = std::fabs(g[j + 1]) / bref;
+      if (g_progress && iters % g_progress == 0) {
+        std::fprintf(stderr, "[mhdg] gmres iteration %d relative residual %.3e\n", iters, rel);
+        std::fflush(stderr);
+      }
       if (rel <= rtol || hn == 0.0) { ++j; break; }
     }
     for (int i = j - 1; i >= 0; --i) {
@@ -701,6 +715,13 @@ mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t 
   for (int64_t e = 0; e < n_macro; ++e) M->order[e] = (int32_t)e;
   std::stable_sort(M->order.begin(), M->order.end(),
                    [&](int32_t a, int32_t b) { return M->macros[a].N > M->macros[b].N; });
+  for (int64_t i = 0; i < n_macro;) {
+    const int N = M->macros[M->order[i]].N;
+    int64_t j = i;
+    while (j < n_macro && M->macros[M->order[j]].N == N) ++j;
+    M->classes.push_back({N, M->macros[M->order[i]].P, i, j - i});
+    i = j;
+  }
   int64_t fo = 0;
   for (int64_t e = 0; e < n_macro; ++e) {
     MacroInfo& mi = M->macros[e];
@@ -844,6 +865,8 @@ mhdg_status mhdg_factor_local(mhdg_mesh* M, const double* kappa, double beta_x, 
                               hipMemcpyHostToDevice, s));
   HIP_TRY(M, hipMemcpyAsync(w + L.tmpl, M->tmpl.data(), M->tmpl.size() * sizeof(double),
                             hipMemcpyHostToDevice, s));
+  HIP_TRY(M, hipMemcpyAsync(w + L.order, M->order.data(), M->order.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
   // the macro order lives after the permutation vector region: reuse status region size n_macro
   MacroInfo* info = (MacroInfo*)(w + L.meta);
   HIP_TRY(M, launch_set_kappa(info, kappa, M->n_macro, s));
@@ -854,8 +877,9 @@ mhdg_status mhdg_factor_local(mhdg_mesh* M, const double* kappa, double beta_x, 
   }
   {
     ProfScope ps(M, 1, s);
-    HIP_TRY(M, launch_lu(w + L.factors, precision, info, nullptr, M->n_macro, M->max_N,
-                         (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+    HIP_TRY(M, launch_lu(w + L.factors, precision, info, (const int32_t*)(w + L.order),
+                         M->classes.data(), (int)M->classes.size(), (int32_t*)(w + L.perm),
+                         (int32_t*)(w + L.status), s));
   }
   std::vector<int32_t> st(M->n_macro);
   HIP_TRY(M, hipMemcpyAsync(st.data(), w + L.status, st.size() * sizeof(int32_t),
@@ -888,7 +912,8 @@ static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const 
   char* w = M->ws;
   ProfScope ps(M, mode == MODE_APPLY ? 2 : 4, s);
   HIP_TRY(M, launch_macro_solve(mode, transpose, w + L.factors, M->precision,
-                                (const MacroInfo*)(w + L.meta), nullptr, M->n_macro, M->max_N,
+                                (const MacroInfo*)(w + L.meta), (const int32_t*)(w + L.order),
+                                M->classes.data(), (int)M->classes.size(),
                                 (const int32_t*)(w + L.perm), (const double*)(w + L.tmpl), M->T,
                                 M->bx, M->by, M->tau, lam, xin, yout, (double*)(w + L.slots), s));
   return MHDG_OK;
@@ -1086,8 +1111,8 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
     HIP_TRY(M, hipMemsetAsync(G.U, 0, nl * sizeof(double), s));
     if (!o->zero_guess) {
       // start U from the low-precision local solve for the given lam
-      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, nullptr,
-                                    M->n_macro, M->max_N, (const int32_t*)(fw + L.perm), tm, M->T,
+      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
+                                    M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
                                     M->bx, M->by, M->tau, lam, (const double*)(fw + L.R), G.U,
                                     (double*)(fw + L.slots), s));
     }
@@ -1103,8 +1128,8 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       HIP_TRY(M, launch_face_combine(FACE_RESID, faces_d, M->n_int, tm, M->T, M->tau, lam,
                                      (const double*)(fw + L.slots), G.cl, s));      // C U + D lam
       // condensed right-hand side b = D^-1 (r_lam - sum C A~^-1 r_U)
-      HIP_TRY(M, launch_macro_solve(MODE_RHS, 0, fw + L.factors, M->precision, info_d, nullptr,
-                                    M->n_macro, M->max_N, (const int32_t*)(fw + L.perm), tm, M->T,
+      HIP_TRY(M, launch_macro_solve(MODE_RHS, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
+                                    M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
                                     M->bx, M->by, M->tau, nullptr, rU, nullptr,
                                     (double*)(fw + L.slots), s));
       ++inf.n_applies;
@@ -1133,8 +1158,8 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
         return st;
       it_total += it;
       // dU = A~^-1 (r_U - B dlam); U += dU; lam += dlam
-      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, nullptr,
-                                    M->n_macro, M->max_N, (const int32_t*)(fw + L.perm), tm, M->T,
+      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
+                                    M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
                                     M->bx, M->by, M->tau, G.dl, rU, rU, (double*)(fw + L.slots), s));
       ++inf.n_applies;
       HIP_TRY(M, launch_axpby(1.0, rU, 1.0, G.U, nl, s));

@@ -73,7 +73,15 @@ struct Templates {
 
 // Device workspace layout for factor_local / apply / rhs / recover.
 struct FactorLayout {
-  size_t meta, faces, bfaces, tmpl, perm, status, R, slots, lamD, work1, work2, factors, total;
+  size_t meta, faces, bfaces, tmpl, order, perm, status, R, slots, lamD, work1, work2, factors, total;
+};
+
+// Macros of one local size, contiguous in the processing order (largest first):
+// the heavy per-macro kernels are launched once per class with a register and
+// thread configuration sized for that class.
+struct SizeClass {
+  int N, P;
+  int64_t start, count;
 };
 
 enum SolveMode { MODE_APPLY = 0, MODE_RHS = 1, MODE_RECOVER = 2, MODE_LOCAL = 3 };
@@ -99,7 +107,8 @@ hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, cons
                            int64_t n, const double* tmpl, const Templates& T, double bx, double by,
                            double tau, hipStream_t s);
 hipError_t launch_lu(void* fac, int precision, const MacroInfo* info, const int32_t* order,
-                     int64_t n, int max_N, int32_t* perm, int32_t* status, hipStream_t s);
+                     const SizeClass* classes, int n_classes, int32_t* perm, int32_t* status,
+                     hipStream_t s);
 hipError_t launch_dirichlet(const BndFaceInfo* bf, int64_t nbf, const double* tmpl,
                             const Templates& T, const double* g, double* lamD, hipStream_t s);
 hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
@@ -107,10 +116,11 @@ hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo*
                             const double* lamD, double bx, double by, double tau, double* R,
                             hipStream_t s);
 hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int precision,
-                              const MacroInfo* info, const int32_t* order, int64_t n, int max_N,
-                              const int32_t* perm, const double* tmpl, const Templates& T,
-                              double bx, double by, double tau, const double* lam,
-                              const double* xin, double* yout, double* slots, hipStream_t s);
+                              const MacroInfo* info, const int32_t* order,
+                              const SizeClass* classes, int n_classes, const int32_t* perm,
+                              const double* tmpl, const Templates& T, double bx, double by,
+                              double tau, const double* lam, const double* xin, double* yout,
+                              double* slots, hipStream_t s);
 hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const double* tmpl,
                                const Templates& T, double tau, const double* lam,
                                const double* slots, double* out, hipStream_t s);

@@ -158,12 +158,13 @@ template <> struct Mfma<float> {
 // perm[i] receives the original row of factor row i; status = first zero
 // pivot column + 1, or 0.  On exit L (unit lower) and U are stored
 // column-major in the block: element (i, j) at j * N + i.
-template <typename T, int NT, int RPT>
+template <typename T, int NT, int RPT, int NB>
 __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restrict__ info,
+                                                const int32_t* __restrict__ order, int64_t base,
                                                 int32_t* perm_all, int32_t* status) {
-  constexpr int NB = 16;
   constexpr int NW = NT / 64;
-  const MacroInfo& mi = info[blockIdx.x];
+  const int e = order[base + blockIdx.x];
+  const MacroInfo& mi = info[e];
   const int N = mi.N;
   T* A = fac + mi.fac_off;
   int32_t* perm = perm_all + mi.loc_off;
@@ -322,18 +323,18 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
       const int li = lane & 15, lk = lane >> 4;
       for (int rt = wid; rt < nt; rt += NW) {
         const int r0 = base + 16 * rt;
-        T a[4];
+        T a[NB / 4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < NB / 4; ++s) {
           const int k = 4 * s + lk, row = r0 + li;
           a[s] = (row < N && k < nb) ? -A[size_t(row) * N + k0 + k] : T(0);
         }
         for (int ct = 0; ct < nt; ++ct) {
           const int c0 = base + 16 * ct;
           const int colc = c0 + li;
-          T b[4];
+          T b[NB / 4];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
+          for (int s = 0; s < NB / 4; ++s) {
             const int k = 4 * s + lk;
             b[s] = (k < nb && colc < N) ? A[size_t(k0 + k) * N + colc] : T(0);
           }
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
             acc[v] = (row < N && colc < N) ? A[size_t(row) * N + colc] : T(0);
           }
 #pragma unroll
-          for (int s = 0; s < 4; ++s) acc = Mfma<T>::run(a[s], b[s], acc);
+          for (int s = 0; s < NB / 4; ++s) acc = Mfma<T>::run(a[s], b[s], acc);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = r0 + Mfma<T>::drow(lk, v);
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
         __syncthreads();
       }
   }
-  if (tid == 0) status[blockIdx.x] = s_status;
+  if (tid == 0) status[e] = s_status;
 }
 
 // ------------------------------------------------------------------ step 4
@@ -816,23 +817,30 @@ hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, cons
 }
 
 template <typename T>
-static hipError_t lu_dispatch(T* fac, const MacroInfo* info, int64_t n, int maxN, int32_t* perm,
-                              int32_t* status, hipStream_t s) {
-  if (maxN <= 256)
-    hipLaunchKernelGGL((lu_kernel<T, 256, 1>), dim3((unsigned)n), dim3(256), 0, s, fac, info, perm, status);
-  else if (maxN <= 1024)
-    hipLaunchKernelGGL((lu_kernel<T, 256, 4>), dim3((unsigned)n), dim3(256), 0, s, fac, info, perm, status);
-  else if (maxN <= 4096)
-    hipLaunchKernelGGL((lu_kernel<T, 1024, 4>), dim3((unsigned)n), dim3(1024), 0, s, fac, info, perm, status);
+static hipError_t lu_class(T* fac, const MacroInfo* info, const int32_t* order, const SizeClass& c,
+                           int32_t* perm, int32_t* status, hipStream_t s) {
+  const dim3 g((unsigned)c.count);
+  if (c.N <= 256)
+    hipLaunchKernelGGL((lu_kernel<T, 256, 1, 16>), g, dim3(256), 0, s, fac, info, order, c.start, perm, status);
+  else if (c.N <= 1024)
+    hipLaunchKernelGGL((lu_kernel<T, 256, 4, 16>), g, dim3(256), 0, s, fac, info, order, c.start, perm, status);
+  else if (c.N <= 4096)
+    hipLaunchKernelGGL((lu_kernel<T, 1024, 4, 8>), g, dim3(1024), 0, s, fac, info, order, c.start, perm, status);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_lu(void* fac, int precision, const MacroInfo* info, const int32_t*, int64_t n,
-                     int maxN, int32_t* perm, int32_t* status, hipStream_t s) {
-  if (precision == 1) return lu_dispatch((float*)fac, info, n, maxN, perm, status, s);
-  return lu_dispatch((double*)fac, info, n, maxN, perm, status, s);
+hipError_t launch_lu(void* fac, int precision, const MacroInfo* info, const int32_t* order,
+                     const SizeClass* classes, int n_classes, int32_t* perm, int32_t* status,
+                     hipStream_t s) {
+  for (int c = 0; c < n_classes; ++c) {
+    hipError_t e = precision == 1
+                       ? lu_class((float*)fac, info, order, classes[c], perm, status, s)
+                       : lu_class((double*)fac, info, order, classes[c], perm, status, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_dirichlet(const BndFaceInfo* bf, int64_t nbf, const double* tmpl,
@@ -863,7 +871,8 @@ hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo*
 
 // instantiated in solve_nq_*.hip
 #define MS_DECL(T_, Q_)                                                                        \
-  extern template void macro_solve_launch<T_, Q_>(int, const void*, const MacroInfo*, int64_t,  \
+  extern template void macro_solve_launch<T_, Q_>(int, const void*, const MacroInfo*,          \
+                                                  const int32_t*, int64_t, int64_t,             \
                                                   size_t, const int32_t*, const double*,        \
                                                   const Templates&, double, double, double,     \
                                                   const double*, const double*, double*,        \
@@ -874,7 +883,8 @@ MS_DECL2(58)
 #undef MS_DECL2
 #undef MS_DECL
 #define MST_DECL(Q_)                                                                           \
-  extern template void macro_solve_t_launch<Q_>(int, const void*, const MacroInfo*, int64_t,    \
+  extern template void macro_solve_t_launch<Q_>(int, const void*, const MacroInfo*,            \
+                                                const int32_t*, int64_t, int64_t,               \
                                                 size_t, const int32_t*, const double*,          \
                                                 const Templates&, double, double, double,       \
                                                 const double*, const double*, double*, double*, \
@@ -883,59 +893,87 @@ MST_DECL(1) MST_DECL(2) MST_DECL(3) MST_DECL(5) MST_DECL(8) MST_DECL(16) MST_DEC
 #undef MST_DECL
 
 static hipError_t macro_solve_t_dispatch(int nq, int mode, const void* fac, const MacroInfo* info,
-                                         int64_t n, size_t lds, const int32_t* perm,
-                                         const double* tmpl, const Templates& Tp, double bx,
-                                         double by, double tau, const double* mu, const double* xin,
-                                         double* yout, double* slots, hipStream_t s) {
-#define MST_CASE(Q_)                                                                           \
-  if (nq <= Q_) {                                                                              \
-    macro_solve_t_launch<Q_>(mode, fac, info, n, lds, perm, tmpl, Tp, bx, by, tau, mu, xin,    \
-                             yout, slots, s);                                                  \
-    return hipGetLastError();                                                                  \
+                                         const int32_t* order, int64_t base, int64_t n, size_t lds,
+                                         const int32_t* perm, const double* tmpl,
+                                         const Templates& Tp, double bx, double by, double tau,
+                                         const double* mu, const double* xin, double* yout,
+                                         double* slots, hipStream_t s) {
+#define MST_CASE(Q_)                                                                          \
+  if (nq <= Q_) {                                                                             \
+    macro_solve_t_launch<Q_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, bx, by,    \
+                             tau, mu, xin, yout, slots, s);                                   \
+    return hipGetLastError();                                                                 \
   }
   MST_CASE(1) MST_CASE(2) MST_CASE(3) MST_CASE(5) MST_CASE(8) MST_CASE(16) MST_CASE(27) MST_CASE(58)
 #undef MST_CASE
   return hipErrorInvalidValue;
 }
 
+#define MSW_DECL(T_, Q_)                                                                      \
+  extern template void macro_solve_mw_launch<T_, Q_>(int, const void*, const MacroInfo*,      \
+                                                     const int32_t*, int64_t, int64_t, size_t,\
+                                                     const int32_t*, const double*,           \
+                                                     const Templates&, double, double, double,\
+                                                     const double*, const double*, double*,   \
+                                                     double*, hipStream_t);
+MSW_DECL(double, 27) MSW_DECL(float, 27) MSW_DECL(double, 58) MSW_DECL(float, 58)
+#undef MSW_DECL
+
 template <typename T>
 static hipError_t macro_solve_dispatch(int nq, int mode, const void* fac, const MacroInfo* info,
-                                       int64_t n, size_t lds, const int32_t* perm,
-                                       const double* tmpl, const Templates& Tp, double bx,
-                                       double by, double tau, const double* lam,
-                                       const double* xin, double* yout, double* slots,
-                                       hipStream_t s) {
-#define MS_CASE(Q_)                                                                         \
-  if (nq <= Q_) {                                                                           \
-    macro_solve_launch<T, Q_>(mode, fac, info, n, lds, perm, tmpl, Tp, bx, by, tau, lam, xin, \
-                              yout, slots, s);                                              \
-    return hipGetLastError();                                                               \
+                                       const int32_t* order, int64_t base, int64_t n, size_t lds,
+                                       const int32_t* perm, const double* tmpl,
+                                       const Templates& Tp, double bx, double by, double tau,
+                                       const double* lam, const double* xin, double* yout,
+                                       double* slots, hipStream_t s) {
+#define MS_CASE(Q_)                                                                           \
+  if (nq <= Q_) {                                                                             \
+    macro_solve_launch<T, Q_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, bx, by,   \
+                              tau, lam, xin, yout, slots, s);                                 \
+    return hipGetLastError();                                                                 \
   }
-  MS_CASE(1) MS_CASE(2) MS_CASE(3) MS_CASE(5) MS_CASE(8) MS_CASE(16) MS_CASE(27) MS_CASE(58)
+  MS_CASE(1) MS_CASE(2) MS_CASE(3) MS_CASE(5) MS_CASE(8) MS_CASE(16)
 #undef MS_CASE
+  // large local sizes: four wavefronts per macro
+  if (nq <= 27) {
+    macro_solve_mw_launch<T, 27>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, bx, by, tau,
+                                 lam, xin, yout, slots, s);
+    return hipGetLastError();
+  }
+  if (nq <= 58) {
+    macro_solve_mw_launch<T, 58>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, bx, by, tau,
+                                 lam, xin, yout, slots, s);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 
+// One launch per size class, each with the register-block count of its
+// local size (NQ = ceil(N/64)) and LDS for its boundary vectors.
 hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int precision,
-                              const MacroInfo* info, const int32_t*, int64_t n, int max_N,
-                              const int32_t* perm, const double* tmpl, const Templates& T,
-                              double bx, double by, double tau, const double* lam,
-                              const double* xin, double* yout, double* slots, hipStream_t s) {
-  int maxP = 0;
-  for (int r = 0; r <= kMaxLevel; ++r)
-    if (T.lev[r].present && T.lev[r].P > maxP) maxP = T.lev[r].P;
-  const size_t lds = size_t(18) * maxP * sizeof(double);
-  const int nq = (max_N + 63) / 64;
-  if (transpose) {
-    if (precision != 0) return hipErrorInvalidValue;
-    return macro_solve_t_dispatch(nq, mode, fac, info, n, lds, perm, tmpl, T, bx, by, tau, lam, xin,
-                                  yout, slots, s);
+                              const MacroInfo* info, const int32_t* order,
+                              const SizeClass* classes, int n_classes, const int32_t* perm,
+                              const double* tmpl, const Templates& T, double bx, double by,
+                              double tau, const double* lam, const double* xin, double* yout,
+                              double* slots, hipStream_t s) {
+  if (transpose && precision != 0) return hipErrorInvalidValue;
+  for (int c = 0; c < n_classes; ++c) {
+    const SizeClass& sc = classes[c];
+    const size_t lds = size_t(18) * sc.P * sizeof(double);
+    const int nq = (sc.N + 63) / 64;
+    hipError_t e;
+    if (transpose)
+      e = macro_solve_t_dispatch(nq, mode, fac, info, order, sc.start, sc.count, lds, perm, tmpl, T,
+                                 bx, by, tau, lam, xin, yout, slots, s);
+    else if (precision == 1)
+      e = macro_solve_dispatch<float>(nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
+                                      tmpl, T, bx, by, tau, lam, xin, yout, slots, s);
+    else
+      e = macro_solve_dispatch<double>(nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
+                                       tmpl, T, bx, by, tau, lam, xin, yout, slots, s);
+    if (e != hipSuccess) return e;
   }
-  if (precision == 1)
-    return macro_solve_dispatch<float>(nq, mode, fac, info, n, lds, perm, tmpl, T, bx, by, tau,
-                                       lam, xin, yout, slots, s);
-  return macro_solve_dispatch<double>(nq, mode, fac, info, n, lds, perm, tmpl, T, bx, by, tau,
-                                      lam, xin, yout, slots, s);
+  return hipSuccess;
 }
 
 hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const double* tmpl,

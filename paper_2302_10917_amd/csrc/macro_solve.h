@@ -110,6 +110,7 @@ template <int NQ> struct SolveOccupancy { static constexpr int waves = NQ <= 16 
 template <typename T, int NQ>
 __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_kernel(int mode, const T* __restrict__ fac,
                                                          const MacroInfo* __restrict__ info,
+                                                         const int32_t* __restrict__ order, int64_t base,
                                                          const int32_t* __restrict__ perm_all,
                                                          const double* __restrict__ tm, Templates Tp,
                                                          double bx, double by, double tau,
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
                                                          const double* xin, double* yout,
                                                          double* __restrict__ slots) {
   extern __shared__ double sm[];
-  const MacroInfo& mi = info[blockIdx.x];
+  const MacroInfo& mi = info[order[base + blockIdx.x]];
   const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P, lane = threadIdx.x;
   double* xc = sm;             // compact boundary rows of the right-hand side
   double* zc = sm + 3 * NBD;   // compact boundary rows of the solution
@@ -237,6 +238,146 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
   }
 }
 
+// Per-macro solve for large local sizes: a workgroup of NW wavefronts per
+// macro, 64-row chunk qq owned by wavefront qq % NW (register slot qq / NW).
+// Each column's solved entry is computed by the owner of its chunk and
+// broadcast through a double-buffered LDS slot with one barrier per column;
+// every wavefront then streams its own chunks of that column, so NW times
+// more loads are in flight per macro than with one wavefront.
+template <typename T, int NQ, int NW>
+__global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
+    int mode, const T* __restrict__ fac, const MacroInfo* __restrict__ info,
+    const int32_t* __restrict__ order, int64_t base, const int32_t* __restrict__ perm_all,
+    const double* __restrict__ tm, Templates Tp, double bx, double by, double tau,
+    const double* __restrict__ lam, const double* xin, double* yout, double* __restrict__ slots) {
+  constexpr int NL = (NQ + NW - 1) / NW;   // chunks per wavefront
+  extern __shared__ double sm[];
+  __shared__ double bc[2];
+  const MacroInfo& mi = info[order[base + blockIdx.x]];
+  const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double* xc = sm;
+  double* zc = sm + 3 * NBD;
+  const int32_t* bidx = ints_(tm, Tp.lev[mi.level].bnd_index);
+  const T* A = fac + mi.fac_off;
+  const int32_t* perm = perm_all + mi.loc_off;
+  const bool with_B = mode == MODE_APPLY || mode == MODE_RECOVER;
+  if (with_B) {
+    for (int i = threadIdx.x; i < 3 * NBD; i += blockDim.x) xc[i] = 0.0;
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+      if (mi.tr_off[k] >= 0)
+        edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], mode == MODE_APPLY ? 1.0 : -1.0, bx, by, tau, xc);
+      __syncthreads();
+    }
+  }
+  double y[NL];
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    const int i = lane + 64 * (wv + NW * t);
+    double v = 0.0;
+    if (i < N) {
+      const int r = perm[i];
+      if (mode != MODE_APPLY) v = xin[mi.loc_off + r];
+      if (with_B) {
+        const int f = r / Q;
+        const int b = bidx[r - f * Q];
+        if (b >= 0) v += xc[f * NBD + b];
+      }
+    }
+    y[t] = v;
+  }
+  const int nq = (N + 63) / 64;
+  // ---- forward substitution (unit lower factor)
+  for (int j = 0; j < N; ++j) {
+    const int q = j >> 6, jj = j & 63;
+    if (wv == q % NW) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < NL; ++t)
+        if (t == q / NW) v = readlane_d(y[t], jj);
+      if (lane == 0) bc[j & 1] = v;
+    }
+    __syncthreads();
+    const double yj = bc[j & 1];
+    const T* col = A + size_t(j) * N;
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int qq = wv + NW * t;
+      if (qq >= q && qq < nq) {
+        const int r = lane + 64 * qq;
+        int rr = r;
+        if (qq == q) rr = r > j ? r : j + 1;
+        rr = rr < N ? rr : N - 1;
+        const double a = (double)col[rr];
+        y[t] -= ((r > j && r < N) ? a : 0.0) * yj;
+      }
+    }
+  }
+  // ---- backward substitution (upper factor)
+  for (int j = N - 1; j >= 0; --j) {
+    const int q = j >> 6, jj = j & 63;
+    const T* col = A + size_t(j) * N;
+    if (wv == q % NW) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < NL; ++t)
+        if (t == q / NW) v = readlane_d(y[t], jj);
+      v /= (double)col[j];
+#pragma unroll
+      for (int t = 0; t < NL; ++t)
+        if (t == q / NW && lane == jj) y[t] = v;
+      if (lane == 0) bc[j & 1] = v;
+    }
+    __syncthreads();
+    const double zj = bc[j & 1];
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int qq = wv + NW * t;
+      if (qq <= q) {
+        const int r = lane + 64 * qq;
+        int rr = r;
+        if (qq == q) rr = r < j ? r : (j > 0 ? j - 1 : 0);
+        const double a = (double)col[rr];
+        y[t] -= (r < j ? a : 0.0) * zj;
+      }
+    }
+  }
+  // ---- outputs
+  if (mode == MODE_RECOVER || mode == MODE_LOCAL) {
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int i = lane + 64 * (wv + NW * t);
+      if (i < N) yout[mi.loc_off + i] = y[t];
+    }
+  }
+  if (mode != MODE_LOCAL) {
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int i = lane + 64 * (wv + NW * t);
+      if (i < N) {
+        const int f = i / Q;
+        const int b = bidx[i - f * Q];
+        if (b >= 0) zc[f * NBD + b] = y[t];
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < 3; ++k)
+      if (mi.tr_off[k] >= 0) edge_C(mi, k, tm, Tp, zc, tau, slots + mi.slot_off[k]);
+  }
+}
+
+template <typename T, int NQ>
+void macro_solve_mw_launch(int mode, const void* fac, const MacroInfo* info, const int32_t* order,
+                           int64_t base, int64_t n, size_t lds, const int32_t* perm,
+                           const double* tmpl, const Templates& Tp, double bx, double by,
+                           double tau, const double* lam, const double* xin, double* yout,
+                           double* slots, hipStream_t s) {
+  hipLaunchKernelGGL((macro_solve_mw_kernel<T, NQ, 4>), dim3((unsigned)n), dim3(256), lds, s, mode,
+                     (const T*)fac, info, order, base, perm, tmpl, Tp, bx, by, tau, lam, xin, yout,
+                     slots);
+}
+
 // Transposed per-macro solve y = A^-T x (adjoint), one wavefront per macro.
 // With P A = L U held column-major: U^T w = x uses column i of U for row i
 // of the forward sweep, L^T v = w column i of L for the backward sweep (each
@@ -246,11 +387,12 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
 template <typename T, int NQ>
 __global__ __launch_bounds__(64) void macro_solve_t_kernel(
     int mode, const T* __restrict__ fac, const MacroInfo* __restrict__ info,
+    const int32_t* __restrict__ order, int64_t base,
     const int32_t* __restrict__ perm_all, const double* __restrict__ tm, Templates Tp, double bx,
     double by, double tau, const double* __restrict__ mu, const double* xin, double* yout,
     double* __restrict__ slots) {
   extern __shared__ double sm[];
-  const MacroInfo& mi = info[blockIdx.x];
+  const MacroInfo& mi = info[order[base + blockIdx.x]];
   const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P, lane = threadIdx.x;
   double* xc = sm;
   double* zc = sm + 3 * NBD;
@@ -347,22 +489,25 @@ __global__ __launch_bounds__(64) void macro_solve_t_kernel(
 }
 
 template <int NQ>
-void macro_solve_t_launch(int mode, const void* fac, const MacroInfo* info, int64_t n, size_t lds,
-                          const int32_t* perm, const double* tmpl, const Templates& Tp, double bx,
-                          double by, double tau, const double* mu, const double* xin, double* yout,
-                          double* slots, hipStream_t s) {
+void macro_solve_t_launch(int mode, const void* fac, const MacroInfo* info, const int32_t* order,
+                          int64_t base, int64_t n, size_t lds, const int32_t* perm,
+                          const double* tmpl, const Templates& Tp, double bx, double by, double tau,
+                          const double* mu, const double* xin, double* yout, double* slots,
+                          hipStream_t s) {
   hipLaunchKernelGGL((macro_solve_t_kernel<double, NQ>), dim3((unsigned)n), dim3(64), lds, s, mode,
-                     (const double*)fac, info, perm, tmpl, Tp, bx, by, tau, mu, xin, yout, slots);
+                     (const double*)fac, info, order, base, perm, tmpl, Tp, bx, by, tau, mu, xin,
+                     yout, slots);
 }
 
 template <typename T, int NQ>
-void macro_solve_launch(int mode, const void* fac, const MacroInfo* info, int64_t n,
-                               size_t lds, const int32_t* perm, const double* tmpl,
-                               const Templates& Tp, double bx, double by, double tau,
-                               const double* lam, const double* xin, double* yout, double* slots,
-                               hipStream_t s) {
+void macro_solve_launch(int mode, const void* fac, const MacroInfo* info, const int32_t* order,
+                        int64_t base, int64_t n, size_t lds, const int32_t* perm,
+                        const double* tmpl, const Templates& Tp, double bx, double by, double tau,
+                        const double* lam, const double* xin, double* yout, double* slots,
+                        hipStream_t s) {
   hipLaunchKernelGGL((macro_solve_kernel<T, NQ>), dim3((unsigned)n), dim3(64), lds, s, mode,
-                     (const T*)fac, info, perm, tmpl, Tp, bx, by, tau, lam, xin, yout, slots);
+                     (const T*)fac, info, order, base, perm, tmpl, Tp, bx, by, tau, lam, xin, yout,
+                     slots);
 }
 
 }  // namespace mhdg

@@ -49,6 +49,9 @@ CASES = {
     "tiles_r3_p3": (2, 0.0, 3, 3, 1e-2, (1.0, 0.5)),
     "p1_r0": (3, 0.0, 0, 1, 1.0, (0.3, 0.2)),
     "p4_r1": (2, 0.05, 1, 4, 0.5, (1.0, -1.0)),
+    # large local sizes: N_K = 1683 and 3675 (multi-wavefront solves, 8-wide LU panels)
+    "two_macro_r3_p4": (1, 0.0, 3, 4, 0.3, (1.0, 0.5)),
+    "two_macro_r4_p3": (1, 0.0, 4, 3, 0.3, (0.5, 1.0)),
 }
 
 
