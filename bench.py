@@ -51,6 +51,13 @@ WORKLOADS = {
     # a random direction, |a| in [0.5, 2], seed 33), u = exp(x) sin(2 pi y) data
     "mixed_r1to4_8192macro_p3_inst0": dict(n=64, r="mixed", p=3, kappa=None, beta=None,
                                            sol="exp_sin", precision="fp64", instance=0),
+    # batching configuration, all 64 coefficient instances in one handle: one 8 x 8-square
+    # block of the mixed-level mesh (128 macros, r from {1,2,3,4}, seed 3) per instance, so
+    # the 64 instances hold the same 219 GB of FP64 factors as one instance of the
+    # 8192-macro mesh; every launch covers all instances, GMRES runs per instance in
+    # lockstep with converged instances masked out of later applies
+    "batched_64inst_128macro_r1to4_p3": dict(n=8, r="mixed", p=3, kappa=None, beta=None,
+                                             sol="exp_sin", precision="fp64", n_inst=64),
     "adjoint_32768macro_r2_p2": dict(n=128, r=2, p=2, kappa=None, beta=(1.0, 1.0), sol="sin_sin",
                                      precision="fp64", form="adjoint", restart=8000, rtol=1e-9),
 }
@@ -143,6 +150,10 @@ def main():
                     help="after the timed steps, solve again with FP64 factors and report the "
                          "relative differences of lambda, q and u")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--compare-sequential", type=int, default=0, metavar="K",
+                    help="batched workload: after the timed steps, solve the first K instances "
+                         "one at a time with single-instance handles (the plain form) and "
+                         "report their time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=20000,
                     help="GMRES iteration cap (a short cap is for counter runs only)")
@@ -166,35 +177,55 @@ def main():
     if w.get("form") == "adjoint":
         return bench_adjoint(args, w)
     xy, tri = inputs.structured_mesh(w["n"])
+    n_inst = w.get("n_inst", 1)
     if w["r"] == "mixed":
         w["r"] = inputs.random_levels(len(tri), (1, 2, 3, 4), seed=3)
         kap_i, beta_i = inputs.coefficient_instances(64, seed=33)
-        w["kappa"] = float(kap_i[w["instance"]])
-        w["beta"] = tuple(float(x) for x in beta_i[w["instance"]])
-    ex = getattr(inputs, w["sol"])(w["kappa"], w["beta"])
+        if n_inst > 1:
+            w["kappa"], w["beta"] = kap_i[:n_inst], beta_i[:n_inst]
+        else:
+            w["kappa"] = float(kap_i[w["instance"]])
+            w["beta"] = tuple(float(x) for x in beta_i[w["instance"]])
     m = mhdg.MacroMesh(xy, tri, w["r"], w["p"])
+    one = m.sizes
+    if n_inst > 1:
+        m.set_instances(n_inst)
     s = m.sizes
     node, bnd = m.sample_points()
     dev = "cuda"
-    f = torch.as_tensor(ex.f(node[:, 0], node[:, 1]), device=dev)
-    g = torch.as_tensor(ex.u(bnd[:, 0], bnd[:, 1]), device=dev)
-    kappa = torch.full((s.n_macro,), w["kappa"], dtype=torch.float64, device=dev)
+    kap_inst = np.atleast_1d(np.asarray(w["kappa"], dtype=np.float64))
+    beta_inst = np.asarray(w["beta"], dtype=np.float64).reshape(-1, 2)
+    fh, gh = np.empty(s.n_nodes), np.empty(s.n_bnd_points)
+    for i in range(n_inst):
+        ex = getattr(inputs, w["sol"])(float(kap_inst[i]), beta_inst[i])
+        a, b_ = i * one.n_nodes, (i + 1) * one.n_nodes
+        fh[a:b_] = ex.f(node[a:b_, 0], node[a:b_, 1])
+        a, b_ = i * one.n_bnd_points, (i + 1) * one.n_bnd_points
+        gh[a:b_] = ex.u(bnd[a:b_, 0], bnd[a:b_, 1])
+    f = torch.as_tensor(fh, device=dev)
+    g = torch.as_tensor(gh, device=dev)
+    kappa = torch.as_tensor(np.repeat(kap_inst, one.n_macro), device=dev)
+    beta_arg = beta_inst if n_inst > 1 else tuple(beta_inst[0])
     lam = torch.zeros(s.n_trace, dtype=torch.float64, device=dev)
     qu = torch.empty(s.n_local, dtype=torch.float64, device=dev)
     print(f"[bench] {args.workload}: {s.n_macro} macros, N_K={s.max_local}, "
-          f"n_trace={s.n_trace}", file=sys.stderr, flush=True)
+          f"n_trace={s.n_trace}, {n_inst} instance(s), factors "
+          f"{m.query().factor_ws_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
 
     infos = []
     Q = s.n_nodes // s.n_macro
 
     prec = mhdg.MHDG_FP32 if w["precision"] == "fp32" else mhdg.MHDG_FP64
 
+    inst_infos = []
+
     def step():
-        m.factor_local(kappa, w["beta"], 1.0, precision=prec)
+        m.factor_local(kappa, beta_arg, 1.0, precision=prec)
         info = m.solve(f, g, lam, rtol=args.rtol, restart=args.restart, max_iter=args.max_iter,
                        check=args.max_iter >= 20000, inner_rtol=args.inner_rtol)
         m.recover_local(lam, qu)
         infos.append(info.as_dict())
+        inst_infos.append(m.last_solve_infos)
 
     for i in range(args.warmup):
         step()
@@ -202,19 +233,24 @@ def main():
         print(f"[bench] warmup {i}: {infos[-1]['iterations']} iterations, "
               f"{infos[-1]['t_gmres_ms']:.0f} ms GMRES", file=sys.stderr, flush=True)
     infos.clear()
+    inst_infos.clear()
     m.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
-        print(f"[bench] step {i}: {infos[-1]['iterations']} iterations, rel res "
-              f"{infos[-1]['rel_res_prec']:.2e} (true {infos[-1]['rel_res_true']:.2e})",
+        its = [x["iterations"] for x in inst_infos[-1]]
+        print(f"[bench] step {i}: {min(its)}..{max(its)} iterations, worst rel res "
+              f"{max(x['rel_res_prec'] for x in inst_infos[-1]):.2e} (true "
+              f"{max(x['rel_res_true'] for x in inst_infos[-1]):.2e})",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = m.profile(False)
     elapsed = t1 - t0
-    applies = sum(i["n_applies"] for i in infos)
+    # applies counted per instance (a batched launch is one apply for every
+    # instance that takes part in it)
+    applies = sum(x["n_applies"] for step_infos in inst_infos for x in step_infos)
     ms_per_step = 1e3 * elapsed / args.steps
 
     print("[bench] timed steps done; operator-only throughput", file=sys.stderr, flush=True)
@@ -247,6 +283,37 @@ def main():
     stream_gbs = 5 * buf.numel() * 8 / (time.perf_counter() - tr) / 1e9
     del buf
 
+    seq = None
+    if args.compare_sequential and n_inst > 1:
+        kk = min(args.compare_sequential, n_inst)
+        print(f"[bench] plain form: {kk} instances solved one at a time", file=sys.stderr,
+              flush=True)
+        m1 = mhdg.MacroMesh(xy, tri, w["r"], w["p"])
+        lam1 = torch.zeros(one.n_trace, dtype=torch.float64, device=dev)
+        qu1 = torch.empty(one.n_local, dtype=torch.float64, device=dev)
+        seq_its, seq_applies, diffs = [], 0, []
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for i in range(kk):
+            m1.factor_local(kappa[i * one.n_macro:(i + 1) * one.n_macro], tuple(beta_inst[i]), 1.0)
+            inf1 = m1.solve(f[i * one.n_nodes:(i + 1) * one.n_nodes],
+                            g[i * one.n_bnd_points:(i + 1) * one.n_bnd_points], lam1,
+                            rtol=args.rtol, restart=args.restart, max_iter=args.max_iter)
+            m1.recover_local(lam1, qu1)
+            seq_its.append(inf1.iterations)
+            seq_applies += inf1.n_applies
+            ref = lam[i * one.n_trace:(i + 1) * one.n_trace]
+            diffs.append(float(torch.linalg.norm(lam1 - ref) / torch.linalg.norm(ref)))
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - ts
+        del m1
+        seq = {"instances": kk, "seconds": t_seq, "seconds_per_instance": t_seq / kk,
+               "applies_per_s": seq_applies / t_seq, "iterations": seq_its,
+               "max_rel_diff_lambda_vs_batched": max(diffs),
+               "batched_seconds_per_instance": elapsed / args.steps / n_inst,
+               "speedup_per_instance": (t_seq / kk) / (elapsed / args.steps / n_inst)}
+        print(f"[bench] plain form: {seq}", file=sys.stderr, flush=True)
+
     # discretisation error of the solution (sanity: the manufactured solution)
     if np.ndim(w["r"]) == 0:
         u_h = qu.view(s.n_macro, 3, Q)[:, 2, :].reshape(-1).cpu().numpy()
@@ -273,7 +340,7 @@ def main():
     ams = kt["apply_macro_solve"]
     avg_ms = ams["ms"] / max(ams["count"], 1)
     nbytes = apply_bytes(m, 4 if prec == mhdg.MHDG_FP32 else 8,
-                         None if np.ndim(w["r"]) == 0 else w["r"], w["p"])
+                         None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"])
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     lu = kt["lu"]
     result = {
@@ -289,12 +356,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == mhdg.MHDG_FP64 else "f32 factors, f64 refinement",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_macro": s.n_macro,
+        "config": {"workload": args.workload, "n_macro": s.n_macro, "n_instances": n_inst,
                    "r": w["r"] if np.ndim(w["r"]) == 0 else "U{1,2,3,4} seed 3", "p": w["p"],
-                   "N_K": s.max_local, "n_trace": s.n_trace, "kappa": w["kappa"],
-                   "beta": list(w["beta"]), "tau": 1.0, "rtol": args.rtol,
-                   "gmres_restart": args.restart,
-                   "form": "plain_fp64" if prec == mhdg.MHDG_FP64 else "fp32_factors_fp64_ir"},
+                   "N_K": s.max_local, "n_trace": s.n_trace,
+                   "kappa": w["kappa"] if n_inst == 1 else "10^U(-3,0) per instance, seed 33",
+                   "beta": list(w["beta"]) if n_inst == 1 else
+                   "|a| U(0.5,2), direction U[0,2pi) per instance, seed 33",
+                   "tau": 1.0, "rtol": args.rtol, "gmres_restart": args.restart,
+                   "form": ("batched_fp64" if n_inst > 1 else "plain_fp64")
+                   if prec == mhdg.MHDG_FP64 else "fp32_factors_fp64_ir"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": ("macro_solve_kernel<double>" if prec == mhdg.MHDG_FP64
@@ -302,12 +372,14 @@ def main():
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
                      "launches": ams["count"]},
         "time_to_solve_s": ms_per_step / 1e3,
-        "iterations": [i["iterations"] for i in infos],
+        "iterations": [i["iterations"] for i in infos] if n_inst == 1 else
+        [[x["iterations"] for x in si] for si in inst_infos],
+        "sequential_plain": seq,
         "outer_iterations": [i["outer_iterations"] for i in infos],
         "applies_per_solve": [i["n_applies"] for i in infos],
         "vs_fp64": cmp,
-        "rel_res_prec": [i["rel_res_prec"] for i in infos],
-        "rel_res_true": [i["rel_res_true"] for i in infos],
+        "rel_res_prec": [max(x["rel_res_prec"] for x in si) for si in inst_infos],
+        "rel_res_true": [max(x["rel_res_true"] for x in si) for si in inst_infos],
         "apply_only_per_s": apply_only,
         "stream_read_gbs": stream_gbs,
         "kernel_ms": {k: v["ms"] / max(args.steps, 1) for k, v in kt.items()},
@@ -316,7 +388,10 @@ def main():
         "u_max_err_vs_exact": u_err,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(xy, tri, w)
+        wc = dict(w)
+        if n_inst > 1:   # the oracle applies one instance's operator
+            wc["kappa"], wc["beta"] = float(kap_inst[0]), tuple(beta_inst[0])
+        result["cpu_baseline"] = cpu_baseline(xy, tri, wc)
     print(json.dumps(result), flush=True)
 
 

@@ -36,7 +36,12 @@
  *     segments of every boundary face (faces in sorted order, segments and
  *     points in increasing t): the Dirichlet trace is its L2 projection onto
  *     M(F) (section 2.3) by that quadrature;
- *   - local solutions U are returned macro-contiguous (n_local values).
+ *   - local solutions U are returned macro-contiguous (n_local values);
+ *   - coefficient instances (mhdg_set_instances): a handle may carry n_inst
+ *     copies of the mesh that differ only in kappa and a.  Every count in
+ *     mhdg_sizes is then the total over the copies, every vector argument
+ *     is instance-major (instance i's block starts at i * count / n_inst),
+ *     and each kernel launch covers all instances at once.
  *
  * Memory and ownership: the caller owns every pointer.  Device memory for
  * factors and scratch comes from caller workspaces sized by mhdg_query();
@@ -99,6 +104,7 @@ typedef struct {
   int64_t max_local;          /* max N_K                                       */
   size_t factor_ws_bytes;     /* workspace for factor_local at this precision  */
   size_t solve_ws_bytes;      /* workspace for solve at this restart length    */
+  int32_t n_instances;        /* coefficient instances (mhdg_set_instances)    */
 } mhdg_sizes;
 
 typedef struct {
@@ -120,7 +126,8 @@ typedef struct {
   double rel_res_true;        /* final ||f^ - S lam|| / ||f^|| (FP64 factors;
                                  -1 with reduced-precision factors)            */
   double t_rhs_ms, t_gmres_ms;
-  int32_t n_applies;          /* operator applies + per-macro solve passes     */
+  int32_t n_applies;          /* operator applies + per-macro solve passes this
+                                 instance took part in                         */
   int32_t outer_iterations;   /* refinement steps (reduced-precision factors)  */
 } mhdg_solve_info;
 
@@ -135,6 +142,17 @@ typedef struct {
 mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t n_macro,
                                   const int32_t* tri, const int32_t* level, int32_t uniform_level,
                                   int32_t p, mhdg_mesh** out);
+
+/* Batch n_inst coefficient instances (kappa, a) of the mesh in one handle
+ * (the many-coefficient workloads of the method's parameter studies, where
+ * every instance is the same discretisation with other data): the handle
+ * then describes n_inst disjoint copies of the mesh, instance-major, and
+ * apply/rhs/recover/solve process all of them in one launch per size class.
+ * GMRES keeps one Krylov space per instance and masks converged instances
+ * out of later applies.  Resets the factor state (call factor_local after).
+ * n_inst >= 1 with n_inst * n_macro <= 2^28 and n_inst * n_trace < 2^31.
+ * Errors: INVALID_ARG. */
+mhdg_status mhdg_set_instances(mhdg_mesh* mesh, int32_t n_inst);
 
 /* Sizes and workspace requirements for a precision and GMRES restart length. */
 mhdg_status mhdg_query(const mhdg_mesh* mesh, int32_t precision, int32_t restart, mhdg_sizes* out);
@@ -154,6 +172,14 @@ mhdg_status mhdg_sample_points(const mhdg_mesh* mesh, double* node_xy, double* b
 mhdg_status mhdg_factor_local(mhdg_mesh* mesh, const double* kappa, double beta_x, double beta_y,
                               double tau, int32_t precision, void* ws, size_t ws_bytes,
                               void* stream);
+
+/* factor_local with one advection vector per coefficient instance:
+ * kappa device f64[n_inst * n_macro_per_instance] (instance-major), beta
+ * host f64[n_inst][2].  mhdg_factor_local gives every instance the same a.
+ * Errors as mhdg_factor_local. */
+mhdg_status mhdg_factor_local_batched(mhdg_mesh* mesh, const double* kappa, const double* beta,
+                                      double tau, int32_t precision, void* ws, size_t ws_bytes,
+                                      void* stream);
 
 /* Copy macro e's assembled (flags=0) local matrix A_e, row-major N_e x N_e,
  * into dst (device f64).  Re-assembles it from the templates; no factor
@@ -188,8 +214,11 @@ mhdg_status mhdg_rhs(mhdg_mesh* mesh, const double* f_nodes, const double* g_bnd
  * FP64 residual is below rtol relative to its initial value.  lam: device
  * f64[n_trace] (initial guess unless opts->zero_guess, then the solution).
  * ws: device workspace of at least solve_ws_bytes (mhdg_query with the same
- * restart).  info (host) may be NULL.  Returns NOT_CONVERGED if max_iter
- * was reached (lam then holds the last iterate). */
+ * restart).  info: host array of n_inst entries (one per coefficient
+ * instance; iterations and residuals are per instance) or NULL.  With
+ * several instances the factors must be FP64 (STATE otherwise).  Returns
+ * NOT_CONVERGED if max_iter was reached before every instance converged
+ * (lam then holds the last iterates). */
 mhdg_status mhdg_solve(mhdg_mesh* mesh, const double* f_nodes, const double* g_bnd,
                        const mhdg_solve_opts* opts, double* lam, void* ws, size_t ws_bytes,
                        mhdg_solve_info* info, void* stream);
@@ -216,7 +245,8 @@ mhdg_status mhdg_mass_apply(mhdg_mesh* mesh, const double* v, double* out, void*
  *   dJ_dbeta[2]        = dJ/da_d = Psi^T (dF/da_d - dK/da_d X)   (device f64)
  * plus psi_lam (device f64[n_trace]) and psi_U (device f64[n_local]).  f is
  * held fixed.  ws: the solve workspace (mhdg_query with the same restart).
- * Errors: STATE without solve or with FP32 factors, NOT_CONVERGED. */
+ * Errors: STATE without solve, with FP32 factors or with more than one
+ * coefficient instance; NOT_CONVERGED. */
 mhdg_status mhdg_adjoint(mhdg_mesh* mesh, const double* lam, const double* qu, const double* dJ_dU,
                          const mhdg_solve_opts* opts, double* psi_lam, double* psi_U,
                          double* dJ_dkappa, double* dJ_dbeta, void* ws, size_t ws_bytes,

@@ -31,13 +31,25 @@ struct mhdg_mesh {
   std::vector<SizeClass> classes; // contiguous runs of equal local size in that order
   int64_t n_trace = 0, n_nodes = 0, n_local = 0, n_bnd_points = 0, n_slots = 0, n_lamD = 0;
   int32_t max_level = 0, max_N = 0;
+  // Coefficient instances: the tables above describe n_inst disjoint copies
+  // of one mesh (instance-major); `one` keeps the single-copy tables.
+  struct One {
+    int64_t n_macro, n_faces, n_int, n_bnd, n_trace, n_nodes, n_local, n_bnd_points, n_slots,
+        n_lamD, fac_total;
+    std::vector<MacroInfo> macros;
+    std::vector<FaceInfo> faces;
+    std::vector<BndFaceInfo> bfaces;
+    std::vector<int32_t> order;
+    std::vector<SizeClass> classes;
+  } one;
+  int32_t n_inst = 1;
   // templates
   Templates T{};
   std::vector<double> tmpl;       // blob (int tables stored bit-wise in doubles' space)
   // factor state
   bool factored = false, have_rhs = false;
   int precision = MHDG_FP64;
-  double bx = 0, by = 0, tau = 1;
+  double tau = 1;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   FactorLayout L{};
@@ -411,100 +423,194 @@ const int g_progress = [] {
 }();
 
 // Device vectors of one solve, carved from the caller's solve workspace.
+// With n_inst coefficient instances every vector holds nseg = n_inst
+// independent segments of length n (instance-major); the Krylov recurrences
+// run per segment in lockstep.
 struct Gm {
-  int64_t n = 0, ld = 0;
-  int nblk = 1;
+  int64_t n = 0, ld = 0;                  // segment length, column stride of V
+  int nseg = 1, nblk = 1;
   int32_t op_flags = MHDG_PRECONDITION;   // MHDG_TRANSPOSE added for adjoint solves
   double *V = nullptr, *wv = nullptr, *rv = nullptr, *tv = nullptr, *fh = nullptr, *pf = nullptr;
-  double *partial = nullptr, *hdev = nullptr, *ydev = nullptr;
+  double *partial = nullptr, *hdev = nullptr, *ydev = nullptr, *adev = nullptr;
+  int32_t* skip = nullptr;                // per-segment flags: 1 = take no part in applies
+  std::vector<int> seg_applies;           // applies each segment took part in
   double *U = nullptr, *dl = nullptr, *cl = nullptr;  // precision-refinement state
+  int64_t len() const { return n * nseg; }
 };
 
+// Per-segment inner products <a_s, b_s> into host[0..nseg).
 mhdg_status dot(mhdg_mesh* M, Gm& G, const double* a, const double* b, double* host, hipStream_t s) {
-  HIP_TRY(M, launch_dots(a, G.ld, 1, b, G.n, G.partial, G.nblk, G.hdev, s));
-  HIP_TRY(M, hipMemcpyAsync(host, G.hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(M, launch_dots(a, G.ld, 1, b, G.n, G.partial, G.nblk, G.hdev, s, G.nseg));
+  HIP_TRY(M, hipMemcpyAsync(host, G.hdev, G.nseg * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(M, hipStreamSynchronize(s));
   return MHDG_OK;
 }
 
+mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
+                     const int32_t* skip, hipStream_t s);
+
 // Left-preconditioned restarted GMRES on D^-1 S x = b (b already
 // preconditioned) with classical Gram-Schmidt applied twice (CGS2); all
 // vectors and inner products in FP64 on the device, the Hessenberg
-// least-squares problem by Givens rotations on the host.  Stops when
-// ||b - D^-1 S x|| <= rtol * bref.  x holds the initial guess.
-mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, double bref, double* x, double rtol,
-                  int R, int max_iter, int& iters, double& rel, int& applies, bool& converged,
-                  hipStream_t s) {
-  const int64_t n = G.n, ld = G.ld;
+// least-squares problems by Givens rotations on the host.  Segment s stops
+// when ||b_s - D^-1 S x_s|| <= rtol * bref[s] (checked on the true
+// preconditioned residual at the start of each cycle); a segment whose
+// estimate converges inside a cycle is masked out of the applies and its
+// Krylov columns are zero from then on.  x holds the initial guess.
+mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, double* x, double rtol,
+                  int R, int max_iter, std::vector<int>& iters, std::vector<double>& rel,
+                  int& applies, std::vector<char>& done, hipStream_t s) {
+  const int64_t n = G.n, ld = G.ld, len = G.len();
+  const int ns = G.nseg;
   mhdg_status st;
-  std::vector<double> H((R + 1) * R), cs(R), sn(R), g(R + 1), h(R + 2), y(R);
-  iters = 0;
-  converged = false;
+  std::vector<double> H(size_t(ns) * (R + 1) * R), cs(size_t(ns) * R), sn(size_t(ns) * R),
+      g(size_t(ns) * (R + 1)), h(size_t(ns) * (R + 2)), y(size_t(ns) * (R + 1)), beta(ns),
+      alpha(ns), nrm(ns);
+  std::vector<int32_t> skip(ns), skip_dev_copy(ns, -1);
+  std::vector<char> active(ns);
+  std::vector<int> jc(ns);
+  iters.assign(ns, 0);
+  rel.assign(ns, 0.0);
+  done.assign(ns, 0);
+  int it = 0;   // lockstep iterations
+  auto push_skip = [&]() -> mhdg_status {
+    if (skip == skip_dev_copy) return MHDG_OK;
+    HIP_TRY(M, hipMemcpyAsync(G.skip, skip.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    skip_dev_copy = skip;
+    return MHDG_OK;
+  };
+  auto push_alpha = [&]() -> mhdg_status {
+    HIP_TRY(M, hipMemcpyAsync(G.adev, alpha.data(), ns * sizeof(double), hipMemcpyHostToDevice, s));
+    return MHDG_OK;
+  };
+  for (int q = 0; q < ns; ++q) {
+    if (bref[q] == 0.0) {   // zero right-hand side: the solution is zero
+      HIP_TRY(M, hipMemsetAsync(x + q * n, 0, n * sizeof(double), s));
+      done[q] = 1;
+    }
+    skip[q] = done[q];
+  }
   while (true) {
-    if ((st = mhdg_apply_trace_operator(M, x, G.tv, G.op_flags, s))) return st;
+    if ((st = push_skip())) return st;
+    if ((st = apply_op(M, x, G.tv, G.op_flags, G.skip, s))) return st;
     ++applies;
-    HIP_TRY(M, launch_scale_copy(1.0, b, G.rv, n, s));
-    HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, n, s));
-    double rn2;
-    if ((st = dot(M, G, G.rv, G.rv, &rn2, s))) return st;
-    const double beta = std::sqrt(rn2);
-    rel = beta / bref;
-    if (rel <= rtol || iters >= max_iter) { converged = rel <= rtol; return MHDG_OK; }
-    HIP_TRY(M, launch_scale_copy(1.0 / beta, G.rv, G.V, n, s));
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
+    for (int q = 0; q < ns; ++q) G.seg_applies[q] += !skip[q];
+    HIP_TRY(M, launch_scale_copy(1.0, b, G.rv, len, s));
+    HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, len, s));
+    if ((st = dot(M, G, G.rv, G.rv, nrm.data(), s))) return st;
+    bool any = false;
+    jc.assign(ns, 0);
+    for (int q = 0; q < ns; ++q) {
+      if (done[q]) { active[q] = 0; alpha[q] = 0.0; skip[q] = 1; continue; }
+      beta[q] = std::sqrt(nrm[q]);
+      rel[q] = beta[q] / bref[q];
+      if (rel[q] <= rtol) done[q] = 1;
+      active[q] = !done[q];
+      alpha[q] = active[q] && beta[q] > 0 ? 1.0 / beta[q] : 0.0;
+      skip[q] = !active[q];
+      any |= active[q] != 0;
+      std::fill(g.begin() + q * (R + 1), g.begin() + (q + 1) * (R + 1), 0.0);
+      g[q * (R + 1)] = beta[q];
+    }
+    if (!any || it >= max_iter) return MHDG_OK;
+    if ((st = push_skip()) || (st = push_alpha())) return st;
+    HIP_TRY(M, launch_seg_scale_copy(G.adev, G.rv, G.V, n, ns, s));
     int j = 0;
-    for (; j < R && iters < max_iter; ++j) {
-      ++iters;
-      if ((st = mhdg_apply_trace_operator(M, G.V + j * ld, G.wv, G.op_flags, s))) return st;
+    for (; j < R && it < max_iter; ++j) {
+      ++it;
+      if ((st = apply_op(M, G.V + j * ld, G.wv, G.op_flags, G.skip, s))) return st;
       ++applies;
+      for (int q = 0; q < ns; ++q) G.seg_applies[q] += !skip[q];
       for (int pass = 0; pass < 2; ++pass) {
-        HIP_TRY(M, launch_dots(G.V, ld, j + 1, G.wv, n, G.partial, G.nblk, G.hdev, s));
-        HIP_TRY(M, launch_gemv_sub(G.V, ld, j + 1, G.hdev, G.wv, n, -1.0, s));
-        HIP_TRY(M, hipMemcpyAsync(h.data(), G.hdev, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(M, launch_dots(G.V, ld, j + 1, G.wv, n, G.partial, G.nblk, G.hdev, s, ns));
+        HIP_TRY(M, launch_gemv_sub(G.V, ld, j + 1, G.hdev, G.wv, n, -1.0, s, ns));
+        HIP_TRY(M, hipMemcpyAsync(h.data(), G.hdev, size_t(j + 1) * ns * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
         HIP_TRY(M, hipStreamSynchronize(s));
-        for (int i = 0; i <= j; ++i) H[i * R + j] = (pass ? H[i * R + j] : 0.0) + h[i];
+        for (int q = 0; q < ns; ++q) {
+          if (!active[q]) continue;
+          double* Hq = &H[size_t(q) * (R + 1) * R];
+          for (int i = 0; i <= j; ++i) Hq[i * R + j] = (pass ? Hq[i * R + j] : 0.0) + h[i * ns + q];
+        }
       }
-      double hn2;
-      if ((st = dot(M, G, G.wv, G.wv, &hn2, s))) return st;
-      const double hn = std::sqrt(hn2);
-      H[(j + 1) * R + j] = hn;
-      if (hn > 0) HIP_TRY(M, launch_scale_copy(1.0 / hn, G.wv, G.V + (j + 1) * ld, n, s));
-      for (int i = 0; i < j; ++i) {
-        const double a = H[i * R + j], bb = H[(i + 1) * R + j];
-        H[i * R + j] = cs[i] * a + sn[i] * bb;
-        H[(i + 1) * R + j] = -sn[i] * a + cs[i] * bb;
+      if ((st = dot(M, G, G.wv, G.wv, nrm.data(), s))) return st;
+      any = false;
+      for (int q = 0; q < ns; ++q) {
+        if (!active[q]) { alpha[q] = 0.0; continue; }
+        double* Hq = &H[size_t(q) * (R + 1) * R];
+        double* c = &cs[size_t(q) * R];
+        double* sq = &sn[size_t(q) * R];
+        double* gq = &g[size_t(q) * (R + 1)];
+        const double hn = std::sqrt(nrm[q]);
+        Hq[(j + 1) * R + j] = hn;
+        alpha[q] = hn > 0 ? 1.0 / hn : 0.0;
+        for (int i = 0; i < j; ++i) {
+          const double a = Hq[i * R + j], bb = Hq[(i + 1) * R + j];
+          Hq[i * R + j] = c[i] * a + sq[i] * bb;
+          Hq[(i + 1) * R + j] = -sq[i] * a + c[i] * bb;
+        }
+        const double a = Hq[j * R + j], bb = Hq[(j + 1) * R + j];
+        const double rr = std::hypot(a, bb);
+        c[j] = rr == 0 ? 1.0 : a / rr;
+        sq[j] = rr == 0 ? 0.0 : bb / rr;
+        Hq[j * R + j] = rr;
+        Hq[(j + 1) * R + j] = 0.0;
+        gq[j + 1] = -sq[j] * gq[j];
+        gq[j] = c[j] * gq[j];
+        rel[q] = std::fabs(gq[j + 1]) / bref[q];
+        jc[q] = j + 1;
+        ++iters[q];
+        if (rel[q] <= rtol || hn == 0.0) {   // this cycle is done for q
+          active[q] = 0;
+          alpha[q] = 0.0;
+          skip[q] = 1;
+        }
+        any |= active[q] != 0;
       }
-      const double a = H[j * R + j], bb = H[(j + 1) * R + j];
-      const double rr = std::hypot(a, bb);
-      cs[j] = rr == 0 ? 1.0 : a / rr;
-      sn[j] = rr == 0 ? 0.0 : bb / rr;
-      H[j * R + j] = rr;
-      H[(j + 1) * R + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      rel = std::fabs(g[j + 1]) / bref;
-      if (g_progress && iters % g_progress == 0) {
-        std::fprintf(stderr, "[mhdg] gmres iteration %d relative residual %.3e\n", iters, rel);
+      if (g_progress && it % g_progress == 0) {
+        double worst = 0;
+        for (int q = 0; q < ns; ++q)
+          if (!done[q]) worst = std::max(worst, rel[q]);
+        std::fprintf(stderr, "[mhdg] gmres iteration %d relative residual %.3e\n", it, worst);
         std::fflush(stderr);
       }
-      if (rel <= rtol || hn == 0.0) { ++j; break; }
+      if ((st = push_alpha())) return st;
+      HIP_TRY(M, launch_seg_scale_copy(G.adev, G.wv, G.V + (j + 1) * ld, n, ns, s));
+      if ((st = push_skip())) return st;
+      if (!any) { ++j; break; }
     }
-    for (int i = j - 1; i >= 0; --i) {
-      double v = g[i];
-      for (int k = i + 1; k < j; ++k) v -= H[i * R + k] * y[k];
-      y[i] = v / H[i * R + i];
+    // x_q += V y_q with R_q y_q = g_q over segment q's jc[q] columns
+    int jmax = 0;
+    std::fill(y.begin(), y.end(), 0.0);
+    for (int q = 0; q < ns; ++q) {
+      const int jq = jc[q];
+      jmax = std::max(jmax, jq);
+      const double* Hq = &H[size_t(q) * (R + 1) * R];
+      const double* gq = &g[size_t(q) * (R + 1)];
+      std::vector<double> yq(jq);
+      for (int i = jq - 1; i >= 0; --i) {
+        double v = gq[i];
+        for (int kk = i + 1; kk < jq; ++kk) v -= Hq[i * R + kk] * yq[kk];
+        yq[i] = v / Hq[i * R + i];
+      }
+      for (int i = 0; i < jq; ++i) y[size_t(i) * ns + q] = yq[i];
     }
-    HIP_TRY(M, hipMemcpyAsync(G.ydev, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_TRY(M, launch_gemv_sub(G.V, ld, j, G.ydev, x, n, 1.0, s));
+    if (jmax > 0) {
+      HIP_TRY(M, hipMemcpyAsync(G.ydev, y.data(), size_t(jmax) * ns * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+      HIP_TRY(M, launch_gemv_sub(G.V, ld, jmax, G.ydev, x, n, 1.0, s, ns));
+    }
     HIP_TRY(M, hipStreamSynchronize(s));
+    for (int q = 0; q < ns; ++q) skip[q] = done[q];
   }
 }
 
 mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
-  G.n = M->n_trace;
+  G.nseg = M->n_inst;
+  G.n = M->n_trace / M->n_inst;
+  G.seg_applies.assign(G.nseg, 0);
   char* w = (char*)ws;
-  const size_t vb = align_up(size_t(G.n) * sizeof(double));
+  const size_t vb = align_up(size_t(G.len()) * sizeof(double));
   G.ld = int64_t(vb / sizeof(double));
   G.V = (double*)w;
   G.wv = (double*)(w + vb * (R + 1));
@@ -517,11 +623,15 @@ mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
   size_t off = align_up(vb * (R + 8));
   G.nblk = dots_nblk(G.n);
   G.partial = (double*)(w + off);
-  off += align_up(size_t(G.nblk) * (R + 2) * sizeof(double));
+  off += align_up(size_t(G.nblk) * G.nseg * (R + 2) * sizeof(double));
   G.hdev = (double*)(w + off);
-  off += align_up(size_t(R + 2) * 8);
+  off += align_up(size_t(R + 2) * G.nseg * 8);
   G.ydev = (double*)(w + off);
-  off += align_up(size_t(R + 2) * 8);
+  off += align_up(size_t(R + 2) * G.nseg * 8);
+  G.adev = (double*)(w + off);
+  off += align_up(size_t(G.nseg) * 8);
+  G.skip = (int32_t*)(w + off);
+  off += align_up(size_t(G.nseg) * 4);
   G.U = (double*)(w + off);
   return MHDG_OK;
 }
@@ -730,7 +840,78 @@ mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t 
     fo = (fo + 63) & ~int64_t(63);
   }
   build_templates(M);
+  M->one = {M->n_macro, M->n_faces, M->n_int, M->n_bnd, M->n_trace, M->n_nodes, M->n_local,
+            M->n_bnd_points, M->n_slots, M->n_lamD, fo, M->macros, M->faces, M->bfaces,
+            M->order, M->classes};
   *out = M;
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_set_instances(mhdg_mesh* M, int32_t n_inst) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  const auto& o = M->one;
+  if (n_inst < 1 || int64_t(n_inst) * o.n_macro > (int64_t(1) << 28) ||
+      int64_t(n_inst) * o.n_trace > INT32_MAX)
+    return fail(M, MHDG_ERR_INVALID_ARG, "set_instances: instance count out of range");
+  M->factored = false;
+  M->have_rhs = false;
+  M->ws = nullptr;
+  M->n_inst = n_inst;
+  M->n_macro = o.n_macro * n_inst;
+  M->n_faces = o.n_faces * n_inst;
+  M->n_int = o.n_int * n_inst;
+  M->n_bnd = o.n_bnd * n_inst;
+  M->n_trace = o.n_trace * n_inst;
+  M->n_nodes = o.n_nodes * n_inst;
+  M->n_local = o.n_local * n_inst;
+  M->n_bnd_points = o.n_bnd_points * n_inst;
+  M->n_slots = o.n_slots * n_inst;
+  M->n_lamD = o.n_lamD * n_inst;
+  M->macros.resize(M->n_macro);
+  M->faces.resize(M->n_int);
+  M->bfaces.resize(M->n_bnd);
+  for (int32_t i = 0; i < n_inst; ++i) {
+    for (int64_t e = 0; e < o.n_macro; ++e) {
+      MacroInfo mi = o.macros[e];
+      mi.inst = i;
+      mi.fac_off += i * o.fac_total;
+      mi.loc_off += i * o.n_local;
+      mi.node_off += i * o.n_nodes;
+      for (int k = 0; k < 3; ++k) {
+        mi.face[k] += int32_t(i * o.n_faces);
+        if (mi.slot_off[k] >= 0) mi.slot_off[k] += i * o.n_slots;
+        if (mi.tr_off[k] >= 0) mi.tr_off[k] += int32_t(i * o.n_trace);
+        if (mi.bnd_face[k] >= 0) mi.bnd_face[k] += int32_t(i * o.n_bnd);
+      }
+      M->macros[i * o.n_macro + e] = mi;
+    }
+    for (int64_t f = 0; f < o.n_int; ++f) {
+      FaceInfo fi = o.faces[f];
+      fi.inst = i;
+      fi.slot[0] += i * o.n_slots;
+      fi.slot[1] += i * o.n_slots;
+      fi.tr_off += int32_t(i * o.n_trace);
+      M->faces[i * o.n_int + f] = fi;
+    }
+    for (int64_t f = 0; f < o.n_bnd; ++f) {
+      BndFaceInfo b = o.bfaces[f];
+      b.g_off += i * o.n_bnd_points;
+      b.lam_off += i * o.n_lamD;
+      M->bfaces[i * o.n_bnd + f] = b;
+    }
+  }
+  // one launch per size class covers every instance
+  M->order.clear();
+  M->classes.clear();
+  for (const SizeClass& c : o.classes) {
+    SizeClass c2 = c;
+    c2.start = (int64_t)M->order.size();
+    c2.count = c.count * n_inst;
+    for (int32_t i = 0; i < n_inst; ++i)
+      for (int64_t j = 0; j < c.count; ++j)
+        M->order.push_back(int32_t(o.order[c.start + j] + i * o.n_macro));
+    M->classes.push_back(c2);
+  }
   return MHDG_OK;
 }
 
@@ -768,6 +949,7 @@ mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, m
   out->p = M->p;
   out->max_level = M->max_level;
   out->max_local = M->max_N;
+  out->n_instances = M->n_inst;
   FactorLayout L = factor_layout(M, precision);
   // factor block offsets are padded to 64 elements per macro
   size_t es = precision == MHDG_FP32 ? 4 : 8;
@@ -783,9 +965,10 @@ mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, m
 
 mhdg_status mhdg_sample_points(const mhdg_mesh* M, double* node_xy, double* bnd_xy) {
   if (!M) return MHDG_ERR_INVALID_ARG;
+  const auto& one = M->one;
   if (node_xy) {
     int64_t o = 0;
-    for (int64_t e = 0; e < M->n_macro; ++e) {
+    for (int64_t e = 0; e < one.n_macro; ++e) {
       const MacroInfo& mi = M->macros[e];
       const int32_t* t = &M->tri[3 * e];
       double x0 = M->xy[2 * t[0]], y0 = M->xy[2 * t[0] + 1];
@@ -804,19 +987,19 @@ mhdg_status mhdg_sample_points(const mhdg_mesh* M, double* node_xy, double* bnd_
     std::vector<double> t, w;
     gauss_legendre01(M->p + 2, t, w);
     // boundary faces in sorted order = order of bfaces
-    std::vector<std::pair<int64_t, int64_t>> fv(M->n_faces);
-    for (int64_t e = 0; e < M->n_macro; ++e)
+    std::vector<std::pair<int64_t, int64_t>> fv(one.n_faces);
+    for (int64_t e = 0; e < one.n_macro; ++e)
       for (int k = 0; k < 3; ++k) {
         int64_t a = M->tri[3 * e + k], b = M->tri[3 * e + (k + 1) % 3];
-        fv[M->macros[e].face[k]] = {std::min(a, b), std::max(a, b)};
+        fv[one.macros[e].face[k]] = {std::min(a, b), std::max(a, b)};
       }
-    std::vector<int32_t> bface_of(M->n_faces, -1);
-    for (int64_t e = 0; e < M->n_macro; ++e)
+    std::vector<int32_t> bface_of(one.n_faces, -1);
+    for (int64_t e = 0; e < one.n_macro; ++e)
       for (int k = 0; k < 3; ++k)
-        if (M->macros[e].bnd_face[k] >= 0) bface_of[M->macros[e].face[k]] = M->macros[e].bnd_face[k];
-    for (int64_t f = 0; f < M->n_faces; ++f) {
+        if (one.macros[e].bnd_face[k] >= 0) bface_of[one.macros[e].face[k]] = one.macros[e].bnd_face[k];
+    for (int64_t f = 0; f < one.n_faces; ++f) {
       if (bface_of[f] < 0) continue;
-      const BndFaceInfo& b = M->bfaces[bface_of[f]];
+      const BndFaceInfo& b = one.bfaces[bface_of[f]];
       double ax = M->xy[2 * fv[f].first], ay = M->xy[2 * fv[f].first + 1];
       double bx = M->xy[2 * fv[f].second], by = M->xy[2 * fv[f].second + 1];
       int npc = 1 << b.level;
@@ -830,6 +1013,13 @@ mhdg_status mhdg_sample_points(const mhdg_mesh* M, double* node_xy, double* bnd_
         }
     }
   }
+  // every instance samples at the same points
+  for (int32_t i = 1; i < M->n_inst; ++i) {
+    if (node_xy)
+      std::memcpy(node_xy + 2 * i * one.n_nodes, node_xy, 2 * one.n_nodes * sizeof(double));
+    if (bnd_xy)
+      std::memcpy(bnd_xy + 2 * i * one.n_bnd_points, bnd_xy, 2 * one.n_bnd_points * sizeof(double));
+  }
   return MHDG_OK;
 }
 
@@ -837,8 +1027,19 @@ mhdg_status mhdg_factor_local(mhdg_mesh* M, const double* kappa, double beta_x, 
                               double tau, int32_t precision, void* ws, size_t ws_bytes,
                               void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;
-  if (!kappa || !ws || !(tau > 0.0) || !std::isfinite(beta_x) || !std::isfinite(beta_y))
+  std::vector<double> beta(2 * size_t(M->n_inst));
+  for (int32_t i = 0; i < M->n_inst; ++i) { beta[2 * i] = beta_x; beta[2 * i + 1] = beta_y; }
+  return mhdg_factor_local_batched(M, kappa, beta.data(), tau, precision, ws, ws_bytes, stream);
+}
+
+mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const double* beta,
+                                      double tau, int32_t precision, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!kappa || !ws || !beta || !(tau > 0.0))
     return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: null pointer or tau <= 0");
+  for (int64_t i = 0; i < 2 * int64_t(M->n_inst); ++i)
+    if (!std::isfinite(beta[i])) return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: non-finite a");
   if (precision != MHDG_FP64 && precision != MHDG_FP32)
     return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: unknown precision");
   mhdg_sizes sz;
@@ -849,9 +1050,10 @@ mhdg_status mhdg_factor_local(mhdg_mesh* M, const double* kappa, double beta_x, 
   M->factored = false;
   M->have_rhs = false;
   M->precision = precision;
-  M->bx = beta_x; M->by = beta_y; M->tau = tau;
+  M->tau = tau;
   M->ws = (char*)ws;
   M->ws_bytes = ws_bytes;
+  for (auto& mi : M->macros) { mi.bx = beta[2 * mi.inst]; mi.by = beta[2 * mi.inst + 1]; }
   M->L = factor_layout(M, precision);
   FactorLayout& L = M->L;
   char* w = M->ws;
@@ -873,7 +1075,7 @@ mhdg_status mhdg_factor_local(mhdg_mesh* M, const double* kappa, double beta_x, 
   {
     ProfScope ps(M, 0, s);
     HIP_TRY(M, launch_assemble(w + L.factors, precision, info, nullptr, M->n_macro,
-                               (const double*)(w + L.tmpl), M->T, beta_x, beta_y, tau, s));
+                               (const double*)(w + L.tmpl), M->T, tau, s));
   }
   {
     ProfScope ps(M, 1, s);
@@ -901,13 +1103,14 @@ mhdg_status mhdg_local_matrix(mhdg_mesh* M, int64_t e, double* dst, void* stream
   if (!M->ws) return fail(M, MHDG_ERR_STATE, "local_matrix: call factor_local first");
   FactorLayout& L = M->L;
   HIP_TRY(M, launch_extract_matrix((const MacroInfo*)(M->ws + L.meta), e,
-                                   (const double*)(M->ws + L.tmpl), M->T, M->bx, M->by, M->tau,
-                                   dst, (hipStream_t)stream));
+                                   (const double*)(M->ws + L.tmpl), M->T, M->tau, dst,
+                                   (hipStream_t)stream));
   return MHDG_OK;
 }
 
 static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const double* lam,
-                                   const double* xin, double* yout, hipStream_t s) {
+                                   const double* xin, double* yout, hipStream_t s,
+                                   const int32_t* skip = nullptr) {
   FactorLayout& L = M->L;
   char* w = M->ws;
   ProfScope ps(M, mode == MODE_APPLY ? 2 : 4, s);
@@ -915,9 +1118,26 @@ static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const 
                                 (const MacroInfo*)(w + L.meta), (const int32_t*)(w + L.order),
                                 M->classes.data(), (int)M->classes.size(),
                                 (const int32_t*)(w + L.perm), (const double*)(w + L.tmpl), M->T,
-                                M->bx, M->by, M->tau, lam, xin, yout, (double*)(w + L.slots), s));
+                                skip, M->tau, lam, xin, yout, (double*)(w + L.slots), s));
   return MHDG_OK;
 }
+
+namespace {
+// The trace operator with an optional per-instance mask (see gmres).
+mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
+                     const int32_t* skip, hipStream_t s) {
+  const int tr = (flags & MHDG_TRANSPOSE) ? 1 : 0;
+  mhdg_status st = run_macro_solve(M, MODE_APPLY, tr, lam, nullptr, nullptr, s, skip);
+  if (st) return st;
+  FactorLayout& L = M->L;
+  ProfScope ps(M, 3, s);
+  HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
+                                 (const FaceInfo*)(M->ws + L.faces), M->n_int,
+                                 (const double*)(M->ws + L.tmpl), M->T, M->tau, lam,
+                                 (const double*)(M->ws + L.slots), out, s, skip));
+  return MHDG_OK;
+}
+}  // namespace
 
 mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
                                       void* stream) {
@@ -929,16 +1149,7 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* o
   if (tr && M->precision != MHDG_FP64)
     return fail(M, MHDG_ERR_STATE, "apply: the transposed operator needs FP64 factors");
   if (M->n_trace == 0) return MHDG_OK;
-  hipStream_t s = (hipStream_t)stream;
-  mhdg_status st = run_macro_solve(M, MODE_APPLY, tr, lam, nullptr, nullptr, s);
-  if (st) return st;
-  FactorLayout& L = M->L;
-  ProfScope ps(M, 3, s);
-  HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
-                                 (const FaceInfo*)(M->ws + L.faces), M->n_int,
-                                 (const double*)(M->ws + L.tmpl), M->T, M->tau, lam,
-                                 (const double*)(M->ws + L.slots), out, s));
-  return MHDG_OK;
+  return apply_op(M, lam, out, flags, nullptr, (hipStream_t)stream);
 }
 
 mhdg_status mhdg_local_solve(mhdg_mesh* M, const double* x, double* y, int32_t flags, void* stream) {
@@ -966,7 +1177,7 @@ mhdg_status mhdg_rhs(mhdg_mesh* M, const double* f_nodes, const double* g_bnd, d
                                 (double*)(w + L.lamD), s));
   HIP_TRY(M, launch_local_rhs((const MacroInfo*)(w + L.meta), M->n_macro,
                               (const BndFaceInfo*)(w + L.bfaces), tm, M->T, f_nodes,
-                              (const double*)(w + L.lamD), M->bx, M->by, M->tau,
+                              (const double*)(w + L.lamD), M->tau,
                               (double*)(w + L.R), s));
   M->have_rhs = true;
   if (M->n_trace == 0) return MHDG_OK;
@@ -1005,7 +1216,7 @@ mhdg_status mhdg_recover_local(mhdg_mesh* M, const double* lam, double* qu, doub
     std::vector<double> hbuf(1);
     double prev = -1.0;
     for (int sweep = 0; sweep < 12; ++sweep) {
-      HIP_TRY(M, launch_local_residual(info_d, M->n_macro, tm, M->T, M->bx, M->by, M->tau,
+      HIP_TRY(M, launch_local_residual(info_d, M->n_macro, tm, M->T, M->tau,
                                        (const double*)(fw + L.R), qu, lam, r, s));
       // ||r||: partial sums in d (nblk doubles), result in d[nblk]
       G.partial = d;
@@ -1034,10 +1245,12 @@ mhdg_status mhdg_recover_local(mhdg_mesh* M, const double* lam, double* qu, doub
 
 
 static size_t solve_bytes_impl(const mhdg_mesh* M, int R) {
+  const size_t ns = size_t(M->n_inst);
   const size_t vb = align_up(size_t(M->n_trace) * sizeof(double));
-  const size_t nblk = size_t(dots_nblk(M->n_trace));
-  return align_up(vb * (R + 8)) + align_up(nblk * size_t(R + 2) * sizeof(double)) +
-         2 * align_up(size_t(R + 2) * 8) + align_up(size_t(M->n_local) * sizeof(double));
+  const size_t nblk = size_t(dots_nblk(M->n_trace / M->n_inst));
+  return align_up(vb * (R + 8)) + align_up(nblk * ns * size_t(R + 2) * sizeof(double)) +
+         2 * align_up(size_t(R + 2) * ns * 8) + align_up(ns * 8) + align_up(ns * 4) +
+         align_up(size_t(M->n_local) * sizeof(double));
 }
 
 mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
@@ -1049,9 +1262,12 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   if (!M->factored) return fail(M, MHDG_ERR_STATE, "solve: call factor_local first");
   if (ws_bytes < solve_bytes_impl(M, o->restart))
     return fail(M, MHDG_ERR_WORKSPACE, "solve: workspace smaller than mhdg_query reports");
+  if (M->precision != MHDG_FP64 && M->n_inst > 1)
+    return fail(M, MHDG_ERR_STATE, "solve: reduced-precision factors need a single instance");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = M->n_trace;
   const int R = o->restart;
+  const int ns = M->n_inst;
   auto t0 = std::chrono::steady_clock::now();
   Gm G;
   carve(M, ws, R, G);
@@ -1065,7 +1281,8 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   // f^ (and R_K, kept in the factor workspace) and D^-1 f^
   if ((st = mhdg_rhs(M, f_nodes, g_bnd, G.fh, 0, stream))) return st;
   if (n == 0) {
-    if (info) *info = inf;
+    if (info)
+      for (int q = 0; q < ns; ++q) info[q] = inf;
     return MHDG_OK;
   }
   if ((st = mhdg_rhs(M, f_nodes, g_bnd, G.pf, MHDG_PRECONDITION, stream))) return st;
@@ -1075,31 +1292,32 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   if (o->zero_guess) HIP_TRY(M, hipMemsetAsync(lam, 0, n * sizeof(double), s));
   bool converged = false;
   double rel = 0.0;
+  std::vector<mhdg_solve_info> per(ns);
   if (M->precision == MHDG_FP64) {
-    // ---- plain form: GMRES on D^-1 S lam = D^-1 f^
-    double b2;
-    if ((st = dot(M, G, G.pf, G.pf, &b2, s))) return st;
-    const double bnorm = std::sqrt(b2);
-    if (bnorm == 0.0) {
-      HIP_TRY(M, hipMemsetAsync(lam, 0, n * sizeof(double), s));
-      converged = true;
-    } else {
-      int it = 0;
-      if ((st = gmres(M, G, G.pf, bnorm, lam, o->rtol, R, o->max_iter, it, rel, inf.n_applies,
-                      converged, s)))
-        return st;
-      inf.iterations = it;
-    }
-    // true residual ||f^ - S lam|| / ||f^||
+    // ---- plain form: GMRES on D^-1 S lam = D^-1 f^, one Krylov space per instance
+    std::vector<double> bnorm(ns), tr2(ns), f2(ns), rels;
+    std::vector<int> its;
+    std::vector<char> done;
+    if ((st = dot(M, G, G.pf, G.pf, bnorm.data(), s))) return st;
+    for (auto& b : bnorm) b = std::sqrt(b);
+    if ((st = gmres(M, G, G.pf, bnorm.data(), lam, o->rtol, R, o->max_iter, its, rels,
+                    inf.n_applies, done, s)))
+      return st;
+    // true residual ||f^ - S lam|| / ||f^|| per instance
     if ((st = mhdg_apply_trace_operator(M, lam, G.tv, 0, stream))) return st;
     ++inf.n_applies;
     HIP_TRY(M, launch_scale_copy(1.0, G.fh, G.rv, n, s));
     HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, n, s));
-    double tr2, f2;
-    if ((st = dot(M, G, G.rv, G.rv, &tr2, s))) return st;
-    if ((st = dot(M, G, G.fh, G.fh, &f2, s))) return st;
-    inf.rel_res_true = f2 > 0 ? std::sqrt(tr2 / f2) : 0.0;
-    inf.rel_res_prec = rel;
+    if ((st = dot(M, G, G.rv, G.rv, tr2.data(), s))) return st;
+    if ((st = dot(M, G, G.fh, G.fh, f2.data(), s))) return st;
+    converged = true;
+    for (int q = 0; q < ns; ++q) {
+      per[q].iterations = its[q];
+      per[q].rel_res_prec = rels[q];
+      per[q].rel_res_true = f2[q] > 0 ? std::sqrt(tr2[q] / f2[q]) : 0.0;
+      per[q].status = done[q] ? MHDG_OK : MHDG_ERR_NOT_CONVERGED;
+      converged &= done[q] != 0;
+    }
   } else {
     // ---- reduced-precision factors: iterative refinement of the whole
     // hybridised system in FP64.  The residual (r_U, r_lam) = (R - A U - B lam,
@@ -1113,7 +1331,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       // start U from the low-precision local solve for the given lam
       HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
                                     M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
-                                    M->bx, M->by, M->tau, lam, (const double*)(fw + L.R), G.U,
+                                    nullptr, M->tau, lam, (const double*)(fw + L.R), G.U,
                                     (double*)(fw + L.slots), s));
     }
     const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
@@ -1122,7 +1340,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
     int outer = 0, it_total = 0;
     for (;; ++outer) {
       // FP64 residual of the full system
-      HIP_TRY(M, launch_local_residual(info_d, M->n_macro, tm, M->T, M->bx, M->by, M->tau,
+      HIP_TRY(M, launch_local_residual(info_d, M->n_macro, tm, M->T, M->tau,
                                        (const double*)(fw + L.R), G.U, lam, rU, s));
       HIP_TRY(M, launch_boundary_C(info_d, M->n_macro, tm, M->T, M->tau, G.U, (double*)(fw + L.slots), s));
       HIP_TRY(M, launch_face_combine(FACE_RESID, faces_d, M->n_int, tm, M->T, M->tau, lam,
@@ -1130,7 +1348,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       // condensed right-hand side b = D^-1 (r_lam - sum C A~^-1 r_U)
       HIP_TRY(M, launch_macro_solve(MODE_RHS, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
                                     M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
-                                    M->bx, M->by, M->tau, nullptr, rU, nullptr,
+                                    nullptr, M->tau, nullptr, rU, nullptr,
                                     (double*)(fw + L.slots), s));
       ++inf.n_applies;
       HIP_TRY(M, launch_face_combine(FACE_PREC_RHS, faces_d, M->n_int, tm, M->T, M->tau, nullptr,
@@ -1150,30 +1368,38 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       const double eta = std::max(inner_rtol, 0.3 * o->rtol / std::max(rel, 1e-300));
       HIP_TRY(M, launch_scale_copy(1.0, G.wv, G.fh, n, s));                        // keep b: GMRES uses V/wv
       HIP_TRY(M, hipMemsetAsync(G.dl, 0, n * sizeof(double), s));
-      int it = 0;
-      double irel = 0;
-      bool iconv = false;
-      if ((st = gmres(M, G, G.fh, rho, G.dl, eta, R, o->max_iter - it_total, it, irel,
+      std::vector<int> it;
+      std::vector<double> irel;
+      std::vector<char> iconv;
+      if ((st = gmres(M, G, G.fh, &rho, G.dl, eta, R, o->max_iter - it_total, it, irel,
                       inf.n_applies, iconv, s)))
         return st;
-      it_total += it;
+      it_total += it[0];
       // dU = A~^-1 (r_U - B dlam); U += dU; lam += dlam
       HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
                                     M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
-                                    M->bx, M->by, M->tau, G.dl, rU, rU, (double*)(fw + L.slots), s));
+                                    nullptr, M->tau, G.dl, rU, rU, (double*)(fw + L.slots), s));
       ++inf.n_applies;
       HIP_TRY(M, launch_axpby(1.0, rU, 1.0, G.U, nl, s));
       HIP_TRY(M, launch_axpby(1.0, G.dl, 1.0, lam, n, s));
     }
-    inf.iterations = it_total;
-    inf.outer_iterations = outer;
-    inf.rel_res_prec = rel;
-    inf.rel_res_true = -1.0;   // needs FP64 factors; see rel_res_prec (FP64 residual, condensed)
+    per[0].iterations = it_total;
+    per[0].outer_iterations = outer;
+    per[0].rel_res_prec = rel;
+    per[0].rel_res_true = -1.0;   // needs FP64 factors; see rel_res_prec (FP64 residual, condensed)
+    per[0].status = converged ? MHDG_OK : MHDG_ERR_NOT_CONVERGED;
   }
   auto t2 = std::chrono::steady_clock::now();
   inf.t_gmres_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
-  inf.status = converged ? MHDG_OK : MHDG_ERR_NOT_CONVERGED;
-  if (info) *info = inf;
+  if (info)
+    for (int q = 0; q < ns; ++q) {
+      info[q] = per[q];
+      info[q].t_rhs_ms = inf.t_rhs_ms;
+      info[q].t_gmres_ms = inf.t_gmres_ms;
+      // applies this instance took part in (rhs 2, GMRES, true residual 1 for FP64)
+      info[q].n_applies = ns == 1 ? inf.n_applies
+                                  : 3 + G.seg_applies[q];
+    }
   if (!converged) return fail(M, MHDG_ERR_NOT_CONVERGED, "solve: max_iter reached");
   return MHDG_OK;
 }
@@ -1204,6 +1430,8 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
     return fail(M, MHDG_ERR_STATE, "adjoint: call factor_local and solve first");
   if (M->precision != MHDG_FP64)
     return fail(M, MHDG_ERR_STATE, "adjoint: needs FP64 factors");
+  if (M->n_inst != 1)
+    return fail(M, MHDG_ERR_STATE, "adjoint: needs a single coefficient instance");
   if (ws_bytes < solve_bytes_impl(M, o->restart))
     return fail(M, MHDG_ERR_WORKSPACE, "adjoint: workspace smaller than mhdg_query reports");
   hipStream_t s = (hipStream_t)stream;
@@ -1229,11 +1457,16 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
     if ((st = dot(M, G, G.pf, G.pf, &b2, s))) return st;
     HIP_TRY(M, hipMemsetAsync(psi_lam, 0, n * sizeof(double), s));
     if (b2 > 0) {
-      double rel = 0;
-      if ((st = gmres(M, G, G.pf, std::sqrt(b2), psi_lam, o->rtol, o->restart, o->max_iter,
-                      inf.iterations, rel, inf.n_applies, converged, s)))
+      const double bn = std::sqrt(b2);
+      std::vector<int> its;
+      std::vector<double> rels;
+      std::vector<char> done;
+      if ((st = gmres(M, G, G.pf, &bn, psi_lam, o->rtol, o->restart, o->max_iter, its, rels,
+                      inf.n_applies, done, s)))
         return st;
-      inf.rel_res_prec = rel;
+      inf.iterations = its[0];
+      inf.rel_res_prec = rels[0];
+      converged = done[0] != 0;
     }
   }
   // psi_U = A^-T (g - C^T psi_lam)

@@ -18,6 +18,7 @@ struct MacroInfo {
   double len[3];      // edge lengths, edge k from vertex k to vertex k+1
   double nrm[6];      // outward unit normals (nx, ny) per edge
   double kappa;       // filled on the device from the caller's kappa array
+  double bx, by;      // advection a of this macro's coefficient instance
   int64_t fac_off;    // element offset of this macro's factor block
   int64_t loc_off;    // offset into n_local vectors
   int64_t node_off;   // offset into n_nodes vectors
@@ -31,7 +32,7 @@ struct MacroInfo {
   int32_t N;          // local size 3Q
   int32_t Q;
   int32_t P;          // 2^r p
-  int32_t pad;
+  int32_t inst;       // coefficient instance this macro belongs to
 };
 
 struct FaceInfo {     // interior faces
@@ -40,7 +41,7 @@ struct FaceInfo {     // interior faces
   int32_t tr_off;
   int32_t nF;
   int32_t level;
-  int32_t pad;
+  int32_t inst;       // coefficient instance
 };
 
 struct BndFaceInfo {  // boundary (Dirichlet) faces
@@ -87,9 +88,8 @@ struct SizeClass {
 enum SolveMode { MODE_APPLY = 0, MODE_RHS = 1, MODE_RECOVER = 2, MODE_LOCAL = 3 };
 
 hipError_t launch_local_residual(const MacroInfo* info, int64_t n, const double* tmpl,
-                                 const Templates& T, double bx, double by, double tau,
-                                 const double* R, const double* U, const double* lam,
-                                 double* out, hipStream_t s);
+                                 const Templates& T, double tau, const double* R, const double* U,
+                                 const double* lam, double* out, hipStream_t s);
 hipError_t launch_adjoint_contract(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
                                    const double* tmpl, const Templates& T, const double* U,
                                    const double* Psi, const double* lam, const double* psi_lam,
@@ -104,8 +104,8 @@ hipError_t launch_boundary_C(const MacroInfo* info, int64_t n, const double* tmp
 // ---- kernel launchers (kernels.hip) ----
 hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, hipStream_t s);
 hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, const int32_t* order,
-                           int64_t n, const double* tmpl, const Templates& T, double bx, double by,
-                           double tau, hipStream_t s);
+                           int64_t n, const double* tmpl, const Templates& T, double tau,
+                           hipStream_t s);
 hipError_t launch_lu(void* fac, int precision, const MacroInfo* info, const int32_t* order,
                      const SizeClass* classes, int n_classes, int32_t* perm, int32_t* status,
                      hipStream_t s);
@@ -113,29 +113,36 @@ hipError_t launch_dirichlet(const BndFaceInfo* bf, int64_t nbf, const double* tm
                             const Templates& T, const double* g, double* lamD, hipStream_t s);
 hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
                             const double* tmpl, const Templates& T, const double* f,
-                            const double* lamD, double bx, double by, double tau, double* R,
-                            hipStream_t s);
+                            const double* lamD, double tau, double* R, hipStream_t s);
+// skip: null, or per-instance flags; macros (faces) of an instance whose flag
+// is non-zero are not processed and their outputs are left untouched (face
+// outputs are written as zero).
 hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int precision,
                               const MacroInfo* info, const int32_t* order,
                               const SizeClass* classes, int n_classes, const int32_t* perm,
-                              const double* tmpl, const Templates& T, double bx, double by,
+                              const double* tmpl, const Templates& T, const int32_t* skip,
                               double tau, const double* lam, const double* xin, double* yout,
                               double* slots, hipStream_t s);
 hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const double* tmpl,
                                const Templates& T, double tau, const double* lam,
-                               const double* slots, double* out, hipStream_t s);
+                               const double* slots, double* out, hipStream_t s,
+                               const int32_t* skip = nullptr);
 hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double* tmpl,
-                                 const Templates& T, double bx, double by, double tau,
-                                 double* dst, hipStream_t s);
+                                 const Templates& T, double tau, double* dst, hipStream_t s);
 // face_combine modes
 enum FaceMode { FACE_S = 0, FACE_PREC_S = 1, FACE_RHS = 2, FACE_PREC_RHS = 3, FACE_RESID = 4,
                 FACE_DINV = 5 /* out = D_F^-1 lam (slots unused) */ };
 
 // GMRES vector kernels
+// Vectors may hold nseg independent segments of length n (coefficient
+// instances): dot products and updates are per segment; out / h are indexed
+// [column * nseg + segment].
 hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, int64_t n,
-                       double* partial, int nblk, double* out, hipStream_t s);
+                       double* partial, int nblk, double* out, hipStream_t s, int nseg = 1);
 hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double* h, double* w,
-                           int64_t n, double sign, hipStream_t s);
+                           int64_t n, double sign, hipStream_t s, int nseg = 1);
+hipError_t launch_seg_scale_copy(const double* alpha, const double* x, double* y, int64_t n, int nseg,
+                                 hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);
 int dots_nblk(int64_t n);

@@ -43,8 +43,7 @@ struct EntryCtx {
 };
 
 __device__ __forceinline__ EntryCtx make_ctx(const MacroInfo& mi, const double* tm,
-                                             const Templates& T, double bx, double by,
-                                             double tau) {
+                                             const Templates& T, double tau) {
   EntryCtx c;
   const LevelTemplates& L = T.lev[mi.level];
   c.Mh = tm + L.Mhat;
@@ -56,8 +55,8 @@ __device__ __forceinline__ EntryCtx make_ctx(const MacroInfo& mi, const double* 
   c.dJ = mi.dJ;
   for (int k = 0; k < 3; ++k) c.len[k] = mi.len[k];
   c.kappa = mi.kappa;
-  c.bx = bx;
-  c.by = by;
+  c.bx = mi.bx;
+  c.by = mi.by;
   c.tau = tau;
   c.Q = mi.Q;
   c.P = mi.P;
@@ -106,13 +105,13 @@ __global__ void set_kappa_kernel(MacroInfo* info, const double* kappa, int64_t n
 template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(T* fac, const MacroInfo* __restrict__ info,
                                                        const double* __restrict__ tm, Templates Tp,
-                                                       double bx, double by, double tau) {
+                                                       double tau) {
   const MacroInfo& mi = info[blockIdx.x];
   const int N = mi.N;
   const int rows_per = 8;
   const int r0 = blockIdx.y * rows_per;
   if (r0 >= N) return;
-  EntryCtx c = make_ctx(mi, tm, Tp, bx, by, tau);
+  EntryCtx c = make_ctx(mi, tm, Tp, tau);
   T* A = fac + mi.fac_off;
   const int r1 = min(N, r0 + rows_per);
   for (int r = r0; r < r1; ++r)
@@ -121,9 +120,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(T* fac, const MacroInfo* 
 }
 
 __global__ void extract_kernel(const MacroInfo* info, int64_t e, const double* tm, Templates Tp,
-                               double bx, double by, double tau, double* dst) {
+                               double tau, double* dst) {
   const MacroInfo& mi = info[e];
-  EntryCtx c = make_ctx(mi, tm, Tp, bx, by, tau);
+  EntryCtx c = make_ctx(mi, tm, Tp, tau);
   const int N = mi.N;
   const int r = blockIdx.x;
   if (r >= N) return;
@@ -391,11 +390,16 @@ __global__ __launch_bounds__(64) void face_combine_kernel(int mode, const FaceIn
                                                           const double* __restrict__ tm, Templates Tp,
                                                           double tau, const double* __restrict__ lam,
                                                           const double* __restrict__ slots,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ out,
+                                                          const int32_t* __restrict__ skip) {
   __shared__ double v[(1 << kMaxLevel) * 4 + 1];
   __shared__ double lf[(1 << kMaxLevel) * 4 + 1];
   const FaceInfo& f = fi[blockIdx.x];
   const int nF = f.nF;
+  if (skip && skip[f.inst]) {   // converged instance: its slots are stale
+    for (int l = threadIdx.x; l < nF; l += 64) out[f.tr_off + l] = 0.0;
+    return;
+  }
   const LevelTemplates& L = Tp.lev[f.level];
   for (int l = threadIdx.x; l < nF; l += 64) {
     v[l] = mode == FACE_DINV ? 0.0 : slots[f.slot[0] + l] + slots[f.slot[1] + l];
@@ -463,8 +467,8 @@ __global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restri
                                                        const BndFaceInfo* __restrict__ bf,
                                                        const double* __restrict__ tm, Templates Tp,
                                                        const double* __restrict__ f,
-                                                       const double* __restrict__ lamD, double bx,
-                                                       double by, double tau, double* __restrict__ R) {
+                                                       const double* __restrict__ lamD, double tau,
+                                                       double* __restrict__ R) {
   extern __shared__ double x[];
   const MacroInfo& mi = info[blockIdx.x];
   const int N = mi.N, Q = mi.Q;
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restri
   __syncthreads();
   for (int k = 0; k < 3; ++k) {
     if (mi.bnd_face[k] >= 0)
-      edge_B(mi, k, tm, Tp, lamD + bf[mi.bnd_face[k]].lam_off, -1.0, bx, by, tau, xc);
+      edge_B(mi, k, tm, Tp, lamD + bf[mi.bnd_face[k]].lam_off, -1.0, tau, xc);
     __syncthreads();
   }
   const int32_t* en = ints(tm, Tp.lev[mi.level].edge_node);
@@ -506,8 +510,8 @@ __global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restri
 //   w:   kappa (E^x^T q_x + E^y^T q_y) - (a_x E^x + a_y E^y) u + tau Mb u,
 // E^d = |J| sum_k G[k][d] Ehat^k.  lam may be NULL (no trace term).
 __global__ __launch_bounds__(256) void local_residual_kernel(
-    const MacroInfo* __restrict__ info, const double* __restrict__ tm, Templates Tp, double bx,
-    double by, double tau, const double* __restrict__ R, const double* __restrict__ U,
+    const MacroInfo* __restrict__ info, const double* __restrict__ tm, Templates Tp,
+    double tau, const double* __restrict__ R, const double* __restrict__ U,
     const double* __restrict__ lam, double* __restrict__ out) {
   extern __shared__ double sh[];
   const MacroInfo& mi = info[blockIdx.x];
@@ -520,7 +524,7 @@ __global__ __launch_bounds__(256) void local_residual_kernel(
   __syncthreads();
   if (lam)
     for (int k = 0; k < 3; ++k) {
-      if (mi.tr_off[k] >= 0) edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], 1.0, bx, by, tau, xc);
+      if (mi.tr_off[k] >= 0) edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], 1.0, tau, xc);
       __syncthreads();
     }
   const double* Mh = tm + L.Mhat;
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(256) void local_residual_kernel(
     double av[3];
     av[0] = dJ * mqx - Exu;
     av[1] = dJ * mqy - Eyu;
-    av[2] = mi.kappa * (ExTqx + EyTqy) - (bx * Exu + by * Eyu) + tau * mbu;
+    av[2] = mi.kappa * (ExTqx + EyTqy) - (mi.bx * Exu + mi.by * Eyu) + tau * mbu;
     const int b = bidx[i];
     for (int f = 0; f < 3; ++f) {
       double r = R[mi.loc_off + f * Q + i] - av[f];
@@ -731,15 +735,21 @@ int dots_nblk(int64_t n) {
 
 // partial[c * nblk + blk] = sum over row chunk blk of V[c][i] w[i]: one
 // wavefront per (column, chunk), coalesced loads, a fixed-order reduction.
+// The vectors hold nseg independent segments of length n (one per coefficient
+// instance); block x handles chunk (x % nblk) of segment (x / nblk).
 __global__ __launch_bounds__(256) void dots_partial_kernel(const double* __restrict__ V, int64_t ld,
                                                            int ncols, const double* __restrict__ w,
                                                            int64_t n, double* __restrict__ partial) {
-  const int nblk = gridDim.x;
+  const int nblk_all = gridDim.x;
+  const int nblk = n > kDotChunk ? (int)((n + kDotChunk - 1) / kDotChunk) : 1;   // = dots_nblk(n)
+  const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+  const int nseg = nblk_all / nblk;
   const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= ncols) return;
-  const double* v = V + c * ld;
-  const int64_t i0 = int64_t(blockIdx.x) * kDotChunk;
+  const double* v = V + c * ld + int64_t(seg) * n;
+  w += int64_t(seg) * n;
+  const int64_t i0 = int64_t(blk) * kDotChunk;
   const int64_t i1 = i0 + kDotChunk < n ? i0 + kDotChunk : n;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int64_t i = i0 + lane;
@@ -751,32 +761,36 @@ __global__ __launch_bounds__(256) void dots_partial_kernel(const double* __restr
   }
   for (; i < i1; i += 64) a0 += v[i] * w[i];
   const double acc = wave_sum((a0 + a1) + (a2 + a3));
-  if (lane == 0) partial[c * nblk + blockIdx.x] = acc;
+  if (lane == 0) partial[(int64_t(c) * nseg + seg) * nblk + blk] = acc;
 }
 
+// out[c * nseg + seg] = sum over the chunks of (column c, segment seg)
 __global__ __launch_bounds__(64) void dots_final_kernel(const double* __restrict__ partial, int nblk,
                                                         double* __restrict__ out) {
   const int c = blockIdx.x;
   double acc = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) acc += partial[c * nblk + b];
+  for (int b = threadIdx.x; b < nblk; b += 64) acc += partial[int64_t(c) * nblk + b];
   acc = wave_sum(acc);
   if (threadIdx.x == 0) out[c] = acc;
 }
 
+// w += sign * V h with one coefficient vector per segment: h[c * nseg + seg]
 __global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ld, int ncols,
-                                const double* __restrict__ h, double* __restrict__ w, int64_t n,
-                                double sign) {
+                                const double* __restrict__ hh, double* __restrict__ w, int64_t n,
+                                int nseg, double sign) {
   int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n * nseg) return;
+  const int seg = (int)(i / n);
+  const double* h = hh + seg;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int c = 0;
   for (; c + 3 < ncols; c += 4) {
-    a0 += V[c * ld + i] * h[c];
-    a1 += V[(c + 1) * ld + i] * h[c + 1];
-    a2 += V[(c + 2) * ld + i] * h[c + 2];
-    a3 += V[(c + 3) * ld + i] * h[c + 3];
+    a0 += V[c * ld + i] * h[int64_t(c) * nseg];
+    a1 += V[(c + 1) * ld + i] * h[int64_t(c + 1) * nseg];
+    a2 += V[(c + 2) * ld + i] * h[int64_t(c + 2) * nseg];
+    a3 += V[(c + 3) * ld + i] * h[int64_t(c + 3) * nseg];
   }
-  for (; c < ncols; ++c) a0 += V[c * ld + i] * h[c];
+  for (; c < ncols; ++c) a0 += V[c * ld + i] * h[int64_t(c) * nseg];
   w[i] += sign * ((a0 + a1) + (a2 + a3));
 }
 
@@ -792,6 +806,16 @@ __global__ void scale_copy_kernel(double a, const double* __restrict__ x, double
   if (i < n) y[i] = a * x[i];
 }
 
+// y = alpha[seg] x per segment of length n
+__global__ void seg_scale_copy_kernel(const double* __restrict__ alpha, const double* __restrict__ x,
+                                      double* __restrict__ y, int64_t n, int nseg) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n * nseg) {
+    const double a = alpha[i / n];
+    y[i] = a == 0.0 ? 0.0 : a * x[i];   // masked segments become exact zeros
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -801,18 +825,18 @@ hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, hip
 }
 
 hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, const int32_t*,
-                           int64_t n, const double* tmpl, const Templates& T, double bx, double by,
-                           double tau, hipStream_t s) {
+                           int64_t n, const double* tmpl, const Templates& T, double tau,
+                           hipStream_t s) {
   int maxN = 0;
   for (int r = 0; r <= kMaxLevel; ++r)
     if (T.lev[r].present) maxN = maxN > T.lev[r].N ? maxN : T.lev[r].N;
   dim3 grid((unsigned)n, (unsigned)((maxN + 7) / 8));
   if (precision == 1)
     hipLaunchKernelGGL(assemble_kernel<float>, grid, dim3(256), 0, s, (float*)fac, info, tmpl, T,
-                       bx, by, tau);
+                       tau);
   else
     hipLaunchKernelGGL(assemble_kernel<double>, grid, dim3(256), 0, s, (double*)fac, info, tmpl, T,
-                       bx, by, tau);
+                       tau);
   return hipGetLastError();
 }
 
@@ -858,14 +882,14 @@ static int max_present_N(const Templates& T) {
 
 hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
                             const double* tmpl, const Templates& T, const double* f,
-                            const double* lamD, double bx, double by, double tau, double* R,
+                            const double* lamD, double tau, double* R,
                             hipStream_t s) {
   int maxP = 0;
   for (int r = 0; r <= kMaxLevel; ++r)
     if (T.lev[r].present && T.lev[r].P > maxP) maxP = T.lev[r].P;
   size_t lds = size_t(max_present_N(T) + 9 * maxP) * sizeof(double);
   hipLaunchKernelGGL(local_rhs_kernel, dim3((unsigned)n), dim3(64), lds, s, info, bf, tmpl, T, f,
-                     lamD, bx, by, tau, R);
+                     lamD, tau, R);
   return hipGetLastError();
 }
 
@@ -874,7 +898,7 @@ hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo*
   extern template void macro_solve_launch<T_, Q_>(int, const void*, const MacroInfo*,          \
                                                   const int32_t*, int64_t, int64_t,             \
                                                   size_t, const int32_t*, const double*,        \
-                                                  const Templates&, double, double, double,     \
+                                                  const Templates&, const int32_t*, double,      \
                                                   const double*, const double*, double*,        \
                                                   double*, hipStream_t);
 #define MS_DECL2(Q_) MS_DECL(double, Q_) MS_DECL(float, Q_)
@@ -886,7 +910,7 @@ MS_DECL2(58)
   extern template void macro_solve_t_launch<Q_>(int, const void*, const MacroInfo*,            \
                                                 const int32_t*, int64_t, int64_t,               \
                                                 size_t, const int32_t*, const double*,          \
-                                                const Templates&, double, double, double,       \
+                                                const Templates&, const int32_t*, double,        \
                                                 const double*, const double*, double*, double*, \
                                                 hipStream_t);
 MST_DECL(1) MST_DECL(2) MST_DECL(3) MST_DECL(5) MST_DECL(8) MST_DECL(16) MST_DECL(27) MST_DECL(58)
@@ -895,12 +919,12 @@ MST_DECL(1) MST_DECL(2) MST_DECL(3) MST_DECL(5) MST_DECL(8) MST_DECL(16) MST_DEC
 static hipError_t macro_solve_t_dispatch(int nq, int mode, const void* fac, const MacroInfo* info,
                                          const int32_t* order, int64_t base, int64_t n, size_t lds,
                                          const int32_t* perm, const double* tmpl,
-                                         const Templates& Tp, double bx, double by, double tau,
+                                         const Templates& Tp, const int32_t* skip, double tau,
                                          const double* mu, const double* xin, double* yout,
                                          double* slots, hipStream_t s) {
 #define MST_CASE(Q_)                                                                          \
   if (nq <= Q_) {                                                                             \
-    macro_solve_t_launch<Q_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, bx, by,    \
+    macro_solve_t_launch<Q_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, skip,      \
                              tau, mu, xin, yout, slots, s);                                   \
     return hipGetLastError();                                                                 \
   }
@@ -913,7 +937,7 @@ static hipError_t macro_solve_t_dispatch(int nq, int mode, const void* fac, cons
   extern template void macro_solve_mw_launch<T_, Q_>(int, const void*, const MacroInfo*,      \
                                                      const int32_t*, int64_t, int64_t, size_t,\
                                                      const int32_t*, const double*,           \
-                                                     const Templates&, double, double, double,\
+                                                     const Templates&, const int32_t*, double, \
                                                      const double*, const double*, double*,   \
                                                      double*, hipStream_t);
 MSW_DECL(double, 27) MSW_DECL(float, 27) MSW_DECL(double, 58) MSW_DECL(float, 58)
@@ -923,12 +947,12 @@ template <typename T>
 static hipError_t macro_solve_dispatch(int nq, int mode, const void* fac, const MacroInfo* info,
                                        const int32_t* order, int64_t base, int64_t n, size_t lds,
                                        const int32_t* perm, const double* tmpl,
-                                       const Templates& Tp, double bx, double by, double tau,
+                                       const Templates& Tp, const int32_t* skip, double tau,
                                        const double* lam, const double* xin, double* yout,
                                        double* slots, hipStream_t s) {
 #define MS_CASE(Q_)                                                                           \
   if (nq <= Q_) {                                                                             \
-    macro_solve_launch<T, Q_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, bx, by,   \
+    macro_solve_launch<T, Q_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, skip,     \
                               tau, lam, xin, yout, slots, s);                                 \
     return hipGetLastError();                                                                 \
   }
@@ -936,12 +960,12 @@ static hipError_t macro_solve_dispatch(int nq, int mode, const void* fac, const 
 #undef MS_CASE
   // large local sizes: four wavefronts per macro
   if (nq <= 27) {
-    macro_solve_mw_launch<T, 27>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, bx, by, tau,
+    macro_solve_mw_launch<T, 27>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, skip, tau,
                                  lam, xin, yout, slots, s);
     return hipGetLastError();
   }
   if (nq <= 58) {
-    macro_solve_mw_launch<T, 58>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, bx, by, tau,
+    macro_solve_mw_launch<T, 58>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, skip, tau,
                                  lam, xin, yout, slots, s);
     return hipGetLastError();
   }
@@ -953,7 +977,7 @@ static hipError_t macro_solve_dispatch(int nq, int mode, const void* fac, const 
 hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int precision,
                               const MacroInfo* info, const int32_t* order,
                               const SizeClass* classes, int n_classes, const int32_t* perm,
-                              const double* tmpl, const Templates& T, double bx, double by,
+                              const double* tmpl, const Templates& T, const int32_t* skip,
                               double tau, const double* lam, const double* xin, double* yout,
                               double* slots, hipStream_t s) {
   if (transpose && precision != 0) return hipErrorInvalidValue;
@@ -964,13 +988,13 @@ hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int prec
     hipError_t e;
     if (transpose)
       e = macro_solve_t_dispatch(nq, mode, fac, info, order, sc.start, sc.count, lds, perm, tmpl, T,
-                                 bx, by, tau, lam, xin, yout, slots, s);
+                                 skip, tau, lam, xin, yout, slots, s);
     else if (precision == 1)
       e = macro_solve_dispatch<float>(nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
-                                      tmpl, T, bx, by, tau, lam, xin, yout, slots, s);
+                                      tmpl, T, skip, tau, lam, xin, yout, slots, s);
     else
       e = macro_solve_dispatch<double>(nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
-                                       tmpl, T, bx, by, tau, lam, xin, yout, slots, s);
+                                       tmpl, T, skip, tau, lam, xin, yout, slots, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -978,20 +1002,20 @@ hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int prec
 
 hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const double* tmpl,
                                const Templates& T, double tau, const double* lam,
-                               const double* slots, double* out, hipStream_t s) {
+                               const double* slots, double* out, hipStream_t s,
+                               const int32_t* skip) {
   if (nf == 0) return hipSuccess;
   hipLaunchKernelGGL(face_combine_kernel, dim3((unsigned)nf), dim3(64), 0, s, mode, fi, tmpl, T,
-                     tau, lam, slots, out);
+                     tau, lam, slots, out, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double* tmpl,
-                                 const Templates& T, double bx, double by, double tau,
-                                 double* dst, hipStream_t s) {
+                                 const Templates& T, double tau, double* dst, hipStream_t s) {
   // the row count is the macro's N; launch max_N rows and let extra rows exit
   int maxN = max_present_N(T);
-  hipLaunchKernelGGL(extract_kernel, dim3((unsigned)maxN), dim3(256), 0, s, info, e, tmpl, T, bx,
-                     by, tau, dst);
+  hipLaunchKernelGGL(extract_kernel, dim3((unsigned)maxN), dim3(256), 0, s, info, e, tmpl, T,
+                     tau, dst);
   return hipGetLastError();
 }
 
@@ -1003,12 +1027,11 @@ static int max_present_P(const Templates& T) {
 }
 
 hipError_t launch_local_residual(const MacroInfo* info, int64_t n, const double* tmpl,
-                                 const Templates& T, double bx, double by, double tau,
-                                 const double* R, const double* U, const double* lam,
+                                 const Templates& T, double tau, const double* R, const double* U, const double* lam,
                                  double* out, hipStream_t s) {
   size_t lds = size_t(max_present_N(T) + 9 * max_present_P(T)) * sizeof(double);
   hipLaunchKernelGGL(local_residual_kernel, dim3((unsigned)n), dim3(256), lds, s, info, tmpl, T,
-                     bx, by, tau, R, U, lam, out);
+                     tau, R, U, lam, out);
   return hipGetLastError();
 }
 
@@ -1041,18 +1064,25 @@ hipError_t launch_mass(const MacroInfo* info, int64_t n, const double* tmpl, con
 }
 
 hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, int64_t n,
-                       double* partial, int nblk, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk, (ncols + 3) / 4), dim3(256), 0, s, V, ld, ncols,
-                     w, n, partial);
-  hipLaunchKernelGGL(dots_final_kernel, dim3(ncols), dim3(64), 0, s, partial, nblk, out);
+                       double* partial, int nblk, double* out, hipStream_t s, int nseg) {
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk * nseg, (ncols + 3) / 4), dim3(256), 0, s, V,
+                     ld, ncols, w, n, partial);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(ncols * nseg), dim3(64), 0, s, partial, nblk, out);
   return hipGetLastError();
 }
 
 hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double* h, double* w,
-                           int64_t n, double sign, hipStream_t s) {
+                           int64_t n, double sign, hipStream_t s, int nseg) {
   if (ncols == 0) return hipSuccess;
-  hipLaunchKernelGGL(gemv_sub_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, V, ld, ncols, h,
-                     w, n, sign);
+  hipLaunchKernelGGL(gemv_sub_kernel, dim3(blocks_for(n * nseg, 256)), dim3(256), 0, s, V, ld,
+                     ncols, h, w, n, nseg, sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_scale_copy(const double* alpha, const double* x, double* y, int64_t n, int nseg,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(seg_scale_copy_kernel, dim3(blocks_for(n * nseg, 256)), dim3(256), 0, s, alpha,
+                     x, y, n, nseg);
   return hipGetLastError();
 }
 

@@ -41,9 +41,9 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 //                                                         B^T z: c = (n_x, n_y, a.n - tau))
 struct EdgeCoef { double c0, c1, c2; };
 
-__device__ __forceinline__ EdgeCoef coef_B(const MacroInfo& mi, int k, double bx, double by, double tau) {
+__device__ __forceinline__ EdgeCoef coef_B(const MacroInfo& mi, int k, double tau) {
   const double nx = mi.nrm[2 * k], ny = mi.nrm[2 * k + 1];
-  return {nx, ny, bx * nx + by * ny - tau};
+  return {nx, ny, mi.bx * nx + mi.by * ny - tau};
 }
 __device__ __forceinline__ EdgeCoef coef_C(const MacroInfo& mi, int k, double tau) {
   return {mi.kappa * mi.nrm[2 * k], mi.kappa * mi.nrm[2 * k + 1], tau};
@@ -85,9 +85,9 @@ __device__ inline void edge_gather(const MacroInfo& mi, int k, const double* tm,
 
 // xc += sgn * B_k lam_F (step 1)
 __device__ inline void edge_B(const MacroInfo& mi, int k, const double* tm, const Templates& Tp,
-                              const double* lamF, double sgn, double bx, double by, double tau,
+                              const double* lamF, double sgn, double tau,
                               double* xc) {
-  edge_scatter(mi, k, tm, Tp, lamF, sgn, coef_B(mi, k, bx, by, tau), xc);
+  edge_scatter(mi, k, tm, Tp, lamF, sgn, coef_B(mi, k, tau), xc);
 }
 
 // out = C_k z (step 3)
@@ -113,12 +113,13 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
                                                          const int32_t* __restrict__ order, int64_t base,
                                                          const int32_t* __restrict__ perm_all,
                                                          const double* __restrict__ tm, Templates Tp,
-                                                         double bx, double by, double tau,
+                                                         const int32_t* __restrict__ skip, double tau,
                                                          const double* __restrict__ lam,
                                                          const double* xin, double* yout,
                                                          double* __restrict__ slots) {
   extern __shared__ double sm[];
   const MacroInfo& mi = info[order[base + blockIdx.x]];
+  if (skip && skip[mi.inst]) return;   // instance already converged: no work, outputs untouched
   const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P, lane = threadIdx.x;
   double* xc = sm;             // compact boundary rows of the right-hand side
   double* zc = sm + 3 * NBD;   // compact boundary rows of the solution
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
     __syncthreads();
     for (int k = 0; k < 3; ++k) {
       if (mi.tr_off[k] >= 0)
-        edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], mode == MODE_APPLY ? 1.0 : -1.0, bx, by, tau, xc);
+        edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], mode == MODE_APPLY ? 1.0 : -1.0, tau, xc);
       __syncthreads();
     }
   }
@@ -248,12 +249,13 @@ template <typename T, int NQ, int NW>
 __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
     int mode, const T* __restrict__ fac, const MacroInfo* __restrict__ info,
     const int32_t* __restrict__ order, int64_t base, const int32_t* __restrict__ perm_all,
-    const double* __restrict__ tm, Templates Tp, double bx, double by, double tau,
+    const double* __restrict__ tm, Templates Tp, const int32_t* __restrict__ skip, double tau,
     const double* __restrict__ lam, const double* xin, double* yout, double* __restrict__ slots) {
   constexpr int NL = (NQ + NW - 1) / NW;   // chunks per wavefront
   extern __shared__ double sm[];
   __shared__ double bc[2];
   const MacroInfo& mi = info[order[base + blockIdx.x]];
+  if (skip && skip[mi.inst]) return;   // instance already converged: no work, outputs untouched
   const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double* xc = sm;
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
     __syncthreads();
     for (int k = 0; k < 3; ++k) {
       if (mi.tr_off[k] >= 0)
-        edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], mode == MODE_APPLY ? 1.0 : -1.0, bx, by, tau, xc);
+        edge_B(mi, k, tm, Tp, lam + mi.tr_off[k], mode == MODE_APPLY ? 1.0 : -1.0, tau, xc);
       __syncthreads();
     }
   }
@@ -370,11 +372,11 @@ __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
 template <typename T, int NQ>
 void macro_solve_mw_launch(int mode, const void* fac, const MacroInfo* info, const int32_t* order,
                            int64_t base, int64_t n, size_t lds, const int32_t* perm,
-                           const double* tmpl, const Templates& Tp, double bx, double by,
+                           const double* tmpl, const Templates& Tp, const int32_t* skip,
                            double tau, const double* lam, const double* xin, double* yout,
                            double* slots, hipStream_t s) {
   hipLaunchKernelGGL((macro_solve_mw_kernel<T, NQ, 4>), dim3((unsigned)n), dim3(256), lds, s, mode,
-                     (const T*)fac, info, order, base, perm, tmpl, Tp, bx, by, tau, lam, xin, yout,
+                     (const T*)fac, info, order, base, perm, tmpl, Tp, skip, tau, lam, xin, yout,
                      slots);
 }
 
@@ -388,11 +390,12 @@ template <typename T, int NQ>
 __global__ __launch_bounds__(64) void macro_solve_t_kernel(
     int mode, const T* __restrict__ fac, const MacroInfo* __restrict__ info,
     const int32_t* __restrict__ order, int64_t base,
-    const int32_t* __restrict__ perm_all, const double* __restrict__ tm, Templates Tp, double bx,
-    double by, double tau, const double* __restrict__ mu, const double* xin, double* yout,
+    const int32_t* __restrict__ perm_all, const double* __restrict__ tm, Templates Tp,
+    const int32_t* __restrict__ skip, double tau, const double* __restrict__ mu, const double* xin, double* yout,
     double* __restrict__ slots) {
   extern __shared__ double sm[];
   const MacroInfo& mi = info[order[base + blockIdx.x]];
+  if (skip && skip[mi.inst]) return;   // instance already converged: no work, outputs untouched
   const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P, lane = threadIdx.x;
   double* xc = sm;
   double* zc = sm + 3 * NBD;
@@ -484,29 +487,29 @@ __global__ __launch_bounds__(64) void macro_solve_t_kernel(
     __syncthreads();
     for (int k = 0; k < 3; ++k)
       if (mi.tr_off[k] >= 0)
-        edge_gather(mi, k, tm, Tp, zc, coef_B(mi, k, bx, by, tau), slots + mi.slot_off[k]);
+        edge_gather(mi, k, tm, Tp, zc, coef_B(mi, k, tau), slots + mi.slot_off[k]);
   }
 }
 
 template <int NQ>
 void macro_solve_t_launch(int mode, const void* fac, const MacroInfo* info, const int32_t* order,
                           int64_t base, int64_t n, size_t lds, const int32_t* perm,
-                          const double* tmpl, const Templates& Tp, double bx, double by, double tau,
+                          const double* tmpl, const Templates& Tp, const int32_t* skip, double tau,
                           const double* mu, const double* xin, double* yout, double* slots,
                           hipStream_t s) {
   hipLaunchKernelGGL((macro_solve_t_kernel<double, NQ>), dim3((unsigned)n), dim3(64), lds, s, mode,
-                     (const double*)fac, info, order, base, perm, tmpl, Tp, bx, by, tau, mu, xin,
+                     (const double*)fac, info, order, base, perm, tmpl, Tp, skip, tau, mu, xin,
                      yout, slots);
 }
 
 template <typename T, int NQ>
 void macro_solve_launch(int mode, const void* fac, const MacroInfo* info, const int32_t* order,
                         int64_t base, int64_t n, size_t lds, const int32_t* perm,
-                        const double* tmpl, const Templates& Tp, double bx, double by, double tau,
+                        const double* tmpl, const Templates& Tp, const int32_t* skip, double tau,
                         const double* lam, const double* xin, double* yout, double* slots,
                         hipStream_t s) {
   hipLaunchKernelGGL((macro_solve_kernel<T, NQ>), dim3((unsigned)n), dim3(64), lds, s, mode,
-                     (const T*)fac, info, order, base, perm, tmpl, Tp, bx, by, tau, lam, xin, yout,
+                     (const T*)fac, info, order, base, perm, tmpl, Tp, skip, tau, lam, xin, yout,
                      slots);
 }
 

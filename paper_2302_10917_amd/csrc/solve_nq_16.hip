@@ -4,12 +4,12 @@
 
 namespace mhdg {
 template void macro_solve_launch<double, 16>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<float, 16>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_t_launch<16>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 }  // namespace mhdg

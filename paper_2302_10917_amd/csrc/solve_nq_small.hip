@@ -4,48 +4,48 @@
 
 namespace mhdg {
 template void macro_solve_launch<double, 1>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<float, 1>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<double, 2>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<float, 2>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<double, 3>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<float, 3>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<double, 5>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<float, 5>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<double, 8>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_launch<float, 8>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_t_launch<1>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_t_launch<2>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_t_launch<3>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_t_launch<5>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 template void macro_solve_t_launch<8>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
-    const int32_t*, const double*, const Templates&, double, double, double, const double*,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
 }  // namespace mhdg

@@ -26,6 +26,7 @@ ABI_SYMBOLS = [
     "mhdg_local_matrix", "mhdg_apply_trace_operator", "mhdg_local_solve", "mhdg_rhs",
     "mhdg_solve", "mhdg_recover_local", "mhdg_destroy", "mhdg_last_error",
     "mhdg_status_string", "mhdg_profile", "mhdg_mass_apply", "mhdg_adjoint",
+    "mhdg_set_instances", "mhdg_factor_local_batched",
 ]
 
 
@@ -41,7 +42,8 @@ class Sizes(ctypes.Structure):
                 ("n_nodes", ctypes.c_int64), ("n_local", ctypes.c_int64),
                 ("n_bnd_points", ctypes.c_int64), ("p", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("max_local", ctypes.c_int64),
-                ("factor_ws_bytes", ctypes.c_size_t), ("solve_ws_bytes", ctypes.c_size_t)]
+                ("factor_ws_bytes", ctypes.c_size_t), ("solve_ws_bytes", ctypes.c_size_t),
+                ("n_instances", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -88,11 +90,13 @@ def load_library(path: str = LIB_PATH):
         "mhdg_query": [P, I32, I32, ctypes.POINTER(Sizes)],
         "mhdg_sample_points": [P, P, P],
         "mhdg_factor_local": [P, P, D, D, D, I32, P, SZ, P],
+        "mhdg_factor_local_batched": [P, P, P, D, I32, P, SZ, P],
+        "mhdg_set_instances": [P, I32],
         "mhdg_local_matrix": [P, I64, P, P],
         "mhdg_apply_trace_operator": [P, P, P, I32, P],
         "mhdg_local_solve": [P, P, P, I32, P],
         "mhdg_rhs": [P, P, P, P, I32, P],
-        "mhdg_solve": [P, P, P, ctypes.POINTER(SolveOpts), P, P, SZ, ctypes.POINTER(SolveInfo), P],
+        "mhdg_solve": [P, P, P, ctypes.POINTER(SolveOpts), P, P, SZ, P, P],
         "mhdg_recover_local": [P, P, P, P, P],
         "mhdg_profile": [P, I32, ctypes.POINTER(KernelTimes)],
         "mhdg_mass_apply": [P, P, P, P],
@@ -171,6 +175,17 @@ class MacroMesh:
         self._check(self._lib.mhdg_query(self.h, precision, restart, ctypes.byref(s)), "query")
         return s
 
+    def set_instances(self, n_inst: int):
+        """n_inst coefficient instances in one handle (instance-major vectors)."""
+        self._check(self._lib.mhdg_set_instances(self.h, int(n_inst)), "set_instances")
+        self.sizes = self.query()
+        self.factor_ws = None
+        self.solve_ws = None
+
+    @property
+    def n_instances(self) -> int:
+        return int(self.sizes.n_instances)
+
     def sample_points(self):
         s = self.sizes
         node = np.zeros((s.n_nodes, 2))
@@ -188,13 +203,25 @@ class MacroMesh:
         kap = torch.as_tensor(kappa, dtype=torch.float64, device="cuda")
         if kap.ndim == 0:
             kap = kap.expand(s.n_macro)
-        kap = kap.contiguous()
+        kap = kap.reshape(-1).contiguous()
+        if kap.numel() != s.n_macro:
+            raise ValueError(f"kappa has {kap.numel()} values, expected {s.n_macro}")
         self._kappa = kap
         self.precision = precision
-        self._check(self._lib.mhdg_factor_local(self.h, _ptr(kap), float(beta[0]), float(beta[1]),
-                                                float(tau), precision, _ptr(self.factor_ws),
-                                                self.factor_ws.numel(), _stream(stream)),
-                    "factor_local")
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        if b.size == 2:
+            self._check(self._lib.mhdg_factor_local(self.h, _ptr(kap), float(b.flat[0]),
+                                                    float(b.flat[1]), float(tau), precision,
+                                                    _ptr(self.factor_ws), self.factor_ws.numel(),
+                                                    _stream(stream)), "factor_local")
+            return
+        if b.size != 2 * s.n_instances:
+            raise ValueError(f"beta must hold 2 or 2 x {s.n_instances} values")
+        self._check(self._lib.mhdg_factor_local_batched(self.h, _ptr(kap), b.ctypes.data,
+                                                        float(tau), precision,
+                                                        _ptr(self.factor_ws),
+                                                        self.factor_ws.numel(), _stream(stream)),
+                    "factor_local_batched")
 
     def local_matrix(self, e, out, stream=None):
         self._check(self._lib.mhdg_local_matrix(self.h, int(e), _ptr(out), _stream(stream)),
@@ -221,14 +248,15 @@ class MacroMesh:
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1 if zero_guess else 0,
                          int(max_outer), float(inner_rtol))
-        info = SolveInfo()
+        infos = (SolveInfo * max(1, s.n_instances))()
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
-                                  _ptr(self.solve_ws), self.solve_ws.numel(), ctypes.byref(info),
-                                  _stream(stream))
-        self.last_solve_info = info.as_dict()
+                                  _ptr(self.solve_ws), self.solve_ws.numel(),
+                                  ctypes.cast(infos, ctypes.c_void_p), _stream(stream))
+        self.last_solve_info = infos[0].as_dict()
+        self.last_solve_infos = [i.as_dict() for i in infos]
         if check:
             self._check(st, "solve")
-        return info
+        return infos[0]
 
     def mass_apply(self, v, out, stream=None):
         self._check(self._lib.mhdg_mass_apply(self.h, _ptr(v), _ptr(out), _stream(stream)),

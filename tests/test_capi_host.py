@@ -137,3 +137,30 @@ def test_gauss_legendre_points_match_library_quadrature():
     t = np.sort(bnd[:3, 0])
     expect = np.sort(0.5 * (1 + np.array([-math.sqrt(0.6), 0.0, math.sqrt(0.6)])))
     assert np.allclose(t, expect, atol=1e-15)
+
+
+def test_instances_replicate_sizes_and_points():
+    """n_inst coefficient instances: every count is n_inst times the single
+    mesh's, the sampling points repeat per instance, the factor workspace
+    grows n_inst-fold (up to block padding) and bad counts are rejected."""
+    xy, tri = inputs.structured_mesh(3, jitter=0.1, seed=7)
+    r = inputs.random_levels(len(tri), (0, 1, 2), seed=3)
+    m = mhdg.MacroMesh(xy, tri, r, 2)
+    one = m.query()
+    node1, bnd1 = m.sample_points()
+    m.set_instances(4)
+    s = m.sizes
+    assert s.n_instances == 4
+    for f in ("n_macro", "n_faces", "n_interior_faces", "n_trace", "n_nodes", "n_local",
+              "n_bnd_points"):
+        assert getattr(s, f) == 4 * getattr(one, f), f
+    assert s.max_local == one.max_local
+    node, bnd = m.sample_points()
+    assert np.array_equal(node, np.tile(node1, (4, 1)))
+    assert np.array_equal(bnd, np.tile(bnd1, (4, 1)))
+    assert 4 * one.factor_ws_bytes - 4 * 2 ** 20 <= s.factor_ws_bytes <= 4 * one.factor_ws_bytes
+    lib = _lib()
+    for bad in (0, -1, 2 ** 30):
+        assert lib.mhdg_set_instances(m.h, bad) == 1
+    m.set_instances(1)
+    assert m.query().n_trace == one.n_trace
