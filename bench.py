@@ -78,11 +78,11 @@ def apply_bytes(m, elem_bytes=8, levels=None, p=None) -> float:
 
 
 def lu_flops(w, s):
-    """(2/3) N_K^3 summed over macros."""
+    """(2/3) N_K^3 summed over macros (and coefficient instances)."""
     if np.ndim(w["r"]) == 0:
         return s.n_macro * (2.0 / 3.0) * float(s.max_local) ** 3
     P = (2 ** np.asarray(w["r"], dtype=np.int64)) * w["p"]
-    return float(np.sum((2.0 / 3.0) * (3.0 * (P + 1) * (P + 2) / 2) ** 3))
+    return s.n_instances * float(np.sum((2.0 / 3.0) * (3.0 * (P + 1) * (P + 2) / 2) ** 3))
 
 
 def cpu_baseline(xy, tri, w, lam_seed=1, n_sample=16, budget_s=15.0):
@@ -155,6 +155,8 @@ def main():
                          "one at a time with single-instance handles (the plain form) and "
                          "report their time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel shapes (no autotuning before the warmup)")
     ap.add_argument("--max-iter", type=int, default=20000,
                     help="GMRES iteration cap (a short cap is for counter runs only)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -227,6 +229,11 @@ def main():
         infos.append(info.as_dict())
         inst_infos.append(m.last_solve_infos)
 
+    tune = None
+    if not args.no_autotune:
+        m.factor_local(kappa, beta_arg, 1.0, precision=prec)
+        tune = m.autotune()
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -341,6 +348,12 @@ def main():
     avg_ms = ams["ms"] / max(ams["count"], 1)
     nbytes = apply_bytes(m, 4 if prec == mhdg.MHDG_FP32 else 8,
                          None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"])
+    if n_inst > 1:
+        # converged instances are masked out of later launches: count the
+        # instances each launch actually processed (GMRES applies + the
+        # true-residual apply of every instance)
+        inst_launches = sum(x["n_applies"] - 2 for si in inst_infos for x in si)
+        nbytes = nbytes / n_inst * inst_launches / max(ams["count"], 1)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     lu = kt["lu"]
     result = {
@@ -386,6 +399,7 @@ def main():
         "lu_tflops": lu_flops(w, s) / (lu["ms"] / max(lu["count"], 1) * 1e-3) / 1e12
         if lu["count"] else None,
         "u_max_err_vs_exact": u_err,
+        "autotune": tune,
     }
     if not args.no_cpu_baseline:
         wc = dict(w)

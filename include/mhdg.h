@@ -86,7 +86,12 @@ typedef enum {
 /* flags for apply_trace_operator / local_solve */
 enum {
   MHDG_PRECONDITION = 1,      /* return D^-1 S lambda instead of S lambda      */
-  MHDG_TRANSPOSE = 2          /* use A_K^-T (adjoint solves)                   */
+  MHDG_TRANSPOSE = 2,         /* use A_K^-T (adjoint solves)                   */
+  MHDG_GRAPH = 4              /* apply: replay a hipGraph of the launches (one
+                                 per size class for all instances, then the
+                                 face combine), captured on first use for this
+                                 (lam, out, flags) and kept until the next
+                                 factor_local or set_instances              */
 };
 
 typedef struct mhdg_mesh mhdg_mesh;
@@ -115,6 +120,8 @@ typedef struct {
   int32_t max_outer;          /* reduced-precision factors: refinement steps (0: 30) */
   double inner_rtol;          /* reduced-precision factors: inner GMRES relative
                                  tolerance per refinement step (0: 1e-5)      */
+  int32_t graph;              /* 1: every GMRES apply replays one captured
+                                 hipGraph (see MHDG_GRAPH); 0: plain launches */
 } mhdg_solve_opts;
 
 typedef struct {
@@ -188,7 +195,10 @@ mhdg_status mhdg_local_matrix(mhdg_mesh* mesh, int64_t e, double* dst, void* str
 
 /* out = S lam, or D^-1 S lam with MHDG_PRECONDITION; with MHDG_TRANSPOSE the
  * transposed operator S^T lam (or D^-1 S^T lam; D is symmetric), FP64
- * factors only.  lam, out: device f64[n_trace], must not alias.
+ * factors only.  lam, out: device f64[n_trace], must not alias.  With
+ * MHDG_GRAPH the launches run as one replay of a captured hipGraph; the
+ * result is the same bit for bit.  (Steps 1-4 of section 6.1's matrix-free
+ * apply: gather, local solve, lift, face sum.)
  * Errors: STATE before factor_local. */
 mhdg_status mhdg_apply_trace_operator(mhdg_mesh* mesh, const double* lam, double* out,
                                       int32_t flags, void* stream);
@@ -252,12 +262,54 @@ mhdg_status mhdg_adjoint(mhdg_mesh* mesh, const double* lam, const double* qu, c
                          double* dJ_dkappa, double* dJ_dbeta, void* ws, size_t ws_bytes,
                          mhdg_solve_info* info, void* stream);
 
+/* Kernel shapes per size class (all macros of one local size N_K).  The
+ * factorisation has two forms: LU variant 1 factors 8- or 16-column panels
+ * held in registers and updates the trailing matrix after each; variant 2
+ * blocks 64-column panels (8-column register sub-panels, a blocked
+ * triangular solve and one rank-64 MFMA update per panel), reading the
+ * trailing matrix 4-8 times less often.  The per-macro triangular solves
+ * (steps 1-3) run on one wavefront per macro (solve variant 1), or on four
+ * or eight wavefronts per macro (variants 2, 3) that split each column. */
+#define MHDG_MAX_CLASSES 8
+enum { MHDG_TUNE_LU = 1, MHDG_TUNE_SOLVE = 2 };
+typedef struct {
+  int32_t n_classes;
+  int32_t N[MHDG_MAX_CLASSES];
+  int64_t count[MHDG_MAX_CLASSES];
+  int32_t lu_variant[MHDG_MAX_CLASSES];     /* chosen (1 or 2)                 */
+  int32_t solve_variant[MHDG_MAX_CLASSES];  /* chosen (1, 2 or 3)              */
+  double lu_ms[MHDG_MAX_CLASSES][3];        /* [class][variant]: LU of up to 512
+                                               macros of the class; 0 = not tried */
+  double apply_ms[MHDG_MAX_CLASSES][4];     /* [class][variant]: one apply solve
+                                               of the whole class; 0 = not tried */
+} mhdg_tune_report;
+
+/* Autotuner: times every available LU variant (flags & MHDG_TUNE_LU) on
+ * the handle's own assembled matrices and every solve variant
+ * (flags & MHDG_TUNE_SOLVE) on its factors, per size class, keeps the
+ * fastest, refactors with the chosen LU variants (the factor state stays
+ * valid) and remembers the choice for this process: later factor_local
+ * calls of any handle with the same (N_K, precision, class size rounded up
+ * to a power of two) start from it.  Needs factor_local first; synchronises;
+ * costs about two factorisations.  out (host) may be NULL.
+ * Errors: STATE, INVALID_ARG (more than MHDG_MAX_CLASSES classes), SINGULAR, HIP. */
+mhdg_status mhdg_autotune(mhdg_mesh* mesh, int32_t flags, mhdg_tune_report* out, void* stream);
+
+/* Fix the variants of the size class with local size N (0 = the default
+ * rule: LU variant 1 for N <= 256, else 2; solve variant 1 for N <= 1024,
+ * else 2).  Takes effect at the next factor_local (LU) or apply (solves).
+ * Errors: INVALID_ARG (no class of that size, variant not available). */
+mhdg_status mhdg_set_kernel_variant(mhdg_mesh* mesh, int32_t N, int32_t lu_variant,
+                                    int32_t solve_variant);
+
 /* Per-kernel timing of the hot path, for measurement.  enable = 1 clears
  * the counters and brackets every later launch of the listed kernels with
  * HIP events recorded on the launch stream; enable = 0 stops recording,
  * waits for the recorded events and fills *out (may be NULL).  Index:
  * 0 assemble, 1 lu, 2 macro solve of apply_trace_operator (steps 1-3),
- * 3 face combine (step 4), 4 macro solve of rhs/recover/local_solve. */
+ * 3 face combine (step 4), 4 macro solve of rhs/recover/local_solve.  An
+ * apply replayed from a captured graph (MHDG_GRAPH) is timed whole under
+ * index 2. */
 typedef struct {
   int32_t count[5];
   double ms[5];

@@ -57,9 +57,28 @@ struct mhdg_mesh {
   // kernel timing (mhdg_profile)
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+  // captured applies (every size class and instance, then the face combine)
+  // keyed by their vector pointers and flags; valid until the next
+  // factor_local / set_instances
+  struct ApplyGraph {
+    const double* lam;
+    double* out;
+    int32_t flags;
+    const int32_t* skip;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<ApplyGraph> graphs;
+  hipStream_t cap = nullptr;   // private stream the graphs are captured on
+  void drop_graphs() {
+    for (auto& a : graphs) { (void)hipGraphExecDestroy(a.x); (void)hipGraphDestroy(a.g); }
+    graphs.clear();
+  }
   ~mhdg_mesh() {
     for (auto& v : ev)
       for (auto& p : v) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
   }
 };
 
@@ -431,6 +450,7 @@ struct Gm {
   int nseg = 1, nblk = 1;
   int32_t op_flags = MHDG_PRECONDITION;   // MHDG_TRANSPOSE added for adjoint solves
   double *V = nullptr, *wv = nullptr, *rv = nullptr, *tv = nullptr, *fh = nullptr, *pf = nullptr;
+  double* xin = nullptr;                  // fixed apply input of the captured graph
   double *partial = nullptr, *hdev = nullptr, *ydev = nullptr, *adev = nullptr;
   int32_t* skip = nullptr;                // per-segment flags: 1 = take no part in applies
   std::vector<int> seg_applies;           // applies each segment took part in
@@ -518,7 +538,12 @@ mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, doub
     int j = 0;
     for (; j < R && it < max_iter; ++j) {
       ++it;
-      if ((st = apply_op(M, G.V + j * ld, G.wv, G.op_flags, G.skip, s))) return st;
+      const double* vj = G.V + j * ld;
+      if (G.op_flags & MHDG_GRAPH) {   // the graph reads a fixed input vector
+        HIP_TRY(M, hipMemcpyAsync(G.xin, vj, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+        vj = G.xin;
+      }
+      if ((st = apply_op(M, vj, G.wv, G.op_flags, G.skip, s))) return st;
       ++applies;
       for (int q = 0; q < ns; ++q) G.seg_applies[q] += !skip[q];
       for (int pass = 0; pass < 2; ++pass) {
@@ -620,7 +645,8 @@ mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
   G.tv = (double*)(w + vb * (R + 5));
   G.dl = (double*)(w + vb * (R + 6));
   G.cl = (double*)(w + vb * (R + 7));
-  size_t off = align_up(vb * (R + 8));
+  G.xin = (double*)(w + vb * (R + 8));
+  size_t off = align_up(vb * (R + 9));
   G.nblk = dots_nblk(G.n);
   G.partial = (double*)(w + off);
   off += align_up(size_t(G.nblk) * G.nseg * (R + 2) * sizeof(double));
@@ -634,6 +660,19 @@ mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
   off += align_up(size_t(G.nseg) * 4);
   G.U = (double*)(w + off);
   return MHDG_OK;
+}
+
+// Kernel choices of earlier autotuning runs in this process, per (local
+// size, precision, log2 of the class size): later handles with the same
+// shapes start from them.
+std::map<std::array<int, 3>, std::pair<int, int>>& tune_cache() {
+  static std::map<std::array<int, 3>, std::pair<int, int>> m;
+  return m;
+}
+std::array<int, 3> tune_key(const SizeClass& c, int precision) {
+  int b = 0;
+  while ((int64_t(1) << b) < c.count) ++b;
+  return {c.N, precision, b};
 }
 
 }  // namespace
@@ -856,6 +895,7 @@ mhdg_status mhdg_set_instances(mhdg_mesh* M, int32_t n_inst) {
   M->factored = false;
   M->have_rhs = false;
   M->ws = nullptr;
+  M->drop_graphs();
   M->n_inst = n_inst;
   M->n_macro = o.n_macro * n_inst;
   M->n_faces = o.n_faces * n_inst;
@@ -1049,12 +1089,18 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   hipStream_t s = (hipStream_t)stream;
   M->factored = false;
   M->have_rhs = false;
+  M->drop_graphs();
   M->precision = precision;
   M->tau = tau;
   M->ws = (char*)ws;
   M->ws_bytes = ws_bytes;
   for (auto& mi : M->macros) { mi.bx = beta[2 * mi.inst]; mi.by = beta[2 * mi.inst + 1]; }
   M->L = factor_layout(M, precision);
+  for (auto& c : M->classes)
+    if (!c.lu_var && !c.solve_var) {
+      auto it = tune_cache().find(tune_key(c, precision));
+      if (it != tune_cache().end()) { c.lu_var = it->second.first; c.solve_var = it->second.second; }
+    }
   FactorLayout& L = M->L;
   char* w = M->ws;
   HIP_TRY(M, hipMemcpyAsync(w + L.meta, M->macros.data(), M->macros.size() * sizeof(MacroInfo),
@@ -1098,6 +1144,131 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   return MHDG_OK;
 }
 
+mhdg_status mhdg_set_kernel_variant(mhdg_mesh* M, int32_t N, int32_t lu_variant,
+                                    int32_t solve_variant) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if ((lu_variant && !lu_variant_ok(lu_variant, N)) ||
+      (solve_variant && !solve_variant_ok(solve_variant, N)))
+    return fail(M, MHDG_ERR_INVALID_ARG, "set_kernel_variant: variant not available for this size");
+  bool found = false;
+  for (auto* cl : {&M->classes, &M->one.classes})
+    for (auto& c : *cl)
+      if (c.N == N) { c.lu_var = lu_variant; c.solve_var = solve_variant; found = true; }
+  if (!found) return fail(M, MHDG_ERR_INVALID_ARG, "set_kernel_variant: no macros of that size");
+  M->drop_graphs();
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->factored) return fail(M, MHDG_ERR_STATE, "autotune: call factor_local first");
+  if (M->classes.size() > MHDG_MAX_CLASSES)
+    return fail(M, MHDG_ERR_INVALID_ARG, "autotune: too many size classes");
+  hipStream_t s = (hipStream_t)stream;
+  FactorLayout& L = M->L;
+  char* w = M->ws;
+  MacroInfo* info = (MacroInfo*)(w + L.meta);
+  const double* tm = (const double*)(w + L.tmpl);
+  const int32_t* order = (const int32_t*)(w + L.order);
+  hipEvent_t b, e;
+  HIP_TRY(M, hipEventCreate(&b));
+  HIP_TRY(M, hipEventCreate(&e));
+  struct Ev {
+    hipEvent_t b, e;
+    ~Ev() { (void)hipEventDestroy(b); (void)hipEventDestroy(e); }
+  } ev{b, e};
+  mhdg_tune_report rep{};
+  rep.n_classes = (int32_t)M->classes.size();
+  auto elapsed = [&](float& ms) -> mhdg_status {
+    HIP_TRY(M, hipEventSynchronize(e));
+    HIP_TRY(M, hipEventElapsedTime(&ms, b, e));
+    return MHDG_OK;
+  };
+  mhdg_status st;
+  for (size_t ci = 0; ci < M->classes.size(); ++ci) {
+    SizeClass& c = M->classes[ci];
+    rep.N[ci] = c.N;
+    rep.count[ci] = c.count;
+    if (flags & MHDG_TUNE_LU) {
+      // a subset of the class large enough to fill the device; the factors
+      // it leaves are rebuilt below
+      SizeClass sub = c;
+      sub.count = std::min<int64_t>(c.count, 512);
+      int best = 0;
+      double best_ms = 0;
+      for (int v = LU_PANEL; v <= LU_BLOCKED; ++v) {
+        if (!lu_variant_ok(v, c.N)) continue;
+        sub.lu_var = v;
+        SizeClass one_m = sub;
+        one_m.count = 1;   // untimed: loads the kernel
+        HIP_TRY(M, launch_lu(w + L.factors, M->precision, info, order, &one_m, 1,
+                             (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+        HIP_TRY(M, launch_assemble(w + L.factors, M->precision, info, nullptr, M->n_macro, tm,
+                                   M->T, M->tau, s));
+        HIP_TRY(M, hipEventRecord(b, s));
+        HIP_TRY(M, launch_lu(w + L.factors, M->precision, info, order, &sub, 1,
+                             (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+        HIP_TRY(M, hipEventRecord(e, s));
+        float ms = 0;
+        if ((st = elapsed(ms))) return st;
+        rep.lu_ms[ci][v] = ms;
+        if (!best || ms < best_ms) { best = v; best_ms = ms; }
+      }
+      c.lu_var = best;
+    }
+    rep.lu_variant[ci] = c.lu_var ? c.lu_var : default_lu_variant(c.N);
+  }
+  // valid factors with the chosen LU variants
+  HIP_TRY(M, launch_assemble(w + L.factors, M->precision, info, nullptr, M->n_macro, tm, M->T,
+                             M->tau, s));
+  HIP_TRY(M, launch_lu(w + L.factors, M->precision, info, order, M->classes.data(),
+                       (int)M->classes.size(), (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+  {
+    std::vector<int32_t> stv(M->n_macro);
+    HIP_TRY(M, hipMemcpyAsync(stv.data(), w + L.status, stv.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(M, hipStreamSynchronize(s));
+    for (int32_t v : stv)
+      if (v) return fail(M, MHDG_ERR_SINGULAR, "autotune: zero pivot while refactoring");
+  }
+  // apply solves: every class with each candidate, trace input zero (timing only)
+  double* lam0 = (double*)(w + L.work1);
+  HIP_TRY(M, hipMemsetAsync(lam0, 0, size_t(M->n_local) * sizeof(double), s));
+  for (size_t ci = 0; ci < M->classes.size(); ++ci) {
+    SizeClass& c = M->classes[ci];
+    if (flags & MHDG_TUNE_SOLVE) {
+      SizeClass sub = c;
+      int best = 0;
+      double best_ms = 0;
+      for (int v = SOLVE_WAVE; v <= SOLVE_MW8; ++v) {
+        if (!solve_variant_ok(v, c.N)) continue;
+        sub.solve_var = v;
+        HIP_TRY(M, launch_macro_solve(MODE_APPLY, 0, w + L.factors, M->precision, info, order, &sub,
+                                      1, (const int32_t*)(w + L.perm), tm, M->T, nullptr, M->tau,
+                                      lam0, nullptr, nullptr, (double*)(w + L.slots), s));
+        HIP_TRY(M, hipEventRecord(b, s));
+        for (int r = 0; r < 3; ++r)
+          HIP_TRY(M, launch_macro_solve(MODE_APPLY, 0, w + L.factors, M->precision, info, order,
+                                        &sub, 1, (const int32_t*)(w + L.perm), tm, M->T, nullptr,
+                                        M->tau, lam0, nullptr, nullptr, (double*)(w + L.slots), s));
+        HIP_TRY(M, hipEventRecord(e, s));
+        float ms = 0;
+        if ((st = elapsed(ms))) return st;
+        rep.apply_ms[ci][v] = ms / 3;
+        if (!best || ms < best_ms) { best = v; best_ms = ms; }
+      }
+      c.solve_var = best;
+    }
+    rep.solve_variant[ci] = c.solve_var ? c.solve_var : default_solve_variant(c.N);
+    tune_cache()[tune_key(c, M->precision)] = {c.lu_var, c.solve_var};
+    for (auto& oc : M->one.classes)
+      if (oc.N == c.N) { oc.lu_var = c.lu_var; oc.solve_var = c.solve_var; }
+  }
+  M->drop_graphs();
+  if (out) *out = rep;
+  return MHDG_OK;
+}
+
 mhdg_status mhdg_local_matrix(mhdg_mesh* M, int64_t e, double* dst, void* stream) {
   if (!M || !dst || e < 0 || e >= M->n_macro) return MHDG_ERR_INVALID_ARG;
   if (!M->ws) return fail(M, MHDG_ERR_STATE, "local_matrix: call factor_local first");
@@ -1123,9 +1294,53 @@ static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const 
 }
 
 namespace {
-// The trace operator with an optional per-instance mask (see gmres).
+mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
+                           const int32_t* skip, hipStream_t s);
+
+// The trace operator with an optional per-instance mask (see gmres).  With
+// MHDG_GRAPH the launches (one per size class, each covering every
+// instance, then the face combine) are captured once per (lam, out, flags,
+// skip) into a hipGraph and replayed as one launch.
 mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
                      const int32_t* skip, hipStream_t s) {
+  if (!(flags & MHDG_GRAPH)) return apply_launches(M, lam, out, flags, skip, s);
+  const int32_t f = flags & ~MHDG_GRAPH;
+  for (auto& a : M->graphs)
+    if (a.lam == lam && a.out == out && a.flags == f && a.skip == skip) {
+      ProfScope ps(M, 2, s);   // the whole replayed apply
+      HIP_TRY(M, hipGraphLaunch(a.x, s));
+      return MHDG_OK;
+    }
+  if (!M->cap) HIP_TRY(M, hipStreamCreateWithFlags(&M->cap, hipStreamNonBlocking));
+  if (M->graphs.size() >= 16) {   // bounded cache: drop the oldest
+    (void)hipGraphExecDestroy(M->graphs.front().x);
+    (void)hipGraphDestroy(M->graphs.front().g);
+    M->graphs.erase(M->graphs.begin());
+  }
+  // capture only records the launches; the graph runs on s when launched
+  HIP_TRY(M, hipStreamBeginCapture(M->cap, hipStreamCaptureModeThreadLocal));
+  const bool prof = M->prof;
+  M->prof = false;   // no event records inside the graph
+  mhdg_status st = apply_launches(M, lam, out, f, skip, M->cap);
+  M->prof = prof;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(M->cap, &g);
+  if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+  if (e != hipSuccess) return fail(M, MHDG_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(M, MHDG_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  M->graphs.push_back({lam, out, f, skip, g, x});
+  ProfScope ps(M, 2, s);
+  HIP_TRY(M, hipGraphLaunch(x, s));
+  return MHDG_OK;
+}
+
+mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
+                           const int32_t* skip, hipStream_t s) {
   const int tr = (flags & MHDG_TRANSPOSE) ? 1 : 0;
   mhdg_status st = run_macro_solve(M, MODE_APPLY, tr, lam, nullptr, nullptr, s, skip);
   if (st) return st;
@@ -1248,7 +1463,7 @@ static size_t solve_bytes_impl(const mhdg_mesh* M, int R) {
   const size_t ns = size_t(M->n_inst);
   const size_t vb = align_up(size_t(M->n_trace) * sizeof(double));
   const size_t nblk = size_t(dots_nblk(M->n_trace / M->n_inst));
-  return align_up(vb * (R + 8)) + align_up(nblk * ns * size_t(R + 2) * sizeof(double)) +
+  return align_up(vb * (R + 9)) + align_up(nblk * ns * size_t(R + 2) * sizeof(double)) +
          2 * align_up(size_t(R + 2) * ns * 8) + align_up(ns * 8) + align_up(ns * 4) +
          align_up(size_t(M->n_local) * sizeof(double));
 }
@@ -1271,6 +1486,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   auto t0 = std::chrono::steady_clock::now();
   Gm G;
   carve(M, ws, R, G);
+  if (o->graph) G.op_flags |= MHDG_GRAPH;
   mhdg_solve_info inf{};
   mhdg_status st;
   FactorLayout& L = M->L;
@@ -1438,7 +1654,7 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
   const int64_t n = M->n_trace;
   Gm G;
   carve(M, ws, o->restart, G);
-  G.op_flags = MHDG_PRECONDITION | MHDG_TRANSPOSE;
+  G.op_flags = MHDG_PRECONDITION | MHDG_TRANSPOSE | (o->graph ? MHDG_GRAPH : 0);
   FactorLayout& L = M->L;
   char* fw = M->ws;
   const double* tm = (const double*)(fw + L.tmpl);

@@ -83,7 +83,21 @@ struct FactorLayout {
 struct SizeClass {
   int N, P;
   int64_t start, count;
+  int32_t lu_var = 0;      // LuVariant, 0 = default rule
+  int32_t solve_var = 0;   // SolveVariant, 0 = default rule
 };
+
+// Kernel variants the autotuner chooses between, per size class.
+enum LuVariant { LU_DEFAULT = 0, LU_PANEL = 1, LU_BLOCKED = 2 };
+enum SolveVariant { SOLVE_DEFAULT = 0, SOLVE_WAVE = 1, SOLVE_MW4 = 2, SOLVE_MW8 = 3 };
+int default_lu_variant(int N);
+int default_solve_variant(int N);
+bool lu_variant_ok(int v, int N);
+bool solve_variant_ok(int v, int N);
+
+template <typename T>
+hipError_t lu_blocked_class(T* fac, const MacroInfo* info, const int32_t* order,
+                            const SizeClass& c, int32_t* perm, int32_t* status, hipStream_t s);
 
 enum SolveMode { MODE_APPLY = 0, MODE_RHS = 1, MODE_RECOVER = 2, MODE_LOCAL = 3 };
 

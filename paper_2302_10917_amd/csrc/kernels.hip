@@ -15,11 +15,10 @@
 //   vector ops    deterministic two-pass dot products and Krylov updates
 #include "internal.h"
 #include "macro_solve.h"
+#include "mfma.h"
 
 namespace mhdg {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -130,25 +129,6 @@ __global__ void extract_kernel(const MacroInfo* info, int64_t e, const double* t
 }
 
 // ------------------------------------------------------------------ LU
-template <typename T> struct Mfma;
-// 16x16x4 MFMA tiles: lane l holds A[l%16][l/16] and B[l/16][l%16]; the
-// accumulator element v of lane l is D[drow(l/16, v)][l%16] (row order
-// measured on gfx950 for each instruction).
-template <> struct Mfma<double> {
-  typedef d4 acc;
-  static __device__ __forceinline__ acc run(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int drow(int g, int v) { return g + 4 * v; }
-};
-template <> struct Mfma<float> {
-  typedef f4 acc;
-  static __device__ __forceinline__ acc run(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int drow(int g, int v) { return 4 * g + v; }
-};
-
 // One workgroup of NT threads factors one macro's N x N row-major block in
 // place: PA = LU with partial pivoting (largest |a|, ties to the smallest
 // row).  Panels of NB columns are held in registers (thread t owns rows
@@ -843,6 +823,8 @@ hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, cons
 template <typename T>
 static hipError_t lu_class(T* fac, const MacroInfo* info, const int32_t* order, const SizeClass& c,
                            int32_t* perm, int32_t* status, hipStream_t s) {
+  const int v = c.lu_var ? c.lu_var : default_lu_variant(c.N);
+  if (v == LU_BLOCKED) return lu_blocked_class(fac, info, order, c, perm, status, s);
   const dim3 g((unsigned)c.count);
   if (c.N <= 256)
     hipLaunchKernelGGL((lu_kernel<T, 256, 1, 16>), g, dim3(256), 0, s, fac, info, order, c.start, perm, status);
@@ -933,44 +915,57 @@ static hipError_t macro_solve_t_dispatch(int nq, int mode, const void* fac, cons
   return hipErrorInvalidValue;
 }
 
-#define MSW_DECL(T_, Q_)                                                                      \
-  extern template void macro_solve_mw_launch<T_, Q_>(int, const void*, const MacroInfo*,      \
+#define MSW_DECL(T_, Q_, W_)                                                                  \
+  extern template void macro_solve_mw_launch<T_, Q_, W_>(int, const void*, const MacroInfo*,  \
                                                      const int32_t*, int64_t, int64_t, size_t,\
                                                      const int32_t*, const double*,           \
                                                      const Templates&, const int32_t*, double, \
                                                      const double*, const double*, double*,   \
                                                      double*, hipStream_t);
-MSW_DECL(double, 27) MSW_DECL(float, 27) MSW_DECL(double, 58) MSW_DECL(float, 58)
+MSW_DECL(double, 27, 4) MSW_DECL(float, 27, 4) MSW_DECL(double, 58, 4) MSW_DECL(float, 58, 4)
+MSW_DECL(double, 27, 8) MSW_DECL(float, 27, 8) MSW_DECL(double, 58, 8) MSW_DECL(float, 58, 8)
+MSW_DECL(double, 16, 4) MSW_DECL(float, 16, 4)
 #undef MSW_DECL
 
 template <typename T>
-static hipError_t macro_solve_dispatch(int nq, int mode, const void* fac, const MacroInfo* info,
-                                       const int32_t* order, int64_t base, int64_t n, size_t lds,
-                                       const int32_t* perm, const double* tmpl,
-                                       const Templates& Tp, const int32_t* skip, double tau,
-                                       const double* lam, const double* xin, double* yout,
-                                       double* slots, hipStream_t s) {
+static hipError_t macro_solve_dispatch(int variant, int nq, int mode, const void* fac,
+                                       const MacroInfo* info, const int32_t* order, int64_t base,
+                                       int64_t n, size_t lds, const int32_t* perm,
+                                       const double* tmpl, const Templates& Tp,
+                                       const int32_t* skip, double tau, const double* lam,
+                                       const double* xin, double* yout, double* slots,
+                                       hipStream_t s) {
+  if (variant == SOLVE_WAVE) {
 #define MS_CASE(Q_)                                                                           \
   if (nq <= Q_) {                                                                             \
     macro_solve_launch<T, Q_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, skip,     \
                               tau, lam, xin, yout, slots, s);                                 \
     return hipGetLastError();                                                                 \
   }
-  MS_CASE(1) MS_CASE(2) MS_CASE(3) MS_CASE(5) MS_CASE(8) MS_CASE(16)
+    MS_CASE(1) MS_CASE(2) MS_CASE(3) MS_CASE(5) MS_CASE(8) MS_CASE(16) MS_CASE(27) MS_CASE(58)
 #undef MS_CASE
-  // large local sizes: four wavefronts per macro
-  if (nq <= 27) {
-    macro_solve_mw_launch<T, 27>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, skip, tau,
-                                 lam, xin, yout, slots, s);
-    return hipGetLastError();
+    return hipErrorInvalidValue;
   }
-  if (nq <= 58) {
-    macro_solve_mw_launch<T, 58>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, skip, tau,
-                                 lam, xin, yout, slots, s);
-    return hipGetLastError();
+#define MW_CASE(Q_, W_)                                                                       \
+  if (nq <= Q_) {                                                                             \
+    macro_solve_mw_launch<T, Q_, W_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp,    \
+                                     skip, tau, lam, xin, yout, slots, s);                    \
+    return hipGetLastError();                                                                 \
   }
+  if (variant == SOLVE_MW4) { MW_CASE(16, 4) MW_CASE(27, 4) MW_CASE(58, 4) }
+  if (variant == SOLVE_MW8) { MW_CASE(27, 8) MW_CASE(58, 8) }
+#undef MW_CASE
   return hipErrorInvalidValue;
 }
+
+int default_solve_variant(int N) { return N <= 1024 ? SOLVE_WAVE : SOLVE_MW4; }
+bool solve_variant_ok(int v, int N) {
+  if (N > 58 * 64) return false;
+  if (v == SOLVE_WAVE || v == SOLVE_MW4) return true;
+  return v == SOLVE_MW8 && N > 16 * 64;
+}
+int default_lu_variant(int N) { return N <= 256 ? LU_PANEL : LU_BLOCKED; }
+bool lu_variant_ok(int v, int N) { return N <= 4096 && (v == LU_PANEL || v == LU_BLOCKED); }
 
 // One launch per size class, each with the register-block count of its
 // local size (NQ = ceil(N/64)) and LDS for its boundary vectors.
@@ -986,15 +981,16 @@ hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int prec
     const size_t lds = size_t(18) * sc.P * sizeof(double);
     const int nq = (sc.N + 63) / 64;
     hipError_t e;
+    const int v = sc.solve_var ? sc.solve_var : default_solve_variant(sc.N);
     if (transpose)
       e = macro_solve_t_dispatch(nq, mode, fac, info, order, sc.start, sc.count, lds, perm, tmpl, T,
                                  skip, tau, lam, xin, yout, slots, s);
     else if (precision == 1)
-      e = macro_solve_dispatch<float>(nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
+      e = macro_solve_dispatch<float>(v, nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
                                       tmpl, T, skip, tau, lam, xin, yout, slots, s);
     else
-      e = macro_solve_dispatch<double>(nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
-                                       tmpl, T, skip, tau, lam, xin, yout, slots, s);
+      e = macro_solve_dispatch<double>(v, nq, mode, fac, info, order, sc.start, sc.count, lds,
+                                       perm, tmpl, T, skip, tau, lam, xin, yout, slots, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -369,13 +369,13 @@ __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
   }
 }
 
-template <typename T, int NQ>
+template <typename T, int NQ, int NW>
 void macro_solve_mw_launch(int mode, const void* fac, const MacroInfo* info, const int32_t* order,
                            int64_t base, int64_t n, size_t lds, const int32_t* perm,
                            const double* tmpl, const Templates& Tp, const int32_t* skip,
                            double tau, const double* lam, const double* xin, double* yout,
                            double* slots, hipStream_t s) {
-  hipLaunchKernelGGL((macro_solve_mw_kernel<T, NQ, 4>), dim3((unsigned)n), dim3(256), lds, s, mode,
+  hipLaunchKernelGGL((macro_solve_mw_kernel<T, NQ, NW>), dim3((unsigned)n), dim3(64 * NW), lds, s, mode,
                      (const T*)fac, info, order, base, perm, tmpl, Tp, skip, tau, lam, xin, yout,
                      slots);
 }

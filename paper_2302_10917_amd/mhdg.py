@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmhdg.so")
 
 MHDG_FP64, MHDG_FP32 = 0, 1
-MHDG_PRECONDITION, MHDG_TRANSPOSE = 1, 2
+MHDG_PRECONDITION, MHDG_TRANSPOSE, MHDG_GRAPH = 1, 2, 4
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "MESH", 3: "SINGULAR", 4: "NOT_CONVERGED",
           5: "WORKSPACE", 6: "HIP", 7: "STATE"}
@@ -26,8 +26,11 @@ ABI_SYMBOLS = [
     "mhdg_local_matrix", "mhdg_apply_trace_operator", "mhdg_local_solve", "mhdg_rhs",
     "mhdg_solve", "mhdg_recover_local", "mhdg_destroy", "mhdg_last_error",
     "mhdg_status_string", "mhdg_profile", "mhdg_mass_apply", "mhdg_adjoint",
-    "mhdg_set_instances", "mhdg_factor_local_batched",
+    "mhdg_set_instances", "mhdg_factor_local_batched", "mhdg_autotune",
+    "mhdg_set_kernel_variant",
 ]
+MHDG_TUNE_LU, MHDG_TUNE_SOLVE = 1, 2
+MAX_CLASSES = 8
 
 
 class MhdgError(RuntimeError):
@@ -49,7 +52,8 @@ class Sizes(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("zero_guess", ctypes.c_int32),
-                ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+                ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+                ("graph", ctypes.c_int32)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -59,6 +63,24 @@ class KernelTimes(ctypes.Structure):
     def as_dict(self):
         return {n: {"count": int(self.count[i]), "ms": float(self.ms[i])}
                 for i, n in enumerate(self.NAMES)}
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("N", ctypes.c_int32 * 8),
+                ("count", ctypes.c_int64 * 8), ("lu_variant", ctypes.c_int32 * 8),
+                ("solve_variant", ctypes.c_int32 * 8), ("lu_ms", (ctypes.c_double * 3) * 8),
+                ("apply_ms", (ctypes.c_double * 4) * 8)]
+
+    def as_list(self):
+        out = []
+        for i in range(self.n_classes):
+            out.append({"N": int(self.N[i]), "count": int(self.count[i]),
+                        "lu_variant": int(self.lu_variant[i]),
+                        "solve_variant": int(self.solve_variant[i]),
+                        "lu_ms": {v: float(self.lu_ms[i][v]) for v in (1, 2) if self.lu_ms[i][v]},
+                        "apply_ms": {v: float(self.apply_ms[i][v]) for v in (1, 2, 3)
+                                     if self.apply_ms[i][v]}})
+        return out
 
 
 class SolveInfo(ctypes.Structure):
@@ -92,6 +114,8 @@ def load_library(path: str = LIB_PATH):
         "mhdg_factor_local": [P, P, D, D, D, I32, P, SZ, P],
         "mhdg_factor_local_batched": [P, P, P, D, I32, P, SZ, P],
         "mhdg_set_instances": [P, I32],
+        "mhdg_autotune": [P, I32, ctypes.POINTER(TuneReport), P],
+        "mhdg_set_kernel_variant": [P, I32, I32, I32],
         "mhdg_local_matrix": [P, I64, P, P],
         "mhdg_apply_trace_operator": [P, P, P, I32, P],
         "mhdg_local_solve": [P, P, P, I32, P],
@@ -240,14 +264,14 @@ class MacroMesh:
                                        _stream(stream)), "rhs")
 
     def solve(self, f_nodes, g_bnd, lam, rtol=1e-10, restart=30, max_iter=10000, zero_guess=True,
-              stream=None, check=True, inner_rtol=0.0, max_outer=0):
+              stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True):
         import torch
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1 if zero_guess else 0,
-                         int(max_outer), float(inner_rtol))
+                         int(max_outer), float(inner_rtol), 1 if graph else 0)
         infos = (SolveInfo * max(1, s.n_instances))()
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
                                   _ptr(self.solve_ws), self.solve_ws.numel(),
@@ -263,13 +287,13 @@ class MacroMesh:
                     "mass_apply")
 
     def adjoint(self, lam, qu, dJ_dU, psi_lam, psi_U, dJ_dkappa, dJ_dbeta, rtol=1e-12,
-                restart=300, max_iter=20000, stream=None):
+                restart=300, max_iter=20000, stream=None, graph=True):
         import torch
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
-        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0)
+        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0)
         info = SolveInfo()
         self._check(self._lib.mhdg_adjoint(self.h, _ptr(lam), _ptr(qu), _ptr(dJ_dU),
                                            ctypes.byref(opts), _ptr(psi_lam), _ptr(psi_U),
@@ -278,6 +302,18 @@ class MacroMesh:
                                            _stream(stream)), "adjoint")
         self.last_adjoint_info = info.as_dict()
         return info
+
+    def autotune(self, flags=MHDG_TUNE_LU | MHDG_TUNE_SOLVE, stream=None):
+        """Time the kernel variants per size class on this handle's data and
+        keep the fastest; returns the per-class report."""
+        rep = TuneReport()
+        self._check(self._lib.mhdg_autotune(self.h, int(flags), ctypes.byref(rep),
+                                            _stream(stream)), "autotune")
+        return rep.as_list()
+
+    def set_kernel_variant(self, N, lu_variant=0, solve_variant=0):
+        self._check(self._lib.mhdg_set_kernel_variant(self.h, int(N), int(lu_variant),
+                                                      int(solve_variant)), "set_kernel_variant")
 
     def profile(self, enable: bool):
         """Start (True) or stop (False) per-kernel event timing; stop returns

@@ -164,3 +164,22 @@ def test_instances_replicate_sizes_and_points():
         assert lib.mhdg_set_instances(m.h, bad) == 1
     m.set_instances(1)
     assert m.query().n_trace == one.n_trace
+
+
+def test_kernel_variant_validation():
+    """Variant choice is checked on the host: unknown sizes and variants that
+    do not exist for a size are rejected before any launch."""
+    xy, tri = inputs.structured_mesh(2)
+    m = mhdg.MacroMesh(xy, tri, 3, 3)          # N = 975
+    N = m.sizes.max_local
+    m.set_kernel_variant(N, 2, 2)
+    m.set_kernel_variant(N, 0, 0)
+    with pytest.raises(mhdg.MhdgError):
+        m.set_kernel_variant(N + 1, 1, 1)       # no class of that size
+    with pytest.raises(mhdg.MhdgError):
+        m.set_kernel_variant(N, 3, 1)           # no such LU variant
+    with pytest.raises(mhdg.MhdgError):
+        m.set_kernel_variant(N, 1, 3)           # eight wavefronts need N > 1024
+    lib = _lib()
+    rep = mhdg.TuneReport()
+    assert lib.mhdg_autotune(m.h, 3, ctypes.byref(rep), None) == 7   # before factor_local

@@ -1,0 +1,128 @@
+"""GPU parity of every kernel variant the autotuner can pick.
+
+Each (LU variant, solve variant) available for a local size must factor and
+solve to the FP64 bound against the oracle (local solves and applies to a
+relative 1e-10), and the autotuner must leave a valid factor state whose
+solve still matches the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import hdg
+from paper_2302_10917_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_10917_amd import mhdg  # noqa: E402
+
+DEV = "cuda"
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# (n, r, p) -> N_K: 45 (r1 p2), 273 (r2 p3), 975 (r3 p3), 1683 (r3 p4), 3675 (r4 p3)
+SHAPES = {"N45": (2, 1, 2), "N273": (2, 2, 3), "N975": (2, 3, 3), "N1683": (1, 3, 4),
+          "N3675": (1, 4, 3)}
+COMBOS = [(lu, sv) for lu in (1, 2) for sv in (1, 2, 3)]
+
+
+def _setup(shape):
+    n, r, p = SHAPES[shape]
+    xy, tri = inputs.structured_mesh(n, jitter=0.08 if n > 1 else 0.0, seed=7)
+    kap = 0.2 * inputs.lognormal_kappa(len(tri), 0.3, seed=9)
+    beta = (1.0, -0.6)
+    return xy, tri, r, p, kap, beta
+
+
+@pytest.fixture(scope="module", params=list(SHAPES))
+def shape(request):
+    print(f"\n[variants {request.param}]", flush=True)
+    xy, tri, r, p, kap, beta = _setup(request.param)
+    orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0)
+    return request.param, (xy, tri, r, p, kap, beta), orc
+
+
+@pytest.mark.parametrize("lu,sv", COMBOS)
+def test_variant_matches_oracle(shape, lu, sv):
+    name, (xy, tri, r, p, kap, beta), orc = shape
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    N = m.sizes.max_local
+    if sv == 3 and N <= 1024:
+        with pytest.raises(mhdg.MhdgError):
+            m.set_kernel_variant(N, lu, sv)
+        return
+    m.set_kernel_variant(N, lu, sv)
+    m.factor_local(gpu(kap), beta, 1.0)
+    topo = orc.topo
+    x = inputs.random_vector(int(topo.local_off[-1]), seed=11)
+    y = torch.empty(len(x), dtype=torch.float64, device=DEV)
+    m.local_solve(gpu(x), y)
+    yh = host(y)
+    for e in range(topo.n_macro):
+        lo, hi = topo.local_off[e], topo.local_off[e + 1]
+        assert rel(yh[lo:hi], orc.local_solve(e, x[lo:hi])) <= 1e-10, (name, lu, sv, e)
+    if topo.n_trace:
+        lam = inputs.random_vector(topo.n_trace, seed=1)
+        out = torch.empty(topo.n_trace, dtype=torch.float64, device=DEV)
+        m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_PRECONDITION)
+        assert rel(host(out), orc.apply(lam, precondition=True)) <= 1e-10, (name, lu, sv)
+
+
+def test_fp32_blocked_lu_is_close():
+    """FP32 factors from the blocked LU: the operator within single-precision
+    accuracy of the FP64 oracle (the same bound as the panel LU's)."""
+    xy, tri, r, p, kap, beta = _setup("N975")
+    orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0)
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    m.set_kernel_variant(m.sizes.max_local, 2, 1)
+    m.factor_local(gpu(kap), beta, 1.0, precision=mhdg.MHDG_FP32)
+    lam = inputs.random_vector(orc.topo.n_trace, seed=1)
+    out = torch.empty(orc.topo.n_trace, dtype=torch.float64, device=DEV)
+    m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_PRECONDITION)
+    assert rel(host(out), orc.apply(lam, precondition=True)) <= 1e-3
+
+
+def test_autotune_keeps_a_valid_factor_state():
+    xy, tri = inputs.structured_mesh(3, jitter=0.1, seed=7)
+    r = inputs.random_levels(len(tri), (0, 1, 2, 3), seed=3)
+    kap = 0.3 * inputs.lognormal_kappa(len(tri), 0.3, seed=9)
+    beta = (0.8, 0.4)
+    orc = hdg.Oracle(xy, tri, r, 2, kap, beta, 1.0)
+    m = mhdg.MacroMesh(xy, tri, r, 2)
+    m.factor_local(gpu(kap), beta, 1.0)
+    rep = m.autotune()
+    assert len(rep) == len(set(int(x) for x in np.unique(r)))
+    for c in rep:
+        assert c["lu_variant"] in (1, 2) and c["solve_variant"] in (1, 2, 3)
+        assert all(t > 0 for t in c["lu_ms"].values()) and len(c["lu_ms"]) == 2
+        assert c["apply_ms"][c["solve_variant"]] == min(c["apply_ms"].values())
+    ex = inputs.exp_sin(0.3, beta)
+    node, bnd = m.sample_points()
+    f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+    fo, go = orc.sample(ex)
+    lam_o, U_o, _ = orc.solve(fo, go)
+    lam = torch.zeros(m.sizes.n_trace, dtype=torch.float64, device=DEV)
+    m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=5000)
+    assert rel(host(lam), lam_o) <= 1e-10
+    # a second handle of the same shapes starts from the tuned choice
+    m2 = mhdg.MacroMesh(xy, tri, r, 2)
+    m2.factor_local(gpu(kap), beta, 1.0)
+    lam2 = torch.zeros(m.sizes.n_trace, dtype=torch.float64, device=DEV)
+    m2.solve(f, g, lam2, rtol=1e-13, restart=300, max_iter=5000)
+    assert torch.equal(lam, lam2)
