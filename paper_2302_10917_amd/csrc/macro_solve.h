@@ -241,10 +241,14 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
 
 // Per-macro solve for large local sizes: a workgroup of NW wavefronts per
 // macro, 64-row chunk qq owned by wavefront qq % NW (register slot qq / NW).
-// Each column's solved entry is computed by the owner of its chunk and
-// broadcast through a double-buffered LDS slot with one barrier per column;
-// every wavefront then streams its own chunks of that column, so NW times
-// more loads are in flight per macro than with one wavefront.
+// Every wavefront also keeps its own copy of the current diagonal chunk (the
+// 64 rows holding the entries being solved) and updates it with the same
+// operations in the same order, so each solved entry is available in every
+// wavefront by a lane read, without a workgroup barrier per column.  The
+// chunk owner publishes the next diagonal chunk through LDS once per 64
+// columns.  Each wavefront streams, per column, its own chunks below (above,
+// for the backward sweep) the diagonal chunk plus the diagonal rows (read by
+// all NW wavefronts, mostly from cache).
 template <typename T, int NQ, int NW>
 __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
     int mode, const T* __restrict__ fac, const MacroInfo* __restrict__ info,
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
     const double* __restrict__ lam, const double* xin, double* yout, double* __restrict__ slots) {
   constexpr int NL = (NQ + NW - 1) / NW;   // chunks per wavefront
   extern __shared__ double sm[];
-  __shared__ double bc[2];
+  __shared__ double dch[2][64];            // published diagonal chunk (double-buffered)
   const MacroInfo& mi = info[order[base + blockIdx.x]];
   if (skip && skip[mi.inst]) return;   // instance already converged: no work, outputs untouched
   const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P;
@@ -290,60 +294,77 @@ __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
     y[t] = v;
   }
   const int nq = (N + 63) / 64;
+  // the owner of chunk q hands its current values to every wavefront
+  auto publish = [&](int q) -> double {
+    if (wv == q % NW) {
+#pragma unroll
+      for (int t = 0; t < NL; ++t)
+        if (t == q / NW) dch[q & 1][lane] = y[t];
+    }
+    __syncthreads();
+    return dch[q & 1][lane];
+  };
+  auto retire = [&](int q, double d) {
+    if (wv == q % NW) {
+#pragma unroll
+      for (int t = 0; t < NL; ++t)
+        if (t == q / NW) y[t] = d;
+    }
+  };
   // ---- forward substitution (unit lower factor)
-  for (int j = 0; j < N; ++j) {
-    const int q = j >> 6, jj = j & 63;
-    if (wv == q % NW) {
-      double v = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    double d = publish(q);
+    const int rd = 64 * q + lane;
+    const int jend = min(64, N - 64 * q);
+    for (int jj = 0; jj < jend; ++jj) {
+      const int j = 64 * q + jj;
+      const double yj = readlane_d(d, jj);
+      const T* col = A + size_t(j) * N;
+      const int rdc = rd > j ? (rd < N ? rd : N - 1) : j;   // in-bounds address for every lane
+      double a[NL];
 #pragma unroll
-      for (int t = 0; t < NL; ++t)
-        if (t == q / NW) v = readlane_d(y[t], jj);
-      if (lane == 0) bc[j & 1] = v;
-    }
-    __syncthreads();
-    const double yj = bc[j & 1];
-    const T* col = A + size_t(j) * N;
-#pragma unroll
-    for (int t = 0; t < NL; ++t) {
-      const int qq = wv + NW * t;
-      if (qq >= q && qq < nq) {
+      for (int t = 0; t < NL; ++t) {
+        const int qq = wv + NW * t;
         const int r = lane + 64 * qq;
-        int rr = r;
-        if (qq == q) rr = r > j ? r : j + 1;
-        rr = rr < N ? rr : N - 1;
-        const double a = (double)col[rr];
-        y[t] -= ((r > j && r < N) ? a : 0.0) * yj;
+        a[t] = (qq > q && qq < nq) ? (double)col[r < N ? r : N - 1] : 0.0;
+      }
+      const double ad = (double)col[rdc];
+      d -= ((rd > j && rd < N) ? ad : 0.0) * yj;
+#pragma unroll
+      for (int t = 0; t < NL; ++t) {
+        const int qq = wv + NW * t;
+        const int r = lane + 64 * qq;
+        if (qq > q && qq < nq) y[t] -= (r < N ? a[t] : 0.0) * yj;
       }
     }
+    retire(q, d);
   }
+  // every wavefront has read the last forward chunk before it is republished
+  __syncthreads();
   // ---- backward substitution (upper factor)
-  for (int j = N - 1; j >= 0; --j) {
-    const int q = j >> 6, jj = j & 63;
-    const T* col = A + size_t(j) * N;
-    if (wv == q % NW) {
-      double v = 0.0;
+  for (int q = nq - 1; q >= 0; --q) {
+    double d = publish(q);
+    const int rd = 64 * q + lane;
+    const int jst = min(63, N - 1 - 64 * q);
+    for (int jj = jst; jj >= 0; --jj) {
+      const int j = 64 * q + jj;
+      const T* col = A + size_t(j) * N;
+      double a[NL];
 #pragma unroll
-      for (int t = 0; t < NL; ++t)
-        if (t == q / NW) v = readlane_d(y[t], jj);
-      v /= (double)col[j];
+      for (int t = 0; t < NL; ++t) {
+        const int qq = wv + NW * t;
+        a[t] = qq < q ? (double)col[lane + 64 * qq] : 0.0;
+      }
+      const double cd = (double)col[rd < j ? rd : j];   // lanes above the diagonal read U[j][j]
+      const double zj = readlane_d(d, jj) / readlane_d(cd, jj);
+      d = lane == jj ? zj : d - (rd < j ? cd : 0.0) * zj;
 #pragma unroll
-      for (int t = 0; t < NL; ++t)
-        if (t == q / NW && lane == jj) y[t] = v;
-      if (lane == 0) bc[j & 1] = v;
-    }
-    __syncthreads();
-    const double zj = bc[j & 1];
-#pragma unroll
-    for (int t = 0; t < NL; ++t) {
-      const int qq = wv + NW * t;
-      if (qq <= q) {
-        const int r = lane + 64 * qq;
-        int rr = r;
-        if (qq == q) rr = r < j ? r : (j > 0 ? j - 1 : 0);
-        const double a = (double)col[rr];
-        y[t] -= (r < j ? a : 0.0) * zj;
+      for (int t = 0; t < NL; ++t) {
+        const int qq = wv + NW * t;
+        if (qq < q) y[t] -= a[t] * zj;
       }
     }
+    retire(q, d);
   }
   // ---- outputs
   if (mode == MODE_RECOVER || mode == MODE_LOCAL) {
