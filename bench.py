@@ -85,6 +85,21 @@ def lu_flops(w, s):
     return s.n_instances * float(np.sum((2.0 / 3.0) * (3.0 * (P + 1) * (P + 2) / 2) ** 3))
 
 
+def measured_traffic(workload):
+    """HBM bytes per apply launch from the committed PMC summary
+    (profiles/traffic.json), or None when there is none for this workload or
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[workload]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec
+
+
 def cpu_baseline(xy, tri, w, lam_seed=1, n_sample=16, budget_s=15.0):
     """The oracle (scipy LU + lu_solve per macro) applying the trace operator
     on a bounded sample of macros, scaled to the full mesh."""
@@ -355,6 +370,7 @@ def main():
         inst_launches = sum(x["n_applies"] - 2 for si in inst_infos for x in si)
         nbytes = nbytes / n_inst * inst_launches / max(ams["count"], 1)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload)
     lu = kt["lu"]
     result = {
         "metric": METRIC,
@@ -379,7 +395,12 @@ def main():
                    "form": ("batched_fp64" if n_inst > 1 else "plain_fp64")
                    if prec == mhdg.MHDG_FP64 else "fp32_factors_fp64_ir"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["traffic_bytes_per_launch"] / 1e9 if traffic else None,
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-kernel calibrated; see profiles/)",
+                     "traffic_vs_algorithmic": traffic["traffic_bytes_per_launch"] / nbytes
+                     if traffic else None,
                      "kernel": ("macro_solve_kernel<double>" if prec == mhdg.MHDG_FP64
                                 else "macro_solve_kernel<float>") + " (apply steps 1-3)",
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,

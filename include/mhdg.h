@@ -197,8 +197,9 @@ mhdg_status mhdg_local_matrix(mhdg_mesh* mesh, int64_t e, double* dst, void* str
  * transposed operator S^T lam (or D^-1 S^T lam; D is symmetric), FP64
  * factors only.  lam, out: device f64[n_trace], must not alias.  With
  * MHDG_GRAPH the launches run as one replay of a captured hipGraph; the
- * result is the same bit for bit.  (Steps 1-4 of section 6.1's matrix-free
- * apply: gather, local solve, lift, face sum.)
+ * result is the same bit for bit.  (Steps 1-4 of the matrix-free method of
+ * section 3.3.2: gather and lift, local solve, restriction, face sum; the
+ * preconditioned step 4 is the D^-1 variant of section 6.1.)
  * Errors: STATE before factor_local. */
 mhdg_status mhdg_apply_trace_operator(mhdg_mesh* mesh, const double* lam, double* out,
                                       int32_t flags, void* stream);
