@@ -36,6 +36,10 @@ WORKLOADS = {
     # name: n, r, p, kappa, beta, manufactured solution, factor precision
     "plain_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5), sol="exp_sin",
                                        precision="fp64"),
+    # folded form (same mesh and data): T_K = C_K A_K^-1 B_K stored per macro after the LU,
+    # GMRES applies read L_K^2 = 75^2 values per macro instead of the 975^2 factors
+    "folded_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                        sol="exp_sin", precision="fp64", form="folded"),
     "plain_fp64_8macro_r1_p2": dict(n=2, r=1, p=2, kappa=1.0, beta=(1.0, 1.0), sol="sin_sin",
                                     precision="fp64"),
     # precision configuration: same mesh, kappa = 1e-3, FP32 factors + FP64 refinement
@@ -75,6 +79,19 @@ def apply_bytes(m, elem_bytes=8, levels=None, p=None) -> float:
         P = (2 ** np.asarray(levels, dtype=np.int64)) * p
         n_e = 3.0 * (P + 1) * (P + 2) / 2
     return float(np.sum(elem_bytes * n_e * n_e + 4.0 * n_e)) + 32.0 * s.n_trace
+
+
+def fold_bytes(tri, r, p, n_trace):
+    """Algorithmic bytes of one folded apply: every T_K once (8 L_K^2, L_K = the
+    macro's interior-face trace dofs, n_F = 2^r p + 1 per interior edge), the
+    gathered trace and the written slots (2 x 8 x 2 n_trace)."""
+    tri = np.asarray(tri)
+    e = np.sort(np.stack([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]], axis=1), axis=2)
+    keys = e[..., 0].astype(np.int64) * (tri.max() + 1) + e[..., 1]
+    _, inv, cnt = np.unique(keys.ravel(), return_inverse=True, return_counts=True)
+    interior = (cnt[inv] == 2).reshape(-1, 3).sum(axis=1)
+    L = interior * (2 ** int(r) * p + 1)
+    return 8.0 * float(np.sum(L.astype(np.float64) ** 2)) + 32.0 * n_trace
 
 
 def lu_flops(w, s):
@@ -193,6 +210,7 @@ def main():
         args.rtol = w.get("rtol", 1e-10)
     if w.get("form") == "adjoint":
         return bench_adjoint(args, w)
+    folded = w.get("form") == "folded"
     xy, tri = inputs.structured_mesh(w["n"])
     n_inst = w.get("n_inst", 1)
     if w["r"] == "mixed":
@@ -238,8 +256,10 @@ def main():
 
     def step():
         m.factor_local(kappa, beta_arg, 1.0, precision=prec)
+        if folded:
+            m.fold_operator()
         info = m.solve(f, g, lam, rtol=args.rtol, restart=args.restart, max_iter=args.max_iter,
-                       check=args.max_iter >= 20000, inner_rtol=args.inner_rtol)
+                       check=args.max_iter >= 20000, inner_rtol=args.inner_rtol, folded=folded)
         m.recover_local(lam, qu)
         infos.append(info.as_dict())
         inst_infos.append(m.last_solve_infos)
@@ -279,11 +299,12 @@ def main():
     # pure operator throughput (outside the timed steps)
     lam_r = torch.as_tensor(inputs.random_vector(s.n_trace, seed=1), device=dev)
     out = torch.empty_like(lam_r)
-    m.apply_trace_operator(lam_r, out, mhdg.MHDG_PRECONDITION)
+    aflags = mhdg.MHDG_PRECONDITION | (mhdg.MHDG_FOLDED if folded else 0)
+    m.apply_trace_operator(lam_r, out, aflags)
     torch.cuda.synchronize()
     ta = time.perf_counter()
     for _ in range(args.apply_reps):
-        m.apply_trace_operator(lam_r, out, mhdg.MHDG_PRECONDITION)
+        m.apply_trace_operator(lam_r, out, aflags)
     torch.cuda.synchronize()
     apply_only = args.apply_reps / (time.perf_counter() - ta)
 
@@ -363,6 +384,9 @@ def main():
     avg_ms = ams["ms"] / max(ams["count"], 1)
     nbytes = apply_bytes(m, 4 if prec == mhdg.MHDG_FP32 else 8,
                          None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"])
+    if folded:
+        # folded apply: T_K read once (8 L_K^2), the gathered trace and the slots
+        nbytes = fold_bytes(tri, w["r"], w["p"], s.n_trace)
     if n_inst > 1:
         # converged instances are masked out of later launches: count the
         # instances each launch actually processed (GMRES applies + the
@@ -392,7 +416,8 @@ def main():
                    "beta": list(w["beta"]) if n_inst == 1 else
                    "|a| U(0.5,2), direction U[0,2pi) per instance, seed 33",
                    "tau": 1.0, "rtol": args.rtol, "gmres_restart": args.restart,
-                   "form": ("batched_fp64" if n_inst > 1 else "plain_fp64")
+                   "form": ("folded_fp64" if folded else
+                            "batched_fp64" if n_inst > 1 else "plain_fp64")
                    if prec == mhdg.MHDG_FP64 else "fp32_factors_fp64_ir"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -401,8 +426,9 @@ def main():
                                      "copy-kernel calibrated; see profiles/)",
                      "traffic_vs_algorithmic": traffic["traffic_bytes_per_launch"] / nbytes
                      if traffic else None,
-                     "kernel": ("macro_solve_kernel<double>" if prec == mhdg.MHDG_FP64
-                                else "macro_solve_kernel<float>") + " (apply steps 1-3)",
+                     "kernel": ("fold_apply_kernel (folded steps 1-3)" if folded else
+                                ("macro_solve_kernel<double>" if prec == mhdg.MHDG_FP64
+                                 else "macro_solve_kernel<float>") + " (apply steps 1-3)"),
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
                      "launches": ams["count"]},
         "time_to_solve_s": ms_per_step / 1e3,

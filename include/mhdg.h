@@ -87,11 +87,13 @@ typedef enum {
 enum {
   MHDG_PRECONDITION = 1,      /* return D^-1 S lambda instead of S lambda      */
   MHDG_TRANSPOSE = 2,         /* use A_K^-T (adjoint solves)                   */
-  MHDG_GRAPH = 4              /* apply: replay a hipGraph of the launches (one
+  MHDG_GRAPH = 4,             /* apply: replay a hipGraph of the launches (one
                                  per size class for all instances, then the
                                  face combine), captured on first use for this
                                  (lam, out, flags) and kept until the next
                                  factor_local or set_instances              */
+  MHDG_FOLDED = 8             /* apply: steps 1-3 with the folded operators
+                                 T_K of mhdg_fold_operator (forward only)     */
 };
 
 typedef struct mhdg_mesh mhdg_mesh;
@@ -110,6 +112,7 @@ typedef struct {
   size_t factor_ws_bytes;     /* workspace for factor_local at this precision  */
   size_t solve_ws_bytes;      /* workspace for solve at this restart length    */
   int32_t n_instances;        /* coefficient instances (mhdg_set_instances)    */
+  size_t fold_ws_bytes;       /* workspace for mhdg_fold_operator              */
 } mhdg_sizes;
 
 typedef struct {
@@ -122,6 +125,8 @@ typedef struct {
                                  tolerance per refinement step (0: 1e-5)      */
   int32_t graph;              /* 1: every GMRES apply replays one captured
                                  hipGraph (see MHDG_GRAPH); 0: plain launches */
+  int32_t folded;             /* 1: GMRES applies use the folded operators
+                                 (MHDG_FOLDED; needs mhdg_fold_operator)      */
 } mhdg_solve_opts;
 
 typedef struct {
@@ -302,6 +307,20 @@ mhdg_status mhdg_autotune(mhdg_mesh* mesh, int32_t flags, mhdg_tune_report* out,
  * Errors: INVALID_ARG (no class of that size, variant not available). */
 mhdg_status mhdg_set_kernel_variant(mhdg_mesh* mesh, int32_t N, int32_t lu_variant,
                                     int32_t solve_variant);
+
+/* Fold steps 1-3 into one dense matrix per macro: T_K = C_K A_K^-1 B_K over
+ * the macro's interior-face trace dofs (L_K = sum of the n_F of its interior
+ * faces, at most 192), so that S lambda = D lambda - sum_K T_K lambda_K (eq.
+ * global_problem) reads L_K^2 values per macro instead of the N_K^2 of the
+ * factors.  The matrices are built with the stored FP64 factors: the
+ * interior faces are coloured so that the faces of one macro differ, and one
+ * apply of the indicator of (colour, trace position) yields one column of
+ * every T_K.  ws: device workspace of at least fold_ws_bytes (mhdg_query),
+ * kept by the handle until the next factor_local or set_instances.  Then
+ * apply_trace_operator with MHDG_FOLDED, or solve with opts->folded = 1, use
+ * them; recover_local, rhs and adjoint keep using the factors.
+ * Synchronises.  Errors: STATE (no FP64 factors), WORKSPACE, INVALID_ARG. */
+mhdg_status mhdg_fold_operator(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing of the hot path, for measurement.  enable = 1 clears
  * the counters and brackets every later launch of the listed kernels with

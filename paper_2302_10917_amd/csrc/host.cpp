@@ -48,6 +48,10 @@ struct mhdg_mesh {
   std::vector<double> tmpl;       // blob (int tables stored bit-wise in doubles' space)
   // factor state
   bool factored = false, have_rhs = false;
+  // folded operators T_K (mhdg_fold_operator): valid until the next factor_local
+  bool folded = false;
+  int64_t* fold_toff = nullptr;   // device: element offset of T_K
+  double* fold_T = nullptr;       // device: T_K column-major, L_K x L_K
   int precision = MHDG_FP64;
   double tau = 1;
   char* ws = nullptr;
@@ -429,6 +433,34 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
 }
 
 static size_t solve_bytes_impl(const mhdg_mesh* M, int R);
+static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const double* lam,
+                                   const double* xin, double* yout, hipStream_t s,
+                                   const int32_t* skip = nullptr);
+
+// Interior-face trace dofs of a macro (the order of its contribution slots).
+static int fold_L(const mhdg_mesh* M, const MacroInfo& mi) {
+  int L = 0;
+  for (int k = 0; k < 3; ++k)
+    if (mi.tr_off[k] >= 0) L += (1 << mi.flevel[k]) * M->p + 1;
+  return L;
+}
+
+// Fold workspace: T_K offsets int64[n_macro], face colours int32[n_faces],
+// interior-face colours int32[n_int], then every T_K (FP64, column-major).
+struct FoldLayout { size_t toff, fcolor, icolor, T, total; int64_t nT; };
+static FoldLayout fold_layout(const mhdg_mesh* M) {
+  FoldLayout F{};
+  size_t o = 0;
+  F.toff = o;   o = align_up(o + size_t(M->n_macro) * 8);
+  F.fcolor = o; o = align_up(o + size_t(M->n_faces) * 4);
+  F.icolor = o; o = align_up(o + size_t(std::max<int64_t>(M->n_int, 1)) * 4);
+  F.T = o;
+  int64_t nT = 0;
+  for (auto& mi : M->macros) { const int64_t L = fold_L(M, mi); nT += L * L; }
+  F.nT = nT;
+  F.total = align_up(o + size_t(nT) * 8);
+  return F;
+}
 static size_t solve_bytes(const mhdg_mesh* M, int restart) { return solve_bytes_impl(M, restart); }
 
 // ---------------------------------------------------------------- GMRES
@@ -894,6 +926,7 @@ mhdg_status mhdg_set_instances(mhdg_mesh* M, int32_t n_inst) {
     return fail(M, MHDG_ERR_INVALID_ARG, "set_instances: instance count out of range");
   M->factored = false;
   M->have_rhs = false;
+  M->folded = false;
   M->ws = nullptr;
   M->drop_graphs();
   M->n_inst = n_inst;
@@ -990,6 +1023,7 @@ mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, m
   out->max_level = M->max_level;
   out->max_local = M->max_N;
   out->n_instances = M->n_inst;
+  out->fold_ws_bytes = fold_layout(M).total;
   FactorLayout L = factor_layout(M, precision);
   // factor block offsets are padded to 64 elements per macro
   size_t es = precision == MHDG_FP32 ? 4 : 8;
@@ -1089,6 +1123,7 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   hipStream_t s = (hipStream_t)stream;
   M->factored = false;
   M->have_rhs = false;
+  M->folded = false;
   M->drop_graphs();
   M->precision = precision;
   M->tau = tau;
@@ -1141,6 +1176,83 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
       return fail(M, MHDG_ERR_SINGULAR, buf);
     }
   M->factored = true;
+  return MHDG_OK;
+}
+
+mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->factored || M->precision != MHDG_FP64)
+    return fail(M, MHDG_ERR_STATE, "fold_operator: needs FP64 factors (call factor_local first)");
+  const FoldLayout F = fold_layout(M);
+  if (!ws || ws_bytes < F.total)
+    return fail(M, MHDG_ERR_WORKSPACE, "fold_operator: workspace smaller than mhdg_query reports");
+  hipStream_t s = (hipStream_t)stream;
+  char* fw = (char*)ws;
+  // per-macro offsets, and a colouring of the interior faces in which the
+  // faces of one macro differ (greedy; at most 5 colours with 3 faces per macro)
+  std::vector<int64_t> toff(M->n_macro);
+  int64_t o = 0;
+  int maxL = 0, maxNF = 0;
+  for (int64_t e = 0; e < M->n_macro; ++e) {
+    toff[e] = o;
+    const int L = fold_L(M, M->macros[e]);
+    maxL = std::max(maxL, L);
+    o += int64_t(L) * L;
+  }
+  if (maxL > kFoldMaxL) return fail(M, MHDG_ERR_INVALID_ARG, "fold_operator: macro trace too large");
+  std::vector<int32_t> fcolor(M->n_faces, -1), icolor(std::max<int64_t>(M->n_int, 1), -1);
+  std::vector<uint8_t> used(M->n_macro, 0);
+  std::vector<std::array<int64_t, 2>> fmac(M->n_faces, {-1, -1});
+  std::vector<int32_t> ftr(M->n_faces, -1);
+  for (int64_t e = 0; e < M->n_macro; ++e)
+    for (int k = 0; k < 3; ++k) {
+      const MacroInfo& mi = M->macros[e];
+      if (mi.tr_off[k] < 0) continue;
+      auto& fm = fmac[mi.face[k]];
+      fm[fm[0] < 0 ? 0 : 1] = e;
+      ftr[mi.face[k]] = mi.tr_off[k];
+      maxNF = std::max(maxNF, (1 << mi.flevel[k]) * M->p + 1);
+    }
+  int ncol = 0;
+  for (int64_t f = 0; f < M->n_faces; ++f) {
+    if (fmac[f][0] < 0) continue;
+    const uint8_t u = used[fmac[f][0]] | (fmac[f][1] >= 0 ? used[fmac[f][1]] : 0);
+    int c = 0;
+    while (u & (1u << c)) ++c;
+    fcolor[f] = c;
+    ncol = std::max(ncol, c + 1);
+    for (int s2 = 0; s2 < 2; ++s2)
+      if (fmac[f][s2] >= 0) used[fmac[f][s2]] |= uint8_t(1u << c);
+  }
+  {
+    std::map<int32_t, int64_t> tr2idx;
+    for (int64_t i = 0; i < M->n_int; ++i) tr2idx[M->faces[i].tr_off] = i;
+    for (int64_t f = 0; f < M->n_faces; ++f)
+      if (fcolor[f] >= 0) icolor[tr2idx.at(ftr[f])] = fcolor[f];
+  }
+  HIP_TRY(M, hipMemcpyAsync(fw + F.toff, toff.data(), toff.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(M, hipMemcpyAsync(fw + F.fcolor, fcolor.data(), fcolor.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(M, hipMemcpyAsync(fw + F.icolor, icolor.data(), icolor.size() * 4, hipMemcpyHostToDevice, s));
+  FactorLayout& L = M->L;
+  char* w = M->ws;
+  const MacroInfo* info = (const MacroInfo*)(w + L.meta);
+  double* lam = (double*)(w + L.work1);   // n_local >= n_trace doubles
+  double* T = (double*)(fw + F.T);
+  for (int c = 0; c < ncol; ++c)
+    for (int i = 0; i < maxNF; ++i) {
+      HIP_TRY(M, launch_fold_indicator((const FaceInfo*)(w + L.faces), M->n_int,
+                                       (const int32_t*)(fw + F.icolor), c, i, lam, s));
+      mhdg_status st = run_macro_solve(M, MODE_APPLY, 0, lam, nullptr, nullptr, s);
+      if (st) return st;
+      HIP_TRY(M, launch_fold_scatter(info, M->n_macro, (const int64_t*)(fw + F.toff),
+                                     (const int32_t*)(fw + F.fcolor), M->p, c, i,
+                                     (const double*)(w + L.slots), T, s));
+    }
+  HIP_TRY(M, hipStreamSynchronize(s));
+  M->fold_toff = (int64_t*)(fw + F.toff);
+  M->fold_T = T;
+  M->folded = true;
+  M->drop_graphs();
   return MHDG_OK;
 }
 
@@ -1281,7 +1393,7 @@ mhdg_status mhdg_local_matrix(mhdg_mesh* M, int64_t e, double* dst, void* stream
 
 static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const double* lam,
                                    const double* xin, double* yout, hipStream_t s,
-                                   const int32_t* skip = nullptr) {
+                                   const int32_t* skip) {
   FactorLayout& L = M->L;
   char* w = M->ws;
   ProfScope ps(M, mode == MODE_APPLY ? 2 : 4, s);
@@ -1342,6 +1454,20 @@ mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags
 mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
                            const int32_t* skip, hipStream_t s) {
   const int tr = (flags & MHDG_TRANSPOSE) ? 1 : 0;
+  if (flags & MHDG_FOLDED) {
+    FactorLayout& L = M->L;
+    {
+      ProfScope ps(M, 2, s);
+      HIP_TRY(M, launch_fold_apply((const MacroInfo*)(M->ws + L.meta), M->n_macro, M->fold_toff,
+                                   M->fold_T, M->p, skip, lam, (double*)(M->ws + L.slots), s));
+    }
+    ProfScope ps(M, 3, s);
+    HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
+                                   (const FaceInfo*)(M->ws + L.faces), M->n_int,
+                                   (const double*)(M->ws + L.tmpl), M->T, M->tau, lam,
+                                   (const double*)(M->ws + L.slots), out, s, skip));
+    return MHDG_OK;
+  }
   mhdg_status st = run_macro_solve(M, MODE_APPLY, tr, lam, nullptr, nullptr, s, skip);
   if (st) return st;
   FactorLayout& L = M->L;
@@ -1363,6 +1489,8 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* o
   const int tr = (flags & MHDG_TRANSPOSE) ? 1 : 0;
   if (tr && M->precision != MHDG_FP64)
     return fail(M, MHDG_ERR_STATE, "apply: the transposed operator needs FP64 factors");
+  if ((flags & MHDG_FOLDED) && (!M->folded || tr))
+    return fail(M, MHDG_ERR_STATE, "apply: folded operators need mhdg_fold_operator (forward only)");
   if (M->n_trace == 0) return MHDG_OK;
   return apply_op(M, lam, out, flags, nullptr, (hipStream_t)stream);
 }
@@ -1487,6 +1615,11 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   Gm G;
   carve(M, ws, R, G);
   if (o->graph) G.op_flags |= MHDG_GRAPH;
+  if (o->folded) {
+    if (!M->folded || M->precision != MHDG_FP64)
+      return fail(M, MHDG_ERR_STATE, "solve: folded applies need mhdg_fold_operator");
+    G.op_flags |= MHDG_FOLDED;
+  }
   mhdg_solve_info inf{};
   mhdg_status st;
   FactorLayout& L = M->L;

@@ -147,6 +147,17 @@ hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double*
 enum FaceMode { FACE_S = 0, FACE_PREC_S = 1, FACE_RHS = 2, FACE_PREC_RHS = 3, FACE_RESID = 4,
                 FACE_DINV = 5 /* out = D_F^-1 lam (slots unused) */ };
 
+// folded macro operators T_K = C_K A_K^-1 B_K (fold.hip)
+constexpr int kFoldMaxL = 192;
+hipError_t launch_fold_indicator(const FaceInfo* fi, int64_t nf, const int32_t* icolor, int c,
+                                 int i, double* lam, hipStream_t s);
+hipError_t launch_fold_scatter(const MacroInfo* info, int64_t n, const int64_t* toff,
+                               const int32_t* fcolor, int p, int c, int i, const double* slots,
+                               double* T, hipStream_t s);
+hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,
+                             int p, const int32_t* skip, const double* lam, double* slots,
+                             hipStream_t s);
+
 // GMRES vector kernels
 // Vectors may hold nseg independent segments of length n (coefficient
 // instances): dot products and updates are per segment; out / h are indexed

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmhdg.so")
 
 MHDG_FP64, MHDG_FP32 = 0, 1
-MHDG_PRECONDITION, MHDG_TRANSPOSE, MHDG_GRAPH = 1, 2, 4
+MHDG_PRECONDITION, MHDG_TRANSPOSE, MHDG_GRAPH, MHDG_FOLDED = 1, 2, 4, 8
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "MESH", 3: "SINGULAR", 4: "NOT_CONVERGED",
           5: "WORKSPACE", 6: "HIP", 7: "STATE"}
@@ -27,7 +27,7 @@ ABI_SYMBOLS = [
     "mhdg_solve", "mhdg_recover_local", "mhdg_destroy", "mhdg_last_error",
     "mhdg_status_string", "mhdg_profile", "mhdg_mass_apply", "mhdg_adjoint",
     "mhdg_set_instances", "mhdg_factor_local_batched", "mhdg_autotune",
-    "mhdg_set_kernel_variant",
+    "mhdg_set_kernel_variant", "mhdg_fold_operator",
 ]
 MHDG_TUNE_LU, MHDG_TUNE_SOLVE = 1, 2
 MAX_CLASSES = 8
@@ -46,14 +46,14 @@ class Sizes(ctypes.Structure):
                 ("n_bnd_points", ctypes.c_int64), ("p", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("max_local", ctypes.c_int64),
                 ("factor_ws_bytes", ctypes.c_size_t), ("solve_ws_bytes", ctypes.c_size_t),
-                ("n_instances", ctypes.c_int32)]
+                ("n_instances", ctypes.c_int32), ("fold_ws_bytes", ctypes.c_size_t)]
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("zero_guess", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("folded", ctypes.c_int32)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH):
         "mhdg_set_instances": [P, I32],
         "mhdg_autotune": [P, I32, ctypes.POINTER(TuneReport), P],
         "mhdg_set_kernel_variant": [P, I32, I32, I32],
+        "mhdg_fold_operator": [P, P, SZ, P],
         "mhdg_local_matrix": [P, I64, P, P],
         "mhdg_apply_trace_operator": [P, P, P, I32, P],
         "mhdg_local_solve": [P, P, P, I32, P],
@@ -264,14 +265,15 @@ class MacroMesh:
                                        _stream(stream)), "rhs")
 
     def solve(self, f_nodes, g_bnd, lam, rtol=1e-10, restart=30, max_iter=10000, zero_guess=True,
-              stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True):
+              stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True, folded=False):
         import torch
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1 if zero_guess else 0,
-                         int(max_outer), float(inner_rtol), 1 if graph else 0)
+                         int(max_outer), float(inner_rtol), 1 if graph else 0,
+                         1 if folded else 0)
         infos = (SolveInfo * max(1, s.n_instances))()
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
                                   _ptr(self.solve_ws), self.solve_ws.numel(),
@@ -293,7 +295,7 @@ class MacroMesh:
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
-        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0)
+        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0, 0)
         info = SolveInfo()
         self._check(self._lib.mhdg_adjoint(self.h, _ptr(lam), _ptr(qu), _ptr(dJ_dU),
                                            ctypes.byref(opts), _ptr(psi_lam), _ptr(psi_U),
@@ -310,6 +312,17 @@ class MacroMesh:
         self._check(self._lib.mhdg_autotune(self.h, int(flags), ctypes.byref(rep),
                                             _stream(stream)), "autotune")
         return rep.as_list()
+
+    def fold_operator(self, stream=None):
+        """Build the folded macro operators T_K = C_K A_K^-1 B_K (FP64 factors
+        needed); then apply/solve can use them (MHDG_FOLDED / folded=True)."""
+        import torch
+        s = self.query(self.precision)
+        if getattr(self, "fold_ws", None) is None or self.fold_ws.numel() < s.fold_ws_bytes:
+            self.fold_ws = None
+            self.fold_ws = torch.empty(max(s.fold_ws_bytes, 1), dtype=torch.uint8, device="cuda")
+        self._check(self._lib.mhdg_fold_operator(self.h, _ptr(self.fold_ws), self.fold_ws.numel(),
+                                                 _stream(stream)), "fold_operator")
 
     def set_kernel_variant(self, N, lu_variant=0, solve_variant=0):
         self._check(self._lib.mhdg_set_kernel_variant(self.h, int(N), int(lu_variant),
