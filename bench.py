@@ -187,6 +187,9 @@ def main():
                          "one at a time with single-instance handles (the plain form) and "
                          "report their time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--folded", action="store_true",
+                    help="run the GMRES applies on the folded macro operators (FP64 workloads, "
+                         "including the differentiation workload's adjoint solve)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel shapes (no autotuning before the warmup)")
     ap.add_argument("--max-iter", type=int, default=20000,
@@ -210,7 +213,7 @@ def main():
         args.rtol = w.get("rtol", 1e-10)
     if w.get("form") == "adjoint":
         return bench_adjoint(args, w)
-    folded = w.get("form") == "folded"
+    folded = w.get("form") == "folded" or args.folded
     xy, tri = inputs.structured_mesh(w["n"])
     n_inst = w.get("n_inst", 1)
     if w["r"] == "mixed":
@@ -380,7 +383,7 @@ def main():
                "lambda": rd(lam_lp, lam), "q": rd(qv_lp[:, :2], qv[:, :2]),
                "u": rd(qv_lp[:, 2], qv[:, 2])}
 
-    ams = kt["apply_macro_solve"]
+    ams = kt["folded_apply" if folded else "apply_macro_solve"]
     avg_ms = ams["ms"] / max(ams["count"], 1)
     nbytes = apply_bytes(m, 4 if prec == mhdg.MHDG_FP32 else 8,
                          None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"])
@@ -437,6 +440,7 @@ def main():
         "sequential_plain": seq,
         "outer_iterations": [i["outer_iterations"] for i in infos],
         "applies_per_solve": [i["n_applies"] for i in infos],
+        "second_gs_passes": [i["reorth_passes"] for i in infos],
         "vs_fp64": cmp,
         "rel_res_prec": [max(x["rel_res_prec"] for x in si) for si in inst_infos],
         "rel_res_true": [max(x["rel_res_true"] for x in si) for si in inst_infos],
@@ -479,7 +483,7 @@ def bench_adjoint(args, w):
           file=sys.stderr, flush=True)
     with torch.no_grad():
         qu_obs = ad.solve(torch.as_tensor(kappa * np.exp(0.1 * eta), device=dev), beta, m, f, g,
-                          args.rtol, args.restart).clone()
+                          args.rtol, args.restart, args.folded).clone()
     print(f"[bench] u_obs solved: {m.last_solve_info['iterations']} iterations", file=sys.stderr,
           flush=True)
     infos = []
@@ -487,7 +491,7 @@ def bench_adjoint(args, w):
     def step():
         k = torch.as_tensor(kappa, device=dev).requires_grad_(True)
         b = beta.clone().requires_grad_(True)
-        J = ad.l2_misfit(m, ad.solve(k, b, m, f, g, args.rtol, args.restart), qu_obs)
+        J = ad.l2_misfit(m, ad.solve(k, b, m, f, g, args.rtol, args.restart, args.folded), qu_obs)
         fwd = dict(m.last_solve_info)
         J.backward()
         infos.append((fwd, dict(m.last_adjoint_info)))
@@ -515,7 +519,7 @@ def bench_adjoint(args, w):
         def Jof(kap, bet):
             with torch.no_grad():
                 qu = ad.solve(torch.as_tensor(kap, device=dev), torch.tensor(bet), m, f, g,
-                              args.rtol, args.restart)
+                              args.rtol, args.restart, args.folded)
                 return ad.l2_misfit(m, qu, qu_obs).item()
         # J is smooth in kappa_K: a relative step of 1e-3 keeps the central-difference
         # truncation small while lifting the J difference above the solve tolerance
@@ -538,9 +542,9 @@ def bench_adjoint(args, w):
             fd["beta"].append({"d": d, "fd": v, "adjoint": float(db[d]),
                                "rel_diff": abs(v - float(db[d])) / abs(v)})
             print(f"[bench] fd beta_{d}: {fd['beta'][-1]}", file=sys.stderr, flush=True)
-    ams = kt["apply_macro_solve"]
+    ams = kt["folded_apply" if args.folded else "apply_macro_solve"]
     avg_ms = ams["ms"] / max(ams["count"], 1)
-    nbytes = apply_bytes(m, 8)
+    nbytes = fold_bytes(tri, w["r"], w["p"], s.n_trace) if args.folded else apply_bytes(m, 8)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     result = {
         "metric": METRIC, "value": applies / elapsed, "unit": "applies/s", "n_gpus": 1,
@@ -550,10 +554,13 @@ def bench_adjoint(args, w):
         "config": {"workload": args.workload, "n_macro": n_macro, "r": w["r"], "p": w["p"],
                    "N_K": s.max_local, "n_trace": s.n_trace, "kappa": "lognormal sigma 0.5 seed 5",
                    "beta": list(w["beta"]), "tau": 1.0, "rtol": args.rtol,
-                   "gmres_restart": args.restart, "form": "forward + adjoint gradient"},
+                   "gmres_restart": args.restart,
+                   "form": "forward + adjoint gradient" + (", folded" if args.folded else "")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "macro_solve_kernel<double> (forward apply steps 1-3)",
+                     "kernel": ("fold_apply_kernel (forward and transposed folded applies)"
+                                if args.folded else
+                                "macro_solve_kernel<double> (forward apply steps 1-3)"),
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms, "launches": ams["count"]},
         "forward_iterations": [a["iterations"] for a, _ in infos],
         "adjoint_iterations": [b_["iterations"] for _, b_ in infos],

@@ -93,7 +93,8 @@ enum {
                                  (lam, out, flags) and kept until the next
                                  factor_local or set_instances              */
   MHDG_FOLDED = 8             /* apply: steps 1-3 with the folded operators
-                                 T_K of mhdg_fold_operator (forward only)     */
+                                 T_K of mhdg_fold_operator (T_K^T with
+                                 MHDG_TRANSPOSE)                              */
 };
 
 typedef struct mhdg_mesh mhdg_mesh;
@@ -125,7 +126,8 @@ typedef struct {
                                  tolerance per refinement step (0: 1e-5)      */
   int32_t graph;              /* 1: every GMRES apply replays one captured
                                  hipGraph (see MHDG_GRAPH); 0: plain launches */
-  int32_t folded;             /* 1: GMRES applies use the folded operators
+  int32_t folded;             /* 1: GMRES applies (forward in solve, transposed
+                                 in adjoint) use the folded operators
                                  (MHDG_FOLDED; needs mhdg_fold_operator)      */
 } mhdg_solve_opts;
 
@@ -141,6 +143,9 @@ typedef struct {
   int32_t n_applies;          /* operator applies + per-macro solve passes this
                                  instance took part in                         */
   int32_t outer_iterations;   /* refinement steps (reduced-precision factors)  */
+  int32_t reorth_passes;      /* second Gram-Schmidt passes taken (the second
+                                 pass runs only when the first leaves less
+                                 than 1/sqrt(2) of the vector's norm)        */
 } mhdg_solve_info;
 
 /* Build the host-side macro mesh: faces, levels, orientation, numbering and
@@ -327,12 +332,12 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void*
  * HIP events recorded on the launch stream; enable = 0 stops recording,
  * waits for the recorded events and fills *out (may be NULL).  Index:
  * 0 assemble, 1 lu, 2 macro solve of apply_trace_operator (steps 1-3),
- * 3 face combine (step 4), 4 macro solve of rhs/recover/local_solve.  An
- * apply replayed from a captured graph (MHDG_GRAPH) is timed whole under
- * index 2. */
+ * 3 face combine (step 4), 4 macro solve of rhs/recover/local_solve,
+ * 5 folded apply (steps 1-3 with T_K).  An apply replayed from a captured
+ * graph (MHDG_GRAPH) is timed whole under index 2 (5 when folded). */
 typedef struct {
-  int32_t count[5];
-  double ms[5];
+  int32_t count[6];
+  double ms[6];
 } mhdg_kernel_times;
 mhdg_status mhdg_profile(mhdg_mesh* mesh, int32_t enable, mhdg_kernel_times* out);
 

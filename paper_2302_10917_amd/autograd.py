@@ -21,30 +21,34 @@ class _State:
         self.key = None
 
 
-def _key(kappa, beta):
-    return (kappa.data_ptr(), kappa._version, float(beta[0]), float(beta[1]),
+def _key(kappa, beta, folded):
+    return (kappa.data_ptr(), kappa._version, float(beta[0]), float(beta[1]), bool(folded),
             hash(kappa.detach().cpu().numpy().tobytes()))
 
 
-def _forward(mesh, kappa, beta, f, g, rtol, restart):
+def _forward(mesh, kappa, beta, f, g, rtol, restart, folded):
     s = mesh.sizes
     mesh.factor_local(kappa.detach(), (float(beta[0]), float(beta[1])), 1.0)
+    if folded:
+        mesh.fold_operator()
     lam = torch.zeros(s.n_trace, dtype=torch.float64, device="cuda")
-    mesh.solve(f, g, lam, rtol=rtol, restart=restart, max_iter=max(50000, 2 * restart))
+    mesh.solve(f, g, lam, rtol=rtol, restart=restart, max_iter=max(50000, 2 * restart),
+               folded=folded)
     qu = torch.empty(s.n_local, dtype=torch.float64, device="cuda")
     mesh.recover_local(lam, qu)
     if not hasattr(mesh, "_ad_state"):
         mesh._ad_state = _State()
-    mesh._ad_state.key = _key(kappa, beta)
+    mesh._ad_state.key = _key(kappa, beta, folded)
     return lam, qu
 
 
 class MacroHDGSolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, kappa, beta, mesh, f, g, rtol, restart):
+    def forward(ctx, kappa, beta, mesh, f, g, rtol, restart, folded):
         beta_h = beta.detach().cpu()
-        lam, qu = _forward(mesh, kappa, beta_h, f, g, rtol, restart)
+        lam, qu = _forward(mesh, kappa, beta_h, f, g, rtol, restart, folded)
         ctx.mesh, ctx.f, ctx.g, ctx.rtol, ctx.restart = mesh, f, g, rtol, restart
+        ctx.folded = folded
         ctx.save_for_backward(kappa.detach().clone(), beta_h.clone(), lam, qu)
         return qu
 
@@ -52,23 +56,25 @@ class MacroHDGSolve(torch.autograd.Function):
     def backward(ctx, grad_qu):
         kappa, beta_h, lam, qu = ctx.saved_tensors
         mesh = ctx.mesh
-        if getattr(getattr(mesh, "_ad_state", None), "key", None) != _key(kappa, beta_h):
+        if getattr(getattr(mesh, "_ad_state", None), "key", None) != _key(kappa, beta_h, ctx.folded):
             # another solve ran since: restore this problem's factors and traces
-            lam, qu = _forward(mesh, kappa, beta_h, ctx.f, ctx.g, ctx.rtol, ctx.restart)
+            lam, qu = _forward(mesh, kappa, beta_h, ctx.f, ctx.g, ctx.rtol, ctx.restart,
+                               ctx.folded)
         s = mesh.sizes
         dk = torch.empty(s.n_macro, dtype=torch.float64, device="cuda")
         db = torch.empty(2, dtype=torch.float64, device="cuda")
         psi_lam = torch.empty(max(s.n_trace, 1), dtype=torch.float64, device="cuda")
         psi_U = torch.empty(s.n_local, dtype=torch.float64, device="cuda")
         mesh.adjoint(lam, qu, grad_qu.contiguous(), psi_lam, psi_U, dk, db, rtol=ctx.rtol,
-                     restart=ctx.restart)
+                     restart=ctx.restart, folded=ctx.folded)
         return dk, db.to(beta_h.device if beta_h.device.type == "cuda" else "cpu"), None, None, \
-            None, None, None
+            None, None, None, None
 
 
-def solve(kappa, beta, mesh, f, g, rtol=1e-12, restart=300):
-    """Differentiable U(kappa, beta) (local vectors [q_x | q_y | u] per macro)."""
-    return MacroHDGSolve.apply(kappa, beta, mesh, f, g, rtol, restart)
+def solve(kappa, beta, mesh, f, g, rtol=1e-12, restart=300, folded=False):
+    """Differentiable U(kappa, beta) (local vectors [q_x | q_y | u] per macro).
+    folded=True runs both GMRES solves on the folded macro operators."""
+    return MacroHDGSolve.apply(kappa, beta, mesh, f, g, rtol, restart, folded)
 
 
 class MassApply(torch.autograd.Function):

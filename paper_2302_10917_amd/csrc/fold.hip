@@ -59,14 +59,19 @@ __global__ __launch_bounds__(64) void fold_scatter_kernel(const MacroInfo* __res
   }
 }
 
-// Steps 1-3 with the folded operators: slots of macro K = T_K lambda_K.
-// One wavefront per macro: lambda_K gathered into LDS, T_K streamed column by
-// column (coalesced across the lanes, lane l accumulating rows l + 64 t).
+// Steps 1-3 with the folded operators: slots of macro K = T_K lambda_K, or
+// T_K^T lambda_K for the transposed operator S^T (adjoint solves).  One
+// wavefront per macro with lambda_K gathered into LDS.  Forward: T_K streamed
+// column by column, coalesced across the lanes, lane l accumulating rows
+// l + 64 t.  Transposed: lane l forms the dot product of column l + 64 t with
+// lambda_K (each lane walks its own contiguous column; a macro's T_K is a
+// few KB and stays in cache).
 constexpr int kFoldRows = 3;   // rows per lane: L_K <= 192 (checked on the host)
 __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restrict__ info,
                                                         const int64_t* __restrict__ toff,
                                                         const double* __restrict__ T, int p,
                                                         const int32_t* __restrict__ skip,
+                                                        int transpose,
                                                         const double* __restrict__ lam,
                                                         double* __restrict__ slots) {
   __shared__ double xl[64 * kFoldRows];
@@ -87,14 +92,27 @@ __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restr
 #pragma unroll
   for (int t = 0; t < kFoldRows; ++t) acc[t] = 0.0;
   const int nt = (L + 63) >> 6;
+  if (!transpose) {
 #pragma unroll 4
-  for (int c = 0; c < L; ++c) {
-    const double x = xl[c];
-    const double* col = Tm + int64_t(c) * L;
+    for (int c = 0; c < L; ++c) {
+      const double x = xl[c];
+      const double* col = Tm + int64_t(c) * L;
+#pragma unroll
+      for (int t = 0; t < kFoldRows; ++t) {
+        const int r = lane + 64 * t;
+        if (t < nt && r < L) acc[t] += col[r] * x;
+      }
+    }
+  } else {
 #pragma unroll
     for (int t = 0; t < kFoldRows; ++t) {
-      const int r = lane + 64 * t;
-      if (t < nt && r < L) acc[t] += col[r] * x;
+      const int c = lane + 64 * t;
+      if (t < nt && c < L) {
+        const double* col = Tm + int64_t(c) * L;
+        double a = 0.0;
+        for (int r = 0; r < L; ++r) a += col[r] * xl[r];
+        acc[t] = a;
+      }
     }
   }
   int r0 = 0;
@@ -127,10 +145,10 @@ hipError_t launch_fold_scatter(const MacroInfo* info, int64_t n, const int64_t* 
 }
 
 hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,
-                             int p, const int32_t* skip, const double* lam, double* slots,
-                             hipStream_t s) {
+                             int p, const int32_t* skip, int transpose, const double* lam,
+                             double* slots, hipStream_t s) {
   hipLaunchKernelGGL(fold_apply_kernel, dim3((unsigned)n), dim3(64), 0, s, info, toff, T, p, skip,
-                     lam, slots);
+                     transpose, lam, slots);
   return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ struct mhdg_mesh {
   std::string err;
   // kernel timing (mhdg_profile)
   bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[6];
   // captured applies (every size class and instance, then the face combine)
   // keyed by their vector pointers and flags; valid until the next
   // factor_local / set_instances
@@ -486,6 +486,7 @@ struct Gm {
   double *partial = nullptr, *hdev = nullptr, *ydev = nullptr, *adev = nullptr;
   int32_t* skip = nullptr;                // per-segment flags: 1 = take no part in applies
   std::vector<int> seg_applies;           // applies each segment took part in
+  int reorth = 0;                         // second Gram-Schmidt passes taken
   double *U = nullptr, *dl = nullptr, *cl = nullptr;  // precision-refinement state
   int64_t len() const { return n * nseg; }
 };
@@ -502,7 +503,8 @@ mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags
                      const int32_t* skip, hipStream_t s);
 
 // Left-preconditioned restarted GMRES on D^-1 S x = b (b already
-// preconditioned) with classical Gram-Schmidt applied twice (CGS2); all
+// preconditioned) with classical Gram-Schmidt and a conditional second pass
+// (taken when the first leaves less than 1/sqrt(2) of the norm); all
 // vectors and inner products in FP64 on the device, the Hessenberg
 // least-squares problems by Givens rotations on the host.  Segment s stops
 // when ||b_s - D^-1 S x_s|| <= rtol * bref[s] (checked on the true
@@ -517,7 +519,7 @@ mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, doub
   mhdg_status st;
   std::vector<double> H(size_t(ns) * (R + 1) * R), cs(size_t(ns) * R), sn(size_t(ns) * R),
       g(size_t(ns) * (R + 1)), h(size_t(ns) * (R + 2)), y(size_t(ns) * (R + 1)), beta(ns),
-      alpha(ns), nrm(ns);
+      alpha(ns), nrm(ns), w2h(2 * size_t(ns));
   std::vector<int32_t> skip(ns), skip_dev_copy(ns, -1);
   std::vector<char> active(ns);
   std::vector<int> jc(ns);
@@ -578,19 +580,31 @@ mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, doub
       if ((st = apply_op(M, vj, G.wv, G.op_flags, G.skip, s))) return st;
       ++applies;
       for (int q = 0; q < ns; ++q) G.seg_applies[q] += !skip[q];
+      // classical Gram-Schmidt; a second pass only where the first removed
+      // most of w (||w_after||^2 < ||w_before||^2 / 2, the "twice is enough"
+      // criterion), so most iterations read the basis twice, not four times.
+      // One host synchronisation per pass: projections and both norms together.
+      double* w2 = G.ydev;   // [0, ns): ||w||^2 before the pass, [ns, 2 ns): after
       for (int pass = 0; pass < 2; ++pass) {
         HIP_TRY(M, launch_dots(G.V, ld, j + 1, G.wv, n, G.partial, G.nblk, G.hdev, s, ns));
+        HIP_TRY(M, launch_dots(G.wv, ld, 1, G.wv, n, G.partial, G.nblk, w2, s, ns));
         HIP_TRY(M, launch_gemv_sub(G.V, ld, j + 1, G.hdev, G.wv, n, -1.0, s, ns));
+        HIP_TRY(M, launch_dots(G.wv, ld, 1, G.wv, n, G.partial, G.nblk, w2 + ns, s, ns));
         HIP_TRY(M, hipMemcpyAsync(h.data(), G.hdev, size_t(j + 1) * ns * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
+        HIP_TRY(M, hipMemcpyAsync(w2h.data(), w2, 2 * ns * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(M, hipStreamSynchronize(s));
+        bool again = false;
         for (int q = 0; q < ns; ++q) {
           if (!active[q]) continue;
           double* Hq = &H[size_t(q) * (R + 1) * R];
           for (int i = 0; i <= j; ++i) Hq[i * R + j] = (pass ? Hq[i * R + j] : 0.0) + h[i * ns + q];
+          nrm[q] = w2h[ns + q];
+          again |= !(w2h[ns + q] >= 0.5 * w2h[q]);
         }
+        if (!again) break;
+        ++G.reorth;
       }
-      if ((st = dot(M, G, G.wv, G.wv, nrm.data(), s))) return st;
       any = false;
       for (int q = 0; q < ns; ++q) {
         if (!active[q]) { alpha[q] = 0.0; continue; }
@@ -628,7 +642,8 @@ mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, doub
         double worst = 0;
         for (int q = 0; q < ns; ++q)
           if (!done[q]) worst = std::max(worst, rel[q]);
-        std::fprintf(stderr, "[mhdg] gmres iteration %d relative residual %.3e\n", it, worst);
+        std::fprintf(stderr, "[mhdg] gmres iteration %d relative residual %.3e (%d second passes)\n",
+                     it, worst, G.reorth);
         std::fflush(stderr);
       }
       if ((st = push_alpha())) return st;
@@ -991,7 +1006,7 @@ mhdg_status mhdg_set_instances(mhdg_mesh* M, int32_t n_inst) {
 mhdg_status mhdg_profile(mhdg_mesh* M, int32_t enable, mhdg_kernel_times* out) {
   if (!M) return MHDG_ERR_INVALID_ARG;
   if (out) std::memset(out, 0, sizeof(*out));
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < 6; ++k) {
     for (auto& p : M->ev[k]) {
       if (!enable && out) {
         HIP_TRY(M, hipEventSynchronize(p.second));
@@ -1419,7 +1434,7 @@ mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags
   const int32_t f = flags & ~MHDG_GRAPH;
   for (auto& a : M->graphs)
     if (a.lam == lam && a.out == out && a.flags == f && a.skip == skip) {
-      ProfScope ps(M, 2, s);   // the whole replayed apply
+      ProfScope ps(M, (f & MHDG_FOLDED) ? 5 : 2, s);   // the whole replayed apply
       HIP_TRY(M, hipGraphLaunch(a.x, s));
       return MHDG_OK;
     }
@@ -1446,7 +1461,7 @@ mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags
     return fail(M, MHDG_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
   }
   M->graphs.push_back({lam, out, f, skip, g, x});
-  ProfScope ps(M, 2, s);
+  ProfScope ps(M, (f & MHDG_FOLDED) ? 5 : 2, s);
   HIP_TRY(M, hipGraphLaunch(x, s));
   return MHDG_OK;
 }
@@ -1457,9 +1472,9 @@ mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t
   if (flags & MHDG_FOLDED) {
     FactorLayout& L = M->L;
     {
-      ProfScope ps(M, 2, s);
+      ProfScope ps(M, 5, s);
       HIP_TRY(M, launch_fold_apply((const MacroInfo*)(M->ws + L.meta), M->n_macro, M->fold_toff,
-                                   M->fold_T, M->p, skip, lam, (double*)(M->ws + L.slots), s));
+                                   M->fold_T, M->p, skip, tr, lam, (double*)(M->ws + L.slots), s));
     }
     ProfScope ps(M, 3, s);
     HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
@@ -1489,8 +1504,8 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* o
   const int tr = (flags & MHDG_TRANSPOSE) ? 1 : 0;
   if (tr && M->precision != MHDG_FP64)
     return fail(M, MHDG_ERR_STATE, "apply: the transposed operator needs FP64 factors");
-  if ((flags & MHDG_FOLDED) && (!M->folded || tr))
-    return fail(M, MHDG_ERR_STATE, "apply: folded operators need mhdg_fold_operator (forward only)");
+  if ((flags & MHDG_FOLDED) && !M->folded)
+    return fail(M, MHDG_ERR_STATE, "apply: folded operators need mhdg_fold_operator");
   if (M->n_trace == 0) return MHDG_OK;
   return apply_op(M, lam, out, flags, nullptr, (hipStream_t)stream);
 }
@@ -1748,6 +1763,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       // applies this instance took part in (rhs 2, GMRES, true residual 1 for FP64)
       info[q].n_applies = ns == 1 ? inf.n_applies
                                   : 3 + G.seg_applies[q];
+      info[q].reorth_passes = G.reorth;
     }
   if (!converged) return fail(M, MHDG_ERR_NOT_CONVERGED, "solve: max_iter reached");
   return MHDG_OK;
@@ -1788,6 +1804,10 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
   Gm G;
   carve(M, ws, o->restart, G);
   G.op_flags = MHDG_PRECONDITION | MHDG_TRANSPOSE | (o->graph ? MHDG_GRAPH : 0);
+  if (o->folded) {
+    if (!M->folded) return fail(M, MHDG_ERR_STATE, "adjoint: folded applies need mhdg_fold_operator");
+    G.op_flags |= MHDG_FOLDED;
+  }
   FactorLayout& L = M->L;
   char* fw = M->ws;
   const double* tm = (const double*)(fw + L.tmpl);

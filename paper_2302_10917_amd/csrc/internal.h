@@ -155,8 +155,8 @@ hipError_t launch_fold_scatter(const MacroInfo* info, int64_t n, const int64_t* 
                                const int32_t* fcolor, int p, int c, int i, const double* slots,
                                double* T, hipStream_t s);
 hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,
-                             int p, const int32_t* skip, const double* lam, double* slots,
-                             hipStream_t s);
+                             int p, const int32_t* skip, int transpose, const double* lam,
+                             double* slots, hipStream_t s);
 
 // GMRES vector kernels
 // Vectors may hold nseg independent segments of length n (coefficient

@@ -117,6 +117,8 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
                                                          const double* __restrict__ lam,
                                                          const double* xin, double* yout,
                                                          double* __restrict__ slots) {
+  // loads in flight per group: the same number of bytes for FP32 factors
+  constexpr int kLG = sizeof(T) == 4 ? 2 * kLoadGroup : kLoadGroup;
   extern __shared__ double sm[];
   const MacroInfo& mi = info[order[base + blockIdx.x]];
   if (skip && skip[mi.inst]) return;   // instance already converged: no work, outputs untouched
@@ -166,22 +168,22 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
       // the workspace's guard tail; values outside the triangle are discarded
       // by the select.
 #pragma unroll
-      for (int g = q; g < NQ; g += kLoadGroup) {
-        double a[kLoadGroup];
+      for (int g = q; g < NQ; g += kLG) {
+        T a[kLG];
 #pragma unroll
-        for (int t = 0; t < kLoadGroup; ++t) {
+        for (int t = 0; t < kLG; ++t) {
           const int r = lane + 64 * (g + t);
           // lanes outside the triangle of the first chunk, and past N in the
           // last chunk, re-read a row whose cache line is fetched anyway
           int rr = r;
           if (g + t == q) rr = r > j ? r : j + 1;
           if (g + t == NQ - 1) rr = rr < N ? rr : N - 1;
-          a[t] = (g + t < NQ) ? (double)col[rr] : 0.0;
+          a[t] = (g + t < NQ) ? col[rr] : T(0);
         }
 #pragma unroll
-        for (int t = 0; t < kLoadGroup; ++t) {
+        for (int t = 0; t < kLG; ++t) {
           const int r = lane + 64 * (g + t);
-          if (g + t < NQ) y[g + t] -= ((r > j && r < N) ? a[t] : 0.0) * yj;
+          if (g + t < NQ) y[g + t] -= ((r > j && r < N) ? (double)a[t] : 0.0) * yj;
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -197,19 +199,19 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
       const double zj = readlane_d(y[q], jj) / (double)col[j];
       if (lane == jj) y[q] = zj;
 #pragma unroll
-      for (int g = 0; g <= q; g += kLoadGroup) {
-        double a[kLoadGroup];
+      for (int g = 0; g <= q; g += kLG) {
+        T a[kLG];
 #pragma unroll
-        for (int t = 0; t < kLoadGroup; ++t) {
+        for (int t = 0; t < kLG; ++t) {
           const int r = lane + 64 * (g + t);
           int rr = r;
           if (g + t == q) rr = r < j ? r : (j > 0 ? j - 1 : 0);
-          a[t] = (g + t <= q) ? (double)col[rr] : 0.0;
+          a[t] = (g + t <= q) ? col[rr] : T(0);
         }
 #pragma unroll
-        for (int t = 0; t < kLoadGroup; ++t) {
+        for (int t = 0; t < kLG; ++t) {
           const int r = lane + 64 * (g + t);
-          if (g + t <= q) y[g + t] -= (r < j ? a[t] : 0.0) * zj;
+          if (g + t <= q) y[g + t] -= (r < j ? (double)a[t] : 0.0) * zj;
         }
         __builtin_amdgcn_sched_barrier(0);
       }

@@ -57,8 +57,9 @@ class SolveOpts(ctypes.Structure):
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("count", ctypes.c_int32 * 5), ("ms", ctypes.c_double * 5)]
-    NAMES = ("assemble", "lu", "apply_macro_solve", "face_combine", "other_macro_solve")
+    _fields_ = [("count", ctypes.c_int32 * 6), ("ms", ctypes.c_double * 6)]
+    NAMES = ("assemble", "lu", "apply_macro_solve", "face_combine", "other_macro_solve",
+             "folded_apply")
 
     def as_dict(self):
         return {n: {"count": int(self.count[i]), "ms": float(self.ms[i])}
@@ -87,7 +88,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_res_prec", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("t_rhs_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
-                ("n_applies", ctypes.c_int32), ("outer_iterations", ctypes.c_int32)]
+                ("n_applies", ctypes.c_int32), ("outer_iterations", ctypes.c_int32),
+                ("reorth_passes", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -289,13 +291,14 @@ class MacroMesh:
                     "mass_apply")
 
     def adjoint(self, lam, qu, dJ_dU, psi_lam, psi_U, dJ_dkappa, dJ_dbeta, rtol=1e-12,
-                restart=300, max_iter=20000, stream=None, graph=True):
+                restart=300, max_iter=20000, stream=None, graph=True, folded=False):
         import torch
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
-        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0, 0)
+        opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0,
+                         1 if folded else 0)
         info = SolveInfo()
         self._check(self._lib.mhdg_adjoint(self.h, _ptr(lam), _ptr(qu), _ptr(dJ_dU),
                                            ctypes.byref(opts), _ptr(psi_lam), _ptr(psi_U),

@@ -3,8 +3,9 @@
 Folding changes the order of the arithmetic, not the operator: the folded
 apply must equal the oracle's S lambda (and D^-1 S lambda) to the FP64
 bound (relative 1e-10) and the unfolded GPU apply to 1e-12, on uniform and
-mixed-level meshes and with several coefficient instances; a folded GMRES
-solve must match the oracle's direct solve like the plain one.
+mixed-level meshes and with several coefficient instances, forward and
+transposed; folded GMRES solves (forward and adjoint) must match the oracle
+like the plain ones.
 """
 import numpy as np
 import pytest
@@ -74,6 +75,14 @@ def test_folded_apply_matches_oracle_and_unfolded(name):
     # graph replay of the folded apply
     m.apply_trace_operator(gpu(lam), b, mhdg.MHDG_PRECONDITION | mhdg.MHDG_FOLDED | mhdg.MHDG_GRAPH)
     assert torch.equal(a, b)
+    # transposed folded operator: S^T lambda and D^-1 S^T lambda
+    S, _, _ = orc.condensed(*orc.sample(inputs.exp_sin(1.0, beta)))
+    for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
+        m.apply_trace_operator(gpu(lam), a, flags | mhdg.MHDG_FOLDED | mhdg.MHDG_TRANSPOSE)
+        m.apply_trace_operator(gpu(lam), b, flags | mhdg.MHDG_TRANSPOSE)
+        ref = S.T @ lam
+        assert rel(host(a), orc.precondition(ref) if prec else ref) <= 1e-10
+        assert rel(host(a), host(b)) <= 1e-12
 
 
 def test_folded_solve_matches_oracle():
@@ -129,11 +138,33 @@ def test_fold_state_rules():
     assert e.value.status == 7
     m.fold_operator()
     m.apply_trace_operator(x, y, mhdg.MHDG_FOLDED)
-    with pytest.raises(mhdg.MhdgError):           # transposed folded apply is not provided
-        m.apply_trace_operator(x, y, mhdg.MHDG_FOLDED | mhdg.MHDG_TRANSPOSE)
     m.factor_local(gpu(kap), beta, 1.0)           # new factors drop the folded operators
     with pytest.raises(mhdg.MhdgError):
         m.apply_trace_operator(x, y, mhdg.MHDG_FOLDED)
     m.factor_local(gpu(kap), beta, 1.0, precision=mhdg.MHDG_FP32)
     with pytest.raises(mhdg.MhdgError):           # folding needs FP64 factors
         m.fold_operator()
+
+
+def test_folded_adjoint_matches_unfolded():
+    """Adjoint gradient with folded transposed applies equals the plain one
+    (both solves to 1e-12, above this problem's attainable ~1e-13 residual
+    floor; the gradients then agree to about the solve tolerance)."""
+    from paper_2302_10917_amd import autograd as ad
+    xy, tri, r, p, kap, beta = _case("uniform_r2_p3")
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    ex = inputs.sin_sin(1.0, beta)
+    node, bnd = m.sample_points()
+    f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+    with torch.no_grad():
+        qu_obs = ad.solve(gpu(kap * 1.1), torch.tensor(beta), m, f, g, 1e-12).clone()
+    grads = []
+    for folded in (False, True):
+        k = gpu(kap).requires_grad_(True)
+        b = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
+        J = ad.l2_misfit(m, ad.solve(k, b, m, f, g, 1e-12, folded=folded), qu_obs)
+        J.backward()
+        grads.append((host(k.grad), b.grad.numpy().copy(), J.item()))
+    assert abs(grads[0][2] - grads[1][2]) <= 1e-9 * abs(grads[0][2])
+    assert rel(grads[1][0], grads[0][0]) <= 1e-8
+    assert rel(grads[1][1], grads[0][1]) <= 1e-8
