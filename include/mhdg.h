@@ -129,6 +129,11 @@ typedef struct {
   int32_t folded;             /* 1: GMRES applies (forward in solve, transposed
                                  in adjoint) use the folded operators
                                  (MHDG_FOLDED; needs mhdg_fold_operator)      */
+  int32_t classic_gs;         /* 0: Arnoldi with delayed reorthogonalisation
+                                 (one synchronisation and two passes over the
+                                 basis per iteration); 1: classical
+                                 Gram-Schmidt, second pass when the first
+                                 keeps less than 1/sqrt(2) of the norm       */
 } mhdg_solve_opts;
 
 typedef struct {

@@ -487,6 +487,8 @@ struct Gm {
   int32_t* skip = nullptr;                // per-segment flags: 1 = take no part in applies
   std::vector<int> seg_applies;           // applies each segment took part in
   int reorth = 0;                         // second Gram-Schmidt passes taken
+  bool classic = false;                   // CGS2 instead of the delayed form
+  double *pq = nullptr, *hy = nullptr, *coef = nullptr, *Hb = nullptr;  // delayed form
   double *U = nullptr, *dl = nullptr, *cl = nullptr;  // precision-refinement state
   int64_t len() const { return n * nseg; }
 };
@@ -511,9 +513,10 @@ mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags
 // preconditioned residual at the start of each cycle); a segment whose
 // estimate converges inside a cycle is masked out of the applies and its
 // Krylov columns are zero from then on.  x holds the initial guess.
-mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, double* x, double rtol,
-                  int R, int max_iter, std::vector<int>& iters, std::vector<double>& rel,
-                  int& applies, std::vector<char>& done, hipStream_t s) {
+mhdg_status gmres_cgs2(mhdg_mesh* M, Gm& G, const double* b, const double* bref, double* x,
+                       double rtol, int R, int max_iter, std::vector<int>& iters,
+                       std::vector<double>& rel, int& applies, std::vector<char>& done,
+                       hipStream_t s) {
   const int64_t n = G.n, ld = G.ld, len = G.len();
   const int ns = G.nseg;
   mhdg_status st;
@@ -677,6 +680,261 @@ mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, doub
   }
 }
 
+// GMRES with delayed reorthogonalisation: the same left-preconditioned,
+// restarted GMRES and stopping rule as gmres_cgs2, with the Arnoldi basis
+// built so that each iteration makes one host synchronisation and reads the
+// basis twice (classical Gram-Schmidt applied twice reads it four times):
+//   u_j      the new direction after one projection against q_0..q_{j-1},
+//            not yet normalised, kept in V column j;
+//   z = D^-1 S u_j                              (apply to u_j, not to q_j)
+//   p = [q_0..q_{j-1}, u_j]^T u_j, c = [q_0..q_{j-1}, u_j]^T z   (one pass)
+//   a = p[0..j), beta = sqrt(p_j - a.a): u_j's second projection and norm,
+//            which complete Arnoldi column j-1 = [h_{j-1} + a; beta]
+//   q_j = (u_j - Q a) / beta
+//   D^-1 S q_j = (z - Q_j Hbar a) / beta   (Arnoldi relation for the columns
+//            before), so the first projection of D^-1 S q_j onto Q_j is
+//            h_j = ([c_0..c_{j-1}, (c_j - a.c) / beta] - Hbar a) / beta and
+//   u_{j+1} = (z - Q_j [c; (c_j - a.c) / beta]) / beta      (one pass for both)
+// Hbar a is formed on the device from the finished columns.  A column is
+// complete one iteration after its apply, so the convergence test lags one
+// apply; the last column of a cycle is completed by a projection pass
+// without an apply.
+mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* bref, double* x,
+                          double rtol, int R, int max_iter, std::vector<int>& iters,
+                          std::vector<double>& rel, int& applies, std::vector<char>& done,
+                          hipStream_t s) {
+  const int64_t n = G.n, ld = G.ld, len = G.len();
+  const int ns = G.nseg;
+  const int64_t hld = R + 1;   // rows of Hbar
+  mhdg_status st;
+  std::vector<double> Hr(size_t(ns) * (R + 1) * R), cs(size_t(ns) * R), sn(size_t(ns) * R),
+      g(size_t(ns) * (R + 1)), hprev(size_t(ns) * (R + 1)), beta(ns), nrm(ns), y(size_t(ns) * R),
+      pq(2 * size_t(R + 2) * ns), hy(size_t(R + 2) * ns), col(size_t(R + 2) * ns),
+      coef((2 * size_t(R) + 3) * ns), alpha(ns);
+  std::vector<int32_t> skip(ns), skip_dev_copy(ns, -1);
+  std::vector<char> active(ns);
+  std::vector<int> jc(ns);
+  iters.assign(ns, 0);
+  rel.assign(ns, 0.0);
+  done.assign(ns, 0);
+  int it = 0;
+  auto push_skip = [&]() -> mhdg_status {
+    if (skip == skip_dev_copy) return MHDG_OK;
+    HIP_TRY(M, hipMemcpyAsync(G.skip, skip.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    skip_dev_copy = skip;
+    return MHDG_OK;
+  };
+  for (int q = 0; q < ns; ++q) {
+    if (bref[q] == 0.0) {
+      HIP_TRY(M, hipMemsetAsync(x + q * n, 0, n * sizeof(double), s));
+      done[q] = 1;
+    }
+    skip[q] = done[q];
+  }
+  double* const ca = G.coef;
+  double* const cd = G.coef + size_t(R) * ns;
+  double* const sc = G.coef + 2 * size_t(R) * ns;
+  while (true) {
+    // ---- true preconditioned residual, cycle start
+    if ((st = push_skip())) return st;
+    if ((st = apply_op(M, x, G.tv, G.op_flags, G.skip, s))) return st;
+    ++applies;
+    for (int q = 0; q < ns; ++q) G.seg_applies[q] += !skip[q];
+    HIP_TRY(M, launch_scale_copy(1.0, b, G.rv, len, s));
+    HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, len, s));
+    if ((st = dot(M, G, G.rv, G.rv, nrm.data(), s))) return st;
+    bool any = false;
+    jc.assign(ns, 0);
+    for (int q = 0; q < ns; ++q) {
+      if (!done[q]) {
+        beta[q] = std::sqrt(nrm[q]);
+        rel[q] = beta[q] / bref[q];
+        if (rel[q] <= rtol || beta[q] == 0.0) done[q] = 1;
+      }
+      active[q] = !done[q];
+      alpha[q] = active[q] ? 1.0 : 0.0;
+      skip[q] = !active[q];
+      any |= active[q] != 0;
+      std::fill(g.begin() + q * (R + 1), g.begin() + (q + 1) * (R + 1), 0.0);
+      g[q * (R + 1)] = active[q] ? beta[q] : 0.0;
+    }
+    if (!any || it >= max_iter) return MHDG_OK;
+    if ((st = push_skip())) return st;
+    HIP_TRY(M, hipMemcpyAsync(G.adev, alpha.data(), ns * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(M, launch_seg_scale_copy(G.adev, G.rv, G.V, n, ns, s));   // u_0 = r
+    int j = 0;
+    while (true) {
+      const bool last = j == R || it >= max_iter;
+      double* u = G.V + j * ld;
+      if (!last) {
+        const double* uin = u;
+        if (G.op_flags & MHDG_GRAPH) {   // the captured graph reads a fixed input vector
+          HIP_TRY(M, hipMemcpyAsync(G.xin, u, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+          uin = G.xin;
+        }
+        if ((st = apply_op(M, uin, G.wv, G.op_flags, G.skip, s))) return st;   // z = A u_j
+        ++applies;
+        ++it;
+        for (int q = 0; q < ns; ++q) G.seg_applies[q] += !skip[q];
+        HIP_TRY(M, launch_dots2(G.V, ld, j + 1, u, G.wv, n, G.partial, G.nblk, G.pq, s, ns));
+      } else {
+        // complete the last column: projections of u_j only
+        HIP_TRY(M, launch_dots(G.V, ld, j + 1, u, n, G.partial, G.nblk, G.hy, s, ns));
+      }
+      if (!last && j >= 2)
+        HIP_TRY(M, launch_hbar_gemv(G.Hb, hld, ns, j - 1, j, G.pq, G.hy, s));
+      if (!last) {
+        HIP_TRY(M, hipMemcpyAsync(pq.data(), G.pq, 2 * size_t(j + 1) * ns * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+        if (j >= 2)
+          HIP_TRY(M, hipMemcpyAsync(hy.data(), G.hy, size_t(j) * ns * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+      } else {
+        // same layout as dots2's first products: pq[(2c) ns + q]
+        std::vector<double> pl(size_t(j + 1) * ns);
+        HIP_TRY(M, hipMemcpyAsync(pl.data(), G.hy, pl.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+        HIP_TRY(M, hipStreamSynchronize(s));
+        for (int c = 0; c <= j; ++c)
+          for (int q = 0; q < ns; ++q) pq[(2 * size_t(c)) * ns + q] = pl[size_t(c) * ns + q];
+      }
+      HIP_TRY(M, hipStreamSynchronize(s));
+      any = false;
+      for (int q = 0; q < ns; ++q) {
+        if (!active[q]) continue;
+        // u_j's second projection and norm
+        double aa = 0.0;
+        for (int c = 0; c < j; ++c) { const double ac = pq[(2 * size_t(c)) * ns + q]; aa += ac * ac; }
+        const double om = pq[(2 * size_t(j)) * ns + q];
+        const double bt = std::sqrt(std::max(om - aa, 0.0));
+        beta[q] = bt;
+        if (j >= 1) {
+          // finish Arnoldi column j-1 = [h_{j-1} + a; beta], rotate, test
+          double* Hq = &Hr[size_t(q) * (R + 1) * R];
+          double* c_ = &cs[size_t(q) * R];
+          double* s_ = &sn[size_t(q) * R];
+          double* gq = &g[size_t(q) * (R + 1)];
+          const int jj = j - 1;
+          for (int i = 0; i < j; ++i) {
+            const double v = hprev[size_t(q) * (R + 1) + i] + pq[(2 * size_t(i)) * ns + q];
+            col[size_t(i) * ns + q] = v;
+            Hq[i * R + jj] = v;
+          }
+          col[size_t(j) * ns + q] = bt;
+          Hq[j * R + jj] = bt;
+          for (int i = 0; i < jj; ++i) {
+            const double a_ = Hq[i * R + jj], b_ = Hq[(i + 1) * R + jj];
+            Hq[i * R + jj] = c_[i] * a_ + s_[i] * b_;
+            Hq[(i + 1) * R + jj] = -s_[i] * a_ + c_[i] * b_;
+          }
+          const double a_ = Hq[jj * R + jj], b_ = Hq[(jj + 1) * R + jj];
+          const double rr = std::hypot(a_, b_);
+          c_[jj] = rr == 0 ? 1.0 : a_ / rr;
+          s_[jj] = rr == 0 ? 0.0 : b_ / rr;
+          Hq[jj * R + jj] = rr;
+          Hq[(jj + 1) * R + jj] = 0.0;
+          gq[jj + 1] = -s_[jj] * gq[jj];
+          gq[jj] = c_[jj] * gq[jj];
+          rel[q] = std::fabs(gq[jj + 1]) / bref[q];
+          jc[q] = j;
+          ++iters[q];
+          if (rel[q] <= rtol || bt == 0.0) { active[q] = 0; skip[q] = 1; }
+        } else if (bt == 0.0) {
+          active[q] = 0;
+          skip[q] = 1;
+        }
+        any |= active[q] != 0;
+      }
+      if (g_progress && !last && it % g_progress == 0) {
+        double worst = 0;
+        for (int q = 0; q < ns; ++q)
+          if (!done[q]) worst = std::max(worst, rel[q]);
+        std::fprintf(stderr, "[mhdg] gmres iteration %d relative residual %.3e\n", it, worst);
+        std::fflush(stderr);
+      }
+      if (j >= 1) {   // finished column j-1 of every segment to the device copy of Hbar
+        for (int q = 0; q < ns; ++q)
+          if (jc[q] != j)   // segments that were already inactive: zero column
+            for (int i = 0; i <= j; ++i) col[size_t(i) * ns + q] = 0.0;
+        HIP_TRY(M, hipMemcpyAsync(G.Hb + (size_t(j - 1) * hld) * ns, col.data(),
+                                  size_t(j + 1) * ns * sizeof(double), hipMemcpyHostToDevice, s));
+      }
+      if (last || !any) break;
+      // coefficients of q_j and u_{j+1}
+      for (int q = 0; q < ns; ++q) {
+        double* cc = coef.data();
+        double* cdd = coef.data() + size_t(R) * ns;
+        double* scc = coef.data() + 2 * size_t(R) * ns;
+        if (!active[q]) {
+          for (int c = 0; c < j; ++c) { cc[size_t(c) * ns + q] = 0.0; cdd[size_t(c) * ns + q] = 0.0; }
+          scc[q] = scc[ns + q] = scc[2 * ns + q] = 0.0;
+          continue;
+        }
+        const double bt = beta[q];
+        double ab = 0.0;
+        for (int c = 0; c < j; ++c) ab += pq[(2 * size_t(c)) * ns + q] * pq[(2 * size_t(c) + 1) * ns + q];
+        const double cj = (pq[(2 * size_t(j) + 1) * ns + q] - ab) / bt;
+        // Hbar a: device part (columns < j-1) plus the column just finished
+        double* hp = &hprev[size_t(q) * (R + 1)];
+        const double aj1 = j >= 1 ? pq[(2 * size_t(j - 1)) * ns + q] : 0.0;
+        for (int i = 0; i <= j; ++i) {
+          double hba = (j >= 2 && i < j) ? hy[size_t(i) * ns + q] : 0.0;
+          if (j >= 1) hba += aj1 * col[size_t(i) * ns + q];
+          const double ci = i < j ? pq[(2 * size_t(i) + 1) * ns + q] : cj;
+          hp[i] = (ci - hba) / bt;
+        }
+        for (int c = 0; c < j; ++c) {
+          const double ac = pq[(2 * size_t(c)) * ns + q];
+          cc[size_t(c) * ns + q] = ac / bt;
+          cdd[size_t(c) * ns + q] = (pq[(2 * size_t(c) + 1) * ns + q] - (cj / bt) * ac) / bt;
+        }
+        scc[q] = 1.0 / bt;
+        scc[ns + q] = 1.0 / bt;
+        scc[2 * ns + q] = -cj / (bt * bt);
+      }
+      HIP_TRY(M, hipMemcpyAsync(ca, coef.data(), size_t(j) * ns * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+      HIP_TRY(M, hipMemcpyAsync(cd, coef.data() + size_t(R) * ns, size_t(j) * ns * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+      HIP_TRY(M, hipMemcpyAsync(sc, coef.data() + 2 * size_t(R) * ns, 3 * size_t(ns) * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+      HIP_TRY(M, launch_dual_update(G.V, ld, j, n, ns, ca, cd, sc, G.wv, s));
+      if ((st = push_skip())) return st;
+      ++j;
+    }
+    // ---- x_q += Q y_q with R_q y_q = g_q over jc[q] columns
+    int jmax = 0;
+    std::fill(y.begin(), y.end(), 0.0);
+    for (int q = 0; q < ns; ++q) {
+      const int jq = jc[q];
+      jmax = std::max(jmax, jq);
+      const double* Hq = &Hr[size_t(q) * (R + 1) * R];
+      const double* gq = &g[size_t(q) * (R + 1)];
+      std::vector<double> yq(jq);
+      for (int i = jq - 1; i >= 0; --i) {
+        double v = gq[i];
+        for (int kk = i + 1; kk < jq; ++kk) v -= Hq[i * R + kk] * yq[kk];
+        yq[i] = v / Hq[i * R + i];
+      }
+      for (int i = 0; i < jq; ++i) y[size_t(i) * ns + q] = yq[i];
+    }
+    if (jmax > 0) {
+      HIP_TRY(M, hipMemcpyAsync(G.ydev, y.data(), size_t(jmax) * ns * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+      HIP_TRY(M, launch_gemv_sub(G.V, ld, jmax, G.ydev, x, n, 1.0, s, ns));
+    }
+    HIP_TRY(M, hipStreamSynchronize(s));
+    for (int q = 0; q < ns; ++q) skip[q] = done[q];
+  }
+}
+
+mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, double* x, double rtol,
+                  int R, int max_iter, std::vector<int>& iters, std::vector<double>& rel,
+                  int& applies, std::vector<char>& done, hipStream_t s) {
+  return G.classic ? gmres_cgs2(M, G, b, bref, x, rtol, R, max_iter, iters, rel, applies, done, s)
+                   : gmres_delayed(M, G, b, bref, x, rtol, R, max_iter, iters, rel, applies, done, s);
+}
+
 mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
   G.nseg = M->n_inst;
   G.n = M->n_trace / M->n_inst;
@@ -696,7 +954,15 @@ mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
   size_t off = align_up(vb * (R + 9));
   G.nblk = dots_nblk(G.n);
   G.partial = (double*)(w + off);
-  off += align_up(size_t(G.nblk) * G.nseg * (R + 2) * sizeof(double));
+  off += align_up(2 * size_t(G.nblk) * G.nseg * (R + 2) * sizeof(double));
+  G.pq = (double*)(w + off);
+  off += align_up(2 * size_t(R + 2) * G.nseg * 8);
+  G.hy = (double*)(w + off);
+  off += align_up(size_t(R + 2) * G.nseg * 8);
+  G.coef = (double*)(w + off);
+  off += align_up((2 * size_t(R) + 3) * G.nseg * 8);
+  G.Hb = (double*)(w + off);
+  off += align_up(size_t(R + 1) * R * G.nseg * 8);
   G.hdev = (double*)(w + off);
   off += align_up(size_t(R + 2) * G.nseg * 8);
   G.ydev = (double*)(w + off);
@@ -1606,7 +1872,9 @@ static size_t solve_bytes_impl(const mhdg_mesh* M, int R) {
   const size_t ns = size_t(M->n_inst);
   const size_t vb = align_up(size_t(M->n_trace) * sizeof(double));
   const size_t nblk = size_t(dots_nblk(M->n_trace / M->n_inst));
-  return align_up(vb * (R + 9)) + align_up(nblk * ns * size_t(R + 2) * sizeof(double)) +
+  return align_up(vb * (R + 9)) + align_up(2 * nblk * ns * size_t(R + 2) * sizeof(double)) +
+         align_up(2 * size_t(R + 2) * ns * 8) + align_up(size_t(R + 2) * ns * 8) +
+         align_up((2 * size_t(R) + 3) * ns * 8) + align_up(size_t(R + 1) * R * ns * 8) +
          2 * align_up(size_t(R + 2) * ns * 8) + align_up(ns * 8) + align_up(ns * 4) +
          align_up(size_t(M->n_local) * sizeof(double));
 }
@@ -1630,6 +1898,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   Gm G;
   carve(M, ws, R, G);
   if (o->graph) G.op_flags |= MHDG_GRAPH;
+  G.classic = o->classic_gs != 0;
   if (o->folded) {
     if (!M->folded || M->precision != MHDG_FP64)
       return fail(M, MHDG_ERR_STATE, "solve: folded applies need mhdg_fold_operator");
@@ -1804,6 +2073,7 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
   Gm G;
   carve(M, ws, o->restart, G);
   G.op_flags = MHDG_PRECONDITION | MHDG_TRANSPOSE | (o->graph ? MHDG_GRAPH : 0);
+  G.classic = o->classic_gs != 0;
   if (o->folded) {
     if (!M->folded) return fail(M, MHDG_ERR_STATE, "adjoint: folded applies need mhdg_fold_operator");
     G.op_flags |= MHDG_FOLDED;

@@ -168,6 +168,15 @@ hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double*
                            int64_t n, double sign, hipStream_t s, int nseg = 1);
 hipError_t launch_seg_scale_copy(const double* alpha, const double* x, double* y, int64_t n, int nseg,
                                  hipStream_t s);
+// delayed-reorthogonalisation Arnoldi (see host gmres): two products per
+// column in one read of V, the Hessenberg correction, the fused two-output update
+hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x, const double* y,
+                        int64_t n, double* partial, int nblk, double* out, hipStream_t s,
+                        int nseg);
+hipError_t launch_hbar_gemv(const double* Hb, int64_t ld, int nseg, int kmax, int rows,
+                            const double* pq, double* out, hipStream_t s);
+hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg, const double* ca,
+                              const double* cd, const double* sc, const double* z, hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);
 int dots_nblk(int64_t n);

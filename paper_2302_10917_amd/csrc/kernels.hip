@@ -744,6 +744,147 @@ __global__ __launch_bounds__(256) void dots_partial_kernel(const double* __restr
   if (lane == 0) partial[(int64_t(c) * nseg + seg) * nblk + blk] = acc;
 }
 
+// Two inner products per column in one read of V: for column c and segment
+// seg, partial[((2c + 0) nseg + seg) nblk + blk] = <V_c, x> and
+// partial[((2c + 1) nseg + seg) nblk + blk] = <V_c, y> over one chunk.  Each
+// wavefront takes two columns (c and c + 4 of its block's eight), so every
+// load of x and y serves two columns.
+__global__ __launch_bounds__(256) void dots2_partial_kernel(const double* __restrict__ V, int64_t ld,
+                                                            int ncols, const double* __restrict__ x,
+                                                            const double* __restrict__ y, int64_t n,
+                                                            double* __restrict__ partial) {
+  const int nblk = n > kDotChunk ? (int)((n + kDotChunk - 1) / kDotChunk) : 1;
+  const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+  const int nseg = gridDim.x / nblk;
+  const int c0 = blockIdx.y * 8 + (threadIdx.x >> 6), c1 = c0 + 4;
+  const int lane = threadIdx.x & 63;
+  if (c0 >= ncols) return;
+  const bool two = c1 < ncols;
+  const double* v0p = V + c0 * ld + int64_t(seg) * n;
+  const double* v1p = V + (two ? c1 : c0) * ld + int64_t(seg) * n;
+  x += int64_t(seg) * n;
+  y += int64_t(seg) * n;
+  const int64_t i0 = int64_t(blk) * kDotChunk;
+  const int64_t i1 = i0 + kDotChunk < n ? i0 + kDotChunk : n;
+  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, e0 = 0.0, e1 = 0.0, f0 = 0.0, f1 = 0.0;
+  int64_t i = i0 + lane;
+  for (; i + 64 < i1; i += 128) {
+    const double x0 = x[i], x1 = x[i + 64], y0 = y[i], y1 = y[i + 64];
+    const double p0 = v0p[i], p1 = v0p[i + 64], q0 = v1p[i], q1 = v1p[i + 64];
+    a0 += p0 * x0;
+    a1 += p1 * x1;
+    b0 += p0 * y0;
+    b1 += p1 * y1;
+    e0 += q0 * x0;
+    e1 += q1 * x1;
+    f0 += q0 * y0;
+    f1 += q1 * y1;
+  }
+  for (; i < i1; i += 64) {
+    const double x0 = x[i], y0 = y[i], p0 = v0p[i], q0 = v1p[i];
+    a0 += p0 * x0;
+    b0 += p0 * y0;
+    e0 += q0 * x0;
+    f0 += q0 * y0;
+  }
+  const double sa = wave_sum(a0 + a1), sb = wave_sum(b0 + b1);
+  const double se = wave_sum(e0 + e1), sf = wave_sum(f0 + f1);
+  if (lane == 0) {
+    partial[(int64_t(2 * c0) * nseg + seg) * nblk + blk] = sa;
+    partial[(int64_t(2 * c0 + 1) * nseg + seg) * nblk + blk] = sb;
+    if (two) {
+      partial[(int64_t(2 * c1) * nseg + seg) * nblk + blk] = se;
+      partial[(int64_t(2 * c1 + 1) * nseg + seg) * nblk + blk] = sf;
+    }
+  }
+}
+
+// Hessenberg correction of the delayed reorthogonalisation:
+// out[i nseg + seg] = sum_{k < kmax, k >= i - 1} a_k Hb[(k ld + i) nseg + seg],
+// with a_k = pq[(2k) nseg + seg] (the first products of dots2) and Hb the
+// finished (unrotated) Hessenberg columns, column k holding rows 0..k+1.
+// Block of 64 (row, segment) pairs x 8 groups of k; the 8 partial sums meet in LDS.
+__global__ __launch_bounds__(512) void hbar_gemv_kernel(const double* __restrict__ Hb, int64_t ld,
+                                                        int nseg, int kmax, int rows,
+                                                        const double* __restrict__ pq,
+                                                        double* __restrict__ out) {
+  __shared__ double red[8][64];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t t = blockIdx.x * int64_t(64) + lane;
+  double acc = 0.0;
+  if (t < int64_t(rows) * nseg) {
+    const int i = (int)(t / nseg), seg = (int)(t % nseg);
+    const int k0 = i > 0 ? i - 1 : 0;
+#pragma unroll 4
+    for (int kk = k0 + grp; kk < kmax; kk += 8)
+      acc += pq[int64_t(2 * kk) * nseg + seg] * Hb[(int64_t(kk) * ld + i) * nseg + seg];
+  }
+  red[grp][lane] = acc;
+  __syncthreads();
+  if (grp == 0 && t < int64_t(rows) * nseg) {
+    double s = 0.0;
+#pragma unroll
+    for (int g2 = 0; g2 < 8; ++g2) s += red[g2][lane];
+    out[t] = s;
+  }
+}
+
+// Fused update of the delayed reorthogonalisation, one read of V_0..V_{j-1}:
+//   V_j     <- s1 u - sum_k ca_k V_k          (u = V_j on entry: q_j)
+//   V_{j+1} <- s2 z + s3 u - sum_k cd_k V_k   (the next once-orthogonalised vector)
+// coefficients per segment: ca, cd [k nseg + seg], s [3 nseg] = (s1, s2, s3).
+// One element per lane; when a wavefront lies in one segment (all but the
+// few straddling a segment boundary) its coefficients are wave-uniform and
+// read with scalar loads, leaving one vector load per column.
+__global__ __launch_bounds__(256) void dual_update_kernel(double* __restrict__ V, int64_t ld, int j,
+                                                          int64_t n, int nseg,
+                                                          const double* __restrict__ ca,
+                                                          const double* __restrict__ cd,
+                                                          const double* __restrict__ sc,
+                                                          const double* __restrict__ z) {
+  const int64_t total = n * nseg;
+  const int64_t idx0 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const bool ok = idx0 < total;
+  const int64_t idx = ok ? idx0 : total - 1;   // in-bounds address; result discarded
+  const int seg = (int)(idx / n);
+  const int seg0 = __builtin_amdgcn_readfirstlane(seg);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  if (__all(seg == seg0)) {
+    const double* cas = ca + seg0;
+    const double* cds = cd + seg0;
+    int k = 0;
+    for (; k + 3 < j; k += 4) {
+      const double v0 = V[k * ld + idx], v1 = V[(k + 1) * ld + idx];
+      const double v2 = V[(k + 2) * ld + idx], v3 = V[(k + 3) * ld + idx];
+      a0 += cas[int64_t(k) * nseg] * v0;
+      d0 += cds[int64_t(k) * nseg] * v0;
+      a1 += cas[int64_t(k + 1) * nseg] * v1;
+      d1 += cds[int64_t(k + 1) * nseg] * v1;
+      a2 += cas[int64_t(k + 2) * nseg] * v2;
+      d2 += cds[int64_t(k + 2) * nseg] * v2;
+      a3 += cas[int64_t(k + 3) * nseg] * v3;
+      d3 += cds[int64_t(k + 3) * nseg] * v3;
+    }
+    for (; k < j; ++k) {
+      const double v0 = V[k * ld + idx];
+      a0 += cas[int64_t(k) * nseg] * v0;
+      d0 += cds[int64_t(k) * nseg] * v0;
+    }
+  } else {
+    for (int k = 0; k < j; ++k) {
+      const double v0 = V[k * ld + idx];
+      a0 += ca[int64_t(k) * nseg + seg] * v0;
+      d0 += cd[int64_t(k) * nseg + seg] * v0;
+    }
+  }
+  if (!ok) return;
+  const double u = V[j * ld + idx];
+  const double s1 = sc[seg], s2 = sc[nseg + seg], s3 = sc[2 * nseg + seg];
+  // masked segments (all coefficients zero) become exact zeros
+  V[j * ld + idx] = s1 == 0.0 ? 0.0 : s1 * u - ((a0 + a1) + (a2 + a3));
+  V[(j + 1) * ld + idx] = s2 == 0.0 ? 0.0 : s2 * z[idx] + s3 * u - ((d0 + d1) + (d2 + d3));
+}
+
 // out[c * nseg + seg] = sum over the chunks of (column c, segment seg)
 __global__ __launch_bounds__(64) void dots_final_kernel(const double* __restrict__ partial, int nblk,
                                                         double* __restrict__ out) {
@@ -1072,6 +1213,31 @@ hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double*
   if (ncols == 0) return hipSuccess;
   hipLaunchKernelGGL(gemv_sub_kernel, dim3(blocks_for(n * nseg, 256)), dim3(256), 0, s, V, ld,
                      ncols, h, w, n, nseg, sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x, const double* y,
+                        int64_t n, double* partial, int nblk, double* out, hipStream_t s,
+                        int nseg) {
+  hipLaunchKernelGGL(dots2_partial_kernel, dim3(nblk * nseg, (ncols + 7) / 8), dim3(256), 0, s, V,
+                     ld, ncols, x, y, n, partial);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(2 * ncols * nseg), dim3(64), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_hbar_gemv(const double* Hb, int64_t ld, int nseg, int kmax, int rows,
+                            const double* pq, double* out, hipStream_t s) {
+  const int64_t tot = int64_t(rows) * nseg;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(hbar_gemv_kernel, dim3(blocks_for(tot, 64)), dim3(512), 0, s, Hb, ld, nseg,
+                     kmax, rows, pq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg, const double* ca,
+                              const double* cd, const double* sc, const double* z, hipStream_t s) {
+  hipLaunchKernelGGL(dual_update_kernel, dim3(blocks_for(n * nseg, 256)), dim3(256), 0, s, V, ld,
+                     j, n, nseg, ca, cd, sc, z);
   return hipGetLastError();
 }
 

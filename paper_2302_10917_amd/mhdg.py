@@ -53,7 +53,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("zero_guess", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("graph", ctypes.c_int32), ("folded", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("folded", ctypes.c_int32),
+                ("classic_gs", ctypes.c_int32)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -267,7 +268,8 @@ class MacroMesh:
                                        _stream(stream)), "rhs")
 
     def solve(self, f_nodes, g_bnd, lam, rtol=1e-10, restart=30, max_iter=10000, zero_guess=True,
-              stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True, folded=False):
+              stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True, folded=False,
+              classic_gs=False):
         import torch
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
@@ -275,7 +277,7 @@ class MacroMesh:
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1 if zero_guess else 0,
                          int(max_outer), float(inner_rtol), 1 if graph else 0,
-                         1 if folded else 0)
+                         1 if folded else 0, 1 if classic_gs else 0)
         infos = (SolveInfo * max(1, s.n_instances))()
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
                                   _ptr(self.solve_ws), self.solve_ws.numel(),
@@ -291,14 +293,15 @@ class MacroMesh:
                     "mass_apply")
 
     def adjoint(self, lam, qu, dJ_dU, psi_lam, psi_U, dJ_dkappa, dJ_dbeta, rtol=1e-12,
-                restart=300, max_iter=20000, stream=None, graph=True, folded=False):
+                restart=300, max_iter=20000, stream=None, graph=True, folded=False,
+                classic_gs=False):
         import torch
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0,
-                         1 if folded else 0)
+                         1 if folded else 0, 1 if classic_gs else 0)
         info = SolveInfo()
         self._check(self._lib.mhdg_adjoint(self.h, _ptr(lam), _ptr(qu), _ptr(dJ_dU),
                                            ctypes.byref(opts), _ptr(psi_lam), _ptr(psi_U),

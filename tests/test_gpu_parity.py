@@ -209,3 +209,24 @@ def test_not_converged_status():
     lam = torch.zeros(orc.topo.n_trace, dtype=torch.float64, device=DEV)
     info = m.solve(gpu(f), gpu(g), lam, rtol=1e-14, restart=5, max_iter=2, check=False)
     assert info.status == 4 and info.iterations == 2
+
+
+@pytest.mark.parametrize("restart", [7, 300])
+def test_delayed_and_classical_gram_schmidt_agree(restart):
+    """Arnoldi with delayed reorthogonalisation (default) and classical
+    Gram-Schmidt with a second pass build the same Krylov basis up to
+    rounding: the same number of Arnoldi columns to the same tolerance, and
+    iterates that agree to the tolerance; both match the oracle."""
+    orc, m, _ = build_case("mixed_levels_p2")
+    f, g, fo, go = _data(orc, m, orc.beta)
+    lam_o, _, _ = orc.solve(fo, go)
+    out = []
+    for classic in (False, True):
+        lam = torch.zeros(orc.topo.n_trace, dtype=torch.float64, device=DEV)
+        info = m.solve(gpu(f), gpu(g), lam, rtol=1e-12, restart=restart, max_iter=5000,
+                       classic_gs=classic)
+        assert info.status == 0 and info.rel_res_prec <= 1e-12
+        out.append((host(lam), info.iterations))
+        assert rel(out[-1][0], lam_o) <= 1e-9
+    assert abs(out[0][1] - out[1][1]) <= 1 + out[1][1] // 50
+    assert rel(out[0][0], out[1][0]) <= 1e-9
