@@ -45,6 +45,9 @@ WORKLOADS = {
     # precision configuration: same mesh, kappa = 1e-3, FP32 factors + FP64 refinement
     "fp32ir_8192macro_r3_p3_kappa1e-3": dict(n=64, r=3, p=3, kappa=1e-3, beta=(1.0, 0.5),
                                              sol="exp_sin", precision="fp32"),
+    # BF16 factors (FP32 LU rounded for storage) + FP64 refinement, same mesh and data
+    "bf16ir_8192macro_r3_p3_kappa1e-3": dict(n=64, r=3, p=3, kappa=1e-3, beta=(1.0, 0.5),
+                                             sol="exp_sin", precision="bf16", inner_rtol=1e-2),
     "plain_fp64_8192macro_r3_p3_kappa1e-3": dict(n=64, r=3, p=3, kappa=1e-3, beta=(1.0, 0.5),
                                                  sol="exp_sin", precision="fp64"),
     # differentiation configuration: 128 x 128 squares (32,768 macros), r = 2, p = 2,
@@ -173,8 +176,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=None,
                     help="GMRES relative tolerance (default 1e-10; 1e-9 for the differentiation "
                          "workload, whose 440,064-unknown trace system stalls near 1e-10)")
-    ap.add_argument("--inner-rtol", type=float, default=1e-5,
-                    help="inner GMRES tolerance per refinement step (FP32 factors)")
+    ap.add_argument("--inner-rtol", type=float, default=None,
+                    help="inner GMRES tolerance per refinement step (reduced-precision factors; "
+                         "default 1e-5 for FP32, 1e-2 for BF16)")
     ap.add_argument("--fd-check", action="store_true",
                     help="differentiation workload: central differences of J on sampled kappa_K "
                          "and on both advection components, against the adjoint gradient")
@@ -211,6 +215,8 @@ def main():
         args.restart = w.get("restart", 2000)
     if args.rtol is None:
         args.rtol = w.get("rtol", 1e-10)
+    if args.inner_rtol is None:
+        args.inner_rtol = w.get("inner_rtol", 1e-5)
     if w.get("form") == "adjoint":
         return bench_adjoint(args, w)
     folded = w.get("form") == "folded" or args.folded
@@ -253,7 +259,7 @@ def main():
     infos = []
     Q = s.n_nodes // s.n_macro
 
-    prec = mhdg.MHDG_FP32 if w["precision"] == "fp32" else mhdg.MHDG_FP64
+    prec = {"fp32": mhdg.MHDG_FP32, "bf16": mhdg.MHDG_BF16}.get(w["precision"], mhdg.MHDG_FP64)
 
     inst_infos = []
 
@@ -262,7 +268,8 @@ def main():
         if folded:
             m.fold_operator()
         info = m.solve(f, g, lam, rtol=args.rtol, restart=args.restart, max_iter=args.max_iter,
-                       check=args.max_iter >= 20000, inner_rtol=args.inner_rtol, folded=folded)
+                       check=args.max_iter >= 20000, inner_rtol=args.inner_rtol, folded=folded,
+                       max_outer=60)
         m.recover_local(lam, qu)
         infos.append(info.as_dict())
         inst_infos.append(m.last_solve_infos)
@@ -385,7 +392,7 @@ def main():
 
     ams = kt["folded_apply" if folded else "apply_macro_solve"]
     avg_ms = ams["ms"] / max(ams["count"], 1)
-    nbytes = apply_bytes(m, 4 if prec == mhdg.MHDG_FP32 else 8,
+    nbytes = apply_bytes(m, {mhdg.MHDG_FP32: 4, mhdg.MHDG_BF16: 2}.get(prec, 8),
                          None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"])
     if folded:
         # folded apply: T_K read once (8 L_K^2), the gathered trace and the slots
@@ -410,7 +417,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == mhdg.MHDG_FP64 else "f32 factors, f64 refinement",
+        "dtype": {mhdg.MHDG_FP64: "f64", mhdg.MHDG_FP32: "f32 factors, f64 refinement",
+                  mhdg.MHDG_BF16: "bf16 factors (f32 LU), f64 refinement"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "n_macro": s.n_macro, "n_instances": n_inst,
                    "r": w["r"] if np.ndim(w["r"]) == 0 else "U{1,2,3,4} seed 3", "p": w["p"],
@@ -421,7 +429,9 @@ def main():
                    "tau": 1.0, "rtol": args.rtol, "gmres_restart": args.restart,
                    "form": ("folded_fp64" if folded else
                             "batched_fp64" if n_inst > 1 else "plain_fp64")
-                   if prec == mhdg.MHDG_FP64 else "fp32_factors_fp64_ir"},
+                   if prec == mhdg.MHDG_FP64 else
+                   ("fp32_factors_fp64_ir" if prec == mhdg.MHDG_FP32 else "bf16_factors_fp64_ir"),
+                   "inner_rtol": args.inner_rtol if prec != mhdg.MHDG_FP64 else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["traffic_bytes_per_launch"] / 1e9 if traffic else None,
@@ -430,8 +440,9 @@ def main():
                      "traffic_vs_algorithmic": traffic["traffic_bytes_per_launch"] / nbytes
                      if traffic else None,
                      "kernel": ("fold_apply_kernel (folded steps 1-3)" if folded else
-                                ("macro_solve_kernel<double>" if prec == mhdg.MHDG_FP64
-                                 else "macro_solve_kernel<float>") + " (apply steps 1-3)"),
+                                "macro_solve_kernel<%s> (apply steps 1-3)"
+                                % {mhdg.MHDG_FP64: "double", mhdg.MHDG_FP32: "float",
+                                   mhdg.MHDG_BF16: "bf16_t"}[prec]),
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
                      "launches": ams["count"]},
         "time_to_solve_s": ms_per_step / 1e3,

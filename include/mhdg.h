@@ -80,7 +80,10 @@ typedef enum {
 
 typedef enum {
   MHDG_FP64 = 0,              /* FP64 factors (the plain form)                 */
-  MHDG_FP32 = 1               /* FP32 factors on MFMA, FP64 refinement         */
+  MHDG_FP32 = 1,              /* FP32 factors on MFMA, FP64 refinement         */
+  MHDG_BF16 = 2               /* FP32 LU on MFMA rounded to BF16 for storage
+                                 (a quarter of the FP64 bytes per apply; N_K
+                                 <= 1024), FP64 refinement                    */
 } mhdg_precision;
 
 /* flags for apply_trace_operator / local_solve */
@@ -186,7 +189,9 @@ mhdg_status mhdg_sample_points(const mhdg_mesh* mesh, double* node_xy, double* b
 
 /* Assemble every A_K (section 3.2 forms: blocks [[M,0,-E^x],[0,M,-E^y],
  * [kappa H^x, kappa H^y, K]]) and factor it in place with partial row
- * pivoting (ties to the smallest row), in the requested precision.
+ * pivoting (ties to the smallest row), in the requested precision (BF16:
+ * the FP32 factors are rounded to nearest-even BF16 for storage; the
+ * refinement of solve and recover_local restores FP64 accuracy).
  * kappa: device f64[n_macro]; a = (beta_x, beta_y) constant; tau > 0.
  * ws: device workspace of at least factor_ws_bytes (mhdg_query with the
  * same precision); it must stay allocated while the handle uses it.

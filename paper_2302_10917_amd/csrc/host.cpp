@@ -423,16 +423,26 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   L.work1 = o;  o = align_up(o + size_t(M->n_local) * sizeof(double));
   L.work2 = o;  o = align_up(o + size_t(M->n_local) * sizeof(double));
   L.factors = o;
-  size_t es = precision == MHDG_FP32 ? 4 : 8;
-  size_t nf = 0;
-  for (auto& mi : M->macros) nf += size_t(mi.N) * mi.N;
-  (void)es;
+  // element count of the factor blocks: offsets are padded to 64 elements per
+  // macro, and the column-streaming solves may read up to 64 x 64 elements
+  // past a block's end (guard tail)
+  const MacroInfo& last = M->macros.back();
+  const size_t nf = size_t(last.fac_off) + size_t(last.N) * last.N + kFactorGuard;
+  const size_t es = precision == MHDG_FP64 ? 8 : 4;   // BF16 factors are factored in FP32
   o = align_up(o + nf * es);
+  L.factors16 = o;
+  if (precision == MHDG_BF16) o = align_up(o + nf * 2);
   L.total = o;
   return L;
 }
 
 static size_t solve_bytes_impl(const mhdg_mesh* M, int R);
+// precision the assembly and LU run in (BF16 factors are factored in FP32)
+static int lu_precision(int precision) { return precision == MHDG_BF16 ? MHDG_FP32 : precision; }
+// the factors the per-macro solves read
+static const void* solve_factors(const mhdg_mesh* M) {
+  return M->ws + (M->precision == MHDG_BF16 ? M->L.factors16 : M->L.factors);
+}
 static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const double* lam,
                                    const double* xin, double* yout, hipStream_t s,
                                    const int32_t* skip = nullptr);
@@ -560,6 +570,8 @@ mhdg_status gmres_cgs2(mhdg_mesh* M, Gm& G, const double* b, const double* bref,
     for (int q = 0; q < ns; ++q) {
       if (done[q]) { active[q] = 0; alpha[q] = 0.0; skip[q] = 1; continue; }
       beta[q] = std::sqrt(nrm[q]);
+      if (!std::isfinite(beta[q]) || !std::isfinite(bref[q]))
+        return fail(M, MHDG_ERR_NOT_CONVERGED, "gmres: non-finite residual");
       rel[q] = beta[q] / bref[q];
       if (rel[q] <= rtol) done[q] = 1;
       active[q] = !done[q];
@@ -748,6 +760,8 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
     for (int q = 0; q < ns; ++q) {
       if (!done[q]) {
         beta[q] = std::sqrt(nrm[q]);
+        if (!std::isfinite(beta[q]) || !std::isfinite(bref[q]))
+          return fail(M, MHDG_ERR_NOT_CONVERGED, "gmres: non-finite residual");
         rel[q] = beta[q] / bref[q];
         if (rel[q] <= rtol || beta[q] == 0.0) done[q] = 1;
       }
@@ -1291,7 +1305,8 @@ mhdg_status mhdg_profile(mhdg_mesh* M, int32_t enable, mhdg_kernel_times* out) {
 }
 
 mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, mhdg_sizes* out) {
-  if (!M || !out || restart < 1 || (precision != MHDG_FP64 && precision != MHDG_FP32))
+  if (!M || !out || restart < 1 ||
+      (precision != MHDG_FP64 && precision != MHDG_FP32 && precision != MHDG_BF16))
     return MHDG_ERR_INVALID_ARG;
   out->n_macro = M->n_macro;
   out->n_faces = M->n_faces;
@@ -1306,14 +1321,7 @@ mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, m
   out->n_instances = M->n_inst;
   out->fold_ws_bytes = fold_layout(M).total;
   FactorLayout L = factor_layout(M, precision);
-  // factor block offsets are padded to 64 elements per macro
-  size_t es = precision == MHDG_FP32 ? 4 : 8;
-  const MacroInfo& last = M->macros.back();
-  // guard tail: the column-streaming solve reads whole 64-row chunks (up to
-  // 64 x 64 rows) past a column start; reads past a block land in the next
-  // block or in this tail and are discarded
-  size_t nf = size_t(last.fac_off) + size_t(last.N) * last.N + kFactorGuard;
-  out->factor_ws_bytes = align_up(L.factors + nf * es);
+  out->factor_ws_bytes = L.total;
   out->solve_ws_bytes = solve_bytes(M, restart);
   return MHDG_OK;
 }
@@ -1395,8 +1403,10 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
     return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: null pointer or tau <= 0");
   for (int64_t i = 0; i < 2 * int64_t(M->n_inst); ++i)
     if (!std::isfinite(beta[i])) return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: non-finite a");
-  if (precision != MHDG_FP64 && precision != MHDG_FP32)
+  if (precision != MHDG_FP64 && precision != MHDG_FP32 && precision != MHDG_BF16)
     return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: unknown precision");
+  if (precision == MHDG_BF16 && M->max_N > 1024)
+    return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: BF16 factors support N_K <= 1024");
   mhdg_sizes sz;
   mhdg_query(M, precision, 1, &sz);
   if (ws_bytes < sz.factor_ws_bytes)
@@ -1436,14 +1446,19 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   HIP_TRY(M, launch_set_kappa(info, kappa, M->n_macro, s));
   {
     ProfScope ps(M, 0, s);
-    HIP_TRY(M, launch_assemble(w + L.factors, precision, info, nullptr, M->n_macro,
+    HIP_TRY(M, launch_assemble(w + L.factors, lu_precision(precision), info, nullptr, M->n_macro,
                                (const double*)(w + L.tmpl), M->T, tau, s));
   }
   {
     ProfScope ps(M, 1, s);
-    HIP_TRY(M, launch_lu(w + L.factors, precision, info, (const int32_t*)(w + L.order),
+    HIP_TRY(M, launch_lu(w + L.factors, lu_precision(precision), info, (const int32_t*)(w + L.order),
                          M->classes.data(), (int)M->classes.size(), (int32_t*)(w + L.perm),
                          (int32_t*)(w + L.status), s));
+  }
+  if (precision == MHDG_BF16) {
+    const MacroInfo& last = M->macros.back();
+    const int64_t nf = last.fac_off + int64_t(last.N) * last.N;
+    HIP_TRY(M, launch_to_bf16((const float*)(w + L.factors), w + L.factors16, nf, s));
   }
   std::vector<int32_t> st(M->n_macro);
   HIP_TRY(M, hipMemcpyAsync(st.data(), w + L.status, st.size() * sizeof(int32_t),
@@ -1594,12 +1609,12 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
         sub.lu_var = v;
         SizeClass one_m = sub;
         one_m.count = 1;   // untimed: loads the kernel
-        HIP_TRY(M, launch_lu(w + L.factors, M->precision, info, order, &one_m, 1,
+        HIP_TRY(M, launch_lu(w + L.factors, lu_precision(M->precision), info, order, &one_m, 1,
                              (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
-        HIP_TRY(M, launch_assemble(w + L.factors, M->precision, info, nullptr, M->n_macro, tm,
+        HIP_TRY(M, launch_assemble(w + L.factors, lu_precision(M->precision), info, nullptr, M->n_macro, tm,
                                    M->T, M->tau, s));
         HIP_TRY(M, hipEventRecord(b, s));
-        HIP_TRY(M, launch_lu(w + L.factors, M->precision, info, order, &sub, 1,
+        HIP_TRY(M, launch_lu(w + L.factors, lu_precision(M->precision), info, order, &sub, 1,
                              (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
         HIP_TRY(M, hipEventRecord(e, s));
         float ms = 0;
@@ -1612,10 +1627,15 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
     rep.lu_variant[ci] = c.lu_var ? c.lu_var : default_lu_variant(c.N);
   }
   // valid factors with the chosen LU variants
-  HIP_TRY(M, launch_assemble(w + L.factors, M->precision, info, nullptr, M->n_macro, tm, M->T,
-                             M->tau, s));
-  HIP_TRY(M, launch_lu(w + L.factors, M->precision, info, order, M->classes.data(),
+  HIP_TRY(M, launch_assemble(w + L.factors, lu_precision(M->precision), info, nullptr, M->n_macro,
+                             tm, M->T, M->tau, s));
+  HIP_TRY(M, launch_lu(w + L.factors, lu_precision(M->precision), info, order, M->classes.data(),
                        (int)M->classes.size(), (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+  if (M->precision == MHDG_BF16) {
+    const MacroInfo& last = M->macros.back();
+    HIP_TRY(M, launch_to_bf16((const float*)(w + L.factors), w + L.factors16,
+                              last.fac_off + int64_t(last.N) * last.N, s));
+  }
   {
     std::vector<int32_t> stv(M->n_macro);
     HIP_TRY(M, hipMemcpyAsync(stv.data(), w + L.status, stv.size() * sizeof(int32_t),
@@ -1635,13 +1655,14 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
       double best_ms = 0;
       for (int v = SOLVE_WAVE; v <= SOLVE_MW8; ++v) {
         if (!solve_variant_ok(v, c.N)) continue;
+        if (M->precision == MHDG_BF16 && v != SOLVE_WAVE) continue;   // BF16: one wavefront
         sub.solve_var = v;
-        HIP_TRY(M, launch_macro_solve(MODE_APPLY, 0, w + L.factors, M->precision, info, order, &sub,
+        HIP_TRY(M, launch_macro_solve(MODE_APPLY, 0, solve_factors(M), M->precision, info, order, &sub,
                                       1, (const int32_t*)(w + L.perm), tm, M->T, nullptr, M->tau,
                                       lam0, nullptr, nullptr, (double*)(w + L.slots), s));
         HIP_TRY(M, hipEventRecord(b, s));
         for (int r = 0; r < 3; ++r)
-          HIP_TRY(M, launch_macro_solve(MODE_APPLY, 0, w + L.factors, M->precision, info, order,
+          HIP_TRY(M, launch_macro_solve(MODE_APPLY, 0, solve_factors(M), M->precision, info, order,
                                         &sub, 1, (const int32_t*)(w + L.perm), tm, M->T, nullptr,
                                         M->tau, lam0, nullptr, nullptr, (double*)(w + L.slots), s));
         HIP_TRY(M, hipEventRecord(e, s));
@@ -1678,7 +1699,7 @@ static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const 
   FactorLayout& L = M->L;
   char* w = M->ws;
   ProfScope ps(M, mode == MODE_APPLY ? 2 : 4, s);
-  HIP_TRY(M, launch_macro_solve(mode, transpose, w + L.factors, M->precision,
+  HIP_TRY(M, launch_macro_solve(mode, transpose, solve_factors(M), M->precision,
                                 (const MacroInfo*)(w + L.meta), (const int32_t*)(w + L.order),
                                 M->classes.data(), (int)M->classes.size(),
                                 (const int32_t*)(w + L.perm), (const double*)(w + L.tmpl), M->T,
@@ -1962,7 +1983,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
     HIP_TRY(M, hipMemsetAsync(G.U, 0, nl * sizeof(double), s));
     if (!o->zero_guess) {
       // start U from the low-precision local solve for the given lam
-      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
+      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, solve_factors(M), M->precision, info_d, (const int32_t*)(fw + L.order),
                                     M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
                                     nullptr, M->tau, lam, (const double*)(fw + L.R), G.U,
                                     (double*)(fw + L.slots), s));
@@ -1979,7 +2000,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       HIP_TRY(M, launch_face_combine(FACE_RESID, faces_d, M->n_int, tm, M->T, M->tau, lam,
                                      (const double*)(fw + L.slots), G.cl, s));      // C U + D lam
       // condensed right-hand side b = D^-1 (r_lam - sum C A~^-1 r_U)
-      HIP_TRY(M, launch_macro_solve(MODE_RHS, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
+      HIP_TRY(M, launch_macro_solve(MODE_RHS, 0, solve_factors(M), M->precision, info_d, (const int32_t*)(fw + L.order),
                                     M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
                                     nullptr, M->tau, nullptr, rU, nullptr,
                                     (double*)(fw + L.slots), s));
@@ -1993,6 +2014,8 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       double b2;
       if ((st = dot(M, G, G.wv, G.wv, &b2, s))) return st;
       const double rho = std::sqrt(b2);
+      if (!std::isfinite(rho))
+        return fail(M, MHDG_ERR_NOT_CONVERGED, "solve: non-finite refinement residual");
       if (outer == 0) rho0 = rho;
       rel = rho0 > 0 ? rho / rho0 : 0.0;
       if (rho0 == 0.0 || rel <= o->rtol) { converged = true; break; }
@@ -2009,7 +2032,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
         return st;
       it_total += it[0];
       // dU = A~^-1 (r_U - B dlam); U += dU; lam += dlam
-      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, fw + L.factors, M->precision, info_d, (const int32_t*)(fw + L.order),
+      HIP_TRY(M, launch_macro_solve(MODE_RECOVER, 0, solve_factors(M), M->precision, info_d, (const int32_t*)(fw + L.order),
                                     M->classes.data(), (int)M->classes.size(), (const int32_t*)(fw + L.perm), tm, M->T,
                                     nullptr, M->tau, G.dl, rU, rU, (double*)(fw + L.slots), s));
       ++inf.n_applies;

@@ -74,7 +74,8 @@ struct Templates {
 
 // Device workspace layout for factor_local / apply / rhs / recover.
 struct FactorLayout {
-  size_t meta, faces, bfaces, tmpl, order, perm, status, R, slots, lamD, work1, work2, factors, total;
+  size_t meta, faces, bfaces, tmpl, order, perm, status, R, slots, lamD, work1, work2, factors,
+      factors16, total;   // factors16: BF16 copy of the FP32 factors (BF16 precision only)
 };
 
 // Macros of one local size, contiguous in the processing order (largest first):
@@ -166,6 +167,7 @@ hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, 
                        double* partial, int nblk, double* out, hipStream_t s, int nseg = 1);
 hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double* h, double* w,
                            int64_t n, double sign, hipStream_t s, int nseg = 1);
+hipError_t launch_to_bf16(const float* src, void* dst, int64_t n, hipStream_t s);
 hipError_t launch_seg_scale_copy(const double* alpha, const double* x, double* y, int64_t n, int nseg,
                                  hipStream_t s);
 // delayed-reorthogonalisation Arnoldi (see host gmres): two products per

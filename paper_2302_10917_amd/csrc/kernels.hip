@@ -1024,6 +1024,8 @@ hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo*
                                                   const Templates&, const int32_t*, double,      \
                                                   const double*, const double*, double*,        \
                                                   double*, hipStream_t);
+MS_DECL(bf16_t, 1) MS_DECL(bf16_t, 2) MS_DECL(bf16_t, 3) MS_DECL(bf16_t, 5) MS_DECL(bf16_t, 8)
+MS_DECL(bf16_t, 16)
 #define MS_DECL2(Q_) MS_DECL(double, Q_) MS_DECL(float, Q_)
 MS_DECL2(1) MS_DECL2(2) MS_DECL2(3) MS_DECL2(5) MS_DECL2(8) MS_DECL2(16) MS_DECL2(27)
 MS_DECL2(58)
@@ -1099,6 +1101,44 @@ static hipError_t macro_solve_dispatch(int variant, int nq, int mode, const void
   return hipErrorInvalidValue;
 }
 
+// BF16 factors: one wavefront per macro, N_K <= 1024
+static hipError_t macro_solve_dispatch_bf16(int variant, int nq, int mode, const void* fac,
+                                            const MacroInfo* info, const int32_t* order,
+                                            int64_t base, int64_t n, size_t lds,
+                                            const int32_t* perm, const double* tmpl,
+                                            const Templates& Tp, const int32_t* skip, double tau,
+                                            const double* lam, const double* xin, double* yout,
+                                            double* slots, hipStream_t s) {
+  if (variant != SOLVE_WAVE) return hipErrorInvalidValue;
+#define MB_CASE(Q_)                                                                           \
+  if (nq <= Q_) {                                                                             \
+    macro_solve_launch<bf16_t, Q_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp, skip,\
+                                   tau, lam, xin, yout, slots, s);                            \
+    return hipGetLastError();                                                                 \
+  }
+  MB_CASE(1) MB_CASE(2) MB_CASE(3) MB_CASE(5) MB_CASE(8) MB_CASE(16)
+#undef MB_CASE
+  return hipErrorInvalidValue;
+}
+
+// FP32 factors -> BF16 storage, rounding to nearest (ties to even).  A
+// grid-stride loop: the factor arrays exceed the 2^32 work-items one
+// dispatch can address.
+__global__ void to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += stride) {
+    const uint32_t b = __float_as_uint(src[i]);
+    dst[i] = (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+  }
+}
+
+hipError_t launch_to_bf16(const float* src, void* dst, int64_t n, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, (uint16_t*)dst,
+                     n);
+  return hipGetLastError();
+}
+
 int default_solve_variant(int N) { return N <= 1024 ? SOLVE_WAVE : SOLVE_MW4; }
 bool solve_variant_ok(int v, int N) {
   if (N > 58 * 64) return false;
@@ -1126,6 +1166,9 @@ hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int prec
     if (transpose)
       e = macro_solve_t_dispatch(nq, mode, fac, info, order, sc.start, sc.count, lds, perm, tmpl, T,
                                  skip, tau, lam, xin, yout, slots, s);
+    else if (precision == 2)
+      e = macro_solve_dispatch_bf16(v, nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
+                                    tmpl, T, skip, tau, lam, xin, yout, slots, s);
     else if (precision == 1)
       e = macro_solve_dispatch<float>(v, nq, mode, fac, info, order, sc.start, sc.count, lds, perm,
                                       tmpl, T, skip, tau, lam, xin, yout, slots, s);

@@ -7,6 +7,17 @@
 
 namespace mhdg {
 
+// BF16 storage of factors (8-bit mantissa): the upper half of an FP32 word,
+// widened exactly on load.
+struct bf16_t {
+  uint16_t bits;
+  bf16_t() = default;
+  __host__ __device__ constexpr explicit bf16_t(int) : bits(0) {}
+  __device__ __forceinline__ operator double() const {
+    return (double)__uint_as_float(uint32_t(bits) << 16);
+  }
+};
+
 __device__ __forceinline__ const int32_t* ints_(const double* base, int64_t off) {
   return reinterpret_cast<const int32_t*>(base + off);
 }
@@ -117,8 +128,9 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
                                                          const double* __restrict__ lam,
                                                          const double* xin, double* yout,
                                                          double* __restrict__ slots) {
-  // loads in flight per group: the same number of bytes for FP32 factors
-  constexpr int kLG = sizeof(T) == 4 ? 2 * kLoadGroup : kLoadGroup;
+  // loads in flight per group: the same number of bytes for FP32 factors,
+  // half of them for BF16 (a wider group does not fit the register budget)
+  constexpr int kLG = sizeof(T) == 8 ? kLoadGroup : 2 * kLoadGroup;
   extern __shared__ double sm[];
   const MacroInfo& mi = info[order[base + blockIdx.x]];
   if (skip && skip[mi.inst]) return;   // instance already converged: no work, outputs untouched

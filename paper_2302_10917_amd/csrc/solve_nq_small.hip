@@ -48,4 +48,19 @@ template void macro_solve_t_launch<5>(int, const void*, const MacroInfo*, const 
 template void macro_solve_t_launch<8>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
     const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
     const double*, double*, double*, hipStream_t);
+template void macro_solve_launch<bf16_t, 1>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
+    const double*, double*, double*, hipStream_t);
+template void macro_solve_launch<bf16_t, 2>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
+    const double*, double*, double*, hipStream_t);
+template void macro_solve_launch<bf16_t, 3>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
+    const double*, double*, double*, hipStream_t);
+template void macro_solve_launch<bf16_t, 5>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
+    const double*, double*, double*, hipStream_t);
+template void macro_solve_launch<bf16_t, 8>(int, const void*, const MacroInfo*, const int32_t*, int64_t, int64_t, size_t,
+    const int32_t*, const double*, const Templates&, const int32_t*, double, const double*,
+    const double*, double*, double*, hipStream_t);
 }  // namespace mhdg
