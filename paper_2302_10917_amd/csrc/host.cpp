@@ -427,7 +427,7 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   // macro, and the column-streaming solves may read up to 64 x 64 elements
   // past a block's end (guard tail)
   const MacroInfo& last = M->macros.back();
-  const size_t nf = size_t(last.fac_off) + size_t(last.N) * last.N + kFactorGuard;
+  const size_t nf = size_t(last.fac_off) + size_t(last.N) * last.ld + kFactorGuard;
   const size_t es = precision == MHDG_FP64 ? 8 : 4;   // BF16 factors are factored in FP32
   o = align_up(o + nf * es);
   L.factors16 = o;
@@ -1081,6 +1081,7 @@ mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t 
     mi.P = (1 << r) * p;
     mi.Q = (mi.P + 1) * (mi.P + 2) / 2;
     mi.N = 3 * mi.Q;
+    mi.ld = (mi.N + 15) & ~15;   // 128-byte aligned FP64 columns
     M->max_N = std::max(M->max_N, mi.N);
   }
   // faces: unique edges sorted by (low, high)
@@ -1202,7 +1203,7 @@ mhdg_status mhdg_setup_macro_mesh(int64_t n_vertices, const double* xy, int64_t 
   for (int64_t e = 0; e < n_macro; ++e) {
     MacroInfo& mi = M->macros[e];
     mi.fac_off = fo;
-    fo += int64_t(mi.N) * mi.N;
+    fo += int64_t(mi.N) * mi.ld;
     fo = (fo + 63) & ~int64_t(63);
   }
   build_templates(M);
@@ -1457,7 +1458,7 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   }
   if (precision == MHDG_BF16) {
     const MacroInfo& last = M->macros.back();
-    const int64_t nf = last.fac_off + int64_t(last.N) * last.N;
+    const int64_t nf = last.fac_off + int64_t(last.N) * last.ld;
     HIP_TRY(M, launch_to_bf16((const float*)(w + L.factors), w + L.factors16, nf, s));
   }
   std::vector<int32_t> st(M->n_macro);
@@ -1634,7 +1635,7 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
   if (M->precision == MHDG_BF16) {
     const MacroInfo& last = M->macros.back();
     HIP_TRY(M, launch_to_bf16((const float*)(w + L.factors), w + L.factors16,
-                              last.fac_off + int64_t(last.N) * last.N, s));
+                              last.fac_off + int64_t(last.N) * last.ld, s));
   }
   {
     std::vector<int32_t> stv(M->n_macro);

@@ -33,6 +33,7 @@ struct MacroInfo {
   int32_t Q;
   int32_t P;          // 2^r p
   int32_t inst;       // coefficient instance this macro belongs to
+  int32_t ld;         // leading dimension of the stored block: N rounded up to 16
 };
 
 struct FaceInfo {     // interior faces

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(T* fac, const MacroInfo* 
                                                        const double* __restrict__ tm, Templates Tp,
                                                        double tau) {
   const MacroInfo& mi = info[blockIdx.x];
-  const int N = mi.N;
+  const int N = mi.N, ld = mi.ld;
   const int rows_per = 8;
   const int r0 = blockIdx.y * rows_per;
   if (r0 >= N) return;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(T* fac, const MacroInfo* 
   const int r1 = min(N, r0 + rows_per);
   for (int r = r0; r < r1; ++r)
     for (int col = threadIdx.x; col < N; col += blockDim.x)
-      A[size_t(r) * N + col] = (T)a_entry(c, r, col);
+      A[size_t(r) * ld + col] = (T)a_entry(c, r, col);
 }
 
 __global__ void extract_kernel(const MacroInfo* info, int64_t e, const double* tm, Templates Tp,
@@ -136,7 +136,8 @@ __global__ void extract_kernel(const MacroInfo* info, int64_t e, const double* t
 // cross-wave reduction in LDS; the trailing update runs on MFMA 16x16x4 tiles.
 // perm[i] receives the original row of factor row i; status = first zero
 // pivot column + 1, or 0.  On exit L (unit lower) and U are stored
-// column-major in the block: element (i, j) at j * N + i.
+// column-major in the block: element (i, j) at j * ld + i, ld = N rounded up
+// to 16 (FP64 columns start on 128-byte lines).
 template <typename T, int NT, int RPT, int NB>
 __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restrict__ info,
                                                 const int32_t* __restrict__ order, int64_t base,
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
   constexpr int NW = NT / 64;
   const int e = order[base + blockIdx.x];
   const MacroInfo& mi = info[e];
-  const int N = mi.N;
+  const int N = mi.N, ld = mi.ld;   // rows of the stored block are ld apart
   T* A = fac + mi.fac_off;
   int32_t* perm = perm_all + mi.loc_off;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
       const int row = k0 + tid + q * NT;
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        pr[q][c] = (row < N && c < nb) ? A[size_t(row) * N + k0 + c] : T(0);
+        pr[q][c] = (row < N && c < nb) ? A[size_t(row) * ld + k0 + c] : T(0);
     }
     // ---- panel factorisation
     for (int j = 0; j < nb; ++j) {
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
       if (row < N) {
 #pragma unroll
         for (int c = 0; c < NB; ++c)
-          if (c < nb) A[size_t(row) * N + k0 + c] = pr[q][c];
+          if (c < nb) A[size_t(row) * ld + k0 + c] = pr[q][c];
         if (row < k0 + nb)
           for (int c = 0; c < NB; ++c) s_L11[(row - k0) * NB + c] = pr[q][c];
       }
@@ -268,9 +269,9 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
       for (int j = 0; j < nb; ++j) {
         const int prow = s_piv[j], col = k0 + j;
         if (prow != col) {
-          T a = A[size_t(col) * N + c], b = A[size_t(prow) * N + c];
-          A[size_t(col) * N + c] = b;
-          A[size_t(prow) * N + c] = a;
+          T a = A[size_t(col) * ld + c], b = A[size_t(prow) * ld + c];
+          A[size_t(col) * ld + c] = b;
+          A[size_t(prow) * ld + c] = a;
         }
       }
     }
@@ -285,14 +286,14 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
     for (int c = k0 + nb + tid; c < N; c += NT) {
       T v[NB];
 #pragma unroll
-      for (int jj = 0; jj < NB; ++jj) v[jj] = jj < nb ? A[size_t(k0 + jj) * N + c] : T(0);
+      for (int jj = 0; jj < NB; ++jj) v[jj] = jj < nb ? A[size_t(k0 + jj) * ld + c] : T(0);
 #pragma unroll
       for (int jj = 1; jj < NB; ++jj)
 #pragma unroll
         for (int ii = 0; ii < jj; ++ii) v[jj] -= s_L11[jj * NB + ii] * v[ii];
 #pragma unroll
       for (int jj = 0; jj < NB; ++jj)
-        if (jj < nb) A[size_t(k0 + jj) * N + c] = v[jj];
+        if (jj < nb) A[size_t(k0 + jj) * ld + c] = v[jj];
     }
     __syncthreads();
     // ---- A22 -= L21 U12 on MFMA 16x16x4 tiles
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
 #pragma unroll
         for (int s = 0; s < NB / 4; ++s) {
           const int k = 4 * s + lk, row = r0 + li;
-          a[s] = (row < N && k < nb) ? -A[size_t(row) * N + k0 + k] : T(0);
+          a[s] = (row < N && k < nb) ? -A[size_t(row) * ld + k0 + k] : T(0);
         }
         for (int ct = 0; ct < nt; ++ct) {
           const int c0 = base + 16 * ct;
@@ -315,20 +316,20 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
 #pragma unroll
           for (int s = 0; s < NB / 4; ++s) {
             const int k = 4 * s + lk;
-            b[s] = (k < nb && colc < N) ? A[size_t(k0 + k) * N + colc] : T(0);
+            b[s] = (k < nb && colc < N) ? A[size_t(k0 + k) * ld + colc] : T(0);
           }
           typename Mfma<T>::acc acc;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = r0 + Mfma<T>::drow(lk, v);
-            acc[v] = (row < N && colc < N) ? A[size_t(row) * N + colc] : T(0);
+            acc[v] = (row < N && colc < N) ? A[size_t(row) * ld + colc] : T(0);
           }
 #pragma unroll
           for (int s = 0; s < NB / 4; ++s) acc = Mfma<T>::run(a[s], b[s], acc);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = r0 + Mfma<T>::drow(lk, v);
-            if (row < N && colc < N) A[size_t(row) * N + colc] = acc[v];
+            if (row < N && colc < N) A[size_t(row) * ld + colc] = acc[v];
           }
         }
       }
@@ -347,17 +348,17 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
         for (int e = tid; e < 1024; e += NT) {
           const int a = e >> 5, b = e & 31;
           const int r = 32 * I + a, c = 32 * J + b;
-          t0[a][b] = (r < N && c < N) ? A[size_t(r) * N + c] : T(0);
+          t0[a][b] = (r < N && c < N) ? A[size_t(r) * ld + c] : T(0);
           const int r2 = 32 * J + a, c2 = 32 * I + b;
-          t1[a][b] = (r2 < N && c2 < N) ? A[size_t(r2) * N + c2] : T(0);
+          t1[a][b] = (r2 < N && c2 < N) ? A[size_t(r2) * ld + c2] : T(0);
         }
         __syncthreads();
         for (int e = tid; e < 1024; e += NT) {
           const int a = e >> 5, b = e & 31;
           const int r = 32 * I + a, c = 32 * J + b;
-          if (r < N && c < N) A[size_t(r) * N + c] = t1[b][a];
+          if (r < N && c < N) A[size_t(r) * ld + c] = t1[b][a];
           const int r2 = 32 * J + a, c2 = 32 * I + b;
-          if (r2 < N && c2 < N) A[size_t(r2) * N + c2] = t0[b][a];
+          if (r2 < N && c2 < N) A[size_t(r2) * ld + c2] = t0[b][a];
         }
         __syncthreads();
       }

@@ -14,14 +14,14 @@
 namespace mhdg {
 
 // A[r0:N, c0:c1] -= A[r0:N, kc:kc+kw] A[kc:kc+kw, c0:c1] (row-major, leading
-// dimension N, kw <= KW) on 16 x 16 MFMA tiles.  Wavefront w takes the row
+// dimension ld, kw <= KW) on 16 x 16 MFMA tiles.  Wavefront w takes the row
 // tiles w, w + NW, ...; a row tile keeps its K-slab of L in registers while
 // the column tiles stream through, so the wavefronts of the workgroup read
 // the same U tiles at about the same time (cache hits) and every element of
 // the updated block is read and written once.
 template <typename T, int KW, int NW>
-__device__ __forceinline__ void slab_update(T* __restrict__ A, int N, int r0, int c0, int c1,
-                                            int kc, int kw, int wid, int lane) {
+__device__ __forceinline__ void slab_update(T* __restrict__ A, int N, int ld, int r0, int c0,
+                                            int c1, int kc, int kw, int wid, int lane) {
   constexpr int S = KW / 4;
   const int nrt = (N - r0 + 15) >> 4, nct = (c1 - c0 + 15) >> 4;
   const int li = lane & 15, lk = lane >> 4;
@@ -31,7 +31,7 @@ __device__ __forceinline__ void slab_update(T* __restrict__ A, int N, int r0, in
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int k = 4 * s + lk, row = rr + li;
-      a[s] = (row < N && k < kw) ? -A[size_t(row) * N + kc + k] : T(0);
+      a[s] = (row < N && k < kw) ? -A[size_t(row) * ld + kc + k] : T(0);
     }
     for (int ct = 0; ct < nct; ++ct) {
       const int col = c0 + 16 * ct + li;
@@ -40,7 +40,7 @@ __device__ __forceinline__ void slab_update(T* __restrict__ A, int N, int r0, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = rr + Mfma<T>::drow(lk, v);
-        acc0[v] = (row < N && cok) ? A[size_t(row) * N + col] : T(0);
+        acc0[v] = (row < N && cok) ? A[size_t(row) * ld + col] : T(0);
         acc1[v] = T(0);
       }
       // the U slab in chunks of CH k-steps (bounded registers); two
@@ -52,7 +52,7 @@ __device__ __forceinline__ void slab_update(T* __restrict__ A, int N, int r0, in
 #pragma unroll
         for (int s = 0; s < CH; ++s) {
           const int k = 4 * (h + s) + lk;
-          b[s] = (cok && k < kw) ? A[size_t(kc + k) * N + col] : T(0);
+          b[s] = (cok && k < kw) ? A[size_t(kc + k) * ld + col] : T(0);
         }
 #pragma unroll
         for (int s = 0; s < CH; s += 2) {
@@ -64,7 +64,7 @@ __device__ __forceinline__ void slab_update(T* __restrict__ A, int N, int r0, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = rr + Mfma<T>::drow(lk, v);
-        if (row < N && cok) A[size_t(row) * N + col] = acc0[v] + acc1[v];
+        if (row < N && cok) A[size_t(row) * ld + col] = acc0[v] + acc1[v];
       }
     }
   }
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
   constexpr int NW = NT / 64;
   const int e = order[base + blockIdx.x];
   const MacroInfo& mi = info[e];
-  const int N = mi.N;
+  const int N = mi.N, ld = mi.ld;   // rows of the stored block are ld apart
   T* A = fac + mi.fac_off;
   int32_t* perm = perm_all + mi.loc_off;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
         const int row = c0 + tid + q * NT;
 #pragma unroll
         for (int c = 0; c < SB; ++c)
-          pr[q][c] = (row < N && c < sb) ? A[size_t(row) * N + c0 + c] : T(0);
+          pr[q][c] = (row < N && c < sb) ? A[size_t(row) * ld + c0 + c] : T(0);
       }
       for (int j = 0; j < sb; ++j) {
         const int col = c0 + j;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
         if (row < N)
 #pragma unroll
           for (int c = 0; c < SB; ++c)
-            if (c < sb) A[size_t(row) * N + c0 + c] = pr[q][c];
+            if (c < sb) A[size_t(row) * ld + c0 + c] = pr[q][c];
       }
       __syncthreads();
       // row interchanges in every column outside the sub-panel, in pivot order
@@ -203,9 +203,9 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
         for (int j = 0; j < sb; ++j) {
           const int prow = s_piv[j], col = c0 + j;
           if (prow != col) {
-            T a = A[size_t(col) * N + c], b = A[size_t(prow) * N + c];
-            A[size_t(col) * N + c] = b;
-            A[size_t(prow) * N + c] = a;
+            T a = A[size_t(col) * ld + c], b = A[size_t(prow) * ld + c];
+            A[size_t(col) * ld + c] = b;
+            A[size_t(prow) * ld + c] = a;
           }
         }
       }
@@ -221,18 +221,18 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
         for (int c = b0 + tid; c < b1; c += NT) {
           T v[SB];
 #pragma unroll
-          for (int jj = 0; jj < SB; ++jj) v[jj] = jj < sb ? A[size_t(c0 + jj) * N + c] : T(0);
+          for (int jj = 0; jj < SB; ++jj) v[jj] = jj < sb ? A[size_t(c0 + jj) * ld + c] : T(0);
 #pragma unroll
           for (int jj = 1; jj < SB; ++jj)
 #pragma unroll
             for (int ii = 0; ii < jj; ++ii)
-              if (jj < sb) v[jj] -= A[size_t(c0 + jj) * N + c0 + ii] * v[ii];
+              if (jj < sb) v[jj] -= A[size_t(c0 + jj) * ld + c0 + ii] * v[ii];
 #pragma unroll
           for (int jj = 0; jj < SB; ++jj)
-            if (jj < sb) A[size_t(c0 + jj) * N + c] = v[jj];
+            if (jj < sb) A[size_t(c0 + jj) * ld + c] = v[jj];
         }
         __syncthreads();
-        slab_update<T, SB, NW>(A, N, b0, b0, b1, c0, sb, wid, lane);
+        slab_update<T, SB, NW>(A, N, ld, b0, b0, b1, c0, sb, wid, lane);
         __syncthreads();
       }
     }
@@ -240,16 +240,16 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
     // ---------------- U12 = L11^-1 A12, SB-row blocks, L11 in LDS
     for (int i = tid; i < NB * NB; i += NT) {
       const int r = i / NB, c = i % NB;
-      s_L[i] = (r < nb && c < r) ? A[size_t(k0 + r) * N + k0 + c] : T(0);
+      s_L[i] = (r < nb && c < r) ? A[size_t(k0 + r) * ld + k0 + c] : T(0);
     }
     __syncthreads();
     for (int c = k0 + nb + tid; c < N; c += NT) {
       for (int b = 0; b < nb; b += SB) {
         T v[SB];
 #pragma unroll
-        for (int jj = 0; jj < SB; ++jj) v[jj] = b + jj < nb ? A[size_t(k0 + b + jj) * N + c] : T(0);
+        for (int jj = 0; jj < SB; ++jj) v[jj] = b + jj < nb ? A[size_t(k0 + b + jj) * ld + c] : T(0);
         for (int i = 0; i < b; ++i) {
-          const T x = A[size_t(k0 + i) * N + c];   // finished U entry (written by this thread)
+          const T x = A[size_t(k0 + i) * ld + c];   // finished U entry (written by this thread)
 #pragma unroll
           for (int jj = 0; jj < SB; ++jj) v[jj] -= s_L[(b + jj) * NB + i] * x;
         }
@@ -259,12 +259,12 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
           for (int ii = 0; ii < jj; ++ii) v[jj] -= s_L[(b + jj) * NB + b + ii] * v[ii];
 #pragma unroll
         for (int jj = 0; jj < SB; ++jj)
-          if (b + jj < nb) A[size_t(k0 + b + jj) * N + c] = v[jj];
+          if (b + jj < nb) A[size_t(k0 + b + jj) * ld + c] = v[jj];
       }
     }
     __syncthreads();
     // ---------------- A22 -= L21 U12 (rank nb)
-    slab_update<T, NB, NW>(A, N, k0 + nb, k0 + nb, N, k0, nb, wid, lane);
+    slab_update<T, NB, NW>(A, N, ld, k0 + nb, k0 + nb, N, k0, nb, wid, lane);
     __syncthreads();
   }
   // ---- store the factors column-major (in-place transpose by 32 x 32 tile pairs)
@@ -277,17 +277,17 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
         for (int x = tid; x < 1024; x += NT) {
           const int a = x >> 5, b = x & 31;
           const int r = 32 * I + a, c = 32 * J + b;
-          t0[a][b] = (r < N && c < N) ? A[size_t(r) * N + c] : T(0);
+          t0[a][b] = (r < N && c < N) ? A[size_t(r) * ld + c] : T(0);
           const int r2 = 32 * J + a, c2 = 32 * I + b;
-          t1[a][b] = (r2 < N && c2 < N) ? A[size_t(r2) * N + c2] : T(0);
+          t1[a][b] = (r2 < N && c2 < N) ? A[size_t(r2) * ld + c2] : T(0);
         }
         __syncthreads();
         for (int x = tid; x < 1024; x += NT) {
           const int a = x >> 5, b = x & 31;
           const int r = 32 * I + a, c = 32 * J + b;
-          if (r < N && c < N) A[size_t(r) * N + c] = t1[b][a];
+          if (r < N && c < N) A[size_t(r) * ld + c] = t1[b][a];
           const int r2 = 32 * J + a, c2 = 32 * I + b;
-          if (r2 < N && c2 < N) A[size_t(r2) * N + c2] = t0[b][a];
+          if (r2 < N && c2 < N) A[size_t(r2) * ld + c2] = t0[b][a];
         }
         __syncthreads();
       }

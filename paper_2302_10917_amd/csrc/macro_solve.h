@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
     for (int jj = 0; jj < jend; ++jj) {
       const int j = 64 * q + jj;
       const double yj = readlane_d(y[q], jj);
-      const T* col = A + size_t(j) * N;
+      const T* col = A + size_t(j) * mi.ld;
       // loads are unconditional and issued in groups of kLoadGroup chunks, so a
       // column costs one or two memory latencies and the in-flight values fit
       // the register budget.  Rows past N land in the next macro's block or in
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
     const int jend = min(64, N - 64 * q);
     for (int jj = jend - 1; jj >= 0; --jj) {
       const int j = 64 * q + jj;
-      const T* col = A + size_t(j) * N;
+      const T* col = A + size_t(j) * mi.ld;
       const double zj = readlane_d(y[q], jj) / (double)col[j];
       if (lane == jj) y[q] = zj;
 #pragma unroll
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
     for (int jj = 0; jj < jend; ++jj) {
       const int j = 64 * q + jj;
       const double yj = readlane_d(d, jj);
-      const T* col = A + size_t(j) * N;
+      const T* col = A + size_t(j) * mi.ld;
       const int rdc = rd > j ? (rd < N ? rd : N - 1) : j;   // in-bounds address for every lane
       double a[NL];
 #pragma unroll
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(64 * NW) void macro_solve_mw_kernel(
     const int jst = min(63, N - 1 - 64 * q);
     for (int jj = jst; jj >= 0; --jj) {
       const int j = 64 * q + jj;
-      const T* col = A + size_t(j) * N;
+      const T* col = A + size_t(j) * mi.ld;
       double a[NL];
 #pragma unroll
       for (int t = 0; t < NL; ++t) {
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(64) void macro_solve_t_kernel(
     const int jend = min(64, N - 64 * q);
     for (int jj = 0; jj < jend; ++jj) {
       const int i = 64 * q + jj;
-      const T* col = A + size_t(i) * N;
+      const T* col = A + size_t(i) * mi.ld;
       double part = 0.0;
 #pragma unroll
       for (int t = 0; t <= q; ++t) {
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(64) void macro_solve_t_kernel(
     const int jend = min(64, N - 64 * q);
     for (int jj = jend - 1; jj >= 0; --jj) {
       const int i = 64 * q + jj;
-      const T* col = A + size_t(i) * N;
+      const T* col = A + size_t(i) * mi.ld;
       double part = 0.0;
 #pragma unroll
       for (int t = q; t < NQ; ++t) {
