@@ -262,9 +262,13 @@ def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int
     idx = lattice_index(P)
     sub = sub_triangles(m, p)
 
+    # The blocks are integrals of the local basis over the macro and its edges,
+    # unchanged by a translation; they are formed in coordinates relative to the
+    # macro's first vertex X0, so that the rounding of quadrature points is
+    # relative to the macro's size rather than to its distance from the origin.
     def lat2xy(ij):
         ij = np.asarray(ij, float)
-        return X[0] + np.outer(ij[..., 0] / P, e1) + np.outer(ij[..., 1] / P, e2)
+        return np.outer(ij[..., 0] / P, e1) + np.outer(ij[..., 1] / P, e2)
 
     xi, eta, wref = triangle_rule(nq)
     M = np.zeros((Q, Q))
@@ -291,8 +295,8 @@ def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int
         f = int(topo.macro_face[K, k])
         nF = int(topo.face_nodes[f])
         rF = int(topo.face_level[f])
-        A = topo.xy[topo.face_verts[f, 0]]
-        B = topo.xy[topo.face_verts[f, 1]]
+        A = topo.xy[topo.face_verts[f, 0]] - X[0]
+        B = topo.xy[topo.face_verts[f, 1]] - X[0]
         L = float(np.linalg.norm(B - A))
         tvec = X[(k + 1) % 3] - X[k]
         n = np.array([tvec[1], -tvec[0]]) / np.linalg.norm(tvec)
@@ -308,7 +312,7 @@ def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int
             w = ws * L / npc
             pts = A + np.outer(t, B - A)
             mid = A + ((c + 0.5) / npc) * (B - A)
-            lat_mid = np.linalg.solve(Tm, mid - X[0]) * P
+            lat_mid = np.linalg.solve(Tm, mid) * P
             s = _locate(sub, lat_mid)
             corners, nodes = sub[s]
             ids = idx[nodes[:, 0], nodes[:, 1]]
@@ -527,34 +531,40 @@ class Oracle:
         return U
 
     # -- O12: the trace operator, steps 1-4 of the matrix-free algorithm ------
-    def macro_contribution(self, K, lam):
+    def macro_contribution(self, K, lam, transpose=False):
         """Steps 1-3 on macro K: x = B_K lam_K, y = A_K^-1 x, v^ = C_K y.
+        With transpose, the same product for the transposed operator:
+        x = C_K^T lam_K, y = A_K^-T x, v^ = B_K^T y.
         Returns {face: v^ restricted to that interior face}."""
         b = self.blocks(K)
         icols = self._interior_cols(K)
         if not icols:
             return {}
+        if transpose:
+            x = sum(b.C[k].T @ lam[o:o + nF] for k, o, nF in icols)
+            y = sla.lu_solve(self.lu(K), x, trans=1)
+            return {int(self.topo.macro_face[K, k]): b.B[k].T @ y for k, _, _ in icols}
         x = sum(b.B[k] @ lam[o:o + nF] for k, o, nF in icols)
         y = sla.lu_solve(self.lu(K), x)
         return {int(self.topo.macro_face[K, k]): b.C[k] @ y for k, _, _ in icols}
 
-    def apply(self, lam, precondition=False, faces=None):
+    def apply(self, lam, precondition=False, faces=None, transpose=False):
         """S lam (or D^-1 S lam: step 4 with the D^-1 preconditioner,
-        w_F = lam_F - D_F^-1 (v^_F1 + v^_F2)).  If `faces` is given, only
-        those interior faces are computed (others left zero)."""
+        w_F = lam_F - D_F^-1 (v^_F1 + v^_F2)).  With transpose, S^T lam (or
+        D^-1 S^T lam): S^T = D^T - sum_K B_K^T A_K^-T C_K^T and D_F is
+        symmetric.  If `faces` is given, only those interior faces are
+        computed (others left zero)."""
         topo = self.topo
         lam = np.asarray(lam, float)
         out = np.zeros(topo.n_trace)
         fs = range(topo.n_faces) if faces is None else faces
-        vsum = {}
         macros = sorted({K for f in fs if topo.interior[f] for K, _ in topo.face_incid[f]})
-        contrib = {K: self.macro_contribution(K, lam) for K in macros}
+        contrib = {K: self.macro_contribution(K, lam, transpose) for K in macros}
         for f in fs:
             if not topo.interior[f]:
                 continue
             o, nF = int(topo.trace_off[f]), int(topo.face_nodes[f])
             v = sum(contrib[K][f] for K, _ in topo.face_incid[f])
-            vsum[f] = v
             D = self.D_face(f)
             if precondition:
                 # D_F is negative definite (-D_F = (tau+ + tau-) M_F): Cholesky of -D_F

@@ -218,6 +218,50 @@ def test_apply_matches_assembled_operator():
     assert np.allclose(o.apply(lam, precondition=True), o.precondition(S @ lam), atol=1e-12)
 
 
+def test_blocks_are_translation_invariant():
+    """The local blocks are integrals of the section 3.2 basis over the macro
+    and its edges, so a translated copy of a macro has the same blocks; far
+    from the origin they must not pick up the rounding of the absolute
+    position (here a macro near (0.65, 0.16) against its copy at the origin,
+    both subdivided to r = 3 with sub-triangles of size 1/512)."""
+    base = np.array([[0.0, 0.0], [1 / 64, 0.0], [1 / 64, 1 / 64]])
+    blocks = []
+    for shift in ((0.0, 0.0), (0.640625, 0.15625), (0.984375, 0.984375)):
+        xy = base + np.array(shift)
+        o = hdg.Oracle(xy, np.array([[0, 1, 2]]), 3, 3, 1e-3, (1.0, 0.5), 1.0)
+        blocks.append(o.blocks(0))
+    for b in blocks[1:]:
+        scale = np.abs(blocks[0].A).max()
+        assert np.abs(b.A - blocks[0].A).max() <= 1e-15 * scale
+        for k in range(3):
+            assert np.abs(b.B[k] - blocks[0].B[k]).max() <= 1e-15 * np.abs(blocks[0].B[k]).max()
+
+
+def test_transposed_apply_is_the_adjoint_of_the_apply():
+    """The transposed matrix-free product satisfies <y, S^T x> = <S y, x>
+    against the forward apply (pinned above to the assembled S), on a
+    mesh with non-matching levels; its D^-1 form and its restriction to a
+    sample of faces agree with the full product."""
+    xy, tri = inputs.structured_mesh(3, jitter=0.1, seed=4)
+    r = inputs.random_levels(len(tri), (0, 1, 2), seed=2)
+    o = hdg.Oracle(xy, tri, r, 2, 0.4 * inputs.lognormal_kappa(len(tri), 0.3, seed=1),
+                   (0.7, -1.1), 1.0)
+    n = o.topo.n_trace
+    x = inputs.random_vector(n, seed=1)
+    y = inputs.random_vector(n, seed=2)
+    StX = o.apply(x, transpose=True)
+    assert abs(y @ StX - o.apply(y) @ x) <= 1e-12 * np.linalg.norm(StX) * np.linalg.norm(y)
+    # not symmetric: the advection term makes S^T differ from S
+    assert np.linalg.norm(StX - o.apply(x)) > 1e-3 * np.linalg.norm(StX)
+    assert np.allclose(o.apply(x, precondition=True, transpose=True), o.precondition(StX),
+                       atol=1e-12)
+    faces = [f for f in range(o.topo.n_faces) if o.topo.interior[f]][::3]
+    part = o.apply(x, faces=faces, transpose=True)
+    for f in faces:
+        sl = slice(o.topo.trace_off[f], o.topo.trace_off[f] + o.topo.face_nodes[f])
+        assert np.array_equal(part[sl], StX[sl])
+
+
 def test_worked_example_structure():
     """The two-macro example of section 3.3.2: one interface carries the only
     unknown trace; steps 1-3 are local to each macro and step 4 sums exactly
