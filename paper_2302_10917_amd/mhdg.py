@@ -186,11 +186,17 @@ class MacroMesh:
         self.precision = MHDG_FP64
         self.sizes = self.query()
 
-    def __del__(self):
+    def close(self):
+        """Destroy the library handle (its device tables, graphs and private
+        stream) and drop the workspaces; the object is unusable afterwards."""
         h = getattr(self, "h", None)
         if h is not None and h.value:
             self._lib.mhdg_destroy(h)
-            self.h = None
+        self.h = None
+        self.factor_ws = self.solve_ws = self.fold_ws = None
+
+    def __del__(self):
+        self.close()
 
     def _check(self, st, what):
         if st != 0:

@@ -1,0 +1,373 @@
+"""GPU parity at the full benchmark sizes, on outputs the oracle forms one by one.
+
+The trace operator is local (eq. global_problem; steps 1-4 of section 3.3.2):
+(S lam)_F, (S^T lam)_F and f^_F involve only the two macros that share face
+F, and the recovered U_K only macro K.  So on the full meshes -- 8192 macros
+at r = 3, p = 3; 8192 macros with r from {1, 2, 3, 4}; 64 coefficient
+instances of a 128-macro block; 32,768 macros at r = 2, p = 2 -- the oracle
+computes a seeded sample of faces and macros exactly, and the GPU results
+there must match it to the FP64 bar (relative 1e-10).  The handles are set
+up the way the benchmark times them: FP64 factors, autotuned variants,
+graph-captured applies, GMRES to 1e-10 with restart 2000.
+
+A converged solve cannot be compared with a direct solve at these sizes;
+there the property checked is the one GMRES guarantees: the
+D^-1-preconditioned residual f^ - S lam, formed by the oracle from the GPU's
+lam on the sampled faces, is a part of the whole residual, which is at most
+rtol = 1e-10 times ||D^-1 f^|| over the whole mesh.  That norm comes from the
+oracle too (every macro's local solve, in worker processes); f^ is far from
+evenly spread (on the 8192-macro mesh a few faces hold most of it), so no
+estimate from the sample would do.  The bound allows a factor 2 for the
+difference between GMRES's residual and the oracle's evaluation of it.
+"""
+import gc
+
+import numpy as np
+import pytest
+
+from oracle import hdg
+from paper_2302_10917_amd import inputs
+
+import oracle_parallel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_10917_amd import mhdg  # noqa: E402
+
+DEV = "cuda"
+TOL = 1e-10          # FP64 parity bar
+RTOL = 1e-10         # solve tolerance (relative preconditioned residual)
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def release(m):
+    """Free a handle's device memory now (the next full-size case needs it)."""
+    m.close()
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def sample_faces(topo, k, seed):
+    """k seeded interior faces plus the first and last interior face."""
+    interior = np.flatnonzero(np.asarray(topo.interior))
+    pick = np.random.default_rng(seed).choice(interior, size=min(k, len(interior)), replace=False)
+    return sorted(set(int(f) for f in pick) | {int(interior[0]), int(interior[-1])})
+
+
+def face_slice(topo, f, base=0):
+    o = base + int(topo.trace_off[f])
+    return slice(o, o + int(topo.face_nodes[f]))
+
+
+def gather(v, topo, faces, base=0):
+    return np.concatenate([v[face_slice(topo, f, base)] for f in faces])
+
+
+def macros_of(topo, faces):
+    return sorted({K for f in faces for K, _ in topo.face_incid[f]})
+
+
+def sampled_local(orc, macros, lam, f_nodal, lamD):
+    """Per sampled macro: A_K^-1 R_K and U_K = A_K^-1 (R_K - B_K lam_K)
+    (eq. local_problem)."""
+    Y, U = {}, {}
+    for K in macros:
+        b = orc.blocks(K)
+        R = orc.local_rhs(K, f_nodal, lamD)
+        Y[K] = orc.local_solve(K, R)
+        rhs = R.copy()
+        for k, o, nF in orc._interior_cols(K):
+            rhs -= b.B[k] @ lam[o:o + nF]
+        U[K] = orc.local_solve(K, rhs)
+    return Y, U
+
+
+def sampled_residual(orc, faces, lam, Y, U):
+    """D^-1 (f^ - S lam) and D^-1 f^ on the sampled faces, with
+    f^_F = -sum C_K A_K^-1 R_K and f^ - S lam = -(sum C_K U_K + D_F lam_F)."""
+    topo = orc.topo
+    res, rhs = [], []
+    for f in faces:
+        D = orc.D_face(f)
+        lf = lam[face_slice(topo, f)]
+        t = D @ lf + sum(orc.blocks(K).C[k] @ U[K] for K, k in topo.face_incid[f])
+        fh = -sum(orc.blocks(K).C[k] @ Y[K] for K, k in topo.face_incid[f])
+        res.append(np.linalg.solve(D, -t))
+        rhs.append(np.linalg.solve(D, fh))
+    return np.concatenate(res), np.concatenate(rhs)
+
+
+def check_residual(res_o, scale, what=""):
+    """Sampled residual within the solve's global bound."""
+    ratio = np.linalg.norm(res_o) / (RTOL * scale)
+    print(f"  {what}sampled residual / (rtol ||D^-1 f^||) = {ratio:.2e}", flush=True)
+    assert ratio <= 2.0, (what, ratio)
+
+
+def apply_sampled(m, orc, faces, lam_h, folded, base=0, n_total=None):
+    """GPU applies (direct and graph-captured, forward and transposed) against
+    the oracle on the sampled faces."""
+    topo = orc.topo
+    n = n_total or topo.n_trace
+    lam = gpu(lam_h)
+    out = torch.empty(n, dtype=torch.float64, device=DEV)
+    lam_i = lam_h[base:base + topo.n_trace]
+    for transpose in (False, True):
+        ref = gather(orc.apply(lam_i, precondition=True, faces=faces, transpose=transpose),
+                     topo, faces)
+        forms = [0, mhdg.MHDG_GRAPH] + ([mhdg.MHDG_FOLDED | mhdg.MHDG_GRAPH] if folded else [])
+        for extra in forms:
+            flags = mhdg.MHDG_PRECONDITION | extra
+            if transpose:
+                flags |= mhdg.MHDG_TRANSPOSE
+            m.apply_trace_operator(lam, out, flags)
+            err = rel(gather(host(out), topo, faces, base), ref)
+            print(f"  apply transpose={transpose} flags={extra}: {err:.2e}", flush=True)
+            assert err <= TOL, (transpose, extra, err)
+
+
+# ------------------------- 8192 macros, r=3, p=3, reduced-precision factors
+_SCALE = {}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_c2_kappa1e3_refined_solve_sampled(precision):
+    """Reduced-precision factors with FP64 refinement, kappa = 1e-3, to the
+    benchmark tolerance: the sampled FP64 residual of the result obeys the
+    same bound as a plain FP64 solve's, and U_K after local refinement
+    matches the oracle's recovery of the same lam."""
+    print(f"\n[fullsize 8192 macros r3 p3 kappa 1e-3 {precision}]", flush=True)
+    beta = (1.0, 0.5)
+    xy, tri = inputs.structured_mesh(64)
+    kap = np.full(len(tri), 1e-3)
+    orc = hdg.Oracle(xy, tri, 3, 3, kap, beta, 1.0)
+    ex = inputs.exp_sin(1e-3, beta)
+    m = mhdg.MacroMesh(xy, tri, 3, 3)
+    try:
+        prec = mhdg.MHDG_FP32 if precision == "fp32" else mhdg.MHDG_BF16
+        m.factor_local(gpu(kap), beta, 1.0, precision=prec)
+        node, bnd = m.sample_points()
+        f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+        lam = torch.zeros(orc.topo.n_trace, dtype=torch.float64, device=DEV)
+        info = m.solve(f, g, lam, rtol=1e-10, restart=2000, max_iter=20000, max_outer=60,
+                       inner_rtol=1e-5 if precision == "fp32" else 1e-2)
+        print(f"  outer={info.outer_iterations} inner={info.iterations}", flush=True)
+        assert info.status == 0
+        qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+        m.recover_local(lam, qu)
+        lam_h, quh = host(lam), host(qu)
+    finally:
+        release(m)
+    faces = sample_faces(orc.topo, 32, seed=102)
+    fo, go = orc.sample(ex)
+    macros = macros_of(orc.topo, faces)
+    lamD = orc.dirichlet_trace(go)
+    Y, U = sampled_local(orc, macros, lam_h, fo, lamD)
+    res_o, _ = sampled_residual(orc, faces, lam_h, Y, U)
+    if "kappa1e-3" not in _SCALE:        # shared by the FP32 and BF16 cases
+        _SCALE["kappa1e-3"] = oracle_parallel.preconditioned_rhs_norm(xy, tri, 3, 3, kap, beta,
+                                                                      1.0, fo, lamD)
+    check_residual(res_o, _SCALE["kappa1e-3"])
+    for K in macros:
+        assert rel(quh[orc.topo.local_off[K]:orc.topo.local_off[K + 1]], U[K]) <= TOL, K
+
+
+# ------------------------------------------ 8192 macros, r from {1,2,3,4}, p = 3
+def test_mixed_levels_8192_apply_sampled():
+    """Non-matching interfaces at full size (instance 0 of the 64
+    coefficient instances): plain and folded, forward and transposed."""
+    print("\n[fullsize 8192 macros r1..4 p3]", flush=True)
+    xy, tri = inputs.structured_mesh(64)
+    r = inputs.random_levels(len(tri), (1, 2, 3, 4), seed=3)
+    kap_i, beta_i = inputs.coefficient_instances(64, seed=33)
+    kap = np.full(len(tri), float(kap_i[0]))
+    beta = tuple(float(x) for x in beta_i[0])
+    orc = hdg.Oracle(xy, tri, r, 3, kap, beta, 1.0)
+    faces = sample_faces(orc.topo, 16, seed=103)
+    m = mhdg.MacroMesh(xy, tri, r, 3)
+    try:
+        m.factor_local(gpu(kap), beta, 1.0)
+        m.autotune()
+        m.fold_operator()
+        lam = inputs.random_vector(orc.topo.n_trace, seed=4)
+        apply_sampled(m, orc, faces, lam, folded=True)
+    finally:
+        release(m)
+
+
+# --------------------------- 64 coefficient instances of a 128-macro mixed block
+def test_batched_64_instances_sampled():
+    """All 64 instances in one handle: the batched apply and the lockstep
+    GMRES (to 1e-10) checked per instance on sampled faces and macros."""
+    print("\n[fullsize 64 instances x 128 macros r1..4 p3]", flush=True)
+    n_inst = 64
+    xy, tri = inputs.structured_mesh(8)
+    r = inputs.random_levels(len(tri), (1, 2, 3, 4), seed=3)
+    kap_i, beta_i = inputs.coefficient_instances(n_inst, seed=33)
+    m = mhdg.MacroMesh(xy, tri, r, 3)
+    one = m.sizes
+    m.set_instances(n_inst)
+    try:
+        m.factor_local(gpu(np.repeat(kap_i, len(tri))), beta_i, 1.0)
+        m.autotune()
+        node, bnd = m.sample_points()
+        fh, gh = np.empty(m.sizes.n_nodes), np.empty(m.sizes.n_bnd_points)
+        for i in range(n_inst):
+            ex = inputs.exp_sin(float(kap_i[i]), beta_i[i])
+            a, b = i * one.n_nodes, (i + 1) * one.n_nodes
+            fh[a:b] = ex.f(node[a:b, 0], node[a:b, 1])
+            a, b = i * one.n_bnd_points, (i + 1) * one.n_bnd_points
+            gh[a:b] = ex.u(bnd[a:b, 0], bnd[a:b, 1])
+        nt = one.n_trace
+        lam_r = inputs.random_vector(n_inst * nt, seed=5)
+        out = torch.empty(n_inst * nt, dtype=torch.float64, device=DEV)
+        m.apply_trace_operator(gpu(lam_r), out, mhdg.MHDG_PRECONDITION | mhdg.MHDG_GRAPH)
+        out_h = host(out)
+        lam = torch.zeros(n_inst * nt, dtype=torch.float64, device=DEV)
+        info = m.solve(gpu(fh), gpu(gh), lam, rtol=1e-10, restart=2000, max_iter=20000)
+        assert info.status == 0
+        lam_h = host(lam)
+        qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+        m.recover_local(lam, qu)
+        quh = host(qu)
+    finally:
+        release(m)
+    for i in (0, 17, 63):
+        beta = tuple(float(x) for x in beta_i[i])
+        orc = hdg.Oracle(xy, tri, r, 3, float(kap_i[i]), beta, 1.0)
+        topo = orc.topo
+        faces = sample_faces(topo, 8, seed=200 + i)
+        base = i * nt
+        ref = gather(orc.apply(lam_r[base:base + nt], precondition=True, faces=faces), topo, faces)
+        assert rel(gather(out_h, topo, faces, base), ref) <= TOL, i
+        ex = inputs.exp_sin(float(kap_i[i]), beta_i[i])
+        fo, go = orc.sample(ex)
+        lamD = orc.dirichlet_trace(go)
+        macros = macros_of(topo, faces)
+        li = lam_h[base:base + nt]
+        Y, U = sampled_local(orc, macros, li, fo, lamD)
+        res_o, _ = sampled_residual(orc, faces, li, Y, U)
+        scale = oracle_parallel.preconditioned_rhs_norm(xy, tri, r, 3, float(kap_i[i]), beta, 1.0,
+                                                        fo, lamD)
+        check_residual(res_o, scale, f"instance {i}: ")
+        lo = i * one.n_local
+        for K in macros:
+            got = quh[lo + topo.local_off[K]:lo + topo.local_off[K + 1]]
+            assert rel(got, U[K]) <= TOL, (i, K)
+
+
+# ------------------------------------------------ 32,768 macros, r = 2, p = 2
+def test_adjoint_mesh_apply_sampled():
+    """The differentiation mesh with its log-normal kappa field: the forward
+    and transposed operators the adjoint gradient runs on, plain and folded."""
+    print("\n[fullsize 32768 macros r2 p2]", flush=True)
+    xy, tri = inputs.structured_mesh(128)
+    kap = inputs.lognormal_kappa(len(tri), 0.5, seed=5)
+    beta = (1.0, 1.0)
+    orc = hdg.Oracle(xy, tri, 2, 2, kap, beta, 1.0)
+    faces = sample_faces(orc.topo, 32, seed=104)
+    m = mhdg.MacroMesh(xy, tri, 2, 2)
+    try:
+        m.factor_local(gpu(kap), beta, 1.0)
+        m.fold_operator()
+        lam = inputs.random_vector(orc.topo.n_trace, seed=6)
+        apply_sampled(m, orc, faces, lam, folded=True)
+    finally:
+        release(m)
+
+
+# ------------------------------------------- 8192 macros, r=3, p=3, FP64
+# (last in the module: its handle lives until the module ends)
+C2 = dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5))
+
+
+@pytest.fixture(scope="module")
+def c2():
+    print("\n[fullsize 8192 macros r3 p3 setup]", flush=True)
+    xy, tri = inputs.structured_mesh(C2["n"])
+    kap = np.full(len(tri), C2["kappa"])
+    orc = hdg.Oracle(xy, tri, C2["r"], C2["p"], kap, C2["beta"], 1.0)
+    m = mhdg.MacroMesh(xy, tri, C2["r"], C2["p"])
+    m.factor_local(gpu(kap), C2["beta"], 1.0)
+    m.autotune()
+    m.fold_operator()
+    ex = inputs.exp_sin(C2["kappa"], C2["beta"])
+    node, bnd = m.sample_points()
+    f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+    fo, go = orc.sample(ex)
+    lamD = orc.dirichlet_trace(go)
+    faces = sample_faces(orc.topo, 32, seed=101)
+    scale = oracle_parallel.preconditioned_rhs_norm(xy, tri, C2["r"], C2["p"], kap, C2["beta"],
+                                                    1.0, fo, lamD)
+    yield dict(m=m, orc=orc, f=f, g=g, fo=fo, lamD=lamD, faces=faces,
+               macros=macros_of(orc.topo, faces), fhat_norm=scale)
+    release(m)
+
+
+def test_c2_apply_sampled(c2):
+    orc = c2["orc"]
+    lam = inputs.random_vector(orc.topo.n_trace, seed=1)
+    apply_sampled(c2["m"], orc, c2["faces"], lam, folded=True)
+
+
+def test_c2_rhs_and_recovery_sampled(c2):
+    """f^ (D^-1 f^) on sampled faces; U_K and the transmission residual for a
+    random lam on sampled macros and faces."""
+    m, orc, faces, macros = c2["m"], c2["orc"], c2["faces"], c2["macros"]
+    topo = orc.topo
+    n = topo.n_trace
+    fhat = torch.empty(n, dtype=torch.float64, device=DEV)
+    m.rhs(c2["f"], c2["g"], fhat, mhdg.MHDG_PRECONDITION)
+    lam_h = inputs.random_vector(n, seed=3)
+    Y, U = sampled_local(orc, macros, lam_h, c2["fo"], c2["lamD"])
+    res_o, fh_o = sampled_residual(orc, faces, lam_h, Y, U)
+    assert rel(gather(host(fhat), topo, faces), fh_o) <= TOL
+    qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+    res = torch.empty(n, dtype=torch.float64, device=DEV)
+    m.recover_local(gpu(lam_h), qu, res)
+    quh, resh = host(qu), host(res)
+    for K in macros:
+        assert rel(quh[topo.local_off[K]:topo.local_off[K + 1]], U[K]) <= TOL, K
+    # flux_res holds sum C U + D lam (unpreconditioned)
+    t_o = np.concatenate([orc.D_face(f) @ lam_h[face_slice(topo, f)]
+                          + sum(orc.blocks(K).C[k] @ U[K] for K, k in topo.face_incid[f])
+                          for f in faces])
+    assert rel(gather(resh, topo, faces), t_o) <= TOL
+
+
+@pytest.mark.parametrize("folded", [False, True])
+def test_c2_solve_sampled(c2, folded):
+    m, orc, faces, macros = c2["m"], c2["orc"], c2["faces"], c2["macros"]
+    topo = orc.topo
+    lam = torch.zeros(topo.n_trace, dtype=torch.float64, device=DEV)
+    info = m.solve(c2["f"], c2["g"], lam, rtol=1e-10, restart=2000, max_iter=20000,
+                   folded=folded)
+    print(f"  folded={folded}: {info.iterations} it, rel {info.rel_res_prec:.2e}", flush=True)
+    assert info.status == 0
+    lam_h = host(lam)
+    Y, U = sampled_local(orc, macros, lam_h, c2["fo"], c2["lamD"])
+    res_o, _ = sampled_residual(orc, faces, lam_h, Y, U)
+    check_residual(res_o, c2["fhat_norm"])
+    qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    quh = host(qu)
+    for K in macros:
+        assert rel(quh[topo.local_off[K]:topo.local_off[K + 1]], U[K]) <= TOL, K
