@@ -5,16 +5,13 @@
 // C_K A_K^-1 B_K to lambda_K through the stored LU factors.  Folding stores the
 // product itself, a dense L_K x L_K matrix over the macro's interior-face
 // trace dofs (L_K = sum of n_F over its interior faces), so an apply reads
-// L_K^2 values per macro instead of N_K^2.  T_K is built column by column with
-// the same per-macro solves: with the interior faces coloured so that no macro
-// has two faces of one colour, one apply of the indicator of (colour c,
-// position i) leaves in every macro's contribution slots exactly one column
-// of its T_K.
+// L_K^2 values per macro instead of N_K^2.  T_K is built from the stored
+// factors by triangular solves with many right-hand sides: the columns of B_K.
 //
 // Local numbering of a macro's trace dofs: its interior edges k = 0, 1, 2 in
 // order, position i along the face (face canonical direction) within each,
-// the same order as its contribution slots.
-#include "internal.h"
+// the same order as its contribution slots.  T_K is column-major.
+#include "macro_solve.h"
 
 namespace mhdg {
 
@@ -22,41 +19,199 @@ __device__ __forceinline__ int face_nodes(const MacroInfo& mi, int k, int p) {
   return (1 << mi.flevel[k]) * p + 1;
 }
 
-// lam = indicator of position i on every interior face of colour c
-__global__ void fold_indicator_kernel(const FaceInfo* __restrict__ fi, int64_t nf,
-                                      const int32_t* __restrict__ icolor, int c, int i,
-                                      double* __restrict__ lam) {
-  const int64_t f = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (f >= nf) return;
-  const FaceInfo& F = fi[f];
-  for (int l = 0; l < F.nF; ++l) lam[F.tr_off + l] = (icolor[f] == c && l == i) ? 1.0 : 0.0;
+// Build of T_K.  One wavefront takes NR consecutive columns col0 .. col0+NR-1
+// of B_K (column col = trace position i of interior edge k: the boundary-row
+// lift of a unit trace value, one column of the edge template), runs the
+// forward and backward sweeps with the NR right-hand sides in registers
+// (lane l holding rows l + 64 q, as in the single-right-hand-side solve; each
+// factor column is loaded once and used NR times), and restricts the NR
+// solutions with C_K into NR columns of T_K.  The ceil(L_K / NR) wavefronts of
+// a macro are consecutive in the dispatch of one XCD (block b runs on XCD
+// b mod 8), so they start together and stream the same factor columns
+// through that XCD's L2.  NQ may exceed ceil(N_K / 64): every row index is
+// clamped to the macro's column and rows past N_K take no part.
+template <int NQ, int NR>
+__global__ __launch_bounds__(64) void fold_build_kernel(
+    const double* __restrict__ fac, const MacroInfo* __restrict__ info,
+    const int32_t* __restrict__ order, int64_t base, int64_t count, int nch,
+    const int32_t* __restrict__ perm_all, const double* __restrict__ tm, Templates Tp,
+    double tau, const int64_t* __restrict__ toff, double* __restrict__ T) {
+  constexpr int kLG = kLoadGroup;
+  extern __shared__ double sm[];   // NR compact boundary vectors of 3 NBD entries
+  const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
+  const int64_t m = int64_t(seq / nch) * 8 + xcd;
+  const int chunk = seq % nch;
+  if (m >= count) return;
+  const int e = order[base + m];
+  const MacroInfo& mi = info[e];
+  const int N = mi.N, Q = mi.Q, P = mi.P, NBD = 3 * P, lane = threadIdx.x, p = Tp.p;
+  int lo[3], nk[3], L = 0;
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = L;
+    nk[k] = mi.tr_off[k] >= 0 ? face_nodes(mi, k, p) : 0;
+    L += nk[k];
+  }
+  const int col0 = chunk * NR;
+  if (col0 >= L) return;
+  const LevelTemplates& LT = Tp.lev[mi.level];
+  // ---- columns of B_K on the compact boundary rows (step 1 for a unit trace value)
+  for (int t = lane; t < NR * 3 * NBD; t += 64) sm[t] = 0.0;
+  __syncthreads();
+  for (int r = 0; r < NR && col0 + r < L; ++r) {
+    const int col = col0 + r;
+    const int k = col < lo[1] ? 0 : (col < lo[2] ? 1 : 2);
+    const int i = col - lo[k], nF = nk[k];
+    const double* T1 = tm + LT.T1[mi.flevel[k]];
+    const EdgeCoef c = coef_B(mi, k, tau);
+    double* xc = sm + r * 3 * NBD;
+    for (int s = lane; s <= P; s += 64) {
+      const int sc = mi.orient[k] > 0 ? s : P - s;
+      const double g = T1[size_t(sc) * nF + i] * mi.len[k];
+      const int b = bpos(k, s, P);
+      xc[b] = c.c0 * g;
+      xc[NBD + b] = c.c1 * g;
+      xc[2 * NBD + b] = c.c2 * g;
+    }
+  }
+  __syncthreads();
+  const int32_t* bidx = ints_(tm, LT.bnd_index);
+  const int32_t* perm = perm_all + mi.loc_off;
+  double y[NQ][NR];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    int b = -1, f = 0;
+    if (i < N) {
+      const int rw = perm[i];
+      f = rw / Q;
+      b = bidx[rw - f * Q];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) y[q][r] = b >= 0 ? sm[r * 3 * NBD + f * NBD + b] : 0.0;
+  }
+  const double* A = fac + mi.fac_off;
+  // ---- forward substitution with the unit lower factor
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int jend = min(64, N - 64 * q);
+    for (int jj = 0; jj < jend; ++jj) {
+      const int j = 64 * q + jj;
+      double yj[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) yj[r] = readlane_d(y[q][r], jj);
+      const double* col = A + size_t(j) * mi.ld;
+#pragma unroll
+      for (int g = q; g < NQ; g += kLG) {
+        double a[kLG];
+#pragma unroll
+        for (int t = 0; t < kLG; ++t) {
+          const int rw = lane + 64 * (g + t);
+          int rr = (g + t == q && rw <= j) ? j + 1 : rw;
+          rr = rr < N ? rr : N - 1;
+          a[t] = (g + t < NQ) ? col[rr] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kLG; ++t) {
+          const int rw = lane + 64 * (g + t);
+          if (g + t < NQ) {
+            const double av = (rw > j && rw < N) ? a[t] : 0.0;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) y[g + t][r] -= av * yj[r];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  // ---- backward substitution with the upper factor
+#pragma unroll
+  for (int q = NQ - 1; q >= 0; --q) {
+    const int jend = min(64, N - 64 * q);
+    for (int jj = jend - 1; jj >= 0; --jj) {
+      const int j = 64 * q + jj;
+      const double* col = A + size_t(j) * mi.ld;
+      const double dj = col[j];
+      double zj[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        zj[r] = readlane_d(y[q][r], jj) / dj;
+        if (lane == jj) y[q][r] = zj[r];
+      }
+#pragma unroll
+      for (int g = 0; g <= q; g += kLG) {
+        double a[kLG];
+#pragma unroll
+        for (int t = 0; t < kLG; ++t) {
+          const int rw = lane + 64 * (g + t);
+          const int rr = (g + t == q && rw >= j) ? (j > 0 ? j - 1 : 0) : rw;
+          a[t] = (g + t <= q) ? col[rr] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kLG; ++t) {
+          const int rw = lane + 64 * (g + t);
+          if (g + t <= q) {
+            const double av = rw < j ? a[t] : 0.0;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) y[g + t][r] -= av * zj[r];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  // ---- restriction with C_K (step 3): boundary rows of the solutions, then
+  // per interior edge the trace moments, into columns col0 .. of T_K
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    if (i < N) {
+      const int f = i / Q;
+      const int b = bidx[i - f * Q];
+      if (b >= 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) sm[r * 3 * NBD + f * NBD + b] = y[q][r];
+      }
+    }
+  }
+  __syncthreads();
+  double* Tm = T + toff[e];
+  for (int r = 0; r < NR && col0 + r < L; ++r) {
+    const double* zc = sm + r * 3 * NBD;
+    double* Tc = Tm + int64_t(col0 + r) * L;
+    for (int k = 0; k < 3; ++k)
+      if (nk[k] > 0) edge_C(mi, k, tm, Tp, zc, tau, Tc + lo[k]);
+  }
 }
 
-// Column (colour c, position i) of every T_K from the contribution slots.
-// fcolor: colour of each face (by face id), -1 on the boundary.
-__global__ __launch_bounds__(64) void fold_scatter_kernel(const MacroInfo* __restrict__ info,
-                                                          const int64_t* __restrict__ toff,
-                                                          const int32_t* __restrict__ fcolor,
-                                                          int p, int c, int i,
-                                                          const double* __restrict__ slots,
-                                                          double* __restrict__ T) {
-  const MacroInfo& mi = info[blockIdx.x];
-  int L = 0, col = -1;
-  for (int k = 0; k < 3; ++k) {
-    if (mi.tr_off[k] < 0) continue;
-    const int nF = face_nodes(mi, k, p);
-    if (fcolor[mi.face[k]] == c && i < nF) col = L + i;
-    L += nF;
+hipError_t launch_fold_build(const double* fac, const MacroInfo* info, const int32_t* order,
+                             const SizeClass* classes, int n_classes, const int32_t* perm,
+                             const double* tmpl, const Templates& T, double tau, int max_L,
+                             const int64_t* toff, double* out, hipStream_t s) {
+  for (int c = 0; c < n_classes; ++c) {
+    const SizeClass& sc = classes[c];
+    if (sc.count == 0) continue;
+    const int nq = (sc.N + 63) / 64;
+    const int nr = nq <= 16 ? 4 : (nq <= 32 ? 2 : 1);
+    const int nch = (max_L + nr - 1) / nr;
+    const int64_t nblk = (sc.count + 7) / 8 * 8 * int64_t(nch);
+    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    const size_t lds = size_t(nr) * 9 * sc.P * sizeof(double);
+    const dim3 g((unsigned)nblk), b(64);
+#define MHDG_FOLD_BUILD(NQ_, NR_)                                                              \
+  hipLaunchKernelGGL((fold_build_kernel<NQ_, NR_>), g, b, lds, s, fac, info, order, sc.start,  \
+                     sc.count, nch, perm, tmpl, T, tau, toff, out)
+    if (nq <= 4) MHDG_FOLD_BUILD(4, 4);
+    else if (nq <= 8) MHDG_FOLD_BUILD(8, 4);
+    else if (nq <= 16) MHDG_FOLD_BUILD(16, 4);
+    else if (nq <= 32) MHDG_FOLD_BUILD(32, 2);
+    else if (nq <= 58) MHDG_FOLD_BUILD(58, 1);
+    else return hipErrorInvalidValue;
+#undef MHDG_FOLD_BUILD
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  if (col < 0) return;
-  double* Tc = T + toff[blockIdx.x] + int64_t(col) * L;
-  int r0 = 0;
-  for (int k = 0; k < 3; ++k) {
-    if (mi.tr_off[k] < 0) continue;
-    const int nF = face_nodes(mi, k, p);
-    for (int l = threadIdx.x; l < nF; l += 64) Tc[r0 + l] = slots[mi.slot_off[k] + l];
-    r0 += nF;
-  }
+  return hipSuccess;
 }
 
 // Steps 1-3 with the folded operators: slots of macro K = T_K lambda_K, or
@@ -126,22 +281,6 @@ __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restr
     }
     r0 += nF;
   }
-}
-
-hipError_t launch_fold_indicator(const FaceInfo* fi, int64_t nf, const int32_t* icolor, int c,
-                                 int i, double* lam, hipStream_t s) {
-  if (nf == 0) return hipSuccess;
-  hipLaunchKernelGGL(fold_indicator_kernel, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
-                     fi, nf, icolor, c, i, lam);
-  return hipGetLastError();
-}
-
-hipError_t launch_fold_scatter(const MacroInfo* info, int64_t n, const int64_t* toff,
-                               const int32_t* fcolor, int p, int c, int i, const double* slots,
-                               double* T, hipStream_t s) {
-  hipLaunchKernelGGL(fold_scatter_kernel, dim3((unsigned)n), dim3(64), 0, s, info, toff, fcolor, p,
-                     c, i, slots, T);
-  return hipGetLastError();
 }
 
 hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,

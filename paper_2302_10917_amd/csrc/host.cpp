@@ -455,15 +455,12 @@ static int fold_L(const mhdg_mesh* M, const MacroInfo& mi) {
   return L;
 }
 
-// Fold workspace: T_K offsets int64[n_macro], face colours int32[n_faces],
-// interior-face colours int32[n_int], then every T_K (FP64, column-major).
-struct FoldLayout { size_t toff, fcolor, icolor, T, total; int64_t nT; };
+// Fold workspace: T_K offsets int64[n_macro], then every T_K (FP64, column-major).
+struct FoldLayout { size_t toff, T, total; int64_t nT; };
 static FoldLayout fold_layout(const mhdg_mesh* M) {
   FoldLayout F{};
   size_t o = 0;
   F.toff = o;   o = align_up(o + size_t(M->n_macro) * 8);
-  F.fcolor = o; o = align_up(o + size_t(M->n_faces) * 4);
-  F.icolor = o; o = align_up(o + size_t(std::max<int64_t>(M->n_int, 1)) * 4);
   F.T = o;
   int64_t nT = 0;
   for (auto& mi : M->macros) { const int64_t L = fold_L(M, mi); nT += L * L; }
@@ -1485,11 +1482,10 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* st
     return fail(M, MHDG_ERR_WORKSPACE, "fold_operator: workspace smaller than mhdg_query reports");
   hipStream_t s = (hipStream_t)stream;
   char* fw = (char*)ws;
-  // per-macro offsets, and a colouring of the interior faces in which the
-  // faces of one macro differ (greedy; at most 5 colours with 3 faces per macro)
+  // per-macro offsets of T_K
   std::vector<int64_t> toff(M->n_macro);
   int64_t o = 0;
-  int maxL = 0, maxNF = 0;
+  int maxL = 0;
   for (int64_t e = 0; e < M->n_macro; ++e) {
     toff[e] = o;
     const int L = fold_L(M, M->macros[e]);
@@ -1497,54 +1493,16 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* st
     o += int64_t(L) * L;
   }
   if (maxL > kFoldMaxL) return fail(M, MHDG_ERR_INVALID_ARG, "fold_operator: macro trace too large");
-  std::vector<int32_t> fcolor(M->n_faces, -1), icolor(std::max<int64_t>(M->n_int, 1), -1);
-  std::vector<uint8_t> used(M->n_macro, 0);
-  std::vector<std::array<int64_t, 2>> fmac(M->n_faces, {-1, -1});
-  std::vector<int32_t> ftr(M->n_faces, -1);
-  for (int64_t e = 0; e < M->n_macro; ++e)
-    for (int k = 0; k < 3; ++k) {
-      const MacroInfo& mi = M->macros[e];
-      if (mi.tr_off[k] < 0) continue;
-      auto& fm = fmac[mi.face[k]];
-      fm[fm[0] < 0 ? 0 : 1] = e;
-      ftr[mi.face[k]] = mi.tr_off[k];
-      maxNF = std::max(maxNF, (1 << mi.flevel[k]) * M->p + 1);
-    }
-  int ncol = 0;
-  for (int64_t f = 0; f < M->n_faces; ++f) {
-    if (fmac[f][0] < 0) continue;
-    const uint8_t u = used[fmac[f][0]] | (fmac[f][1] >= 0 ? used[fmac[f][1]] : 0);
-    int c = 0;
-    while (u & (1u << c)) ++c;
-    fcolor[f] = c;
-    ncol = std::max(ncol, c + 1);
-    for (int s2 = 0; s2 < 2; ++s2)
-      if (fmac[f][s2] >= 0) used[fmac[f][s2]] |= uint8_t(1u << c);
-  }
-  {
-    std::map<int32_t, int64_t> tr2idx;
-    for (int64_t i = 0; i < M->n_int; ++i) tr2idx[M->faces[i].tr_off] = i;
-    for (int64_t f = 0; f < M->n_faces; ++f)
-      if (fcolor[f] >= 0) icolor[tr2idx.at(ftr[f])] = fcolor[f];
-  }
   HIP_TRY(M, hipMemcpyAsync(fw + F.toff, toff.data(), toff.size() * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(M, hipMemcpyAsync(fw + F.fcolor, fcolor.data(), fcolor.size() * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(M, hipMemcpyAsync(fw + F.icolor, icolor.data(), icolor.size() * 4, hipMemcpyHostToDevice, s));
   FactorLayout& L = M->L;
   char* w = M->ws;
-  const MacroInfo* info = (const MacroInfo*)(w + L.meta);
-  double* lam = (double*)(w + L.work1);   // n_local >= n_trace doubles
   double* T = (double*)(fw + F.T);
-  for (int c = 0; c < ncol; ++c)
-    for (int i = 0; i < maxNF; ++i) {
-      HIP_TRY(M, launch_fold_indicator((const FaceInfo*)(w + L.faces), M->n_int,
-                                       (const int32_t*)(fw + F.icolor), c, i, lam, s));
-      mhdg_status st = run_macro_solve(M, MODE_APPLY, 0, lam, nullptr, nullptr, s);
-      if (st) return st;
-      HIP_TRY(M, launch_fold_scatter(info, M->n_macro, (const int64_t*)(fw + F.toff),
-                                     (const int32_t*)(fw + F.fcolor), M->p, c, i,
-                                     (const double*)(w + L.slots), T, s));
-    }
+  if (maxL > 0)
+    HIP_TRY(M, launch_fold_build((const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
+                                 (const int32_t*)(w + L.order), M->classes.data(),
+                                 (int)M->classes.size(), (const int32_t*)(w + L.perm),
+                                 (const double*)(w + L.tmpl), M->T, M->tau, maxL,
+                                 (const int64_t*)(fw + F.toff), T, s));
   HIP_TRY(M, hipStreamSynchronize(s));
   M->fold_toff = (int64_t*)(fw + F.toff);
   M->fold_T = T;

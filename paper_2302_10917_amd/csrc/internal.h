@@ -151,11 +151,11 @@ enum FaceMode { FACE_S = 0, FACE_PREC_S = 1, FACE_RHS = 2, FACE_PREC_RHS = 3, FA
 
 // folded macro operators T_K = C_K A_K^-1 B_K (fold.hip)
 constexpr int kFoldMaxL = 192;
-hipError_t launch_fold_indicator(const FaceInfo* fi, int64_t nf, const int32_t* icolor, int c,
-                                 int i, double* lam, hipStream_t s);
-hipError_t launch_fold_scatter(const MacroInfo* info, int64_t n, const int64_t* toff,
-                               const int32_t* fcolor, int p, int c, int i, const double* slots,
-                               double* T, hipStream_t s);
+// T_K for every macro, from the FP64 factors (max_L: the largest L_K)
+hipError_t launch_fold_build(const double* fac, const MacroInfo* info, const int32_t* order,
+                             const SizeClass* classes, int n_classes, const int32_t* perm,
+                             const double* tmpl, const Templates& T, double tau, int max_L,
+                             const int64_t* toff, double* out, hipStream_t s);
 hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,
                              int p, const int32_t* skip, int transpose, const double* lam,
                              double* slots, hipStream_t s);
