@@ -216,12 +216,14 @@ hipError_t launch_fold_build(const double* fac, const MacroInfo* info, const int
 
 // Steps 1-3 with the folded operators: slots of macro K = T_K lambda_K, or
 // T_K^T lambda_K for the transposed operator S^T (adjoint solves).  One
-// wavefront per macro with lambda_K gathered into LDS.  Forward: T_K streamed
-// column by column, coalesced across the lanes, lane l accumulating rows
-// l + 64 t.  Transposed: lane l forms the dot product of column l + 64 t with
-// lambda_K (each lane walks its own contiguous column; a macro's T_K is a
-// few KB and stays in cache).
-constexpr int kFoldRows = 3;   // rows per lane: L_K <= 192 (checked on the host)
+// wavefront per macro with lambda_K gathered into LDS; lane l owns rows
+// l + 64 t (t < NT, L_K <= 64 NT).  T_K is read column by column, coalesced
+// across the lanes, in batches of CB columns whose loads are all issued
+// before any of them is used (a macro's T_K is read in ceil(L_K / CB) memory
+// round trips).  Forward: row r accumulates T[r][c] lambda_c.  Transposed:
+// column c's dot product with lambda is summed across the wavefront and kept
+// by the lane that owns row c.
+template <int NT>
 __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restrict__ info,
                                                         const int64_t* __restrict__ toff,
                                                         const double* __restrict__ T, int p,
@@ -229,7 +231,8 @@ __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restr
                                                         int transpose,
                                                         const double* __restrict__ lam,
                                                         double* __restrict__ slots) {
-  __shared__ double xl[64 * kFoldRows];
+  constexpr int CB = NT == 3 ? 8 : 16;
+  __shared__ double xl[64 * NT];
   const MacroInfo& mi = info[blockIdx.x];
   if (skip && skip[mi.inst]) return;
   const int lane = threadIdx.x;
@@ -243,30 +246,40 @@ __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restr
   if (L == 0) return;
   __syncthreads();
   const double* Tm = T + toff[blockIdx.x];
-  double acc[kFoldRows];
+  double xr[NT], acc[NT];
 #pragma unroll
-  for (int t = 0; t < kFoldRows; ++t) acc[t] = 0.0;
-  const int nt = (L + 63) >> 6;
-  if (!transpose) {
-#pragma unroll 4
-    for (int c = 0; c < L; ++c) {
-      const double x = xl[c];
-      const double* col = Tm + int64_t(c) * L;
+  for (int t = 0; t < NT; ++t) {
+    const int r = lane + 64 * t;
+    xr[t] = r < L ? xl[r] : 0.0;
+    acc[t] = 0.0;
+  }
+  for (int c0 = 0; c0 < L; c0 += CB) {
+    double a[CB][NT];
 #pragma unroll
-      for (int t = 0; t < kFoldRows; ++t) {
-        const int r = lane + 64 * t;
-        if (t < nt && r < L) acc[t] += col[r] * x;
+    for (int cc = 0; cc < CB; ++cc)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int c = c0 + cc, r = lane + 64 * t;
+        a[cc][t] = (c < L && r < L) ? Tm[int64_t(c) * L + r] : 0.0;
       }
-    }
-  } else {
+    if (!transpose) {
 #pragma unroll
-    for (int t = 0; t < kFoldRows; ++t) {
-      const int c = lane + 64 * t;
-      if (t < nt && c < L) {
-        const double* col = Tm + int64_t(c) * L;
-        double a = 0.0;
-        for (int r = 0; r < L; ++r) a += col[r] * xl[r];
-        acc[t] = a;
+      for (int cc = 0; cc < CB; ++cc) {
+        const double x = c0 + cc < L ? xl[c0 + cc] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] += a[cc][t] * x;
+      }
+    } else {
+#pragma unroll
+      for (int cc = 0; cc < CB; ++cc) {
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) v += a[cc][t] * xr[t];
+        v = wave_sum_(v);
+        const int c = c0 + cc;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (c == lane + 64 * t) acc[t] = v;
       }
     }
   }
@@ -275,19 +288,26 @@ __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restr
     if (mi.tr_off[k] < 0) continue;
     const int nF = face_nodes(mi, k, p);
 #pragma unroll
-    for (int t = 0; t < kFoldRows; ++t) {
+    for (int t = 0; t < NT; ++t) {
       const int r = lane + 64 * t;
-      if (t < nt && r >= r0 && r < r0 + nF) slots[mi.slot_off[k] + (r - r0)] = acc[t];
+      if (r >= r0 && r < r0 + nF) slots[mi.slot_off[k] + (r - r0)] = acc[t];
     }
     r0 += nF;
   }
 }
 
 hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,
-                             int p, const int32_t* skip, int transpose, const double* lam,
-                             double* slots, hipStream_t s) {
-  hipLaunchKernelGGL(fold_apply_kernel, dim3((unsigned)n), dim3(64), 0, s, info, toff, T, p, skip,
-                     transpose, lam, slots);
+                             int p, int max_L, const int32_t* skip, int transpose,
+                             const double* lam, double* slots, hipStream_t s) {
+  const dim3 g((unsigned)n), b(64);
+  if (max_L <= 64)
+    hipLaunchKernelGGL(fold_apply_kernel<1>, g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
+  else if (max_L <= 128)
+    hipLaunchKernelGGL(fold_apply_kernel<2>, g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
+  else if (max_L <= kFoldMaxL)
+    hipLaunchKernelGGL(fold_apply_kernel<3>, g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

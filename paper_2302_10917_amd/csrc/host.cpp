@@ -52,6 +52,7 @@ struct mhdg_mesh {
   bool folded = false;
   int64_t* fold_toff = nullptr;   // device: element offset of T_K
   double* fold_T = nullptr;       // device: T_K column-major, L_K x L_K
+  int fold_maxL = 0;              // largest L_K
   int precision = MHDG_FP64;
   double tau = 1;
   char* ws = nullptr;
@@ -1506,6 +1507,7 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* st
   HIP_TRY(M, hipStreamSynchronize(s));
   M->fold_toff = (int64_t*)(fw + F.toff);
   M->fold_T = T;
+  M->fold_maxL = maxL;
   M->folded = true;
   M->drop_graphs();
   return MHDG_OK;
@@ -1720,7 +1722,8 @@ mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t
     {
       ProfScope ps(M, 5, s);
       HIP_TRY(M, launch_fold_apply((const MacroInfo*)(M->ws + L.meta), M->n_macro, M->fold_toff,
-                                   M->fold_T, M->p, skip, tr, lam, (double*)(M->ws + L.slots), s));
+                                   M->fold_T, M->p, M->fold_maxL, skip, tr, lam,
+                                   (double*)(M->ws + L.slots), s));
     }
     ProfScope ps(M, 3, s);
     HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,

@@ -157,8 +157,8 @@ hipError_t launch_fold_build(const double* fac, const MacroInfo* info, const int
                              const double* tmpl, const Templates& T, double tau, int max_L,
                              const int64_t* toff, double* out, hipStream_t s);
 hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,
-                             int p, const int32_t* skip, int transpose, const double* lam,
-                             double* slots, hipStream_t s);
+                             int p, int max_L, const int32_t* skip, int transpose,
+                             const double* lam, double* slots, hipStream_t s);
 
 // GMRES vector kernels
 // Vectors may hold nseg independent segments of length n (coefficient
