@@ -44,6 +44,15 @@ WORKLOADS = {
     "folded_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
                                         sol="exp_sin", precision="fp64", form="folded",
                                         restart=50),
+    # flux eliminated exactly (same mesh and data): q through the reference mass, only the
+    # Q x Q Schur block on u factored and streamed (Q = 325: 8 Q^2 bytes per macro)
+    "qelim_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                       sol="exp_sin", precision="qelim"),
+    # folded operators built from the Schur-block factors: LU of Q x Q blocks, T_K by
+    # many-right-hand-side Schur-block solves, GMRES(50) with folded applies
+    "folded_qelim_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                              sol="exp_sin", precision="qelim", form="folded",
+                                              restart=50),
     "plain_fp64_8macro_r1_p2": dict(n=2, r=1, p=2, kappa=1.0, beta=(1.0, 1.0), sol="sin_sin",
                                     precision="fp64"),
     # precision configuration: same mesh, kappa = 1e-3, FP32 factors + FP64 refinement
@@ -74,17 +83,21 @@ WORKLOADS = {
 }
 
 
-def apply_bytes(m, elem_bytes=8, levels=None, p=None) -> float:
+def apply_bytes(m, elem_bytes=8, levels=None, p=None, qelim=False) -> float:
     """Algorithmic HBM bytes of one apply's per-macro solves: every stored LU
     entry once (b N_K^2, b = 8 for FP64 factors, 4 for FP32), the pivot vector
     (4 N_K), the gathered trace and the written contribution slots (about
-    2 x 8 x 2 n_trace)."""
+    2 x 8 x 2 n_trace).  With the flux eliminated the stored factor is the
+    Q x Q Schur block (Q = N_K / 3); the per-level templates are shared by all
+    macros and read from cache, not counted."""
     s = m.sizes
     if levels is None:
         n_e = np.full(s.n_macro, float(s.max_local))
     else:
         P = (2 ** np.asarray(levels, dtype=np.int64)) * p
         n_e = 3.0 * (P + 1) * (P + 2) / 2
+    if qelim:
+        n_e = n_e / 3.0
     return float(np.sum(elem_bytes * n_e * n_e + 4.0 * n_e)) + 32.0 * s.n_trace
 
 
@@ -101,12 +114,14 @@ def fold_bytes(tri, r, p, n_trace):
     return 8.0 * float(np.sum(L.astype(np.float64) ** 2)) + 32.0 * n_trace
 
 
-def lu_flops(w, s):
-    """(2/3) N_K^3 summed over macros (and coefficient instances)."""
+def lu_flops(w, s, qelim=False):
+    """(2/3) N_K^3 summed over macros (and coefficient instances); (2/3) Q^3
+    for the Schur blocks of the flux-eliminated form (Q = N_K / 3)."""
+    f = 1.0 / 27.0 if qelim else 1.0
     if np.ndim(w["r"]) == 0:
-        return s.n_macro * (2.0 / 3.0) * float(s.max_local) ** 3
+        return f * s.n_macro * (2.0 / 3.0) * float(s.max_local) ** 3
     P = (2 ** np.asarray(w["r"], dtype=np.int64)) * w["p"]
-    return s.n_instances * float(np.sum((2.0 / 3.0) * (3.0 * (P + 1) * (P + 2) / 2) ** 3))
+    return f * s.n_instances * float(np.sum((2.0 / 3.0) * (3.0 * (P + 1) * (P + 2) / 2) ** 3))
 
 
 def measured_traffic(workload):
@@ -268,7 +283,9 @@ def main():
     infos = []
     Q = s.n_nodes // s.n_macro
 
-    prec = {"fp32": mhdg.MHDG_FP32, "bf16": mhdg.MHDG_BF16}.get(w["precision"], mhdg.MHDG_FP64)
+    prec = {"fp32": mhdg.MHDG_FP32, "bf16": mhdg.MHDG_BF16,
+            "qelim": mhdg.MHDG_QELIM}.get(w["precision"], mhdg.MHDG_FP64)
+    reduced = prec in (mhdg.MHDG_FP32, mhdg.MHDG_BF16)
 
     inst_infos = []
 
@@ -284,7 +301,7 @@ def main():
         inst_infos.append(m.last_solve_infos)
 
     tune = None
-    if not args.no_autotune:
+    if not args.no_autotune and prec != mhdg.MHDG_QELIM:
         m.factor_local(kappa, beta_arg, 1.0, precision=prec)
         tune = m.autotune()
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
@@ -381,6 +398,39 @@ def main():
                     "stored factors), GMRES applies read 8 L_K^2 bytes per macro"}}
         print(f"[bench] folded: {tuned}", file=sys.stderr, flush=True)
 
+        # the same folded form with the flux eliminated: LU of the Q x Q Schur blocks
+        # (Q = N_K / 3), T_K built from them
+        print("[bench] folded form from the Schur-block factors", file=sys.stderr, flush=True)
+        q_infos = []
+
+        def qstep():
+            m.factor_local(kappa, beta_arg, 1.0, precision=mhdg.MHDG_QELIM)
+            m.fold_operator()
+            inf = m.solve(f, g, lam, rtol=args.rtol, restart=args.folded_restart,
+                          max_iter=args.max_iter, folded=True)
+            m.recover_local(lam, qu)
+            q_infos.append(inf.as_dict())
+        qstep()
+        q_infos.clear()
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        for _ in range(args.steps):
+            qstep()
+        torch.cuda.synchronize()
+        tq = (time.perf_counter() - tq0) / args.steps
+        tuned["folded_flux_eliminated_fp64"] = {
+            "time_to_solve_s": tq,
+            "applies_per_s": sum(x["n_applies"] for x in q_infos) / (tq * args.steps),
+            "iterations": [x["iterations"] for x in q_infos],
+            "gmres_restart": args.folded_restart,
+            "speedup_vs_plain": (ms_per_step / 1e3) / tq,
+            "max_rel_diff_lambda_vs_plain":
+                float(torch.linalg.norm(lam - lam_plain) / torch.linalg.norm(lam_plain)),
+            "what": "q eliminated exactly through the reference mass; LU of the Q x Q Schur "
+                    "block on u only; T_K = C_K A_K^-1 B_K from it; folded GMRES applies"}
+        print(f"[bench] folded from Schur factors: {tuned['folded_flux_eliminated_fp64']}",
+              file=sys.stderr, flush=True)
+
     seq = None
     if args.compare_sequential and n_inst > 1:
         kk = min(args.compare_sequential, n_inst)
@@ -438,7 +488,8 @@ def main():
     ams = kt["folded_apply" if folded else "apply_macro_solve"]
     avg_ms = ams["ms"] / max(ams["count"], 1)
     nbytes = apply_bytes(m, {mhdg.MHDG_FP32: 4, mhdg.MHDG_BF16: 2}.get(prec, 8),
-                         None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"])
+                         None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"],
+                         qelim=prec == mhdg.MHDG_QELIM)
     if folded:
         # folded apply: T_K read once (8 L_K^2), the gathered trace and the slots
         nbytes = fold_bytes(tri, w["r"], w["p"], s.n_trace)
@@ -462,7 +513,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {mhdg.MHDG_FP64: "f64", mhdg.MHDG_FP32: "f32 factors, f64 refinement",
+        "dtype": {mhdg.MHDG_FP64: "f64", mhdg.MHDG_QELIM: "f64",
+                  mhdg.MHDG_FP32: "f32 factors, f64 refinement",
                   mhdg.MHDG_BF16: "bf16 factors (f32 LU), f64 refinement"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "n_macro": s.n_macro, "n_instances": n_inst,
@@ -475,8 +527,10 @@ def main():
                    "form": ("folded_fp64" if folded else
                             "batched_fp64" if n_inst > 1 else "plain_fp64")
                    if prec == mhdg.MHDG_FP64 else
+                   ("folded_flux_eliminated_fp64" if folded else "flux_eliminated_fp64")
+                   if prec == mhdg.MHDG_QELIM else
                    ("fp32_factors_fp64_ir" if prec == mhdg.MHDG_FP32 else "bf16_factors_fp64_ir"),
-                   "inner_rtol": args.inner_rtol if prec != mhdg.MHDG_FP64 else None},
+                   "inner_rtol": args.inner_rtol if reduced else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["traffic_bytes_per_launch"] / 1e9 if traffic else None,
@@ -485,6 +539,8 @@ def main():
                      "traffic_vs_algorithmic": traffic["traffic_bytes_per_launch"] / nbytes
                      if traffic else None,
                      "kernel": ("fold_apply_kernel (folded steps 1-3)" if folded else
+                                "qelim_solve_kernel (apply steps 1-3, flux eliminated)"
+                                if prec == mhdg.MHDG_QELIM else
                                 "macro_solve_kernel<%s> (apply steps 1-3)"
                                 % {mhdg.MHDG_FP64: "double", mhdg.MHDG_FP32: "float",
                                    mhdg.MHDG_BF16: "bf16_t"}[prec]),
@@ -503,7 +559,8 @@ def main():
         "apply_only_per_s": apply_only,
         "stream_read_gbs": stream_gbs,
         "kernel_ms": {k: v["ms"] / max(args.steps, 1) for k, v in kt.items()},
-        "lu_tflops": lu_flops(w, s) / (lu["ms"] / max(lu["count"], 1) * 1e-3) / 1e12
+        "lu_tflops": lu_flops(w, s, prec == mhdg.MHDG_QELIM) / (lu["ms"] / max(lu["count"], 1) * 1e-3)
+        / 1e12
         if lu["count"] else None,
         "u_max_err_vs_exact": u_err,
         "autotune": tune,

@@ -81,9 +81,22 @@ typedef enum {
 typedef enum {
   MHDG_FP64 = 0,              /* FP64 factors (the plain form)                 */
   MHDG_FP32 = 1,              /* FP32 factors on MFMA, FP64 refinement         */
-  MHDG_BF16 = 2               /* FP32 LU on MFMA rounded to BF16 for storage
+  MHDG_BF16 = 2,              /* FP32 LU on MFMA rounded to BF16 for storage
                                  (a quarter of the FP64 bytes per apply; N_K
                                  <= 1024), FP64 refinement                    */
+  MHDG_QELIM = 3              /* FP64 with the flux eliminated exactly: the
+                                 macro mass matrix is |det J| times the
+                                 reference one (section 3.2 spaces on an
+                                 affine macro), so the first two block rows of
+                                 A_K (section 3.3.1) give q = M^-1 (x_q + E u)
+                                 and u solves the Q x Q Schur block
+                                 S_u = K + kappa sum_d (E^d)^T M^-1 E^d, which
+                                 is the only per-macro factor (LU with partial
+                                 pivoting, Q = N_K / 3).  Same discrete
+                                 operator as MHDG_FP64 up to rounding; apply,
+                                 rhs, recover, local solve, solve and
+                                 mhdg_fold_operator supported; no transposed
+                                 solves, adjoint or autotuning; Q <= 1237     */
 } mhdg_precision;
 
 /* flags for apply_trace_operator / local_solve */

@@ -6,13 +6,16 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace mhdg;
@@ -46,6 +49,8 @@ struct mhdg_mesh {
   // templates
   Templates T{};
   std::vector<double> tmpl;       // blob (int tables stored bit-wise in doubles' space)
+  QTemplates QT{};                // flux-eliminated form: offsets into qtmpl
+  std::vector<double> qtmpl;      // built on first use of MHDG_QELIM
   // factor state
   bool factored = false, have_rhs = false;
   // folded operators T_K (mhdg_fold_operator): valid until the next factor_local
@@ -408,6 +413,141 @@ static void build_templates(mhdg_mesh* M) {
 // ---------------------------------------------------------------- layout
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------- flux elimination
+// Offsets of the per-level templates of the flux-eliminated form (8 Q x Q
+// arrays per level present); returns the blob size in doubles.
+static size_t qelim_plan(const mhdg_mesh* M, QTemplates* QT) {
+  size_t o = 0;
+  for (int r = 0; r <= kMaxLevel; ++r) {
+    QLevel& q = QT->lev[r];
+    q = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    if (!M->T.lev[r].present) continue;
+    const size_t QQ = size_t(M->T.lev[r].Q) * M->T.lev[r].Q;
+    const size_t step = (QQ + 31) / 32 * 32;
+    int64_t* f[8] = {&q.Minv, &q.P0, &q.P1, &q.PT0, &q.PT1, &q.L00, &q.L01, &q.L11};
+    for (auto* x : f) { *x = int64_t(o); o += step; }
+    const size_t nb = 3 * size_t(M->T.lev[r].P);
+    q.Mbb = int64_t(o);
+    o += (nb * nb + 31) / 32 * 32;
+  }
+  return o;
+}
+
+// Element offsets of the Schur blocks (Q x sld each, 64-element aligned) and
+// of their pivot vectors; returns the element count of the factor region.
+static int64_t qelim_factor_elems(const std::vector<MacroInfo>& macros) {
+  int64_t fo = 0;
+  for (auto& mi : macros) {
+    fo += int64_t(mi.Q) * ((mi.Q + 15) & ~15);
+    fo = (fo + 63) & ~int64_t(63);
+  }
+  return fo;
+}
+static void qelim_offsets(std::vector<MacroInfo>& macros) {
+  int64_t fo = 0, po = 0;
+  for (auto& mi : macros) {
+    mi.sld = (mi.Q + 15) & ~15;
+    mi.sfac_off = fo;
+    mi.sperm_off = po;
+    fo += int64_t(mi.Q) * mi.sld;
+    fo = (fo + 63) & ~int64_t(63);
+    po += mi.Q;
+  }
+}
+
+// Host build of the templates: Minv = Mhat^-1 (Cholesky; Mhat is the SPD
+// reference macro mass), P_a = (Ehat^a)^T Minv, PT_a = P_a^T, L_ab = P_a Ehat^b.
+// The row loops are split over host threads.
+static void build_qelim_templates(mhdg_mesh* M) {
+  if (!M->qtmpl.empty()) return;
+  const size_t total = qelim_plan(M, &M->QT);
+  std::vector<double>& B = M->qtmpl;
+  B.assign(total, 0.0);
+  const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto par_rows = [&](int n, const std::function<void(int)>& f) {
+    std::vector<std::thread> th;
+    std::atomic<int> next(0);
+    for (unsigned t = 0; t < nth; ++t)
+      th.emplace_back([&] { for (int i = next++; i < n; i = next++) f(i); });
+    for (auto& x : th) x.join();
+  };
+  for (int r = 0; r <= kMaxLevel; ++r) {
+    const LevelTemplates& LT = M->T.lev[r];
+    if (!LT.present) continue;
+    const QLevel& q = M->QT.lev[r];
+    const int Q = LT.Q;
+    const double* Mh = &M->tmpl[LT.Mhat];
+    const double* E[2] = {&M->tmpl[LT.E0], &M->tmpl[LT.E1]};
+    // Cholesky Mhat = C C^T (lower C), then Minv column by column
+    std::vector<double> C(Mh, Mh + size_t(Q) * Q);
+    for (int j = 0; j < Q; ++j) {
+      double d = C[size_t(j) * Q + j];
+      for (int k = 0; k < j; ++k) d -= C[size_t(j) * Q + k] * C[size_t(j) * Q + k];
+      d = std::sqrt(d);
+      C[size_t(j) * Q + j] = d;
+      for (int i = j + 1; i < Q; ++i) {
+        double v = C[size_t(i) * Q + j];
+        for (int k = 0; k < j; ++k) v -= C[size_t(i) * Q + k] * C[size_t(j) * Q + k];
+        C[size_t(i) * Q + j] = v / d;
+      }
+    }
+    double* Minv = &B[q.Minv];
+    par_rows(Q, [&](int c) {   // column c of Minv (= row c: symmetric)
+      std::vector<double> y(Q, 0.0);
+      for (int i = 0; i < Q; ++i) {   // C y = e_c
+        double v = i == c ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) v -= C[size_t(i) * Q + k] * y[k];
+        y[i] = v / C[size_t(i) * Q + i];
+      }
+      for (int i = Q - 1; i >= 0; --i) {   // C^T x = y
+        double v = y[i];
+        for (int k = i + 1; k < Q; ++k) v -= C[size_t(k) * Q + i] * y[k];
+        y[i] = v / C[size_t(i) * Q + i];
+      }
+      for (int i = 0; i < Q; ++i) Minv[size_t(c) * Q + i] = y[i];
+    });
+    {   // boundary block of Minv, boundary order b = kP + s
+      const int P = LT.P;
+      const int32_t* en = reinterpret_cast<const int32_t*>(&M->tmpl[LT.edge_node]);
+      double* Mbb = &B[q.Mbb];
+      for (int b = 0; b < 3 * P; ++b)
+        for (int b2 = 0; b2 < 3 * P; ++b2) {
+          const int n1 = en[(b / P) * (P + 1) + b % P], n2 = en[(b2 / P) * (P + 1) + b2 % P];
+          Mbb[size_t(b) * 3 * P + b2] = Minv[size_t(n1) * Q + n2];
+        }
+    }
+    double* Pa[2] = {&B[q.P0], &B[q.P1]};
+    double* PTa[2] = {&B[q.PT0], &B[q.PT1]};
+    for (int a = 0; a < 2; ++a) {
+      par_rows(Q, [&](int i) {   // P_a[i][j] = sum_k Ehat^a[k][i] Minv[k][j]
+        double* row = Pa[a] + size_t(i) * Q;
+        for (int k = 0; k < Q; ++k) {
+          const double e = E[a][size_t(k) * Q + i];
+          if (e == 0.0) continue;
+          const double* mk = Minv + size_t(k) * Q;
+          for (int j = 0; j < Q; ++j) row[j] += e * mk[j];
+        }
+      });
+      for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) PTa[a][size_t(j) * Q + i] = Pa[a][size_t(i) * Q + j];
+    }
+    const int ab[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+    double* Lab[3] = {&B[q.L00], &B[q.L01], &B[q.L11]};
+    for (int t = 0; t < 3; ++t) {
+      const double* Pl = Pa[ab[t][0]];
+      const double* Er = E[ab[t][1]];
+      par_rows(Q, [&](int i) {   // L[i][j] = sum_k P_a[i][k] Ehat^b[k][j]
+        double* row = Lab[t] + size_t(i) * Q;
+        for (int k = 0; k < Q; ++k) {
+          const double pv = Pl[size_t(i) * Q + k];
+          const double* ek = Er + size_t(k) * Q;
+          for (int j = 0; j < Q; ++j) row[j] += pv * ek[j];
+        }
+      });
+    }
+  }
+}
+
 static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   FactorLayout L{};
   size_t o = 0;
@@ -428,6 +568,16 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   // macro, and the column-streaming solves may read up to 64 x 64 elements
   // past a block's end (guard tail)
   const MacroInfo& last = M->macros.back();
+  if (precision == MHDG_QELIM) {
+    const size_t nf = size_t(qelim_factor_elems(M->macros)) + kFactorGuard;
+    o = align_up(o + nf * 8);
+    L.factors16 = o;
+    QTemplates qt;
+    L.qtmpl = o;   o = align_up(o + qelim_plan(M, &qt) * sizeof(double));
+    L.info_lu = o; o = align_up(o + M->macros.size() * sizeof(MacroInfo));
+    L.total = o;
+    return L;
+  }
   const size_t nf = size_t(last.fac_off) + size_t(last.N) * last.ld + kFactorGuard;
   const size_t es = precision == MHDG_FP64 ? 8 : 4;   // BF16 factors are factored in FP32
   o = align_up(o + nf * es);
@@ -1305,7 +1455,8 @@ mhdg_status mhdg_profile(mhdg_mesh* M, int32_t enable, mhdg_kernel_times* out) {
 
 mhdg_status mhdg_query(const mhdg_mesh* M, int32_t precision, int32_t restart, mhdg_sizes* out) {
   if (!M || !out || restart < 1 ||
-      (precision != MHDG_FP64 && precision != MHDG_FP32 && precision != MHDG_BF16))
+      (precision != MHDG_FP64 && precision != MHDG_FP32 && precision != MHDG_BF16 &&
+       precision != MHDG_QELIM))
     return MHDG_ERR_INVALID_ARG;
   out->n_macro = M->n_macro;
   out->n_faces = M->n_faces;
@@ -1402,10 +1553,15 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
     return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: null pointer or tau <= 0");
   for (int64_t i = 0; i < 2 * int64_t(M->n_inst); ++i)
     if (!std::isfinite(beta[i])) return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: non-finite a");
-  if (precision != MHDG_FP64 && precision != MHDG_FP32 && precision != MHDG_BF16)
+  if (precision != MHDG_FP64 && precision != MHDG_FP32 && precision != MHDG_BF16 &&
+      precision != MHDG_QELIM)
     return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: unknown precision");
   if (precision == MHDG_BF16 && M->max_N > 1024)
     return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: BF16 factors support N_K <= 1024");
+  if (precision == MHDG_QELIM)
+    for (auto& c : M->classes)
+      if (c.N / 3 > 1237 || qelim_lds_bytes(c.N / 3, c.P) > 65536)
+        return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: flux elimination supports Q <= 1237");
   mhdg_sizes sz;
   mhdg_query(M, precision, 1, &sz);
   if (ws_bytes < sz.factor_ws_bytes)
@@ -1420,6 +1576,10 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   M->ws = (char*)ws;
   M->ws_bytes = ws_bytes;
   for (auto& mi : M->macros) { mi.bx = beta[2 * mi.inst]; mi.by = beta[2 * mi.inst + 1]; }
+  if (precision == MHDG_QELIM) {
+    qelim_offsets(M->macros);
+    build_qelim_templates(M);
+  }
   M->L = factor_layout(M, precision);
   for (auto& c : M->classes)
     if (!c.lu_var && !c.solve_var) {
@@ -1443,16 +1603,51 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   // the macro order lives after the permutation vector region: reuse status region size n_macro
   MacroInfo* info = (MacroInfo*)(w + L.meta);
   HIP_TRY(M, launch_set_kappa(info, kappa, M->n_macro, s));
-  {
-    ProfScope ps(M, 0, s);
-    HIP_TRY(M, launch_assemble(w + L.factors, lu_precision(precision), info, nullptr, M->n_macro,
-                               (const double*)(w + L.tmpl), M->T, tau, s));
-  }
-  {
-    ProfScope ps(M, 1, s);
-    HIP_TRY(M, launch_lu(w + L.factors, lu_precision(precision), info, (const int32_t*)(w + L.order),
-                         M->classes.data(), (int)M->classes.size(), (int32_t*)(w + L.perm),
-                         (int32_t*)(w + L.status), s));
+  if (precision == MHDG_QELIM) {
+    // the Schur block on u per macro, factored by the same LU kernels through a
+    // table whose N / ld / offsets describe the Q x Q blocks
+    HIP_TRY(M, hipMemcpyAsync(w + L.qtmpl, M->qtmpl.data(), M->qtmpl.size() * sizeof(double),
+                              hipMemcpyHostToDevice, s));
+    std::vector<MacroInfo> lu_info(M->macros);
+    int maxQ = 0;
+    for (auto& mi : lu_info) {
+      maxQ = std::max(maxQ, mi.Q);
+      mi.N = mi.Q;
+      mi.ld = mi.sld;
+      mi.fac_off = mi.sfac_off;
+      mi.loc_off = mi.sperm_off;
+    }
+    std::vector<SizeClass> lu_classes(M->classes);
+    for (auto& c : lu_classes) { c.N /= 3; c.lu_var = 0; c.solve_var = 0; }
+    HIP_TRY(M, hipMemcpyAsync(w + L.info_lu, lu_info.data(), lu_info.size() * sizeof(MacroInfo),
+                              hipMemcpyHostToDevice, s));
+    {
+      ProfScope ps(M, 0, s);
+      HIP_TRY(M, launch_qelim_assemble((double*)(w + L.factors), info, M->n_macro, maxQ,
+                                       (const double*)(w + L.tmpl), M->T,
+                                       (const double*)(w + L.qtmpl), M->QT, tau, s));
+    }
+    {
+      ProfScope ps(M, 1, s);
+      HIP_TRY(M, launch_lu(w + L.factors, MHDG_FP64, (const MacroInfo*)(w + L.info_lu),
+                           (const int32_t*)(w + L.order), lu_classes.data(),
+                           (int)lu_classes.size(), (int32_t*)(w + L.perm),
+                           (int32_t*)(w + L.status), s));
+    }
+    // the host vectors above must outlive the copies
+    HIP_TRY(M, hipStreamSynchronize(s));
+  } else {
+    {
+      ProfScope ps(M, 0, s);
+      HIP_TRY(M, launch_assemble(w + L.factors, lu_precision(precision), info, nullptr, M->n_macro,
+                                 (const double*)(w + L.tmpl), M->T, tau, s));
+    }
+    {
+      ProfScope ps(M, 1, s);
+      HIP_TRY(M, launch_lu(w + L.factors, lu_precision(precision), info, (const int32_t*)(w + L.order),
+                           M->classes.data(), (int)M->classes.size(), (int32_t*)(w + L.perm),
+                           (int32_t*)(w + L.status), s));
+    }
   }
   if (precision == MHDG_BF16) {
     const MacroInfo& last = M->macros.back();
@@ -1476,7 +1671,7 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
 
 mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;
-  if (!M->factored || M->precision != MHDG_FP64)
+  if (!M->factored || (M->precision != MHDG_FP64 && M->precision != MHDG_QELIM))
     return fail(M, MHDG_ERR_STATE, "fold_operator: needs FP64 factors (call factor_local first)");
   const FoldLayout F = fold_layout(M);
   if (!ws || ws_bytes < F.total)
@@ -1498,7 +1693,14 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* st
   FactorLayout& L = M->L;
   char* w = M->ws;
   double* T = (double*)(fw + F.T);
-  if (maxL > 0)
+  if (maxL > 0 && M->precision == MHDG_QELIM)
+    HIP_TRY(M, launch_qelim_fold_build((const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
+                                       (const int32_t*)(w + L.order), M->classes.data(),
+                                       (int)M->classes.size(), (const int32_t*)(w + L.perm),
+                                       (const double*)(w + L.tmpl), M->T,
+                                       (const double*)(w + L.qtmpl), M->QT, M->tau, maxL,
+                                       (const int64_t*)(fw + F.toff), T, s));
+  else if (maxL > 0)
     HIP_TRY(M, launch_fold_build((const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
                                  (const int32_t*)(w + L.order), M->classes.data(),
                                  (int)M->classes.size(), (const int32_t*)(w + L.perm),
@@ -1531,6 +1733,8 @@ mhdg_status mhdg_set_kernel_variant(mhdg_mesh* M, int32_t N, int32_t lu_variant,
 mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;
   if (!M->factored) return fail(M, MHDG_ERR_STATE, "autotune: call factor_local first");
+  if (M->precision == MHDG_QELIM)
+    return fail(M, MHDG_ERR_STATE, "autotune: not available for the flux-eliminated form");
   if (M->classes.size() > MHDG_MAX_CLASSES)
     return fail(M, MHDG_ERR_INVALID_ARG, "autotune: too many size classes");
   hipStream_t s = (hipStream_t)stream;
@@ -1660,6 +1864,16 @@ static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const 
   FactorLayout& L = M->L;
   char* w = M->ws;
   ProfScope ps(M, mode == MODE_APPLY ? 2 : 4, s);
+  if (M->precision == MHDG_QELIM) {
+    if (transpose)
+      return fail(M, MHDG_ERR_STATE, "transposed solves need MHDG_FP64 factors");
+    HIP_TRY(M, launch_qelim_solve(mode, (const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
+                                  (const int32_t*)(w + L.order), M->classes.data(),
+                                  (int)M->classes.size(), (const int32_t*)(w + L.perm),
+                                  (const double*)(w + L.tmpl), M->T, (const double*)(w + L.qtmpl),
+                                  M->QT, skip, M->tau, lam, xin, yout, (double*)(w + L.slots), s));
+    return MHDG_OK;
+  }
   HIP_TRY(M, launch_macro_solve(mode, transpose, solve_factors(M), M->precision,
                                 (const MacroInfo*)(w + L.meta), (const int32_t*)(w + L.order),
                                 M->classes.data(), (int)M->classes.size(),
@@ -1806,7 +2020,7 @@ mhdg_status mhdg_recover_local(mhdg_mesh* M, const double* lam, double* qu, doub
   FactorLayout& L = M->L;
   mhdg_status st = run_macro_solve(M, MODE_RECOVER, 0, lam, (const double*)(M->ws + L.R), qu, s);
   if (st) return st;
-  if (M->precision != MHDG_FP64) {
+  if (M->precision == MHDG_FP32 || M->precision == MHDG_BF16) {
     // local iterative refinement: r = R - A U - B lam in FP64 (matrix-free),
     // U += A~^-1 r with the low-precision factors, until r stops decreasing
     char* fw = M->ws;
@@ -1871,7 +2085,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   if (!M->factored) return fail(M, MHDG_ERR_STATE, "solve: call factor_local first");
   if (ws_bytes < solve_bytes_impl(M, o->restart))
     return fail(M, MHDG_ERR_WORKSPACE, "solve: workspace smaller than mhdg_query reports");
-  if (M->precision != MHDG_FP64 && M->n_inst > 1)
+  if ((M->precision == MHDG_FP32 || M->precision == MHDG_BF16) && M->n_inst > 1)
     return fail(M, MHDG_ERR_STATE, "solve: reduced-precision factors need a single instance");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = M->n_trace;
@@ -1883,7 +2097,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   if (o->graph) G.op_flags |= MHDG_GRAPH;
   G.classic = o->classic_gs != 0;
   if (o->folded) {
-    if (!M->folded || M->precision != MHDG_FP64)
+    if (!M->folded || (M->precision != MHDG_FP64 && M->precision != MHDG_QELIM))
       return fail(M, MHDG_ERR_STATE, "solve: folded applies need mhdg_fold_operator");
     G.op_flags |= MHDG_FOLDED;
   }
@@ -1909,7 +2123,7 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   bool converged = false;
   double rel = 0.0;
   std::vector<mhdg_solve_info> per(ns);
-  if (M->precision == MHDG_FP64) {
+  if (M->precision == MHDG_FP64 || M->precision == MHDG_QELIM) {
     // ---- plain form: GMRES on D^-1 S lam = D^-1 f^, one Krylov space per instance
     std::vector<double> bnorm(ns), tr2(ns), f2(ns), rels;
     std::vector<int> its;

@@ -34,6 +34,10 @@ struct MacroInfo {
   int32_t P;          // 2^r p
   int32_t inst;       // coefficient instance this macro belongs to
   int32_t ld;         // leading dimension of the stored block: N rounded up to 16
+  // flux-eliminated form: the Q x Q Schur block on u
+  int32_t sld;        // its leading dimension (Q rounded up to 16)
+  int64_t sfac_off;   // element offset of its factor block
+  int64_t sperm_off;  // offset of its pivot vector (Q entries)
 };
 
 struct FaceInfo {     // interior faces
@@ -66,6 +70,13 @@ struct LevelTemplates {
   int32_t present, Q, P, N;
 };
 
+// Per-level templates of the flux-eliminated form (row-major Q x Q, offsets
+// into their own device blob): Minv = Mhat^-1, P_a = (Ehat^a)^T Minv and its
+// transpose PT_a, L_ab = P_a Ehat^b (a, b = 0, 1; L_10 = L_01^T), and Mbb, the
+// 3P x 3P block of Minv on the boundary nodes in boundary order (b = kP + s).
+struct QLevel { int64_t Minv, P0, P1, PT0, PT1, L00, L01, L11, Mbb; };
+struct QTemplates { QLevel lev[kMaxLevel + 1]; };
+
 struct Templates {
   LevelTemplates lev[kMaxLevel + 1];
   int64_t dir_basis;        // (p+1) x kb: trace basis at the Dirichlet points of a segment
@@ -77,6 +88,7 @@ struct Templates {
 struct FactorLayout {
   size_t meta, faces, bfaces, tmpl, order, perm, status, R, slots, lamD, work1, work2, factors,
       factors16, total;   // factors16: BF16 copy of the FP32 factors (BF16 precision only)
+  size_t qtmpl = 0, info_lu = 0;   // flux-eliminated form: templates, Schur-block LU table
 };
 
 // Macros of one local size, contiguous in the processing order (largest first):
@@ -151,6 +163,25 @@ enum FaceMode { FACE_S = 0, FACE_PREC_S = 1, FACE_RHS = 2, FACE_PREC_RHS = 3, FA
 
 // folded macro operators T_K = C_K A_K^-1 B_K (fold.hip)
 constexpr int kFoldMaxL = 192;
+// flux-eliminated form (qelim.hip, kernels.hip): Schur block assembly (row-major
+// into the factor blocks at sfac_off) and the per-macro solves in every mode
+hipError_t launch_qelim_assemble(double* fac, const MacroInfo* info, int64_t n, int maxQ,
+                                 const double* tmpl, const Templates& T, const double* qtm,
+                                 const QTemplates& QT, double tau, hipStream_t s);
+hipError_t launch_qelim_solve(int mode, const double* fac, const MacroInfo* info,
+                              const int32_t* order, const SizeClass* classes, int n_classes,
+                              const int32_t* perm, const double* tmpl, const Templates& T,
+                              const double* qtm, const QTemplates& QT, const int32_t* skip,
+                              double tau, const double* lam, const double* xin, double* yout,
+                              double* slots, hipStream_t s);
+size_t qelim_lds_bytes(int Q, int P);
+// T_K for every macro from the Schur-block factors (max_L: the largest L_K)
+hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, const int32_t* order,
+                                   const SizeClass* classes, int n_classes, const int32_t* perm,
+                                   const double* tmpl, const Templates& T, const double* qtm,
+                                   const QTemplates& QT, double tau, int max_L,
+                                   const int64_t* toff, double* out, hipStream_t s);
+
 // T_K for every macro, from the FP64 factors (max_L: the largest L_K)
 hipError_t launch_fold_build(const double* fac, const MacroInfo* info, const int32_t* order,
                              const SizeClass* classes, int n_classes, const int32_t* perm,

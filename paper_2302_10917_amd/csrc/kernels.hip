@@ -118,6 +118,49 @@ __global__ __launch_bounds__(256) void assemble_kernel(T* fac, const MacroInfo* 
       A[size_t(r) * ld + col] = (T)a_entry(c, r, col);
 }
 
+// Schur block of the flux-eliminated form, row-major into the block at sfac_off:
+// S_u = K + kappa |det J| (c_00 L_00 + c_01 (L_01 + L_01^T) + c_11 L_11) with
+// c_ab = sum_d g_ad g_bd, g_0d = G[d], g_1d = G[2 + d] (E^d = |det J| sum_a
+// g_ad Ehat^a) and K the u-u block of A_K.
+__global__ __launch_bounds__(256) void qelim_assemble_kernel(double* fac,
+                                                             const MacroInfo* __restrict__ info,
+                                                             const double* __restrict__ tm,
+                                                             Templates Tp,
+                                                             const double* __restrict__ qt,
+                                                             QTemplates QT, double tau) {
+  const MacroInfo& mi = info[blockIdx.x];
+  const int Q = mi.Q, ld = mi.sld;
+  const int rows_per = 8;
+  const int r0 = blockIdx.y * rows_per;
+  if (r0 >= Q) return;
+  EntryCtx c = make_ctx(mi, tm, Tp, tau);
+  const QLevel& QL = QT.lev[mi.level];
+  const double* L00 = qt + QL.L00;
+  const double* L01 = qt + QL.L01;
+  const double* L11 = qt + QL.L11;
+  const double G0 = mi.G[0], G1 = mi.G[1], G2 = mi.G[2], G3 = mi.G[3];
+  const double c00 = G0 * G0 + G1 * G1, c01 = G0 * G2 + G1 * G3, c11 = G2 * G2 + G3 * G3;
+  const double sc = mi.kappa * mi.dJ;
+  double* A = fac + mi.sfac_off;
+  const int r1 = min(Q, r0 + rows_per);
+  for (int r = r0; r < r1; ++r)
+    for (int col = threadIdx.x; col < Q; col += blockDim.x) {
+      const size_t o = size_t(r) * Q + col;
+      const double lap = c00 * L00[o] + c01 * (L01[o] + L01[size_t(col) * Q + r]) + c11 * L11[o];
+      A[size_t(r) * ld + col] = a_entry(c, 2 * Q + r, 2 * Q + col) + sc * lap;
+    }
+}
+
+hipError_t launch_qelim_assemble(double* fac, const MacroInfo* info, int64_t n, int maxQ,
+                                 const double* tmpl, const Templates& T, const double* qtm,
+                                 const QTemplates& QT, double tau, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)n, (unsigned)((maxQ + 7) / 8));
+  hipLaunchKernelGGL(qelim_assemble_kernel, grid, dim3(256), 0, s, fac, info, tmpl, T, qtm, QT,
+                     tau);
+  return hipGetLastError();
+}
+
 __global__ void extract_kernel(const MacroInfo* info, int64_t e, const double* tm, Templates Tp,
                                double tau, double* dst) {
   const MacroInfo& mi = info[e];

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmhdg.so")
 
-MHDG_FP64, MHDG_FP32, MHDG_BF16 = 0, 1, 2
+MHDG_FP64, MHDG_FP32, MHDG_BF16, MHDG_QELIM = 0, 1, 2, 3
 MHDG_PRECONDITION, MHDG_TRANSPOSE, MHDG_GRAPH, MHDG_FOLDED = 1, 2, 4, 8
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "MESH", 3: "SINGULAR", 4: "NOT_CONVERGED",

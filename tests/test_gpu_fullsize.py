@@ -371,3 +371,38 @@ def test_c2_solve_sampled(c2, folded):
     quh = host(qu)
     for K in macros:
         assert rel(quh[topo.local_off[K]:topo.local_off[K + 1]], U[K]) <= TOL, K
+
+
+def test_c2_flux_eliminated_apply_and_solve_sampled(c2):
+    """The flux-eliminated form on the same mesh and data: applies on the
+    sampled faces to the FP64 bar, and its solve to 1e-10 within the same
+    global residual bound; recovery on the sampled macros to 1e-10."""
+    orc, faces, macros = c2["orc"], c2["faces"], c2["macros"]
+    topo = orc.topo
+    xy, tri = inputs.structured_mesh(C2["n"])
+    kap = np.full(len(tri), C2["kappa"])
+    m = mhdg.MacroMesh(xy, tri, C2["r"], C2["p"])
+    try:
+        m.factor_local(gpu(kap), C2["beta"], 1.0, precision=mhdg.MHDG_QELIM)
+        lam_r = inputs.random_vector(topo.n_trace, seed=1)
+        out = torch.empty(topo.n_trace, dtype=torch.float64, device=DEV)
+        ref = gather(orc.apply(lam_r, precondition=True, faces=faces), topo, faces)
+        for flags in (mhdg.MHDG_PRECONDITION, mhdg.MHDG_PRECONDITION | mhdg.MHDG_GRAPH):
+            m.apply_trace_operator(gpu(lam_r), out, flags)
+            err = rel(gather(host(out), topo, faces), ref)
+            print(f"  flux-eliminated apply flags={flags}: {err:.2e}", flush=True)
+            assert err <= TOL
+        lam = torch.zeros(topo.n_trace, dtype=torch.float64, device=DEV)
+        info = m.solve(c2["f"], c2["g"], lam, rtol=1e-10, restart=2000, max_iter=20000)
+        assert info.status == 0
+        qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+        m.recover_local(lam, qu)
+        lam_h, quh = host(lam), host(qu)
+    finally:
+        release(m)
+    Y, U = sampled_local(orc, macros, lam_h, c2["fo"], c2["lamD"])
+    res_o, _ = sampled_residual(orc, faces, lam_h, Y, U)
+    check_residual(res_o, c2["fhat_norm"])
+    for K in macros:
+        assert rel(quh[topo.local_off[K]:topo.local_off[K + 1]], U[K]) <= TOL, K
+

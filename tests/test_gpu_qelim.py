@@ -1,0 +1,224 @@
+"""GPU parity of the flux-eliminated form (MHDG_QELIM).
+
+Eliminating q through the macro mass matrix changes the order of the
+arithmetic, not the operator: local solves, S lambda, D^-1 S lambda, f^, the
+solve and the recovery must match the FP64 oracle to the FP64 bar (relative
+1e-10) and the full-block FP64 path to 1e-11, on uniform, mixed-level and
+jittered meshes and with several coefficient instances.  The folded operators
+built from the Schur-block factors must match the oracle like the ones built
+from the full-block factors.  Transposed solves, the adjoint and autotuning
+are not offered for this form and must be refused with MHDG_ERR_STATE.
+"""
+import numpy as np
+import pytest
+
+from oracle import hdg
+from paper_2302_10917_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_10917_amd import mhdg  # noqa: E402
+
+DEV = "cuda"
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# name: (n squares, jitter, levels, p)
+CASES = {"uniform_r2_p3": (3, 0.0, 2, 3), "mixed_p2_jitter": (3, 0.1, "mixed", 2),
+         "r3_p3": (2, 0.0, 3, 3), "mixed_r1to4_p3": (2, 0.05, "mixed4", 3),
+         "single_r1_p1": (1, 0.0, 1, 1)}
+
+
+def _case(name):
+    n, jit, lev, p = CASES[name]
+    xy, tri = inputs.structured_mesh(n, jitter=jit, seed=7)
+    if lev == "mixed":
+        r = inputs.random_levels(len(tri), (0, 1, 2), seed=3)
+    elif lev == "mixed4":
+        r = inputs.random_levels(len(tri), (1, 2, 3, 4), seed=3)
+    else:
+        r = lev
+    kap = 0.2 * inputs.lognormal_kappa(len(tri), 0.3, seed=9)
+    return xy, tri, r, p, kap, (1.0, -0.4)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    print(f"\n[qelim {request.param}]", flush=True)
+    xy, tri, r, p, kap, beta = _case(request.param)
+    orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0)
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    m.factor_local(gpu(kap), beta, 1.0, precision=mhdg.MHDG_QELIM)
+    yield request.param, (xy, tri, r, p, kap, beta), orc, m
+    m.close()
+
+
+def test_local_solve_matches_oracle(case):
+    name, _, orc, m = case
+    topo = orc.topo
+    x = inputs.random_vector(int(topo.local_off[-1]), seed=11)
+    y = torch.empty(len(x), dtype=torch.float64, device=DEV)
+    m.local_solve(gpu(x), y)
+    yh = host(y)
+    for e in range(topo.n_macro):
+        lo, hi = topo.local_off[e], topo.local_off[e + 1]
+        assert rel(yh[lo:hi], orc.local_solve(e, x[lo:hi])) <= 1e-10, (name, e)
+
+
+def test_apply_matches_oracle_and_full_block_path(case):
+    name, (xy, tri, r, p, kap, beta), orc, m = case
+    n = orc.topo.n_trace
+    if n == 0:
+        return
+    lam = inputs.random_vector(n, seed=1)
+    full = mhdg.MacroMesh(xy, tri, r, p)
+    full.factor_local(gpu(kap), beta, 1.0)
+    a = torch.empty(n, dtype=torch.float64, device=DEV)
+    b = torch.empty(n, dtype=torch.float64, device=DEV)
+    for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
+        m.apply_trace_operator(gpu(lam), a, flags)
+        full.apply_trace_operator(gpu(lam), b, flags)
+        assert rel(host(a), orc.apply(lam, precondition=prec)) <= 1e-10, (name, flags)
+        assert rel(host(a), host(b)) <= 1e-11, (name, flags)
+    # graph replay equals the eager launches bit for bit
+    m.apply_trace_operator(gpu(lam), b, mhdg.MHDG_PRECONDITION | mhdg.MHDG_GRAPH)
+    for _ in range(3):
+        m.apply_trace_operator(gpu(lam), b, mhdg.MHDG_PRECONDITION | mhdg.MHDG_GRAPH)
+    assert torch.equal(a, b)
+    full.close()
+
+
+def test_solve_and_recover_match_oracle(case):
+    name, (xy, tri, r, p, kap, beta), orc, m = case
+    ex = inputs.exp_sin(0.2, beta)
+    node, bnd = m.sample_points()
+    f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+    fo, go = orc.sample(ex)
+    lam_o, U_o, _ = orc.solve(fo, go)
+    n = orc.topo.n_trace
+    if n:
+        S, fhat, _ = orc.condensed(fo, go)
+        fh = torch.empty(n, dtype=torch.float64, device=DEV)
+        m.rhs(f, g, fh, mhdg.MHDG_PRECONDITION)
+        assert rel(host(fh), orc.precondition(fhat)) <= 1e-10
+    lam = torch.zeros(max(n, 1), dtype=torch.float64, device=DEV)[:n]
+    info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=5000)
+    assert info.status == 0
+    if n:
+        assert rel(host(lam), lam_o) <= 1e-10, name
+    qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+    res = torch.empty(max(n, 1), dtype=torch.float64, device=DEV)[:n]
+    m.recover_local(lam, qu, res if n else None)
+    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10, name
+    if n:
+        assert np.linalg.norm(host(res)) <= 1e-10 * np.linalg.norm(fhat)
+
+
+def test_instances_match_oracle_per_instance():
+    xy, tri, r, p, _, _ = _case("mixed_p2_jitter")
+    kap_i, beta = inputs.coefficient_instances(3, seed=33)
+    field = inputs.lognormal_kappa(len(tri), 0.3, seed=9)
+    kappa = np.stack([k * field for k in kap_i])
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    one = m.sizes
+    m.set_instances(3)
+    m.factor_local(gpu(kappa.ravel()), beta, 1.0, precision=mhdg.MHDG_QELIM)
+    nt = one.n_trace
+    lam = inputs.random_vector(3 * nt, seed=2)
+    out = torch.empty(3 * nt, dtype=torch.float64, device=DEV)
+    m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_PRECONDITION)
+    o = host(out)
+    node, bnd = m.sample_points()
+    fh, gh = np.empty(m.sizes.n_nodes), np.empty(m.sizes.n_bnd_points)
+    orcs = []
+    for i in range(3):
+        orc = hdg.Oracle(xy, tri, r, p, kappa[i], beta[i], 1.0)
+        orcs.append(orc)
+        sl = slice(i * nt, (i + 1) * nt)
+        assert rel(o[sl], orc.apply(lam[sl], precondition=True)) <= 1e-10, i
+        ex = inputs.exp_sin(float(kap_i[i]), beta[i])
+        a, b = i * one.n_nodes, (i + 1) * one.n_nodes
+        fh[a:b] = ex.f(node[a:b, 0], node[a:b, 1])
+        a, b = i * one.n_bnd_points, (i + 1) * one.n_bnd_points
+        gh[a:b] = ex.u(bnd[a:b, 0], bnd[a:b, 1])
+    lam_g = torch.zeros(3 * nt, dtype=torch.float64, device=DEV)
+    info = m.solve(gpu(fh), gpu(gh), lam_g, rtol=1e-13, restart=300, max_iter=5000)
+    assert info.status == 0
+    lh = host(lam_g)
+    for i in range(3):
+        ex = inputs.exp_sin(float(kap_i[i]), beta[i])
+        lam_o, _, _ = orcs[i].solve(*orcs[i].sample(ex))
+        assert rel(lh[i * nt:(i + 1) * nt], lam_o) <= 1e-10, i
+    m.close()
+
+
+def test_unsupported_calls_are_refused():
+    xy, tri, r, p, kap, beta = _case("uniform_r2_p3")
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    m.factor_local(gpu(kap), beta, 1.0, precision=mhdg.MHDG_QELIM)
+    n = m.sizes.n_trace
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    y = torch.empty(n, dtype=torch.float64, device=DEV)
+    calls = [lambda: m.apply_trace_operator(x, y, mhdg.MHDG_TRANSPOSE),
+             lambda: m.local_solve(torch.zeros(m.sizes.n_local, dtype=torch.float64, device=DEV),
+                                   torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV),
+                                   mhdg.MHDG_TRANSPOSE),
+             lambda: m.autotune()]
+    for call in calls:
+        with pytest.raises(mhdg.MhdgError) as e:
+            call()
+        assert e.value.status == 7
+    # the handle still works, and a later FP64 factorisation replaces the form
+    m.apply_trace_operator(x, y, 0)
+    m.factor_local(gpu(kap), beta, 1.0)
+    m.fold_operator()
+    m.close()
+
+
+@pytest.mark.parametrize("name", ["uniform_r2_p3", "mixed_r1to4_p3", "r3_p3"])
+def test_folded_from_schur_factors_matches_oracle(name):
+    xy, tri, r, p, kap, beta = _case(name)
+    print(f"\n[qelim folded {name}]", flush=True)
+    orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0)
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    m.factor_local(gpu(kap), beta, 1.0, precision=mhdg.MHDG_QELIM)
+    m.fold_operator()
+    n = orc.topo.n_trace
+    lam = inputs.random_vector(n, seed=1)
+    a = torch.empty(n, dtype=torch.float64, device=DEV)
+    b = torch.empty(n, dtype=torch.float64, device=DEV)
+    for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
+        m.apply_trace_operator(gpu(lam), a, flags | mhdg.MHDG_FOLDED)
+        m.apply_trace_operator(gpu(lam), b, flags)
+        assert rel(host(a), orc.apply(lam, precondition=prec)) <= 1e-10, (name, flags)
+        assert rel(host(a), host(b)) <= 1e-12, (name, flags)
+    ex = inputs.exp_sin(0.2, beta)
+    node, bnd = m.sample_points()
+    f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+    lam_o, U_o, _ = orc.solve(*orc.sample(ex))
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = m.solve(f, g, x, rtol=1e-13, restart=50, max_iter=20000, folded=True)
+    assert info.status == 0
+    assert rel(host(x), lam_o) <= 1e-10
+    qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+    m.recover_local(x, qu)
+    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    m.close()
+

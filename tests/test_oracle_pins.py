@@ -237,6 +237,41 @@ def test_blocks_are_translation_invariant():
             assert np.abs(b.B[k] - blocks[0].B[k]).max() <= 1e-15 * np.abs(blocks[0].B[k]).max()
 
 
+def test_flux_elimination_reproduces_the_local_solve():
+    """The reading behind the flux-eliminated form, on the oracle's blocks of
+    A_K = [[M, 0, -E^x], [0, M, -E^y], [kappa H^x, kappa H^y, K]] (section
+    3.3.1): M is SPD and equals |det J| times one reference matrix for every
+    macro of a level (affine macros, jittered mesh), H^d = (E^d)^T, and
+    u = S_u^-1 (x_u - kappa sum_d H^d M^-1 x_d), q_d = M^-1 (x_d + E^d u) with
+    S_u = K + kappa sum_d H^d M^-1 E^d reproduce A_K^-1 x."""
+    xy, tri = inputs.structured_mesh(2, jitter=0.12, seed=3)
+    kappa = 0.37
+    o = hdg.Oracle(xy, tri, 2, 2, kappa, (0.8, -1.3), 1.0)
+    Q = int(o.topo.Q[0])
+    ref = None
+    for K in range(o.topo.n_macro):
+        A = o.blocks(K).A
+        Mq, Ex, Ey = A[:Q, :Q], -A[:Q, 2 * Q:], -A[Q:2 * Q, 2 * Q:]
+        assert np.array_equal(A[Q:2 * Q, Q:2 * Q], Mq) and not np.any(A[:Q, Q:2 * Q])
+        assert np.abs(Mq - Mq.T).max() <= 1e-14 * np.abs(Mq).max()
+        assert np.linalg.eigvalsh(Mq).min() > 0
+        X = xy[tri[K]]
+        dJ = abs(np.linalg.det(np.array([X[1] - X[0], X[2] - X[0]])))
+        if ref is None:
+            ref = Mq / dJ
+        assert np.allclose(Mq / dJ, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+        assert np.abs(A[2 * Q:, :Q] - kappa * Ex.T).max() <= 1e-12 * kappa * np.abs(Ex).max()
+        assert np.abs(A[2 * Q:, Q:2 * Q] - kappa * Ey.T).max() <= 1e-12 * kappa * np.abs(Ey).max()
+        Kuu = A[2 * Q:, 2 * Q:]
+        Mi = np.linalg.inv(Mq)
+        Su = Kuu + kappa * (Ex.T @ Mi @ Ex + Ey.T @ Mi @ Ey)
+        x = inputs.random_vector(3 * Q, seed=K)
+        u = np.linalg.solve(Su, x[2 * Q:] - kappa * (Ex.T @ Mi @ x[:Q] + Ey.T @ Mi @ x[Q:2 * Q]))
+        y = np.concatenate([Mi @ (x[:Q] + Ex @ u), Mi @ (x[Q:2 * Q] + Ey @ u), u])
+        ly = o.local_solve(K, x)
+        assert np.linalg.norm(y - ly) <= 1e-10 * np.linalg.norm(ly)
+
+
 def test_transposed_apply_is_the_adjoint_of_the_apply():
     """The transposed matrix-free product satisfies <y, S^T x> = <S y, x>
     against the forward apply (pinned above to the assembled S), on a
