@@ -869,8 +869,8 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
   mhdg_status st;
   std::vector<double> Hr(size_t(ns) * (R + 1) * R), cs(size_t(ns) * R), sn(size_t(ns) * R),
       g(size_t(ns) * (R + 1)), hprev(size_t(ns) * (R + 1)), beta(ns), nrm(ns), y(size_t(ns) * R),
-      pq(2 * size_t(R + 2) * ns), hy(size_t(R + 2) * ns), col(size_t(R + 2) * ns),
-      coef((2 * size_t(R) + 3) * ns), alpha(ns);
+      pq(3 * size_t(R + 2) * ns), col(size_t(R + 2) * ns), coef((2 * size_t(R) + 3) * ns),
+      alpha(ns);
   std::vector<int32_t> skip(ns), skip_dev_copy(ns, -1);
   std::vector<char> active(ns);
   std::vector<int> jc(ns);
@@ -891,9 +891,9 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
     }
     skip[q] = done[q];
   }
-  double* const ca = G.coef;
-  double* const cd = G.coef + size_t(R) * ns;
-  double* const sc = G.coef + 2 * size_t(R) * ns;
+  // q_j / u_{j+1} coefficients, packed per iteration as [ca (j ns) | cd (j ns) |
+  // sc (3 ns)] in one host buffer and one device buffer, one copy per iteration
+  double* const coefd = G.coef;
   while (true) {
     // ---- true preconditioned residual, cycle start
     if ((st = push_skip())) return st;
@@ -943,14 +943,16 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
         // complete the last column: projections of u_j only
         HIP_TRY(M, launch_dots(G.V, ld, j + 1, u, n, G.partial, G.nblk, G.hy, s, ns));
       }
+      // Hbar a lands right after the 2 (j + 1) ns dual products (the pq and hy
+      // regions of the workspace are contiguous), so one copy brings both back
+      const size_t npq = 2 * size_t(j + 1) * ns;
       if (!last && j >= 2)
-        HIP_TRY(M, launch_hbar_gemv(G.Hb, hld, ns, j - 1, j, G.pq, G.hy, s));
+        HIP_TRY(M, launch_hbar_gemv(G.Hb, hld, ns, j - 1, j, G.pq, G.pq + npq, s));
+      const double* hyv = pq.data() + npq;
       if (!last) {
-        HIP_TRY(M, hipMemcpyAsync(pq.data(), G.pq, 2 * size_t(j + 1) * ns * sizeof(double),
+        HIP_TRY(M, hipMemcpyAsync(pq.data(), G.pq,
+                                  (npq + (j >= 2 ? size_t(j) * ns : 0)) * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
-        if (j >= 2)
-          HIP_TRY(M, hipMemcpyAsync(hy.data(), G.hy, size_t(j) * ns * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
       } else {
         // same layout as dots2's first products: pq[(2c) ns + q]
         std::vector<double> pl(size_t(j + 1) * ns);
@@ -1025,8 +1027,8 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
       // coefficients of q_j and u_{j+1}
       for (int q = 0; q < ns; ++q) {
         double* cc = coef.data();
-        double* cdd = coef.data() + size_t(R) * ns;
-        double* scc = coef.data() + 2 * size_t(R) * ns;
+        double* cdd = coef.data() + size_t(j) * ns;
+        double* scc = coef.data() + 2 * size_t(j) * ns;
         if (!active[q]) {
           for (int c = 0; c < j; ++c) { cc[size_t(c) * ns + q] = 0.0; cdd[size_t(c) * ns + q] = 0.0; }
           scc[q] = scc[ns + q] = scc[2 * ns + q] = 0.0;
@@ -1040,7 +1042,7 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
         double* hp = &hprev[size_t(q) * (R + 1)];
         const double aj1 = j >= 1 ? pq[(2 * size_t(j - 1)) * ns + q] : 0.0;
         for (int i = 0; i <= j; ++i) {
-          double hba = (j >= 2 && i < j) ? hy[size_t(i) * ns + q] : 0.0;
+          double hba = (j >= 2 && i < j) ? hyv[size_t(i) * ns + q] : 0.0;
           if (j >= 1) hba += aj1 * col[size_t(i) * ns + q];
           const double ci = i < j ? pq[(2 * size_t(i) + 1) * ns + q] : cj;
           hp[i] = (ci - hba) / bt;
@@ -1054,13 +1056,10 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
         scc[ns + q] = 1.0 / bt;
         scc[2 * ns + q] = -cj / (bt * bt);
       }
-      HIP_TRY(M, hipMemcpyAsync(ca, coef.data(), size_t(j) * ns * sizeof(double),
+      HIP_TRY(M, hipMemcpyAsync(coefd, coef.data(), (2 * size_t(j) + 3) * ns * sizeof(double),
                                 hipMemcpyHostToDevice, s));
-      HIP_TRY(M, hipMemcpyAsync(cd, coef.data() + size_t(R) * ns, size_t(j) * ns * sizeof(double),
-                                hipMemcpyHostToDevice, s));
-      HIP_TRY(M, hipMemcpyAsync(sc, coef.data() + 2 * size_t(R) * ns, 3 * size_t(ns) * sizeof(double),
-                                hipMemcpyHostToDevice, s));
-      HIP_TRY(M, launch_dual_update(G.V, ld, j, n, ns, ca, cd, sc, G.wv, s));
+      HIP_TRY(M, launch_dual_update(G.V, ld, j, n, ns, coefd, coefd + size_t(j) * ns,
+                                    coefd + 2 * size_t(j) * ns, G.wv, s));
       if ((st = push_skip())) return st;
       ++j;
     }
