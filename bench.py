@@ -78,8 +78,14 @@ WORKLOADS = {
     # lockstep with converged instances masked out of later applies
     "batched_64inst_128macro_r1to4_p3": dict(n=8, r="mixed", p=3, kappa=None, beta=None,
                                              sol="exp_sin", precision="fp64", n_inst=64),
+    # GMRES(1000) for the forward and the adjoint solves (about 12,000 iterations each at
+    # 1e-9; GMRES(300) stalls on the adjoint, no restart costs 1.8x more basis traffic)
     "adjoint_32768macro_r2_p2": dict(n=128, r=2, p=2, kappa=None, beta=(1.0, 1.0), sol="sin_sin",
-                                     precision="fp64", form="adjoint", restart=8000, rtol=1e-9),
+                                     precision="fp64", form="adjoint", restart=1000, rtol=1e-9),
+    # the same with folded applies (T_K, forward and transposed)
+    "adjoint_folded_32768macro_r2_p2": dict(n=128, r=2, p=2, kappa=None, beta=(1.0, 1.0),
+                                            sol="sin_sin", precision="fp64", form="adjoint",
+                                            restart=1000, rtol=1e-9, folded=True),
 }
 
 
@@ -580,6 +586,8 @@ def bench_adjoint(args, w):
     import torch
     from paper_2302_10917_amd import autograd as ad
     from paper_2302_10917_amd import inputs, mhdg
+
+    args.folded = args.folded or w.get("folded", False)
 
     xy, tri = inputs.structured_mesh(w["n"])
     n_macro = len(tri)
