@@ -750,7 +750,7 @@ __global__ __launch_bounds__(256) void mass_kernel(const MacroInfo* __restrict__
 
 // ------------------------------------------------------------------ vector ops
 // Row chunks of the Krylov vectors handled by one partial dot product.
-constexpr int kDotChunk = 8192;
+constexpr int kDotChunk = 2048;   // rows per partial sum: enough workgroups for a few columns
 
 int dots_nblk(int64_t n) {
   int64_t b = (n + kDotChunk - 1) / kDotChunk;
