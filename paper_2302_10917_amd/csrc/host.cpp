@@ -930,8 +930,10 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
       double* u = G.V + j * ld;
       if (!last) {
         const double* uin = u;
-        if (G.op_flags & MHDG_GRAPH) {   // the captured graph reads a fixed input vector
-          HIP_TRY(M, hipMemcpyAsync(G.xin, u, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (G.op_flags & MHDG_GRAPH) {   // the captured graph reads a fixed input vector;
+          // after the first column the previous dual update wrote u_j there too
+          if (j == 0)
+            HIP_TRY(M, hipMemcpyAsync(G.xin, u, len * sizeof(double), hipMemcpyDeviceToDevice, s));
           uin = G.xin;
         }
         if ((st = apply_op(M, uin, G.wv, G.op_flags, G.skip, s))) return st;   // z = A u_j
@@ -1059,7 +1061,8 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
       HIP_TRY(M, hipMemcpyAsync(coefd, coef.data(), (2 * size_t(j) + 3) * ns * sizeof(double),
                                 hipMemcpyHostToDevice, s));
       HIP_TRY(M, launch_dual_update(G.V, ld, j, n, ns, coefd, coefd + size_t(j) * ns,
-                                    coefd + 2 * size_t(j) * ns, G.wv, s));
+                                    coefd + 2 * size_t(j) * ns, G.wv,
+                                    (G.op_flags & MHDG_GRAPH) ? G.xin : nullptr, s));
       if ((st = push_skip())) return st;
       ++j;
     }

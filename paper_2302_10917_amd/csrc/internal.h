@@ -210,7 +210,8 @@ hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x,
 hipError_t launch_hbar_gemv(const double* Hb, int64_t ld, int nseg, int kmax, int rows,
                             const double* pq, double* out, hipStream_t s);
 hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg, const double* ca,
-                              const double* cd, const double* sc, const double* z, hipStream_t s);
+                              const double* cd, const double* sc, const double* z, double* u2,
+                              hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);
 int dots_nblk(int64_t n);

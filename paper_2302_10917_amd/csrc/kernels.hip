@@ -885,7 +885,8 @@ __global__ __launch_bounds__(256) void dual_update_kernel(double* __restrict__ V
                                                           const double* __restrict__ ca,
                                                           const double* __restrict__ cd,
                                                           const double* __restrict__ sc,
-                                                          const double* __restrict__ z) {
+                                                          const double* __restrict__ z,
+                                                          double* __restrict__ u2) {
   const int64_t total = n * nseg;
   const int64_t idx0 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   const bool ok = idx0 < total;
@@ -926,7 +927,9 @@ __global__ __launch_bounds__(256) void dual_update_kernel(double* __restrict__ V
   const double s1 = sc[seg], s2 = sc[nseg + seg], s3 = sc[2 * nseg + seg];
   // masked segments (all coefficients zero) become exact zeros
   V[j * ld + idx] = s1 == 0.0 ? 0.0 : s1 * u - ((a0 + a1) + (a2 + a3));
-  V[(j + 1) * ld + idx] = s2 == 0.0 ? 0.0 : s2 * z[idx] + s3 * u - ((d0 + d1) + (d2 + d3));
+  const double un = s2 == 0.0 ? 0.0 : s2 * z[idx] + s3 * u - ((d0 + d1) + (d2 + d3));
+  V[(j + 1) * ld + idx] = un;
+  if (u2) u2[idx] = un;   // second copy of u_{j+1} (the captured apply's input vector)
 }
 
 // out[c * nseg + seg] = sum over the chunks of (column c, segment seg)
@@ -1322,9 +1325,10 @@ hipError_t launch_hbar_gemv(const double* Hb, int64_t ld, int nseg, int kmax, in
 }
 
 hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg, const double* ca,
-                              const double* cd, const double* sc, const double* z, hipStream_t s) {
+                              const double* cd, const double* sc, const double* z, double* u2,
+                              hipStream_t s) {
   hipLaunchKernelGGL(dual_update_kernel, dim3(blocks_for(n * nseg, 256)), dim3(256), 0, s, V, ld,
-                     j, n, nseg, ca, cd, sc, z);
+                     j, n, nseg, ca, cd, sc, z, u2);
   return hipGetLastError();
 }
 
