@@ -53,6 +53,11 @@ WORKLOADS = {
     "folded_qelim_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
                                               sol="exp_sin", precision="qelim", form="folded",
                                               restart=50),
+    # the best tuned form on the uneven-level mesh (instance 0 of the batching configuration)
+    "folded_qelim_mixed_r1to4_8192macro_p3_inst0": dict(n=64, r="mixed", p=3, kappa=None,
+                                                        beta=None, sol="exp_sin",
+                                                        precision="qelim", form="folded",
+                                                        instance=0, restart=50),
     "plain_fp64_8macro_r1_p2": dict(n=2, r=1, p=2, kappa=1.0, beta=(1.0, 1.0), sol="sin_sin",
                                     precision="fp64"),
     # precision configuration: same mesh, kappa = 1e-3, FP32 factors + FP64 refinement
@@ -109,14 +114,18 @@ def apply_bytes(m, elem_bytes=8, levels=None, p=None, qelim=False) -> float:
 
 def fold_bytes(tri, r, p, n_trace):
     """Algorithmic bytes of one folded apply: every T_K once (8 L_K^2, L_K = the
-    macro's interior-face trace dofs, n_F = 2^r p + 1 per interior edge), the
-    gathered trace and the written slots (2 x 8 x 2 n_trace)."""
+    macro's interior-face trace dofs, n_F = 2^{r_F} p + 1 per interior edge with
+    r_F the larger level of the two macros), the gathered trace and the written
+    slots (2 x 8 x 2 n_trace)."""
     tri = np.asarray(tri)
+    r = np.broadcast_to(np.asarray(r, dtype=np.int64), (len(tri),))
     e = np.sort(np.stack([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]], axis=1), axis=2)
     keys = e[..., 0].astype(np.int64) * (tri.max() + 1) + e[..., 1]
     _, inv, cnt = np.unique(keys.ravel(), return_inverse=True, return_counts=True)
-    interior = (cnt[inv] == 2).reshape(-1, 3).sum(axis=1)
-    L = interior * (2 ** int(r) * p + 1)
+    flev = np.zeros(len(cnt), dtype=np.int64)
+    np.maximum.at(flev, inv, np.repeat(r, 3))
+    nF = (2 ** flev[inv] * p + 1).reshape(-1, 3)
+    L = np.where((cnt[inv] == 2).reshape(-1, 3), nF, 0).sum(axis=1)
     return 8.0 * float(np.sum(L.astype(np.float64) ** 2)) + 32.0 * n_trace
 
 
@@ -282,16 +291,16 @@ def main():
     beta_arg = beta_inst if n_inst > 1 else tuple(beta_inst[0])
     lam = torch.zeros(s.n_trace, dtype=torch.float64, device=dev)
     qu = torch.empty(s.n_local, dtype=torch.float64, device=dev)
+    prec = {"fp32": mhdg.MHDG_FP32, "bf16": mhdg.MHDG_BF16,
+            "qelim": mhdg.MHDG_QELIM}.get(w["precision"], mhdg.MHDG_FP64)
+    reduced = prec in (mhdg.MHDG_FP32, mhdg.MHDG_BF16)
     print(f"[bench] {args.workload}: {s.n_macro} macros, N_K={s.max_local}, "
-          f"n_trace={s.n_trace}, {n_inst} instance(s), factors "
-          f"{m.query().factor_ws_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
+          f"n_trace={s.n_trace}, {n_inst} instance(s), factor workspace "
+          f"{m.query(prec).factor_ws_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
 
     infos = []
     Q = s.n_nodes // s.n_macro
 
-    prec = {"fp32": mhdg.MHDG_FP32, "bf16": mhdg.MHDG_BF16,
-            "qelim": mhdg.MHDG_QELIM}.get(w["precision"], mhdg.MHDG_FP64)
-    reduced = prec in (mhdg.MHDG_FP32, mhdg.MHDG_BF16)
 
     inst_infos = []
 
