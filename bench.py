@@ -85,6 +85,12 @@ WORKLOADS = {
                                              sol="exp_sin", precision="fp64", n_inst=64),
     # GMRES(1000) for the forward and the adjoint solves (about 12,000 iterations each at
     # 1e-9; GMRES(300) stalls on the adjoint, no restart costs 1.8x more basis traffic)
+    # the batching configuration with the folded Schur-factor form: all 64 instances
+    # factored (Q x Q Schur blocks), folded and solved together, GMRES(50) per instance
+    "batched_folded_qelim_64inst_128macro_r1to4_p3": dict(n=8, r="mixed", p=3, kappa=None,
+                                                          beta=None, sol="exp_sin",
+                                                          precision="qelim", form="folded",
+                                                          n_inst=64, restart=50),
     "adjoint_32768macro_r2_p2": dict(n=128, r=2, p=2, kappa=None, beta=(1.0, 1.0), sol="sin_sin",
                                      precision="fp64", form="adjoint", restart=1000, rtol=1e-9),
     # the same with folded applies (T_K, forward and transposed)
@@ -506,8 +512,9 @@ def main():
                          None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"],
                          qelim=prec == mhdg.MHDG_QELIM)
     if folded:
-        # folded apply: T_K read once (8 L_K^2), the gathered trace and the slots
-        nbytes = fold_bytes(tri, w["r"], w["p"], s.n_trace)
+        # folded apply: T_K read once (8 L_K^2), the gathered trace and the slots, for
+        # every instance
+        nbytes = n_inst * fold_bytes(tri, w["r"], w["p"], one.n_trace)
     if n_inst > 1:
         # converged instances are masked out of later launches: count the
         # instances each launch actually processed (GMRES applies + the
