@@ -38,12 +38,14 @@ WORKLOADS = {
                                        precision="fp64"),
     # folded form (same mesh and data): T_K = C_K A_K^-1 B_K stored per macro after the LU,
     # GMRES applies read L_K^2 = 75^2 values per macro instead of the 975^2 factors
-    # GMRES(50): with cheap applies the Krylov basis work dominates, and restarting
-    # at 30-50 columns solves fastest on this mesh (2000, i.e. no restart: 1207
-    # iterations, 2.31 s; 100: 1826, 1.76 s; 50: 1584, 1.67 s; 30: 1572, 1.71 s)
+    # GMRES(40): with cheap applies the Krylov basis work dominates, and restarting
+    # at 30-50 columns solves fastest on this mesh (folded full-block factors: 2000,
+    # i.e. no restart, 1207 iterations, 2.31 s; 100: 1826, 1.76 s; 50: 1584, 1.67 s;
+    # 30: 1572, 1.71 s.  Folded Schur factors: 50: 0.415 s; 40: 1551, 0.399 s;
+    # 30: 1572, 0.397 s; 20: 1999, 0.469 s)
     "folded_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
                                         sol="exp_sin", precision="fp64", form="folded",
-                                        restart=50),
+                                        restart=40),
     # flux eliminated exactly (same mesh and data): q through the reference mass, only the
     # Q x Q Schur block on u factored and streamed (Q = 325: 8 Q^2 bytes per macro)
     "qelim_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
@@ -52,7 +54,7 @@ WORKLOADS = {
     # many-right-hand-side Schur-block solves, GMRES(50) with folded applies
     "folded_qelim_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
                                               sol="exp_sin", precision="qelim", form="folded",
-                                              restart=50),
+                                              restart=40),
     # the best tuned form on the uneven-level mesh (instance 0 of the batching configuration)
     "folded_qelim_mixed_r1to4_8192macro_p3_inst0": dict(n=64, r="mixed", p=3, kappa=None,
                                                         beta=None, sol="exp_sin",
@@ -211,7 +213,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plain_fp64_8192macro_r3_p3", choices=list(WORKLOADS))
-    ap.add_argument("--folded-restart", type=int, default=50,
+    ap.add_argument("--folded-restart", type=int, default=40,
                     help="GMRES restart of the folded form run beside the plain one")
     ap.add_argument("--restart", type=int, default=None,
                     help="GMRES Krylov length (default: 2000, 8000 for the differentiation workload)")
