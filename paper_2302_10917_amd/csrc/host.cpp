@@ -80,6 +80,21 @@ struct mhdg_mesh {
   };
   std::vector<ApplyGraph> graphs;
   hipStream_t cap = nullptr;   // private stream the graphs are captured on
+  // page-locked host buffer for the small per-iteration GMRES transfers (kept
+  // until the handle is destroyed; host memory only)
+  double* pinned = nullptr;
+  size_t pinned_n = 0;
+  double* host_buffer(size_t n) {
+    if (n > pinned_n) {
+      if (pinned) (void)hipHostFree(pinned);
+      pinned = nullptr;
+      pinned_n = 0;
+      if (hipHostMalloc((void**)&pinned, n * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return nullptr;
+      pinned_n = n;
+    }
+    return pinned;
+  }
   void drop_graphs() {
     for (auto& a : graphs) { (void)hipGraphExecDestroy(a.x); (void)hipGraphDestroy(a.g); }
     graphs.clear();
@@ -89,6 +104,7 @@ struct mhdg_mesh {
       for (auto& p : v) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
     drop_graphs();
     if (cap) (void)hipStreamDestroy(cap);
+    if (pinned) (void)hipHostFree(pinned);
   }
 };
 
@@ -869,8 +885,19 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
   mhdg_status st;
   std::vector<double> Hr(size_t(ns) * (R + 1) * R), cs(size_t(ns) * R), sn(size_t(ns) * R),
       g(size_t(ns) * (R + 1)), hprev(size_t(ns) * (R + 1)), beta(ns), nrm(ns), y(size_t(ns) * R),
-      pq(3 * size_t(R + 2) * ns), col(size_t(R + 2) * ns), coef((2 * size_t(R) + 3) * ns),
       alpha(ns);
+  // the buffers that cross to and from the device every iteration, page-locked:
+  // dual products and Hbar a (read back), the finished Hbar column and the update
+  // coefficients (sent).  Each is rewritten by the host only after the stream
+  // synchronisation of the next iteration, so an earlier copy has always run.
+  const size_t n_pq = 3 * size_t(R + 2) * ns, n_col = size_t(R + 2) * ns,
+               n_coef = (2 * size_t(R) + 3) * ns;
+  double* const pin = M->host_buffer(n_pq + n_col + n_coef);
+  if (!pin) return fail(M, MHDG_ERR_HIP, "solve: page-locked host buffer not available");
+  double* const pq = pin;
+  double* const col = pin + n_pq;
+  double* const coef = col + n_col;
+  std::fill(pin, pin + n_pq + n_col + n_coef, 0.0);
   std::vector<int32_t> skip(ns), skip_dev_copy(ns, -1);
   std::vector<char> active(ns);
   std::vector<int> jc(ns);
@@ -950,9 +977,9 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
       const size_t npq = 2 * size_t(j + 1) * ns;
       if (!last && j >= 2)
         HIP_TRY(M, launch_hbar_gemv(G.Hb, hld, ns, j - 1, j, G.pq, G.pq + npq, s));
-      const double* hyv = pq.data() + npq;
+      const double* hyv = pq + npq;
       if (!last) {
-        HIP_TRY(M, hipMemcpyAsync(pq.data(), G.pq,
+        HIP_TRY(M, hipMemcpyAsync(pq, G.pq,
                                   (npq + (j >= 2 ? size_t(j) * ns : 0)) * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
       } else {
@@ -1022,15 +1049,15 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
         for (int q = 0; q < ns; ++q)
           if (jc[q] != j)   // segments that were already inactive: zero column
             for (int i = 0; i <= j; ++i) col[size_t(i) * ns + q] = 0.0;
-        HIP_TRY(M, hipMemcpyAsync(G.Hb + (size_t(j - 1) * hld) * ns, col.data(),
+        HIP_TRY(M, hipMemcpyAsync(G.Hb + (size_t(j - 1) * hld) * ns, col,
                                   size_t(j + 1) * ns * sizeof(double), hipMemcpyHostToDevice, s));
       }
       if (last || !any) break;
       // coefficients of q_j and u_{j+1}
       for (int q = 0; q < ns; ++q) {
-        double* cc = coef.data();
-        double* cdd = coef.data() + size_t(j) * ns;
-        double* scc = coef.data() + 2 * size_t(j) * ns;
+        double* cc = coef;
+        double* cdd = coef + size_t(j) * ns;
+        double* scc = coef + 2 * size_t(j) * ns;
         if (!active[q]) {
           for (int c = 0; c < j; ++c) { cc[size_t(c) * ns + q] = 0.0; cdd[size_t(c) * ns + q] = 0.0; }
           scc[q] = scc[ns + q] = scc[2 * ns + q] = 0.0;
@@ -1058,7 +1085,7 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
         scc[ns + q] = 1.0 / bt;
         scc[2 * ns + q] = -cj / (bt * bt);
       }
-      HIP_TRY(M, hipMemcpyAsync(coefd, coef.data(), (2 * size_t(j) + 3) * ns * sizeof(double),
+      HIP_TRY(M, hipMemcpyAsync(coefd, coef, (2 * size_t(j) + 3) * ns * sizeof(double),
                                 hipMemcpyHostToDevice, s));
       HIP_TRY(M, launch_dual_update(G.V, ld, j, n, ns, coefd, coefd + size_t(j) * ns,
                                     coefd + 2 * size_t(j) * ns, G.wv,
