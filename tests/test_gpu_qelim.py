@@ -185,13 +185,6 @@ def test_unsupported_calls_are_refused():
         with pytest.raises(mhdg.MhdgError) as e:
             call()
         assert e.value.status == 7
-    # Schur blocks beyond the kernels' register and LDS budget are refused up front
-    xy1, tri1 = inputs.structured_mesh(1)
-    big = mhdg.MacroMesh(xy1, tri1, 4, 4)              # P = 64, Q = 2145
-    with pytest.raises(mhdg.MhdgError) as e:
-        big.factor_local(gpu(np.full(len(tri1), 0.3)), beta, 1.0, precision=mhdg.MHDG_QELIM)
-    assert e.value.status == 1
-    big.close()
     # the handle still works, and a later FP64 factorisation replaces the form
     m.apply_trace_operator(x, y, 0)
     m.factor_local(gpu(kap), beta, 1.0)
