@@ -43,7 +43,7 @@ def host(t):
 # name: (n squares, jitter, levels, p)
 CASES = {"uniform_r2_p3": (3, 0.0, 2, 3), "mixed_p2_jitter": (3, 0.1, "mixed", 2),
          "r3_p3": (2, 0.0, 3, 3), "mixed_r1to4_p3": (2, 0.05, "mixed4", 3),
-         "single_r1_p1": (1, 0.0, 1, 1)}
+         "single_r1_p1": (1, 0.0, 1, 1), "r3_p4": (2, 0.0, 3, 4)}
 
 
 def _case(name):
@@ -220,5 +220,27 @@ def test_folded_from_schur_factors_matches_oracle(name):
     qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
     m.recover_local(x, qu)
     assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    m.close()
+
+
+def test_folded_instances_from_schur_factors():
+    xy, tri, r, p, _, _ = _case("mixed_p2_jitter")
+    kap_i, beta = inputs.coefficient_instances(3, seed=34)
+    field = inputs.lognormal_kappa(len(tri), 0.3, seed=9)
+    kappa = np.stack([k * field for k in kap_i])
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    one = m.sizes
+    m.set_instances(3)
+    m.factor_local(gpu(kappa.ravel()), beta, 1.0, precision=mhdg.MHDG_QELIM)
+    m.fold_operator()
+    nt = one.n_trace
+    lam = inputs.random_vector(3 * nt, seed=2)
+    out = torch.empty(3 * nt, dtype=torch.float64, device=DEV)
+    m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_PRECONDITION | mhdg.MHDG_FOLDED)
+    o = host(out)
+    for i in range(3):
+        orc = hdg.Oracle(xy, tri, r, p, kappa[i], beta[i], 1.0)
+        sl = slice(i * nt, (i + 1) * nt)
+        assert rel(o[sl], orc.apply(lam[sl], precondition=True)) <= 1e-10, i
     m.close()
 
