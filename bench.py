@@ -93,6 +93,20 @@ WORKLOADS = {
                                                           beta=None, sol="exp_sin",
                                                           precision="qelim", form="folded",
                                                           n_inst=64, restart=50),
+    # the batching configuration at full size: all 64 coefficient instances on the
+    # 8192-macro mixed-level mesh, one after another on one handle (their factors do not
+    # fit together), each with the folded Schur-factor form.  The diffusion-dominated
+    # instances need a longer Krylov basis: with GMRES(50) those with kappa >= 0.1 stall
+    # at 20000 iterations, with GMRES(150) they converge in 8300..16300 (GMRES(400) and
+    # (1000) are no faster there: fewer iterations, each dearer), while for kappa ~ 1e-3
+    # GMRES(50) is the fastest (551 ms against 830 ms at 150)
+    "all64_folded_qelim_mixed_r1to4_8192macro_p3": dict(n=64, r="mixed", p=3, kappa=None,
+                                                        beta=None, sol="exp_sin",
+                                                        precision="qelim",
+                                                        form="sequential_instances",
+                                                        n_inst=64, restart=50,
+                                                        restart_diffusive=150,
+                                                        kappa_diffusive=0.015),
     "adjoint_32768macro_r2_p2": dict(n=128, r=2, p=2, kappa=None, beta=(1.0, 1.0), sol="sin_sin",
                                      precision="fp64", form="adjoint", restart=1000, rtol=1e-9),
     # the same with folded applies (T_K, forward and transposed)
@@ -234,6 +248,9 @@ def main():
                     help="batched workload: after the timed steps, solve the first K instances "
                          "one at a time with single-instance handles (the plain form) and "
                          "report their time")
+    ap.add_argument("--instances", default=None, metavar="I,J,...",
+                    help="sequential-instances workload: solve only these coefficient "
+                         "instances (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--folded", action="store_true",
                     help="run the GMRES applies on the folded macro operators (FP64 workloads, "
@@ -258,6 +275,7 @@ def main():
     from paper_2302_10917_amd import inputs, mhdg
 
     w = dict(WORKLOADS[args.workload])
+    args.restart_override = args.restart is not None
     if args.restart is None:
         args.restart = w.get("restart", 2000)
     if args.rtol is None:
@@ -266,6 +284,8 @@ def main():
         args.inner_rtol = w.get("inner_rtol", 1e-5)
     if w.get("form") == "adjoint":
         return bench_adjoint(args, w)
+    if w.get("form") == "sequential_instances":
+        return bench_sequential_instances(args, w)
     folded = w.get("form") == "folded" or args.folded
     xy, tri = inputs.structured_mesh(w["n"])
     n_inst = w.get("n_inst", 1)
@@ -596,6 +616,99 @@ def main():
             wc["kappa"], wc["beta"] = float(kap_inst[0]), tuple(beta_inst[0])
         result["cpu_baseline"] = cpu_baseline(xy, tri, wc)
     print(json.dumps(result), flush=True)
+
+
+def bench_sequential_instances(args, w):
+    """One step = every coefficient instance of the batching configuration on the
+    full mixed-level mesh, solved one after another on one handle with the folded
+    Schur-factor form (factor_local with the flux eliminated, fold_operator,
+    folded GMRES, recover_local), each to rtol."""
+    import torch
+    from paper_2302_10917_amd import inputs, mhdg
+
+    xy, tri = inputs.structured_mesh(w["n"])
+    r = inputs.random_levels(len(tri), (1, 2, 3, 4), seed=3)
+    kap_i, beta_i = inputs.coefficient_instances(64, seed=33)
+    ids = (list(range(w["n_inst"])) if args.instances is None
+           else [int(x) for x in args.instances.split(",")])
+    n_inst = len(ids)
+    m = mhdg.MacroMesh(xy, tri, r, w["p"])
+    s = m.sizes
+    node, bnd = m.sample_points()
+    dev = "cuda"
+    lam = torch.zeros(s.n_trace, dtype=torch.float64, device=dev)
+    qu = torch.empty(s.n_local, dtype=torch.float64, device=dev)
+    data = {}
+    for i in ids:
+        ex = getattr(inputs, w["sol"])(float(kap_i[i]), beta_i[i])
+        data[i] = (torch.as_tensor(ex.f(node[:, 0], node[:, 1]), device=dev),
+                   torch.as_tensor(ex.u(bnd[:, 0], bnd[:, 1]), device=dev),
+                   torch.full((s.n_macro,), float(kap_i[i]), dtype=torch.float64, device=dev),
+                   tuple(float(x) for x in beta_i[i]))
+    print(f"[bench] {args.workload}: {n_inst} instances x {s.n_macro} macros, N_K up to "
+          f"{s.max_local}, n_trace={s.n_trace}", file=sys.stderr, flush=True)
+    infos = []
+
+    def restart_for(i):
+        if args.restart_override:
+            return args.restart
+        return w["restart_diffusive"] if kap_i[i] >= w["kappa_diffusive"] else w["restart"]
+
+    def solve_one(i):
+        f, g, kap, beta = data[i]
+        m.factor_local(kap, beta, 1.0, precision=mhdg.MHDG_QELIM)
+        m.fold_operator()
+        inf = m.solve(f, g, lam, rtol=args.rtol, restart=restart_for(i), max_iter=args.max_iter,
+                      folded=True, check=False)
+        m.recover_local(lam, qu)
+        d = inf.as_dict()
+        print(f"[bench] instance {i}: kappa {kap_i[i]:.3e} |beta| {np.hypot(*beta_i[i]):.2f}: "
+              f"GMRES({restart_for(i)}) {d['iterations']} iterations, status {d['status']}, rel res "
+              f"{d['rel_res_prec']:.2e}, {d['t_gmres_ms']:.0f} ms GMRES", file=sys.stderr,
+              flush=True)
+        return d
+
+    for _ in range(args.warmup):
+        solve_one(ids[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(args.steps):
+        for i in ids:
+            infos.append(solve_one(i))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    applies = sum(x["n_applies"] for x in infos)
+    its = [x["iterations"] for x in infos]
+    worst = max(x["rel_res_prec"] for x in infos)
+    result = {
+        "metric": METRIC,
+        "value": applies / elapsed,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_macro": s.n_macro, "n_instances": n_inst,
+                   "r": "U{1,2,3,4} seed 3", "p": w["p"],
+                   "kappa": "10^U(-3,0) per instance, seed 33",
+                   "beta": "|a| U(0.5,2), direction U[0,2pi) per instance, seed 33",
+                   "tau": 1.0, "rtol": args.rtol,
+                   "gmres_restart": (args.restart if args.restart_override else
+                                     f"{w['restart']} for kappa < {w['kappa_diffusive']}, "
+                                     f"else {w['restart_diffusive']}"),
+                   "form": "folded_flux_eliminated_fp64, instances in sequence"},
+        "time_to_solve_s": elapsed / args.steps,
+        "per_instance_s": elapsed / (args.steps * n_inst),
+        "iterations_min_max": [min(its), max(its)],
+        "worst_rel_res_prec": worst,
+        "all_converged": all(x["status"] == 0 for x in infos),
+    }
+    print(json.dumps(result))
 
 
 def bench_adjoint(args, w):
