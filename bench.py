@@ -93,6 +93,10 @@ WORKLOADS = {
                                                           beta=None, sol="exp_sin",
                                                           precision="qelim", form="folded",
                                                           n_inst=64, restart=50),
+    # the plain at-scale operator applied to many vectors per call (one factorisation,
+    # several right-hand sides): a wavefront carries 4 vectors through the local solve
+    "many_rhs_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                          precision="fp64", form="many_rhs", n_rhs=32),
     # the batching configuration at full size: all 64 coefficient instances on the
     # 8192-macro mixed-level mesh, one after another on one handle (their factors do not
     # fit together), each with the folded Schur-factor form.  The diffusion-dominated
@@ -251,6 +255,8 @@ def main():
     ap.add_argument("--instances", default=None, metavar="I,J,...",
                     help="sequential-instances workload: solve only these coefficient "
                          "instances (default: all)")
+    ap.add_argument("--n-rhs", type=int, default=None,
+                    help="many-vector workload: vectors per call (default 32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--folded", action="store_true",
                     help="run the GMRES applies on the folded macro operators (FP64 workloads, "
@@ -286,6 +292,8 @@ def main():
         return bench_adjoint(args, w)
     if w.get("form") == "sequential_instances":
         return bench_sequential_instances(args, w)
+    if w.get("form") == "many_rhs":
+        return bench_many_rhs(args, w)
     folded = w.get("form") == "folded" or args.folded
     xy, tri = inputs.structured_mesh(w["n"])
     n_inst = w.get("n_inst", 1)
@@ -615,6 +623,91 @@ def main():
         if n_inst > 1:   # the oracle applies one instance's operator
             wc["kappa"], wc["beta"] = float(kap_inst[0]), tuple(beta_inst[0])
         result["cpu_baseline"] = cpu_baseline(xy, tri, wc)
+    print(json.dumps(result), flush=True)
+
+
+def bench_many_rhs(args, w):
+    """One step = the preconditioned trace operator D^-1 S applied to n_rhs vectors
+    by one call of the many-vector apply (FP64 factors of the plain at-scale mesh).
+    After the timed steps: the per-vector rate for 1..32 vectors per call and of
+    the single-vector apply."""
+    import torch
+    from paper_2302_10917_amd import inputs, mhdg
+
+    xy, tri = inputs.structured_mesh(w["n"])
+    m = mhdg.MacroMesh(xy, tri, w["r"], w["p"])
+    s = m.sizes
+    dev = "cuda"
+    kappa = torch.full((s.n_macro,), w["kappa"], dtype=torch.float64, device=dev)
+    m.factor_local(kappa, w["beta"], 1.0)
+    n_rhs = args.n_rhs or w["n_rhs"]
+    vec = 32.0 * s.n_trace                       # gathered trace + written slots, per vector
+    fac = apply_bytes(m) - vec                   # every stored factor entry once
+    flags = mhdg.MHDG_PRECONDITION
+    lam = torch.as_tensor(np.stack([inputs.random_vector(s.n_trace, seed=1 + v)
+                                    for v in range(32)]), device=dev)
+    out = torch.empty_like(lam)
+    print(f"[bench] {args.workload}: {s.n_macro} macros, N_K={s.max_local}, "
+          f"n_trace={s.n_trace}, {n_rhs} vectors per call", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        m.apply_trace_operator_many(lam[:n_rhs], out[:n_rhs], flags)
+    torch.cuda.synchronize()
+    m.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        m.apply_trace_operator_many(lam[:n_rhs], out[:n_rhs], flags)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = m.profile(False)
+    k_ms = kt["apply_macro_solve"]["ms"] / max(kt["apply_macro_solve"]["count"], 1)
+    nbytes = fac + n_rhs * vec
+    # single-vector apply and other group sizes (outside the timed steps)
+    one = torch.empty(s.n_trace, dtype=torch.float64, device=dev)
+    m.apply_trace_operator(lam[0], one, flags)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(5):
+        m.apply_trace_operator(lam[0], one, flags)
+    torch.cuda.synchronize()
+    single = 5 / (time.perf_counter() - t1)
+    sweep = {}
+    for k in (1, 2, 4, 8, 16, 32):
+        m.apply_trace_operator_many(lam[:k], out[:k], flags)
+        torch.cuda.synchronize()
+        reps = max(2, 32 // k)
+        t2 = time.perf_counter()
+        for _ in range(reps):
+            m.apply_trace_operator_many(lam[:k], out[:k], flags)
+        torch.cuda.synchronize()
+        sweep[k] = reps * k / (time.perf_counter() - t2)
+        print(f"[bench] {k} vectors per call: {sweep[k]:.1f} vector-applies/s",
+              file=sys.stderr, flush=True)
+    result = {
+        "metric": METRIC,
+        "value": args.steps * n_rhs / elapsed,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_macro": s.n_macro, "r": w["r"], "p": w["p"],
+                   "N_K": s.max_local, "n_trace": s.n_trace, "kappa": w["kappa"],
+                   "beta": list(w["beta"]), "tau": 1.0, "n_rhs": n_rhs,
+                   "form": "plain_fp64, many vectors per apply"},
+        "roofline": {"bound": "hbm", "achieved": nbytes / (k_ms * 1e-3) / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": nbytes / (k_ms * 1e-3) / 1e9 / 8000.0,
+                     "traffic": None,
+                     "kernel": "apply_many_kernel<16, 4>",
+                     "algorithmic_bytes_per_launch": nbytes,
+                     "kernel_ms": k_ms},
+        "single_vector_applies_per_s": single,
+        "vector_applies_per_s_by_n_rhs": sweep,
+    }
     print(json.dumps(result), flush=True)
 
 

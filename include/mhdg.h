@@ -237,6 +237,26 @@ mhdg_status mhdg_local_matrix(mhdg_mesh* mesh, int64_t e, double* dst, void* str
 mhdg_status mhdg_apply_trace_operator(mhdg_mesh* mesh, const double* lam, double* out,
                                       int32_t flags, void* stream);
 
+/* The trace operator applied to n_rhs vectors at once: out_v = S lam_v (or
+ * D^-1 S lam_v with MHDG_PRECONDITION) for v = 0 .. n_rhs-1, the same
+ * operator as mhdg_apply_trace_operator (steps 1-4 of section 3.3.2) with
+ * several right-hand sides per local solve: each macro's factors are read
+ * once per group of vectors (8 vectors for N_K <= 512, 4 up to 1024, 2 up to
+ * 2048, 1 above), not once per vector.  For callers with many vectors
+ * against one factorisation (several load cases, block Krylov methods).
+ * lam, out: device f64[n_rhs][n_trace] (vector v at offset v * n_trace);
+ * the two ranges must not overlap.  ws: device workspace of at least
+ * mhdg_apply_many_ws_bytes(mesh, n_rhs) bytes (per-vector contribution
+ * slots), owned by the caller; its contents on entry do not matter.
+ * flags: 0 or MHDG_PRECONDITION.  n_rhs = 0 is a no-op.
+ * Errors: INVALID_ARG (n_rhs < 0, other flags, null or overlapping
+ * vectors), STATE (before factor_local, or factors other than MHDG_FP64),
+ * WORKSPACE (ws too small). */
+size_t mhdg_apply_many_ws_bytes(const mhdg_mesh* mesh, int32_t n_rhs);
+mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* mesh, int32_t n_rhs, const double* lam,
+                                           double* out, int32_t flags, void* ws,
+                                           size_t ws_bytes, void* stream);
+
 /* y_K = A_K^-1 x_K (or A_K^-T x_K with MHDG_TRANSPOSE) for every macro with
  * the stored factors (step 2).  x, y: device f64[n_local], may alias. */
 mhdg_status mhdg_local_solve(mhdg_mesh* mesh, const double* x, double* y, int32_t flags,

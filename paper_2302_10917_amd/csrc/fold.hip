@@ -36,7 +36,6 @@ __global__ __launch_bounds__(64) void fold_build_kernel(
     const int32_t* __restrict__ order, int64_t base, int64_t count, int nch,
     const int32_t* __restrict__ perm_all, const double* __restrict__ tm, Templates Tp,
     double tau, const int64_t* __restrict__ toff, double* __restrict__ T) {
-  constexpr int kLG = kLoadGroup;
   extern __shared__ double sm[];   // NR compact boundary vectors of 3 NBD entries
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int64_t m = int64_t(seq / nch) * 8 + xcd;
@@ -89,76 +88,7 @@ __global__ __launch_bounds__(64) void fold_build_kernel(
 #pragma unroll
     for (int r = 0; r < NR; ++r) y[q][r] = b >= 0 ? sm[r * 3 * NBD + f * NBD + b] : 0.0;
   }
-  const double* A = fac + mi.fac_off;
-  // ---- forward substitution with the unit lower factor
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int jend = min(64, N - 64 * q);
-    for (int jj = 0; jj < jend; ++jj) {
-      const int j = 64 * q + jj;
-      double yj[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) yj[r] = readlane_d(y[q][r], jj);
-      const double* col = A + size_t(j) * mi.ld;
-#pragma unroll
-      for (int g = q; g < NQ; g += kLG) {
-        double a[kLG];
-#pragma unroll
-        for (int t = 0; t < kLG; ++t) {
-          const int rw = lane + 64 * (g + t);
-          int rr = (g + t == q && rw <= j) ? j + 1 : rw;
-          rr = rr < N ? rr : N - 1;
-          a[t] = (g + t < NQ) ? col[rr] : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < kLG; ++t) {
-          const int rw = lane + 64 * (g + t);
-          if (g + t < NQ) {
-            const double av = (rw > j && rw < N) ? a[t] : 0.0;
-#pragma unroll
-            for (int r = 0; r < NR; ++r) y[g + t][r] -= av * yj[r];
-          }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
-  // ---- backward substitution with the upper factor
-#pragma unroll
-  for (int q = NQ - 1; q >= 0; --q) {
-    const int jend = min(64, N - 64 * q);
-    for (int jj = jend - 1; jj >= 0; --jj) {
-      const int j = 64 * q + jj;
-      const double* col = A + size_t(j) * mi.ld;
-      const double dj = col[j];
-      double zj[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        zj[r] = readlane_d(y[q][r], jj) / dj;
-        if (lane == jj) y[q][r] = zj[r];
-      }
-#pragma unroll
-      for (int g = 0; g <= q; g += kLG) {
-        double a[kLG];
-#pragma unroll
-        for (int t = 0; t < kLG; ++t) {
-          const int rw = lane + 64 * (g + t);
-          const int rr = (g + t == q && rw >= j) ? (j > 0 ? j - 1 : 0) : rw;
-          a[t] = (g + t <= q) ? col[rr] : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < kLG; ++t) {
-          const int rw = lane + 64 * (g + t);
-          if (g + t <= q) {
-            const double av = rw < j ? a[t] : 0.0;
-#pragma unroll
-            for (int r = 0; r < NR; ++r) y[g + t][r] -= av * zj[r];
-          }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
+  lu_sweeps_nr<NQ, NR>(y, fac + mi.fac_off, N, mi.ld, lane);
   // ---- restriction with C_K (step 3): boundary rows of the solutions, then
   // per interior edge the trace moments, into columns col0 .. of T_K
   __syncthreads();

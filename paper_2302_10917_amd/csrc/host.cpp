@@ -2002,6 +2002,50 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* o
   return apply_op(M, lam, out, flags, nullptr, (hipStream_t)stream);
 }
 
+size_t mhdg_apply_many_ws_bytes(const mhdg_mesh* M, int32_t n_rhs) {
+  if (!M || n_rhs < 0) return 0;
+  return size_t(n_rhs) * size_t(M->n_slots) * sizeof(double);
+}
+
+mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* M, int32_t n_rhs, const double* lam,
+                                           double* out, int32_t flags, void* ws, size_t ws_bytes,
+                                           void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (n_rhs < 0) return fail(M, MHDG_ERR_INVALID_ARG, "apply_many: n_rhs < 0");
+  if (flags & ~MHDG_PRECONDITION)
+    return fail(M, MHDG_ERR_INVALID_ARG, "apply_many: only MHDG_PRECONDITION is accepted in flags");
+  if (!M->factored) return fail(M, MHDG_ERR_STATE, "apply_many: call factor_local first");
+  if (M->precision != MHDG_FP64)
+    return fail(M, MHDG_ERR_STATE, "apply_many: needs MHDG_FP64 factors");
+  if (n_rhs == 0 || M->n_trace == 0) return MHDG_OK;
+  if (!lam || !out) return fail(M, MHDG_ERR_INVALID_ARG, "apply_many: null vector");
+  const int64_t len = int64_t(n_rhs) * M->n_trace;
+  if (lam < out + len && out < lam + len)
+    return fail(M, MHDG_ERR_INVALID_ARG, "apply_many: lam and out overlap");
+  if (!ws || ws_bytes < mhdg_apply_many_ws_bytes(M, n_rhs))
+    return fail(M, MHDG_ERR_WORKSPACE, "apply_many: workspace smaller than mhdg_apply_many_ws_bytes");
+  hipStream_t s = (hipStream_t)stream;
+  FactorLayout& L = M->L;
+  char* w = M->ws;
+  double* slots = (double*)ws;
+  {
+    ProfScope ps(M, 2, s);
+    HIP_TRY(M, launch_apply_many((const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
+                                 (const int32_t*)(w + L.order), M->classes.data(),
+                                 (int)M->classes.size(), (const int32_t*)(w + L.perm),
+                                 (const double*)(w + L.tmpl), M->T, M->tau, n_rhs, lam,
+                                 M->n_trace, slots, M->n_slots, s));
+  }
+  ProfScope ps(M, 3, s);
+  for (int32_t v = 0; v < n_rhs; ++v)
+    HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
+                                   (const FaceInfo*)(w + L.faces), M->n_int,
+                                   (const double*)(w + L.tmpl), M->T, M->tau,
+                                   lam + int64_t(v) * M->n_trace, slots + int64_t(v) * M->n_slots,
+                                   out + int64_t(v) * M->n_trace, s));
+  return MHDG_OK;
+}
+
 mhdg_status mhdg_local_solve(mhdg_mesh* M, const double* x, double* y, int32_t flags, void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;
   if (!M->factored) return fail(M, MHDG_ERR_STATE, "local_solve: call factor_local first");

@@ -191,6 +191,16 @@ hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* to
                              int p, int max_L, const int32_t* skip, int transpose,
                              const double* lam, double* slots, hipStream_t s);
 
+// steps 1-3 for n_rhs trace vectors at once (many.hip): vector v reads
+// lam + v * ld_lam and writes its slots at slots + v * ld_slots
+hipError_t launch_apply_many(const double* fac, const MacroInfo* info, const int32_t* order,
+                             const SizeClass* classes, int n_classes, const int32_t* perm,
+                             const double* tmpl, const Templates& T, double tau, int n_rhs,
+                             const double* lam, int64_t ld_lam, double* slots, int64_t ld_slots,
+                             hipStream_t s);
+// vectors per wavefront of launch_apply_many for local size N
+int apply_many_group(int N);
+
 // GMRES vector kernels
 // Vectors may hold nseg independent segments of length n (coefficient
 // instances): dot products and updates are per segment; out / h are indexed

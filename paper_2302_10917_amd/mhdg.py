@@ -27,7 +27,8 @@ ABI_SYMBOLS = [
     "mhdg_solve", "mhdg_recover_local", "mhdg_destroy", "mhdg_last_error",
     "mhdg_status_string", "mhdg_profile", "mhdg_mass_apply", "mhdg_adjoint",
     "mhdg_set_instances", "mhdg_factor_local_batched", "mhdg_autotune",
-    "mhdg_set_kernel_variant", "mhdg_fold_operator",
+    "mhdg_set_kernel_variant", "mhdg_fold_operator", "mhdg_apply_many_ws_bytes",
+    "mhdg_apply_trace_operator_many",
 ]
 MHDG_TUNE_LU, MHDG_TUNE_SOLVE = 1, 2
 MAX_CLASSES = 8
@@ -122,6 +123,7 @@ def load_library(path: str = LIB_PATH):
         "mhdg_fold_operator": [P, P, SZ, P],
         "mhdg_local_matrix": [P, I64, P, P],
         "mhdg_apply_trace_operator": [P, P, P, I32, P],
+        "mhdg_apply_trace_operator_many": [P, I32, P, P, I32, P, SZ, P],
         "mhdg_local_solve": [P, P, P, I32, P],
         "mhdg_rhs": [P, P, P, P, I32, P],
         "mhdg_solve": [P, P, P, ctypes.POINTER(SolveOpts), P, P, SZ, P, P],
@@ -135,6 +137,8 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.mhdg_apply_many_ws_bytes.argtypes = [P, I32]
+    lib.mhdg_apply_many_ws_bytes.restype = SZ
     lib.mhdg_destroy.argtypes = [P]
     lib.mhdg_destroy.restype = None
     lib.mhdg_last_error.argtypes = [P]
@@ -193,7 +197,7 @@ class MacroMesh:
         if h is not None and h.value:
             self._lib.mhdg_destroy(h)
         self.h = None
-        self.factor_ws = self.solve_ws = self.fold_ws = None
+        self.factor_ws = self.solve_ws = self.fold_ws = self.many_ws = None
 
     def __del__(self):
         self.close()
@@ -264,6 +268,19 @@ class MacroMesh:
     def apply_trace_operator(self, lam, out, flags=0, stream=None):
         self._check(self._lib.mhdg_apply_trace_operator(self.h, _ptr(lam), _ptr(out), flags,
                                                         _stream(stream)), "apply_trace_operator")
+
+    def apply_trace_operator_many(self, lam, out, flags=0, stream=None):
+        """out[v] = S lam[v] (D^-1 S lam[v] with MHDG_PRECONDITION) for every row v
+        of the contiguous device tensors lam, out of shape (n_rhs, n_trace)."""
+        import torch
+        n_rhs = int(lam.shape[0]) if lam.dim() == 2 else 1
+        need = int(self._lib.mhdg_apply_many_ws_bytes(self.h, n_rhs))
+        if getattr(self, "many_ws", None) is None or self.many_ws.numel() < need:
+            self.many_ws = None
+            self.many_ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+        self._check(self._lib.mhdg_apply_trace_operator_many(
+            self.h, n_rhs, _ptr(lam), _ptr(out), flags, _ptr(self.many_ws), self.many_ws.numel(),
+            _stream(stream)), "apply_trace_operator_many")
 
     def local_solve(self, x, y, flags=0, stream=None):
         self._check(self._lib.mhdg_local_solve(self.h, _ptr(x), _ptr(y), flags, _stream(stream)),

@@ -328,6 +328,29 @@ def test_c2_apply_sampled(c2):
     apply_sampled(c2["m"], orc, c2["faces"], lam, folded=True)
 
 
+def test_c2_apply_many_sampled(c2):
+    """The many-vector apply at full size: 9 vectors in one call (groups of
+    4, 4 and 1 per macro), each against the oracle on the sampled faces and
+    against the single-vector apply everywhere."""
+    m, orc, faces = c2["m"], c2["orc"], c2["faces"]
+    topo = orc.topo
+    n = topo.n_trace
+    lam_h = np.stack([inputs.random_vector(n, seed=70 + v) for v in range(9)])
+    lam = gpu(lam_h)
+    out = torch.empty((9, n), dtype=torch.float64, device=DEV)
+    one = torch.empty(n, dtype=torch.float64, device=DEV)
+    m.apply_trace_operator_many(lam, out, mhdg.MHDG_PRECONDITION)
+    outh = host(out)
+    for v in range(9):
+        m.apply_trace_operator(lam[v], one, mhdg.MHDG_PRECONDITION)
+        assert rel(outh[v], host(one)) <= 1e-12, v
+    for v in (0, 4, 8):
+        ref = gather(orc.apply(lam_h[v], precondition=True, faces=faces), topo, faces)
+        err = rel(gather(outh[v], topo, faces), ref)
+        print(f"  many-vector apply, vector {v}: {err:.2e}", flush=True)
+        assert err <= TOL, v
+
+
 def test_c2_rhs_and_recovery_sampled(c2):
     """f^ (D^-1 f^) on sampled faces; U_K and the transmission residual for a
     random lam on sampled macros and faces."""
