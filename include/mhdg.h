@@ -287,6 +287,20 @@ mhdg_status mhdg_solve(mhdg_mesh* mesh, const double* f_nodes, const double* g_b
                        const mhdg_solve_opts* opts, double* lam, void* ws, size_t ws_bytes,
                        mhdg_solve_info* info, void* stream);
 
+/* Macro conservation residual, per macro K: <flux^.n, 1>_dK - (f_h, 1)_K
+ * with the LDG-H flux a.n lam + kappa q.n + tau (u - lam) of section 3.1
+ * (eq. weak_form tested with w = 1, the statement of macro-element
+ * conservation).  lam: device f64[n_trace] (the interior trace; boundary
+ * faces use the Dirichlet trace of the last mhdg_rhs / mhdg_solve), qu:
+ * device f64[n_local] (q_x, q_y, u per macro, as written by
+ * mhdg_recover_local), f_nodes: device f64[n_nodes] (the source given to
+ * rhs/solve), out: device f64[n_macro].  Zero to rounding for local fields
+ * recovered from any lam; any factor precision.
+ * Errors: STATE before factor_local and rhs/solve, INVALID_ARG on null
+ * vectors. */
+mhdg_status mhdg_flux_balance(mhdg_mesh* mesh, const double* lam, const double* qu,
+                              const double* f_nodes, double* out, void* stream);
+
 /* Local recovery U_K = A_K^-1 (R_K - B_K lam_K) into qu (device
  * f64[n_local]; with FP32 factors refined in FP64 until the local residual
  * stops decreasing) and, if flux_res is not NULL, the transmission residual

@@ -643,13 +643,14 @@ class Oracle:
                 eq += np.sum(wq * ((phi @ qx[ids] - qe[0]) ** 2 + (phi @ qy[ids] - qe[1]) ** 2))
         return float(np.sqrt(eu)), float(np.sqrt(eq))
 
-    def flux_balance(self, U, lam, lamD, f_nodal):
+    def flux_balance(self, U, lam, lamD, f_nodal, macros=None):
         """Per macro: <flux^.n, 1>_dK - (f_h, 1)_K with the LDG-H flux
         flux^.n = a.n u^ + kappa q.n + tau (u - u^) (section 3.1); zero for
-        the discrete solution because w = 1 lies in W(K)."""
+        the discrete solution because w = 1 lies in W(K).  macros: the macros
+        to evaluate (default all; the others are left zero)."""
         topo = self.topo
         res = np.zeros(topo.n_macro)
-        for K in range(topo.n_macro):
+        for K in (range(topo.n_macro) if macros is None else macros):
             b = self.blocks(K)
             Q = int(topo.Q[K])
             qx, qy, u = U[K][:Q], U[K][Q:2 * Q], U[K][2 * Q:]

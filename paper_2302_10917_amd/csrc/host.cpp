@@ -2083,6 +2083,22 @@ mhdg_status mhdg_rhs(mhdg_mesh* M, const double* f_nodes, const double* g_bnd, d
   return MHDG_OK;
 }
 
+mhdg_status mhdg_flux_balance(mhdg_mesh* M, const double* lam, const double* qu,
+                              const double* f_nodes, double* out, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->factored || !M->have_rhs)
+    return fail(M, MHDG_ERR_STATE, "flux_balance: call factor_local and rhs/solve first");
+  if (!qu || !f_nodes || !out || (!lam && M->n_trace > 0))
+    return fail(M, MHDG_ERR_INVALID_ARG, "flux_balance: null vector");
+  FactorLayout& L = M->L;
+  char* w = M->ws;
+  HIP_TRY(M, launch_flux_balance((const MacroInfo*)(w + L.meta), M->n_macro,
+                                 (const BndFaceInfo*)(w + L.bfaces), (const double*)(w + L.tmpl),
+                                 M->T, M->tau, lam, (const double*)(w + L.lamD), qu, f_nodes, out,
+                                 (hipStream_t)stream));
+  return MHDG_OK;
+}
+
 mhdg_status mhdg_recover_local(mhdg_mesh* M, const double* lam, double* qu, double* flux_res,
                                void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;

@@ -155,6 +155,11 @@ hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const d
                                const Templates& T, double tau, const double* lam,
                                const double* slots, double* out, hipStream_t s,
                                const int32_t* skip = nullptr);
+// per macro <flux^.n, 1>_dK - (f_h, 1)_K (the local problem tested with w = 1)
+hipError_t launch_flux_balance(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
+                               const double* tmpl, const Templates& T, double tau,
+                               const double* lam, const double* lamD, const double* U,
+                               const double* f, double* out, hipStream_t s);
 hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double* tmpl,
                                  const Templates& T, double tau, double* dst, hipStream_t s);
 // face_combine modes

@@ -527,6 +527,71 @@ __global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restri
   for (int i = threadIdx.x; i < N; i += 64) R[mi.loc_off + i] = x[i];
 }
 
+// ------------------------------------------------------------------ macro conservation
+// out_K = <flux^.n, 1>_dK - (f_h, 1)_K with the LDG-H flux
+// flux^.n = a.n lam + kappa q.n + tau (u - lam) (section 3.1): the local
+// problem tested with w = 1, which lies in the macro's space, so the value
+// vanishes (to rounding) for every U_K that solves its local problem.  Per
+// edge k, with G[i][l] = |F| T1[s][l] and sum_l mu_l = 1 on the face:
+//   <lam, 1>_F = |F| sum_s sum_l T1[s][l] lam_l,
+//   <v, 1>_F   = |F| sum_s (sum_l T1[s][l]) v(node s)   (v = q_x, q_y, u),
+// lam being the interior trace or the Dirichlet trace of a boundary face;
+// (f_h, 1)_K = |det J| 1^T Mhat f_K.  One wavefront per macro.
+__global__ __launch_bounds__(64) void flux_balance_kernel(
+    const MacroInfo* __restrict__ info, const BndFaceInfo* __restrict__ bf,
+    const double* __restrict__ tm, Templates Tp, double tau, const double* __restrict__ lam,
+    const double* __restrict__ lamD, const double* __restrict__ U,
+    const double* __restrict__ f, double* __restrict__ out) {
+  const MacroInfo& mi = info[blockIdx.x];
+  const int Q = mi.Q, P = mi.P, lane = threadIdx.x, p = Tp.p;
+  const LevelTemplates& LT = Tp.lev[mi.level];
+  const double* Mh = tm + LT.Mhat;
+  const double* fK = f + mi.node_off;
+  const double* qx = U + mi.loc_off;
+  const double* qy = qx + Q;
+  const double* u = qx + 2 * Q;
+  double acc = 0.0;
+  for (int i = lane; i < Q; i += 64) {
+    double v = 0.0;
+    for (int j = 0; j < Q; ++j) v += Mh[size_t(i) * Q + j] * fK[j];
+    acc -= mi.dJ * v;
+  }
+  const int32_t* en = ints(tm, LT.edge_node);
+  for (int k = 0; k < 3; ++k) {
+    const double* lF = mi.tr_off[k] >= 0 ? lam + mi.tr_off[k]
+                                         : lamD + bf[mi.bnd_face[k]].lam_off;
+    const int nF = (1 << mi.flevel[k]) * p + 1;
+    const double* T1 = tm + LT.T1[mi.flevel[k]];
+    const double nx = mi.nrm[2 * k], ny = mi.nrm[2 * k + 1];
+    const double an = mi.bx * nx + mi.by * ny;
+    double e = 0.0;
+    for (int s = lane; s <= P; s += 64) {
+      const int sc = mi.orient[k] > 0 ? s : P - s;
+      double w = 0.0, gl = 0.0;
+      for (int l = 0; l < nF; ++l) {
+        const double t = T1[size_t(sc) * nF + l];
+        w += t;
+        gl += t * lF[l];
+      }
+      const int node = en[k * (P + 1) + s];
+      e += (an - tau) * gl + (mi.kappa * (nx * qx[node] + ny * qy[node]) + tau * u[node]) * w;
+    }
+    acc += mi.len[k] * e;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) out[blockIdx.x] = acc;
+}
+
+hipError_t launch_flux_balance(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,
+                               const double* tmpl, const Templates& T, double tau,
+                               const double* lam, const double* lamD, const double* U,
+                               const double* f, double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(flux_balance_kernel, dim3((unsigned)n), dim3(64), 0, s, info, bf, tmpl, T,
+                     tau, lam, lamD, U, f, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ FP64 residual of the local rows
 // out_K = R_K - A_K U_K - B_K lam_K in FP64, matrix-free: with the reference
 // templates (Mhat symmetric, E^k and their transposes) the three block rows are

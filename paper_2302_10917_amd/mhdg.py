@@ -28,7 +28,7 @@ ABI_SYMBOLS = [
     "mhdg_status_string", "mhdg_profile", "mhdg_mass_apply", "mhdg_adjoint",
     "mhdg_set_instances", "mhdg_factor_local_batched", "mhdg_autotune",
     "mhdg_set_kernel_variant", "mhdg_fold_operator", "mhdg_apply_many_ws_bytes",
-    "mhdg_apply_trace_operator_many",
+    "mhdg_apply_trace_operator_many", "mhdg_flux_balance",
 ]
 MHDG_TUNE_LU, MHDG_TUNE_SOLVE = 1, 2
 MAX_CLASSES = 8
@@ -128,6 +128,7 @@ def load_library(path: str = LIB_PATH):
         "mhdg_rhs": [P, P, P, P, I32, P],
         "mhdg_solve": [P, P, P, ctypes.POINTER(SolveOpts), P, P, SZ, P, P],
         "mhdg_recover_local": [P, P, P, P, P],
+        "mhdg_flux_balance": [P, P, P, P, P, P],
         "mhdg_profile": [P, I32, ctypes.POINTER(KernelTimes)],
         "mhdg_mass_apply": [P, P, P, P],
         "mhdg_adjoint": [P, P, P, P, ctypes.POINTER(SolveOpts), P, P, P, P, P, SZ,
@@ -363,6 +364,11 @@ class MacroMesh:
         kt = KernelTimes()
         self._check(self._lib.mhdg_profile(self.h, 1 if enable else 0, ctypes.byref(kt)), "profile")
         return None if enable else kt.as_dict()
+
+    def flux_balance(self, lam, qu, f_nodes, out, stream=None):
+        """out[K] = <flux^.n, 1>_dK - (f_h, 1)_K for every macro (device f64[n_macro])."""
+        self._check(self._lib.mhdg_flux_balance(self.h, _ptr(lam), _ptr(qu), _ptr(f_nodes),
+                                                _ptr(out), _stream(stream)), "flux_balance")
 
     def recover_local(self, lam, qu, flux_res=None, stream=None):
         self._check(self._lib.mhdg_recover_local(self.h, _ptr(lam), _ptr(qu), _ptr(flux_res),

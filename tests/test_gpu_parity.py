@@ -154,6 +154,34 @@ def test_solve_and_recover_match_oracle(case):
     assert np.linalg.norm(host(res)) <= 1e-10 * np.linalg.norm(fhat)
 
 
+def test_flux_balance_matches_oracle(case):
+    """Macro conservation residual <flux^.n, 1>_dK - (f_h, 1)_K: on arbitrary
+    (lam, U) it equals the oracle's to 1e-12; on the local fields recovered
+    from any lam it vanishes to rounding (w = 1 lies in the local space)."""
+    orc, m, _ = case
+    topo = orc.topo
+    f, g, fo, go = _data(orc, m, orc.beta)
+    fhat = torch.empty(max(topo.n_trace, 1), dtype=torch.float64, device=DEV)
+    m.rhs(gpu(f), gpu(g), fhat)
+    lamD = orc.dirichlet_trace(go)
+    nl = int(topo.local_off[-1])
+    lam_h = inputs.random_vector(max(topo.n_trace, 1), seed=31)[:topo.n_trace]
+    qu_h = inputs.random_vector(nl, seed=32)
+    out = torch.empty(topo.n_macro, dtype=torch.float64, device=DEV)
+    lam = gpu(lam_h) if topo.n_trace else torch.zeros(1, dtype=torch.float64, device=DEV)
+    m.flux_balance(lam, gpu(qu_h), gpu(f), out)
+    U = [qu_h[topo.local_off[K]:topo.local_off[K + 1]] for K in range(topo.n_macro)]
+    ref = orc.flux_balance(U, lam_h, lamD, fo)
+    assert rel(host(out), ref) <= 1e-12
+    qu = torch.empty(nl, dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    m.flux_balance(lam, qu, gpu(f), out)
+    cons = host(out)
+    print(f"  max |conservation residual| {np.abs(cons).max():.2e} "
+          f"(terms ~{np.abs(ref).max():.2e})", flush=True)
+    assert np.abs(cons).max() <= 1e-11 * max(1.0, np.abs(ref).max())
+
+
 def test_solve_backward_error_with_oracle_operator():
     """GMRES to 1e-10 (preconditioned relative residual), then the true
     residual measured with the oracle's own operator."""
