@@ -68,7 +68,10 @@ def objective(orc: Oracle, U, u_obs):
 
 
 def gradient(orc: Oracle, f_nodal, g_bnd, u_obs):
-    """(J, dJ/dkappa [n_macro], dJ/da [2], Psi_U list, Psi_lam) by the adjoint."""
+    """(J, dJ/dkappa [n_macro], dJ/da [2], Psi_U list, Psi_lam) by the adjoint.
+    Unstabilised forms only: with SUPG the forms are not affine in kappa and a."""
+    if orc.supg:
+        raise ValueError("the adjoint gradient covers the forms without SUPG")
     topo = orc.topo
     Kmat, F, lamD = full_system(orc, f_nodal, g_bnd)
     X = spla.splu(Kmat).solve(F)

@@ -216,6 +216,41 @@ def lagrange_2d(nodes_xy, p, x, y):
     return mono @ Cinv, mdx @ Cinv, mdy @ Cinv
 
 
+def lagrange_2d_lap(nodes_xy, p, x, y):
+    """Laplacian at (x, y) of the P_p Lagrange basis on the given physical
+    nodes (the same monomial representation as lagrange_2d): [n_pts, n_nodes]."""
+    c = nodes_xy.mean(axis=0)
+    h = np.max(np.linalg.norm(nodes_xy - c, axis=1))
+    ex = _monomials(p)
+    X = (nodes_xy[:, 0] - c[0]) / h
+    Y = (nodes_xy[:, 1] - c[1]) / h
+    V = np.stack([X ** a * Y ** b for a, b in ex], axis=1)
+    Cinv = np.linalg.inv(V)
+    xs = (np.asarray(x) - c[0]) / h
+    ys = (np.asarray(y) - c[1]) / h
+    lap = np.stack([(a * (a - 1) * xs ** max(a - 2, 0) * ys ** b if a > 1 else 0 * xs)
+                    / h ** 2
+                    + (b * (b - 1) * xs ** a * ys ** max(b - 2, 0) if b > 1 else 0 * xs) / h ** 2
+                    for a, b in ex], axis=1)
+    return lap @ Cinv
+
+
+def supg_tau(h, a_norm, kappa):
+    """SUPG parameter of section 3.4 with the element Peclet number
+    Pe = |a| h / (2 kappa): tau = h / (2 |a|) (coth Pe - 1/Pe), the classical
+    optimal value for 1D advection-diffusion (the printed '+ 1/Pe' read as
+    '- 1/Pe'); zero without advection.  For small Pe the difference
+    coth Pe - 1/Pe is taken from its series Pe/3 - Pe^3/45 + 2 Pe^5/945."""
+    if a_norm == 0.0:
+        return 0.0
+    pe = a_norm * h / (2.0 * kappa)
+    if pe < 1e-2:
+        xi = pe / 3.0 - pe ** 3 / 45.0 + 2.0 * pe ** 5 / 945.0
+    else:
+        xi = 1.0 / np.tanh(pe) - 1.0 / pe
+    return h / (2.0 * a_norm) * xi
+
+
 def lagrange_1d(nodes_t, t):
     """Values at t of the 1D Lagrange basis on nodes_t: [n_pts, n_nodes]."""
     nodes_t = np.asarray(nodes_t, float)
@@ -251,7 +286,8 @@ def _locate(sub, lat_pts):
     return best
 
 
-def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int | None = None):
+def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int | None = None,
+                 supg: bool = False):
     p = topo.p
     m = int(topo.m[K])
     P = int(topo.P[K])
@@ -274,6 +310,16 @@ def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int
     M = np.zeros((Q, Q))
     Ex = np.zeros((Q, Q))
     Ey = np.zeros((Q, Q))
+    bx, by = float(beta[0]), float(beta[1])
+    # SUPG (section 3.4): tau_e (a.grad w, a.grad u - kappa lap u)_e summed over
+    # the sub-triangles e of K; all of them are congruent, h is their diameter
+    Ks = np.zeros((Q, Q))
+    tau_s = 0.0
+    if supg:
+        Xc = lat2xy(sub[0][0])
+        h = max(np.linalg.norm(Xc[1] - Xc[0]), np.linalg.norm(Xc[2] - Xc[1]),
+                np.linalg.norm(Xc[0] - Xc[2]))
+        tau_s = supg_tau(h, float(np.hypot(bx, by)), float(kappa))
     for corners, nodes in sub:
         ids = idx[nodes[:, 0], nodes[:, 1]]
         cxy = lat2xy(corners)
@@ -284,6 +330,10 @@ def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int
         M[np.ix_(ids, ids)] += phi.T @ (W * phi)
         Ex[np.ix_(ids, ids)] += dx.T @ (W * phi)     # (phi_j, d_x phi_i)
         Ey[np.ix_(ids, ids)] += dy.T @ (W * phi)
+        if tau_s != 0.0:
+            adv = bx * dx + by * dy                   # a.grad of each basis function
+            lap = lagrange_2d_lap(lat2xy(nodes), p, xq, yq)
+            Ks[np.ix_(ids, ids)] += tau_s * (adv.T @ (W * (adv - kappa * lap)))
 
     # boundary terms on the face partitions (level r_F >= r_K)
     ts, ws = segment_rule(nq)
@@ -327,10 +377,9 @@ def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int
             Gk[np.ix_(ids, lr)] += phi.T @ (Wb * mu)
         G.append(Gk)
 
-    bx, by = float(beta[0]), float(beta[1])
     Hx = -Ex + Mbx
     Hy = -Ey + Mby
-    Kuu = -(bx * Ex + by * Ey) + tau * Mb
+    Kuu = -(bx * Ex + by * Ey) + tau * Mb + Ks
     Z = np.zeros((Q, Q))
     Amat = np.block([[M, Z, -Ex], [Z, M, -Ey], [kappa * Hx, kappa * Hy, Kuu]])
     Bk, Ck = [], []
@@ -343,6 +392,10 @@ def macro_blocks(topo: Topology, K: int, kappa: float, beta, tau: float, nq: int
     out.A, out.B, out.C, out.G = Amat, Bk, Ck, G
     out.M, out.Mb, out.Ex, out.Ey = M, Mb, Ex, Ey
     out.normals, out.lengths = normals, lengths
+    # SUPG: the stabilisation block and the matrix of the source term
+    # tau (a.grad w, f_h)_K = tau (a_x E^x + a_y E^y) f_K (E^d_ij = (phi_j, d_d phi_i))
+    out.Ksupg, out.tau_supg = Ks, tau_s
+    out.Fsupg = tau_s * (bx * Ex + by * Ey)
     return out
 
 
@@ -375,8 +428,9 @@ class Oracle:
     paper); tau: LDG-H stabilisation, the same on every macro side.
     """
 
-    def __init__(self, xy, tri, r, p, kappa, beta, tau=1.0, nq=None, cache=True):
+    def __init__(self, xy, tri, r, p, kappa, beta, tau=1.0, nq=None, cache=True, supg=False):
         self.topo = Topology(xy, tri, r, p)
+        self.supg = bool(supg)
         self.kappa = np.broadcast_to(np.asarray(kappa, float), (self.topo.n_macro,)).copy()
         self.beta = np.asarray(beta, float).reshape(2)
         self.tau = float(tau)
@@ -387,7 +441,8 @@ class Oracle:
     def blocks(self, K):
         if self._cache is not None and K in self._cache:
             return self._cache[K]
-        b = macro_blocks(self.topo, K, self.kappa[K], self.beta, self.tau, self.nq)
+        b = macro_blocks(self.topo, K, self.kappa[K], self.beta, self.tau, self.nq,
+                         supg=self.supg)
         if self._cache is not None:
             self._cache[K] = b
         return b
@@ -441,14 +496,15 @@ class Oracle:
         return lamD
 
     def local_rhs(self, K, f_nodal, lamD):
-        """R_K: (f_h, w)_K on the w rows minus the Dirichlet columns of B_K."""
+        """R_K: (f_h, w)_K (plus the SUPG source term tau (a.grad w, f_h)_K when
+        stabilised) on the w rows minus the Dirichlet columns of B_K."""
         topo = self.topo
         b = self.blocks(K)
         Q = int(topo.Q[K])
         fo = topo.node_off[K]
         fK = np.asarray(f_nodal[fo:fo + Q], float)
         R = np.zeros(3 * Q)
-        R[2 * Q:] = b.M @ fK
+        R[2 * Q:] = b.M @ fK + b.Fsupg @ fK
         for k in range(3):
             f = int(topo.macro_face[K, k])
             if not topo.interior[f]:

@@ -379,3 +379,91 @@ def test_oracle_rejects_clockwise():
     xy, tri = inputs.structured_mesh(1)
     with pytest.raises(ValueError):
         hdg.Topology(xy, tri[:, ::-1], 1, 1)
+
+
+# ---------------------------------------------------------------------------
+# SUPG inside the macro-elements (section 3.4)
+# ---------------------------------------------------------------------------
+def test_supg_tau_limits():
+    """tau = h/(2|a|) (coth Pe - 1/Pe) tends to h/(2|a|) for Pe -> infinity and
+    to h^2/(12 kappa) for Pe -> 0; it is continuous where the small-Pe series
+    takes over; no advection, no stabilisation."""
+    h, a = 0.1, 2.0
+    # Pe = 1e11: tau = h/(2|a|) (1 - 1/Pe) to rounding
+    assert abs(hdg.supg_tau(h, a, 1e-12) - h / (2 * a)) <= 1e-10 * h / a
+    for kappa in (1e3, 1e5):   # Pe = 1e-4, 1e-6: relative correction Pe^2 / 15
+        t = hdg.supg_tau(h, a, kappa)
+        assert abs(t - h * h / (12 * kappa)) <= 1e-8 * t
+    # tau kappa is smooth in kappa; compare it on both sides of Pe = 1e-2
+    k1, k2 = a * h / (2 * 1e-2) * (1 + 1e-9), a * h / (2 * 1e-2) * (1 - 1e-9)
+    t1, t2 = hdg.supg_tau(h, a, k1) * k1, hdg.supg_tau(h, a, k2) * k2
+    assert abs(t1 - t2) <= 1e-10 * t1
+    assert hdg.supg_tau(h, 0.0, 1.0) == 0.0
+
+
+def test_supg_block_p1_single_triangle():
+    """p = 1 on an unrefined macro: the basis gradients are constant and the
+    Laplacians vanish, so the block is tau |T| (a.grad lam_i)(a.grad lam_j) with
+    the barycentric gradients grad lam_i = (y_j - y_k, x_k - x_j) / (2|T|),
+    (i, j, k) cyclic; h is the longest edge."""
+    X = np.array([[0.1, 0.2], [1.3, 0.1], [0.4, 1.1]])
+    beta, kappa = np.array([1.5, -0.7]), 0.05
+    topo = hdg.Topology(X, np.array([[0, 1, 2]]), 0, 1)
+    bl = hdg.macro_blocks(topo, 0, kappa, beta, 1.0, supg=True)
+    area = 0.5 * ((X[1, 0] - X[0, 0]) * (X[2, 1] - X[0, 1]) - (X[2, 0] - X[0, 0]) * (X[1, 1] - X[0, 1]))
+    grads = np.array([[X[(i + 1) % 3, 1] - X[(i + 2) % 3, 1], X[(i + 2) % 3, 0] - X[(i + 1) % 3, 0]]
+                      for i in range(3)]) / (2 * area)
+    h = max(np.linalg.norm(X[i] - X[(i + 1) % 3]) for i in range(3))
+    an = np.linalg.norm(beta)
+    pe = an * h / (2 * kappa)
+    tau = h / (2 * an) * (1 / np.tanh(pe) - 1 / pe)
+    adv = grads @ beta
+    assert np.allclose(bl.Ksupg, tau * area * np.outer(adv, adv), rtol=1e-12, atol=1e-14)
+    assert abs(bl.tau_supg - tau) <= 1e-14 * tau
+
+
+@pytest.mark.parametrize("p,r", [(2, 1), (3, 1)])
+def test_supg_block_annihilates_constants(p, r):
+    """a.grad 1 = 0 and lap 1 = 0: the stabilisation block and the source term
+    vanish for u = 1 and for w = 1 (so macro conservation is unchanged)."""
+    xy, tri = inputs.structured_mesh(1, jitter=0.0, seed=0)
+    topo = hdg.Topology(xy, tri, r, p)
+    bl = hdg.macro_blocks(topo, 0, 0.01, (1.0, 0.6), 1.0, supg=True)
+    one = np.ones(int(topo.Q[0]))
+    scale = np.abs(bl.Ksupg).max()
+    assert scale > 0
+    assert np.abs(bl.Ksupg @ one).max() <= 1e-12 * scale
+    assert np.abs(one @ bl.Ksupg).max() <= 1e-12 * scale
+    assert np.abs(one @ bl.Fsupg).max() <= 1e-12 * np.abs(bl.Fsupg).max()
+
+
+@pytest.mark.parametrize("p,r", [(2, 1), (3, 1), (2, 2)])
+def test_supg_polynomial_reproduction(p, r):
+    """SUPG is consistent: for u in P_p the strong residual a.grad u -
+    kappa lap u - f vanishes pointwise (f is exact in W(K)), so the stabilised
+    method still returns u to rounding, with the Laplacian and source terms
+    active (p >= 2); and the macro flux balance still vanishes."""
+    xy, tri = inputs.structured_mesh(2, jitter=0.1, seed=2)
+    ex = inputs.polynomial(p, 0.02, (1.0, -0.5), seed=p + 10 * r)
+    o = hdg.Oracle(xy, tri, r, p, 0.02, (1.0, -0.5), 1.0, supg=True)
+    assert o.blocks(0).tau_supg > 0
+    f, g = o.sample(ex)
+    lam, U, lamD = o.solve(f, g)
+    eu, eq = o.l2_errors(U, ex)
+    assert eu < 1e-11 and eq < 1e-9
+    assert np.abs(o.flux_balance(U, lam, lamD, f)).max() < 1e-12
+
+
+def test_supg_changes_the_advection_dominated_solution():
+    """With kappa small the stabilisation is active: the stabilised and plain
+    solutions of a non-polynomial problem differ, and the stabilised one has
+    no larger interior overshoot on a boundary-layer problem."""
+    xy, tri = inputs.structured_mesh(2)
+    ex = inputs.exp_sin(1e-3, (1.0, 0.5))
+    o0 = hdg.Oracle(xy, tri, 2, 2, 1e-3, (1.0, 0.5), 1.0)
+    o1 = hdg.Oracle(xy, tri, 2, 2, 1e-3, (1.0, 0.5), 1.0, supg=True)
+    f, g = o0.sample(ex)
+    _, U0, _ = o0.solve(f, g)
+    _, U1, _ = o1.solve(f, g)
+    d = max(np.abs(a - b).max() for a, b in zip(U0, U1))
+    assert d > 1e-6
