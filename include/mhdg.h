@@ -363,6 +363,18 @@ typedef struct {
  * Errors: STATE, INVALID_ARG (more than MHDG_MAX_CLASSES classes), SINGULAR, HIP. */
 mhdg_status mhdg_autotune(mhdg_mesh* mesh, int32_t flags, mhdg_tune_report* out, void* stream);
 
+/* SUPG stabilisation inside the macro-elements (section 3.4): with on = 1
+ * the local forms get tau_e (a.grad w, a.grad u - kappa lap u)_e on every
+ * sub-triangle e and the source tau_e (a.grad w, f_h)_e, with h the
+ * sub-triangle diameter, Pe = |a| h / (2 kappa) and tau = h / (2|a|)
+ * (coth Pe - 1/Pe) (the classical value; zero without advection).  The
+ * local blocks change, the trace system keeps its form; conservation per
+ * macro is unaffected (a.grad 1 = 0).  on = 0 restores the plain forms.
+ * Either way the factors are invalidated (call factor_local again).  Every
+ * precision and form supports it except mhdg_adjoint (STATE: the forms are no
+ * longer affine in kappa and a).  Errors: INVALID_ARG if on is not 0 or 1. */
+mhdg_status mhdg_set_supg(mhdg_mesh* mesh, int32_t on);
+
 /* Fix the variants of the size class with local size N (0 = the default
  * rule: LU variant 1 for N <= 256, else 2; solve variant 1 for N <= 1024,
  * else 2).  Takes effect at the next factor_local (LU) or apply (solves).

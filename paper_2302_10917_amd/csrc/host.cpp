@@ -53,6 +53,7 @@ struct mhdg_mesh {
   std::vector<double> qtmpl;      // built on first use of MHDG_QELIM
   // factor state
   bool factored = false, have_rhs = false;
+  bool supg = false;               // SUPG inside the macros (mhdg_set_supg)
   // folded operators T_K (mhdg_fold_operator): valid until the next factor_local
   bool folded = false;
   int64_t* fold_toff = nullptr;   // device: element offset of T_K
@@ -229,6 +230,64 @@ static void silvester(int p, int n, double z, double& val, double& der) {
   }
 }
 
+// R_n with its first and second derivatives.
+static void silvester2(int p, int n, double z, double& val, double& der, double& dd) {
+  val = 1.0;
+  der = 0.0;
+  dd = 0.0;
+  for (int a = 0; a < n; ++a) {
+    const double f = (p * z - a) / (a + 1), fp = double(p) / (a + 1);
+    dd = dd * f + 2.0 * der * fp;
+    der = der * f + val * fp;
+    val *= f;
+  }
+}
+
+// Reference P_p triangle matrices of the SUPG forms (same nodes and rule as
+// reference_triangle; the integrands have degree <= 2p - 2):
+// St[2k + l][i][j] = (d_k psi_i, d_l psi_j) and Tt[3k + c][i][j] =
+// (d_k psi_i, D_c psi_j) with D_0 = d_xi^2, D_1 = d_xi d_eta, D_2 = d_eta^2.
+void reference_triangle_supg(int p, std::vector<double> St[4], std::vector<double> Tt[6]) {
+  std::vector<std::pair<int, int>> loc;
+  for (int t = 0; t <= p; ++t)
+    for (int s = 0; s <= p - t; ++s) loc.push_back({s, t});
+  const int n = (int)loc.size();
+  std::vector<double> t01, w01;
+  gauss_legendre01(p + 2, t01, w01);
+  for (int k = 0; k < 4; ++k) St[k].assign(n * n, 0.0);
+  for (int k = 0; k < 6; ++k) Tt[k].assign(n * n, 0.0);
+  std::vector<double> d[2], dd[3];
+  for (auto& v : d) v.resize(n);
+  for (auto& v : dd) v.resize(n);
+  for (size_t qa = 0; qa < t01.size(); ++qa)
+    for (size_t qb = 0; qb < t01.size(); ++qb) {
+      const double a = 2 * t01[qa] - 1, b = 2 * t01[qb] - 1;
+      const double xi = (1 + a) * (1 - b) / 4, eta = (1 + b) / 2;
+      const double w = 4 * w01[qa] * w01[qb] * (1 - b) / 8;
+      const double l1 = 1 - xi - eta;
+      for (int m = 0; m < n; ++m) {
+        const int j = loc[m].first, k = loc[m].second, i = p - j - k;
+        double r1, d1, e1, r2, d2, e2, r3, d3, e3;
+        silvester2(p, i, l1, r1, d1, e1);
+        silvester2(p, j, xi, r2, d2, e2);
+        silvester2(p, k, eta, r3, d3, e3);
+        // d/dxi = d/dl2 - d/dl1, d/deta = d/dl3 - d/dl1
+        d[0][m] = r1 * d2 * r3 - d1 * r2 * r3;
+        d[1][m] = r1 * r2 * d3 - d1 * r2 * r3;
+        dd[0][m] = r1 * e2 * r3 - 2 * d1 * d2 * r3 + e1 * r2 * r3;
+        dd[1][m] = r1 * d2 * d3 - d1 * d2 * r3 - d1 * r2 * d3 + e1 * r2 * r3;
+        dd[2][m] = r1 * r2 * e3 - 2 * d1 * r2 * d3 + e1 * r2 * r3;
+      }
+      for (int ii = 0; ii < n; ++ii)
+        for (int jj = 0; jj < n; ++jj) {
+          for (int k = 0; k < 2; ++k)
+            for (int l = 0; l < 2; ++l) St[2 * k + l][ii * n + jj] += w * d[k][ii] * d[l][jj];
+          for (int k = 0; k < 2; ++k)
+            for (int c = 0; c < 3; ++c) Tt[3 * k + c][ii * n + jj] += w * d[k][ii] * dd[c][jj];
+        }
+    }
+}
+
 // Reference P_p triangle matrices on {xi, eta >= 0, xi + eta <= 1} with
 // equispaced nodes (s/p, t/p), t outer: mass Mt[i][j] = (psi_j, psi_i) and
 // Et[k][i][j] = (psi_j, d_k psi_i).  Integrated exactly (degree 2p) by a
@@ -325,6 +384,7 @@ static void build_templates(mhdg_mesh* M) {
     const int m = 1 << r, P = m * p, Q = (P + 1) * (P + 2) / 2;
     L.P = P; L.Q = Q; L.N = 3 * Q;
     for (int k = 0; k <= kMaxLevel; ++k) L.T1[k] = -1;
+    L.supg = -1;
     if (!present[r]) continue;
     auto idx = [&](int i, int j) { return j * (P + 1) - j * (j - 1) / 2 + i; };
     L.Mhat = take(size_t(Q) * Q);
@@ -459,6 +519,56 @@ static int64_t qelim_factor_elems(const std::vector<MacroInfo>& macros) {
   }
   return fo;
 }
+// SUPG templates per present level, appended to the template blob: the
+// reference-macro integrals of section 3.4's stabilisation, assembled from the
+// sub-triangle matrices (up sub-triangles x = (a + xi)/m, down x = (a+1 - xi)/m,
+// so a first derivative scales by +-m, a second by m^2, the measure by 1/m^2).
+static void build_supg_templates(mhdg_mesh* M) {
+  const int p = M->p;
+  std::vector<double> St[4], Tt[6];
+  reference_triangle_supg(p, St, Tt);
+  const int nl = (p + 1) * (p + 2) / 2;
+  std::vector<std::pair<int, int>> loc;
+  for (int t = 0; t <= p; ++t)
+    for (int s = 0; s <= p - t; ++s) loc.push_back({s, t});
+  std::vector<double>& B = M->tmpl;
+  for (int r = 0; r <= kMaxLevel; ++r) {
+    LevelTemplates& L = M->T.lev[r];
+    if (!L.present || L.supg >= 0) continue;
+    const int m = 1 << r, P = m * p, Q = (P + 1) * (P + 2) / 2;
+    const size_t QQ = size_t(Q) * Q;
+    const size_t o = B.size();
+    B.resize(o + ((9 * QQ + 31) / 32) * 32, 0.0);
+    L.supg = (int64_t)o;
+    double* S = &B[o];
+    auto idx = [&](int i, int j) { return j * (P + 1) - j * (j - 1) / 2 + i; };
+    for (int pass = 0; pass < 2; ++pass) {
+      const int bmax = pass == 0 ? m : m - 1;
+      const double sg = pass == 0 ? 1.0 : -1.0;
+      for (int b = 0; b < bmax; ++b)
+        for (int a = 0; a < bmax - b; ++a) {
+          std::vector<int> g(nl);
+          for (int n = 0; n < nl; ++n) {
+            const int s = loc[n].first, t = loc[n].second;
+            g[n] = pass == 0 ? idx(a * p + s, b * p + t) : idx((a + 1) * p - s, (b + 1) * p - t);
+          }
+          for (int i = 0; i < nl; ++i)
+            for (int j = 0; j < nl; ++j) {
+              const size_t e = size_t(g[i]) * Q + g[j];
+              const int ij = i * nl + j;
+              S[e] += St[0][ij];
+              S[QQ + e] += St[3][ij];
+              S[2 * QQ + e] += St[1][ij] + St[2][ij];
+              for (int c = 0; c < 3; ++c) {
+                S[(3 + c) * QQ + e] += sg * m * Tt[c][ij];
+                S[(6 + c) * QQ + e] += sg * m * Tt[3 + c][ij];
+              }
+            }
+        }
+    }
+  }
+}
+
 static void qelim_offsets(std::vector<MacroInfo>& macros) {
   int64_t fo = 0, po = 0;
   for (auto& mi : macros) {
@@ -1744,6 +1854,25 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* st
   return MHDG_OK;
 }
 
+mhdg_status mhdg_set_supg(mhdg_mesh* M, int32_t on) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (on != 0 && on != 1) return fail(M, MHDG_ERR_INVALID_ARG, "set_supg: on must be 0 or 1");
+  if (on) build_supg_templates(M);
+  auto mark = [&](std::vector<MacroInfo>& v) {
+    for (auto& mi : v)
+      mi.hsupg = on ? std::max(mi.len[0], std::max(mi.len[1], mi.len[2])) / double(1 << mi.level)
+                    : 0.0;
+  };
+  mark(M->macros);
+  mark(M->one.macros);
+  M->supg = on != 0;
+  M->factored = false;
+  M->have_rhs = false;
+  M->folded = false;
+  M->drop_graphs();
+  return MHDG_OK;
+}
+
 mhdg_status mhdg_set_kernel_variant(mhdg_mesh* M, int32_t N, int32_t lu_variant,
                                     int32_t solve_variant) {
   if (!M) return MHDG_ERR_INVALID_ARG;
@@ -2348,6 +2477,9 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
   if (!o || !qu || !dJ_dU || !psi_U || !dJ_dkappa || !dJ_dbeta || !ws || o->restart < 1 ||
       (M->n_trace > 0 && (!lam || !psi_lam)))
     return fail(M, MHDG_ERR_INVALID_ARG, "adjoint: bad options or null pointer");
+  if (M->supg)
+    return fail(M, MHDG_ERR_STATE,
+                "adjoint: the SUPG forms are not affine in kappa and a (call mhdg_set_supg(mesh, 0))");
   if (!M->factored || !M->have_rhs)
     return fail(M, MHDG_ERR_STATE, "adjoint: call factor_local and solve first");
   if (M->precision != MHDG_FP64)

@@ -19,6 +19,7 @@ struct MacroInfo {
   double nrm[6];      // outward unit normals (nx, ny) per edge
   double kappa;       // filled on the device from the caller's kappa array
   double bx, by;      // advection a of this macro's coefficient instance
+  double hsupg;       // SUPG: sub-triangle diameter, 0 when the forms are not stabilised
   int64_t fac_off;    // element offset of this macro's factor block
   int64_t loc_off;    // offset into n_local vectors
   int64_t node_off;   // offset into n_nodes vectors
@@ -67,6 +68,9 @@ struct LevelTemplates {
   int64_t bnd_index;        // int32 [Q]: position b in the macro boundary loop (edge k,
                             // position s < P -> kP + s), or -1 for nodes off the boundary
   int64_t T1[kMaxLevel + 1];// (P+1) x (P_F+1): int phi_s mu_l over [0,1], face level F >= r
+  int64_t supg;             // SUPG: 9 Q x Q blocks (reference macro), or -1: (d_k phi_i, d_l phi_j)
+                            // for kl = 00, 11, then 01 + 10; (d_k phi_i, D_c phi_j) for
+                            // k = 0, 1 and D_c = d_00, d_01, d_11
   int32_t present, Q, P, N;
 };
 

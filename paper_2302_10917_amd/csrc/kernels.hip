@@ -31,13 +31,29 @@ __device__ __forceinline__ const int32_t* ints(const double* base, int64_t off) 
 }
 
 // ------------------------------------------------------------------ assembly
+// SUPG parameter of section 3.4 for a macro's sub-triangles (all congruent,
+// diameter h): Pe = |a| h / (2 kappa), tau = h / (2|a|) (coth Pe - 1/Pe), with
+// the series Pe/3 - Pe^3/45 + 2 Pe^5/945 of the bracket for small Pe; zero when
+// the forms are not stabilised or there is no advection.
+__device__ __forceinline__ double supg_tau(const MacroInfo& mi) {
+  const double h = mi.hsupg, an = sqrt(mi.bx * mi.bx + mi.by * mi.by);
+  if (!(h > 0.0) || an == 0.0) return 0.0;
+  const double pe = an * h / (2.0 * mi.kappa);
+  const double xi = pe < 1e-2 ? pe * (1.0 / 3.0 - pe * pe * (1.0 / 45.0 - pe * pe * (2.0 / 945.0)))
+                              : 1.0 / tanh(pe) - 1.0 / pe;
+  return h / (2.0 * an) * xi;
+}
+
 struct EntryCtx {
   const double* Mh;
   const double* E0;
   const double* E1;
   const double* M1;
   const int32_t* epos;
+  const double* Sp;   // SUPG templates (null when not stabilised)
   double G[4], dJ, len[3], kappa, bx, by, tau;
+  // SUPG: tau_supg, a.grad = al0 d_xi + al1 d_eta, lap = sum g_bc d_b d_c
+  double ts, al0, al1, g00, g01, g11;
   int Q, P;
 };
 
@@ -59,7 +75,25 @@ __device__ __forceinline__ EntryCtx make_ctx(const MacroInfo& mi, const double* 
   c.tau = tau;
   c.Q = mi.Q;
   c.P = mi.P;
+  c.ts = supg_tau(mi);
+  c.Sp = c.ts != 0.0 ? tm + L.supg : nullptr;
+  c.al0 = mi.G[0] * mi.bx + mi.G[1] * mi.by;
+  c.al1 = mi.G[2] * mi.bx + mi.G[3] * mi.by;
+  c.g00 = mi.G[0] * mi.G[0] + mi.G[1] * mi.G[1];
+  c.g01 = mi.G[0] * mi.G[2] + mi.G[1] * mi.G[3];
+  c.g11 = mi.G[2] * mi.G[2] + mi.G[3] * mi.G[3];
   return c;
+}
+
+// SUPG block entry tau sum_e (a.grad phi_i, a.grad phi_j - kappa lap phi_j)_e
+// = tau |det J| (sum_kl al_k al_l S_kl - kappa sum_k al_k sum_c g_c T_kc)_ij
+__device__ __forceinline__ double supg_entry(const EntryCtx& c, int i, int j) {
+  const size_t QQ = size_t(c.Q) * c.Q, o = size_t(i) * c.Q + j;
+  const double* S = c.Sp;
+  const double s = c.al0 * c.al0 * S[o] + c.al1 * c.al1 * S[QQ + o] + c.al0 * c.al1 * S[2 * QQ + o];
+  const double t0 = c.g00 * S[3 * QQ + o] + 2.0 * c.g01 * S[4 * QQ + o] + c.g11 * S[5 * QQ + o];
+  const double t1 = c.g00 * S[6 * QQ + o] + 2.0 * c.g01 * S[7 * QQ + o] + c.g11 * S[8 * QQ + o];
+  return c.ts * c.dJ * (s - c.kappa * (c.al0 * t0 + c.al1 * t1));
 }
 
 // E^d_ij = (phi_j, d_d phi_i)_K = |det J| sum_k G[k][d] Ehat^k_ij
@@ -81,7 +115,7 @@ __device__ __forceinline__ double Mb(const EntryCtx& c, int i, int j) {
 
 // Entry (r, c) of A_K = [[M, 0, -E^x], [0, M, -E^y], [kappa H^x, kappa H^y, K]]
 // with H^d = (E^d)^T (integration by parts inside the continuous macro space)
-// and K = -(a_x E^x + a_y E^y) + tau Mb.
+// and K = -(a_x E^x + a_y E^y) + tau Mb (+ the SUPG block when stabilised).
 __device__ double a_entry(const EntryCtx& c, int r, int col) {
   const int Q = c.Q;
   const int rb = r / Q, i = r - rb * Q, cb = col / Q, j = col - cb * Q;
@@ -92,7 +126,9 @@ __device__ double a_entry(const EntryCtx& c, int r, int col) {
     case 5: return -Ed(c, 1, i, j);
     case 6: return c.kappa * Ed(c, 0, j, i);
     case 7: return c.kappa * Ed(c, 1, j, i);
-    default: return -(c.bx * Ed(c, 0, i, j) + c.by * Ed(c, 1, i, j)) + c.tau * Mb(c, i, j);
+    default:
+      return -(c.bx * Ed(c, 0, i, j) + c.by * Ed(c, 1, i, j)) + c.tau * Mb(c, i, j) +
+             (c.Sp ? supg_entry(c, i, j) : 0.0);
   }
 }
 
@@ -498,11 +534,20 @@ __global__ __launch_bounds__(64) void local_rhs_kernel(const MacroInfo* __restri
   const int N = mi.N, Q = mi.Q;
   const double* Mh = tm + Tp.lev[mi.level].Mhat;
   const double* fK = f + mi.node_off;
+  // SUPG source tau (a.grad w, f_h)_K = tau |det J| (al0 Ehat^0 + al1 Ehat^1) f_K
+  const double ts = supg_tau(mi);
+  const double* E0 = tm + Tp.lev[mi.level].E0;
+  const double* E1 = tm + Tp.lev[mi.level].E1;
+  const double al0 = ts * (mi.G[0] * mi.bx + mi.G[1] * mi.by);
+  const double al1 = ts * (mi.G[2] * mi.bx + mi.G[3] * mi.by);
   for (int i = threadIdx.x; i < N; i += 64) {
     double v = 0.0;
     if (i >= 2 * Q) {
       const int ii = i - 2 * Q;
       for (int j = 0; j < Q; ++j) v += Mh[size_t(ii) * Q + j] * fK[j];
+      if (ts != 0.0)
+        for (int j = 0; j < Q; ++j)
+          v += (al0 * E0[size_t(ii) * Q + j] + al1 * E1[size_t(ii) * Q + j]) * fK[j];
       v *= mi.dJ;
     }
     x[i] = v;
@@ -626,6 +671,7 @@ __global__ __launch_bounds__(256) void local_residual_kernel(
   const int32_t* en = ints(tm, L.edge_node);
   const int32_t* bidx = ints(tm, L.bnd_index);
   const double dJ = mi.dJ, g0 = mi.G[0], g1 = mi.G[1], g2 = mi.G[2], g3 = mi.G[3];
+  const EntryCtx sc = make_ctx(mi, tm, Tp, tau);
   for (int i = threadIdx.x; i < Q; i += blockDim.x) {
     double mqx = 0, mqy = 0, e0u = 0, e1u = 0, e0x = 0, e1x = 0, e0y = 0, e1y = 0;
     for (int j = 0; j < Q; ++j) {
@@ -656,6 +702,11 @@ __global__ __launch_bounds__(256) void local_residual_kernel(
     av[0] = dJ * mqx - Exu;
     av[1] = dJ * mqy - Eyu;
     av[2] = mi.kappa * (ExTqx + EyTqy) - (mi.bx * Exu + mi.by * Eyu) + tau * mbu;
+    if (sc.Sp) {   // SUPG block row i (row-major templates)
+      double su = 0.0;
+      for (int j = 0; j < Q; ++j) su += supg_entry(sc, i, j) * u[2 * Q + j];
+      av[2] += su;
+    }
     const int b = bidx[i];
     for (int f = 0; f < 3; ++f) {
       double r = R[mi.loc_off + f * Q + i] - av[f];

@@ -28,7 +28,7 @@ ABI_SYMBOLS = [
     "mhdg_status_string", "mhdg_profile", "mhdg_mass_apply", "mhdg_adjoint",
     "mhdg_set_instances", "mhdg_factor_local_batched", "mhdg_autotune",
     "mhdg_set_kernel_variant", "mhdg_fold_operator", "mhdg_apply_many_ws_bytes",
-    "mhdg_apply_trace_operator_many", "mhdg_flux_balance",
+    "mhdg_apply_trace_operator_many", "mhdg_flux_balance", "mhdg_set_supg",
 ]
 MHDG_TUNE_LU, MHDG_TUNE_SOLVE = 1, 2
 MAX_CLASSES = 8
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH):
         "mhdg_set_instances": [P, I32],
         "mhdg_autotune": [P, I32, ctypes.POINTER(TuneReport), P],
         "mhdg_set_kernel_variant": [P, I32, I32, I32],
+        "mhdg_set_supg": [P, I32],
         "mhdg_fold_operator": [P, P, SZ, P],
         "mhdg_local_matrix": [P, I64, P, P],
         "mhdg_apply_trace_operator": [P, P, P, I32, P],
@@ -353,6 +354,11 @@ class MacroMesh:
             self.fold_ws = torch.empty(max(s.fold_ws_bytes, 1), dtype=torch.uint8, device="cuda")
         self._check(self._lib.mhdg_fold_operator(self.h, _ptr(self.fold_ws), self.fold_ws.numel(),
                                                  _stream(stream)), "fold_operator")
+
+    def set_supg(self, on: bool):
+        """SUPG stabilisation inside the macros (section 3.4) on or off; the
+        factors must be computed again afterwards."""
+        self._check(self._lib.mhdg_set_supg(self.h, 1 if on else 0), "set_supg")
 
     def set_kernel_variant(self, N, lu_variant=0, solve_variant=0):
         self._check(self._lib.mhdg_set_kernel_variant(self.h, int(N), int(lu_variant),

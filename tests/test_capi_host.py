@@ -125,6 +125,8 @@ def test_calls_before_factor_are_rejected():
     assert st == 7
     assert lib.mhdg_apply_trace_operator_many(m.h, 2, None, None, 0, None, 0, None) == 7
     assert lib.mhdg_flux_balance(m.h, None, None, None, None, None) == 7
+    assert lib.mhdg_set_supg(m.h, 2) == 1
+    assert lib.mhdg_set_supg(m.h, 1) == 0 and lib.mhdg_set_supg(m.h, 0) == 0
     assert lib.mhdg_apply_trace_operator_many(m.h, -1, None, None, 0, None, 0, None) == 1
     one = lib.mhdg_apply_many_ws_bytes(m.h, 1)
     assert one > 0 and lib.mhdg_apply_many_ws_bytes(m.h, 3) == 3 * one

@@ -1,0 +1,211 @@
+"""GPU parity of the SUPG-stabilised forms (section 3.4) against the oracle.
+
+mhdg_set_supg adds tau_e (a.grad w, a.grad u - kappa lap u)_e per sub-triangle
+to the local blocks and tau_e (a.grad w, f_h)_e to the source.  The GPU builds
+the block from reference-macro templates in the macro's reference coordinates;
+the oracle integrates it sub-triangle by sub-triangle in physical coordinates
+with its own Lagrange basis.  Bars as for the plain forms: the assembled
+block to 1e-12 of its largest entry, applies, right-hand sides, solves and
+recoveries to 1e-10, for FP64, FP32 with FP64 refinement (whose matrix-free
+FP64 residual carries the SUPG block), the flux-eliminated and the folded
+forms.  The small diffusion (kappa = 1e-3 .. 1e-2) makes the sub-triangle
+Peclet numbers 1.6 .. 30, where the stabilisation is strong.
+"""
+import numpy as np
+import pytest
+
+from oracle import hdg
+from paper_2302_10917_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_10917_amd import mhdg  # noqa: E402
+
+DEV = "cuda"
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    # name: (n, jitter, levels, p, kappa, beta)
+    "mixed_p2": (3, 0.1, "mixed", 2, 2e-3, (1.0, -0.6)),
+    "r2_p3": (2, 0.05, 2, 3, 1e-2, (0.8, 0.5)),
+    "r1_p4": (2, 0.0, 1, 4, 1e-3, (-1.0, 0.3)),
+    "two_macro_r4_p3": (1, 0.0, 4, 3, 5e-3, (0.5, 1.0)),
+}
+
+
+def build(name, precision=mhdg.MHDG_FP64):
+    n, jit, lev, p, kappa, beta = CASES[name]
+    xy, tri = inputs.structured_mesh(n, jitter=jit, seed=7)
+    r = inputs.random_levels(len(tri), (0, 1, 2), seed=3) if lev == "mixed" else lev
+    kap = kappa * inputs.lognormal_kappa(len(tri), 0.3, seed=9)
+    orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0, supg=True)
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    m.set_supg(True)
+    m.factor_local(gpu(kap), beta, 1.0, precision=precision)
+    return orc, m, kappa, beta
+
+
+def data(orc, m, kappa, beta):
+    node, bnd = m.sample_points()
+    ex = inputs.exp_sin(kappa, beta)
+    fo, go = orc.sample(ex)
+    return gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1])), fo, go
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    print(f"\n[supg {request.param}]", flush=True)
+    return build(request.param)
+
+
+def test_supg_assembly_matches_oracle(case):
+    orc, m, _, _ = case
+    for e in sorted({0, orc.topo.n_macro // 2, orc.topo.n_macro - 1}):
+        b = orc.blocks(e)
+        assert b.tau_supg > 0
+        N = int(orc.topo.N_e[e])
+        out = torch.empty(N * N, dtype=torch.float64, device=DEV)
+        m.local_matrix(e, out)
+        A = host(out).reshape(N, N)
+        assert np.abs(A - b.A).max() <= 1e-12 * np.abs(b.A).max(), e
+        # the stabilisation is a visible part of the u-u block
+        Q = N // 3
+        assert np.abs(b.Ksupg).max() > 1e-3 * np.abs(b.A[2 * Q:, 2 * Q:]).max()
+
+
+def test_supg_apply_rhs_solve_recover_match_oracle(case):
+    orc, m, kappa, beta = case
+    topo = orc.topo
+    n = topo.n_trace
+    lam_r = inputs.random_vector(n, seed=1)
+    out = torch.empty(n, dtype=torch.float64, device=DEV)
+    for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
+        m.apply_trace_operator(gpu(lam_r), out, flags)
+        assert rel(host(out), orc.apply(lam_r, precondition=prec)) <= 1e-10
+    f, g, fo, go = data(orc, m, kappa, beta)
+    S, fhat, _ = orc.condensed(fo, go)
+    m.rhs(f, g, out)
+    assert rel(host(out), fhat) <= 1e-10
+    lam_o, U_o, lamD = orc.solve(fo, go)
+    lam = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=20000)
+    assert info.status == 0
+    assert rel(host(lam), lam_o) <= 1e-10
+    qu = torch.empty(int(topo.local_off[-1]), dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    cons = torch.empty(topo.n_macro, dtype=torch.float64, device=DEV)
+    m.flux_balance(lam, qu, f, cons)
+    assert np.abs(host(cons)).max() <= 1e-11
+
+
+def test_supg_fp32_refined_solve_matches_oracle():
+    """FP32 factors of the stabilised blocks; the refinement's FP64 residual
+    is matrix-free and carries the SUPG block, so the result is the FP64
+    stabilised solution."""
+    orc, m, kappa, beta = build("r2_p3", precision=mhdg.MHDG_FP32)
+    topo = orc.topo
+    f, g, fo, go = data(orc, m, kappa, beta)
+    lam_o, U_o, _ = orc.solve(fo, go)
+    lam = torch.zeros(topo.n_trace, dtype=torch.float64, device=DEV)
+    info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=20000, inner_rtol=1e-4)
+    print(f"  outer={info.outer_iterations} inner={info.iterations}", flush=True)
+    assert info.status == 0 and info.outer_iterations >= 2
+    assert rel(host(lam), lam_o) <= 1e-10
+    qu = torch.empty(int(topo.local_off[-1]), dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["mixed_p2", "r2_p3"])
+def test_supg_flux_eliminated_and_folded_match_oracle(name):
+    orc, m, kappa, beta = build(name, precision=mhdg.MHDG_QELIM)
+    topo = orc.topo
+    n = topo.n_trace
+    lam_r = inputs.random_vector(n, seed=2)
+    out = torch.empty(n, dtype=torch.float64, device=DEV)
+    ref = orc.apply(lam_r, precondition=True)
+    m.apply_trace_operator(gpu(lam_r), out, mhdg.MHDG_PRECONDITION)
+    assert rel(host(out), ref) <= 1e-10
+    m.fold_operator()
+    m.apply_trace_operator(gpu(lam_r), out, mhdg.MHDG_PRECONDITION | mhdg.MHDG_FOLDED)
+    assert rel(host(out), ref) <= 1e-10
+    f, g, fo, go = data(orc, m, kappa, beta)
+    lam_o, U_o, _ = orc.solve(fo, go)
+    lam = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=20000, folded=True)
+    assert info.status == 0
+    assert rel(host(lam), lam_o) <= 1e-10
+    qu = torch.empty(int(topo.local_off[-1]), dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+
+
+def test_supg_off_restores_the_plain_forms():
+    orc, m, kappa, beta = build("r2_p3")
+    n, lib = orc.topo.n_trace, m._lib
+    plain = hdg.Oracle(orc.topo.xy, orc.topo.tri, orc.topo.r, orc.topo.p, orc.kappa, beta, 1.0)
+    lam_r = gpu(inputs.random_vector(n, seed=3))
+    out = torch.empty(n, dtype=torch.float64, device=DEV)
+    assert lib.mhdg_set_supg(m.h, 2) == 1
+    m.set_supg(False)
+    assert lib.mhdg_apply_trace_operator(m.h, lam_r.data_ptr(), out.data_ptr(), 0, None) == 7
+    m.factor_local(gpu(orc.kappa), beta, 1.0)
+    m.apply_trace_operator(lam_r, out, mhdg.MHDG_PRECONDITION)
+    lh = host(lam_r)
+    assert rel(host(out), plain.apply(lh, precondition=True)) <= 1e-10
+    assert rel(host(out), orc.apply(lh, precondition=True)) > 1e-6
+
+
+def test_supg_adjoint_is_rejected():
+    orc, m, kappa, beta = build("r2_p3")
+    f, g, _, _ = data(orc, m, kappa, beta)
+    lam = torch.zeros(orc.topo.n_trace, dtype=torch.float64, device=DEV)
+    m.solve(f, g, lam, rtol=1e-10, restart=300, max_iter=20000)
+    qu = torch.empty(int(orc.topo.local_off[-1]), dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    with pytest.raises(mhdg.MhdgError) as e:
+        m.adjoint(lam, qu, torch.ones_like(qu), torch.empty_like(lam), torch.empty_like(qu),
+                  torch.empty(orc.topo.n_macro, dtype=torch.float64, device=DEV),
+                  torch.empty(2, dtype=torch.float64, device=DEV))
+    assert "SUPG" in str(e.value)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_supg_polynomial_reproduction_on_gpu(p):
+    """Consistency of the stabilised forms on the GPU: u in P_p is returned
+    to rounding with kappa = 0.02 (sub-triangle Peclet numbers near 3)."""
+    xy, tri = inputs.structured_mesh(2, jitter=0.1, seed=2)
+    ex = inputs.polynomial(p, 0.02, (1.0, -0.5), seed=p)
+    m = mhdg.MacroMesh(xy, tri, 1, p)
+    m.set_supg(True)
+    m.factor_local(gpu(np.full(len(tri), 0.02)), (1.0, -0.5), 1.0)
+    node, bnd = m.sample_points()
+    lam = torch.zeros(m.sizes.n_trace, dtype=torch.float64, device=DEV)
+    info = m.solve(gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1])), lam,
+                   rtol=1e-14, restart=200, max_iter=5000)
+    assert info.status == 0
+    qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    u = host(qu).reshape(-1)
+    Q = m.sizes.n_nodes // len(tri)
+    uh = np.concatenate([u[3 * Q * K + 2 * Q:3 * Q * (K + 1)] for K in range(len(tri))])
+    assert np.abs(uh - ex.u(node[:, 0], node[:, 1])).max() <= 1e-10
