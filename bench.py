@@ -93,6 +93,10 @@ WORKLOADS = {
                                                           beta=None, sol="exp_sin",
                                                           precision="qelim", form="folded",
                                                           n_inst=64, restart=50),
+    # the default job with SUPG inside the macros (section 3.4; sub-triangle Peclet number
+    # 0.15, tau = 2.9e-4): the stabilised local blocks, plain and tuned forms
+    "supg_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                      sol="exp_sin", precision="fp64", supg=True),
     # the plain at-scale operator applied to many vectors per call (one factorisation,
     # several right-hand sides): a wavefront carries 4 vectors through the local solve
     "many_rhs_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
@@ -190,7 +194,8 @@ def cpu_baseline(xy, tri, w, lam_seed=1, n_sample=16, budget_s=15.0):
         cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
-    orc = hdg.Oracle(xy, tri, w["r"], w["p"], w["kappa"], w["beta"], 1.0)
+    orc = hdg.Oracle(xy, tri, w["r"], w["p"], w["kappa"], w["beta"], 1.0,
+                     supg=bool(w.get("supg")))
     n_macro = orc.topo.n_macro
     sample = np.unique(np.linspace(0, n_macro - 1, min(n_sample, n_macro)).astype(int))
     lam = inputs.random_vector(orc.topo.n_trace, seed=lam_seed)
@@ -306,6 +311,8 @@ def main():
             w["kappa"] = float(kap_i[w["instance"]])
             w["beta"] = tuple(float(x) for x in beta_i[w["instance"]])
     m = mhdg.MacroMesh(xy, tri, w["r"], w["p"])
+    if w.get("supg"):
+        m.set_supg(True)
     one = m.sizes
     if n_inst > 1:
         m.set_instances(n_inst)
@@ -582,6 +589,7 @@ def main():
                    ("folded_flux_eliminated_fp64" if folded else "flux_eliminated_fp64")
                    if prec == mhdg.MHDG_QELIM else
                    ("fp32_factors_fp64_ir" if prec == mhdg.MHDG_FP32 else "bf16_factors_fp64_ir"),
+                   "supg": bool(w.get("supg")),
                    "inner_rtol": args.inner_rtol if reduced else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
