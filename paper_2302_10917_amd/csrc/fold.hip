@@ -11,7 +11,7 @@
 // Local numbering of a macro's trace dofs: its interior edges k = 0, 1, 2 in
 // order, position i along the face (face canonical direction) within each,
 // the same order as its contribution slots.  T_K is column-major.
-#include "macro_solve.h"
+#include "lu_sweeps.h"
 
 namespace mhdg {
 

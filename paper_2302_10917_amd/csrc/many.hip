@@ -2,7 +2,7 @@
 // once.  With one vector per launch every apply streams all stored factors
 // from HBM; here a wavefront carries NR vectors through the forward and
 // backward sweeps, so a factor column load serves NR products.
-#include "macro_solve.h"
+#include "lu_sweeps.h"
 
 namespace mhdg {
 
