@@ -7,7 +7,7 @@ Vandermonde matrix in physical coordinates, whose condition number grows to
 ~1e3-1e4 at p = 4, the library uses the product form -- so entries agree to
 a few hundred ulps of the largest entry);
 local solves, applies and the right-hand side to a relative 1e-10 (the
-north-star bound for FP64 paths; observed errors are ~1e-14..1e-12);
+stated FP64 parity bound; observed errors are ~1e-14..1e-12);
 solutions of a GMRES solve run to rtol 1e-13 to a relative 1e-10.
 """
 import numpy as np
