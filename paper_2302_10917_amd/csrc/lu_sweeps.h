@@ -86,4 +86,5 @@ __device__ __forceinline__ void lu_sweeps_nr(double (&y)[NQ][NR], const double* 
   }
 }
 
+
 }  // namespace mhdg
