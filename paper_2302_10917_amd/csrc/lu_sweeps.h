@@ -86,5 +86,4 @@ __device__ __forceinline__ void lu_sweeps_nr(double (&y)[NQ][NR], const double* 
   }
 }
 
-
 }  // namespace mhdg
