@@ -262,6 +262,9 @@ def main():
                          "instances (default: all)")
     ap.add_argument("--n-rhs", type=int, default=None,
                     help="many-vector workload: vectors per call (default 32)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="sequential-instances workload: one handle, no overlap of the next "
+                         "instance's factorisation with the current solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--folded", action="store_true",
                     help="run the GMRES applies on the folded macro operators (FP64 workloads, "
@@ -755,13 +758,31 @@ def bench_sequential_instances(args, w):
             return args.restart
         return w["restart_diffusive"] if kap_i[i] >= w["kappa_diffusive"] else w["restart"]
 
-    def solve_one(i):
-        f, g, kap, beta = data[i]
-        m.factor_local(kap, beta, 1.0, precision=mhdg.MHDG_QELIM)
-        m.fold_operator()
-        inf = m.solve(f, g, lam, rtol=args.rtol, restart=restart_for(i), max_iter=args.max_iter,
-                      folded=True, check=False)
-        m.recover_local(lam, qu)
+    # Two handles on two streams (default priority): while one instance's GMRES
+    # runs, a second host thread factors and folds the next instance on the other
+    # handle.  The library calls release the GIL; each handle keeps its own
+    # workspaces, graphs and pinned buffers.
+    from concurrent.futures import ThreadPoolExecutor
+    n_h = 1 if args.no_overlap else 2
+    meshes = [m] + [mhdg.MacroMesh(xy, tri, r, w["p"]) for _ in range(n_h - 1)]
+    streams = [torch.cuda.Stream() for _ in meshes]
+    lams = [lam] + [torch.zeros_like(lam) for _ in range(n_h - 1)]
+    qus = [qu] + [torch.empty_like(qu) for _ in range(n_h - 1)]
+    torch.cuda.synchronize()
+
+    def prepare(h, i):
+        _, _, kap, beta = data[i]
+        with torch.cuda.stream(streams[h]):
+            meshes[h].factor_local(kap, beta, 1.0, precision=mhdg.MHDG_QELIM)
+            meshes[h].fold_operator()
+
+    def finish(h, i):
+        f, g, _, _ = data[i]
+        with torch.cuda.stream(streams[h]):
+            inf = meshes[h].solve(f, g, lams[h], rtol=args.rtol, restart=restart_for(i),
+                                  max_iter=args.max_iter, folded=True, check=False)
+            meshes[h].recover_local(lams[h], qus[h])
+            streams[h].synchronize()
         d = inf.as_dict()
         print(f"[bench] instance {i}: kappa {kap_i[i]:.3e} |beta| {np.hypot(*beta_i[i]):.2f}: "
               f"GMRES({restart_for(i)}) {d['iterations']} iterations, status {d['status']}, rel res "
@@ -769,13 +790,28 @@ def bench_sequential_instances(args, w):
               flush=True)
         return d
 
+    def run(seq):
+        out = []
+        if n_h == 1:
+            for i in seq:
+                prepare(0, i)
+                out.append(finish(0, i))
+            return out
+        with ThreadPoolExecutor(1) as pool:
+            prepare(0, seq[0])
+            for k, i in enumerate(seq):
+                nxt = pool.submit(prepare, (k + 1) % 2, seq[k + 1]) if k + 1 < len(seq) else None
+                out.append(finish(k % 2, i))
+                if nxt is not None:
+                    nxt.result()
+        return out
+
     for _ in range(args.warmup):
-        solve_one(ids[0])
+        run(ids[:n_h])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(args.steps):
-        for i in ids:
-            infos.append(solve_one(i))
+        infos.extend(run(ids))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     applies = sum(x["n_applies"] for x in infos)
@@ -802,7 +838,9 @@ def bench_sequential_instances(args, w):
                    "gmres_restart": (args.restart if args.restart_override else
                                      f"{w['restart']} for kappa < {w['kappa_diffusive']}, "
                                      f"else {w['restart_diffusive']}"),
-                   "form": "folded_flux_eliminated_fp64, instances in sequence"},
+                   "form": "folded_flux_eliminated_fp64, instances in sequence" +
+                           ("" if args.no_overlap else
+                            ", next instance factored and folded during the current solve")},
         "time_to_solve_s": elapsed / args.steps,
         "per_instance_s": elapsed / (args.steps * n_inst),
         "iterations_min_max": [min(its), max(its)],
