@@ -129,6 +129,10 @@ def test_solve_and_recover_match_oracle(case):
     assert rel(host(qu), np.concatenate(U_o)) <= 1e-10, name
     if n:
         assert np.linalg.norm(host(res)) <= 1e-10 * np.linalg.norm(fhat)
+    # macro conservation of the fields recovered through the Schur block
+    cons = torch.empty(orc.topo.n_macro, dtype=torch.float64, device=DEV)
+    m.flux_balance(lam if n else torch.zeros(1, dtype=torch.float64, device=DEV), qu, f, cons)
+    assert np.abs(host(cons)).max() <= 1e-11, name
 
 
 def test_instances_match_oracle_per_instance():
