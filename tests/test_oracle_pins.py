@@ -467,3 +467,34 @@ def test_supg_changes_the_advection_dominated_solution():
     _, U1, _ = o1.solve(f, g)
     d = max(np.abs(a - b).max() for a, b in zip(U0, U1))
     assert d > 1e-6
+
+
+def _interior_block(p, r, kappa=1.0, beta=(1.0, 0.5)):
+    """A_K restricted to the macro's interior lattice nodes (all three fields)."""
+    xy, tri = inputs.structured_mesh(1)
+    topo = hdg.Topology(xy, tri, r, p)
+    b = hdg.macro_blocks(topo, 0, kappa, beta, 1.0)
+    Q = int(topo.Q[0])
+    on_bnd = np.zeros(Q, bool)
+    for Gk in b.G:
+        on_bnd |= np.abs(Gk).sum(axis=1) > 1e-12 * np.abs(Gk).max()
+    inner = np.flatnonzero(~on_bnd)
+    idx = np.concatenate([inner, Q + inner, 2 * Q + inner])
+    return b.A[np.ix_(idx, idx)], inner.size
+
+
+def test_interior_block_nonsingular_except_lone_bubble():
+    """A boundary-condensed apply would invert the interior block A_ii of
+    each macro.  With one interior node (p = 3, r = 0: the cubic bubble)
+    A_ii = diag(M_bb, M_bb, 0) -- the bubble's E^d_bb = (phi_b, d_d phi_b) and
+    its boundary mass vanish -- so it is singular; with several interior
+    nodes it is not (smallest over largest singular value >= 1e-5 here)."""
+    A, n = _interior_block(3, 0)
+    assert n == 1
+    s = np.linalg.svd(A, compute_uv=False)
+    assert s[-1] <= 1e-12 * s[0]
+    for p, r in ((1, 2), (2, 2), (3, 1), (3, 2)):
+        for kappa in (1.0, 1e-3):
+            A, n = _interior_block(p, r, kappa)
+            s = np.linalg.svd(A, compute_uv=False)
+            assert n > 1 and s[-1] >= 1e-5 * s[0], (p, r, kappa)
