@@ -18,6 +18,14 @@
  *   recover_local           A_K U_K = R_K - B_K lambda_K (eq. local_problem)
  *                           plus the transmission residual C U + D lambda
  *
+ * Variants of the same operator: several trace vectors per call
+ * (mhdg_apply_trace_operator_many), folded per-macro operators
+ * (mhdg_fold_operator), the flux eliminated through the reference mass
+ * (MHDG_QELIM), FP32/BF16 factors with FP64 refinement, coefficient
+ * instances, SUPG inside the macros (mhdg_set_supg, section 3.4), the
+ * adjoint (mhdg_adjoint) and the macro conservation residual
+ * (mhdg_flux_balance).
+ *
  * Conventions (the same written specification is implemented independently
  * by the CPU oracle used in the tests):
  *   - macro lattice node (i, j), i + j <= P = 2^r p, sits at
@@ -55,7 +63,8 @@
  *
  * Errors: every call returns an mhdg_status; nothing throws across the ABI.
  * mhdg_last_error() gives a message for the last failing call on a handle.
- * Handles are not thread-safe.
+ * Handles are not thread-safe: one thread at a time per handle; distinct
+ * handles may be driven from different threads on different streams.
  */
 #ifndef MHDG_H_
 #define MHDG_H_
