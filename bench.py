@@ -693,6 +693,21 @@ def bench_many_rhs(args, w):
         sweep[k] = reps * k / (time.perf_counter() - t2)
         print(f"[bench] {k} vectors per call: {sweep[k]:.1f} vector-applies/s",
               file=sys.stderr, flush=True)
+    # the same with the folded operators (T_K read once per group of 8 vectors)
+    m.fold_operator()
+    fsweep = {}
+    for k in (1, 8, 32):
+        fl = flags | mhdg.MHDG_FOLDED
+        m.apply_trace_operator_many(lam[:k], out[:k], fl)
+        torch.cuda.synchronize()
+        reps = max(4, 128 // k)
+        t2 = time.perf_counter()
+        for _ in range(reps):
+            m.apply_trace_operator_many(lam[:k], out[:k], fl)
+        torch.cuda.synchronize()
+        fsweep[k] = reps * k / (time.perf_counter() - t2)
+        print(f"[bench] folded, {k} vectors per call: {fsweep[k]:.1f} vector-applies/s",
+              file=sys.stderr, flush=True)
     result = {
         "metric": METRIC,
         "value": args.steps * n_rhs / elapsed,
@@ -718,6 +733,7 @@ def bench_many_rhs(args, w):
                      "kernel_ms": k_ms},
         "single_vector_applies_per_s": single,
         "vector_applies_per_s_by_n_rhs": sweep,
+        "folded_vector_applies_per_s_by_n_rhs": fsweep,
     }
     print(json.dumps(result), flush=True)
 

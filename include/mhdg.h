@@ -253,14 +253,18 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* mesh, const double* lam, double
  * once per group of vectors (8 vectors for N_K <= 512, 4 up to 1024, 2 up to
  * 2048, 1 above), not once per vector.  For callers with many vectors
  * against one factorisation (several load cases, block Krylov methods).
+ * With MHDG_FOLDED the folded operators T_K (mhdg_fold_operator, from
+ * MHDG_FP64 or MHDG_QELIM factors) are applied instead, each T_K read once
+ * per group of 8 vectors.
  * lam, out: device f64[n_rhs][n_trace] (vector v at offset v * n_trace);
  * the two ranges must not overlap.  ws: device workspace of at least
  * mhdg_apply_many_ws_bytes(mesh, n_rhs) bytes (per-vector contribution
  * slots), owned by the caller; its contents on entry do not matter.
- * flags: 0 or MHDG_PRECONDITION.  n_rhs = 0 is a no-op.
+ * flags: MHDG_PRECONDITION and/or MHDG_FOLDED.  n_rhs = 0 is a no-op.
  * Errors: INVALID_ARG (n_rhs < 0, other flags, null or overlapping
- * vectors), STATE (before factor_local, or factors other than MHDG_FP64),
- * WORKSPACE (ws too small). */
+ * vectors), STATE (before factor_local; without MHDG_FOLDED, factors other
+ * than MHDG_FP64; with it, before mhdg_fold_operator), WORKSPACE (ws too
+ * small). */
 size_t mhdg_apply_many_ws_bytes(const mhdg_mesh* mesh, int32_t n_rhs);
 mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* mesh, int32_t n_rhs, const double* lam,
                                            double* out, int32_t flags, void* ws,

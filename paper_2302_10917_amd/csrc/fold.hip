@@ -226,6 +226,96 @@ __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restr
   }
 }
 
+// Folded steps 1-3 for n_rhs trace vectors: workgroup (macro, group of NR
+// consecutive vectors) reads T_K once for the NR vectors of its group, in the
+// same column batches as the single-vector kernel.  Vector v reads
+// lam + v * ld_lam and writes its slots at slots + v * ld_slots.
+template <int NT, int NR>
+__global__ __launch_bounds__(64) void fold_apply_many_kernel(const MacroInfo* __restrict__ info,
+                                                             const int64_t* __restrict__ toff,
+                                                             const double* __restrict__ T, int p,
+                                                             int n_rhs,
+                                                             const double* __restrict__ lam,
+                                                             int64_t ld_lam,
+                                                             double* __restrict__ slots,
+                                                             int64_t ld_slots) {
+  constexpr int CB = 8;
+  __shared__ double xl[NR][64 * NT];
+  const MacroInfo& mi = info[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int v0 = blockIdx.y * NR, nv = min(NR, n_rhs - v0);
+  int L = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (mi.tr_off[k] < 0) continue;
+    const int nF = face_nodes(mi, k, p);
+    for (int r = 0; r < NR; ++r)
+      for (int l = lane; l < nF; l += 64)
+        xl[r][L + l] = r < nv ? lam[int64_t(v0 + r) * ld_lam + mi.tr_off[k] + l] : 0.0;
+    L += nF;
+  }
+  if (L == 0) return;
+  __syncthreads();
+  const double* Tm = T + toff[blockIdx.x];
+  double acc[NT][NR];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[t][r] = 0.0;
+  for (int c0 = 0; c0 < L; c0 += CB) {
+    double a[CB][NT];
+#pragma unroll
+    for (int cc = 0; cc < CB; ++cc)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int c = c0 + cc, rw = lane + 64 * t;
+        a[cc][t] = (c < L && rw < L) ? Tm[int64_t(c) * L + rw] : 0.0;
+      }
+#pragma unroll
+    for (int cc = 0; cc < CB; ++cc) {
+      const int c = min(c0 + cc, 64 * NT - 1);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const double x = c0 + cc < L ? xl[r][c] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t][r] += a[cc][t] * x;
+      }
+    }
+  }
+  int r0 = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (mi.tr_off[k] < 0) continue;
+    const int nF = face_nodes(mi, k, p);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int rw = lane + 64 * t;
+      if (rw >= r0 && rw < r0 + nF)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nv) slots[int64_t(v0 + r) * ld_slots + mi.slot_off[k] + (rw - r0)] = acc[t][r];
+    }
+    r0 += nF;
+  }
+}
+
+hipError_t launch_fold_apply_many(const MacroInfo* info, int64_t n, const int64_t* toff,
+                                  const double* T, int p, int max_L, int n_rhs, const double* lam,
+                                  int64_t ld_lam, double* slots, int64_t ld_slots, hipStream_t s) {
+  constexpr int NR = 8;
+  const dim3 g((unsigned)n, (unsigned)((n_rhs + NR - 1) / NR)), b(64);
+  if (max_L <= 64)
+    hipLaunchKernelGGL((fold_apply_many_kernel<1, NR>), g, b, 0, s, info, toff, T, p, n_rhs, lam,
+                       ld_lam, slots, ld_slots);
+  else if (max_L <= 128)
+    hipLaunchKernelGGL((fold_apply_many_kernel<2, NR>), g, b, 0, s, info, toff, T, p, n_rhs, lam,
+                       ld_lam, slots, ld_slots);
+  else if (max_L <= kFoldMaxL)
+    hipLaunchKernelGGL((fold_apply_many_kernel<3, NR>), g, b, 0, s, info, toff, T, p, n_rhs, lam,
+                       ld_lam, slots, ld_slots);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,
                              int p, int max_L, const int32_t* skip, int transpose,
                              const double* lam, double* slots, hipStream_t s) {

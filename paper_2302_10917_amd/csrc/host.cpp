@@ -2141,11 +2141,15 @@ mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* M, int32_t n_rhs, const do
                                            void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;
   if (n_rhs < 0) return fail(M, MHDG_ERR_INVALID_ARG, "apply_many: n_rhs < 0");
-  if (flags & ~MHDG_PRECONDITION)
-    return fail(M, MHDG_ERR_INVALID_ARG, "apply_many: only MHDG_PRECONDITION is accepted in flags");
+  if (flags & ~(MHDG_PRECONDITION | MHDG_FOLDED))
+    return fail(M, MHDG_ERR_INVALID_ARG,
+                "apply_many: only MHDG_PRECONDITION and MHDG_FOLDED are accepted in flags");
+  const bool folded = (flags & MHDG_FOLDED) != 0;
   if (!M->factored) return fail(M, MHDG_ERR_STATE, "apply_many: call factor_local first");
-  if (M->precision != MHDG_FP64)
-    return fail(M, MHDG_ERR_STATE, "apply_many: needs MHDG_FP64 factors");
+  if (folded && !M->folded)
+    return fail(M, MHDG_ERR_STATE, "apply_many: folded operators need mhdg_fold_operator");
+  if (!folded && M->precision != MHDG_FP64)
+    return fail(M, MHDG_ERR_STATE, "apply_many: needs MHDG_FP64 factors (or MHDG_FOLDED)");
   if (n_rhs == 0 || M->n_trace == 0) return MHDG_OK;
   if (!lam || !out) return fail(M, MHDG_ERR_INVALID_ARG, "apply_many: null vector");
   const int64_t len = int64_t(n_rhs) * M->n_trace;
@@ -2157,7 +2161,12 @@ mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* M, int32_t n_rhs, const do
   FactorLayout& L = M->L;
   char* w = M->ws;
   double* slots = (double*)ws;
-  {
+  if (folded) {
+    ProfScope ps(M, 5, s);
+    HIP_TRY(M, launch_fold_apply_many((const MacroInfo*)(w + L.meta), M->n_macro, M->fold_toff,
+                                      M->fold_T, M->p, M->fold_maxL, n_rhs, lam, M->n_trace,
+                                      slots, M->n_slots, s));
+  } else {
     ProfScope ps(M, 2, s);
     HIP_TRY(M, launch_apply_many((const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
                                  (const int32_t*)(w + L.order), M->classes.data(),

@@ -210,6 +210,11 @@ hipError_t launch_apply_many(const double* fac, const MacroInfo* info, const int
 // vectors per wavefront of launch_apply_many for local size N
 int apply_many_group(int N);
 
+// folded steps 1-3 for n_rhs trace vectors (T_K read once per group of 8)
+hipError_t launch_fold_apply_many(const MacroInfo* info, int64_t n, const int64_t* toff,
+                                  const double* T, int p, int max_L, int n_rhs, const double* lam,
+                                  int64_t ld_lam, double* slots, int64_t ld_slots, hipStream_t s);
+
 // GMRES vector kernels
 // Vectors may hold nseg independent segments of length n (coefficient
 // instances): dot products and updates are per segment; out / h are indexed

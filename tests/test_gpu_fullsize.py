@@ -349,6 +349,14 @@ def test_c2_apply_many_sampled(c2):
         err = rel(gather(outh[v], topo, faces), ref)
         print(f"  many-vector apply, vector {v}: {err:.2e}", flush=True)
         assert err <= TOL, v
+    # folded operators (built by the fixture): each T_K read once for the 9 vectors
+    m.apply_trace_operator_many(lam, out, mhdg.MHDG_PRECONDITION | mhdg.MHDG_FOLDED)
+    outh = host(out)
+    for v in range(9):
+        m.apply_trace_operator(lam[v], one, mhdg.MHDG_PRECONDITION | mhdg.MHDG_FOLDED)
+        assert rel(outh[v], host(one)) <= 1e-12, v
+    ref = gather(orc.apply(lam_h[8], precondition=True, faces=faces), topo, faces)
+    assert rel(gather(outh[8], topo, faces), ref) <= TOL
 
 
 def test_c2_flux_balance(c2):

@@ -104,6 +104,35 @@ def test_many_vector_counts(n_rhs):
         assert rel(outh[v], host(one)) <= 1e-12, v
 
 
+@pytest.mark.parametrize("name,precision", [("r3_p3", mhdg.MHDG_FP64),
+                                            ("mixed_r1to4_p3", mhdg.MHDG_FP64),
+                                            ("mixed_r1to4_p3", mhdg.MHDG_QELIM),
+                                            ("mixed_p2", mhdg.MHDG_QELIM)])
+def test_folded_many_matches_single_and_oracle(name, precision):
+    """MHDG_FOLDED: T_K read once per group of 8 vectors; 11 vectors (a full
+    and a partial group) against single folded applies (1e-12) and the
+    oracle (1e-10)."""
+    xy, tri, r, p, kap, beta = _case(name)
+    orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0)
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    m.factor_local(gpu(kap), beta, 1.0, precision=precision)
+    m.fold_operator()
+    n = orc.topo.n_trace
+    lam_h = np.stack([inputs.random_vector(n, seed=90 + v) for v in range(11)])
+    lam = gpu(lam_h)
+    out = torch.empty((11, n), dtype=torch.float64, device=DEV)
+    one = torch.empty(n, dtype=torch.float64, device=DEV)
+    for flags, prec in ((mhdg.MHDG_FOLDED, False),
+                        (mhdg.MHDG_FOLDED | mhdg.MHDG_PRECONDITION, True)):
+        m.apply_trace_operator_many(lam, out, flags)
+        outh = host(out)
+        for v in range(11):
+            m.apply_trace_operator(lam[v], one, flags)
+            assert rel(outh[v], host(one)) <= 1e-12, (flags, v)
+        for v in (0, 10):
+            assert rel(outh[v], orc.apply(lam_h[v], precondition=prec)) <= 1e-10, (flags, v)
+
+
 def test_many_with_instances():
     """Coefficient instances: each vector spans every instance's trace."""
     xy, tri, r, p, _, _ = _case("mixed_p2")
@@ -154,7 +183,8 @@ def test_many_errors():
     m.factor_local(gpu(kap), beta, 1.0)
     assert call(-1, P(lam), P(out), 0, P(ws), ws.numel()) == 1
     assert call(2, P(lam), P(out), mhdg.MHDG_TRANSPOSE, P(ws), ws.numel()) == 1
-    assert call(2, P(lam), P(out), mhdg.MHDG_FOLDED, P(ws), ws.numel()) == 1
+    assert call(2, P(lam), P(out), mhdg.MHDG_GRAPH, P(ws), ws.numel()) == 1
+    assert call(2, P(lam), P(out), mhdg.MHDG_FOLDED, P(ws), ws.numel()) == 7  # not folded
     assert call(2, None, P(out), 0, P(ws), ws.numel()) == 1
     assert call(2, P(lam), P(lam[1:]), 0, P(ws), ws.numel()) == 1      # overlapping ranges
     assert call(2, P(lam), P(out), 0, P(ws), ws.numel() - 8) == 5      # workspace too small
