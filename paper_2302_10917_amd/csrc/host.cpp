@@ -2175,12 +2175,14 @@ mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* M, int32_t n_rhs, const do
                                  M->n_trace, slots, M->n_slots, s));
   }
   ProfScope ps(M, 3, s);
-  for (int32_t v = 0; v < n_rhs; ++v)
-    HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
-                                   (const FaceInfo*)(w + L.faces), M->n_int,
-                                   (const double*)(w + L.tmpl), M->T, M->tau,
-                                   lam + int64_t(v) * M->n_trace, slots + int64_t(v) * M->n_slots,
-                                   out + int64_t(v) * M->n_trace, s));
+  for (int32_t v0 = 0; v0 < n_rhs; v0 += 65535)   // grid y limit
+    HIP_TRY(M, launch_face_combine_many((flags & MHDG_PRECONDITION) ? 1 : 0,
+                                        (const FaceInfo*)(w + L.faces), M->n_int,
+                                        (const double*)(w + L.tmpl), M->T, M->tau,
+                                        std::min<int32_t>(65535, n_rhs - v0),
+                                        lam + int64_t(v0) * M->n_trace, M->n_trace,
+                                        slots + int64_t(v0) * M->n_slots, M->n_slots,
+                                        out + int64_t(v0) * M->n_trace, s));
   return MHDG_OK;
 }
 

@@ -164,6 +164,13 @@ hipError_t launch_flux_balance(const MacroInfo* info, int64_t n, const BndFaceIn
                                const double* tmpl, const Templates& T, double tau,
                                const double* lam, const double* lamD, const double* U,
                                const double* f, double* out, hipStream_t s);
+// step 4 for n_rhs vectors in one launch (FACE_S, or FACE_PREC_S with precondition = 1);
+// vector v at lam / out + v * ld_lam, its slots at slots + v * ld_slots
+hipError_t launch_face_combine_many(int precondition, const FaceInfo* fi, int64_t nf,
+                                    const double* tmpl, const Templates& T, double tau,
+                                    int n_rhs, const double* lam, int64_t ld_lam,
+                                    const double* slots, int64_t ld_slots, double* out,
+                                    hipStream_t s);
 hipError_t launch_extract_matrix(const MacroInfo* info, int64_t e, const double* tmpl,
                                  const Templates& T, double tau, double* dst, hipStream_t s);
 // face_combine modes

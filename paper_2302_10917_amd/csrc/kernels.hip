@@ -491,6 +491,39 @@ __global__ __launch_bounds__(64) void face_combine_kernel(int mode, const FaceIn
   }
 }
 
+// Step 4 for n_rhs vectors in one launch (workgroup (face, vector)): vector v
+// reads lam + v * ld_lam and slots + v * ld_slots and writes out + v * ld_lam.
+// out = D lam - v^ (precondition = 0) or lam - D^-1 v^ (precondition = 1).
+__global__ __launch_bounds__(64) void face_combine_many_kernel(
+    int precondition, const FaceInfo* __restrict__ fi, const double* __restrict__ tm,
+    Templates Tp, double tau, const double* __restrict__ lam, int64_t ld_lam,
+    const double* __restrict__ slots, int64_t ld_slots, double* __restrict__ out) {
+  __shared__ double v[(1 << kMaxLevel) * 4 + 1];
+  __shared__ double lf[(1 << kMaxLevel) * 4 + 1];
+  const FaceInfo& f = fi[blockIdx.x];
+  const int nF = f.nF;
+  const double* lv = lam + int64_t(blockIdx.y) * ld_lam + f.tr_off;
+  const double* sv = slots + int64_t(blockIdx.y) * ld_slots;
+  double* ov = out + int64_t(blockIdx.y) * ld_lam + f.tr_off;
+  for (int l = threadIdx.x; l < nF; l += 64) {
+    v[l] = sv[f.slot[0] + l] + sv[f.slot[1] + l];
+    lf[l] = lv[l];
+  }
+  __syncthreads();
+  const LevelTemplates& L = Tp.lev[f.level];
+  const double* M = tm + (precondition ? L.M1inv : L.M1);
+  for (int l = threadIdx.x; l < nF; l += 64) {
+    double d = 0.0;
+    if (precondition) {   // lam - D_F^-1 v = lam + M1^-1 v / (2 tau |F|)
+      for (int k = 0; k < nF; ++k) d += M[size_t(l) * nF + k] * v[k];
+      ov[l] = lf[l] + d / (2.0 * tau * f.len);
+    } else {              // D_F lam - v = -2 tau |F| M1 lam - v
+      for (int k = 0; k < nF; ++k) d += M[size_t(l) * nF + k] * lf[k];
+      ov[l] = d * (-2.0 * tau * f.len) - v[l];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ data
 // lam_D = M1^-1 b, b_l = sum over segments and sampling points of
 // (w_q / npc) g_q mu_l(t_q): the L2 projection of g_D onto M(F).
@@ -1350,6 +1383,18 @@ hipError_t launch_face_combine(int mode, const FaceInfo* fi, int64_t nf, const d
   if (nf == 0) return hipSuccess;
   hipLaunchKernelGGL(face_combine_kernel, dim3((unsigned)nf), dim3(64), 0, s, mode, fi, tmpl, T,
                      tau, lam, slots, out, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_combine_many(int precondition, const FaceInfo* fi, int64_t nf,
+                                    const double* tmpl, const Templates& T, double tau,
+                                    int n_rhs, const double* lam, int64_t ld_lam,
+                                    const double* slots, int64_t ld_slots, double* out,
+                                    hipStream_t s) {
+  if (nf == 0 || n_rhs == 0) return hipSuccess;
+  if (n_rhs > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(face_combine_many_kernel, dim3((unsigned)nf, (unsigned)n_rhs), dim3(64), 0,
+                     s, precondition, fi, tmpl, T, tau, lam, ld_lam, slots, ld_slots, out);
   return hipGetLastError();
 }
 
