@@ -214,8 +214,6 @@ hipError_t launch_apply_many(const double* fac, const MacroInfo* info, const int
                              const double* tmpl, const Templates& T, double tau, int n_rhs,
                              const double* lam, int64_t ld_lam, double* slots, int64_t ld_slots,
                              hipStream_t s);
-// vectors per wavefront of launch_apply_many for local size N
-int apply_many_group(int N);
 
 // folded steps 1-3 for n_rhs trace vectors (T_K read once per group of 8)
 hipError_t launch_fold_apply_many(const MacroInfo* info, int64_t n, const int64_t* toff,

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(64) void apply_many_kernel(
   }
 }
 
-int apply_many_group(int N) {
+// vectors per wavefront for local size N
+static int apply_many_group(int N) {
   const int nq = (N + 63) / 64;
   return nq <= 8 ? 8 : (nq <= 16 ? 4 : (nq <= 32 ? 2 : 1));
 }
