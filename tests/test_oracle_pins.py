@@ -498,3 +498,20 @@ def test_interior_block_nonsingular_except_lone_bubble():
             A, n = _interior_block(p, r, kappa)
             s = np.linalg.svd(A, compute_uv=False)
             assert n > 1 and s[-1] >= 1e-5 * s[0], (p, r, kappa)
+
+
+def test_flux_balance_subset_equals_full_evaluation():
+    """The macros= argument only restricts which macros are evaluated."""
+    xy, tri = inputs.structured_mesh(2, jitter=0.1, seed=4)
+    o = hdg.Oracle(xy, tri, 1, 2, 0.3, (1.0, -0.4), 1.0)
+    ex = inputs.exp_sin(0.3, (1.0, -0.4))
+    f, g = o.sample(ex)
+    lamD = o.dirichlet_trace(g)
+    rng = np.random.default_rng(5)
+    lam = rng.standard_normal(o.topo.n_trace)
+    U = [rng.standard_normal(int(o.topo.N_e[K])) for K in range(o.topo.n_macro)]
+    full = o.flux_balance(U, lam, lamD, f)
+    sub = [1, 4, 6]
+    part = o.flux_balance(U, lam, lamD, f, macros=sub)
+    assert np.array_equal(part[sub], full[sub])
+    assert np.all(np.delete(part, sub) == 0.0)
