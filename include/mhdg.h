@@ -216,7 +216,8 @@ mhdg_status mhdg_sample_points(const mhdg_mesh* mesh, double* node_xy, double* b
  * refinement of solve and recover_local restores FP64 accuracy).
  * kappa: device f64[n_macro], each value finite and > 0 (not checked on the
  * host, since the values live on the device: a zero pivot is reported as
- * SINGULAR, non-finite results by solve's residual check); a = (beta_x,
+ * SINGULAR, non-finite results by solve as NOT_CONVERGED with a
+ * non-finite residual); a = (beta_x,
  * beta_y) constant and finite; tau > 0.
  * ws: device workspace of at least factor_ws_bytes (mhdg_query with the
  * same precision); it must stay allocated while the handle uses it.
