@@ -58,7 +58,7 @@
  * host metadata.  Device pointers are plain device addresses (for example
  * from a torch tensor); "stream" is a hipStream_t passed as void*
  * (NULL = the null stream).  Calls are asynchronous on that stream, except
- * setup (host only), factor_local (synchronises once to check pivots) and
+ * setup (host only), factor_local (synchronises to check kappa and the pivots) and
  * solve (synchronises each iteration to run the Arnoldi recurrences).
  *
  * Errors: every call returns an mhdg_status; nothing throws across the ABI.
@@ -84,7 +84,9 @@ typedef enum {
   MHDG_ERR_NOT_CONVERGED = 4, /* GMRES hit max_iter before rtol               */
   MHDG_ERR_WORKSPACE = 5,     /* workspace smaller than mhdg_query reports    */
   MHDG_ERR_HIP = 6,           /* a HIP runtime call failed                    */
-  MHDG_ERR_STATE = 7          /* e.g. apply before factor_local               */
+  MHDG_ERR_STATE = 7,         /* e.g. apply before factor_local               */
+  MHDG_ERR_NONFINITE = 8      /* a non-finite pivot in some A_K (an entry
+                                 overflowed; macro and column in last_error)  */
 } mhdg_status;
 
 typedef enum {
@@ -178,8 +180,12 @@ typedef struct {
                                  than 1/sqrt(2) of the vector's norm)        */
 } mhdg_solve_info;
 
-/* Build the host-side macro mesh: faces, levels, orientation, numbering and
- * the reference templates.  xy[n_vertices][2] (host, f64), tri[n_macro][3]
+/* Build the host-side macro mesh (the partition of Omega into simplicial
+ * macro-elements of section 2.2, each uniformly subdivided r times as in
+ * section 3.2, with the face trace spaces M(F) of section 3.2 and the finer
+ * level on non-matching faces as in the local refinement of section 4.2):
+ * faces, levels, orientation, numbering and the reference templates.
+ * xy[n_vertices][2] (host, f64), tri[n_macro][3]
  * (host, i32, counter-clockwise), level[n_macro] (host, i32, 0..5; NULL means
  * every macro has level `uniform_level`), p in 1..4, local size
  * N_K = 3 (2^r p + 1)(2^r p + 2)/2 <= 4096.
@@ -214,14 +220,18 @@ mhdg_status mhdg_sample_points(const mhdg_mesh* mesh, double* node_xy, double* b
  * pivoting (ties to the smallest row), in the requested precision (BF16:
  * the FP32 factors are rounded to nearest-even BF16 for storage; the
  * refinement of solve and recover_local restores FP64 accuracy).
- * kappa: device f64[n_macro], each value finite and > 0 (not checked on the
- * host, since the values live on the device: a zero pivot is reported as
- * SINGULAR, non-finite results by solve as NOT_CONVERGED with a
- * non-finite residual); a = (beta_x,
- * beta_y) constant and finite; tau > 0.
+ * kappa: device f64[n_macro], each value finite and > 0: the values are
+ * checked on the device before anything is assembled (one synchronisation)
+ * and a violation returns INVALID_ARG naming the first such macro, with no
+ * block assembled or factored.  a = (beta_x, beta_y) constant and finite;
+ * tau finite and > 0 (both checked on the host, INVALID_ARG).  Entries that
+ * still overflow (e.g. kappa or a near the largest double) make a pivot
+ * non-finite: NONFINITE, with the macro and column in last_error.
  * ws: device workspace of at least factor_ws_bytes (mhdg_query with the
  * same precision); it must stay allocated while the handle uses it.
- * Errors: INVALID_ARG, WORKSPACE, SINGULAR (first macro in last_error), HIP. */
+ * Synchronises (the kappa check and the pivot status).
+ * Errors: INVALID_ARG, WORKSPACE, SINGULAR (an exactly zero pivot; first
+ * macro and column in last_error), NONFINITE, HIP. */
 mhdg_status mhdg_factor_local(mhdg_mesh* mesh, const double* kappa, double beta_x, double beta_y,
                               double tau, int32_t precision, void* ws, size_t ws_bytes,
                               void* stream);
@@ -286,7 +296,9 @@ mhdg_status mhdg_local_solve(mhdg_mesh* mesh, const double* x, double* y, int32_
 mhdg_status mhdg_rhs(mhdg_mesh* mesh, const double* f_nodes, const double* g_bnd, double* fhat,
                      int32_t flags, void* stream);
 
-/* Solve S lam = f^ by GMRES(restart) left-preconditioned with D^-1, all
+/* Solve the global problem S lam = f^ (eq. global_problem of section
+ * 3.3.1, with S applied matrix-free by the steps of section 3.3.2) by
+ * GMRES(restart) left-preconditioned with D^-1 as in section 6.1, all
  * vector work in FP64 on the device.  Calls mhdg_rhs first.  When the
  * factors are FP32 the solve is an FP64 iterative refinement of the whole
  * hybridised system: the residual (R - A U - B lam, -(C U + D lam)) is formed
@@ -403,14 +415,19 @@ mhdg_status mhdg_set_kernel_variant(mhdg_mesh* mesh, int32_t N, int32_t lu_varia
  * the macro's interior-face trace dofs (L_K = sum of the n_F of its interior
  * faces, at most 192), so that S lambda = D lambda - sum_K T_K lambda_K (eq.
  * global_problem) reads L_K^2 values per macro instead of the N_K^2 of the
- * factors.  The matrices are built with the stored FP64 factors: the
- * interior faces are coloured so that the faces of one macro differ, and one
- * apply of the indicator of (colour, trace position) yields one column of
- * every T_K.  ws: device workspace of at least fold_ws_bytes (mhdg_query),
- * kept by the handle until the next factor_local or set_instances.  Then
- * apply_trace_operator with MHDG_FOLDED, or solve with opts->folded = 1, use
- * them; recover_local, rhs and adjoint keep using the factors.
- * Synchronises.  Errors: STATE (no FP64 factors), WORKSPACE, INVALID_ARG. */
+ * factors.  The matrices are built in one launch from the stored factors as
+ * a many-right-hand-side solve: every column of B_K (the lift of one trace
+ * unit vector) is solved with A_K's factors, several columns per pass over
+ * them, and restricted with C_K into the matching column of T_K.  With
+ * MHDG_FP64 factors A_K is the full block; with MHDG_QELIM factors the
+ * solve goes through the Schur block on u and the reference mass (the same
+ * operator up to rounding).  ws: device workspace of at least
+ * fold_ws_bytes (mhdg_query), kept by the handle until the next
+ * factor_local or set_instances.  Then apply_trace_operator with
+ * MHDG_FOLDED, or solve with opts->folded = 1, use them; recover_local, rhs
+ * and adjoint keep using the factors.  Synchronises.
+ * Errors: STATE (before factor_local, or FP32 / BF16 factors), WORKSPACE,
+ * INVALID_ARG (a macro trace larger than 192). */
 mhdg_status mhdg_fold_operator(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing of the hot path, for measurement.  enable = 1 clears

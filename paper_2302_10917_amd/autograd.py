@@ -14,31 +14,17 @@ import torch
 from . import mhdg
 
 
-class _State:
-    """Which (kappa, beta) the mesh's factors and right-hand side belong to."""
-
-    def __init__(self):
-        self.key = None
-
-
-def _key(kappa, beta, folded):
-    return (kappa.data_ptr(), kappa._version, float(beta[0]), float(beta[1]), bool(folded),
-            hash(kappa.detach().cpu().numpy().tobytes()))
-
-
 def _forward(mesh, kappa, beta, f, g, rtol, restart, folded):
     s = mesh.sizes
+    dev = kappa.device
     mesh.factor_local(kappa.detach(), (float(beta[0]), float(beta[1])), 1.0)
     if folded:
         mesh.fold_operator()
-    lam = torch.zeros(s.n_trace, dtype=torch.float64, device="cuda")
+    lam = torch.zeros(s.n_trace, dtype=torch.float64, device=dev)
     mesh.solve(f, g, lam, rtol=rtol, restart=restart, max_iter=max(50000, 2 * restart),
                folded=folded)
-    qu = torch.empty(s.n_local, dtype=torch.float64, device="cuda")
+    qu = torch.empty(s.n_local, dtype=torch.float64, device=dev)
     mesh.recover_local(lam, qu)
-    if not hasattr(mesh, "_ad_state"):
-        mesh._ad_state = _State()
-    mesh._ad_state.key = _key(kappa, beta, folded)
     return lam, qu
 
 
@@ -49,6 +35,9 @@ class MacroHDGSolve(torch.autograd.Function):
         lam, qu = _forward(mesh, kappa, beta_h, f, g, rtol, restart, folded)
         ctx.mesh, ctx.f, ctx.g, ctx.rtol, ctx.restart = mesh, f, g, rtol, restart
         ctx.folded = folded
+        # the handle's state counter after this forward: any later call that
+        # changes its factors or stored right-hand side moves it on
+        ctx.gen = mesh.state_gen
         ctx.save_for_backward(kappa.detach().clone(), beta_h.clone(), lam, qu)
         return qu
 
@@ -56,17 +45,20 @@ class MacroHDGSolve(torch.autograd.Function):
     def backward(ctx, grad_qu):
         kappa, beta_h, lam, qu = ctx.saved_tensors
         mesh = ctx.mesh
-        if getattr(getattr(mesh, "_ad_state", None), "key", None) != _key(kappa, beta_h, ctx.folded):
+        ctx.reforwarded = mesh.state_gen != ctx.gen
+        if ctx.reforwarded:
             # another solve ran since: restore this problem's factors and traces
             lam, qu = _forward(mesh, kappa, beta_h, ctx.f, ctx.g, ctx.rtol, ctx.restart,
                                ctx.folded)
         s = mesh.sizes
-        dk = torch.empty(s.n_macro, dtype=torch.float64, device="cuda")
-        db = torch.empty(2, dtype=torch.float64, device="cuda")
-        psi_lam = torch.empty(max(s.n_trace, 1), dtype=torch.float64, device="cuda")
-        psi_U = torch.empty(s.n_local, dtype=torch.float64, device="cuda")
+        dev = kappa.device
+        dk = torch.empty(s.n_macro, dtype=torch.float64, device=dev)
+        db = torch.empty(2, dtype=torch.float64, device=dev)
+        psi_lam = torch.empty(max(s.n_trace, 1), dtype=torch.float64, device=dev)
+        psi_U = torch.empty(s.n_local, dtype=torch.float64, device=dev)
         mesh.adjoint(lam, qu, grad_qu.contiguous(), psi_lam, psi_U, dk, db, rtol=ctx.rtol,
                      restart=ctx.restart, folded=ctx.folded)
+        mesh.last_backward_reforwarded = ctx.reforwarded
         return dk, db.to(beta_h.device if beta_h.device.type == "cuda" else "cpu"), None, None, \
             None, None, None, None
 

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1279,9 +1280,26 @@ mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
 // Kernel choices of earlier autotuning runs in this process, per (local
 // size, precision, log2 of the class size): later handles with the same
 // shapes start from them.
+// Shared by every handle of the process, so guarded by a mutex: distinct
+// handles may be factored and tuned from different threads.
+std::mutex& tune_mutex() {
+  static std::mutex mu;
+  return mu;
+}
 std::map<std::array<int, 3>, std::pair<int, int>>& tune_cache() {
   static std::map<std::array<int, 3>, std::pair<int, int>> m;
   return m;
+}
+bool tune_lookup(const std::array<int, 3>& key, std::pair<int, int>* out) {
+  std::lock_guard<std::mutex> g(tune_mutex());
+  auto it = tune_cache().find(key);
+  if (it == tune_cache().end()) return false;
+  *out = it->second;
+  return true;
+}
+void tune_store(const std::array<int, 3>& key, std::pair<int, int> v) {
+  std::lock_guard<std::mutex> g(tune_mutex());
+  tune_cache()[key] = v;
 }
 std::array<int, 3> tune_key(const SizeClass& c, int precision) {
   int b = 0;
@@ -1304,6 +1322,7 @@ const char* mhdg_status_string(int32_t s) {
     case MHDG_ERR_WORKSPACE: return "workspace too small";
     case MHDG_ERR_HIP: return "HIP error";
     case MHDG_ERR_STATE: return "invalid call order";
+    case MHDG_ERR_NONFINITE: return "non-finite local matrix";
   }
   return "unknown status";
 }
@@ -1688,8 +1707,10 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
                                       double tau, int32_t precision, void* ws, size_t ws_bytes,
                                       void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;
-  if (!kappa || !ws || !beta || !(tau > 0.0))
-    return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: null pointer or tau <= 0");
+  if (!kappa || !ws || !beta)
+    return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: null pointer");
+  if (!(tau > 0.0) || !std::isfinite(tau))
+    return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: tau must be finite and > 0");
   for (int64_t i = 0; i < 2 * int64_t(M->n_inst); ++i)
     if (!std::isfinite(beta[i])) return fail(M, MHDG_ERR_INVALID_ARG, "factor_local: non-finite a");
   if (precision != MHDG_FP64 && precision != MHDG_FP32 && precision != MHDG_BF16 &&
@@ -1722,8 +1743,8 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   M->L = factor_layout(M, precision);
   for (auto& c : M->classes)
     if (!c.lu_var && !c.solve_var) {
-      auto it = tune_cache().find(tune_key(c, precision));
-      if (it != tune_cache().end()) { c.lu_var = it->second.first; c.solve_var = it->second.second; }
+      std::pair<int, int> v;
+      if (tune_lookup(tune_key(c, precision), &v)) { c.lu_var = v.first; c.solve_var = v.second; }
     }
   FactorLayout& L = M->L;
   char* w = M->ws;
@@ -1741,7 +1762,23 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
                             hipMemcpyHostToDevice, s));
   // the macro order lives after the permutation vector region: reuse status region size n_macro
   MacroInfo* info = (MacroInfo*)(w + L.meta);
-  HIP_TRY(M, launch_set_kappa(info, kappa, M->n_macro, s));
+  // kappa is read on the device; every value must be finite and > 0 before any
+  // block is assembled or factored
+  {
+    HIP_TRY(M, launch_set_kappa(info, kappa, M->n_macro, (int32_t*)(w + L.status), s));
+    std::vector<int32_t> bad(M->n_macro);
+    HIP_TRY(M, hipMemcpyAsync(bad.data(), w + L.status, bad.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(M, hipStreamSynchronize(s));
+    for (int64_t e = 0; e < M->n_macro; ++e)
+      if (bad[e]) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "factor_local: kappa of macro %lld is not finite and > 0 (first such macro)",
+                 (long long)e);
+        return fail(M, MHDG_ERR_INVALID_ARG, buf);
+      }
+  }
   if (precision == MHDG_QELIM) {
     // the Schur block on u per macro, factored by the same LU kernels through a
     // table whose N / ld / offsets describe the Q x Q blocks
@@ -1800,9 +1837,14 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   for (int64_t e = 0; e < M->n_macro; ++e)
     if (st[e] != 0) {
       char buf[160];
-      snprintf(buf, sizeof buf, "factor_local: zero pivot in macro %lld at column %d",
-               (long long)e, st[e] - 1);
-      return fail(M, MHDG_ERR_SINGULAR, buf);
+      if (st[e] > 0) {
+        snprintf(buf, sizeof buf, "factor_local: zero pivot in macro %lld at column %d",
+                 (long long)e, st[e] - 1);
+        return fail(M, MHDG_ERR_SINGULAR, buf);
+      }
+      snprintf(buf, sizeof buf, "factor_local: non-finite pivot in macro %lld at column %d",
+               (long long)e, -st[e] - 1);
+      return fail(M, MHDG_ERR_NONFINITE, buf);
     }
   M->factored = true;
   return MHDG_OK;
@@ -1997,7 +2039,7 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
       c.solve_var = best;
     }
     rep.solve_variant[ci] = c.solve_var ? c.solve_var : default_solve_variant(c.N);
-    tune_cache()[tune_key(c, M->precision)] = {c.lu_var, c.solve_var};
+    tune_store(tune_key(c, M->precision), {c.lu_var, c.solve_var});
     for (auto& oc : M->one.classes)
       if (oc.N == c.N) { oc.lu_var = c.lu_var; oc.solve_var = c.solve_var; }
   }

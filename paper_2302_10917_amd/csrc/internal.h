@@ -10,6 +10,21 @@ namespace mhdg {
 constexpr int kMaxLevel = 5;
 constexpr int kFactorGuard = 64 * 64;  // elements of readable padding after the last factor block
 
+// Pivot search of the LU kernels: the magnitude compared for a candidate,
+// with NaN ranked above every number so that a column whose candidates are
+// all NaN still picks a row inside the block (and is reported), and the
+// status word of a macro: 0, col + 1 for an exactly zero pivot, or
+// -(col + 1) for a non-finite one (the first failing column).
+__device__ __forceinline__ double pivot_mag(double x) {
+  const double v = fabs(x);
+  return v == v ? v : __builtin_huge_val();
+}
+__device__ __forceinline__ int pivot_status(double best, int col) {
+  if (best == 0.0) return col + 1;
+  if (!(best < __builtin_huge_val())) return -(col + 1);
+  return 0;
+}
+
 // Per-macro data, built on the host at setup and copied into the factor
 // workspace by factor_local.  All doubles first so the layout has no holes.
 struct MacroInfo {
@@ -134,7 +149,9 @@ hipError_t launch_boundary_C(const MacroInfo* info, int64_t n, const double* tmp
                              hipStream_t s);
 
 // ---- kernel launchers (kernels.hip) ----
-hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, hipStream_t s);
+// kappa into the macro table; bad[e] = 1 where kappa[e] is not finite and > 0
+hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, int32_t* bad,
+                            hipStream_t s);
 hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, const int32_t* order,
                            int64_t n, const double* tmpl, const Templates& T, double tau,
                            hipStream_t s);

@@ -132,9 +132,13 @@ __device__ double a_entry(const EntryCtx& c, int r, int col) {
   }
 }
 
-__global__ void set_kappa_kernel(MacroInfo* info, const double* kappa, int64_t n) {
+__global__ void set_kappa_kernel(MacroInfo* info, const double* kappa, int64_t n, int32_t* bad) {
   int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (e < n) info[e].kappa = kappa[e];
+  if (e < n) {
+    const double k = kappa[e];
+    info[e].kappa = k;
+    bad[e] = (k > 0.0 && k < __builtin_huge_val()) ? 0 : 1;
+  }
 }
 
 template <typename T>
@@ -254,15 +258,17 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
     // ---- panel factorisation
     for (int j = 0; j < nb; ++j) {
       const int col = k0 + j;
+      // candidates are rows col..N-1; a NaN counts as +inf so that it is
+      // chosen and reported, and the chosen row always lies in [col, N)
       double best = -1.0;
-      int bidx = 0x7fffffff;
+      int bidx = col;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int row = k0 + tid + q * NT;
         double v = -1.0;
 #pragma unroll
         for (int c = 0; c < NB; ++c)
-          if (c == j) v = fabs((double)pr[q][c]);
+          if (c == j) v = pivot_mag((double)pr[q][c]);
         if (row >= col && row < N && v > best) { best = v; bidx = row; }
       }
 #pragma unroll
@@ -281,7 +287,7 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
         int oi = s_red_i[w];
         if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
       }
-      const int prow = bidx;
+      const int prow = min(max(bidx, col), N - 1);
       const int own_c = (col - k0) % NT, slot_c = (col - k0) / NT;
       const int own_p = (prow - k0) % NT, slot_p = (prow - k0) / NT;
       if (prow != col) {
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(NT) void lu_kernel(T* fac, const MacroInfo* __restr
           for (int c = 0; c < NB; ++c) s_row[c] = pr[q][c];
       if (tid == 0) {
         s_piv[j] = prow;
-        if (best == 0.0 && s_status == 0) s_status = col + 1;
+        if (s_status == 0) s_status = pivot_status(best, col);
       }
       __syncthreads();
       if (best != 0.0) {
@@ -1136,8 +1142,10 @@ __global__ void seg_scale_copy_kernel(const double* __restrict__ alpha, const do
 // ------------------------------------------------------------------ launchers
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(set_kappa_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, info, kappa, n);
+hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, int32_t* bad,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(set_kappa_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, info, kappa, n,
+                     bad);
   return hipGetLastError();
 }
 

@@ -113,15 +113,17 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
       }
       for (int j = 0; j < sb; ++j) {
         const int col = c0 + j;
+        // candidates are rows col..N-1; a NaN counts as +inf so that it is
+        // chosen and reported, and the chosen row always lies in [col, N)
         double best = -1.0;
-        int bidx = 0x7fffffff;
+        int bidx = col;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
           const int row = c0 + tid + q * NT;
           double v = -1.0;
 #pragma unroll
           for (int c = 0; c < SB; ++c)
-            if (c == j) v = fabs((double)pr[q][c]);
+            if (c == j) v = pivot_mag((double)pr[q][c]);
           if (row >= col && row < N && v > best) { best = v; bidx = row; }
         }
 #pragma unroll
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
           int oi = s_red_i[w];
           if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
         }
-        const int prow = bidx;
+        const int prow = min(max(bidx, col), N - 1);
         const int own_c = (col - c0) % NT, slot_c = (col - c0) / NT;
         const int own_p = (prow - c0) % NT, slot_p = (prow - c0) / NT;
         if (prow != col) {
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
             for (int c = 0; c < SB; ++c) s_row[c] = pr[q][c];
         if (tid == 0) {
           s_piv[j] = prow;
-          if (best == 0.0 && s_status == 0) s_status = col + 1;
+          if (s_status == 0) s_status = pivot_status(best, col);
         }
         __syncthreads();
         if (best != 0.0) {

@@ -19,7 +19,7 @@ MHDG_FP64, MHDG_FP32, MHDG_BF16, MHDG_QELIM = 0, 1, 2, 3
 MHDG_PRECONDITION, MHDG_TRANSPOSE, MHDG_GRAPH, MHDG_FOLDED = 1, 2, 4, 8
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "MESH", 3: "SINGULAR", 4: "NOT_CONVERGED",
-          5: "WORKSPACE", 6: "HIP", 7: "STATE"}
+          5: "WORKSPACE", 6: "HIP", 7: "STATE", 8: "NONFINITE"}
 
 ABI_SYMBOLS = [
     "mhdg_setup_macro_mesh", "mhdg_query", "mhdg_sample_points", "mhdg_factor_local",
@@ -191,6 +191,10 @@ class MacroMesh:
         self.solve_ws = None
         self.precision = MHDG_FP64
         self.sizes = self.query()
+        # bumped by every call that changes the factors, the folded operators or
+        # the stored local right-hand sides (lets wrappers tell whether the
+        # handle still holds the state they left in it)
+        self.state_gen = 0
 
     def close(self):
         """Destroy the library handle (its device tables, graphs and private
@@ -217,6 +221,7 @@ class MacroMesh:
 
     def set_instances(self, n_inst: int):
         """n_inst coefficient instances in one handle (instance-major vectors)."""
+        self.state_gen += 1
         self._check(self._lib.mhdg_set_instances(self.h, int(n_inst)), "set_instances")
         self.sizes = self.query()
         self.factor_ws = None
@@ -235,6 +240,7 @@ class MacroMesh:
         return node, bnd[:s.n_bnd_points]
 
     def factor_local(self, kappa, beta, tau=1.0, precision=MHDG_FP64, stream=None):
+        self.state_gen += 1
         import torch
         s = self.query(precision)
         if self.factor_ws is None or self.factor_ws.numel() < s.factor_ws_bytes:
@@ -289,6 +295,7 @@ class MacroMesh:
                     "local_solve")
 
     def rhs(self, f_nodes, g_bnd, fhat, flags=0, stream=None):
+        self.state_gen += 1
         self._check(self._lib.mhdg_rhs(self.h, _ptr(f_nodes), _ptr(g_bnd), _ptr(fhat), flags,
                                        _stream(stream)), "rhs")
 
@@ -296,6 +303,7 @@ class MacroMesh:
               stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True, folded=False,
               classic_gs=False):
         import torch
+        self.state_gen += 1
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
@@ -339,6 +347,7 @@ class MacroMesh:
     def autotune(self, flags=MHDG_TUNE_LU | MHDG_TUNE_SOLVE, stream=None):
         """Time the kernel variants per size class on this handle's data and
         keep the fastest; returns the per-class report."""
+        self.state_gen += 1
         rep = TuneReport()
         self._check(self._lib.mhdg_autotune(self.h, int(flags), ctypes.byref(rep),
                                             _stream(stream)), "autotune")
@@ -347,6 +356,7 @@ class MacroMesh:
     def fold_operator(self, stream=None):
         """Build the folded macro operators T_K = C_K A_K^-1 B_K (FP64 factors
         needed); then apply/solve can use them (MHDG_FOLDED / folded=True)."""
+        self.state_gen += 1
         import torch
         s = self.query(self.precision)
         if getattr(self, "fold_ws", None) is None or self.fold_ws.numel() < s.fold_ws_bytes:
@@ -358,6 +368,7 @@ class MacroMesh:
     def set_supg(self, on: bool):
         """SUPG stabilisation inside the macros (section 3.4) on or off; the
         factors must be computed again afterwards."""
+        self.state_gen += 1
         self._check(self._lib.mhdg_set_supg(self.h, 1 if on else 0), "set_supg")
 
     def set_kernel_variant(self, N, lu_variant=0, solve_variant=0):
