@@ -1,10 +1,16 @@
 """GPU parity of the transposed operator and the hand-written adjoint.
 
-Transposed applies and A^-T solves against the oracle (relative 1e-10);
-dJ/dkappa and dJ/dbeta against the oracle adjoint (relative 1e-8, both sides
-solving to tight tolerances) and against central finite differences of the
-GPU forward solve (relative 1e-5: the FD truncation and solve tolerance
-bound it); the torch.autograd path end to end.
+Transposed applies and A^-T solves against the oracle (relative 1e-10, per
+face and per macro field).  dJ/dkappa and dJ/dbeta against the oracle
+adjoint, which solves the unhybridised system and its transpose directly, at
+the FP64 bar: relative 1e-10 per entry.  Both GPU solves (forward and
+transposed) run to a preconditioned residual of 1e-14 there.  On this 8-macro
+mesh D^-1 S (40 unknowns) has a condition number of 69, so each solve's
+forward error stays below 1e-12, and the gradient, bilinear in the two solutions,
+inherits about twice that.  Against central finite differences of the GPU
+forward solve the bound is 1e-5 relative: the truncation error of a step of
+1e-5 and the solve tolerance set it.  The torch.autograd path runs end to
+end.
 """
 import numpy as np
 import pytest
@@ -12,6 +18,8 @@ import pytest
 from oracle import adjoint as oadj
 from oracle import hdg
 from paper_2302_10917_amd import inputs
+
+import parity as P
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -23,10 +31,6 @@ from paper_2302_10917_amd import autograd as ad  # noqa: E402
 from paper_2302_10917_amd import mhdg  # noqa: E402
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def gpu(x):
@@ -58,16 +62,16 @@ def test_transposed_apply_and_local_solve(spec):
     lam = inputs.random_vector(orc.topo.n_trace, seed=4)
     out = torch.empty(orc.topo.n_trace, dtype=torch.float64, device=DEV)
     m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_TRANSPOSE)
-    assert rel(host(out), S.T @ lam) <= 1e-10
+    assert P.faces(host(out), S.T @ lam, orc.topo) <= 1e-10
     m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_TRANSPOSE | mhdg.MHDG_PRECONDITION)
-    assert rel(host(out), orc.precondition(S.T @ lam)) <= 1e-10
+    assert P.faces(host(out), orc.precondition(S.T @ lam), orc.topo) <= 1e-10
     x = inputs.random_vector(int(orc.topo.local_off[-1]), seed=6)
     y = torch.empty(len(x), dtype=torch.float64, device=DEV)
     m.local_solve(gpu(x), y, mhdg.MHDG_TRANSPOSE)
     yh = host(y)
     for K in range(orc.topo.n_macro):
         lo, hi = orc.topo.local_off[K], orc.topo.local_off[K + 1]
-        assert rel(yh[lo:hi], orc.local_solve(K, x[lo:hi], transpose=True)) <= 1e-10
+        assert P.fields(yh[lo:hi], orc.local_solve(K, x[lo:hi], transpose=True)) <= 1e-10
 
 
 def _u_obs(xy, tri, r, p, kappa, beta, ex, m):
@@ -88,7 +92,7 @@ def test_adjoint_matches_oracle_adjoint():
     qu_obs, f, g = _u_obs(xy, tri, r, p, kappa, beta, ex, m)
     k = gpu(kappa).requires_grad_(True)
     b = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
-    qu = ad.solve(k, b, m, f, g)
+    qu = ad.solve(k, b, m, f, g, rtol=1e-14)
     J = ad.l2_misfit(m, qu, qu_obs)
     J.backward()
     # oracle adjoint with the same u_obs field
@@ -97,9 +101,12 @@ def test_adjoint_matches_oracle_adjoint():
     uo = host(qu_obs).reshape(len(tri), 3, Q)[:, 2, :]
     fo, go = orc.sample(ex)
     Jo, dko, dbo, _, _, _, _ = oadj.gradient(orc, fo, go, [uo[K] for K in range(len(tri))])
-    assert abs(J.item() - Jo) <= 1e-9 * abs(Jo)
-    assert rel(host(k.grad), dko) <= 1e-8
-    assert rel(b.grad.numpy(), dbo) <= 1e-8
+    ek, eb = P.entries(host(k.grad), dko), P.entries(b.grad.numpy(), dbo)
+    print(f"  J {abs(J.item() - Jo) / abs(Jo):.2e}  dJ/dkappa {ek:.2e}  dJ/dbeta {eb:.2e}",
+          flush=True)
+    assert abs(J.item() - Jo) <= 1e-10 * abs(Jo)
+    assert ek <= 1e-10
+    assert eb <= 1e-10
 
 
 def test_adjoint_matches_central_differences_on_gpu():

@@ -16,6 +16,8 @@ import pytest
 from oracle import hdg
 from paper_2302_10917_amd import inputs
 
+import parity as P
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -25,11 +27,6 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2302_10917_amd import mhdg  # noqa: E402
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def gpu(x):
@@ -83,7 +80,7 @@ def test_batched_apply_and_local_solve_match_oracle(batch):
         o = host(out)
         for i, orc in enumerate(orcs):
             sl = slice(i * nt, (i + 1) * nt)
-            assert rel(o[sl], orc.apply(lam[sl], precondition=prec)) <= 1e-10, (i, flags)
+            assert P.faces(o[sl], orc.apply(lam[sl], precondition=prec), orc.topo) <= 1e-10, (i, flags)
     x = inputs.random_vector(N_INST * nl, seed=11)
     y = torch.empty(len(x), dtype=torch.float64, device=DEV)
     m.local_solve(gpu(x), y)
@@ -92,7 +89,7 @@ def test_batched_apply_and_local_solve_match_oracle(batch):
         topo = orc.topo
         for e in (0, topo.n_macro // 2, topo.n_macro - 1):
             lo, hi = i * nl + topo.local_off[e], i * nl + topo.local_off[e + 1]
-            assert rel(yh[lo:hi], orc.local_solve(e, x[lo:hi])) <= 1e-10, (i, e)
+            assert P.fields(yh[lo:hi], orc.local_solve(e, x[lo:hi])) <= 1e-10, (i, e)
 
 
 def _data(m, beta, kap_i, n_inst):
@@ -125,8 +122,8 @@ def test_batched_solve_matches_oracle_per_instance(batch):
         ex = inputs.exp_sin(float(kap_i[i]), beta[i])
         fo, go = orc.sample(ex)
         lam_o, U_o, _ = orc.solve(fo, go)
-        assert rel(lh[i * nt:(i + 1) * nt], lam_o) <= 1e-10, i
-        assert rel(uh[i * nl:(i + 1) * nl], np.concatenate(U_o)) <= 1e-10, i
+        assert P.faces(lh[i * nt:(i + 1) * nt], lam_o, orc.topo) <= 1e-10, i
+        assert P.macros(uh[i * nl:(i + 1) * nl], np.concatenate(U_o), orc.topo) <= 1e-10, i
         _, fhat, _ = orc.condensed(fo, go)
         assert np.linalg.norm(rh[i * nt:(i + 1) * nt]) <= 1e-10 * np.linalg.norm(fhat)
 
@@ -142,6 +139,7 @@ def test_batched_solve_equals_single_instance_solves(batch):
     lh = host(lam)
     nt, nn, nb = one.n_trace, one.n_nodes, one.n_bnd_points
     its = []
+    topo = hdg.Topology(xy, tri, r, p)
     for i in range(N_INST):
         s1 = mhdg.MacroMesh(xy, tri, r, p)
         s1.factor_local(gpu(kappa[i]), beta[i], 1.0)
@@ -150,7 +148,7 @@ def test_batched_solve_equals_single_instance_solves(batch):
                  restart=25, max_iter=5000)
         its.append(s1.last_solve_info["iterations"])
         assert infos[i]["iterations"] == its[-1], (i, infos[i]["iterations"], its[-1])
-        assert rel(lh[i * nt:(i + 1) * nt], host(l1)) <= 1e-13, i
+        assert P.faces(lh[i * nt:(i + 1) * nt], host(l1), topo) <= 1e-13, i
     # the instances need different iteration counts, so masking was exercised
     assert len(set(its)) > 1, its
 
@@ -169,7 +167,7 @@ def test_zero_instance_in_batch_stays_zero(batch):
     ex = inputs.exp_sin(float(kap_i[2]), beta[2])
     fo, go = orcs[2].sample(ex)
     lam_o, _, _ = orcs[2].solve(fo, go)
-    assert rel(lh[2 * nt:3 * nt], lam_o) <= 1e-9
+    assert P.faces(lh[2 * nt:3 * nt], lam_o, orcs[2].topo) <= 1e-9
 
 
 def test_rejected_combinations():

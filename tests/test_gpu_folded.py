@@ -13,6 +13,8 @@ import pytest
 from oracle import hdg
 from paper_2302_10917_amd import inputs
 
+import parity as P
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -22,11 +24,6 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2302_10917_amd import mhdg  # noqa: E402
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def gpu(x):
@@ -70,8 +67,8 @@ def test_folded_apply_matches_oracle_and_unfolded(name):
     for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
         m.apply_trace_operator(gpu(lam), a, flags | mhdg.MHDG_FOLDED)
         m.apply_trace_operator(gpu(lam), b, flags)
-        assert rel(host(a), orc.apply(lam, precondition=prec)) <= 1e-10
-        assert rel(host(a), host(b)) <= 1e-12
+        assert P.faces(host(a), orc.apply(lam, precondition=prec), orc.topo) <= 1e-10
+        assert P.faces(host(a), host(b), orc.topo) <= 1e-12
     # graph replay of the folded apply
     m.apply_trace_operator(gpu(lam), b, mhdg.MHDG_PRECONDITION | mhdg.MHDG_FOLDED | mhdg.MHDG_GRAPH)
     assert torch.equal(a, b)
@@ -81,8 +78,8 @@ def test_folded_apply_matches_oracle_and_unfolded(name):
         m.apply_trace_operator(gpu(lam), a, flags | mhdg.MHDG_FOLDED | mhdg.MHDG_TRANSPOSE)
         m.apply_trace_operator(gpu(lam), b, flags | mhdg.MHDG_TRANSPOSE)
         ref = S.T @ lam
-        assert rel(host(a), orc.precondition(ref) if prec else ref) <= 1e-10
-        assert rel(host(a), host(b)) <= 1e-12
+        assert P.faces(host(a), orc.precondition(ref) if prec else ref, orc.topo) <= 1e-10
+        assert P.faces(host(a), host(b), orc.topo) <= 1e-12
 
 
 def test_folded_solve_matches_oracle():
@@ -99,10 +96,10 @@ def test_folded_solve_matches_oracle():
     lam = torch.zeros(orc.topo.n_trace, dtype=torch.float64, device=DEV)
     info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=5000, folded=True)
     assert info.status == 0 and info.rel_res_prec <= 1e-13 and info.rel_res_true <= 1e-11
-    assert rel(host(lam), lam_o) <= 1e-10
+    assert P.faces(host(lam), lam_o, orc.topo) <= 1e-10
     qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
     m.recover_local(lam, qu)
-    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    assert P.macros(host(qu), np.concatenate(U_o), orc.topo) <= 1e-10
 
 
 def test_folded_batched_instances():
@@ -123,7 +120,7 @@ def test_folded_batched_instances():
     for i in range(3):
         orc = hdg.Oracle(xy, tri, r, p, kappa[i], beta[i], 1.0)
         sl = slice(i * nt, (i + 1) * nt)
-        assert rel(o[sl], orc.apply(lam[sl], precondition=True)) <= 1e-10, i
+        assert P.faces(o[sl], orc.apply(lam[sl], precondition=True), orc.topo) <= 1e-10, i
 
 
 def test_fold_state_rules():
@@ -166,5 +163,5 @@ def test_folded_adjoint_matches_unfolded():
         J.backward()
         grads.append((host(k.grad), b.grad.numpy().copy(), J.item()))
     assert abs(grads[0][2] - grads[1][2]) <= 1e-9 * abs(grads[0][2])
-    assert rel(grads[1][0], grads[0][0]) <= 1e-8
-    assert rel(grads[1][1], grads[0][1]) <= 1e-8
+    assert P.entries(grads[1][0], grads[0][0]) <= 1e-8
+    assert P.entries(grads[1][1], grads[0][1]) <= 1e-8

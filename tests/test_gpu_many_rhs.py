@@ -16,6 +16,8 @@ import pytest
 from oracle import hdg
 from paper_2302_10917_amd import inputs
 
+import parity as P
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -25,11 +27,6 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2302_10917_amd import mhdg  # noqa: E402
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def gpu(x):
@@ -79,9 +76,9 @@ def test_many_matches_oracle_and_single(name):
         outh = host(out)
         for v in range(n_rhs):
             m.apply_trace_operator(lam[v], one, flags)
-            assert rel(outh[v], host(one)) <= 1e-12, (flags, v)
+            assert P.faces(outh[v], host(one), orc.topo) <= 1e-12, (flags, v)
         for v in (0, 5, n_rhs - 1):
-            err = rel(outh[v], orc.apply(lam_h[v], precondition=prec))
+            err = P.faces(outh[v], orc.apply(lam_h[v], precondition=prec), orc.topo)
             print(f"  flags={flags} vector {v}: {err:.2e} against the oracle", flush=True)
             assert err <= 1e-10, (flags, v)
 
@@ -99,9 +96,10 @@ def test_many_vector_counts(n_rhs):
     one = torch.empty(n, dtype=torch.float64, device=DEV)
     m.apply_trace_operator_many(lam, out, mhdg.MHDG_PRECONDITION)
     outh = host(out)
+    topo = hdg.Topology(xy, tri, r, p)
     for v in range(n_rhs):
         m.apply_trace_operator(lam[v], one, mhdg.MHDG_PRECONDITION)
-        assert rel(outh[v], host(one)) <= 1e-12, v
+        assert P.faces(outh[v], host(one), topo) <= 1e-12, v
 
 
 @pytest.mark.parametrize("name,precision", [("r3_p3", mhdg.MHDG_FP64),
@@ -128,9 +126,9 @@ def test_folded_many_matches_single_and_oracle(name, precision):
         outh = host(out)
         for v in range(11):
             m.apply_trace_operator(lam[v], one, flags)
-            assert rel(outh[v], host(one)) <= 1e-12, (flags, v)
+            assert P.faces(outh[v], host(one), orc.topo) <= 1e-12, (flags, v)
         for v in (0, 10):
-            assert rel(outh[v], orc.apply(lam_h[v], precondition=prec)) <= 1e-10, (flags, v)
+            assert P.faces(outh[v], orc.apply(lam_h[v], precondition=prec), orc.topo) <= 1e-10, (flags, v)
 
 
 def test_many_with_instances():
@@ -151,14 +149,16 @@ def test_many_with_instances():
     one = torch.empty(n, dtype=torch.float64, device=DEV)
     m.apply_trace_operator_many(gpu(lam_h), out, mhdg.MHDG_PRECONDITION)
     outh = host(out)
+    topo = hdg.Topology(xy, tri, r, p)
     for v in range(5):
         m.apply_trace_operator(gpu(lam_h[v]), one, mhdg.MHDG_PRECONDITION)
-        assert rel(outh[v], host(one)) <= 1e-12, v
+        # n_inst instances back to back: P.faces compares each one face by face
+        assert P.faces(outh[v], host(one), topo) <= 1e-12, v
     # instance 1 of vector 2 against the oracle of that instance
     i, v = 1, 2
     orc = hdg.Oracle(xy, tri, r, p, kap[i * len(tri):(i + 1) * len(tri)], tuple(beta[i]), 1.0)
     seg = slice(i * n_one, (i + 1) * n_one)
-    assert rel(outh[v][seg], orc.apply(lam_h[v][seg], precondition=True)) <= 1e-10
+    assert P.faces(outh[v][seg], orc.apply(lam_h[v][seg], precondition=True), orc.topo) <= 1e-10
 
 
 def test_many_errors():

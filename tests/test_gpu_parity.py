@@ -16,6 +16,8 @@ import pytest
 from oracle import hdg
 from paper_2302_10917_amd import inputs
 
+import parity as P
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -25,11 +27,6 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2302_10917_amd import mhdg  # noqa: E402
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def gpu(x):
@@ -93,7 +90,7 @@ def test_local_solve_matches_oracle(case):
     for e in range(topo.n_macro):
         lo, hi = topo.local_off[e], topo.local_off[e + 1]
         yo = orc.local_solve(e, x[lo:hi])
-        assert rel(yh[lo:hi], yo) <= 1e-10, e
+        assert P.fields(yh[lo:hi], yo) <= 1e-10, e
 
 
 def test_apply_matches_oracle(case):
@@ -103,7 +100,7 @@ def test_apply_matches_oracle(case):
     out = torch.empty(n, dtype=torch.float64, device=DEV)
     for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
         m.apply_trace_operator(gpu(lam), out, flags)
-        assert rel(host(out), orc.apply(lam, precondition=prec)) <= 1e-10
+        assert P.faces(host(out), orc.apply(lam, precondition=prec), orc.topo) <= 1e-10
 
 
 def test_apply_is_deterministic(case):
@@ -133,7 +130,7 @@ def test_rhs_matches_oracle(case):
     S, fhat, _ = orc.condensed(fo, go)
     out = torch.empty(max(orc.topo.n_trace, 1), dtype=torch.float64, device=DEV)
     m.rhs(gpu(f), gpu(g), out)
-    assert rel(host(out)[:orc.topo.n_trace], fhat) <= 1e-10
+    assert P.faces(host(out)[:orc.topo.n_trace], fhat, orc.topo) <= 1e-10
 
 
 def test_solve_and_recover_match_oracle(case):
@@ -144,11 +141,11 @@ def test_solve_and_recover_match_oracle(case):
     lam = torch.zeros(topo.n_trace, dtype=torch.float64, device=DEV)
     info = m.solve(gpu(f), gpu(g), lam, rtol=1e-13, restart=200, max_iter=5000)
     assert info.status == 0 and info.rel_res_prec <= 1e-13
-    assert rel(host(lam), lam_o) <= 1e-10
+    assert P.faces(host(lam), lam_o, topo) <= 1e-10
     qu = torch.empty(int(topo.local_off[-1]), dtype=torch.float64, device=DEV)
     res = torch.empty(topo.n_trace, dtype=torch.float64, device=DEV)
     m.recover_local(lam, qu, res)
-    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    assert P.macros(host(qu), np.concatenate(U_o), topo) <= 1e-10
     # transmission residual C U + D lam = S lam - f^ is at the GMRES residual level
     S, fhat, _ = orc.condensed(fo, go)
     assert np.linalg.norm(host(res)) <= 1e-10 * np.linalg.norm(fhat)
@@ -172,7 +169,7 @@ def test_flux_balance_matches_oracle(case):
     m.flux_balance(lam, gpu(qu_h), gpu(f), out)
     U = [qu_h[topo.local_off[K]:topo.local_off[K + 1]] for K in range(topo.n_macro)]
     ref = orc.flux_balance(U, lam_h, lamD, fo)
-    assert rel(host(out), ref) <= 1e-12
+    assert P.entries(host(out), ref) <= 1e-12
     qu = torch.empty(nl, dtype=torch.float64, device=DEV)
     m.recover_local(lam, qu)
     m.flux_balance(lam, qu, gpu(f), out)
@@ -212,7 +209,7 @@ def test_single_macro_has_no_trace_unknowns():
     m.recover_local(lam, qu)
     fo, go = orc.sample(ex)
     _, U_o, _ = orc.solve(fo, go)
-    assert rel(host(qu), U_o[0]) <= 1e-12
+    assert P.fields(host(qu), U_o[0]) <= 1e-12
 
 
 def test_polynomial_reproduction_on_gpu():
@@ -255,6 +252,6 @@ def test_delayed_and_classical_gram_schmidt_agree(restart):
                        classic_gs=classic)
         assert info.status == 0 and info.rel_res_prec <= 1e-12
         out.append((host(lam), info.iterations))
-        assert rel(out[-1][0], lam_o) <= 1e-9
+        assert P.faces(out[-1][0], lam_o, orc.topo) <= 1e-9
     assert abs(out[0][1] - out[1][1]) <= 1 + out[1][1] // 50
-    assert rel(out[0][0], out[1][0]) <= 1e-9
+    assert P.faces(out[0][0], out[1][0], orc.topo) <= 1e-9

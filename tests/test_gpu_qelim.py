@@ -15,6 +15,8 @@ import pytest
 from oracle import hdg
 from paper_2302_10917_amd import inputs
 
+import parity as P
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -24,11 +26,6 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2302_10917_amd import mhdg  # noqa: E402
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def gpu(x):
@@ -79,7 +76,7 @@ def test_local_solve_matches_oracle(case):
     yh = host(y)
     for e in range(topo.n_macro):
         lo, hi = topo.local_off[e], topo.local_off[e + 1]
-        assert rel(yh[lo:hi], orc.local_solve(e, x[lo:hi])) <= 1e-10, (name, e)
+        assert P.fields(yh[lo:hi], orc.local_solve(e, x[lo:hi])) <= 1e-10, (name, e)
 
 
 def test_apply_matches_oracle_and_full_block_path(case):
@@ -95,8 +92,8 @@ def test_apply_matches_oracle_and_full_block_path(case):
     for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
         m.apply_trace_operator(gpu(lam), a, flags)
         full.apply_trace_operator(gpu(lam), b, flags)
-        assert rel(host(a), orc.apply(lam, precondition=prec)) <= 1e-10, (name, flags)
-        assert rel(host(a), host(b)) <= 1e-11, (name, flags)
+        assert P.faces(host(a), orc.apply(lam, precondition=prec), orc.topo) <= 1e-10, (name, flags)
+        assert P.faces(host(a), host(b), orc.topo) <= 1e-11, (name, flags)
     # graph replay equals the eager launches bit for bit
     m.apply_trace_operator(gpu(lam), b, mhdg.MHDG_PRECONDITION | mhdg.MHDG_GRAPH)
     for _ in range(3):
@@ -117,16 +114,16 @@ def test_solve_and_recover_match_oracle(case):
         S, fhat, _ = orc.condensed(fo, go)
         fh = torch.empty(n, dtype=torch.float64, device=DEV)
         m.rhs(f, g, fh, mhdg.MHDG_PRECONDITION)
-        assert rel(host(fh), orc.precondition(fhat)) <= 1e-10
+        assert P.faces(host(fh), orc.precondition(fhat), orc.topo) <= 1e-10
     lam = torch.zeros(max(n, 1), dtype=torch.float64, device=DEV)[:n]
     info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=5000)
     assert info.status == 0
     if n:
-        assert rel(host(lam), lam_o) <= 1e-10, name
+        assert P.faces(host(lam), lam_o, orc.topo) <= 1e-10, name
     qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
     res = torch.empty(max(n, 1), dtype=torch.float64, device=DEV)[:n]
     m.recover_local(lam, qu, res if n else None)
-    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10, name
+    assert P.macros(host(qu), np.concatenate(U_o), orc.topo) <= 1e-10, name
     if n:
         assert np.linalg.norm(host(res)) <= 1e-10 * np.linalg.norm(fhat)
     # macro conservation of the fields recovered through the Schur block
@@ -156,7 +153,7 @@ def test_instances_match_oracle_per_instance():
         orc = hdg.Oracle(xy, tri, r, p, kappa[i], beta[i], 1.0)
         orcs.append(orc)
         sl = slice(i * nt, (i + 1) * nt)
-        assert rel(o[sl], orc.apply(lam[sl], precondition=True)) <= 1e-10, i
+        assert P.faces(o[sl], orc.apply(lam[sl], precondition=True), orc.topo) <= 1e-10, i
         ex = inputs.exp_sin(float(kap_i[i]), beta[i])
         a, b = i * one.n_nodes, (i + 1) * one.n_nodes
         fh[a:b] = ex.f(node[a:b, 0], node[a:b, 1])
@@ -169,7 +166,7 @@ def test_instances_match_oracle_per_instance():
     for i in range(3):
         ex = inputs.exp_sin(float(kap_i[i]), beta[i])
         lam_o, _, _ = orcs[i].solve(*orcs[i].sample(ex))
-        assert rel(lh[i * nt:(i + 1) * nt], lam_o) <= 1e-10, i
+        assert P.faces(lh[i * nt:(i + 1) * nt], lam_o, orc.topo) <= 1e-10, i
     m.close()
 
 
@@ -211,8 +208,8 @@ def test_folded_from_schur_factors_matches_oracle(name):
     for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
         m.apply_trace_operator(gpu(lam), a, flags | mhdg.MHDG_FOLDED)
         m.apply_trace_operator(gpu(lam), b, flags)
-        assert rel(host(a), orc.apply(lam, precondition=prec)) <= 1e-10, (name, flags)
-        assert rel(host(a), host(b)) <= 1e-12, (name, flags)
+        assert P.faces(host(a), orc.apply(lam, precondition=prec), orc.topo) <= 1e-10, (name, flags)
+        assert P.faces(host(a), host(b), orc.topo) <= 1e-12, (name, flags)
     ex = inputs.exp_sin(0.2, beta)
     node, bnd = m.sample_points()
     f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
@@ -220,10 +217,10 @@ def test_folded_from_schur_factors_matches_oracle(name):
     x = torch.zeros(n, dtype=torch.float64, device=DEV)
     info = m.solve(f, g, x, rtol=1e-13, restart=50, max_iter=20000, folded=True)
     assert info.status == 0
-    assert rel(host(x), lam_o) <= 1e-10
+    assert P.faces(host(x), lam_o, orc.topo) <= 1e-10
     qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
     m.recover_local(x, qu)
-    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    assert P.macros(host(qu), np.concatenate(U_o), orc.topo) <= 1e-10
     m.close()
 
 
@@ -245,6 +242,6 @@ def test_folded_instances_from_schur_factors():
     for i in range(3):
         orc = hdg.Oracle(xy, tri, r, p, kappa[i], beta[i], 1.0)
         sl = slice(i * nt, (i + 1) * nt)
-        assert rel(o[sl], orc.apply(lam[sl], precondition=True)) <= 1e-10, i
+        assert P.faces(o[sl], orc.apply(lam[sl], precondition=True), orc.topo) <= 1e-10, i
     m.close()
 

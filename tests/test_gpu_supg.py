@@ -17,6 +17,8 @@ import pytest
 from oracle import hdg
 from paper_2302_10917_amd import inputs
 
+import parity as P
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -26,11 +28,6 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2302_10917_amd import mhdg  # noqa: E402
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def gpu(x):
@@ -99,19 +96,19 @@ def test_supg_apply_rhs_solve_recover_match_oracle(case):
     out = torch.empty(n, dtype=torch.float64, device=DEV)
     for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
         m.apply_trace_operator(gpu(lam_r), out, flags)
-        assert rel(host(out), orc.apply(lam_r, precondition=prec)) <= 1e-10
+        assert P.faces(host(out), orc.apply(lam_r, precondition=prec), topo) <= 1e-10
     f, g, fo, go = data(orc, m, kappa, beta)
     S, fhat, _ = orc.condensed(fo, go)
     m.rhs(f, g, out)
-    assert rel(host(out), fhat) <= 1e-10
+    assert P.faces(host(out), fhat, topo) <= 1e-10
     lam_o, U_o, lamD = orc.solve(fo, go)
     lam = torch.zeros(n, dtype=torch.float64, device=DEV)
     info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=20000)
     assert info.status == 0
-    assert rel(host(lam), lam_o) <= 1e-10
+    assert P.faces(host(lam), lam_o, topo) <= 1e-10
     qu = torch.empty(int(topo.local_off[-1]), dtype=torch.float64, device=DEV)
     m.recover_local(lam, qu)
-    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    assert P.macros(host(qu), np.concatenate(U_o), topo) <= 1e-10
     cons = torch.empty(topo.n_macro, dtype=torch.float64, device=DEV)
     m.flux_balance(lam, qu, f, cons)
     assert np.abs(host(cons)).max() <= 1e-11
@@ -129,10 +126,10 @@ def test_supg_fp32_refined_solve_matches_oracle():
     info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=20000, inner_rtol=1e-4)
     print(f"  outer={info.outer_iterations} inner={info.iterations}", flush=True)
     assert info.status == 0 and info.outer_iterations >= 2
-    assert rel(host(lam), lam_o) <= 1e-10
+    assert P.faces(host(lam), lam_o, topo) <= 1e-10
     qu = torch.empty(int(topo.local_off[-1]), dtype=torch.float64, device=DEV)
     m.recover_local(lam, qu)
-    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    assert P.macros(host(qu), np.concatenate(U_o), topo) <= 1e-10
 
 
 @pytest.mark.parametrize("name", ["mixed_p2", "r2_p3"])
@@ -144,19 +141,19 @@ def test_supg_flux_eliminated_and_folded_match_oracle(name):
     out = torch.empty(n, dtype=torch.float64, device=DEV)
     ref = orc.apply(lam_r, precondition=True)
     m.apply_trace_operator(gpu(lam_r), out, mhdg.MHDG_PRECONDITION)
-    assert rel(host(out), ref) <= 1e-10
+    assert P.faces(host(out), ref, topo) <= 1e-10
     m.fold_operator()
     m.apply_trace_operator(gpu(lam_r), out, mhdg.MHDG_PRECONDITION | mhdg.MHDG_FOLDED)
-    assert rel(host(out), ref) <= 1e-10
+    assert P.faces(host(out), ref, topo) <= 1e-10
     f, g, fo, go = data(orc, m, kappa, beta)
     lam_o, U_o, _ = orc.solve(fo, go)
     lam = torch.zeros(n, dtype=torch.float64, device=DEV)
     info = m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=20000, folded=True)
     assert info.status == 0
-    assert rel(host(lam), lam_o) <= 1e-10
+    assert P.faces(host(lam), lam_o, topo) <= 1e-10
     qu = torch.empty(int(topo.local_off[-1]), dtype=torch.float64, device=DEV)
     m.recover_local(lam, qu)
-    assert rel(host(qu), np.concatenate(U_o)) <= 1e-10
+    assert P.macros(host(qu), np.concatenate(U_o), topo) <= 1e-10
 
 
 def test_supg_off_restores_the_plain_forms():
@@ -171,8 +168,8 @@ def test_supg_off_restores_the_plain_forms():
     m.factor_local(gpu(orc.kappa), beta, 1.0)
     m.apply_trace_operator(lam_r, out, mhdg.MHDG_PRECONDITION)
     lh = host(lam_r)
-    assert rel(host(out), plain.apply(lh, precondition=True)) <= 1e-10
-    assert rel(host(out), orc.apply(lh, precondition=True)) > 1e-6
+    assert P.faces(host(out), plain.apply(lh, precondition=True), orc.topo) <= 1e-10
+    assert P.faces(host(out), orc.apply(lh, precondition=True), orc.topo) > 1e-6
 
 
 def test_supg_adjoint_is_rejected():
@@ -238,7 +235,7 @@ def test_supg_with_instances_matches_oracle():
         o = host(out)
         for i, orc in enumerate(orcs):
             sl = slice(i * nt, (i + 1) * nt)
-            assert rel(o[sl], orc.apply(lam[sl], precondition=True)) <= 1e-10, (order, i)
+            assert P.faces(o[sl], orc.apply(lam[sl], precondition=True), orc.topo) <= 1e-10, (order, i)
     # batched solve against each instance's oracle solve
     node, bnd = m.sample_points()
     s = m.sizes
@@ -255,4 +252,4 @@ def test_supg_with_instances_matches_oracle():
     for i, (orc, ex) in enumerate(zip(orcs, exs)):
         fo, go = orc.sample(ex)
         lam_o, _, _ = orc.solve(fo, go)
-        assert rel(lh[i * nt:(i + 1) * nt], lam_o) <= 1e-10, i
+        assert P.faces(lh[i * nt:(i + 1) * nt], lam_o, orc.topo) <= 1e-10, i

@@ -11,6 +11,8 @@ import pytest
 from oracle import hdg
 from paper_2302_10917_amd import inputs
 
+import parity as P
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -20,11 +22,6 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2302_10917_amd import mhdg  # noqa: E402
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    b = np.asarray(b)
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def gpu(x):
@@ -76,12 +73,12 @@ def test_variant_matches_oracle(shape, lu, sv):
     yh = host(y)
     for e in range(topo.n_macro):
         lo, hi = topo.local_off[e], topo.local_off[e + 1]
-        assert rel(yh[lo:hi], orc.local_solve(e, x[lo:hi])) <= 1e-10, (name, lu, sv, e)
+        assert P.fields(yh[lo:hi], orc.local_solve(e, x[lo:hi])) <= 1e-10, (name, lu, sv, e)
     if topo.n_trace:
         lam = inputs.random_vector(topo.n_trace, seed=1)
         out = torch.empty(topo.n_trace, dtype=torch.float64, device=DEV)
         m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_PRECONDITION)
-        assert rel(host(out), orc.apply(lam, precondition=True)) <= 1e-10, (name, lu, sv)
+        assert P.faces(host(out), orc.apply(lam, precondition=True), topo) <= 1e-10, (name, lu, sv)
 
 
 def test_fp32_blocked_lu_is_close():
@@ -95,7 +92,7 @@ def test_fp32_blocked_lu_is_close():
     lam = inputs.random_vector(orc.topo.n_trace, seed=1)
     out = torch.empty(orc.topo.n_trace, dtype=torch.float64, device=DEV)
     m.apply_trace_operator(gpu(lam), out, mhdg.MHDG_PRECONDITION)
-    assert rel(host(out), orc.apply(lam, precondition=True)) <= 1e-3
+    assert P.faces(host(out), orc.apply(lam, precondition=True), orc.topo) <= 1e-3
 
 
 def test_autotune_keeps_a_valid_factor_state():
@@ -119,7 +116,7 @@ def test_autotune_keeps_a_valid_factor_state():
     lam_o, U_o, _ = orc.solve(fo, go)
     lam = torch.zeros(m.sizes.n_trace, dtype=torch.float64, device=DEV)
     m.solve(f, g, lam, rtol=1e-13, restart=300, max_iter=5000)
-    assert rel(host(lam), lam_o) <= 1e-10
+    assert P.faces(host(lam), lam_o, orc.topo) <= 1e-10
     # a second handle of the same shapes starts from the tuned choice
     m2 = mhdg.MacroMesh(xy, tri, r, 2)
     m2.factor_local(gpu(kap), beta, 1.0)
