@@ -2,9 +2,10 @@
 
 A step is one pass of the whole hot path over the plain-FP64-at-scale
 workload: factor_local (assemble + pivoted LU of every A_K), solve (right-hand
-side, then GMRES on the trace system to a 1e-10 preconditioned relative
-residual) and recover_local.  Inputs (mesh metadata, kappa, f and g_D
-samples) are resident in HBM before the timed region.
+side, then GMRES on the trace system until the relative residual
+||f^ - S lam|| / ||f^|| is at most 1e-10, checked exactly at every restart)
+and recover_local.  Inputs (mesh metadata, kappa, f and g_D samples) are
+resident in HBM before the timed region.
 
 Workload (default): unit square, 64 x 64 squares -> 8192 macro-triangles,
 r = 3 (64 sub-triangles each), p = 3, kappa = 1e-2, a = (1, 0.5), tau = 1,
@@ -213,11 +214,53 @@ def cpu_baseline(xy, tri, w, lam_seed=1, n_sample=16, budget_s=15.0):
             break
     t = (time.perf_counter() - t0) / reps
     per_apply = t * n_macro / len(sample)
+    o7 = oracle_condensation_time(orc, sample[:4])
     return {"value": 1.0 / per_apply, "unit": "applies/s", "cores": cores, "kind": "oracle",
             "sample": (f"steps 1-3 (x = B lam, lu_solve, C y) on {len(sample)} of {n_macro} "
                        f"macros, {reps} repetitions, scaled by {n_macro / len(sample):.0f}; "
                        f"assembly + lu_factor of the sample took {t_setup:.1f} s and is excluded"),
-            "cpu": _cpu_model()}
+            "cpu": _cpu_model(), "os_cpu_count": os.cpu_count(),
+            "condensation": o7}
+
+
+def oracle_condensation_time(orc, sample):
+    """The oracle's per-macro condensation (assembly of A_K, B_K, C_K, lu_factor,
+    S_K = -C_K A_K^-1 B_K on the interior faces and f^_K; the step before its sparse
+    direct solve) timed on a few macros with one BLAS thread and with all of them,
+    extrapolated to the whole mesh by the macro count."""
+    import scipy.linalg as sla
+    from threadpoolctl import threadpool_limits, threadpool_info
+    f = np.ones(int(orc.topo.node_off[-1]))
+    lamD = orc.dirichlet_trace(np.zeros(orc.topo.n_bnd))
+
+    def one_pass():
+        t0 = time.perf_counter()
+        for K in sample:
+            K = int(K)
+            orc._cache.clear()
+            b = orc.blocks(K)
+            lu = orc.lu(K)
+            icols = orc._interior_cols(K)
+            if icols:
+                Bi = np.hstack([b.B[k] for k, _, _ in icols])
+                Ci = np.vstack([b.C[k] for k, _, _ in icols])
+                _ = -Ci @ sla.lu_solve(lu, Bi)
+                _ = -Ci @ sla.lu_solve(lu, orc.local_rhs(K, f, lamD))
+        orc._cache.clear()
+        return (time.perf_counter() - t0) / len(sample)
+
+    with threadpool_limits(1):
+        t1 = one_pass()
+    t_all = one_pass()
+    threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    n = orc.topo.n_macro
+    return {"per_macro_s_1_thread": t1, "per_macro_s_all_threads": t_all,
+            "all_threads": threads,
+            "whole_mesh_s_1_thread": t1 * n, "whole_mesh_s_all_threads": t_all * n,
+            "whole_mesh_s_one_macro_per_core_estimate": t1 * n / (os.cpu_count() or 1),
+            "sample": f"{len(sample)} macros, extrapolated by {n / len(sample):.0f}",
+            "direct_solve": "the sparse LU of the assembled S (SuperLU) is not timed here: "
+                            "it is minutes on the host at the 8192-macro size"}
 
 
 def _cpu_model():
@@ -274,6 +317,16 @@ def main():
                          "the timed steps")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel shapes (no autotuning before the warmup)")
+    ap.add_argument("--stop-norm", choices=["true", "preconditioned"], default="true",
+                    help="stopping test of the FP64 and flux-eliminated solves: the "
+                         "unpreconditioned relative residual ||f^ - S lam|| / ||f^|| (default) "
+                         "or the preconditioned one; reduced-precision factors stop on the "
+                         "refined system's residual")
+    ap.add_argument("--driver", choices=["device", "host"], default="device",
+                    help="GMRES driver: Arnoldi recurrences on the device, one host wait per "
+                         "restart cycle (default), or on the host, one wait per iteration")
+    ap.add_argument("--no-jitter-control", action="store_true",
+                    help="default job: skip the jittered-mesh control (factor + 20 applies)")
     ap.add_argument("--max-iter", type=int, default=20000,
                     help="GMRES iteration cap (a short cap is for counter runs only)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -350,13 +403,23 @@ def main():
 
     inst_infos = []
 
+    stop = (mhdg.MHDG_NORM_TRUE if args.stop_norm == "true" and not reduced
+            else mhdg.MHDG_NORM_PRECONDITIONED)
+    drv = mhdg.MHDG_DRIVER_DEVICE if args.driver == "device" else mhdg.MHDG_DRIVER_HOST
+    if stop == mhdg.MHDG_NORM_TRUE and drv == mhdg.MHDG_DRIVER_HOST:
+        stop = mhdg.MHDG_NORM_PRECONDITIONED
+    # the plain form's cycles run as direct launches, so that every apply is
+    # bracketed by HIP events for the roofline (its 11 ms applies leave no
+    # launch overhead to hide); the folded forms replay captured cycles
+    sgraph = folded
+
     def step():
         m.factor_local(kappa, beta_arg, 1.0, precision=prec)
         if folded:
             m.fold_operator()
         info = m.solve(f, g, lam, rtol=args.rtol, restart=args.restart, max_iter=args.max_iter,
                        check=args.max_iter >= 20000, inner_rtol=args.inner_rtol, folded=folded,
-                       max_outer=60)
+                       max_outer=60, graph=sgraph, driver=drv, stop_norm=stop)
         m.recover_local(lam, qu)
         infos.append(info.as_dict())
         inst_infos.append(m.last_solve_infos)
@@ -404,6 +467,13 @@ def main():
         m.apply_trace_operator(lam_r, out, aflags)
     torch.cuda.synchronize()
     apply_only = args.apply_reps / (time.perf_counter() - ta)
+    # the same applies with events around each kernel (used for the roofline when the
+    # timed solves replayed captured cycles, which carry no per-apply events)
+    m.profile(True)
+    for _ in range(args.apply_reps):
+        m.apply_trace_operator(lam_r, out, aflags)
+    torch.cuda.synchronize()
+    kt_apply = m.profile(False)
 
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -436,7 +506,7 @@ def main():
             m.factor_local(kappa, beta_arg, 1.0, precision=prec)
             m.fold_operator()
             inf = m.solve(f, g, lam, rtol=args.rtol, restart=args.folded_restart,
-                          max_iter=args.max_iter, folded=True)
+                          max_iter=args.max_iter, folded=True, driver=drv, stop_norm=stop)
             m.recover_local(lam, qu)
             f_infos.append(inf.as_dict())
         fstep()                                  # warm-up (captures the folded graph)
@@ -453,6 +523,9 @@ def main():
             "iterations": [x["iterations"] for x in f_infos],
             "gmres_restart": args.folded_restart,
             "speedup_vs_plain": (ms_per_step / 1e3) / tf,
+            "rel_res_true": max(x["rel_res_true"] for x in f_infos),
+            "rel_res_prec": max(x["rel_res_prec"] for x in f_infos),
+            "cycles": f_infos[-1]["cycles"], "host_waits": f_infos[-1]["host_waits"],
             "max_rel_diff_lambda_vs_plain":
                 float(torch.linalg.norm(lam - lam_plain) / torch.linalg.norm(lam_plain)),
             "what": "T_K = C_K A_K^-1 B_K stored per macro after the LU (built with the "
@@ -468,7 +541,7 @@ def main():
             m.factor_local(kappa, beta_arg, 1.0, precision=mhdg.MHDG_QELIM)
             m.fold_operator()
             inf = m.solve(f, g, lam, rtol=args.rtol, restart=args.folded_restart,
-                          max_iter=args.max_iter, folded=True)
+                          max_iter=args.max_iter, folded=True, driver=drv, stop_norm=stop)
             m.recover_local(lam, qu)
             q_infos.append(inf.as_dict())
         qstep()
@@ -485,12 +558,52 @@ def main():
             "iterations": [x["iterations"] for x in q_infos],
             "gmres_restart": args.folded_restart,
             "speedup_vs_plain": (ms_per_step / 1e3) / tq,
+            "rel_res_true": max(x["rel_res_true"] for x in q_infos),
+            "rel_res_prec": max(x["rel_res_prec"] for x in q_infos),
+            "cycles": q_infos[-1]["cycles"], "host_waits": q_infos[-1]["host_waits"],
             "max_rel_diff_lambda_vs_plain":
                 float(torch.linalg.norm(lam - lam_plain) / torch.linalg.norm(lam_plain)),
             "what": "q eliminated exactly through the reference mass; LU of the Q x Q Schur "
                     "block on u only; T_K = C_K A_K^-1 B_K from it; folded GMRES applies"}
         print(f"[bench] folded from Schur factors: {tuned['folded_flux_eliminated_fp64']}",
               file=sys.stderr, flush=True)
+
+    jitter = None
+    if not args.no_jitter_control and args.workload == "plain_fp64_8192macro_r3_p3":
+        # control: the same job on a mesh whose interior vertices move by up to 0.15 h in
+        # each coordinate (seed 7), so no two macros share a Jacobian: factorisation and
+        # applies must cost what they cost on the uniform mesh (nothing is reused between
+        # macros that happen to be congruent)
+        print("[bench] jittered-mesh control: factor + 20 applies", file=sys.stderr, flush=True)
+
+        def factor_and_applies(mm):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mm.factor_local(kappa, beta_arg, 1.0)
+            torch.cuda.synchronize()
+            t_f = time.perf_counter() - t0
+            o = torch.empty_like(lam_r)
+            mm.apply_trace_operator(lam_r, o, mhdg.MHDG_PRECONDITION | mhdg.MHDG_GRAPH)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(20):
+                mm.apply_trace_operator(lam_r, o, mhdg.MHDG_PRECONDITION | mhdg.MHDG_GRAPH)
+            torch.cuda.synchronize()
+            return t_f, (time.perf_counter() - t1) / 20
+
+        uni = factor_and_applies(m)
+        xyj, trij = inputs.structured_mesh(w["n"], jitter=0.15, seed=7)
+        mj = mhdg.MacroMesh(xyj, trij, w["r"], w["p"])
+        jit = factor_and_applies(mj)
+        mj.close()
+        del mj
+        torch.cuda.empty_cache()
+        jitter = {"mesh": f"{w['n']} x {w['n']} squares, interior vertices moved by "
+                          f"U(-0.15 h, 0.15 h) per coordinate, seed 7",
+                  "factor_s": jit[0], "apply_ms": 1e3 * jit[1],
+                  "uniform_factor_s": uni[0], "uniform_apply_ms": 1e3 * uni[1],
+                  "factor_ratio": jit[0] / uni[0], "apply_ratio": jit[1] / uni[1]}
+        print(f"[bench] jittered control: {jitter}", file=sys.stderr, flush=True)
 
     seq = None
     if args.compare_sequential and n_inst > 1:
@@ -547,7 +660,22 @@ def main():
                "u": rd(qv_lp[:, 2], qv[:, 2])}
 
     ams = kt["folded_apply" if folded else "apply_macro_solve"]
-    avg_ms = ams["ms"] / max(ams["count"], 1)
+    # apply launches that did work: GMRES and residual applies (n_applies less the
+    # two right-hand-side passes), per solve the largest count over instances.  The
+    # event time of launches after every instance converged (the rest of the last
+    # restart cycle runs as near-empty kernels) stays in the total, so the average
+    # below is a slight overestimate of a working launch's duration
+    work_launches = sum(max(x["n_applies"] - 2 for x in si) for si in inst_infos)
+    if reduced:
+        work_launches = ams["count"]   # refinement: every launch of the kernel is an apply
+    apply_timing = "HIP events around every apply kernel of the timed solves"
+    if ams["count"] == 0:
+        # captured cycles: the apply kernel timed by events in the apply-only loop
+        ams = kt_apply["folded_apply" if folded else "apply_macro_solve"]
+        work_launches = ams["count"]
+        apply_timing = ("HIP events around the apply kernel in an apply-only loop after the "
+                        "timed solves (those replay captured GMRES cycles, without events)")
+    avg_ms = ams["ms"] / max(work_launches, 1)
     nbytes = apply_bytes(m, {mhdg.MHDG_FP32: 4, mhdg.MHDG_BF16: 2}.get(prec, 8),
                          None if np.ndim(w["r"]) == 0 else np.tile(w["r"], n_inst), w["p"],
                          qelim=prec == mhdg.MHDG_QELIM)
@@ -560,7 +688,7 @@ def main():
         # instances each launch actually processed (GMRES applies + the
         # true-residual apply of every instance)
         inst_launches = sum(x["n_applies"] - 2 for si in inst_infos for x in si)
-        nbytes = nbytes / n_inst * inst_launches / max(ams["count"], 1)
+        nbytes = nbytes / n_inst * inst_launches / max(work_launches, 1)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
     lu = kt["lu"]
@@ -593,7 +721,11 @@ def main():
                    if prec == mhdg.MHDG_QELIM else
                    ("fp32_factors_fp64_ir" if prec == mhdg.MHDG_FP32 else "bf16_factors_fp64_ir"),
                    "supg": bool(w.get("supg")),
-                   "inner_rtol": args.inner_rtol if reduced else None},
+                   "inner_rtol": args.inner_rtol if reduced else None,
+                   "stop_norm": ("unpreconditioned ||f^ - S lam|| / ||f^||"
+                                 if stop == mhdg.MHDG_NORM_TRUE else
+                                 "preconditioned ||D^-1 (f^ - S lam)|| / ||D^-1 f^||"),
+                   "gmres_driver": args.driver, "cycles_graph_captured": sgraph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["traffic_bytes_per_launch"] / 1e9 if traffic else None,
@@ -608,7 +740,8 @@ def main():
                                 % {mhdg.MHDG_FP64: "double", mhdg.MHDG_FP32: "float",
                                    mhdg.MHDG_BF16: "bf16_t"}[prec]),
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
-                     "launches": ams["count"]},
+                     "launches": work_launches, "launch_records": ams["count"],
+                     "timing": apply_timing},
         "time_to_solve_s": ms_per_step / 1e3,
         "iterations": [i["iterations"] for i in infos] if n_inst == 1 else
         [[x["iterations"] for x in si] for si in inst_infos],
@@ -616,6 +749,8 @@ def main():
         "outer_iterations": [i["outer_iterations"] for i in infos],
         "applies_per_solve": [i["n_applies"] for i in infos],
         "second_gs_passes": [i["reorth_passes"] for i in infos],
+        "gmres_cycles": [i["cycles"] for i in infos],
+        "host_waits_per_solve": [i["host_waits"] for i in infos],
         "vs_fp64": cmp,
         "rel_res_prec": [max(x["rel_res_prec"] for x in si) for si in inst_infos],
         "rel_res_true": [max(x["rel_res_true"] for x in si) for si in inst_infos],
@@ -628,6 +763,7 @@ def main():
         "u_max_err_vs_exact": u_err,
         "autotune": tune,
         "tuned_forms": tuned,
+        "jitter_control": jitter,
     }
     if not args.no_cpu_baseline:
         wc = dict(w)
@@ -951,7 +1087,11 @@ def bench_adjoint(args, w):
                                "rel_diff": abs(v - float(db[d])) / abs(v)})
             print(f"[bench] fd beta_{d}: {fd['beta'][-1]}", file=sys.stderr, flush=True)
     ams = kt["folded_apply" if args.folded else "apply_macro_solve"]
-    avg_ms = ams["ms"] / max(ams["count"], 1)
+    # launches that did work: forward GMRES + residual applies (n_applies less the two
+    # right-hand-side passes) and adjoint GMRES applies (less its right side and the
+    # final A^-T pass); near-empty launches after convergence stay in the event time
+    work = sum((a["n_applies"] - 2) + (b_["n_applies"] - 2) for a, b_ in infos)
+    avg_ms = ams["ms"] / max(work, 1)
     nbytes = fold_bytes(tri, w["r"], w["p"], s.n_trace) if args.folded else apply_bytes(m, 8)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     result = {
@@ -969,7 +1109,8 @@ def bench_adjoint(args, w):
                      "kernel": ("fold_apply_kernel (forward and transposed folded applies)"
                                 if args.folded else
                                 "macro_solve_kernel<double> (forward apply steps 1-3)"),
-                     "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms, "launches": ams["count"]},
+                     "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms, "launches": work,
+                     "launch_records": ams["count"]},
         "forward_iterations": [a["iterations"] for a, _ in infos],
         "adjoint_iterations": [b_["iterations"] for _, b_ in infos],
         "kernel_ms": {k: v["ms"] / max(args.steps, 1) for k, v in kt.items()},

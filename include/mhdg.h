@@ -124,6 +124,21 @@ enum {
                                  MHDG_TRANSPOSE)                              */
 };
 
+/* GMRES drivers (mhdg_solve_opts.driver) and stopping norms (.stop_norm) */
+enum {
+  MHDG_DRIVER_DEVICE = 0,     /* the Arnoldi recurrences, rotations and the
+                                 least-squares solve run on the device; the
+                                 host waits once per restart cycle (restart
+                                 <= 2048, delayed reorthogonalisation)       */
+  MHDG_DRIVER_HOST = 1        /* the host runs them and synchronises once per
+                                 iteration                                   */
+};
+enum {
+  MHDG_NORM_PRECONDITIONED = 0,  /* stop when ||D^-1 r|| <= rtol ||D^-1 f^||  */
+  MHDG_NORM_TRUE = 1             /* stop when ||r|| <= rtol ||f^|| (FP64 or
+                                    QELIM factors, device driver)            */
+};
+
 typedef struct mhdg_mesh mhdg_mesh;
 
 typedef struct {
@@ -144,15 +159,20 @@ typedef struct {
 } mhdg_sizes;
 
 typedef struct {
-  double rtol;                /* stop when ||D^-1 r|| <= rtol ||D^-1 f^||      */
+  double rtol;                /* stop when ||D^-1 r|| <= rtol ||D^-1 f^||
+                                 (or ||r|| <= rtol ||f^||, see stop_norm)     */
   int32_t restart;            /* Krylov length per cycle (>= 1)                */
   int32_t max_iter;           /* total (inner) GMRES iterations                */
   int32_t zero_guess;         /* 1: start from lambda = 0; 0: use lam on entry */
   int32_t max_outer;          /* reduced-precision factors: refinement steps (0: 30) */
   double inner_rtol;          /* reduced-precision factors: inner GMRES relative
                                  tolerance per refinement step (0: 1e-5)      */
-  int32_t graph;              /* 1: every GMRES apply replays one captured
-                                 hipGraph (see MHDG_GRAPH); 0: plain launches */
+  int32_t graph;              /* device driver: 1 replays each restart cycle
+                                 from hipGraphs captured on first use (per
+                                 vectors, restart and flags; kept until the
+                                 next factor_local); host driver: 1 replays
+                                 every apply from one hipGraph (MHDG_GRAPH);
+                                 0: plain launches                           */
   int32_t folded;             /* 1: GMRES applies (forward in solve, transposed
                                  in adjoint) use the folded operators
                                  (MHDG_FOLDED; needs mhdg_fold_operator)      */
@@ -160,7 +180,13 @@ typedef struct {
                                  (one synchronisation and two passes over the
                                  basis per iteration); 1: classical
                                  Gram-Schmidt, second pass when the first
-                                 keeps less than 1/sqrt(2) of the norm       */
+                                 keeps less than 1/sqrt(2) of the norm
+                                 (host driver)                               */
+  int32_t driver;             /* MHDG_DRIVER_DEVICE (default) or _HOST; the
+                                 device driver falls back to the host one for
+                                 classic_gs = 1 or restart > 2048             */
+  int32_t stop_norm;          /* MHDG_NORM_PRECONDITIONED (default) or
+                                 MHDG_NORM_TRUE                              */
 } mhdg_solve_opts;
 
 typedef struct {
@@ -178,6 +204,15 @@ typedef struct {
   int32_t reorth_passes;      /* second Gram-Schmidt passes taken (the second
                                  pass runs only when the first leaves less
                                  than 1/sqrt(2) of the vector's norm)        */
+  int32_t cycles;             /* GMRES restart cycles run                      */
+  int32_t host_waits;         /* times the host waited for the stream inside
+                                 GMRES.  Device driver: once per cycle, once
+                                 for the first cycle start and, with
+                                 MHDG_NORM_TRUE, once for ||f^||; cycles of
+                                 more than 64 columns run without graphs also
+                                 wait once per 32 columns (two chunks stay
+                                 queued), to skip what is left of a cycle
+                                 once every instance has converged          */
 } mhdg_solve_info;
 
 /* Build the host-side macro mesh (the partition of Omega into simplicial
@@ -309,9 +344,12 @@ mhdg_status mhdg_rhs(mhdg_mesh* mesh, const double* f_nodes, const double* g_bnd
  * ws: device workspace of at least solve_ws_bytes (mhdg_query with the same
  * restart).  info: host array of n_inst entries (one per coefficient
  * instance; iterations and residuals are per instance) or NULL.  With
- * several instances the factors must be FP64 (STATE otherwise).  Returns
- * NOT_CONVERGED if max_iter was reached before every instance converged
- * (lam then holds the last iterates). */
+ * several instances the factors must be FP64 (STATE otherwise).  The
+ * stopping test (opts->stop_norm) is checked on the exact residual at the
+ * start of every restart cycle; with the device driver the host waits once
+ * per cycle.  Returns NOT_CONVERGED if max_iter was reached before every
+ * instance converged (lam then holds the last iterates), INVALID_ARG for
+ * MHDG_NORM_TRUE with reduced-precision factors or with the host driver. */
 mhdg_status mhdg_solve(mhdg_mesh* mesh, const double* f_nodes, const double* g_bnd,
                        const mhdg_solve_opts* opts, double* lam, void* ws, size_t ws_bytes,
                        mhdg_solve_info* info, void* stream);

@@ -81,7 +81,33 @@ struct mhdg_mesh {
     hipGraphExec_t x;
   };
   std::vector<ApplyGraph> graphs;
+  // captured GMRES cycles (gmres_device): the chunks of a cycle and the first
+  // cycle start, keyed by the solve's vectors, restart, segments and flags
+  struct GmKey {
+    const double* V;
+    const double* x;
+    const double* b;
+    const double* fh;
+    int R, ns;
+    int32_t flags;
+    bool operator==(const GmKey& o) const {
+      return V == o.V && x == o.x && b == o.b && fh == o.fh && R == o.R && ns == o.ns &&
+             flags == o.flags;
+    }
+  };
+  struct GmGraphs {
+    GmKey key;
+    std::vector<hipGraphExec_t> x;
+  };
+  std::vector<GmGraphs> gm_graphs;
   hipStream_t cap = nullptr;   // private stream the graphs are captured on
+  // two events for the look-ahead of directly launched GMRES cycles
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+  hipEvent_t* chunk_events() {
+    for (auto& e : chunk_ev)
+      if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return chunk_ev;
+  }
   // page-locked host buffer for the small per-iteration GMRES transfers (kept
   // until the handle is destroyed; host memory only)
   double* pinned = nullptr;
@@ -100,11 +126,16 @@ struct mhdg_mesh {
   void drop_graphs() {
     for (auto& a : graphs) { (void)hipGraphExecDestroy(a.x); (void)hipGraphDestroy(a.g); }
     graphs.clear();
+    for (auto& c : gm_graphs)
+      for (auto x : c.x) (void)hipGraphExecDestroy(x);
+    gm_graphs.clear();
   }
   ~mhdg_mesh() {
     for (auto& v : ev)
       for (auto& p : v) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
     drop_graphs();
+    for (auto e : chunk_ev)
+      if (e) (void)hipEventDestroy(e);
     if (cap) (void)hipStreamDestroy(cap);
     if (pinned) (void)hipHostFree(pinned);
   }
@@ -775,6 +806,14 @@ struct Gm {
   bool classic = false;                   // CGS2 instead of the delayed form
   double *pq = nullptr, *hy = nullptr, *coef = nullptr, *Hb = nullptr;  // delayed form
   double *U = nullptr, *dl = nullptr, *cl = nullptr;  // precision-refinement state
+  // device-resident recurrences (gmres_device): state in the workspace, the
+  // per-cycle status block (doubles then ints, one copy to the host)
+  bool device = false;
+  int cycles = 0, waits = 0;              // restart cycles, host waits on the stream
+  GmDev dev{};
+  char* stat = nullptr;
+  size_t stat_bytes = 0;
+  const double* fh_true = nullptr;        // f^ when stopping on the unpreconditioned residual
   int64_t len() const { return n * nseg; }
 };
 
@@ -839,6 +878,7 @@ mhdg_status gmres_cgs2(mhdg_mesh* M, Gm& G, const double* b, const double* bref,
     for (int q = 0; q < ns; ++q) G.seg_applies[q] += !skip[q];
     HIP_TRY(M, launch_scale_copy(1.0, b, G.rv, len, s));
     HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, len, s));
+    ++G.waits;
     if ((st = dot(M, G, G.rv, G.rv, nrm.data(), s))) return st;
     bool any = false;
     jc.assign(ns, 0);
@@ -857,6 +897,7 @@ mhdg_status gmres_cgs2(mhdg_mesh* M, Gm& G, const double* b, const double* bref,
       g[q * (R + 1)] = beta[q];
     }
     if (!any || it >= max_iter) return MHDG_OK;
+    ++G.cycles;
     if ((st = push_skip()) || (st = push_alpha())) return st;
     HIP_TRY(M, launch_seg_scale_copy(G.adev, G.rv, G.V, n, ns, s));
     int j = 0;
@@ -883,6 +924,7 @@ mhdg_status gmres_cgs2(mhdg_mesh* M, Gm& G, const double* b, const double* bref,
         HIP_TRY(M, hipMemcpyAsync(h.data(), G.hdev, size_t(j + 1) * ns * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
         HIP_TRY(M, hipMemcpyAsync(w2h.data(), w2, 2 * ns * sizeof(double), hipMemcpyDeviceToHost, s));
+        ++G.waits;
         HIP_TRY(M, hipStreamSynchronize(s));
         bool again = false;
         for (int q = 0; q < ns; ++q) {
@@ -962,6 +1004,7 @@ mhdg_status gmres_cgs2(mhdg_mesh* M, Gm& G, const double* b, const double* bref,
                                 hipMemcpyHostToDevice, s));
       HIP_TRY(M, launch_gemv_sub(G.V, ld, jmax, G.ydev, x, n, 1.0, s, ns));
     }
+    ++G.waits;
     HIP_TRY(M, hipStreamSynchronize(s));
     for (int q = 0; q < ns; ++q) skip[q] = done[q];
   }
@@ -1040,6 +1083,7 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
     for (int q = 0; q < ns; ++q) G.seg_applies[q] += !skip[q];
     HIP_TRY(M, launch_scale_copy(1.0, b, G.rv, len, s));
     HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, len, s));
+    ++G.waits;
     if ((st = dot(M, G, G.rv, G.rv, nrm.data(), s))) return st;
     bool any = false;
     jc.assign(ns, 0);
@@ -1059,6 +1103,7 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
       g[q * (R + 1)] = active[q] ? beta[q] : 0.0;
     }
     if (!any || it >= max_iter) return MHDG_OK;
+    ++G.cycles;
     if ((st = push_skip())) return st;
     HIP_TRY(M, hipMemcpyAsync(G.adev, alpha.data(), ns * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(M, launch_seg_scale_copy(G.adev, G.rv, G.V, n, ns, s));   // u_0 = r
@@ -1098,10 +1143,12 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
         std::vector<double> pl(size_t(j + 1) * ns);
         HIP_TRY(M, hipMemcpyAsync(pl.data(), G.hy, pl.size() * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
+        ++G.waits;
         HIP_TRY(M, hipStreamSynchronize(s));
         for (int c = 0; c <= j; ++c)
           for (int q = 0; q < ns; ++q) pq[(2 * size_t(c)) * ns + q] = pl[size_t(c) * ns + q];
       }
+      ++G.waits;
       HIP_TRY(M, hipStreamSynchronize(s));
       any = false;
       for (int q = 0; q < ns; ++q) {
@@ -1225,14 +1272,292 @@ mhdg_status gmres_delayed(mhdg_mesh* M, Gm& G, const double* b, const double* br
                                 hipMemcpyHostToDevice, s));
       HIP_TRY(M, launch_gemv_sub(G.V, ld, jmax, G.ydev, x, n, 1.0, s, ns));
     }
+    ++G.waits;
     HIP_TRY(M, hipStreamSynchronize(s));
     for (int q = 0; q < ns; ++q) skip[q] = done[q];
   }
 }
 
+mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
+                           const int32_t* skip, hipStream_t s);
+
+// Columns per captured graph of a cycle (the cycle's graphs are launched back
+// to back; the host waits once per cycle).
+constexpr int kGmChunk = 32;
+// Longest restart of the device driver (gm_step keeps 3 (R + 2) doubles in LDS).
+constexpr int kDeviceMaxRestart = 2048;
+
+// Restarted GMRES with the per-segment recurrences on the device
+// (gmres_dev.hip): the same left-preconditioned Arnoldi process with delayed
+// reorthogonalisation and the same stopping rule as gmres_delayed, but the
+// scalar work between kernels (projections, Givens rotations, residual
+// estimate, update coefficients, the triangular solve) runs in kernels, so a
+// restart cycle is a fixed sequence of launches that ends with the residual
+// of the next cycle.  With MHDG_GRAPH in G.op_flags each cycle replays
+// hipGraphs captured once per (vectors, restart, flags); otherwise the same
+// launches run directly.  The host synchronises once per cycle, to read the
+// per-segment status.  A segment that converges, or reaches max_iter
+// finished columns, inside a cycle is masked out of every later launch.
+// With G.fh_true set the test is on the unpreconditioned residual:
+// ||f^_s - S x_s|| <= rtol ||f^_s||, checked exactly at each cycle start; in
+// the cycle the estimate of the preconditioned residual is compared with a
+// target scaled by the ratio of the two norms at the cycle start.
+mhdg_status gmres_device(mhdg_mesh* M, Gm& G, const double* b, const double* bref, double* x,
+                         double rtol, int R, int max_iter, std::vector<int>& iters,
+                         std::vector<double>& rel, std::vector<double>& rel_true, int& applies,
+                         std::vector<char>& done, hipStream_t s) {
+  const int64_t n = G.n, ld = G.ld, len = G.len();
+  const int ns = G.nseg;
+  const int64_t hld = R + 1;
+  GmDev& d = G.dev;
+  const bool use_graph = (G.op_flags & MHDG_GRAPH) != 0;
+  const int32_t aflags = G.op_flags & ~MHDG_GRAPH;
+  const bool true_norm = G.fh_true != nullptr;
+  if (!true_norm) d.nrm_true = nullptr;   // gm_start tests the preconditioned residual
+  mhdg_status st;
+  // ---- initial state: parameters, reference norms, flags
+  const size_t nd_in = 2 + 2 * size_t(ns);   // prm, bref, fref
+  const size_t ni = 7 * size_t(ns) + 1;      // the int block (see carve)
+  double* const pin = M->host_buffer(nd_in + G.stat_bytes / sizeof(double) + ni);
+  if (!pin) return fail(M, MHDG_ERR_HIP, "solve: page-locked host buffer not available");
+  double* const hin = pin;
+  char* const hstat = (char*)(pin + nd_in);
+  int32_t* const hint = (int32_t*)(hstat + G.stat_bytes);
+  hin[0] = rtol;
+  hin[1] = double(max_iter);
+  std::vector<double> fref(ns, 0.0);
+  if (true_norm) {
+    HIP_TRY(M, launch_dots(G.fh_true, ld, 1, G.fh_true, n, G.partial, G.nblk, G.hdev, s, ns));
+    HIP_TRY(M, hipMemcpyAsync(fref.data(), G.hdev, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    ++G.waits;
+    HIP_TRY(M, hipStreamSynchronize(s));
+    for (auto& v : fref) v = std::sqrt(v);
+  }
+  done.assign(ns, 0);
+  std::fill(hint, hint + ni, 0);
+  for (int q = 0; q < ns; ++q) {
+    hin[2 + q] = bref[q];
+    hin[2 + ns + q] = fref[q];
+    if (bref[q] == 0.0 || (true_norm && fref[q] == 0.0)) {
+      HIP_TRY(M, hipMemsetAsync(x + q * n, 0, n * sizeof(double), s));
+      done[q] = 1;
+    }
+    hint[2 * ns + q] = done[q];   // done
+    hint[6 * ns + q] = done[q];   // skip
+  }
+  HIP_TRY(M, hipMemcpyAsync(d.prm, hin, nd_in * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(M, hipMemcpyAsync(d.active, hint, ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
+
+  // ---- the launch sequences of a cycle
+  auto seq_start = [&](hipStream_t t) -> mhdg_status {
+    mhdg_status e;
+    if (true_norm) {   // r = f^ - S x, ||r||, then D^-1 r
+      if ((e = apply_launches(M, x, G.tv, aflags & ~MHDG_PRECONDITION, d.skip, t))) return e;
+      HIP_TRY(M, launch_scale_copy(1.0, G.fh_true, G.cl, len, t));
+      HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.cl, len, t));
+      HIP_TRY(M, launch_dots(G.cl, ld, 1, G.cl, n, G.partial, G.nblk, d.nrm_true, t, ns));
+      FactorLayout& L = M->L;
+      HIP_TRY(M, launch_face_combine(FACE_DINV, (const FaceInfo*)(M->ws + L.faces), M->n_int,
+                                     (const double*)(M->ws + L.tmpl), M->T, M->tau, G.cl,
+                                     nullptr, G.rv, t));
+    } else {           // r = b - D^-1 S x
+      if ((e = apply_launches(M, x, G.tv, aflags, d.skip, t))) return e;
+      HIP_TRY(M, launch_scale_copy(1.0, b, G.rv, len, t));
+      HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, len, t));
+    }
+    HIP_TRY(M, launch_dots(G.rv, ld, 1, G.rv, n, G.partial, G.nblk, d.nrm, t, ns));
+    HIP_TRY(M, launch_gm_start(d, R, t));
+    HIP_TRY(M, launch_seg_scale_copy(d.alpha, G.rv, G.V, n, ns, t));   // u_0 = r
+    return MHDG_OK;
+  };
+  auto seq_column = [&](int j, hipStream_t t) -> mhdg_status {
+    double* u = G.V + j * ld;
+    mhdg_status e;
+    if ((e = apply_launches(M, u, G.wv, aflags, d.skip, t))) return e;   // z = D^-1 S u_j
+    HIP_TRY(M, launch_dots2(G.V, ld, j + 1, u, G.wv, n, G.partial, G.nblk, d.pq, t, ns, d.skip));
+    if (j >= 2)
+      HIP_TRY(M, launch_hbar_gemv(G.Hb, hld, ns, j - 1, j, d.pq, d.pq + 2 * size_t(j + 1) * ns, t));
+    HIP_TRY(M, launch_gm_step(d, R, j, 0, t));
+    HIP_TRY(M, launch_dual_update(G.V, ld, j, n, ns, d.coef, d.coef + size_t(j) * ns,
+                                  d.coef + 2 * size_t(j) * ns, G.wv, nullptr, t, d.skip));
+    return MHDG_OK;
+  };
+  auto seq_close = [&](hipStream_t t) -> mhdg_status {
+    // the last column: projections of u_R only; then y and x += V y
+    HIP_TRY(M, launch_dots(G.V, ld, R + 1, G.V + R * ld, n, G.partial, G.nblk, d.hy, t, ns,
+                           d.skip));
+    HIP_TRY(M, launch_gm_step(d, R, R, 1, t));
+    HIP_TRY(M, launch_gm_lsq(d, R, t));
+    HIP_TRY(M, launch_gemv_sub(G.V, ld, R, d.y, x, n, 1.0, t, ns, d.jc));
+    return seq_start(t);
+  };
+  const int nchunk = (R + kGmChunk - 1) / kGmChunk;
+  // graph p < nchunk: columns [p kGmChunk, ...) (the last one with the close);
+  // graph nchunk: the first cycle start
+  auto seq_graph = [&](int p, hipStream_t t) -> mhdg_status {
+    if (p == nchunk) return seq_start(t);
+    mhdg_status e;
+    for (int j = p * kGmChunk; j < std::min(R, (p + 1) * kGmChunk); ++j)
+      if ((e = seq_column(j, t))) return e;
+    return p == nchunk - 1 ? seq_close(t) : MHDG_OK;
+  };
+  mhdg_mesh::GmGraphs* gg = nullptr;
+  if (use_graph) {
+    const mhdg_mesh::GmKey key{G.V, x, b, G.fh_true, R, ns, aflags};
+    for (auto& e : M->gm_graphs)
+      if (e.key == key) gg = &e;
+    if (!gg) {
+      if (!M->cap) HIP_TRY(M, hipStreamCreateWithFlags(&M->cap, hipStreamNonBlocking));
+      mhdg_mesh::GmGraphs ng;
+      ng.key = key;
+      const bool prof = M->prof;
+      M->prof = false;   // no event records inside the graphs
+      for (int p = 0; p <= nchunk; ++p) {
+        HIP_TRY(M, hipStreamBeginCapture(M->cap, hipStreamCaptureModeThreadLocal));
+        mhdg_status e = seq_graph(p, M->cap);
+        hipGraph_t g = nullptr;
+        hipError_t he = hipStreamEndCapture(M->cap, &g);
+        hipGraphExec_t gx = nullptr;
+        if (!e && he == hipSuccess) he = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e || he != hipSuccess) {
+          M->prof = prof;
+          for (auto xg : ng.x) (void)hipGraphExecDestroy(xg);
+          if (e) return e;
+          return fail(M, MHDG_ERR_HIP, std::string("solve: graph capture: ") + hipGetErrorString(he));
+        }
+        ng.x.push_back(gx);
+      }
+      M->prof = prof;
+      if (M->gm_graphs.size() >= 4) {   // bounded cache: drop the oldest
+        for (auto xg : M->gm_graphs.front().x) (void)hipGraphExecDestroy(xg);
+        M->gm_graphs.erase(M->gm_graphs.begin());
+      }
+      M->gm_graphs.push_back(std::move(ng));
+      gg = &M->gm_graphs.back();
+    }
+  }
+  // status after a cycle: rel | rel_true | est (doubles), then the int block
+  const double* srel = (const double*)hstat;
+  const double* srel_true = srel + ns;
+  const int32_t* sint = (const int32_t*)(hstat + G.stat_bytes - ni * sizeof(int32_t));
+  const int32_t* s_done = sint + 2 * ns;
+  const int32_t* s_iters = sint + 3 * ns;
+  const int32_t* s_flag = sint + 4 * ns;
+  const int32_t* s_napp = sint + 5 * ns;
+  const int32_t* s_any = sint + 7 * ns;
+  std::vector<int32_t> napp_prev(ns, 0);
+  auto read_status = [&]() -> mhdg_status {
+    HIP_TRY(M, hipMemcpyAsync(hstat, G.stat, G.stat_bytes, hipMemcpyDeviceToHost, s));
+    ++G.waits;
+    HIP_TRY(M, hipStreamSynchronize(s));
+    for (int q = 0; q < ns; ++q)
+      if (s_flag[q]) return fail(M, MHDG_ERR_NOT_CONVERGED, "gmres: non-finite residual");
+    for (int q = 0; q < ns; ++q) {
+      // applies per segment: its residual apply (when not done before the
+      // cycle start) plus the Krylov applies it took part in
+      G.seg_applies[q] += s_napp[q] - napp_prev[q];
+      napp_prev[q] = s_napp[q];
+    }
+    return MHDG_OK;
+  };
+  auto run = [&](int p) -> mhdg_status {
+    if (use_graph) {
+      HIP_TRY(M, hipGraphLaunch(gg->x[p], s));
+      return MHDG_OK;
+    }
+    return seq_graph(p, s);
+  };
+  // cycle starts: residual apply for the segments not yet done
+  auto count_start = [&]() {
+    int any = 0;
+    for (int q = 0; q < ns; ++q)
+      if (!done[q]) { ++G.seg_applies[q]; any = 1; }
+    applies += any;
+  };
+  count_start();
+  if ((st = run(nchunk))) return st;
+  if ((st = read_status())) return st;
+  int cycles = 0;
+  // every cycle finishes at least one column of each segment that iterates in
+  // it (or retires the segment), so max_iter bounds the cycles; the second
+  // bound only guards against a cycle that makes no progress
+  while (*s_any && cycles <= max_iter) {
+    int prev_max = 0;
+    for (int q = 0; q < ns; ++q) prev_max = std::max(prev_max, s_napp[q]);
+    for (int q = 0; q < ns; ++q) done[q] = s_done[q] != 0;
+    if (use_graph || nchunk <= 2) {
+      for (int p = 0; p < nchunk; ++p)
+        if ((st = run(p))) return st;
+    } else {
+      // direct launches of a long cycle: keep two chunks queued and look at the
+      // active flags of the chunk before the last one queued; once no segment is
+      // active the rest of the cycle is skipped (the closing step still runs)
+      int32_t* act_h = hint;   // the init staging area is free again: [2][ns]
+      hipEvent_t* ev = M->chunk_events();
+      if (!ev) return fail(M, MHDG_ERR_HIP, "solve: events not available");
+      int p = 0;
+      for (; p < nchunk - 1; ++p) {
+        if (p >= 2) {
+          ++G.waits;
+          HIP_TRY(M, hipEventSynchronize(ev[p % 2]));
+          bool any = false;
+          for (int q = 0; q < ns; ++q) any |= act_h[(p % 2) * ns + q] != 0;
+          if (!any) break;
+        }
+        if ((st = seq_graph(p, s))) return st;
+        HIP_TRY(M, hipMemcpyAsync(act_h + (p % 2) * ns, d.active, ns * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s));
+        HIP_TRY(M, hipEventRecord(ev[p % 2], s));
+      }
+      if (p == nchunk - 1) {
+        if ((st = seq_graph(p, s))) return st;   // last columns and the close
+      } else {
+        if ((st = seq_close(s))) return st;
+      }
+    }
+    ++cycles;
+    ++G.cycles;
+    if ((st = read_status())) return st;
+    int now_max = 0;
+    for (int q = 0; q < ns; ++q) now_max = std::max(now_max, s_napp[q]);
+    applies += now_max - prev_max;   // launches in which some segment took part
+    count_start();
+    if (g_progress) {
+      double worst = 0;
+      int it = 0;
+      for (int q = 0; q < ns; ++q) {
+        if (!s_done[q]) worst = std::max(worst, srel[q]);
+        it = std::max(it, s_iters[q]);
+      }
+      std::fprintf(stderr, "[mhdg] gmres cycle %d, %d iterations, relative residual %.3e\n",
+                   cycles, it, worst);
+      std::fflush(stderr);
+    }
+  }
+  iters.assign(ns, 0);
+  rel.assign(ns, 0.0);
+  rel_true.assign(ns, -1.0);
+  for (int q = 0; q < ns; ++q) {
+    iters[q] = s_iters[q];
+    done[q] = s_done[q] != 0;
+    rel[q] = bref[q] == 0.0 ? 0.0 : srel[q];
+    if (true_norm) rel_true[q] = fref[q] == 0.0 ? 0.0 : srel_true[q];
+  }
+  return MHDG_OK;
+}
+
 mhdg_status gmres(mhdg_mesh* M, Gm& G, const double* b, const double* bref, double* x, double rtol,
                   int R, int max_iter, std::vector<int>& iters, std::vector<double>& rel,
-                  int& applies, std::vector<char>& done, hipStream_t s) {
+                  int& applies, std::vector<char>& done, hipStream_t s,
+                  std::vector<double>* rel_true = nullptr) {
+  if (G.device) {
+    std::vector<double> rt;
+    mhdg_status st = gmres_device(M, G, b, bref, x, rtol, R, max_iter, iters, rel, rt, applies,
+                                  done, s);
+    if (rel_true) *rel_true = rt;
+    return st;
+  }
   return G.classic ? gmres_cgs2(M, G, b, bref, x, rtol, R, max_iter, iters, rel, applies, done, s)
                    : gmres_delayed(M, G, b, bref, x, rtol, R, max_iter, iters, rel, applies, done, s);
 }
@@ -1274,7 +1599,58 @@ mhdg_status carve(mhdg_mesh* M, void* ws, int R, Gm& G) {
   G.skip = (int32_t*)(w + off);
   off += align_up(size_t(G.nseg) * 4);
   G.U = (double*)(w + off);
+  off += align_up(size_t(M->n_local) * sizeof(double));
+  // device-resident GMRES state (gmres_device)
+  const size_t ns = size_t(G.nseg), Rs = size_t(R);
+  GmDev& d = G.dev;
+  d.ns = G.nseg;
+  d.Hb = G.Hb;
+  d.pq = G.pq;
+  d.hy = G.hy;
+  d.coef = G.coef;
+  d.y = G.ydev;
+  d.alpha = G.adev;
+  auto take = [&](size_t n_doubles) {
+    double* p = (double*)(w + off);
+    off += align_up(n_doubles * sizeof(double));
+    return p;
+  };
+  d.H = take(ns * Rs * (Rs + 1));
+  d.cs = take(ns * Rs);
+  d.sn = take(ns * Rs);
+  d.g = take(ns * (Rs + 1));
+  d.hprev = take(ns * (Rs + 1));
+  d.nrm = take(ns);
+  d.nrm_true = take(ns);
+  d.tgt = take(ns);
+  d.prm = take(2 + 2 * ns);   // rtol, max_iter | bref | fref: one copy from the host
+  d.bref = d.prm + 2;
+  d.fref = d.prm + 2 + ns;
+  // status block read back once per cycle: rel | rel_true | est, then
+  // active | jc | done | iters | flag | napp | skip | any
+  G.stat = w + off;
+  G.stat_bytes = 3 * ns * sizeof(double) + (7 * ns + 1) * sizeof(int32_t);
+  d.rel = (double*)G.stat;
+  d.rel_true = d.rel + ns;
+  d.est = d.rel + 2 * ns;
+  int32_t* ib = (int32_t*)(G.stat + 3 * ns * sizeof(double));
+  d.active = ib;
+  d.jc = ib + ns;
+  d.done = ib + 2 * ns;
+  d.iters = ib + 3 * ns;
+  d.flag = ib + 4 * ns;
+  d.napp = ib + 5 * ns;
+  d.skip = ib + 6 * ns;
+  d.any = ib + 7 * ns;
   return MHDG_OK;
+}
+
+// Bytes of the device-resident GMRES state after the vectors (see carve).
+size_t gm_dev_bytes(int R, int nseg) {
+  const size_t ns = size_t(nseg), Rs = size_t(R);
+  return align_up(ns * Rs * (Rs + 1) * 8) + 2 * align_up(ns * Rs * 8) +
+         2 * align_up(ns * (Rs + 1) * 8) + 3 * align_up(ns * 8) + align_up((2 + 2 * ns) * 8) +
+         align_up(3 * ns * 8 + (7 * ns + 1) * 4);
 }
 
 // Kernel choices of earlier autotuning runs in this process, per (local
@@ -2344,7 +2720,7 @@ static size_t solve_bytes_impl(const mhdg_mesh* M, int R) {
          align_up(2 * size_t(R + 2) * ns * 8) + align_up(size_t(R + 2) * ns * 8) +
          align_up((2 * size_t(R) + 3) * ns * 8) + align_up(size_t(R + 1) * R * ns * 8) +
          2 * align_up(size_t(R + 2) * ns * 8) + align_up(ns * 8) + align_up(ns * 4) +
-         align_up(size_t(M->n_local) * sizeof(double));
+         align_up(size_t(M->n_local) * sizeof(double)) + gm_dev_bytes(R, M->n_inst);
 }
 
 mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
@@ -2367,11 +2743,21 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
   carve(M, ws, R, G);
   if (o->graph) G.op_flags |= MHDG_GRAPH;
   G.classic = o->classic_gs != 0;
+  G.device = o->driver == MHDG_DRIVER_DEVICE && !G.classic && R <= kDeviceMaxRestart;
   if (o->folded) {
     if (!M->folded || (M->precision != MHDG_FP64 && M->precision != MHDG_QELIM))
       return fail(M, MHDG_ERR_STATE, "solve: folded applies need mhdg_fold_operator");
     G.op_flags |= MHDG_FOLDED;
   }
+  const bool stop_true = o->stop_norm == MHDG_NORM_TRUE;
+  if (stop_true && !(M->precision == MHDG_FP64 || M->precision == MHDG_QELIM))
+    return fail(M, MHDG_ERR_INVALID_ARG,
+                "solve: MHDG_NORM_TRUE needs FP64 or QELIM factors (reduced-precision factors "
+                "stop on the refined system's residual)");
+  if (stop_true && !G.device)
+    return fail(M, MHDG_ERR_INVALID_ARG,
+                "solve: MHDG_NORM_TRUE runs with the device driver only (classic_gs = 0, "
+                "restart <= 2048)");
   mhdg_solve_info inf{};
   mhdg_status st;
   FactorLayout& L = M->L;
@@ -2401,21 +2787,29 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
     std::vector<char> done;
     if ((st = dot(M, G, G.pf, G.pf, bnorm.data(), s))) return st;
     for (auto& b : bnorm) b = std::sqrt(b);
+    if (stop_true) G.fh_true = G.fh;
+    std::vector<double> rtrue;
     if ((st = gmres(M, G, G.pf, bnorm.data(), lam, o->rtol, R, o->max_iter, its, rels,
-                    inf.n_applies, done, s)))
+                    inf.n_applies, done, s, &rtrue)))
       return st;
-    // true residual ||f^ - S lam|| / ||f^|| per instance
-    if ((st = mhdg_apply_trace_operator(M, lam, G.tv, 0, stream))) return st;
-    ++inf.n_applies;
-    HIP_TRY(M, launch_scale_copy(1.0, G.fh, G.rv, n, s));
-    HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, n, s));
-    if ((st = dot(M, G, G.rv, G.rv, tr2.data(), s))) return st;
-    if ((st = dot(M, G, G.fh, G.fh, f2.data(), s))) return st;
+    if (!stop_true) {
+      // true residual ||f^ - S lam|| / ||f^|| per instance (with MHDG_NORM_TRUE the
+      // last cycle start measured it)
+      if ((st = mhdg_apply_trace_operator(M, lam, G.tv, 0, stream))) return st;
+      ++inf.n_applies;
+      for (int q = 0; q < ns; ++q) ++G.seg_applies[q];
+      HIP_TRY(M, launch_scale_copy(1.0, G.fh, G.rv, n, s));
+      HIP_TRY(M, launch_axpby(-1.0, G.tv, 1.0, G.rv, n, s));
+      if ((st = dot(M, G, G.rv, G.rv, tr2.data(), s))) return st;
+      if ((st = dot(M, G, G.fh, G.fh, f2.data(), s))) return st;
+      rtrue.assign(ns, 0.0);
+      for (int q = 0; q < ns; ++q) rtrue[q] = f2[q] > 0 ? std::sqrt(tr2[q] / f2[q]) : 0.0;
+    }
     converged = true;
     for (int q = 0; q < ns; ++q) {
       per[q].iterations = its[q];
       per[q].rel_res_prec = rels[q];
-      per[q].rel_res_true = f2[q] > 0 ? std::sqrt(tr2[q] / f2[q]) : 0.0;
+      per[q].rel_res_true = rtrue[q];
       per[q].status = done[q] ? MHDG_OK : MHDG_ERR_NOT_CONVERGED;
       converged &= done[q] != 0;
     }
@@ -2499,10 +2893,12 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       info[q] = per[q];
       info[q].t_rhs_ms = inf.t_rhs_ms;
       info[q].t_gmres_ms = inf.t_gmres_ms;
-      // applies this instance took part in (rhs 2, GMRES, true residual 1 for FP64)
-      info[q].n_applies = ns == 1 ? inf.n_applies
-                                  : 3 + G.seg_applies[q];
+      // applies this instance took part in (rhs 2, GMRES, and for FP64 the
+      // true residual unless the stopping test measured it)
+      info[q].n_applies = ns == 1 ? inf.n_applies : 2 + G.seg_applies[q];
       info[q].reorth_passes = G.reorth;
+      info[q].cycles = G.cycles;
+      info[q].host_waits = G.waits;
     }
   if (!converged) return fail(M, MHDG_ERR_NOT_CONVERGED, "solve: max_iter reached");
   return MHDG_OK;
@@ -2547,6 +2943,9 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
   carve(M, ws, o->restart, G);
   G.op_flags = MHDG_PRECONDITION | MHDG_TRANSPOSE | (o->graph ? MHDG_GRAPH : 0);
   G.classic = o->classic_gs != 0;
+  G.device = o->driver == MHDG_DRIVER_DEVICE && !G.classic && o->restart <= kDeviceMaxRestart;
+  if (o->stop_norm == MHDG_NORM_TRUE)
+    return fail(M, MHDG_ERR_INVALID_ARG, "adjoint: stops on the preconditioned residual only");
   if (o->folded) {
     if (!M->folded) return fail(M, MHDG_ERR_STATE, "adjoint: folded applies need mhdg_fold_operator");
     G.op_flags |= MHDG_FOLDED;
@@ -2578,6 +2977,8 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
         return st;
       inf.iterations = its[0];
       inf.rel_res_prec = rels[0];
+      inf.cycles = G.cycles;
+      inf.host_waits = G.waits;
       converged = done[0] != 0;
     }
   }

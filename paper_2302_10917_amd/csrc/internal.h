@@ -241,10 +241,15 @@ hipError_t launch_fold_apply_many(const MacroInfo* info, int64_t n, const int64_
 // Vectors may hold nseg independent segments of length n (coefficient
 // instances): dot products and updates are per segment; out / h are indexed
 // [column * nseg + segment].
+// skip (null, or per segment): segments with a nonzero flag are left out
+// (their outputs are not written); ncol_seg (null, or per segment) limits the
+// columns gemv_sub reads for each segment.
 hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, int64_t n,
-                       double* partial, int nblk, double* out, hipStream_t s, int nseg = 1);
+                       double* partial, int nblk, double* out, hipStream_t s, int nseg = 1,
+                       const int32_t* skip = nullptr);
 hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double* h, double* w,
-                           int64_t n, double sign, hipStream_t s, int nseg = 1);
+                           int64_t n, double sign, hipStream_t s, int nseg = 1,
+                           const int32_t* ncol_seg = nullptr);
 hipError_t launch_to_bf16(const float* src, void* dst, int64_t n, hipStream_t s);
 hipError_t launch_seg_scale_copy(const double* alpha, const double* x, double* y, int64_t n, int nseg,
                                  hipStream_t s);
@@ -252,12 +257,32 @@ hipError_t launch_seg_scale_copy(const double* alpha, const double* x, double* y
 // column in one read of V, the Hessenberg correction, the fused two-output update
 hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x, const double* y,
                         int64_t n, double* partial, int nblk, double* out, hipStream_t s,
-                        int nseg);
+                        int nseg, const int32_t* skip = nullptr);
 hipError_t launch_hbar_gemv(const double* Hb, int64_t ld, int nseg, int kmax, int rows,
                             const double* pq, double* out, hipStream_t s);
 hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg, const double* ca,
                               const double* cd, const double* sc, const double* z, double* u2,
-                              hipStream_t s);
+                              hipStream_t s, const int32_t* skip = nullptr);
+
+// Device state of the GMRES whose per-segment recurrences run on the device
+// (gmres_dev.hip); every pointer is into the solve workspace.  Per segment
+// q of ns: H rotated Hessenberg ((R + 1) x R, column-major), cs / sn
+// rotations [R], g rotated right side [R + 1], hprev [R + 1]; Hb finished
+// unrotated columns ((k (R + 1) + i) ns + q); pq dual products and Hbar a,
+// hy single products, coef update coefficients, y least-squares solution
+// [R ns]; alpha, nrm, nrm_true, fref, bref, rel, rel_true, tgt, est [ns];
+// prm = (rtol, max_iter); skip, active, done, jc (finished columns this
+// cycle), iters (in all), flag (non-finite residual), napp (applies taken
+// part in) [ns]; any [1].
+struct GmDev {
+  double *H, *cs, *sn, *g, *hprev, *Hb, *pq, *hy, *coef, *y;
+  double *alpha, *nrm, *nrm_true, *fref, *bref, *rel, *rel_true, *tgt, *est, *prm;
+  int32_t *skip, *active, *done, *jc, *iters, *flag, *napp, *any;
+  int ns;
+};
+hipError_t launch_gm_start(const GmDev& d, int R, hipStream_t s);
+hipError_t launch_gm_step(const GmDev& d, int R, int j, int last, hipStream_t s);
+hipError_t launch_gm_lsq(const GmDev& d, int R, hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);
 int dots_nblk(int64_t n);

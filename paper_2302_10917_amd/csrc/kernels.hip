@@ -918,14 +918,15 @@ int dots_nblk(int64_t n) {
 // instance); block x handles chunk (x % nblk) of segment (x / nblk).
 __global__ __launch_bounds__(256) void dots_partial_kernel(const double* __restrict__ V, int64_t ld,
                                                            int ncols, const double* __restrict__ w,
-                                                           int64_t n, double* __restrict__ partial) {
+                                                           int64_t n, double* __restrict__ partial,
+                                                           const int32_t* __restrict__ skip) {
   const int nblk_all = gridDim.x;
   const int nblk = n > kDotChunk ? (int)((n + kDotChunk - 1) / kDotChunk) : 1;   // = dots_nblk(n)
   const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
   const int nseg = nblk_all / nblk;
   const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (c >= ncols) return;
+  if (c >= ncols || (skip && skip[seg])) return;
   const double* v = V + c * ld + int64_t(seg) * n;
   w += int64_t(seg) * n;
   const int64_t i0 = int64_t(blk) * kDotChunk;
@@ -951,13 +952,14 @@ __global__ __launch_bounds__(256) void dots_partial_kernel(const double* __restr
 __global__ __launch_bounds__(256) void dots2_partial_kernel(const double* __restrict__ V, int64_t ld,
                                                             int ncols, const double* __restrict__ x,
                                                             const double* __restrict__ y, int64_t n,
-                                                            double* __restrict__ partial) {
+                                                            double* __restrict__ partial,
+                                                            const int32_t* __restrict__ skip) {
   const int nblk = n > kDotChunk ? (int)((n + kDotChunk - 1) / kDotChunk) : 1;
   const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
   const int nseg = gridDim.x / nblk;
   const int c0 = blockIdx.y * 8 + (threadIdx.x >> 6), c1 = c0 + 4;
   const int lane = threadIdx.x & 63;
-  if (c0 >= ncols) return;
+  if (c0 >= ncols || (skip && skip[seg])) return;
   const bool two = c1 < ncols;
   const double* v0p = V + c0 * ld + int64_t(seg) * n;
   const double* v1p = V + (two ? c1 : c0) * ld + int64_t(seg) * n;
@@ -1041,12 +1043,14 @@ __global__ __launch_bounds__(256) void dual_update_kernel(double* __restrict__ V
                                                           const double* __restrict__ cd,
                                                           const double* __restrict__ sc,
                                                           const double* __restrict__ z,
-                                                          double* __restrict__ u2) {
+                                                          double* __restrict__ u2,
+                                                          const int32_t* __restrict__ skip) {
   const int64_t total = n * nseg;
   const int64_t idx0 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   const bool ok = idx0 < total;
   const int64_t idx = ok ? idx0 : total - 1;   // in-bounds address; result discarded
   const int seg = (int)(idx / n);
+  if (skip && skip[seg]) return;   // segment out of this cycle: V left as it is
   const int seg0 = __builtin_amdgcn_readfirstlane(seg);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
   if (__all(seg == seg0)) {
@@ -1089,8 +1093,10 @@ __global__ __launch_bounds__(256) void dual_update_kernel(double* __restrict__ V
 
 // out[c * nseg + seg] = sum over the chunks of (column c, segment seg)
 __global__ __launch_bounds__(64) void dots_final_kernel(const double* __restrict__ partial, int nblk,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, int nseg,
+                                                        const int32_t* __restrict__ skip) {
   const int c = blockIdx.x;
+  if (skip && skip[c % nseg]) return;   // segment out of this cycle: no partial sums to add
   double acc = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) acc += partial[int64_t(c) * nblk + b];
   acc = wave_sum(acc);
@@ -1098,12 +1104,14 @@ __global__ __launch_bounds__(64) void dots_final_kernel(const double* __restrict
 }
 
 // w += sign * V h with one coefficient vector per segment: h[c * nseg + seg]
-__global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ld, int ncols,
+__global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ld, int ncols_all,
                                 const double* __restrict__ hh, double* __restrict__ w, int64_t n,
-                                int nseg, double sign) {
+                                int nseg, double sign, const int32_t* __restrict__ ncol_seg) {
   int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (i >= n * nseg) return;
   const int seg = (int)(i / n);
+  const int ncols = ncol_seg ? min(ncols_all, ncol_seg[seg]) : ncols_all;
+  if (ncols <= 0) return;
   const double* h = hh + seg;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int c = 0;
@@ -1460,27 +1468,31 @@ hipError_t launch_mass(const MacroInfo* info, int64_t n, const double* tmpl, con
 }
 
 hipError_t launch_dots(const double* V, int64_t ld, int ncols, const double* w, int64_t n,
-                       double* partial, int nblk, double* out, hipStream_t s, int nseg) {
+                       double* partial, int nblk, double* out, hipStream_t s, int nseg,
+                       const int32_t* skip) {
   hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk * nseg, (ncols + 3) / 4), dim3(256), 0, s, V,
-                     ld, ncols, w, n, partial);
-  hipLaunchKernelGGL(dots_final_kernel, dim3(ncols * nseg), dim3(64), 0, s, partial, nblk, out);
+                     ld, ncols, w, n, partial, skip);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(ncols * nseg), dim3(64), 0, s, partial, nblk, out,
+                     nseg, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double* h, double* w,
-                           int64_t n, double sign, hipStream_t s, int nseg) {
+                           int64_t n, double sign, hipStream_t s, int nseg,
+                           const int32_t* ncol_seg) {
   if (ncols == 0) return hipSuccess;
   hipLaunchKernelGGL(gemv_sub_kernel, dim3(blocks_for(n * nseg, 256)), dim3(256), 0, s, V, ld,
-                     ncols, h, w, n, nseg, sign);
+                     ncols, h, w, n, nseg, sign, ncol_seg);
   return hipGetLastError();
 }
 
 hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x, const double* y,
                         int64_t n, double* partial, int nblk, double* out, hipStream_t s,
-                        int nseg) {
+                        int nseg, const int32_t* skip) {
   hipLaunchKernelGGL(dots2_partial_kernel, dim3(nblk * nseg, (ncols + 7) / 8), dim3(256), 0, s, V,
-                     ld, ncols, x, y, n, partial);
-  hipLaunchKernelGGL(dots_final_kernel, dim3(2 * ncols * nseg), dim3(64), 0, s, partial, nblk, out);
+                     ld, ncols, x, y, n, partial, skip);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(2 * ncols * nseg), dim3(64), 0, s, partial, nblk, out,
+                     nseg, skip);
   return hipGetLastError();
 }
 
@@ -1495,9 +1507,9 @@ hipError_t launch_hbar_gemv(const double* Hb, int64_t ld, int nseg, int kmax, in
 
 hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg, const double* ca,
                               const double* cd, const double* sc, const double* z, double* u2,
-                              hipStream_t s) {
+                              hipStream_t s, const int32_t* skip) {
   hipLaunchKernelGGL(dual_update_kernel, dim3(blocks_for(n * nseg, 256)), dim3(256), 0, s, V, ld,
-                     j, n, nseg, ca, cd, sc, z, u2);
+                     j, n, nseg, ca, cd, sc, z, u2, skip);
   return hipGetLastError();
 }
 

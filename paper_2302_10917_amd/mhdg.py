@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libmhdg.so")
 
 MHDG_FP64, MHDG_FP32, MHDG_BF16, MHDG_QELIM = 0, 1, 2, 3
 MHDG_PRECONDITION, MHDG_TRANSPOSE, MHDG_GRAPH, MHDG_FOLDED = 1, 2, 4, 8
+MHDG_DRIVER_DEVICE, MHDG_DRIVER_HOST = 0, 1
+MHDG_NORM_PRECONDITIONED, MHDG_NORM_TRUE = 0, 1
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "MESH", 3: "SINGULAR", 4: "NOT_CONVERGED",
           5: "WORKSPACE", 6: "HIP", 7: "STATE", 8: "NONFINITE"}
@@ -55,7 +57,8 @@ class SolveOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("zero_guess", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
                 ("graph", ctypes.c_int32), ("folded", ctypes.c_int32),
-                ("classic_gs", ctypes.c_int32)]
+                ("classic_gs", ctypes.c_int32), ("driver", ctypes.c_int32),
+                ("stop_norm", ctypes.c_int32)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -91,7 +94,8 @@ class SolveInfo(ctypes.Structure):
                 ("rel_res_prec", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("t_rhs_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
                 ("n_applies", ctypes.c_int32), ("outer_iterations", ctypes.c_int32),
-                ("reorth_passes", ctypes.c_int32)]
+                ("reorth_passes", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("host_waits", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -301,7 +305,7 @@ class MacroMesh:
 
     def solve(self, f_nodes, g_bnd, lam, rtol=1e-10, restart=30, max_iter=10000, zero_guess=True,
               stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True, folded=False,
-              classic_gs=False):
+              classic_gs=False, driver=None, stop_norm=None):
         import torch
         self.state_gen += 1
         s = self.query(self.precision, restart)
@@ -310,7 +314,9 @@ class MacroMesh:
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1 if zero_guess else 0,
                          int(max_outer), float(inner_rtol), 1 if graph else 0,
-                         1 if folded else 0, 1 if classic_gs else 0)
+                         1 if folded else 0, 1 if classic_gs else 0,
+                         MHDG_DRIVER_DEVICE if driver is None else int(driver),
+                         MHDG_NORM_PRECONDITIONED if stop_norm is None else int(stop_norm))
         infos = (SolveInfo * max(1, s.n_instances))()
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
                                   _ptr(self.solve_ws), self.solve_ws.numel(),
@@ -327,14 +333,16 @@ class MacroMesh:
 
     def adjoint(self, lam, qu, dJ_dU, psi_lam, psi_U, dJ_dkappa, dJ_dbeta, rtol=1e-12,
                 restart=300, max_iter=20000, stream=None, graph=True, folded=False,
-                classic_gs=False):
+                classic_gs=False, driver=None):
         import torch
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
             self.solve_ws = None
             self.solve_ws = torch.empty(s.solve_ws_bytes, dtype=torch.uint8, device="cuda")
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0,
-                         1 if folded else 0, 1 if classic_gs else 0)
+                         1 if folded else 0, 1 if classic_gs else 0,
+                         MHDG_DRIVER_DEVICE if driver is None else int(driver),
+                         MHDG_NORM_PRECONDITIONED)
         info = SolveInfo()
         self._check(self._lib.mhdg_adjoint(self.h, _ptr(lam), _ptr(qu), _ptr(dJ_dU),
                                            ctypes.byref(opts), _ptr(psi_lam), _ptr(psi_U),

@@ -1,0 +1,177 @@
+"""GMRES with the Arnoldi recurrences on the device (section 6.1: GMRES on the
+condensed trace system, left-preconditioned with D^-1).
+
+The device driver runs the same delayed-reorthogonalisation Arnoldi process
+as the host driver; its restart cycles replay captured hipGraphs (or the same
+launches directly) and the host waits once per cycle.  Checks:
+
+* solutions to rtol 1e-13 match the oracle's direct solve per face (1e-10)
+  and the host driver's iteration counts (the same Krylov process up to
+  rounding);
+* the graph-captured solve equals the directly launched one bit for bit, on
+  every replay, with eager work and synchronisations between replays;
+* host waits per solve are at most the number of cycles plus one with
+  graphs (plus one per 32 columns for long cycles launched directly);
+* stopping on the unpreconditioned residual: the oracle's ||f^ - S lam|| /
+  ||f^|| of the result is at most rtol;
+* coefficient instances, the folded flux-eliminated form, the iteration cap.
+"""
+import numpy as np
+import pytest
+
+from oracle import hdg
+from paper_2302_10917_amd import inputs
+
+import parity as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_10917_amd import mhdg  # noqa: E402
+
+DEV = "cuda"
+
+
+def gpu(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _case(n=3, r=2, p=3, kappa=0.05, beta=(1.0, 0.5), jitter=0.12, precision=None):
+    xy, tri = inputs.structured_mesh(n, jitter=jitter, seed=7)
+    kap = kappa * inputs.lognormal_kappa(len(tri), 0.3, seed=9)
+    orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0)
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    kw = {} if precision is None else {"precision": precision}
+    m.factor_local(gpu(kap), beta, 1.0, **kw)
+    node, bnd = m.sample_points()
+    ex = inputs.exp_sin(kappa, beta)
+    f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+    fo, go = orc.sample(ex)
+    return orc, m, f, g, fo, go
+
+
+@pytest.mark.parametrize("restart", [7, 300])
+def test_device_driver_matches_oracle_and_host_driver(restart):
+    orc, m, f, g, fo, go = _case()
+    lam_o, U_o, _ = orc.solve(fo, go)
+    n = orc.topo.n_trace
+    res = {}
+    for name, kw in (("host", dict(driver=mhdg.MHDG_DRIVER_HOST)),
+                     ("device", dict(graph=False)), ("device_graph", dict(graph=True))):
+        lam = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = m.solve(f, g, lam, rtol=1e-13, restart=restart, max_iter=5000, **kw)
+        assert info.status == 0 and info.rel_res_prec <= 1e-13, name
+        err = P.faces(host(lam), lam_o, orc.topo)
+        print(f"  {name}: {info.iterations} it, {info.cycles} cycles, {info.host_waits} waits, "
+              f"lam vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-10, name
+        res[name] = info
+    # graphs: one wait per cycle (and one for the first cycle start); direct
+    # launches of long cycles also wait once per 32 columns
+    g = res["device_graph"]
+    assert g.host_waits <= g.cycles + 1
+    d = res["device"]
+    assert d.host_waits <= d.cycles + 2 + d.iterations // 32
+    it_h, it_d = res["host"].iterations, res["device"].iterations
+    assert abs(it_h - it_d) <= 1 + it_h // 50
+    qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    assert P.macros(host(qu), np.concatenate(U_o), orc.topo) <= 1e-10
+
+
+@pytest.mark.parametrize("folded,restart", [(False, 9), (True, 9), (False, 100)])
+def test_graph_replays_equal_the_direct_launches_bitwise(folded, restart):
+    """restart 100: the direct launches skip the rest of the converged cycle
+    (look-ahead over 32-column chunks), the graphs replay it as empty launches;
+    the results are the same bits."""
+    orc, m, f, g, _, _ = _case(precision=mhdg.MHDG_QELIM if folded else None)
+    if folded:
+        m.fold_operator()
+    n = orc.topo.n_trace
+    ref = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info_ref = m.solve(f, g, ref, rtol=1e-12, restart=restart, max_iter=5000, graph=False,
+                       folded=folded)
+    ref_h = host(ref)
+    scratch = torch.empty(n, dtype=torch.float64, device=DEV)
+    for rep in range(3):
+        lam = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = m.solve(f, g, lam, rtol=1e-12, restart=restart, max_iter=5000, graph=True,
+                       folded=folded)
+        assert info.iterations == info_ref.iterations, rep
+        assert info.cycles == info_ref.cycles, rep
+        assert np.array_equal(host(lam), ref_h), rep
+        # eager work and a synchronisation between the replays
+        m.apply_trace_operator(lam, scratch, mhdg.MHDG_PRECONDITION)
+        torch.cuda.synchronize()
+    print(f"  folded={folded}: {info_ref.iterations} it in {info_ref.cycles} cycles, "
+          f"{info.host_waits} host waits", flush=True)
+    assert info.host_waits <= info.cycles + 1
+
+
+def test_true_residual_stopping():
+    orc, m, f, g, fo, go = _case(kappa=1e-2)
+    S, fhat, _ = orc.condensed(fo, go)
+    n = orc.topo.n_trace
+    for restart in (10, 200):
+        lam = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = m.solve(f, g, lam, rtol=1e-10, restart=restart, max_iter=5000,
+                       stop_norm=mhdg.MHDG_NORM_TRUE)
+        lh = host(lam)
+        r_true = np.linalg.norm(fhat - S @ lh) / np.linalg.norm(fhat)
+        print(f"  GMRES({restart}): {info.iterations} it, reported true {info.rel_res_true:.3e}, "
+              f"oracle {r_true:.3e}, preconditioned {info.rel_res_prec:.3e}", flush=True)
+        assert info.status == 0
+        assert info.rel_res_true <= 1e-10
+        assert r_true <= 1.05e-10
+        assert abs(r_true - info.rel_res_true) <= 1e-12 + 0.05 * r_true
+    with pytest.raises(mhdg.MhdgError):
+        m.solve(f, g, lam, rtol=1e-10, restart=10, stop_norm=mhdg.MHDG_NORM_TRUE,
+                driver=mhdg.MHDG_DRIVER_HOST)
+
+
+def test_device_driver_with_instances():
+    xy, tri = inputs.structured_mesh(3, jitter=0.1, seed=7)
+    r = inputs.random_levels(len(tri), (1, 2), seed=3)
+    kap_i = np.array([1e-2, 0.3, 1.0])
+    beta_i = np.array([[1.0, 0.5], [-0.5, 1.0], [0.2, 0.1]])
+    m = mhdg.MacroMesh(xy, tri, r, 2)
+    one = m.sizes
+    m.set_instances(3)
+    m.factor_local(gpu(np.repeat(kap_i, len(tri))), beta_i, 1.0)
+    node, bnd = m.sample_points()
+    fh, gh = np.empty(m.sizes.n_nodes), np.empty(m.sizes.n_bnd_points)
+    for i in range(3):
+        ex = inputs.exp_sin(float(kap_i[i]), beta_i[i])
+        a, b = i * one.n_nodes, (i + 1) * one.n_nodes
+        fh[a:b] = ex.f(node[a:b, 0], node[a:b, 1])
+        a, b = i * one.n_bnd_points, (i + 1) * one.n_bnd_points
+        gh[a:b] = ex.u(bnd[a:b, 0], bnd[a:b, 1])
+    lam = torch.zeros(m.sizes.n_trace, dtype=torch.float64, device=DEV)
+    m.solve(gpu(fh), gpu(gh), lam, rtol=1e-13, restart=11, max_iter=5000)
+    infos = m.last_solve_infos
+    lh = host(lam)
+    nt = one.n_trace
+    for i in range(3):
+        orc = hdg.Oracle(xy, tri, r, 2, float(kap_i[i]), tuple(beta_i[i]), 1.0)
+        lam_o, _, _ = orc.solve(*orc.sample(inputs.exp_sin(float(kap_i[i]), beta_i[i])))
+        assert infos[i]["status"] == 0 and infos[i]["rel_res_prec"] <= 1e-13, i
+        err = P.faces(lh[i * nt:(i + 1) * nt], lam_o, orc.topo)
+        print(f"  instance {i}: {infos[i]['iterations']} it, {err:.2e}", flush=True)
+        assert err <= 1e-10, i
+    assert infos[0]["host_waits"] <= infos[0]["cycles"] + 1
+
+
+def test_device_driver_iteration_cap():
+    orc, m, f, g, _, _ = _case()
+    lam = torch.zeros(orc.topo.n_trace, dtype=torch.float64, device=DEV)
+    info = m.solve(f, g, lam, rtol=1e-15, restart=5, max_iter=7, check=False)
+    assert info.status == 4 and info.iterations == 7
+    assert np.all(np.isfinite(host(lam)))
