@@ -319,6 +319,25 @@ mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* mesh, int32_t n_rhs, const
                                            double* out, int32_t flags, void* ws,
                                            size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream or
+ * graph capture, tight serving loops, hosts that forbid allocation): the
+ * many-vector apply of mhdg_apply_trace_operator_many, same arguments and
+ * result, without the workspace.  The contribution slots live in a fixed
+ * device array of the library, MHDG_NOALLOC_SCRATCH_BYTES per GPU, held from
+ * the first call on that GPU until the process ends.  The call makes no
+ * device allocation and records no timing events.  Needs
+ * mhdg_apply_many_ws_bytes(mesh, n_rhs) <= MHDG_NOALLOC_SCRATCH_BYTES
+ * (at 8192 macros, r = 3, p = 3, up to 13 vectors per call); larger requests
+ * return INVALID_ARG before anything is launched.  Every call on one GPU
+ * shares that GPU's array, whose contents on entry do not matter: calls that
+ * overlap on one GPU (other streams, threads or handles) race, and the caller
+ * must order them.  Errors: as mhdg_apply_trace_operator_many, and HIP if the
+ * array's address cannot be looked up. */
+#define MHDG_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+mhdg_status mhdg_apply_trace_operator_many_noalloc(mhdg_mesh* mesh, int32_t n_rhs,
+                                                   const double* lam, double* out, int32_t flags,
+                                                   void* stream);
+
 /* y_K = A_K^-1 x_K (or A_K^-T x_K with MHDG_TRANSPOSE) for every macro with
  * the stored factors (step 2).  x, y: device f64[n_local], may alias. */
 mhdg_status mhdg_local_solve(mhdg_mesh* mesh, const double* x, double* y, int32_t flags,

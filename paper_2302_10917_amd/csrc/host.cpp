@@ -2554,9 +2554,13 @@ size_t mhdg_apply_many_ws_bytes(const mhdg_mesh* M, int32_t n_rhs) {
   return size_t(n_rhs) * size_t(M->n_slots) * sizeof(double);
 }
 
-mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* M, int32_t n_rhs, const double* lam,
-                                           double* out, int32_t flags, void* ws, size_t ws_bytes,
-                                           void* stream) {
+}  // extern "C"
+
+namespace {
+// The many-vector apply with the contribution slots at `slots` (bytes of room
+// given); shared by the workspace and the no-allocation entry points.
+mhdg_status apply_many_impl(mhdg_mesh* M, int32_t n_rhs, const double* lam, double* out,
+                            int32_t flags, void* ws, size_t ws_bytes, void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;
   if (n_rhs < 0) return fail(M, MHDG_ERR_INVALID_ARG, "apply_many: n_rhs < 0");
   if (flags & ~(MHDG_PRECONDITION | MHDG_FOLDED))
@@ -2602,6 +2606,74 @@ mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* M, int32_t n_rhs, const do
                                         slots + int64_t(v0) * M->n_slots, M->n_slots,
                                         out + int64_t(v0) * M->n_trace, s));
   return MHDG_OK;
+}
+
+}  // namespace
+
+// Contribution slots of mhdg_apply_trace_operator_many_noalloc: a fixed
+// device array instead of a caller workspace.  Each GPU the library runs on
+// holds its own copy (at its own address) until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device, never through the array's name.
+static constexpr size_t kNoAllocBytes = size_t(MHDG_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex& scratch_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+void* g_scratch[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up on the first call
+// on that device.
+mhdg_status scratch_address(mhdg_mesh* M, void** out) {
+  int dev = -1;
+  HIP_TRY(M, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(M, MHDG_ERR_HIP, "apply_many_noalloc: device id out of range");
+  std::lock_guard<std::mutex> lk(scratch_mutex());
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(M, MHDG_ERR_HIP, std::string("apply_many_noalloc: scratch address: ") +
+                                       hipGetErrorString(e));
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return MHDG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+mhdg_status mhdg_apply_trace_operator_many(mhdg_mesh* M, int32_t n_rhs, const double* lam,
+                                           double* out, int32_t flags, void* ws, size_t ws_bytes,
+                                           void* stream) {
+  return apply_many_impl(M, n_rhs, lam, out, flags, ws, ws_bytes, stream);
+}
+
+mhdg_status mhdg_apply_trace_operator_many_noalloc(mhdg_mesh* M, int32_t n_rhs, const double* lam,
+                                                   double* out, int32_t flags, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (n_rhs < 0) return fail(M, MHDG_ERR_INVALID_ARG, "apply_many_noalloc: n_rhs < 0");
+  const size_t need = mhdg_apply_many_ws_bytes(M, n_rhs);
+  if (need > kNoAllocBytes)
+    return fail(M, MHDG_ERR_INVALID_ARG,
+                "apply_many_noalloc: n_rhs * n_slots * 8 = " + std::to_string(need) +
+                    " bytes exceeds the fixed scratch of " + std::to_string(kNoAllocBytes) +
+                    " bytes (use fewer vectors per call, or mhdg_apply_trace_operator_many)");
+  if (n_rhs == 0 || M->n_trace == 0) return apply_many_impl(M, n_rhs, lam, out, flags, nullptr, 0, stream);
+  void* ptr = nullptr;
+  mhdg_status st = scratch_address(M, &ptr);
+  if (st) return st;
+  // no event records here (they would create events): timing stays off for this call
+  const bool prof = M->prof;
+  M->prof = false;
+  st = apply_many_impl(M, n_rhs, lam, out, flags, ptr, kNoAllocBytes, stream);
+  M->prof = prof;
+  return st;
 }
 
 mhdg_status mhdg_local_solve(mhdg_mesh* M, const double* x, double* y, int32_t flags, void* stream) {

@@ -31,7 +31,9 @@ ABI_SYMBOLS = [
     "mhdg_set_instances", "mhdg_factor_local_batched", "mhdg_autotune",
     "mhdg_set_kernel_variant", "mhdg_fold_operator", "mhdg_apply_many_ws_bytes",
     "mhdg_apply_trace_operator_many", "mhdg_flux_balance", "mhdg_set_supg",
+    "mhdg_apply_trace_operator_many_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 MHDG_TUNE_LU, MHDG_TUNE_SOLVE = 1, 2
 MAX_CLASSES = 8
 
@@ -129,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         "mhdg_local_matrix": [P, I64, P, P],
         "mhdg_apply_trace_operator": [P, P, P, I32, P],
         "mhdg_apply_trace_operator_many": [P, I32, P, P, I32, P, SZ, P],
+        "mhdg_apply_trace_operator_many_noalloc": [P, I32, P, P, I32, P],
         "mhdg_local_solve": [P, P, P, I32, P],
         "mhdg_rhs": [P, P, P, P, I32, P],
         "mhdg_solve": [P, P, P, ctypes.POINTER(SolveOpts), P, P, SZ, P, P],
@@ -293,6 +296,19 @@ class MacroMesh:
         self._check(self._lib.mhdg_apply_trace_operator_many(
             self.h, n_rhs, _ptr(lam), _ptr(out), flags, _ptr(self.many_ws), self.many_ws.numel(),
             _stream(stream)), "apply_trace_operator_many")
+
+    def apply_many_ws_bytes(self, n_rhs):
+        """Bytes of contribution slots a many-vector apply of n_rhs vectors needs."""
+        return int(self._lib.mhdg_apply_many_ws_bytes(self.h, int(n_rhs)))
+
+    def apply_trace_operator_many_noalloc(self, lam, out, flags=0, stream=None):
+        """The same as apply_trace_operator_many with the library's fixed
+        per-GPU scratch instead of a workspace (no device allocation; calls
+        on one GPU must not overlap)."""
+        n_rhs = int(lam.shape[0]) if lam.dim() == 2 else 1
+        self._check(self._lib.mhdg_apply_trace_operator_many_noalloc(
+            self.h, n_rhs, _ptr(lam), _ptr(out), flags, _stream(stream)),
+            "apply_trace_operator_many_noalloc")
 
     def local_solve(self, x, y, flags=0, stream=None):
         self._check(self._lib.mhdg_local_solve(self.h, _ptr(x), _ptr(y), flags, _stream(stream)),
