@@ -423,7 +423,10 @@ mhdg_status mhdg_adjoint(mhdg_mesh* mesh, const double* lam, const double* qu, c
  * triangular solve and one rank-64 MFMA update per panel), reading the
  * trailing matrix 4-8 times less often.  The per-macro triangular solves
  * (steps 1-3) run on one wavefront per macro (solve variant 1), or on four
- * or eight wavefronts per macro (variants 2, 3) that split each column. */
+ * or eight wavefronts per macro (variants 2, 3) that split each column, or,
+ * for N_K in (512, 1024], on one wavefront per macro with the register
+ * budget of 6, 5, 5 or 4 resident wavefronts per SIMD and 8, 8, 12 or 16
+ * factor columns' chunks in flight per load group (variants 4 to 7). */
 #define MHDG_MAX_CLASSES 8
 enum { MHDG_TUNE_LU = 1, MHDG_TUNE_SOLVE = 2 };
 typedef struct {
@@ -431,10 +434,10 @@ typedef struct {
   int32_t N[MHDG_MAX_CLASSES];
   int64_t count[MHDG_MAX_CLASSES];
   int32_t lu_variant[MHDG_MAX_CLASSES];     /* chosen (1 or 2)                 */
-  int32_t solve_variant[MHDG_MAX_CLASSES];  /* chosen (1, 2 or 3)              */
+  int32_t solve_variant[MHDG_MAX_CLASSES];  /* chosen (1 to 7)                 */
   double lu_ms[MHDG_MAX_CLASSES][3];        /* [class][variant]: LU of up to 512
                                                macros of the class; 0 = not tried */
-  double apply_ms[MHDG_MAX_CLASSES][4];     /* [class][variant]: one apply solve
+  double apply_ms[MHDG_MAX_CLASSES][8];     /* [class][variant]: one apply solve
                                                of the whole class; 0 = not tried */
 } mhdg_tune_report;
 

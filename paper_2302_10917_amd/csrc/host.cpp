@@ -2394,7 +2394,7 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
       SizeClass sub = c;
       int best = 0;
       double best_ms = 0;
-      for (int v = SOLVE_WAVE; v <= SOLVE_MW8; ++v) {
+      for (int v = SOLVE_WAVE; v <= SOLVE_WAVE4_LG16; ++v) {
         if (!solve_variant_ok(v, c.N)) continue;
         if (M->precision == MHDG_BF16 && v != SOLVE_WAVE) continue;   // BF16: one wavefront
         sub.solve_var = v;

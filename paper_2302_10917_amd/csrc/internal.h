@@ -122,7 +122,14 @@ struct SizeClass {
 
 // Kernel variants the autotuner chooses between, per size class.
 enum LuVariant { LU_DEFAULT = 0, LU_PANEL = 1, LU_BLOCKED = 2 };
-enum SolveVariant { SOLVE_DEFAULT = 0, SOLVE_WAVE = 1, SOLVE_MW4 = 2, SOLVE_MW8 = 3 };
+// SOLVE_WAVE6 / SOLVE_WAVE5: one wavefront per macro like SOLVE_WAVE, with
+// the register budget of 6 or 5 resident wavefronts per SIMD (for N_K in
+// (512, 1024], where the 8-wavefront budget spills); SOLVE_WAVE5_LG12 and
+// SOLVE_WAVE4_LG16 also keep 12 or 16 column chunks in flight per load group
+// instead of 8.
+enum SolveVariant { SOLVE_DEFAULT = 0, SOLVE_WAVE = 1, SOLVE_MW4 = 2, SOLVE_MW8 = 3,
+                    SOLVE_WAVE6 = 4, SOLVE_WAVE5 = 5, SOLVE_WAVE5_LG12 = 6,
+                    SOLVE_WAVE4_LG16 = 7 };
 int default_lu_variant(int N);
 int default_solve_variant(int N);
 bool lu_variant_ok(int v, int N);

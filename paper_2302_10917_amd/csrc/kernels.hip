@@ -1270,6 +1270,17 @@ static hipError_t macro_solve_t_dispatch(int nq, int mode, const void* fac, cons
   return hipErrorInvalidValue;
 }
 
+#define MSO_DECL(T_, W_, LG_)                                                                 \
+  extern template void macro_solve_launch<T_, 16, W_, LG_>(int, const void*, const MacroInfo*,   \
+                                                           const int32_t*, int64_t, int64_t,     \
+                                                           size_t, const int32_t*, const double*,\
+                                                           const Templates&, const int32_t*,     \
+                                                           double, const double*, const double*, \
+                                                           double*, double*, hipStream_t);
+MSO_DECL(double, 6, 8) MSO_DECL(double, 5, 8) MSO_DECL(double, 5, 12) MSO_DECL(double, 4, 16)
+MSO_DECL(float, 6, 8) MSO_DECL(float, 5, 8) MSO_DECL(float, 5, 12) MSO_DECL(float, 4, 16)
+#undef MSO_DECL
+
 #define MSW_DECL(T_, Q_, W_)                                                                  \
   extern template void macro_solve_mw_launch<T_, Q_, W_>(int, const void*, const MacroInfo*,  \
                                                      const int32_t*, int64_t, int64_t, size_t,\
@@ -1300,6 +1311,17 @@ static hipError_t macro_solve_dispatch(int variant, int nq, int mode, const void
     MS_CASE(1) MS_CASE(2) MS_CASE(3) MS_CASE(5) MS_CASE(8) MS_CASE(16) MS_CASE(27) MS_CASE(58)
 #undef MS_CASE
     return hipErrorInvalidValue;
+  }
+  if (variant >= SOLVE_WAVE6 && variant <= SOLVE_WAVE4_LG16 && nq > 8 && nq <= 16) {
+#define MO_CASE(V_, W_, LG_)                                                                  \
+  if (variant == V_) {                                                                        \
+    macro_solve_launch<T, 16, W_, LG_>(mode, fac, info, order, base, n, lds, perm, tmpl, Tp,  \
+                                       skip, tau, lam, xin, yout, slots, s);                  \
+    return hipGetLastError();                                                                 \
+  }
+    MO_CASE(SOLVE_WAVE6, 6, 8) MO_CASE(SOLVE_WAVE5, 5, 8) MO_CASE(SOLVE_WAVE5_LG12, 5, 12)
+    MO_CASE(SOLVE_WAVE4_LG16, 4, 16)
+#undef MO_CASE
   }
 #define MW_CASE(Q_, W_)                                                                       \
   if (nq <= Q_) {                                                                             \
@@ -1355,6 +1377,7 @@ int default_solve_variant(int N) { return N <= 1024 ? SOLVE_WAVE : SOLVE_MW4; }
 bool solve_variant_ok(int v, int N) {
   if (N > 58 * 64) return false;
   if (v == SOLVE_WAVE || v == SOLVE_MW4) return true;
+  if (v >= SOLVE_WAVE6 && v <= SOLVE_WAVE4_LG16) return N > 8 * 64 && N <= 16 * 64;
   return v == SOLVE_MW8 && N > 16 * 64;
 }
 int default_lu_variant(int N) { return N <= 256 ? LU_PANEL : LU_BLOCKED; }

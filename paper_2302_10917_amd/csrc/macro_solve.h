@@ -118,8 +118,8 @@ __device__ inline void edge_C(const MacroInfo& mi, int k, const double* tm, cons
 constexpr int kLoadGroup = 8;
 template <int NQ> struct SolveOccupancy { static constexpr int waves = NQ <= 16 ? 8 : (NQ <= 27 ? 4 : 2); };
 
-template <typename T, int NQ>
-__global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_kernel(int mode, const T* __restrict__ fac,
+template <typename T, int NQ, int W = SolveOccupancy<NQ>::waves, int LG = kLoadGroup>
+__global__ __launch_bounds__(64, W) void macro_solve_kernel(int mode, const T* __restrict__ fac,
                                                          const MacroInfo* __restrict__ info,
                                                          const int32_t* __restrict__ order, int64_t base,
                                                          const int32_t* __restrict__ perm_all,
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(64, SolveOccupancy<NQ>::waves) void macro_solve_ker
                                                          double* __restrict__ slots) {
   // loads in flight per group: the same number of bytes for FP32 factors,
   // half of them for BF16 (a wider group does not fit the register budget)
-  constexpr int kLG = sizeof(T) == 8 ? kLoadGroup : 2 * kLoadGroup;
+  constexpr int kLG = sizeof(T) == 8 ? LG : 2 * LG;
   extern __shared__ double sm[];
   const MacroInfo& mi = info[order[base + blockIdx.x]];
   if (skip && skip[mi.inst]) return;   // instance already converged: no work, outputs untouched
@@ -537,13 +537,13 @@ void macro_solve_t_launch(int mode, const void* fac, const MacroInfo* info, cons
                      yout, slots);
 }
 
-template <typename T, int NQ>
+template <typename T, int NQ, int W = SolveOccupancy<NQ>::waves, int LG = kLoadGroup>
 void macro_solve_launch(int mode, const void* fac, const MacroInfo* info, const int32_t* order,
                         int64_t base, int64_t n, size_t lds, const int32_t* perm,
                         const double* tmpl, const Templates& Tp, const int32_t* skip, double tau,
                         const double* lam, const double* xin, double* yout, double* slots,
                         hipStream_t s) {
-  hipLaunchKernelGGL((macro_solve_kernel<T, NQ>), dim3((unsigned)n), dim3(64), lds, s, mode,
+  hipLaunchKernelGGL((macro_solve_kernel<T, NQ, W, LG>), dim3((unsigned)n), dim3(64), lds, s, mode,
                      (const T*)fac, info, order, base, perm, tmpl, Tp, skip, tau, lam, xin, yout,
                      slots);
 }
