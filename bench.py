@@ -56,6 +56,11 @@ WORKLOADS = {
     "folded_qelim_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
                                               sol="exp_sin", precision="qelim", form="folded",
                                               restart=40),
+    # the matrix-based form (section 6.1): the global trace matrix assembled block-sparse
+    # from the operators folded from the Schur-block factors, GMRES(40) on its products
+    "assembled_qelim_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                                 sol="exp_sin", precision="qelim",
+                                                 form="assembled", restart=40),
     # the best tuned form on the uneven-level mesh (instance 0 of the batching configuration)
     "folded_qelim_mixed_r1to4_8192macro_p3_inst0": dict(n=64, r="mixed", p=3, kappa=None,
                                                         beta=None, sol="exp_sin",
@@ -355,7 +360,8 @@ def main():
         return bench_sequential_instances(args, w)
     if w.get("form") == "many_rhs":
         return bench_many_rhs(args, w)
-    folded = w.get("form") == "folded" or args.folded
+    assembled = w.get("form") == "assembled"
+    folded = (w.get("form") == "folded" or args.folded) and not assembled
     xy, tri = inputs.structured_mesh(w["n"])
     n_inst = w.get("n_inst", 1)
     if w["r"] == "mixed":
@@ -411,15 +417,18 @@ def main():
     # the plain form's cycles run as direct launches, so that every apply is
     # bracketed by HIP events for the roofline (its 11 ms applies leave no
     # launch overhead to hide); the folded forms replay captured cycles
-    sgraph = folded
+    sgraph = folded or assembled
 
     def step():
         m.factor_local(kappa, beta_arg, 1.0, precision=prec)
-        if folded:
+        if folded or assembled:
             m.fold_operator()
+        if assembled:
+            m.assemble_trace_matrix()
         info = m.solve(f, g, lam, rtol=args.rtol, restart=args.restart, max_iter=args.max_iter,
                        check=args.max_iter >= 20000, inner_rtol=args.inner_rtol, folded=folded,
-                       max_outer=60, graph=sgraph, driver=drv, stop_norm=stop)
+                       max_outer=60, graph=sgraph, driver=drv, stop_norm=stop,
+                       assembled=assembled)
         m.recover_local(lam, qu)
         infos.append(info.as_dict())
         inst_infos.append(m.last_solve_infos)
@@ -459,7 +468,8 @@ def main():
     # pure operator throughput (outside the timed steps)
     lam_r = torch.as_tensor(inputs.random_vector(s.n_trace, seed=1), device=dev)
     out = torch.empty_like(lam_r)
-    aflags = mhdg.MHDG_PRECONDITION | (mhdg.MHDG_FOLDED if folded else 0)
+    aflags = (mhdg.MHDG_PRECONDITION | (mhdg.MHDG_FOLDED if folded else 0) |
+              (mhdg.MHDG_ASSEMBLED if assembled else 0))
     m.apply_trace_operator(lam_r, out, aflags)
     torch.cuda.synchronize()
     ta = time.perf_counter()
@@ -568,6 +578,44 @@ def main():
         print(f"[bench] folded from Schur factors: {tuned['folded_flux_eliminated_fp64']}",
               file=sys.stderr, flush=True)
 
+        # the matrix-based form (section 6.1): S assembled from the operators folded
+        # from the Schur factors, GMRES on block-sparse products
+        print("[bench] assembled trace matrix from the Schur-block factors", file=sys.stderr,
+              flush=True)
+        a_infos = []
+
+        def astep():
+            m.factor_local(kappa, beta_arg, 1.0, precision=mhdg.MHDG_QELIM)
+            m.fold_operator()
+            m.assemble_trace_matrix()
+            inf = m.solve(f, g, lam, rtol=args.rtol, restart=args.folded_restart,
+                          max_iter=args.max_iter, assembled=True, driver=drv, stop_norm=stop)
+            m.recover_local(lam, qu)
+            a_infos.append(inf.as_dict())
+        astep()
+        a_infos.clear()
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        for _ in range(args.steps):
+            astep()
+        torch.cuda.synchronize()
+        tma = (time.perf_counter() - tm0) / args.steps
+        tuned["matrix_based_flux_eliminated_fp64"] = {
+            "time_to_solve_s": tma,
+            "applies_per_s": sum(x["n_applies"] for x in a_infos) / (tma * args.steps),
+            "iterations": [x["iterations"] for x in a_infos],
+            "gmres_restart": args.folded_restart,
+            "speedup_vs_plain": (ms_per_step / 1e3) / tma,
+            "rel_res_true": max(x["rel_res_true"] for x in a_infos),
+            "rel_res_prec": max(x["rel_res_prec"] for x in a_infos),
+            "cycles": a_infos[-1]["cycles"], "host_waits": a_infos[-1]["host_waits"],
+            "max_rel_diff_lambda_vs_plain":
+                float(torch.linalg.norm(lam - lam_plain) / torch.linalg.norm(lam_plain)),
+            "what": "the global trace matrix S = D - sum T_K assembled block-sparse from the "
+                    "folded Schur-factor operators; GMRES on its products (matrix-based form)"}
+        print(f"[bench] assembled: {tuned['matrix_based_flux_eliminated_fp64']}",
+              file=sys.stderr, flush=True)
+
     jitter = None
     if not args.no_jitter_control and args.workload == "plain_fp64_8192macro_r3_p3":
         # control: the same job on a mesh whose interior vertices move by up to 0.15 h in
@@ -659,7 +707,7 @@ def main():
                "lambda": rd(lam_lp, lam), "q": rd(qv_lp[:, :2], qv[:, :2]),
                "u": rd(qv_lp[:, 2], qv[:, 2])}
 
-    ams = kt["folded_apply" if folded else "apply_macro_solve"]
+    ams = kt["folded_apply" if (folded or assembled) else "apply_macro_solve"]
     # apply launches that did work: GMRES and residual applies (n_applies less the
     # two right-hand-side passes), per solve the largest count over instances.  The
     # event time of launches after every instance converged (the rest of the last
@@ -671,7 +719,7 @@ def main():
     apply_timing = "HIP events around every apply kernel of the timed solves"
     if ams["count"] == 0:
         # captured cycles: the apply kernel timed by events in the apply-only loop
-        ams = kt_apply["folded_apply" if folded else "apply_macro_solve"]
+        ams = kt_apply["folded_apply" if (folded or assembled) else "apply_macro_solve"]
         work_launches = ams["count"]
         apply_timing = ("HIP events around the apply kernel in an apply-only loop after the "
                         "timed solves (those replay captured GMRES cycles, without events)")
@@ -683,6 +731,10 @@ def main():
         # folded apply: T_K read once (8 L_K^2), the gathered trace and the slots, for
         # every instance
         nbytes = n_inst * fold_bytes(tri, w["r"], w["p"], one.n_trace)
+    if assembled:
+        # assembled product: every stored block once (and its table), the trace read and
+        # the result written once
+        nbytes = float(mhdg.load_library().mhdg_trace_matrix_ws_bytes(m.h)) + 16.0 * s.n_trace
     if n_inst > 1:
         # converged instances are masked out of later launches: count the
         # instances each launch actually processed (GMRES applies + the
@@ -717,7 +769,8 @@ def main():
                    "form": ("folded_fp64" if folded else
                             "batched_fp64" if n_inst > 1 else "plain_fp64")
                    if prec == mhdg.MHDG_FP64 else
-                   ("folded_flux_eliminated_fp64" if folded else "flux_eliminated_fp64")
+                   ("matrix_based_flux_eliminated_fp64" if assembled else
+                    "folded_flux_eliminated_fp64" if folded else "flux_eliminated_fp64")
                    if prec == mhdg.MHDG_QELIM else
                    ("fp32_factors_fp64_ir" if prec == mhdg.MHDG_FP32 else "bf16_factors_fp64_ir"),
                    "supg": bool(w.get("supg")),
@@ -733,7 +786,8 @@ def main():
                                      "copy-kernel calibrated; see profiles/)",
                      "traffic_vs_algorithmic": traffic["traffic_bytes_per_launch"] / nbytes
                      if traffic else None,
-                     "kernel": ("fold_apply_kernel (folded steps 1-3)" if folded else
+                     "kernel": ("trace_matrix_apply_kernel (assembled S)" if assembled else
+                                "fold_apply_kernel (folded steps 1-3)" if folded else
                                 "qelim_solve_kernel (apply steps 1-3, flux eliminated)"
                                 if prec == mhdg.MHDG_QELIM else
                                 "macro_solve_kernel<%s> (apply steps 1-3)"

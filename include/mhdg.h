@@ -119,9 +119,11 @@ enum {
                                  face combine), captured on first use for this
                                  (lam, out, flags) and kept until the next
                                  factor_local or set_instances              */
-  MHDG_FOLDED = 8             /* apply: steps 1-3 with the folded operators
+  MHDG_FOLDED = 8,            /* apply: steps 1-3 with the folded operators
                                  T_K of mhdg_fold_operator (T_K^T with
                                  MHDG_TRANSPOSE)                              */
+  MHDG_ASSEMBLED = 16         /* apply: the assembled matrix S of
+                                 mhdg_assemble_trace_matrix (no TRANSPOSE)   */
 };
 
 /* GMRES drivers (mhdg_solve_opts.driver) and stopping norms (.stop_norm) */
@@ -187,6 +189,9 @@ typedef struct {
                                  classic_gs = 1 or restart > 2048             */
   int32_t stop_norm;          /* MHDG_NORM_PRECONDITIONED (default) or
                                  MHDG_NORM_TRUE                              */
+  int32_t assembled;          /* 1: GMRES applies use the assembled matrix
+                                 (MHDG_ASSEMBLED; needs
+                                 mhdg_assemble_trace_matrix)                 */
 } mhdg_solve_opts;
 
 typedef struct {
@@ -421,7 +426,9 @@ mhdg_status mhdg_adjoint(mhdg_mesh* mesh, const double* lam, const double* qu, c
  * held in registers and updates the trailing matrix after each; variant 2
  * blocks 64-column panels (8-column register sub-panels, a blocked
  * triangular solve and one rank-64 MFMA update per panel), reading the
- * trailing matrix 4-8 times less often.  The per-macro triangular solves
+ * trailing matrix 4-8 times less often; variants 3 and 4 are variant 2 with
+ * the rank-64 update's U tiles loaded once into LDS for 2 or 4 row tiles
+ * per wavefront instead of streamed per row tile.  The per-macro triangular solves
  * (steps 1-3) run on one wavefront per macro (solve variant 1), or on four
  * or eight wavefronts per macro (variants 2, 3) that split each column, or,
  * for N_K in (512, 1024], on one wavefront per macro with the register
@@ -433,9 +440,9 @@ typedef struct {
   int32_t n_classes;
   int32_t N[MHDG_MAX_CLASSES];
   int64_t count[MHDG_MAX_CLASSES];
-  int32_t lu_variant[MHDG_MAX_CLASSES];     /* chosen (1 or 2)                 */
+  int32_t lu_variant[MHDG_MAX_CLASSES];     /* chosen (1 to 4)                 */
   int32_t solve_variant[MHDG_MAX_CLASSES];  /* chosen (1 to 7)                 */
-  double lu_ms[MHDG_MAX_CLASSES][3];        /* [class][variant]: LU of up to 512
+  double lu_ms[MHDG_MAX_CLASSES][5];        /* [class][variant]: LU of up to 512
                                                macros of the class; 0 = not tried */
   double apply_ms[MHDG_MAX_CLASSES][8];     /* [class][variant]: one apply solve
                                                of the whole class; 0 = not tried */
@@ -489,6 +496,23 @@ mhdg_status mhdg_set_kernel_variant(mhdg_mesh* mesh, int32_t N, int32_t lu_varia
  * Errors: STATE (before factor_local, or FP32 / BF16 factors), WORKSPACE,
  * INVALID_ARG (a macro trace larger than 192). */
 mhdg_status mhdg_fold_operator(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void* stream);
+
+/* The matrix-based form of section 6.1: the global trace matrix
+ * S = D - sum_K C_K A_K^-1 B_K (eq. global_problem) assembled over the
+ * interior trace unknowns from the folded operators T_K of
+ * mhdg_fold_operator.  Storage is block-sparse: one block per pair of
+ * interior faces that share a macro (rows and columns in the faces'
+ * canonical trace order), S_FF' = delta_FF' D_F - sum_{K holds F, F'}
+ * T_K[F, F'], each block column-major; at 8192 macros, r = 3, p = 3 this
+ * holds 304 MB against the 369 MB of the T_K.  Applies with MHDG_ASSEMBLED
+ * (and solves with opts->assembled) then run one block-sparse product per
+ * face row.  ws: device workspace of at least mhdg_trace_matrix_ws_bytes
+ * bytes, owned by the caller and used until the next factor_local or
+ * fold_operator.  Synchronises the stream once.
+ * Errors: STATE (before mhdg_fold_operator), WORKSPACE, INVALID_ARG (face
+ * traces over 129 values), HIP. */
+size_t mhdg_trace_matrix_ws_bytes(const mhdg_mesh* mesh);
+mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing of the hot path, for measurement.  enable = 1 clears
  * the counters and brackets every later launch of the listed kernels with

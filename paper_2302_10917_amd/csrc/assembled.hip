@@ -1,0 +1,151 @@
+// The matrix-based form of the trace operator (section 6.1's comparison of a
+// globally assembled S with the matrix-free apply): S = D - sum_K C_K A_K^-1
+// B_K (eq. global_problem) assembled over the interior trace unknowns from
+// the folded macro operators T_K = C_K A_K^-1 B_K, stored block-sparse, and
+// applied as one sparse matrix-vector product.
+//
+// Block (F, F') of S couples two interior faces of one macro (F = F' for the
+// diagonal block, which both macros of F contribute to):
+//   S_FF' = delta_FF' D_F - sum over the macros K holding F and F' of T_K[F, F'],
+// with D_F = -2 tau |F| M_F (M_F the face's 1D trace mass), rows and columns in
+// the faces' canonical trace order.  Each block is stored column-major
+// (n_F rows, n_F' columns), so one column is contiguous across the lanes of
+// the product kernel.
+#include "internal.h"
+
+namespace mhdg {
+
+// One workgroup per block: its values from the (one or two) T_K sub-blocks
+// and, on the diagonal, D_F.  T_K is column-major with leading dimension L_K.
+__global__ __launch_bounds__(256) void trace_matrix_build_kernel(
+    const TraceBlock* __restrict__ blk, const FaceInfo* __restrict__ faces,
+    const double* __restrict__ tm, Templates Tp, double tau, const double* __restrict__ T,
+    double* __restrict__ S) {
+  const TraceBlock& b = blk[blockIdx.x];
+  const int nF = b.nF, nC = b.nC;
+  const FaceInfo& f = faces[b.row_face];
+  const double* M1 = tm + Tp.lev[f.level].M1;
+  double* out = S + b.voff;
+  for (int x = threadIdx.x; x < nF * nC; x += blockDim.x) {
+    const int j = x / nF, i = x % nF;
+    double v = b.diag ? -2.0 * tau * f.len * M1[size_t(i) * nF + j] : 0.0;
+    for (int c = 0; c < b.ncontrib; ++c)
+      v -= T[b.toff[c] + int64_t(b.c0[c] + j) * b.L[c] + (b.r0[c] + i)];
+    out[x] = v;
+  }
+}
+
+// y = S lam (or D^-1 S lam with precondition) for one face row per
+// wavefront.  The row's blocks are stored one after another, so the row is
+// one column-major n_F x K array (K = the sum of its blocks' column counts)
+// whose columns k multiply the gathered trace values xs[k].  The wavefront
+// splits into G groups of 64 / G lanes (G = 4, 2, 1 for n_F <= 16, 32,
+// more); group g takes the columns k = g mod G, lane i of a group rows i,
+// i + 64 / G, ..., and the G partial sums meet by lane exchanges, so most
+// lanes load and every column is read once, coalesced.  Faces of a masked
+// coefficient instance write zeros (as the matrix-free apply does).
+constexpr int kMaxTraceNF = (1 << kMaxLevel) * 4 + 1;
+constexpr int kMaxRowCols = 5 * kMaxTraceNF;   // a face couples with at most 5 faces
+__global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
+    const int32_t* __restrict__ row_ptr, const TraceBlock* __restrict__ blk,
+    const FaceInfo* __restrict__ faces, const double* __restrict__ S,
+    const double* __restrict__ tm, Templates Tp, double tau, int precondition,
+    const int32_t* __restrict__ skip, const double* __restrict__ lam, double* __restrict__ out) {
+  __shared__ double xs[kMaxRowCols];
+  __shared__ double ys[kMaxTraceNF];
+  const int fr = blockIdx.x, lane = threadIdx.x;
+  const FaceInfo& f = faces[fr];
+  const int nF = f.nF;
+  if (skip && skip[f.inst]) {
+    for (int i = lane; i < nF; i += 64) out[f.tr_off + i] = 0.0;
+    return;
+  }
+  const int b0 = row_ptr[fr], b1 = row_ptr[fr + 1];
+  int K = 0;
+  for (int bi = b0; bi < b1; ++bi) {
+    const TraceBlock& b = blk[bi];
+    const int c_off = faces[b.col_face].tr_off;
+    for (int j = lane; j < b.nC; j += 64) xs[K + j] = lam[c_off + j];
+    K += b.nC;
+  }
+  __syncthreads();
+  const double* Sr = S + blk[b0].voff;
+  const int G = nF <= 16 ? 4 : (nF <= 32 ? 2 : 1);
+  const int W = 64 / G, g = lane / W, i0 = lane % W;
+  double acc[3] = {0.0, 0.0, 0.0};
+  int k = g;
+  for (; k + 3 * G < K; k += 4 * G) {
+    double v[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int i = i0 + W * t;
+        v[u][t] = i < nF ? Sr[int64_t(k + u * G) * nF + i] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double x = xs[k + u * G];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[t] += v[u][t] * x;
+    }
+  }
+  for (; k < K; k += G) {
+    const double x = xs[k];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int i = i0 + W * t;
+      if (i < nF) acc[t] += Sr[int64_t(k) * nF + i] * x;
+    }
+  }
+  // the groups' partial sums: lane i0 of group 0 ends with the row sums
+  for (int o = W; o < 64; o <<= 1)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[t] += __shfl_xor(acc[t], o, 64);
+  if (!precondition) {
+    if (g == 0)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int i = i0 + W * t;
+        if (i < nF) out[f.tr_off + i] = acc[t];
+      }
+    return;
+  }
+  // D_F^-1 y = -M_F^-1 y / (2 tau |F|)
+  if (g == 0)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int i = i0 + W * t;
+      if (i < nF) ys[i] = acc[t];
+    }
+  __syncthreads();
+  const double* Mi = tm + Tp.lev[f.level].M1inv;
+  const double sc = -1.0 / (2.0 * tau * f.len);
+  for (int i = lane; i < nF; i += 64) {
+    double d = 0.0;
+    for (int kk = 0; kk < nF; ++kk) d += Mi[size_t(i) * nF + kk] * ys[kk];
+    out[f.tr_off + i] = sc * d;
+  }
+}
+
+hipError_t launch_trace_matrix_build(const TraceBlock* blk, int64_t n_blocks, const FaceInfo* faces,
+                                     const double* tmpl, const Templates& T, double tau,
+                                     const double* Tk, double* S, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(trace_matrix_build_kernel, dim3((unsigned)n_blocks), dim3(256), 0, s, blk,
+                     faces, tmpl, T, tau, Tk, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_matrix_apply(const int32_t* row_ptr, const TraceBlock* blk,
+                                     const FaceInfo* faces, int64_t n_faces, const double* S,
+                                     const double* tmpl, const Templates& T, double tau,
+                                     int precondition, const int32_t* skip, const double* lam,
+                                     double* out, hipStream_t s) {
+  if (n_faces == 0) return hipSuccess;
+  hipLaunchKernelGGL(trace_matrix_apply_kernel, dim3((unsigned)n_faces), dim3(64), 0, s, row_ptr,
+                     blk, faces, S, tmpl, T, tau, precondition, skip, lam, out);
+  return hipGetLastError();
+}
+
+}  // namespace mhdg

@@ -60,6 +60,13 @@ struct mhdg_mesh {
   int64_t* fold_toff = nullptr;   // device: element offset of T_K
   double* fold_T = nullptr;       // device: T_K column-major, L_K x L_K
   int fold_maxL = 0;              // largest L_K
+  // assembled trace matrix (mhdg_assemble_trace_matrix): valid until the next
+  // factor_local or fold
+  bool assembled = false;
+  const int32_t* tm_row_ptr = nullptr;    // device: block rows per interior face
+  const TraceBlock* tm_blocks = nullptr;  // device: block table
+  const double* tm_values = nullptr;      // device: block values
+  int64_t tm_n_blocks = 0, tm_n_values = 0;
   int precision = MHDG_FP64;
   double tau = 1;
   char* ws = nullptr;
@@ -778,6 +785,82 @@ static FoldLayout fold_layout(const mhdg_mesh* M) {
   return F;
 }
 static size_t solve_bytes(const mhdg_mesh* M, int restart) { return solve_bytes_impl(M, restart); }
+
+// Block table of the assembled trace matrix: for every macro, every ordered
+// pair of its interior faces gives a block (F, F') fed by that macro's T_K
+// sub-block; the diagonal block of a face is fed by both of its macros.
+// Rows in the FaceInfo order, blocks of a row in the order of first
+// appearance.  T_K offsets follow mhdg_fold_operator's layout.
+struct TracePlan {
+  std::vector<int32_t> row_ptr;
+  std::vector<TraceBlock> blocks;
+  int64_t n_values = 0;
+  size_t off_row = 0, off_blk = 0, off_val = 0, total = 0;
+};
+static TracePlan trace_plan(const mhdg_mesh* M) {
+  TracePlan P;
+  const int64_t nf = M->n_int;
+  std::map<int64_t, int32_t> face_of_tr;   // trace offset -> interior face index
+  for (int64_t f = 0; f < nf; ++f) face_of_tr[M->faces[f].tr_off] = int32_t(f);
+  std::vector<std::map<int32_t, int32_t>> rowmap(nf);   // col face -> block index
+  std::vector<std::vector<int32_t>> rows(nf);
+  std::vector<TraceBlock> tmp;
+  int64_t toff = 0;
+  for (const MacroInfo& mi : M->macros) {
+    const int L = fold_L(M, mi);
+    int face[3], nF[3], r0[3], cnt = 0, o = 0;
+    for (int k = 0; k < 3; ++k) {
+      if (mi.tr_off[k] < 0) continue;
+      face[cnt] = face_of_tr.at(mi.tr_off[k]);
+      nF[cnt] = (1 << mi.flevel[k]) * M->p + 1;
+      r0[cnt] = o;
+      o += nF[cnt];
+      ++cnt;
+    }
+    for (int a = 0; a < cnt; ++a)
+      for (int b = 0; b < cnt; ++b) {
+        auto it = rowmap[face[a]].find(face[b]);
+        int32_t bi;
+        if (it == rowmap[face[a]].end()) {
+          bi = int32_t(tmp.size());
+          TraceBlock tb{};
+          tb.row_face = face[a];
+          tb.col_face = face[b];
+          tb.nF = nF[a];
+          tb.nC = nF[b];
+          tb.diag = face[a] == face[b];
+          tmp.push_back(tb);
+          rowmap[face[a]][face[b]] = bi;
+          rows[face[a]].push_back(bi);
+        } else {
+          bi = it->second;
+        }
+        TraceBlock& tb = tmp[bi];
+        const int c = tb.ncontrib++;
+        tb.toff[c] = toff;
+        tb.L[c] = L;
+        tb.r0[c] = r0[a];
+        tb.c0[c] = r0[b];
+      }
+    toff += int64_t(L) * L;
+  }
+  P.row_ptr.assign(nf + 1, 0);
+  for (int64_t f = 0; f < nf; ++f) {
+    P.row_ptr[f + 1] = P.row_ptr[f] + int32_t(rows[f].size());
+    for (int32_t bi : rows[f]) {
+      TraceBlock tb = tmp[bi];
+      tb.voff = P.n_values;
+      P.n_values += int64_t(tb.nF) * tb.nC;
+      P.blocks.push_back(tb);
+    }
+  }
+  size_t o = 0;
+  P.off_row = o;  o = align_up(o + P.row_ptr.size() * sizeof(int32_t));
+  P.off_blk = o;  o = align_up(o + P.blocks.size() * sizeof(TraceBlock));
+  P.off_val = o;  o = align_up(o + size_t(P.n_values) * sizeof(double));
+  P.total = o;
+  return P;
+}
 
 // ---------------------------------------------------------------- GMRES
 namespace {
@@ -1905,6 +1988,7 @@ mhdg_status mhdg_set_instances(mhdg_mesh* M, int32_t n_inst) {
   M->factored = false;
   M->have_rhs = false;
   M->folded = false;
+  M->assembled = false;
   M->ws = nullptr;
   M->drop_graphs();
   M->n_inst = n_inst;
@@ -2106,6 +2190,7 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   M->factored = false;
   M->have_rhs = false;
   M->folded = false;
+  M->assembled = false;
   M->drop_graphs();
   M->precision = precision;
   M->tau = tau;
@@ -2268,6 +2353,46 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* st
   M->fold_T = T;
   M->fold_maxL = maxL;
   M->folded = true;
+  M->assembled = false;
+  M->drop_graphs();
+  return MHDG_OK;
+}
+
+size_t mhdg_trace_matrix_ws_bytes(const mhdg_mesh* M) {
+  if (!M) return 0;
+  return trace_plan(M).total;
+}
+
+mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* M, void* ws, size_t ws_bytes, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->folded)
+    return fail(M, MHDG_ERR_STATE, "assemble_trace_matrix: needs mhdg_fold_operator first");
+  if (M->n_int > 0 && M->faces[0].nF > 0)
+    for (const FaceInfo& f : M->faces)
+      if (f.nF > (1 << kMaxLevel) * 4 + 1)
+        return fail(M, MHDG_ERR_INVALID_ARG, "assemble_trace_matrix: face trace too large");
+  const TracePlan P = trace_plan(M);
+  if (!ws || ws_bytes < P.total)
+    return fail(M, MHDG_ERR_WORKSPACE,
+                "assemble_trace_matrix: workspace smaller than mhdg_trace_matrix_ws_bytes");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  HIP_TRY(M, hipMemcpyAsync(w + P.off_row, P.row_ptr.data(), P.row_ptr.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(M, hipMemcpyAsync(w + P.off_blk, P.blocks.data(), P.blocks.size() * sizeof(TraceBlock),
+                            hipMemcpyHostToDevice, s));
+  FactorLayout& L = M->L;
+  HIP_TRY(M, launch_trace_matrix_build((const TraceBlock*)(w + P.off_blk), int64_t(P.blocks.size()),
+                                       (const FaceInfo*)(M->ws + L.faces),
+                                       (const double*)(M->ws + L.tmpl), M->T, M->tau, M->fold_T,
+                                       (double*)(w + P.off_val), s));
+  HIP_TRY(M, hipStreamSynchronize(s));   // the host tables above are freed on return
+  M->tm_row_ptr = (const int32_t*)(w + P.off_row);
+  M->tm_blocks = (const TraceBlock*)(w + P.off_blk);
+  M->tm_values = (const double*)(w + P.off_val);
+  M->tm_n_blocks = int64_t(P.blocks.size());
+  M->tm_n_values = P.n_values;
+  M->assembled = true;
   M->drop_graphs();
   return MHDG_OK;
 }
@@ -2287,6 +2412,7 @@ mhdg_status mhdg_set_supg(mhdg_mesh* M, int32_t on) {
   M->factored = false;
   M->have_rhs = false;
   M->folded = false;
+  M->assembled = false;
   M->drop_graphs();
   return MHDG_OK;
 }
@@ -2345,7 +2471,7 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
       sub.count = std::min<int64_t>(c.count, 512);
       int best = 0;
       double best_ms = 0;
-      for (int v = LU_PANEL; v <= LU_BLOCKED; ++v) {
+      for (int v = LU_PANEL; v <= LU_BLOCKED_U4; ++v) {
         if (!lu_variant_ok(v, c.N)) continue;
         sub.lu_var = v;
         SizeClass one_m = sub;
@@ -2507,6 +2633,16 @@ mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags
 mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
                            const int32_t* skip, hipStream_t s) {
   const int tr = (flags & MHDG_TRANSPOSE) ? 1 : 0;
+  if (flags & MHDG_ASSEMBLED) {
+    FactorLayout& L = M->L;
+    ProfScope ps(M, 5, s);
+    HIP_TRY(M, launch_trace_matrix_apply(M->tm_row_ptr, M->tm_blocks,
+                                         (const FaceInfo*)(M->ws + L.faces), M->n_int,
+                                         M->tm_values, (const double*)(M->ws + L.tmpl), M->T,
+                                         M->tau, (flags & MHDG_PRECONDITION) ? 1 : 0, skip, lam,
+                                         out, s));
+    return MHDG_OK;
+  }
   if (flags & MHDG_FOLDED) {
     FactorLayout& L = M->L;
     {
@@ -2545,6 +2681,13 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* o
     return fail(M, MHDG_ERR_STATE, "apply: the transposed operator needs FP64 factors");
   if ((flags & MHDG_FOLDED) && !M->folded)
     return fail(M, MHDG_ERR_STATE, "apply: folded operators need mhdg_fold_operator");
+  if (flags & MHDG_ASSEMBLED) {
+    if (!M->assembled)
+      return fail(M, MHDG_ERR_STATE, "apply: the assembled matrix needs mhdg_assemble_trace_matrix");
+    if (tr || (flags & MHDG_FOLDED))
+      return fail(M, MHDG_ERR_INVALID_ARG,
+                  "apply: MHDG_ASSEMBLED takes no MHDG_TRANSPOSE or MHDG_FOLDED");
+  }
   if (M->n_trace == 0) return MHDG_OK;
   return apply_op(M, lam, out, flags, nullptr, (hipStream_t)stream);
 }
@@ -2820,6 +2963,13 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
     if (!M->folded || (M->precision != MHDG_FP64 && M->precision != MHDG_QELIM))
       return fail(M, MHDG_ERR_STATE, "solve: folded applies need mhdg_fold_operator");
     G.op_flags |= MHDG_FOLDED;
+  }
+  if (o->assembled) {
+    if (!M->assembled)
+      return fail(M, MHDG_ERR_STATE, "solve: assembled applies need mhdg_assemble_trace_matrix");
+    if (o->folded)
+      return fail(M, MHDG_ERR_INVALID_ARG, "solve: folded and assembled are exclusive");
+    G.op_flags |= MHDG_ASSEMBLED;
   }
   const bool stop_true = o->stop_norm == MHDG_NORM_TRUE;
   if (stop_true && !(M->precision == MHDG_FP64 || M->precision == MHDG_QELIM))

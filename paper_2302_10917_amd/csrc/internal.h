@@ -121,7 +121,9 @@ struct SizeClass {
 };
 
 // Kernel variants the autotuner chooses between, per size class.
-enum LuVariant { LU_DEFAULT = 0, LU_PANEL = 1, LU_BLOCKED = 2 };
+// LU_BLOCKED_U2 / _U4: the blocked LU with the trailing update's U tiles
+// shared through LDS by 2 or 4 row tiles per wavefront
+enum LuVariant { LU_DEFAULT = 0, LU_PANEL = 1, LU_BLOCKED = 2, LU_BLOCKED_U2 = 3, LU_BLOCKED_U4 = 4 };
 // SOLVE_WAVE6 / SOLVE_WAVE5: one wavefront per macro like SOLVE_WAVE, with
 // the register budget of 6 or 5 resident wavefronts per SIMD (for N_K in
 // (512, 1024], where the 8-wavefront budget spills); SOLVE_WAVE5_LG12 and
@@ -136,7 +138,7 @@ bool lu_variant_ok(int v, int N);
 bool solve_variant_ok(int v, int N);
 
 template <typename T>
-hipError_t lu_blocked_class(T* fac, const MacroInfo* info, const int32_t* order,
+hipError_t lu_blocked_class(int variant, T* fac, const MacroInfo* info, const int32_t* order,
                             const SizeClass& c, int32_t* perm, int32_t* status, hipStream_t s);
 
 enum SolveMode { MODE_APPLY = 0, MODE_RHS = 1, MODE_RECOVER = 2, MODE_LOCAL = 3 };
@@ -270,6 +272,26 @@ hipError_t launch_hbar_gemv(const double* Hb, int64_t ld, int nseg, int kmax, in
 hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg, const double* ca,
                               const double* cd, const double* sc, const double* z, double* u2,
                               hipStream_t s, const int32_t* skip = nullptr);
+
+// One block of the assembled trace matrix (assembled.hip): rows of interior
+// face row_face, columns of interior face col_face (indices into the
+// FaceInfo array), values column-major at S + voff; built from ncontrib
+// (1 or 2) sub-blocks T_K[r0 + i, c0 + j] of folded operators (T_K at toff,
+// leading dimension L), plus D_F when diag.
+struct TraceBlock {
+  int64_t voff;
+  int64_t toff[2];
+  int32_t row_face, col_face, nF, nC, ncontrib, diag;
+  int32_t L[2], r0[2], c0[2];
+};
+hipError_t launch_trace_matrix_build(const TraceBlock* blk, int64_t n_blocks, const FaceInfo* faces,
+                                     const double* tmpl, const Templates& T, double tau,
+                                     const double* Tk, double* S, hipStream_t s);
+hipError_t launch_trace_matrix_apply(const int32_t* row_ptr, const TraceBlock* blk,
+                                     const FaceInfo* faces, int64_t n_faces, const double* S,
+                                     const double* tmpl, const Templates& T, double tau,
+                                     int precondition, const int32_t* skip, const double* lam,
+                                     double* out, hipStream_t s);
 
 // Device state of the GMRES whose per-segment recurrences run on the device
 // (gmres_dev.hip); every pointer is into the solve workspace.  Per segment

@@ -1177,7 +1177,7 @@ template <typename T>
 static hipError_t lu_class(T* fac, const MacroInfo* info, const int32_t* order, const SizeClass& c,
                            int32_t* perm, int32_t* status, hipStream_t s) {
   const int v = c.lu_var ? c.lu_var : default_lu_variant(c.N);
-  if (v == LU_BLOCKED) return lu_blocked_class(fac, info, order, c, perm, status, s);
+  if (v >= LU_BLOCKED) return lu_blocked_class(v, fac, info, order, c, perm, status, s);
   const dim3 g((unsigned)c.count);
   if (c.N <= 256)
     hipLaunchKernelGGL((lu_kernel<T, 256, 1, 16>), g, dim3(256), 0, s, fac, info, order, c.start, perm, status);
@@ -1381,7 +1381,7 @@ bool solve_variant_ok(int v, int N) {
   return v == SOLVE_MW8 && N > 16 * 64;
 }
 int default_lu_variant(int N) { return N <= 256 ? LU_PANEL : LU_BLOCKED; }
-bool lu_variant_ok(int v, int N) { return N <= 4096 && (v == LU_PANEL || v == LU_BLOCKED); }
+bool lu_variant_ok(int v, int N) { return N <= 4096 && v >= LU_PANEL && v <= LU_BLOCKED_U4; }
 
 // One launch per size class, each with the register-block count of its
 // local size (NQ = ceil(N/64)) and LDS for its boundary vectors.

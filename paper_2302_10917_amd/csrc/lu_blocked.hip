@@ -70,9 +70,76 @@ __device__ __forceinline__ void slab_update(T* __restrict__ A, int N, int ld, in
   }
 }
 
+// The same update with the U slab shared through LDS: the workgroup walks
+// groups of NW * RT row tiles; each wavefront keeps the L slab of its RT row
+// tiles in registers, and every 16-column tile of U is loaded once per row
+// group into LDS (Us: KW x 16 values) for all of them.  U is then read
+// ceil(rows / (16 NW RT)) times instead of once per row tile, and every
+// element of the updated block is still read and written once.
+template <typename T, int KW, int NW, int RT>
+__device__ __forceinline__ void slab_update_lds(T* __restrict__ A, int N, int ld, int r0, int c0,
+                                                int c1, int kc, int kw, int wid, int lane,
+                                                T* __restrict__ Us) {
+  constexpr int S = KW / 4;
+  const int nrt = (N - r0 + 15) >> 4, nct = (c1 - c0 + 15) >> 4;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tid = wid * 64 + lane;
+  for (int rg = 0; rg < nrt; rg += NW * RT) {
+    T a[RT][S];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = r0 + 16 * (rg + wid * RT + t) + li;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int k = 4 * s + lk;
+        a[t][s] = (row < N && k < kw) ? -A[size_t(row) * ld + kc + k] : T(0);
+      }
+    }
+    for (int ct = 0; ct < nct; ++ct) {
+      const int cb = c0 + 16 * ct;
+      __syncthreads();   // the previous tile's readers are done
+      for (int x = tid; x < KW * 16; x += NW * 64) {
+        const int k = x >> 4, c = x & 15;
+        Us[x] = (k < kw && cb + c < c1) ? A[size_t(kc + k) * ld + cb + c] : T(0);
+      }
+      __syncthreads();
+      T b[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) b[s] = Us[(4 * s + lk) * 16 + li];
+      const int col = cb + li;
+      const bool cok = col < c1;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int rr = r0 + 16 * (rg + wid * RT + t);
+        if (rr >= N) break;
+        typename Mfma<T>::acc acc0, acc1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = rr + Mfma<T>::drow(lk, v);
+          acc0[v] = (row < N && cok) ? A[size_t(row) * ld + col] : T(0);
+          acc1[v] = T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < S; s += 2) {
+          acc0 = Mfma<T>::run(a[t][s], b[s], acc0);
+          if (s + 1 < S) acc1 = Mfma<T>::run(a[t][s + 1], b[s + 1], acc1);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = rr + Mfma<T>::drow(lk, v);
+          if (row < N && cok) A[size_t(row) * ld + col] = acc0[v] + acc1[v];
+        }
+      }
+    }
+  }
+}
+
 // One workgroup of NT threads per macro; thread t owns the sub-panel rows
-// c0 + t + q NT (q < RPT), so RPT * NT >= N is required.
-template <typename T, int NT, int RPT, int NB, int SB>
+// c0 + t + q NT (q < RPT), so RPT * NT >= N is required.  TRT: row tiles
+// per wavefront in the trailing update with U tiles shared through LDS
+// (slab_update_lds; each keeps NB / 4 L values per row tile in registers),
+// or 0 for the update that streams U from memory per row tile.
+template <typename T, int NT, int RPT, int NB, int SB, int TRT>
 __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo* __restrict__ info,
                                                         const int32_t* __restrict__ order,
                                                         int64_t base, int32_t* perm_all,
@@ -90,7 +157,7 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
   __shared__ int s_red_i[NW];
   __shared__ T s_row[SB];
   __shared__ T s_swap[2][SB];
-  __shared__ T s_L[NB * NB];
+  __shared__ T s_L[NB * NB];   // L11 of the U12 solve; U tiles of the trailing update
   __shared__ int s_piv[SB];
   __shared__ int s_status;
 
@@ -266,7 +333,10 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
     }
     __syncthreads();
     // ---------------- A22 -= L21 U12 (rank nb)
-    slab_update<T, NB, NW>(A, N, ld, k0 + nb, k0 + nb, N, k0, nb, wid, lane);
+    if constexpr (TRT > 0)
+      slab_update_lds<T, NB, NW, TRT>(A, N, ld, k0 + nb, k0 + nb, N, k0, nb, wid, lane, s_L);
+    else
+      slab_update<T, NB, NW>(A, N, ld, k0 + nb, k0 + nb, N, k0, nb, wid, lane);
     __syncthreads();
   }
   // ---- store the factors column-major (in-place transpose by 32 x 32 tile pairs)
@@ -298,25 +368,35 @@ __global__ __launch_bounds__(NT) void lu_blocked_kernel(T* fac, const MacroInfo*
 }
 
 // Blocked NB = 64 / SB = 8 with 256 threads (N <= 1024) or 512 threads
-// (N <= 4096).
-template <typename T>
-hipError_t lu_blocked_class(T* fac, const MacroInfo* info, const int32_t* order,
-                            const SizeClass& c, int32_t* perm, int32_t* status, hipStream_t s) {
+// (N <= 4096); TRT from the variant (LU_BLOCKED: 0, LU_BLOCKED_U2: 2,
+// LU_BLOCKED_U4: 4).
+template <typename T, int TRT>
+static hipError_t lu_blocked_launch(T* fac, const MacroInfo* info, const int32_t* order,
+                                    const SizeClass& c, int32_t* perm, int32_t* status,
+                                    hipStream_t s) {
   const dim3 g((unsigned)c.count);
   if (c.N <= 1024)
-    hipLaunchKernelGGL((lu_blocked_kernel<T, 256, 4, 64, 8>), g, dim3(256), 0, s, fac, info, order,
-                       c.start, perm, status);
-  else if (c.N <= 4096)   // 8 wavefronts (two workgroups per CU fit the register file)
-    hipLaunchKernelGGL((lu_blocked_kernel<T, 512, 8, 64, 8>), g, dim3(512), 0, s, fac, info,
+    hipLaunchKernelGGL((lu_blocked_kernel<T, 256, 4, 64, 8, TRT>), g, dim3(256), 0, s, fac, info,
+                       order, c.start, perm, status);
+  else if (c.N <= 4096)   // 8 wavefronts
+    hipLaunchKernelGGL((lu_blocked_kernel<T, 512, 8, 64, 8, TRT>), g, dim3(512), 0, s, fac, info,
                        order, c.start, perm, status);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-template hipError_t lu_blocked_class<double>(double*, const MacroInfo*, const int32_t*,
+template <typename T>
+hipError_t lu_blocked_class(int variant, T* fac, const MacroInfo* info, const int32_t* order,
+                            const SizeClass& c, int32_t* perm, int32_t* status, hipStream_t s) {
+  if (variant == LU_BLOCKED_U2) return lu_blocked_launch<T, 2>(fac, info, order, c, perm, status, s);
+  if (variant == LU_BLOCKED_U4) return lu_blocked_launch<T, 4>(fac, info, order, c, perm, status, s);
+  return lu_blocked_launch<T, 0>(fac, info, order, c, perm, status, s);
+}
+
+template hipError_t lu_blocked_class<double>(int, double*, const MacroInfo*, const int32_t*,
                                              const SizeClass&, int32_t*, int32_t*, hipStream_t);
-template hipError_t lu_blocked_class<float>(float*, const MacroInfo*, const int32_t*,
+template hipError_t lu_blocked_class<float>(int, float*, const MacroInfo*, const int32_t*,
                                             const SizeClass&, int32_t*, int32_t*, hipStream_t);
 
 }  // namespace mhdg

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmhdg.so")
 
 MHDG_FP64, MHDG_FP32, MHDG_BF16, MHDG_QELIM = 0, 1, 2, 3
 MHDG_PRECONDITION, MHDG_TRANSPOSE, MHDG_GRAPH, MHDG_FOLDED = 1, 2, 4, 8
+MHDG_ASSEMBLED = 16
 MHDG_DRIVER_DEVICE, MHDG_DRIVER_HOST = 0, 1
 MHDG_NORM_PRECONDITIONED, MHDG_NORM_TRUE = 0, 1
 
@@ -31,7 +32,8 @@ ABI_SYMBOLS = [
     "mhdg_set_instances", "mhdg_factor_local_batched", "mhdg_autotune",
     "mhdg_set_kernel_variant", "mhdg_fold_operator", "mhdg_apply_many_ws_bytes",
     "mhdg_apply_trace_operator_many", "mhdg_flux_balance", "mhdg_set_supg",
-    "mhdg_apply_trace_operator_many_noalloc",
+    "mhdg_apply_trace_operator_many_noalloc", "mhdg_trace_matrix_ws_bytes",
+    "mhdg_assemble_trace_matrix",
 ]
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 MHDG_TUNE_LU, MHDG_TUNE_SOLVE = 1, 2
@@ -60,7 +62,7 @@ class SolveOpts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
                 ("graph", ctypes.c_int32), ("folded", ctypes.c_int32),
                 ("classic_gs", ctypes.c_int32), ("driver", ctypes.c_int32),
-                ("stop_norm", ctypes.c_int32)]
+                ("stop_norm", ctypes.c_int32), ("assembled", ctypes.c_int32)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -76,7 +78,7 @@ class KernelTimes(ctypes.Structure):
 class TuneReport(ctypes.Structure):
     _fields_ = [("n_classes", ctypes.c_int32), ("N", ctypes.c_int32 * 8),
                 ("count", ctypes.c_int64 * 8), ("lu_variant", ctypes.c_int32 * 8),
-                ("solve_variant", ctypes.c_int32 * 8), ("lu_ms", (ctypes.c_double * 3) * 8),
+                ("solve_variant", ctypes.c_int32 * 8), ("lu_ms", (ctypes.c_double * 5) * 8),
                 ("apply_ms", (ctypes.c_double * 8) * 8)]
 
     def as_list(self):
@@ -85,7 +87,7 @@ class TuneReport(ctypes.Structure):
             out.append({"N": int(self.N[i]), "count": int(self.count[i]),
                         "lu_variant": int(self.lu_variant[i]),
                         "solve_variant": int(self.solve_variant[i]),
-                        "lu_ms": {v: float(self.lu_ms[i][v]) for v in (1, 2) if self.lu_ms[i][v]},
+                        "lu_ms": {v: float(self.lu_ms[i][v]) for v in (1, 2, 3, 4) if self.lu_ms[i][v]},
                         "apply_ms": {v: float(self.apply_ms[i][v]) for v in range(1, 8)
                                      if self.apply_ms[i][v]}})
         return out
@@ -128,6 +130,7 @@ def load_library(path: str = LIB_PATH):
         "mhdg_set_kernel_variant": [P, I32, I32, I32],
         "mhdg_set_supg": [P, I32],
         "mhdg_fold_operator": [P, P, SZ, P],
+        "mhdg_assemble_trace_matrix": [P, P, SZ, P],
         "mhdg_local_matrix": [P, I64, P, P],
         "mhdg_apply_trace_operator": [P, P, P, I32, P],
         "mhdg_apply_trace_operator_many": [P, I32, P, P, I32, P, SZ, P],
@@ -148,6 +151,8 @@ def load_library(path: str = LIB_PATH):
         fn.restype = ctypes.c_int
     lib.mhdg_apply_many_ws_bytes.argtypes = [P, I32]
     lib.mhdg_apply_many_ws_bytes.restype = SZ
+    lib.mhdg_trace_matrix_ws_bytes.argtypes = [P]
+    lib.mhdg_trace_matrix_ws_bytes.restype = SZ
     lib.mhdg_destroy.argtypes = [P]
     lib.mhdg_destroy.restype = None
     lib.mhdg_last_error.argtypes = [P]
@@ -321,7 +326,7 @@ class MacroMesh:
 
     def solve(self, f_nodes, g_bnd, lam, rtol=1e-10, restart=30, max_iter=10000, zero_guess=True,
               stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True, folded=False,
-              classic_gs=False, driver=None, stop_norm=None):
+              classic_gs=False, driver=None, stop_norm=None, assembled=False):
         import torch
         self.state_gen += 1
         s = self.query(self.precision, restart)
@@ -332,7 +337,8 @@ class MacroMesh:
                          int(max_outer), float(inner_rtol), 1 if graph else 0,
                          1 if folded else 0, 1 if classic_gs else 0,
                          MHDG_DRIVER_DEVICE if driver is None else int(driver),
-                         MHDG_NORM_PRECONDITIONED if stop_norm is None else int(stop_norm))
+                         MHDG_NORM_PRECONDITIONED if stop_norm is None else int(stop_norm),
+                         1 if assembled else 0)
         infos = (SolveInfo * max(1, s.n_instances))()
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
                                   _ptr(self.solve_ws), self.solve_ws.numel(),
@@ -358,7 +364,7 @@ class MacroMesh:
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0,
                          1 if folded else 0, 1 if classic_gs else 0,
                          MHDG_DRIVER_DEVICE if driver is None else int(driver),
-                         MHDG_NORM_PRECONDITIONED)
+                         MHDG_NORM_PRECONDITIONED, 0)
         info = SolveInfo()
         self._check(self._lib.mhdg_adjoint(self.h, _ptr(lam), _ptr(qu), _ptr(dJ_dU),
                                            ctypes.byref(opts), _ptr(psi_lam), _ptr(psi_U),
@@ -388,6 +394,20 @@ class MacroMesh:
             self.fold_ws = torch.empty(max(s.fold_ws_bytes, 1), dtype=torch.uint8, device="cuda")
         self._check(self._lib.mhdg_fold_operator(self.h, _ptr(self.fold_ws), self.fold_ws.numel(),
                                                  _stream(stream)), "fold_operator")
+
+    def assemble_trace_matrix(self, stream=None):
+        """Assemble the global trace matrix S from the folded operators (call
+        fold_operator first); then apply/solve can use it (MHDG_ASSEMBLED /
+        assembled=True)."""
+        self.state_gen += 1
+        import torch
+        need = int(self._lib.mhdg_trace_matrix_ws_bytes(self.h))
+        if getattr(self, "matrix_ws", None) is None or self.matrix_ws.numel() < need:
+            self.matrix_ws = None
+            self.matrix_ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+        self._check(self._lib.mhdg_assemble_trace_matrix(self.h, _ptr(self.matrix_ws),
+                                                         self.matrix_ws.numel(), _stream(stream)),
+                    "assemble_trace_matrix")
 
     def set_supg(self, on: bool):
         """SUPG stabilisation inside the macros (section 3.4) on or off; the

@@ -183,10 +183,31 @@ def test_kernel_variant_validation():
     m.set_kernel_variant(N, 0, 0)
     with pytest.raises(mhdg.MhdgError):
         m.set_kernel_variant(N + 1, 1, 1)       # no class of that size
+    m.set_kernel_variant(N, 4, 7)               # LDS-shared update, 4-wave budget
     with pytest.raises(mhdg.MhdgError):
-        m.set_kernel_variant(N, 3, 1)           # no such LU variant
+        m.set_kernel_variant(N, 5, 1)           # no such LU variant
+    with pytest.raises(mhdg.MhdgError):
+        m.set_kernel_variant(N, 1, 8)           # no such solve variant
     with pytest.raises(mhdg.MhdgError):
         m.set_kernel_variant(N, 1, 3)           # eight wavefronts need N > 1024
     lib = _lib()
     rep = mhdg.TuneReport()
     assert lib.mhdg_autotune(m.h, 3, ctypes.byref(rep), None) == 7   # before factor_local
+
+
+def test_trace_matrix_size_counts_the_face_pair_blocks():
+    """The assembled trace matrix holds one block per pair of interior faces
+    that share a macro: each interior face's diagonal block and, per macro,
+    every ordered pair of distinct interior faces (computed on the host)."""
+    lib = _lib()
+    for n, r in ((3, 1), (64, 3)):
+        xy, tri = inputs.structured_mesh(n)
+        m = mhdg.MacroMesh(xy, tri, r, 3)
+        topo = hdg.Topology(xy, tri, r, 3)
+        c = np.array([sum(1 for k in range(3) if topo.interior[topo.macro_face[K, k]])
+                      for K in range(topo.n_macro)])
+        blocks = int(topo.interior.sum()) + int(np.sum(c * (c - 1)))
+        nF = 2 ** r * 3 + 1
+        got = lib.mhdg_trace_matrix_ws_bytes(m.h)
+        assert blocks * nF * nF * 8 <= got <= blocks * nF * nF * 8 + blocks * 128 + 4 * 4096 + \
+            4 * (int(topo.interior.sum()) + 1), (n, got)

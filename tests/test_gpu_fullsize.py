@@ -570,6 +570,46 @@ def test_c2_folded_flux_eliminated_sampled(c2):
     check_recovery(quh, U, topo, macros)
 
 
+
+def test_c2_assembled_matrix_sampled(c2):
+    """The matrix-based form at full size (S assembled from the operators
+    folded from the Schur factors): products on the sampled faces to the FP64
+    bar, GMRES(40) with assembled products within the residual bound, and
+    recovery on the sampled macros."""
+    orc, faces, macros = c2["orc"], c2["faces"], c2["macros"]
+    topo = orc.topo
+    xy, tri = inputs.structured_mesh(C2["n"])
+    kap = np.full(len(tri), C2["kappa"])
+    m = mhdg.MacroMesh(xy, tri, C2["r"], C2["p"])
+    try:
+        m.factor_local(gpu(kap), C2["beta"], 1.0, precision=mhdg.MHDG_QELIM)
+        m.fold_operator()
+        m.assemble_trace_matrix()
+        lam_r = inputs.random_vector(topo.n_trace, seed=1)
+        out = torch.empty(topo.n_trace, dtype=torch.float64, device=DEV)
+        for prec in (False, True):
+            ref = gather(orc.apply(lam_r, precondition=prec, faces=faces), topo, faces)
+            flags = mhdg.MHDG_ASSEMBLED | (mhdg.MHDG_PRECONDITION if prec else 0)
+            m.apply_trace_operator(gpu(lam_r), out, flags)
+            err = P.blocks(gather(host(out), topo, faces), ref, sizes_of(topo, faces))
+            print(f"  assembled product precondition={prec}: {err:.2e}", flush=True)
+            assert err <= TOL, prec
+        lam = torch.zeros(topo.n_trace, dtype=torch.float64, device=DEV)
+        info = m.solve(c2["f"], c2["g"], lam, rtol=RTOL, restart=40, max_iter=20000,
+                       assembled=True)
+        print(f"  GMRES(40) assembled: {info.iterations} it, rel {info.rel_res_prec:.2e}",
+              flush=True)
+        assert info.status == 0
+        qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+        m.recover_local(lam, qu)
+        lam_h, quh = host(lam), host(qu)
+    finally:
+        release(m)
+    Y, U = sampled_local(orc, macros, lam_h, c2["fo"], c2["lamD"])
+    res_o, _ = sampled_residual(orc, faces, lam_h, Y, U)
+    check_residual(res_o, c2["fhat_norm"])
+    check_recovery(quh, U, topo, macros)
+
 @pytest.mark.parametrize("folded", [True, False])
 def test_c2_forward_error_against_direct_solve(c2, folded):
     """Forward error at the benchmark size: lam from GMRES (no restart) to a
