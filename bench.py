@@ -66,6 +66,14 @@ WORKLOADS = {
                                                         beta=None, sol="exp_sin",
                                                         precision="qelim", form="folded",
                                                         instance=0, restart=50),
+    # standard HDG (r = 0: every element its own macro, section 3.2's special case) on the
+    # same data: 160 x 160 squares give 305,920 trace unknowns, the macro-element job's
+    # 304,000 (matched global size); 512 x 512 squares give the macro job's element size
+    # (matched resolution, 3.1 million trace unknowns)
+    "standard_hdg_160x160_r0_p3": dict(n=160, r=0, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                       sol="exp_sin", precision="fp64"),
+    "standard_hdg_512x512_r0_p3": dict(n=512, r=0, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                       sol="exp_sin", precision="fp64", restart=300),
     "plain_fp64_8macro_r1_p2": dict(n=2, r=1, p=2, kappa=1.0, beta=(1.0, 1.0), sol="sin_sin",
                                     precision="fp64"),
     # precision configuration: same mesh, kappa = 1e-3, FP32 factors + FP64 refinement
@@ -684,10 +692,23 @@ def main():
                "speedup_per_instance": (t_seq / kk) / (elapsed / args.steps / n_inst)}
         print(f"[bench] plain form: {seq}", file=sys.stderr, flush=True)
 
-    # discretisation error of the solution (sanity: the manufactured solution)
-    if np.ndim(w["r"]) == 0:
+    # discretisation error of the solution against the manufactured one: the largest
+    # nodal difference, and the L2 norm of u_h minus the interpolant of u (the macros'
+    # mass matrices), relative to the interpolant's
+    u_l2 = None
+    if np.ndim(w["r"]) == 0 and n_inst == 1:
         u_h = qu.view(s.n_macro, 3, Q)[:, 2, :].reshape(-1).cpu().numpy()
-        u_err = float(np.abs(u_h - ex.u(node[:, 0], node[:, 1])).max())
+        u_ex = ex.u(node[:, 0], node[:, 1])
+        u_err = float(np.abs(u_h - u_ex).max())
+
+        def l2(v):
+            d = torch.zeros(s.n_macro, 3, Q, dtype=torch.float64, device=dev)
+            d[:, 2, :] = torch.as_tensor(v, device=dev).view(s.n_macro, Q)
+            d = d.reshape(-1)
+            o = torch.empty_like(d)
+            m.mass_apply(d, o)
+            return float(torch.sqrt(torch.dot(d, o)))
+        u_l2 = l2(u_h - u_ex) / l2(u_ex)
     else:
         u_err = None
 
@@ -815,6 +836,7 @@ def main():
         / 1e12
         if lu["count"] else None,
         "u_max_err_vs_exact": u_err,
+        "u_rel_l2_err_vs_exact": u_l2,
         "autotune": tune,
         "tuned_forms": tuned,
         "jitter_control": jitter,
