@@ -332,9 +332,11 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
   }
   const int col0 = chunk * NR;
   if (col0 >= L) return;
+  // LDS: the columns of B_K, then one region that first holds the unpermuted
+  // right-hand sides and later the boundary rows of the solutions
   double* xc = sm;                    // NR x 3 NBD: columns of B_K (boundary rows)
-  double* zc = xc + NR * 3 * NBD;     // NR x 3 NBD: boundary rows of the solutions
-  double* us = zc + NR * 3 * NBD;     // NR x Q: z, then u
+  double* us = xc + NR * 3 * NBD;     // NR x Q: z, before the permuted gather
+  double* zc = us;                    // NR x 3 NBD: boundary rows of the solutions
   const LevelTemplates& LT = Tp.lev[mi.level];
   const QLevel& QL = QT.lev[mi.level];
   const int32_t* enode = ints_(tm, LT.edge_node);
@@ -480,15 +482,7 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
       }
     }
   }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int i = lane + 64 * q;
-    if (i < Q)
-#pragma unroll
-      for (int r = 0; r < NR; ++r) us[r * Q + i] = y[q][r];
-  }
-  __syncthreads();
-  // ---- boundary rows of the solutions
+  // ---- boundary rows of the solutions (u_j in registers: lane l holds j = l + 64 q)
   for (int b = 0; b < NBD; ++b) {
     const int k = b / P;
     const int nb = enode[k * (P + 1) + (b - k * P)];
@@ -498,13 +492,15 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
     double v0[NR], v1[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) v0[r] = v1[r] = 0.0;
-    for (int j = lane; j < Q; j += 64) {
-      const double p0 = r0[j], p1 = r1[j];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int j = lane + 64 * q;
+      const int jj = j < Q ? j : Q - 1;
+      const double p0 = j < Q ? r0[jj] : 0.0, p1 = j < Q ? r1[jj] : 0.0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const double uj = us[r * Q + j];
-        v0[r] += (G0 * p0 + G2 * p1) * uj;
-        v1[r] += (G1 * p0 + G3 * p1) * uj;
+        v0[r] += (G0 * p0 + G2 * p1) * y[q][r];
+        v1[r] += (G1 * p0 + G3 * p1) * y[q][r];
       }
     }
     for (int b2 = lane; b2 < NBD; b2 += 64) {
@@ -520,12 +516,21 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
       v0[r] = wave_sum_(v0[r]);
       v1[r] = wave_sum_(v1[r]);
     }
+    // u at boundary node nb: lane nb % 64 of register block nb / 64
+    double un[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) un[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (q == (nb >> 6))
+#pragma unroll
+        for (int r = 0; r < NR; ++r) un[r] = readlane_d(y[q][r], nb & 63);
     if (lane == 0)
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         zc[r * 3 * NBD + b] = v0[r];
         zc[r * 3 * NBD + NBD + b] = v1[r];
-        zc[r * 3 * NBD + 2 * NBD + b] = us[r * Q + nb];
+        zc[r * 3 * NBD + 2 * NBD + b] = un[r];
       }
   }
   __syncthreads();
@@ -551,7 +556,7 @@ hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, con
     const int nch = (max_L + nr - 1) / nr;
     const int64_t nblk = (sc.count + 7) / 8 * 8 * int64_t(nch);
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    const size_t lds = (size_t(nr) * (18 * sc.P + Q)) * sizeof(double);
+    const size_t lds = (size_t(nr) * (9 * sc.P + std::max(9 * sc.P, Q))) * sizeof(double);
     if (lds > 65536) return hipErrorInvalidValue;
     const dim3 g((unsigned)nblk), b(64);
 #define MHDG_QFOLD(NQ_, NR_)                                                                   \
