@@ -428,7 +428,11 @@ mhdg_status mhdg_adjoint(mhdg_mesh* mesh, const double* lam, const double* qu, c
  * triangular solve and one rank-64 MFMA update per panel), reading the
  * trailing matrix 4-8 times less often; variants 3 and 4 are variant 2 with
  * the rank-64 update's U tiles loaded once into LDS for 2 or 4 row tiles
- * per wavefront instead of streamed per row tile.  The per-macro triangular solves
+ * per wavefront instead of streamed per row tile; variant 5 takes 128-column
+ * panels, one launch per step (panel factorisation in one workgroup per
+ * macro, row moves and U12 = L11^-1 A12 on MFMA, then the rank-128 trailing
+ * update as a batched MFMA GEMM over 64 x 64 tiles spread across the chip,
+ * all tiles of one macro on one XCD).  The per-macro triangular solves
  * (steps 1-3) run on one wavefront per macro (solve variant 1), or on four
  * or eight wavefronts per macro (variants 2, 3) that split each column, or,
  * for N_K in (512, 1024], on one wavefront per macro with the register
@@ -440,9 +444,9 @@ typedef struct {
   int32_t n_classes;
   int32_t N[MHDG_MAX_CLASSES];
   int64_t count[MHDG_MAX_CLASSES];
-  int32_t lu_variant[MHDG_MAX_CLASSES];     /* chosen (1 to 4)                 */
+  int32_t lu_variant[MHDG_MAX_CLASSES];     /* chosen (1 to 5)                 */
   int32_t solve_variant[MHDG_MAX_CLASSES];  /* chosen (1 to 7)                 */
-  double lu_ms[MHDG_MAX_CLASSES][5];        /* [class][variant]: LU of up to 512
+  double lu_ms[MHDG_MAX_CLASSES][6];        /* [class][variant]: LU of up to 512
                                                macros of the class; 0 = not tried */
   double apply_ms[MHDG_MAX_CLASSES][8];     /* [class][variant]: one apply solve
                                                of the whole class; 0 = not tried */

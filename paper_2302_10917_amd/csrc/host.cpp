@@ -713,6 +713,17 @@ static void build_qelim_templates(mhdg_mesh* M) {
   }
 }
 
+// scratch of the split LU for every class it may factor (the LU variant can
+// change between factorisations); the flux-eliminated form factors Q x Q blocks
+static size_t split_lu_scratch(const mhdg_mesh* M, bool schur) {
+  size_t b = 0;
+  for (SizeClass c : M->classes) {
+    if (schur) c.N /= 3;
+    b += lu_split_scratch_bytes(c);
+  }
+  return b;
+}
+
 static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   FactorLayout L{};
   size_t o = 0;
@@ -740,6 +751,8 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
     QTemplates qt;
     L.qtmpl = o;   o = align_up(o + qelim_plan(M, &qt) * sizeof(double));
     L.info_lu = o; o = align_up(o + M->macros.size() * sizeof(MacroInfo));
+    L.lu_scr = o;  L.lu_scr_bytes = split_lu_scratch(M, true);
+    o = align_up(o + L.lu_scr_bytes);
     L.total = o;
     return L;
   }
@@ -748,6 +761,8 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
   o = align_up(o + nf * es);
   L.factors16 = o;
   if (precision == MHDG_BF16) o = align_up(o + nf * 2);
+  L.lu_scr = o;  L.lu_scr_bytes = split_lu_scratch(M, false);
+  o = align_up(o + L.lu_scr_bytes);
   L.total = o;
   return L;
 }
@@ -755,6 +770,9 @@ static FactorLayout factor_layout(const mhdg_mesh* M, int precision) {
 static size_t solve_bytes_impl(const mhdg_mesh* M, int R);
 // precision the assembly and LU run in (BF16 factors are factored in FP32)
 static int lu_precision(int precision) { return precision == MHDG_BF16 ? MHDG_FP32 : precision; }
+// scratch of the split LU (row moves and inverse diagonal blocks per macro)
+static char* lu_scratch(mhdg_mesh* M) { return M->ws + M->L.lu_scr; }
+static size_t lu_scratch_bytes(const mhdg_mesh* M) { return M->L.lu_scr_bytes; }
 // the factors the per-macro solves read
 static const void* solve_factors(const mhdg_mesh* M) {
   return M->ws + (M->precision == MHDG_BF16 ? M->L.factors16 : M->L.factors);
@@ -2269,7 +2287,8 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
       HIP_TRY(M, launch_lu(w + L.factors, MHDG_FP64, (const MacroInfo*)(w + L.info_lu),
                            (const int32_t*)(w + L.order), lu_classes.data(),
                            (int)lu_classes.size(), (int32_t*)(w + L.perm),
-                           (int32_t*)(w + L.status), s));
+                           (int32_t*)(w + L.status),
+                           lu_scratch(M), lu_scratch_bytes(M), s));
     }
     // the host vectors above must outlive the copies
     HIP_TRY(M, hipStreamSynchronize(s));
@@ -2283,7 +2302,8 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
       ProfScope ps(M, 1, s);
       HIP_TRY(M, launch_lu(w + L.factors, lu_precision(precision), info, (const int32_t*)(w + L.order),
                            M->classes.data(), (int)M->classes.size(), (int32_t*)(w + L.perm),
-                           (int32_t*)(w + L.status), s));
+                           (int32_t*)(w + L.status),
+                           lu_scratch(M), lu_scratch_bytes(M), s));
     }
   }
   if (precision == MHDG_BF16) {
@@ -2471,18 +2491,20 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
       sub.count = std::min<int64_t>(c.count, 512);
       int best = 0;
       double best_ms = 0;
-      for (int v = LU_PANEL; v <= LU_BLOCKED_U4; ++v) {
+      for (int v = LU_PANEL; v <= LU_SPLIT; ++v) {
         if (!lu_variant_ok(v, c.N)) continue;
         sub.lu_var = v;
         SizeClass one_m = sub;
         one_m.count = 1;   // untimed: loads the kernel
         HIP_TRY(M, launch_lu(w + L.factors, lu_precision(M->precision), info, order, &one_m, 1,
-                             (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+                             (int32_t*)(w + L.perm), (int32_t*)(w + L.status),
+                           lu_scratch(M), lu_scratch_bytes(M), s));
         HIP_TRY(M, launch_assemble(w + L.factors, lu_precision(M->precision), info, nullptr, M->n_macro, tm,
                                    M->T, M->tau, s));
         HIP_TRY(M, hipEventRecord(b, s));
         HIP_TRY(M, launch_lu(w + L.factors, lu_precision(M->precision), info, order, &sub, 1,
-                             (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+                             (int32_t*)(w + L.perm), (int32_t*)(w + L.status),
+                           lu_scratch(M), lu_scratch_bytes(M), s));
         HIP_TRY(M, hipEventRecord(e, s));
         float ms = 0;
         if ((st = elapsed(ms))) return st;
@@ -2497,7 +2519,8 @@ mhdg_status mhdg_autotune(mhdg_mesh* M, int32_t flags, mhdg_tune_report* out, vo
   HIP_TRY(M, launch_assemble(w + L.factors, lu_precision(M->precision), info, nullptr, M->n_macro,
                              tm, M->T, M->tau, s));
   HIP_TRY(M, launch_lu(w + L.factors, lu_precision(M->precision), info, order, M->classes.data(),
-                       (int)M->classes.size(), (int32_t*)(w + L.perm), (int32_t*)(w + L.status), s));
+                       (int)M->classes.size(), (int32_t*)(w + L.perm), (int32_t*)(w + L.status),
+                           lu_scratch(M), lu_scratch_bytes(M), s));
   if (M->precision == MHDG_BF16) {
     const MacroInfo& last = M->macros.back();
     HIP_TRY(M, launch_to_bf16((const float*)(w + L.factors), w + L.factors16,

@@ -108,6 +108,7 @@ struct FactorLayout {
   size_t meta, faces, bfaces, tmpl, order, perm, status, R, slots, lamD, work1, work2, factors,
       factors16, total;   // factors16: BF16 copy of the FP32 factors (BF16 precision only)
   size_t qtmpl = 0, info_lu = 0;   // flux-eliminated form: templates, Schur-block LU table
+  size_t lu_scr = 0, lu_scr_bytes = 0;   // scratch of the split LU
 };
 
 // Macros of one local size, contiguous in the processing order (largest first):
@@ -122,8 +123,12 @@ struct SizeClass {
 
 // Kernel variants the autotuner chooses between, per size class.
 // LU_BLOCKED_U2 / _U4: the blocked LU with the trailing update's U tiles
-// shared through LDS by 2 or 4 row tiles per wavefront
-enum LuVariant { LU_DEFAULT = 0, LU_PANEL = 1, LU_BLOCKED = 2, LU_BLOCKED_U2 = 3, LU_BLOCKED_U4 = 4 };
+// shared through LDS by 2 or 4 row tiles per wavefront.  LU_SPLIT: one
+// launch per step of each 128-column panel, the trailing update as a
+// batched MFMA GEMM over 64 x 64 tiles (needs a row-move scratch).
+enum LuVariant {
+  LU_DEFAULT = 0, LU_PANEL = 1, LU_BLOCKED = 2, LU_BLOCKED_U2 = 3, LU_BLOCKED_U4 = 4, LU_SPLIT = 5
+};
 // SOLVE_WAVE6 / SOLVE_WAVE5: one wavefront per macro like SOLVE_WAVE, with
 // the register budget of 6 or 5 resident wavefronts per SIMD (for N_K in
 // (512, 1024], where the 8-wavefront budget spills); SOLVE_WAVE5_LG12 and
@@ -140,6 +145,13 @@ bool solve_variant_ok(int v, int N);
 template <typename T>
 hipError_t lu_blocked_class(int variant, T* fac, const MacroInfo* info, const int32_t* order,
                             const SizeClass& c, int32_t* perm, int32_t* status, hipStream_t s);
+// bytes of per-macro scratch LU_SPLIT needs for a class (row moves and
+// inverse diagonal blocks of the current panel; 0 for N <= 128)
+size_t lu_split_scratch_bytes(const SizeClass& c);
+template <typename T>
+hipError_t lu_split_class(T* fac, const MacroInfo* info, const int32_t* order, const SizeClass& c,
+                          int32_t* perm, int32_t* status, char* scratch, size_t scratch_bytes,
+                          hipStream_t s);
 
 enum SolveMode { MODE_APPLY = 0, MODE_RHS = 1, MODE_RECOVER = 2, MODE_LOCAL = 3 };
 
@@ -164,9 +176,11 @@ hipError_t launch_set_kappa(MacroInfo* info, const double* kappa, int64_t n, int
 hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, const int32_t* order,
                            int64_t n, const double* tmpl, const Templates& T, double tau,
                            hipStream_t s);
+// scratch: per-macro scratch for classes factored with LU_SPLIT
+// (lu_split_scratch_bytes per class)
 hipError_t launch_lu(void* fac, int precision, const MacroInfo* info, const int32_t* order,
                      const SizeClass* classes, int n_classes, int32_t* perm, int32_t* status,
-                     hipStream_t s);
+                     char* scratch, size_t scratch_bytes, hipStream_t s);
 hipError_t launch_dirichlet(const BndFaceInfo* bf, int64_t nbf, const double* tmpl,
                             const Templates& T, const double* g, double* lamD, hipStream_t s);
 hipError_t launch_local_rhs(const MacroInfo* info, int64_t n, const BndFaceInfo* bf,

@@ -1175,8 +1175,11 @@ hipError_t launch_assemble(void* fac, int precision, const MacroInfo* info, cons
 
 template <typename T>
 static hipError_t lu_class(T* fac, const MacroInfo* info, const int32_t* order, const SizeClass& c,
-                           int32_t* perm, int32_t* status, hipStream_t s) {
+                           int32_t* perm, int32_t* status, char* scratch, size_t scratch_bytes,
+                           hipStream_t s) {
   const int v = c.lu_var ? c.lu_var : default_lu_variant(c.N);
+  if (v == LU_SPLIT)
+    return lu_split_class(fac, info, order, c, perm, status, scratch, scratch_bytes, s);
   if (v >= LU_BLOCKED) return lu_blocked_class(v, fac, info, order, c, perm, status, s);
   const dim3 g((unsigned)c.count);
   if (c.N <= 256)
@@ -1192,11 +1195,13 @@ static hipError_t lu_class(T* fac, const MacroInfo* info, const int32_t* order, 
 
 hipError_t launch_lu(void* fac, int precision, const MacroInfo* info, const int32_t* order,
                      const SizeClass* classes, int n_classes, int32_t* perm, int32_t* status,
-                     hipStream_t s) {
+                     char* scratch, size_t scratch_bytes, hipStream_t s) {
   for (int c = 0; c < n_classes; ++c) {
     hipError_t e = precision == 1
-                       ? lu_class((float*)fac, info, order, classes[c], perm, status, s)
-                       : lu_class((double*)fac, info, order, classes[c], perm, status, s);
+                       ? lu_class((float*)fac, info, order, classes[c], perm, status, scratch,
+                                  scratch_bytes, s)
+                       : lu_class((double*)fac, info, order, classes[c], perm, status, scratch,
+                                  scratch_bytes, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1381,7 +1386,7 @@ bool solve_variant_ok(int v, int N) {
   return v == SOLVE_MW8 && N > 16 * 64;
 }
 int default_lu_variant(int N) { return N <= 256 ? LU_PANEL : LU_BLOCKED; }
-bool lu_variant_ok(int v, int N) { return N <= 4096 && v >= LU_PANEL && v <= LU_BLOCKED_U4; }
+bool lu_variant_ok(int v, int N) { return N <= 4096 && v >= LU_PANEL && v <= LU_SPLIT; }
 
 // One launch per size class, each with the register-block count of its
 // local size (NQ = ceil(N/64)) and LDS for its boundary vectors.

@@ -78,7 +78,7 @@ class KernelTimes(ctypes.Structure):
 class TuneReport(ctypes.Structure):
     _fields_ = [("n_classes", ctypes.c_int32), ("N", ctypes.c_int32 * 8),
                 ("count", ctypes.c_int64 * 8), ("lu_variant", ctypes.c_int32 * 8),
-                ("solve_variant", ctypes.c_int32 * 8), ("lu_ms", (ctypes.c_double * 5) * 8),
+                ("solve_variant", ctypes.c_int32 * 8), ("lu_ms", (ctypes.c_double * 6) * 8),
                 ("apply_ms", (ctypes.c_double * 8) * 8)]
 
     def as_list(self):
@@ -87,7 +87,7 @@ class TuneReport(ctypes.Structure):
             out.append({"N": int(self.N[i]), "count": int(self.count[i]),
                         "lu_variant": int(self.lu_variant[i]),
                         "solve_variant": int(self.solve_variant[i]),
-                        "lu_ms": {v: float(self.lu_ms[i][v]) for v in (1, 2, 3, 4) if self.lu_ms[i][v]},
+                        "lu_ms": {v: float(self.lu_ms[i][v]) for v in range(1, 6) if self.lu_ms[i][v]},
                         "apply_ms": {v: float(self.apply_ms[i][v]) for v in range(1, 8)
                                      if self.apply_ms[i][v]}})
         return out

@@ -184,8 +184,9 @@ def test_kernel_variant_validation():
     with pytest.raises(mhdg.MhdgError):
         m.set_kernel_variant(N + 1, 1, 1)       # no class of that size
     m.set_kernel_variant(N, 4, 7)               # LDS-shared update, 4-wave budget
+    m.set_kernel_variant(N, 5, 1)               # split LU, one launch per panel step
     with pytest.raises(mhdg.MhdgError):
-        m.set_kernel_variant(N, 5, 1)           # no such LU variant
+        m.set_kernel_variant(N, 6, 1)           # no such LU variant
     with pytest.raises(mhdg.MhdgError):
         m.set_kernel_variant(N, 1, 8)           # no such solve variant
     with pytest.raises(mhdg.MhdgError):

@@ -36,7 +36,7 @@ def host(t):
 # (n, r, p) -> N_K: 45 (r1 p2), 273 (r2 p3), 975 (r3 p3), 1683 (r3 p4), 3675 (r4 p3)
 SHAPES = {"N45": (2, 1, 2), "N273": (2, 2, 3), "N975": (2, 3, 3), "N1683": (1, 3, 4),
           "N3675": (1, 4, 3)}
-COMBOS = [(lu, sv) for lu in range(1, 5) for sv in range(1, 8)]
+COMBOS = [(lu, sv) for lu in range(1, 6) for sv in range(1, 8)]
 
 
 def _setup(shape):
@@ -83,13 +83,15 @@ def test_variant_matches_oracle(shape, lu, sv):
         assert P.faces(host(out), orc.apply(lam, precondition=True), topo) <= 1e-10, (name, lu, sv)
 
 
-def test_fp32_blocked_lu_is_close():
-    """FP32 factors from the blocked LU: the operator within single-precision
-    accuracy of the FP64 oracle (the same bound as the panel LU's)."""
+@pytest.mark.parametrize("lu", [2, 5])
+def test_fp32_blocked_lu_is_close(lu):
+    """FP32 factors from the blocked and the split LU: the operator within
+    single-precision accuracy of the FP64 oracle (the same bound as the panel
+    LU's)."""
     xy, tri, r, p, kap, beta = _setup("N975")
     orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0)
     m = mhdg.MacroMesh(xy, tri, r, p)
-    m.set_kernel_variant(m.sizes.max_local, 2, 1)
+    m.set_kernel_variant(m.sizes.max_local, lu, 1)
     m.factor_local(gpu(kap), beta, 1.0, precision=mhdg.MHDG_FP32)
     lam = inputs.random_vector(orc.topo.n_trace, seed=1)
     out = torch.empty(orc.topo.n_trace, dtype=torch.float64, device=DEV)
@@ -108,8 +110,8 @@ def test_autotune_keeps_a_valid_factor_state():
     rep = m.autotune()
     assert len(rep) == len(set(int(x) for x in np.unique(r)))
     for c in rep:
-        assert c["lu_variant"] in (1, 2, 3, 4) and c["solve_variant"] in range(1, 8)
-        assert all(t > 0 for t in c["lu_ms"].values()) and len(c["lu_ms"]) == 4
+        assert c["lu_variant"] in range(1, 6) and c["solve_variant"] in range(1, 8)
+        assert all(t > 0 for t in c["lu_ms"].values()) and len(c["lu_ms"]) == 5
         assert c["apply_ms"][c["solve_variant"]] == min(c["apply_ms"].values())
     ex = inputs.exp_sin(0.3, beta)
     node, bnd = m.sample_points()
