@@ -20,7 +20,7 @@
 //      on the right, solves U12 = L11^-1 A12: each wavefront holds 16 columns
 //      of the window rows in registers and runs the block solve on MFMA;
 //   3. lu_update_kernel (one workgroup per 64 x 64 tile of the trailing
-//      matrix) computes A22 -= L21 U12 on MFMA through 32-deep slices of L21
+//      matrix) computes A22 -= L21 U12 on MFMA through 16-deep slices of L21
 //      and U12 staged in LDS.  All tiles of one macro run on one XCD, so its
 //      L21 and U12 are read from that XCD's L2.
 // A last launch stores the factors column-major, one 32 x 32 tile pair per
@@ -38,15 +38,6 @@ constexpr int kMoveInts = 1 + 4 * kSplitW;  // count, then up to 2W (destination
 constexpr size_t kMoveBytes = 2304;
 constexpr size_t kSplitScratch = kMoveBytes + size_t(kSplitW / 16) * 256 * sizeof(double);
 static_assert(kMoveBytes >= kMoveInts * sizeof(int32_t), "row moves fit");
-
-__device__ __forceinline__ int sel4(const int (&a)[4], int i) {
-  return i == 0 ? a[0] : (i == 1 ? a[1] : (i == 2 ? a[2] : a[3]));
-}
-__device__ __forceinline__ void set4(int (&a)[4], int i, int v) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (q == i) a[q] = v;
-}
 
 // The B operand of k-step s (rows 4 s .. 4 s + 3 of a 16 x 16 tile) from the
 // tile held in the MFMA accumulator layout.  FP64: accumulator element v of
@@ -186,11 +177,15 @@ __global__ __launch_bounds__(NT, 2) void lu_panel_kernel(T* fac, const MacroInfo
 
   __shared__ double s_red_v[NW];
   __shared__ int s_red_i[NW];
-  __shared__ T s_row[SB];
-  __shared__ T s_swap[2][SB];
+  __shared__ T s_row[2][SB];        // pivot rows (alternating slots per column)
+  __shared__ T s_swap[2][SB];       // the rows they displace
   __shared__ T s_L[H * H];          // L11 of the first half; U blocks of the band updates
   __shared__ int s_piv[kSplitW];    // pivot row of each window column
-  __shared__ int s_md[2 * SB], s_ms[2 * SB], s_mn;   // a sub-panel's row moves
+  __shared__ int s_md[2 * SB], s_ms[2 * SB];   // a sub-panel's row moves (-1: none)
+  // row k0 + r holds the content that row s_pos[r] had before the window
+  // (s_sub: before the current sub-panel)
+  __shared__ int s_pos[RPT * NT], s_sub[RPT * NT];
+  __shared__ int s_cnt;
   __shared__ T s_Lb[16][17];        // a unit lower 16 x 16 block (strict lower part)
   __shared__ T s_Li[16][17];        // its inverse
   __shared__ T s_Lih[4][16][17];    // inverses of the first half's diagonal blocks
@@ -199,7 +194,8 @@ __global__ __launch_bounds__(NT, 2) void lu_panel_kernel(T* fac, const MacroInfo
 
   if (k0 == 0)
     for (int i = tid; i < N; i += NT) perm[i] = i;
-  if (tid == 0) s_status = k0 == 0 ? 0 : status[e];
+  if (tid == 0) { s_status = k0 == 0 ? 0 : status[e]; s_cnt = 0; }
+  for (int r = tid; r < N - k0; r += NT) s_pos[r] = k0 + r;
   __syncthreads();
 
   T pr[RPT][SB];
@@ -254,10 +250,11 @@ __global__ __launch_bounds__(NT, 2) void lu_panel_kernel(T* fac, const MacroInfo
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
           const int row = c0 + tid + q * NT;
-          double v = -1.0;
+          T x = T(0);
 #pragma unroll
           for (int c = 0; c < SB; ++c)
-            if (c == j) v = pivot_mag((double)pr[q][c]);
+            if (c == j) x = pr[q][c];
+          const double v = pivot_mag((double)x);
           if (row >= col && row < N && v > best) { best = v; bidx = row; }
         }
 #pragma unroll
@@ -279,47 +276,51 @@ __global__ __launch_bounds__(NT, 2) void lu_panel_kernel(T* fac, const MacroInfo
         const int prow = min(max(bidx, col), N - 1);
         const int own_c = (col - c0) % NT, slot_c = (col - c0) / NT;
         const int own_p = (prow - c0) % NT, slot_p = (prow - c0) / NT;
-        if (prow != col) {
+        // the pivot row and the row it displaces through LDS, one barrier:
+        // s_row (slot j & 1) holds the new row col, s_swap the old one
+        T* prow_s = s_row[j & 1];
+        T* crow_s = s_swap[j & 1];
 #pragma unroll
-          for (int q = 0; q < RPT; ++q) {
-            if (tid == own_p && q == slot_p)
-              for (int c = 0; c < SB; ++c) s_swap[0][c] = pr[q][c];
-            if (tid == own_c && q == slot_c)
-              for (int c = 0; c < SB; ++c) s_swap[1][c] = pr[q][c];
-          }
+        for (int q = 0; q < RPT; ++q) {
+          if (tid == own_p && q == slot_p)
+#pragma unroll
+            for (int c = 0; c < SB; ++c) prow_s[c] = pr[q][c];
+          if (prow != col && tid == own_c && q == slot_c)
+#pragma unroll
+            for (int c = 0; c < SB; ++c) crow_s[c] = pr[q][c];
         }
-        __syncthreads();
-        if (prow != col) {
-#pragma unroll
-          for (int q = 0; q < RPT; ++q) {
-            if (tid == own_c && q == slot_c)
-              for (int c = 0; c < SB; ++c) pr[q][c] = s_swap[0][c];
-            if (tid == own_p && q == slot_p)
-              for (int c = 0; c < SB; ++c) pr[q][c] = s_swap[1][c];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < RPT; ++q)
-          if (tid == own_c && q == slot_c)
-            for (int c = 0; c < SB; ++c) s_row[c] = pr[q][c];
         if (tid == 0) {
           s_piv[col - k0] = prow;
           if (s_status == 0) s_status = pivot_status(best, col);
         }
         __syncthreads();
+        if (prow != col) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) {
+            if (tid == own_c && q == slot_c)
+#pragma unroll
+              for (int c = 0; c < SB; ++c) pr[q][c] = prow_s[c];
+            if (tid == own_p && q == slot_p)
+#pragma unroll
+              for (int c = 0; c < SB; ++c) pr[q][c] = crow_s[c];
+          }
+        }
         if (best != 0.0) {
-          const T piv = s_row[j];
+          const T piv = prow_s[j];
 #pragma unroll
           for (int q = 0; q < RPT; ++q) {
             const int row = c0 + tid + q * NT;
             if (row > col && row < N) {
-              T l = T(0);
+              T x = T(0);
 #pragma unroll
               for (int c = 0; c < SB; ++c)
-                if (c == j) { l = pr[q][c] / piv; pr[q][c] = l; }
+                if (c == j) x = pr[q][c];
+              const T l = x / piv;   // one division per row
 #pragma unroll
-              for (int c = 0; c < SB; ++c)
-                if (c > j) pr[q][c] -= l * s_row[c];
+              for (int c = 0; c < SB; ++c) {
+                if (c == j) pr[q][c] = l;
+                if (c > j) pr[q][c] -= l * prow_s[c];
+              }
             }
           }
         }
@@ -338,54 +339,50 @@ __global__ __launch_bounds__(NT, 2) void lu_panel_kernel(T* fac, const MacroInfo
         for (int c = 0; c < 16; ++c)
           s_Lb[tid][c] = (c < SB && tid < sb && c < tid) ? pr[0][c < SB ? c : 0] : T(0);
       __syncthreads();
-      // the sub-panel's interchanges in the other window columns: thread 0
-      // composes them into row moves (at most 2 SB rows), then every moved
-      // value is read before any is written
-      if (tid == 0) {
-        int n = sb;
-        for (int t = 0; t < sb; ++t) { s_md[t] = c0 + t; s_ms[t] = c0 + t; }
+      // the sub-panel's interchanges as row moves: thread 0 applies them to
+      // the rows they touch (candidates: the sub-panel rows and the pivot
+      // rows), then every candidate whose content changed is a move
+      const int kc = tid % SB;
+      const bool cand = tid < 2 * SB && kc < sb;
+      const int cp = cand ? (tid < SB ? c0 + kc : s_piv[c0 - k0 + kc]) : 0;
+      if (cand) s_sub[cp - k0] = cp;
+      __syncthreads();
+      if (tid == 0)
         for (int j = 0; j < sb; ++j) {
-          const int prow = s_piv[c0 - k0 + j];
-          if (prow == c0 + j) continue;
-          int sp = prow - c0;
-          if (prow >= c0 + sb) {
-            sp = -1;
-            for (int t = sb; t < n; ++t)
-              if (s_md[t] == prow) { sp = t; break; }
-            if (sp < 0) { sp = n++; s_md[sp] = prow; s_ms[sp] = prow; }
-          }
-          const int tmp = s_ms[j];
-          s_ms[j] = s_ms[sp];
-          s_ms[sp] = tmp;
+          const int a = c0 + j - k0, b = s_piv[c0 - k0 + j] - k0;
+          const int ta = s_sub[a], tb = s_sub[b];
+          s_sub[a] = tb;
+          s_sub[b] = ta;
         }
-        int m = 0;
-        for (int t = 0; t < n; ++t)
-          if (s_md[t] != s_ms[t]) { s_md[m] = s_md[t]; s_ms[m] = s_ms[t]; ++m; }
-        s_mn = m;
+      __syncthreads();
+      int wpos = 0;
+      if (tid < 2 * SB) {
+        const int src = cand ? s_sub[cp - k0] : -1;
+        s_md[tid] = (cand && src != cp) ? cp : -1;
+        s_ms[tid] = src;
+        if (cand) wpos = s_pos[src - k0];
       }
       __syncthreads();
+      if (cand) s_pos[cp - k0] = wpos;   // the window's composition so far
       {
+        // the moves in the other window columns: every moved value is read
+        // before any is written
         constexpr int PARTS = NT / kSplitW, PV = (2 * SB + PARTS - 1) / PARTS;
-        const int nm = s_mn, c = k0 + tid % kSplitW, part = tid / kSplitW;
+        const int c = k0 + tid % kSplitW, part = tid / kSplitW;
         const bool act = c < cw1 && (c < c0 || c >= c0 + sb);
         T vals[PV];
 #pragma unroll
         for (int q = 0; q < PV; ++q) {
           const int x = part + PARTS * q;
-          vals[q] = (act && x < nm) ? A[size_t(s_ms[x]) * ld + c] : T(0);
+          vals[q] = (act && x < 2 * SB && s_md[x] >= 0) ? A[size_t(s_ms[x]) * ld + c] : T(0);
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PV; ++q) {
           const int x = part + PARTS * q;
-          if (act && x < nm) A[size_t(s_md[x]) * ld + c] = vals[q];
+          if (act && x < 2 * SB && s_md[x] >= 0) A[size_t(s_md[x]) * ld + c] = vals[q];
         }
       }
-      if (tid == 0)
-        for (int j = 0; j < sb; ++j) {
-          const int prow = s_piv[c0 - k0 + j], col = c0 + j;
-          if (prow != col) { int t = perm[col]; perm[col] = perm[prow]; perm[prow] = t; }
-        }
       __syncthreads();
       // the inverse of the sub-panel's unit lower block (in a 16 x 16 frame)
       invert_unit_lower16<T, NT>(s_Lb, s_Li, sb);
@@ -438,55 +435,32 @@ __global__ __launch_bounds__(NT, 2) void lu_panel_kernel(T* fac, const MacroInfo
       }
     }
   }
-  // The window's interchanges as row moves for the columns outside it.  Slot
-  // t (lane t mod 64, register t / 64) is a row touched by an interchange:
-  // the w window rows first, then rows below the window in the order they are
-  // met; src is the row (before this panel) whose content the slot's row
-  // holds now.  Every interchange of the window swaps two slots' contents.
-  if ((k0 > 0 || cw1 < N) && wid == 0) {
+  // The window's interchanges as row moves for the columns outside it, and
+  // the permutation: row k0 + r now holds the old content of row s_pos[r]
+  {
+    int pv[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + q * NT;
+      pv[q] = (r < N - k0 && s_pos[r] != k0 + r) ? perm[s_pos[r]] : 0;
+    }
+    __syncthreads();
+    const bool outside = k0 > 0 || cw1 < N;
     int32_t* mv = (int32_t*)(scratch + int64_t(blockIdx.x) * kSplitScratch);
-    int rows[4], src[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = lane + 64 * q;
-      rows[q] = t < w ? k0 + t : -1;
-      src[q] = rows[q];
-    }
-    int ns = w;
-    for (int j = 0; j < w; ++j) {
-      const int prow = s_piv[j];
-      if (prow == k0 + j) continue;
-      int sp = prow - k0;
-      if (prow >= cw1) {
-        sp = -1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const unsigned long long m = __ballot(rows[q] == prow);
-          if (m && sp < 0) sp = 64 * q + __ffsll((long long)m) - 1;
-        }
-        if (sp < 0) {
-          sp = ns++;
-          if (lane == (sp & 63)) { set4(rows, sp >> 6, prow); set4(src, sp >> 6, prow); }
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + q * NT;
+      if (r < N - k0 && s_pos[r] != k0 + r) {
+        perm[k0 + r] = pv[q];
+        if (outside) {
+          const int x = atomicAdd(&s_cnt, 1);
+          mv[1 + 2 * x] = k0 + r;
+          mv[2 + 2 * x] = s_pos[r];
         }
       }
-      const int va = __shfl(sel4(src, j >> 6), j & 63, 64);
-      const int vb = __shfl(sel4(src, sp >> 6), sp & 63, 64);
-      if (lane == (j & 63)) set4(src, j >> 6, vb);
-      if (lane == (sp & 63)) set4(src, sp >> 6, va);
     }
-    int cnt = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool moved = rows[q] >= 0 && rows[q] != src[q];
-      const unsigned long long m = __ballot(moved);
-      if (moved) {
-        const int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
-        mv[1 + 2 * pos] = rows[q];
-        mv[2 + 2 * pos] = src[q];
-      }
-      cnt += __popcll(m);
-    }
-    if (lane == 0) mv[0] = cnt;
+    __syncthreads();
+    if (outside && tid == 0) mv[0] = s_cnt;
   }
   if (tid == 0) status[e] = s_status;
 }
@@ -570,20 +544,23 @@ __global__ __launch_bounds__(256) void lu_swap_u12_kernel(T* fac, const MacroInf
     }
 }
 
-// A22 -= L21 U12 for one 64 x 64 tile of the trailing matrix (rows and
+// A22 -= L21 U12 for one TM x TN tile of the trailing matrix (rows and
 // columns from k0 + W).  Workgroups are dispatched to the XCDs in turn
 // (block b runs on XCD b mod 8), so macro 8 m + x of the class takes the
 // blocks b = 8 (m T2 + tile) + x: all its T2 tiles on XCD x, one after another.
-// Wavefront v computes the 32 x 32 quarter (v / 2, v mod 2) of the tile as
-// 2 x 2 MFMA tiles; the next 32-deep slices of L21 and U12 are loaded into
+// Wavefront v computes the (TM/2) x (TN/2) quarter (v / 2, v mod 2) of the
+// tile as MFMA tiles; the next 16-deep slices of L21 and U12 are loaded into
 // registers while the current ones are multiplied out of LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void lu_update_kernel(T* fac, const MacroInfo* __restrict__ info,
+template <typename T, int TM, int TN>
+__global__ __launch_bounds__(256, 4) void lu_update_kernel(T* fac, const MacroInfo* __restrict__ info,
                                                         const int32_t* __restrict__ order,
-                                                        int64_t base, int count, int k0, int tpd) {
-  constexpr int W = kSplitW, KC = 32, PL = 64 * KC / 256;
+                                                        int64_t base, int count, int k0, int tpr,
+                                                        int tpc) {
+  constexpr int W = kSplitW, KC = 16;
+  constexpr int PL = TM * KC / 256, PU = KC * TN / 256;   // prefetched values per thread
+  constexpr int MI = TM / 32, NI = TN / 32;                // MFMA tiles per wavefront
   const int b = blockIdx.x, x = b & 7, i = b >> 3;
-  const int T2 = tpd * tpd;
+  const int T2 = tpr * tpc;
   const int mpos = (i / T2) * 8 + x;
   if (mpos >= count) return;
   const int tile = i % T2;
@@ -592,61 +569,73 @@ __global__ __launch_bounds__(256) void lu_update_kernel(T* fac, const MacroInfo*
   const int N = mi.N, ld = mi.ld;
   T* A = fac + mi.fac_off;
   const int r0 = k0 + W;
-  const int row0 = r0 + 64 * (tile / tpd), col0 = r0 + 64 * (tile % tpd);
+  const int row0 = r0 + TM * (tile / tpc), col0 = r0 + TN * (tile % tpc);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr = 32 * (wid >> 1), wc = 32 * (wid & 1);
+  const int wr = (TM / 2) * (wid >> 1), wc = (TN / 2) * (wid & 1);
 
-  __shared__ T Ls[64][KC + 1];
-  __shared__ T Us[KC][64 + 1];
-  T pl[PL], pu[PL];
+  __shared__ T Ls[TM][KC + 1];
+  __shared__ T Us[KC][TN + 1];
+  T pl[PL], pu[PU];
   auto fetch = [&](int kc) {
 #pragma unroll
     for (int q = 0; q < PL; ++q) {
       const int x2 = tid + 256 * q;
       const int r = x2 / KC, k = x2 % KC, row = row0 + r;
       pl[q] = row < N ? -A[size_t(row) * ld + k0 + kc + k] : T(0);
-      const int kk = x2 / 64, cc = x2 % 64, col = col0 + cc;
+    }
+#pragma unroll
+    for (int q = 0; q < PU; ++q) {
+      const int x2 = tid + 256 * q;
+      const int kk = x2 / TN, cc = x2 % TN, col = col0 + cc;
       pu[q] = col < N ? A[size_t(k0 + kc + kk) * ld + col] : T(0);
     }
   };
   fetch(0);
-  typename Mfma<T>::acc acc[2][2];
+  typename Mfma<T>::acc acc[MI][NI];
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < MI; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < NI; ++tj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + wr + 16 * ti + Mfma<T>::drow(lk, v);
         const int col = col0 + wc + 16 * tj + li;
         acc[ti][tj][v] = (row < N && col < N) ? A[size_t(row) * ld + col] : T(0);
       }
+#pragma unroll 1
   for (int kc = 0; kc < W; kc += KC) {
 #pragma unroll
     for (int q = 0; q < PL; ++q) {
       const int x2 = tid + 256 * q;
       Ls[x2 / KC][x2 % KC] = pl[q];
-      Us[x2 / 64][x2 % 64] = pu[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PU; ++q) {
+      const int x2 = tid + 256 * q;
+      Us[x2 / TN][x2 % TN] = pu[q];
     }
     __syncthreads();
     if (kc + KC < W) fetch(kc + KC);
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int k = 4 * s + lk;
-      const T a0 = Ls[wr + li][k], a1 = Ls[wr + 16 + li][k];
-      const T b0 = Us[k][wc + li], b1 = Us[k][wc + 16 + li];
-      acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
+      T a[MI], bb[NI];
+#pragma unroll
+      for (int ti = 0; ti < MI; ++ti) a[ti] = Ls[wr + 16 * ti + li][k];
+#pragma unroll
+      for (int tj = 0; tj < NI; ++tj) bb[tj] = Us[k][wc + 16 * tj + li];
+#pragma unroll
+      for (int ti = 0; ti < MI; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NI; ++tj) acc[ti][tj] = Mfma<T>::run(a[ti], bb[tj], acc[ti][tj]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < MI; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < NI; ++tj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + wr + 16 * ti + Mfma<T>::drow(lk, v);
@@ -716,8 +705,8 @@ hipError_t lu_split_class(T* fac, const MacroInfo* info, const int32_t* order, c
     if (k0 + w < N) {
       const int tpd = (N - k0 - w + 63) / 64;
       const int64_t blocks = (cnt + 7) / 8 * 8 * int64_t(tpd) * tpd;
-      hipLaunchKernelGGL(lu_update_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, fac, info,
-                         order, c.start, (int)cnt, k0, tpd);
+      hipLaunchKernelGGL((lu_update_kernel<T, 64, 64>), dim3((unsigned)blocks), dim3(256), 0, s,
+                         fac, info, order, c.start, (int)cnt, k0, tpd, tpd);
     }
   }
   const int nt = (N + 31) / 32;
