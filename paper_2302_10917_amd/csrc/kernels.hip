@@ -1385,7 +1385,7 @@ bool solve_variant_ok(int v, int N) {
   if (v >= SOLVE_WAVE6 && v <= SOLVE_WAVE4_LG16) return N > 8 * 64 && N <= 16 * 64;
   return v == SOLVE_MW8 && N > 16 * 64;
 }
-int default_lu_variant(int N) { return N <= 256 ? LU_PANEL : LU_BLOCKED; }
+int default_lu_variant(int N) { return N <= 256 ? LU_PANEL : LU_SPLIT; }
 bool lu_variant_ok(int v, int N) { return N <= 4096 && v >= LU_PANEL && v <= LU_SPLIT; }
 
 // One launch per size class, each with the register-block count of its

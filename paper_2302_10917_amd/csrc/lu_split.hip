@@ -471,7 +471,7 @@ __global__ __launch_bounds__(NT, 2) void lu_panel_kernel(T* fac, const MacroInfo
 // (accumulator layout); right of the window it then solves U12 = L11^-1 A12
 // for them on its own.
 template <typename T>
-__global__ __launch_bounds__(256) void lu_swap_u12_kernel(T* fac, const MacroInfo* __restrict__ info,
+__global__ __launch_bounds__(256, 4) void lu_swap_u12_kernel(T* fac, const MacroInfo* __restrict__ info,
                                                           const int32_t* __restrict__ order,
                                                           int64_t base, int k0,
                                                           const char* __restrict__ scratch) {
