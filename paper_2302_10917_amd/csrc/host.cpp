@@ -530,12 +530,13 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------- flux elimination
 // Offsets of the per-level templates of the flux-eliminated form (8 Q x Q
-// arrays per level present); returns the blob size in doubles.
+// arrays, the boundary block of Minv and the two transposed boundary blocks
+// of PT_a per level present); returns the blob size in doubles.
 static size_t qelim_plan(const mhdg_mesh* M, QTemplates* QT) {
   size_t o = 0;
   for (int r = 0; r <= kMaxLevel; ++r) {
     QLevel& q = QT->lev[r];
-    q = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    q = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
     if (!M->T.lev[r].present) continue;
     const size_t QQ = size_t(M->T.lev[r].Q) * M->T.lev[r].Q;
     const size_t step = (QQ + 31) / 32 * 32;
@@ -544,6 +545,11 @@ static size_t qelim_plan(const mhdg_mesh* M, QTemplates* QT) {
     const size_t nb = 3 * size_t(M->T.lev[r].P);
     q.Mbb = int64_t(o);
     o += (nb * nb + 31) / 32 * 32;
+    const size_t qb = (size_t(M->T.lev[r].Q) * nb + 31) / 32 * 32;
+    q.PB0 = int64_t(o);
+    o += qb;
+    q.PB1 = int64_t(o);
+    o += qb;
   }
   return o;
 }
@@ -695,6 +701,14 @@ static void build_qelim_templates(mhdg_mesh* M) {
       });
       for (int i = 0; i < Q; ++i)
         for (int j = 0; j < Q; ++j) PTa[a][size_t(j) * Q + i] = Pa[a][size_t(i) * Q + j];
+      // boundary rows of PT_a, transposed (row j, boundary position b)
+      const int P = LT.P, NB = 3 * P;
+      const int32_t* en = reinterpret_cast<const int32_t*>(&M->tmpl[LT.edge_node]);
+      double* PB = &B[a == 0 ? q.PB0 : q.PB1];
+      for (int b = 0; b < NB; ++b) {
+        const int nb = en[(b / P) * (P + 1) + b % P];
+        for (int j = 0; j < Q; ++j) PB[size_t(j) * NB + b] = PTa[a][size_t(nb) * Q + j];
+      }
     }
     const int ab[3][2] = {{0, 0}, {0, 1}, {1, 1}};
     double* Lab[3] = {&B[q.L00], &B[q.L01], &B[q.L11]};

@@ -93,7 +93,9 @@ struct LevelTemplates {
 // into their own device blob): Minv = Mhat^-1, P_a = (Ehat^a)^T Minv and its
 // transpose PT_a, L_ab = P_a Ehat^b (a, b = 0, 1; L_10 = L_01^T), and Mbb, the
 // 3P x 3P block of Minv on the boundary nodes in boundary order (b = kP + s).
-struct QLevel { int64_t Minv, P0, P1, PT0, PT1, L00, L01, L11, Mbb; };
+// PB0 / PB1: the boundary rows of PT_a transposed, PB_a[j * 3P + b] =
+// PT_a[node of boundary position b][j]
+struct QLevel { int64_t Minv, P0, P1, PT0, PT1, L00, L01, L11, Mbb, PB0, PB1; };
 struct QTemplates { QLevel lev[kMaxLevel + 1]; };
 
 struct Templates {

@@ -306,9 +306,11 @@ __global__ __launch_bounds__(64) void qelim_solve_kernel(
 // on the boundary and w_a = sum_d g_ad x_d too.  z = x_u - kappa sum_a P_a w_a
 // uses the boundary columns of P_a (rows of PT_a), each row read once for the
 // NR columns; the NR Schur-block solves run together in registers; the
-// boundary values q_d = Mbb x_d / |det J| + sum_a g_ad P_a^T u and u are
-// restricted with C_K into NR columns of T_K.  The wavefronts of a macro are
-// consecutive in one XCD's dispatch (block b runs on XCD b mod 8).
+// boundary values q_d = Mbb x_d / |det J| + sum_a g_ad P_a^T u (each lane
+// summing its own boundary position over the rows of the transposed boundary
+// rows of PT_a, u read from LDS) and u are restricted with C_K into NR columns
+// of T_K.  The wavefronts of a macro are consecutive in one XCD's dispatch
+// (block b runs on XCD b mod 8).
 template <int NQ, int NR>
 __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
     const double* __restrict__ fac, const MacroInfo* __restrict__ info,
@@ -332,11 +334,11 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
   }
   const int col0 = chunk * NR;
   if (col0 >= L) return;
-  // LDS: the columns of B_K, then one region that first holds the unpermuted
-  // right-hand sides and later the boundary rows of the solutions
+  // LDS: the columns of B_K (later the boundary values of the solutions),
+  // then the unpermuted right-hand sides (later the solutions)
   double* xc = sm;                    // NR x 3 NBD: columns of B_K (boundary rows)
-  double* us = xc + NR * 3 * NBD;     // NR x Q: z, before the permuted gather
-  double* zc = us;                    // NR x 3 NBD: boundary rows of the solutions
+  double* us = xc + NR * 3 * NBD;     // NR x Q: z before the permuted gather; then u
+  double* zc = xc;                    // NR x 3 NBD: boundary values of the solutions
   const LevelTemplates& LT = Tp.lev[mi.level];
   const QLevel& QL = QT.lev[mi.level];
   const int32_t* enode = ints_(tm, LT.edge_node);
@@ -482,55 +484,86 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
       }
     }
   }
-  // ---- boundary rows of the solutions (u_j in registers: lane l holds j = l + 64 q)
-  for (int b = 0; b < NBD; ++b) {
-    const int k = b / P;
-    const int nb = enode[k * (P + 1) + (b - k * P)];
-    const double* r0 = PT0 + size_t(nb) * Q;
-    const double* r1 = PT1 + size_t(nb) * Q;
-    const double* mb = Mbb + size_t(b) * NBD;
-    double v0[NR], v1[NR];
+  // ---- boundary values of the solutions: u to LDS, then each lane sums q_d
+  // at its own boundary position over all rows (no cross-lane sums): one
+  // lane per position, or, for the last fewer than 64 positions, T lanes per
+  // row group and 64 / T groups whose partial sums meet by lane exchanges
 #pragma unroll
-    for (int r = 0; r < NR; ++r) v0[r] = v1[r] = 0.0;
+  for (int q = 0; q < NQ; ++q) {
+    const int j = lane + 64 * q;
+    if (j < Q)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int j = lane + 64 * q;
-      const int jj = j < Q ? j : Q - 1;
-      const double p0 = j < Q ? r0[jj] : 0.0, p1 = j < Q ? r1[jj] : 0.0;
+      for (int r = 0; r < NR; ++r) us[r * Q + j] = y[q][r];
+  }
+  __syncthreads();
+  const double* PB0 = qt + QL.PB0;
+  const double* PB1 = qt + QL.PB1;
+  constexpr int kPass = 3;   // boundary positions up to 192 (P <= 64)
+  double v0[kPass][NR], v1[kPass][NR], ub[kPass][NR];
+#pragma unroll
+  for (int h = 0; h < kPass; ++h) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v0[h][r] = v1[h][r] = ub[h][r] = 0.0;
+    const int cnt = min(64, NBD - 64 * h);
+    if (cnt <= 0) continue;
+    int Tl = 1;
+    while (Tl < cnt) Tl <<= 1;
+    const int Gn = 64 / Tl, bi = lane & (Tl - 1), g = lane / Tl;
+    const int b = 64 * h + bi;
+    const bool bok = bi < cnt;
+    const int bb = bok ? b : 64 * h;
+    double s0[NR], s1[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s0[r] = s1[r] = 0.0;
+#pragma unroll 4
+    for (int j = g; j < Q; j += Gn) {
+      const double p0 = PB0[size_t(j) * NBD + bb], p1 = PB1[size_t(j) * NBD + bb];
+      const double c0 = G0 * p0 + G2 * p1, c1 = G1 * p0 + G3 * p1;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        v0[r] += (G0 * p0 + G2 * p1) * y[q][r];
-        v1[r] += (G1 * p0 + G3 * p1) * y[q][r];
+        const double u = us[r * Q + j];
+        s0[r] += c0 * u;
+        s1[r] += c1 * u;
       }
     }
-    for (int b2 = lane; b2 < NBD; b2 += 64) {
-      const double mv = mb[b2] * idJ;
+#pragma unroll 4
+    for (int b2 = g; b2 < NBD; b2 += Gn) {   // Mbb x_d / |det J| (Mbb is symmetric)
+      const double mv = Mbb[size_t(b2) * NBD + bb] * idJ;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        v0[r] += mv * xc[r * 3 * NBD + b2];
-        v1[r] += mv * xc[r * 3 * NBD + NBD + b2];
+        s0[r] += mv * xc[r * 3 * NBD + b2];
+        s1[r] += mv * xc[r * 3 * NBD + NBD + b2];
       }
     }
+    for (int o = Tl; o < 64; o <<= 1)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        s0[r] += __shfl_xor(s0[r], o, 64);
+        s1[r] += __shfl_xor(s1[r], o, 64);
+      }
+    const int kb = bb / P;
+    const int nb = enode[kb * (P + 1) + (bb - kb * P)];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      v0[r] = wave_sum_(v0[r]);
-      v1[r] = wave_sum_(v1[r]);
+      v0[h][r] = s0[r];
+      v1[h][r] = s1[r];
+      ub[h][r] = us[r * Q + nb];
     }
-    // u at boundary node nb: lane nb % 64 of register block nb / 64
-    double un[NR];
+  }
+  __syncthreads();   // xc is read by every lane above; zc takes its place
 #pragma unroll
-    for (int r = 0; r < NR; ++r) un[r] = 0.0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      if (q == (nb >> 6))
-#pragma unroll
-        for (int r = 0; r < NR; ++r) un[r] = readlane_d(y[q][r], nb & 63);
-    if (lane == 0)
+  for (int h = 0; h < kPass; ++h) {
+    const int cnt = min(64, NBD - 64 * h);
+    int Tl = 1;
+    while (Tl < cnt) Tl <<= 1;
+    const int bi = lane & (Tl - 1);
+    if (cnt > 0 && lane < Tl && bi < cnt)
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        zc[r * 3 * NBD + b] = v0[r];
-        zc[r * 3 * NBD + NBD + b] = v1[r];
-        zc[r * 3 * NBD + 2 * NBD + b] = un[r];
+        const int b = 64 * h + bi;
+        zc[r * 3 * NBD + b] = v0[h][r];
+        zc[r * 3 * NBD + NBD + b] = v1[h][r];
+        zc[r * 3 * NBD + 2 * NBD + b] = ub[h][r];
       }
   }
   __syncthreads();
@@ -552,11 +585,11 @@ hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, con
     if (sc.count == 0) continue;
     const int Q = sc.N / 3;
     const int nq = (Q + 63) / 64;
-    const int nr = nq <= 6 ? 4 : (nq <= 14 ? 2 : 1);
+    const int nr = nq <= 4 ? 4 : (nq <= 14 ? 2 : 1);
     const int nch = (max_L + nr - 1) / nr;
     const int64_t nblk = (sc.count + 7) / 8 * 8 * int64_t(nch);
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    const size_t lds = (size_t(nr) * (9 * sc.P + std::max(9 * sc.P, Q))) * sizeof(double);
+    const size_t lds = (size_t(nr) * (9 * sc.P + Q)) * sizeof(double);
     if (lds > 65536) return hipErrorInvalidValue;
     const dim3 g((unsigned)nblk), b(64);
 #define MHDG_QFOLD(NQ_, NR_)                                                                   \
@@ -564,7 +597,7 @@ hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, con
                      sc.start, sc.count, nch, perm, tmpl, T, qtm, QT, tau, toff, out)
     if (nq <= 2) MHDG_QFOLD(2, 4);
     else if (nq <= 4) MHDG_QFOLD(4, 4);
-    else if (nq <= 6) MHDG_QFOLD(6, 4);
+    else if (nq <= 6) MHDG_QFOLD(6, 2);
     else if (nq <= 9) MHDG_QFOLD(9, 2);
     else if (nq <= 14) MHDG_QFOLD(14, 2);
     else if (nq <= 20) MHDG_QFOLD(20, 1);
