@@ -195,6 +195,8 @@ def measured_traffic(workload):
         return None
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
         return None
+    if rec.get("traffic_bytes_per_launch") is None:   # counters taken but not usable
+        return None
     return rec
 
 

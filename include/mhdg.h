@@ -476,8 +476,9 @@ mhdg_status mhdg_autotune(mhdg_mesh* mesh, int32_t flags, mhdg_tune_report* out,
 mhdg_status mhdg_set_supg(mhdg_mesh* mesh, int32_t on);
 
 /* Fix the variants of the size class with local size N (0 = the default
- * rule: LU variant 1 for N <= 256, else 5; solve variant 1 for N <= 1024,
- * else 2).  Takes effect at the next factor_local (LU) or apply (solves).
+ * rule: LU variant 1 for N <= 256, else 5; solve variant 1 for N <= 512,
+ * 7 for N in (512, 1024] (1 with BF16 factors), else 2).  Takes effect at the
+ * next factor_local (LU) or apply (solves).
  * Errors: INVALID_ARG (no class of that size, variant not available). */
 mhdg_status mhdg_set_kernel_variant(mhdg_mesh* mesh, int32_t N, int32_t lu_variant,
                                     int32_t solve_variant);

@@ -1378,7 +1378,10 @@ hipError_t launch_to_bf16(const float* src, void* dst, int64_t n, hipStream_t s)
   return hipGetLastError();
 }
 
-int default_solve_variant(int N) { return N <= 1024 ? SOLVE_WAVE : SOLVE_MW4; }
+int default_solve_variant(int N) {
+  if (N > 16 * 64) return SOLVE_MW4;
+  return N > 8 * 64 ? SOLVE_WAVE4_LG16 : SOLVE_WAVE;
+}
 bool solve_variant_ok(int v, int N) {
   if (N > 58 * 64) return false;
   if (v == SOLVE_WAVE || v == SOLVE_MW4) return true;
@@ -1402,7 +1405,9 @@ hipError_t launch_macro_solve(int mode, int transpose, const void* fac, int prec
     const size_t lds = size_t(18) * sc.P * sizeof(double);
     const int nq = (sc.N + 63) / 64;
     hipError_t e;
-    const int v = sc.solve_var ? sc.solve_var : default_solve_variant(sc.N);
+    // BF16 factors have the one-wavefront kernel only
+    const int v = sc.solve_var ? sc.solve_var
+                               : (precision == 2 ? SOLVE_WAVE : default_solve_variant(sc.N));
     if (transpose)
       e = macro_solve_t_dispatch(nq, mode, fac, info, order, sc.start, sc.count, lds, perm, tmpl, T,
                                  skip, tau, lam, xin, yout, slots, s);
