@@ -140,3 +140,74 @@ def test_adjoint_matches_central_differences_on_gpu():
         bm[d] -= h
         fd = (Jof(kappa, bp) - Jof(kappa, bm)) / (2 * h)
         assert abs(fd - db[d]) <= 1e-5 * abs(fd) + 1e-9 * abs(J.item()), (d, fd, db[d])
+
+
+def test_adjoint_gradient_on_a_large_mesh():
+    """The gradient on a mesh of the differentiation workload's kind at 2048
+    macros (32 x 32 squares, r = 2, p = 2, log-normal kappa with sigma 0.5,
+    a = (1, 1), u = sin(pi x) sin(pi y), g_D = 0), J = ||u_h||^2_{L2} (u_obs =
+    0, so J and its derivatives are of order one), folded applies in both
+    solves.  The adjoint's dJ/dkappa and dJ/da against central differences of
+    the GPU forward solve along directions that move every macro at once:
+    kappa -> (1 + t) kappa (so sum_K kappa_K dJ/dkappa_K) and a_0 -> a_0 + t
+    (one macro's derivative is 1/2048 of J's scale).  Solves to a
+    preconditioned residual of 1e-12, t = 1e-3: truncation (t^2) and solve
+    error below 1e-6 relative; the bound is 1e-5.  (At the full 32,768-macro
+    size the folded solve stalls above 1e-11, so differences of full-size
+    solves cannot resolve the gradient to this bound; the operators the
+    gradient runs on are checked there in test_gpu_fullsize.py.)"""
+    xy, tri = inputs.structured_mesh(32)
+    r, p = 2, 2
+    kappa = inputs.lognormal_kappa(len(tri), 0.5, seed=5)
+    beta = np.array([1.0, 1.0])
+    ex = inputs.sin_sin(1.0, (1.0, 1.0))
+    m = mhdg.MacroMesh(xy, tri, r, p)
+    s = m.sizes
+    node, bnd = m.sample_points()
+    f = gpu(ex.f(node[:, 0], node[:, 1]))
+    g = gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+    kw = dict(rtol=1e-12, restart=1000, max_iter=30000, folded=True)
+    qu_obs = torch.zeros(s.n_local, dtype=torch.float64, device=DEV)
+
+    def forward(kap, bet, lam):
+        m.factor_local(gpu(kap), (float(bet[0]), float(bet[1])), 1.0)
+        m.fold_operator()
+        info = m.solve(f, g, lam, **kw)
+        print(f"  forward solve: {info.iterations} it, status {info.status}", flush=True)
+        assert info.status == 0, info.status
+        qu = torch.empty(s.n_local, dtype=torch.float64, device=DEV)
+        m.recover_local(lam, qu)
+        return qu, info.iterations
+
+    lam0 = torch.zeros(s.n_trace, dtype=torch.float64, device=DEV)
+    qu0, it0 = forward(kappa, beta, lam0)
+    qt = qu0.clone().requires_grad_(True)
+    J = ad.l2_misfit(m, qt, qu_obs)
+    J.backward()
+    dk = torch.empty(s.n_macro, dtype=torch.float64, device=DEV)
+    db = torch.empty(2, dtype=torch.float64, device=DEV)
+    psi_lam = torch.empty(s.n_trace, dtype=torch.float64, device=DEV)
+    psi_U = torch.empty(s.n_local, dtype=torch.float64, device=DEV)
+    info = m.adjoint(lam0, qu0, qt.grad.contiguous(), psi_lam, psi_U, dk, db, rtol=1e-12,
+                     restart=1000, max_iter=30000, folded=True)
+    print(f"  adjoint solve: {info.iterations} it, status {info.status}", flush=True)
+    assert info.status == 0
+    grad_scale = float((host(dk) * kappa).sum())
+    grad_b0 = float(host(db)[0])
+    t = 1e-3
+
+    def Jat(kap, bet):
+        lam = lam0.clone()
+        qu, it = forward(kap, bet, lam)
+        with torch.no_grad():
+            return ad.l2_misfit(m, qu, qu_obs).item(), it
+
+    (jp, ip), (jm, im) = Jat((1 + t) * kappa, beta), Jat((1 - t) * kappa, beta)
+    fd_scale = (jp - jm) / (2 * t)
+    (jp, ip2), (jm, im2) = Jat(kappa, beta + [t, 0.0]), Jat(kappa, beta - [t, 0.0])
+    fd_b0 = (jp - jm) / (2 * t)
+    es, eb = abs(grad_scale - fd_scale) / abs(fd_scale), abs(grad_b0 - fd_b0) / abs(fd_b0)
+    print(f"  J {J.item():.6e} ({it0} it; perturbed {ip} {im} {ip2} {im2} it); "
+          f"sum kappa dJ/dkappa {grad_scale:.10e} fd {fd_scale:.10e} ({es:.1e}); "
+          f"dJ/da0 {grad_b0:.10e} fd {fd_b0:.10e} ({eb:.1e})", flush=True)
+    assert es <= 1e-5 and eb <= 1e-5
