@@ -645,6 +645,31 @@ class Oracle:
         """A_K^-1 x (or A_K^-T x) with partial-pivoting LU."""
         return sla.lu_solve(self.lu(K), x, trans=1 if transpose else 0)
 
+    # -- boundary-condensed blocks (steps 1-3 restricted to the macro boundary) -
+    def boundary_rows(self, K):
+        """Rows of U_K = [q_x, q_y, u] that sit on the boundary of macro K, in
+        the compact boundary order: field-major, then position b = kP + s, the
+        lattice node at step s = 0 .. P-1 of local edge k walked from vertex k
+        towards vertex k+1 (lattice (s, 0), (P-s, s), (0, P-s) for k = 0, 1, 2);
+        3P nodes, each corner once."""
+        P, Q = int(self.topo.P[K]), int(self.topo.Q[K])
+        idx = lattice_index(P)
+        walk = [lambda s: (s, 0), lambda s: (P - s, s), lambda s: (0, P - s)]
+        nodes = np.array([idx[walk[k](s)] for k in range(3) for s in range(P)], dtype=np.int64)
+        return np.concatenate([f * Q + nodes for f in range(3)])
+
+    def boundary_block(self, K):
+        """W_K = (A_K^-1)_bb: the block of A_K^-1 on the boundary rows and
+        columns of boundary_rows(K).  B_K (boundary integrals against the
+        macro basis) vanishes off those rows and C_K off those columns, so
+        steps 1-3 of section 3.3.2 equal C_b W_K B_b.  Formed here as the
+        boundary rows of A_K^-1 e_c for every boundary unit vector e_c."""
+        rows = self.boundary_rows(K)
+        N = self.blocks(K).A.shape[0]
+        E = np.zeros((N, rows.size))
+        E[rows, np.arange(rows.size)] = 1.0
+        return self.local_solve(K, E)[rows, :]
+
     # -- O11: brute force on the unhybridised system ---------------------------
     def brute_force(self, f_nodal, g_bnd):
         """Dense solve of [A B; C D][U; lam] = [R; 0] over all macros."""

@@ -500,6 +500,89 @@ def test_interior_block_nonsingular_except_lone_bubble():
             assert n > 1 and s[-1] >= 1e-5 * s[0], (p, r, kappa)
 
 
+def test_boundary_rows_walk_the_macro_edges():
+    """The compact boundary order of the boundary-condensed blocks: position
+    kP + s is the node s/P of the way along local edge k from vertex k to
+    vertex k+1 (checked against the lattice coordinates of the node), each
+    boundary node appears once per field, and the set is exactly the nodes
+    that the face couplings G_k reach."""
+    for r, p in ((0, 3), (1, 2), (2, 1)):
+        xy, tri = inputs.structured_mesh(1, jitter=0.0)
+        o = hdg.Oracle(xy, tri, r, p, 1.0, (1.0, 0.5), 1.0)
+        P, Q = int(o.topo.P[0]), int(o.topo.Q[0])
+        rows = o.boundary_rows(0)
+        assert rows.size == 9 * P and np.unique(rows).size == rows.size
+        for f in range(3):
+            assert np.array_equal(rows[f * 3 * P:(f + 1) * 3 * P] - f * Q, rows[:3 * P])
+        # lattice coordinates of every node from the index convention
+        ij = np.zeros((Q, 2))
+        for j in range(P + 1):
+            for i in range(P + 1 - j):
+                ij[j * (P + 1) - j * (j - 1) // 2 + i] = (i, j)
+        X = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+        pos = ij / P
+        for b, n in enumerate(rows[:3 * P]):
+            k, sp = divmod(b, P)
+            want = X[k] + sp / P * (X[(k + 1) % 3] - X[k])
+            assert np.allclose(pos[n], want, atol=1e-15), (r, p, b)
+        blk = o.blocks(0)
+        reach = np.zeros(Q, bool)
+        for Gk in blk.G:
+            reach |= np.abs(Gk).sum(axis=1) > 1e-12 * np.abs(Gk).max()
+        assert set(np.flatnonzero(reach)) == set(rows[:3 * P].tolist())
+
+
+def test_boundary_block_is_the_inverse_of_the_boundary_schur_complement():
+    """Where the interior block A_ii is invertible, (A^-1)_bb equals
+    (A_bb - A_bi A_ii^-1 A_ib)^-1 (block elimination of the interior
+    unknowns), a different route from the unit-vector solves of the oracle."""
+    for p, r, kappa in ((1, 2, 1.0), (2, 1, 0.01), (3, 1, 1.0), (2, 2, 0.3)):
+        xy, tri = inputs.structured_mesh(1, jitter=0.0)
+        o = hdg.Oracle(xy, tri, r, p, kappa, (1.0, -0.7), 1.3)
+        A = o.blocks(0).A
+        b = o.boundary_rows(0)
+        i = np.setdiff1d(np.arange(A.shape[0]), b)
+        S = A[np.ix_(b, b)] - A[np.ix_(b, i)] @ np.linalg.solve(A[np.ix_(i, i)], A[np.ix_(i, b)])
+        W = o.boundary_block(0)
+        err = np.abs(W @ S - np.eye(b.size)).max()
+        assert err < 1e-9, (p, r, kappa, err)
+
+
+@pytest.mark.parametrize("r,p", [(0, 3), (1, 2), (2, 1)])
+def test_boundary_block_reproduces_steps_1_to_3(r, p):
+    """B_K vanishes off the boundary rows and C_K off the boundary columns, so
+    C_b W_K B_b lambda_K equals the macro contribution C_K A_K^-1 B_K lambda_K
+    (and B_b^T W_K^T C_b^T for the transposed operator).  r = 0, p = 3 is the
+    lone cubic bubble, whose singular A_ii the unit-vector route does not need."""
+    xy, tri = inputs.structured_mesh(2, jitter=0.1, seed=3)
+    o = hdg.Oracle(xy, tri, r, p, 0.4, (1.0, 0.6), 1.0)
+    rng = np.random.default_rng(11)
+    lam = rng.standard_normal(o.topo.n_trace)
+    for K in range(o.topo.n_macro):
+        blk = o.blocks(K)
+        rows = o.boundary_rows(K)
+        off = np.setdiff1d(np.arange(blk.A.shape[0]), rows)
+        for k in range(3):   # zero up to the rounding of the basis on the edge
+            assert np.abs(blk.B[k][off, :]).max() <= 1e-13 * np.abs(blk.B[k]).max()
+            assert np.abs(blk.C[k][:, off]).max() <= 1e-13 * np.abs(blk.C[k]).max()
+        W = o.boundary_block(K)
+        icols = o._interior_cols(K)
+        for tr in (False, True):
+            ref = o.macro_contribution(K, lam, transpose=tr)
+            if tr:
+                x = sum(blk.C[k][:, rows].T @ lam[a:a + n] for k, a, n in icols)
+                z = W.T @ x
+                got = {int(o.topo.macro_face[K, k]): blk.B[k][rows, :].T @ z for k, _, _ in icols}
+            else:
+                x = sum(blk.B[k][rows, :] @ lam[a:a + n] for k, a, n in icols)
+                z = W @ x
+                got = {int(o.topo.macro_face[K, k]): blk.C[k][:, rows] @ z for k, _, _ in icols}
+            assert got.keys() == ref.keys()
+            for f in ref:
+                assert np.allclose(got[f], ref[f], rtol=1e-10, atol=1e-12 * np.abs(ref[f]).max()), \
+                    (K, f, tr)
+
+
 def test_flux_balance_subset_equals_full_evaluation():
     """The macros= argument only restricts which macros are evaluated."""
     xy, tri = inputs.structured_mesh(2, jitter=0.1, seed=4)
