@@ -61,6 +61,12 @@ WORKLOADS = {
     "assembled_qelim_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
                                                  sol="exp_sin", precision="qelim",
                                                  form="assembled", restart=40),
+    # the boundary-condensed form (same mesh and data): W_K = (A_K^-1)_bb over the 9P = 216
+    # boundary unknowns of each macro, built from the FP64 factors; GMRES applies read
+    # 8 x 216^2 bytes per macro (3.06 GB) between the factors' 62 GB and T_K's 0.37 GB
+    "boundary_fp64_8192macro_r3_p3": dict(n=64, r=3, p=3, kappa=1e-2, beta=(1.0, 0.5),
+                                          sol="exp_sin", precision="fp64", form="boundary",
+                                          restart=40),
     # the best tuned form on the uneven-level mesh (instance 0 of the batching configuration)
     "folded_qelim_mixed_r1to4_8192macro_p3_inst0": dict(n=64, r="mixed", p=3, kappa=None,
                                                         beta=None, sol="exp_sin",
@@ -171,6 +177,14 @@ def fold_bytes(tri, r, p, n_trace):
     nF = (2 ** flev[inv] * p + 1).reshape(-1, 3)
     L = np.where((cnt[inv] == 2).reshape(-1, 3), nF, 0).sum(axis=1)
     return 8.0 * float(np.sum(L.astype(np.float64) ** 2)) + 32.0 * n_trace
+
+
+def boundary_bytes(m, n_trace):
+    """Algorithmic bytes of one boundary-condensed apply: every W_K once
+    (8 (9P)^2, P = 2^r_K p), the gathered trace and the written slots
+    (2 x 8 x 2 n_trace)."""
+    P = m.macro_P().astype(np.float64)
+    return 8.0 * float(np.sum((9.0 * P) ** 2)) + 32.0 * n_trace
 
 
 def lu_flops(w, s, qelim=False):
@@ -371,7 +385,9 @@ def main():
     if w.get("form") == "many_rhs":
         return bench_many_rhs(args, w)
     assembled = w.get("form") == "assembled"
-    folded = (w.get("form") == "folded" or args.folded) and not assembled
+    boundary = w.get("form") == "boundary"
+    folded = (w.get("form") == "folded" or args.folded) and not (assembled or boundary)
+    condensed = folded or assembled or boundary
     xy, tri = inputs.structured_mesh(w["n"])
     n_inst = w.get("n_inst", 1)
     if w["r"] == "mixed":
@@ -427,7 +443,7 @@ def main():
     # the plain form's cycles run as direct launches, so that every apply is
     # bracketed by HIP events for the roofline (its 11 ms applies leave no
     # launch overhead to hide); the folded forms replay captured cycles
-    sgraph = folded or assembled
+    sgraph = condensed
 
     def step():
         m.factor_local(kappa, beta_arg, 1.0, precision=prec)
@@ -435,10 +451,12 @@ def main():
             m.fold_operator()
         if assembled:
             m.assemble_trace_matrix()
+        if boundary:
+            m.condense_boundary()
         info = m.solve(f, g, lam, rtol=args.rtol, restart=args.restart, max_iter=args.max_iter,
                        check=args.max_iter >= 20000, inner_rtol=args.inner_rtol, folded=folded,
                        max_outer=60, graph=sgraph, driver=drv, stop_norm=stop,
-                       assembled=assembled)
+                       assembled=assembled, boundary=boundary)
         m.recover_local(lam, qu)
         infos.append(info.as_dict())
         inst_infos.append(m.last_solve_infos)
@@ -479,7 +497,7 @@ def main():
     lam_r = torch.as_tensor(inputs.random_vector(s.n_trace, seed=1), device=dev)
     out = torch.empty_like(lam_r)
     aflags = (mhdg.MHDG_PRECONDITION | (mhdg.MHDG_FOLDED if folded else 0) |
-              (mhdg.MHDG_ASSEMBLED if assembled else 0))
+              (mhdg.MHDG_ASSEMBLED if assembled else 0) | (mhdg.MHDG_BOUNDARY if boundary else 0))
     m.apply_trace_operator(lam_r, out, aflags)
     torch.cuda.synchronize()
     ta = time.perf_counter()
@@ -514,7 +532,7 @@ def main():
     del buf
 
     tuned = None
-    if (not args.no_tuned_forms and not folded and n_inst == 1 and prec == mhdg.MHDG_FP64
+    if (not args.no_tuned_forms and not condensed and n_inst == 1 and prec == mhdg.MHDG_FP64
             and np.ndim(w["r"]) == 0):
         # the tuned form of the same job: folded macro operators (timed like the
         # plain steps, same handle, same data; outside the plain timed region)
@@ -626,6 +644,55 @@ def main():
         print(f"[bench] assembled: {tuned['matrix_based_flux_eliminated_fp64']}",
               file=sys.stderr, flush=True)
 
+        # the boundary-condensed form: W_K = (A_K^-1)_bb built from the FP64 factors,
+        # GMRES applies through W_K
+        print("[bench] boundary-condensed form", file=sys.stderr, flush=True)
+        b_infos = []
+
+        def bstep():
+            m.factor_local(kappa, beta_arg, 1.0, precision=prec)
+            m.condense_boundary()
+            inf = m.solve(f, g, lam, rtol=args.rtol, restart=args.folded_restart,
+                          max_iter=args.max_iter, boundary=True, driver=drv, stop_norm=stop)
+            m.recover_local(lam, qu)
+            b_infos.append(inf.as_dict())
+        bstep()
+        b_infos.clear()
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        for _ in range(args.steps):
+            bstep()
+        torch.cuda.synchronize()
+        tbc = (time.perf_counter() - tb0) / args.steps
+        lam_b = torch.as_tensor(inputs.random_vector(s.n_trace, seed=1), device=dev)
+        out_b = torch.empty_like(lam_b)
+        m.profile(True)
+        for _ in range(args.apply_reps):
+            m.apply_trace_operator(lam_b, out_b, mhdg.MHDG_PRECONDITION | mhdg.MHDG_BOUNDARY)
+        torch.cuda.synchronize()
+        kb = m.profile(False)["folded_apply"]
+        b_ms = kb["ms"] / max(kb["count"], 1)
+        b_bytes = boundary_bytes(m, s.n_trace)
+        tuned["boundary_condensed_fp64"] = {
+            "time_to_solve_s": tbc,
+            "applies_per_s": sum(x["n_applies"] for x in b_infos) / (tbc * args.steps),
+            "iterations": [x["iterations"] for x in b_infos],
+            "gmres_restart": args.folded_restart,
+            "speedup_vs_plain": (ms_per_step / 1e3) / tbc,
+            "rel_res_true": max(x["rel_res_true"] for x in b_infos),
+            "rel_res_prec": max(x["rel_res_prec"] for x in b_infos),
+            "max_rel_diff_lambda_vs_plain":
+                float(torch.linalg.norm(lam - lam_plain) / torch.linalg.norm(lam_plain)),
+            "apply_kernel_ms": b_ms,
+            "apply_bytes": b_bytes,
+            "apply_gbs": b_bytes / (b_ms * 1e-3) / 1e9,
+            "apply_frac_hbm": b_bytes / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "what": "W_K = (A_K^-1)_bb over the macro's 9P boundary unknowns (the interior "
+                    "condensed out), built by unit-vector solves on the FP64 factors; GMRES "
+                    "applies lift with B_K, multiply by W_K, restrict with C_K"}
+        print(f"[bench] boundary-condensed: {tuned['boundary_condensed_fp64']}",
+              file=sys.stderr, flush=True)
+
     jitter = None
     if not args.no_jitter_control and args.workload == "plain_fp64_8192macro_r3_p3":
         # control: the same job on a mesh whose interior vertices move by up to 0.15 h in
@@ -730,7 +797,7 @@ def main():
                "lambda": rd(lam_lp, lam), "q": rd(qv_lp[:, :2], qv[:, :2]),
                "u": rd(qv_lp[:, 2], qv[:, 2])}
 
-    ams = kt["folded_apply" if (folded or assembled) else "apply_macro_solve"]
+    ams = kt["folded_apply" if condensed else "apply_macro_solve"]
     # apply launches that did work: GMRES and residual applies (n_applies less the
     # two right-hand-side passes), per solve the largest count over instances.  The
     # event time of launches after every instance converged (the rest of the last
@@ -742,7 +809,7 @@ def main():
     apply_timing = "HIP events around every apply kernel of the timed solves"
     if ams["count"] == 0:
         # captured cycles: the apply kernel timed by events in the apply-only loop
-        ams = kt_apply["folded_apply" if (folded or assembled) else "apply_macro_solve"]
+        ams = kt_apply["folded_apply" if condensed else "apply_macro_solve"]
         work_launches = ams["count"]
         apply_timing = ("HIP events around the apply kernel in an apply-only loop after the "
                         "timed solves (those replay captured GMRES cycles, without events)")
@@ -758,6 +825,8 @@ def main():
         # assembled product: every stored block once (and its table), the trace read and
         # the result written once
         nbytes = float(mhdg.load_library().mhdg_trace_matrix_ws_bytes(m.h)) + 16.0 * s.n_trace
+    if boundary:
+        nbytes = boundary_bytes(m, s.n_trace)
     if n_inst > 1:
         # converged instances are masked out of later launches: count the
         # instances each launch actually processed (GMRES applies + the
@@ -789,8 +858,8 @@ def main():
                    "beta": list(w["beta"]) if n_inst == 1 else
                    "|a| U(0.5,2), direction U[0,2pi) per instance, seed 33",
                    "tau": 1.0, "rtol": args.rtol, "gmres_restart": args.restart,
-                   "form": ("folded_fp64" if folded else
-                            "batched_fp64" if n_inst > 1 else "plain_fp64")
+                   "form": ("folded_fp64" if folded else "boundary_condensed_fp64" if boundary
+                            else "batched_fp64" if n_inst > 1 else "plain_fp64")
                    if prec == mhdg.MHDG_FP64 else
                    ("matrix_based_flux_eliminated_fp64" if assembled else
                     "folded_flux_eliminated_fp64" if folded else "flux_eliminated_fp64")
@@ -810,6 +879,7 @@ def main():
                      "traffic_vs_algorithmic": traffic["traffic_bytes_per_launch"] / nbytes
                      if traffic else None,
                      "kernel": ("trace_matrix_apply_kernel (assembled S)" if assembled else
+                                "bc_apply_kernel (boundary-condensed steps 1-3)" if boundary else
                                 "fold_apply_kernel (folded steps 1-3)" if folded else
                                 "qelim_solve_kernel (apply steps 1-3, flux eliminated)"
                                 if prec == mhdg.MHDG_QELIM else

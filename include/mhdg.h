@@ -122,8 +122,11 @@ enum {
   MHDG_FOLDED = 8,            /* apply: steps 1-3 with the folded operators
                                  T_K of mhdg_fold_operator (T_K^T with
                                  MHDG_TRANSPOSE)                              */
-  MHDG_ASSEMBLED = 16         /* apply: the assembled matrix S of
+  MHDG_ASSEMBLED = 16,        /* apply: the assembled matrix S of
                                  mhdg_assemble_trace_matrix (no TRANSPOSE)   */
+  MHDG_BOUNDARY = 32          /* apply: steps 1-3 through the boundary blocks
+                                 W_K of mhdg_condense_boundary (W_K^T with
+                                 MHDG_TRANSPOSE); excludes FOLDED, ASSEMBLED */
 };
 
 /* GMRES drivers (mhdg_solve_opts.driver) and stopping norms (.stop_norm) */
@@ -192,6 +195,9 @@ typedef struct {
   int32_t assembled;          /* 1: GMRES applies use the assembled matrix
                                  (MHDG_ASSEMBLED; needs
                                  mhdg_assemble_trace_matrix)                 */
+  int32_t boundary;           /* 1: GMRES applies (solve and adjoint) use the
+                                 boundary-condensed blocks (MHDG_BOUNDARY;
+                                 needs mhdg_condense_boundary)               */
 } mhdg_solve_opts;
 
 typedef struct {
@@ -295,8 +301,12 @@ mhdg_status mhdg_local_matrix(mhdg_mesh* mesh, int64_t e, double* dst, void* str
  * MHDG_GRAPH the launches run as one replay of a captured hipGraph; the
  * result is the same bit for bit.  (Steps 1-4 of the matrix-free method of
  * section 3.3.2: gather and lift, local solve, restriction, face sum; the
- * preconditioned step 4 is the D^-1 variant of section 6.1.)
- * Errors: STATE before factor_local. */
+ * preconditioned step 4 is the D^-1 variant of section 6.1.)  MHDG_FOLDED,
+ * MHDG_ASSEMBLED and MHDG_BOUNDARY run steps 1-3 through the stored
+ * condensed operators instead of the factors.
+ * Errors: STATE before factor_local, or a condensed form not yet built;
+ * INVALID_ARG for MHDG_ASSEMBLED with MHDG_TRANSPOSE or with another
+ * condensed form, MHDG_BOUNDARY with MHDG_FOLDED. */
 mhdg_status mhdg_apply_trace_operator(mhdg_mesh* mesh, const double* lam, double* out,
                                       int32_t flags, void* stream);
 
@@ -519,14 +529,39 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void*
 size_t mhdg_trace_matrix_ws_bytes(const mhdg_mesh* mesh);
 mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void* stream);
 
+/* Boundary-condensed macro operators.  Steps 1-3 of section 3.3.2 apply
+ * C_K A_K^-1 B_K; B_K (face integrals against the macro basis) is nonzero
+ * only on boundary-node rows and C_K only on boundary-node columns, so the
+ * product equals C_b W_K B_b with W_K = (A_K^-1)_bb, the block of A_K^-1 on
+ * the boundary nodes of all three fields.  Where the interior block A_ii is
+ * invertible, W_K is the inverse of the boundary Schur complement
+ * A_bb - A_bi A_ii^-1 A_ib (the interior unknowns condensed out); W_K is
+ * formed from the stored LU of A_K (9P solves with unit right-hand sides),
+ * which also covers a macro whose A_ii is singular.
+ * Layout of ws (device memory of at least mhdg_boundary_ws_bytes bytes, owned
+ * by the caller and read by every later MHDG_BOUNDARY apply until the next
+ * factor_local, set_instances or set_supg): int64 offsets[n_macro], then from
+ * byte offset align256(8 n_macro) the blocks, W_K at element offsets[K]:
+ * 9P x 9P FP64 column-major (P = 2^r_K p), rows and columns in the order
+ * field (q_x, q_y, u) major, then boundary position b = kP + s, the node at
+ * position s = 0 .. P-1 of local edge k (from vertex k towards vertex k+1).
+ * At 8192 macros, r = 3, p = 3 the blocks take 3.06 GB (216 x 216 each).
+ * Applies with MHDG_BOUNDARY (and solves or adjoints with opts->boundary)
+ * then read W_K once per macro.  Synchronises the stream once.
+ * Errors: STATE (before factor_local, or factors other than MHDG_FP64),
+ * WORKSPACE, INVALID_ARG (9P > 512), HIP. */
+size_t mhdg_boundary_ws_bytes(const mhdg_mesh* mesh);
+mhdg_status mhdg_condense_boundary(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void* stream);
+
 /* Per-kernel timing of the hot path, for measurement.  enable = 1 clears
  * the counters and brackets every later launch of the listed kernels with
  * HIP events recorded on the launch stream; enable = 0 stops recording,
  * waits for the recorded events and fills *out (may be NULL).  Index:
  * 0 assemble, 1 lu, 2 macro solve of apply_trace_operator (steps 1-3),
  * 3 face combine (step 4), 4 macro solve of rhs/recover/local_solve,
- * 5 folded apply (steps 1-3 with T_K).  An apply replayed from a captured
- * graph (MHDG_GRAPH) is timed whole under index 2 (5 when folded). */
+ * 5 condensed apply (steps 1-3 through T_K or W_K, or the assembled
+ * product).  An apply replayed from a captured graph (MHDG_GRAPH) is timed
+ * whole under index 2 (5 for the condensed forms). */
 typedef struct {
   int32_t count[6];
   double ms[6];

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhdg.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["host.cpp", "kernels.hip", "lu_blocked.hip", "lu_split.hip", "fold.hip", "qelim.hip", "many.hip", "gmres_dev.hip", "assembled.hip", "solve_nq_small.hip", "solve_nq_16.hip",
+SOURCES = ["host.cpp", "kernels.hip", "lu_blocked.hip", "lu_split.hip", "fold.hip", "qelim.hip", "many.hip", "gmres_dev.hip", "assembled.hip", "boundary.hip", "solve_nq_small.hip", "solve_nq_16.hip",
            "solve_nq_27.hip", "solve_nq_58.hip", "solve_mw_variants.hip"]
 
 HIPCC_FLAGS = [

@@ -67,6 +67,12 @@ struct mhdg_mesh {
   const TraceBlock* tm_blocks = nullptr;  // device: block table
   const double* tm_values = nullptr;      // device: block values
   int64_t tm_n_blocks = 0, tm_n_values = 0;
+  // boundary-condensed blocks W_K (mhdg_condense_boundary): valid until the
+  // next factor_local
+  bool bcond = false;
+  const int64_t* bc_off = nullptr;   // device: element offset of W_K
+  const double* bc_W = nullptr;      // device: W_K column-major, 9P x 9P
+  int bc_maxP = 0;
   int precision = MHDG_FP64;
   double tau = 1;
   char* ws = nullptr;
@@ -817,6 +823,21 @@ static FoldLayout fold_layout(const mhdg_mesh* M) {
   return F;
 }
 static size_t solve_bytes(const mhdg_mesh* M, int restart) { return solve_bytes_impl(M, restart); }
+
+// Boundary-condensed workspace: W_K offsets int64[n_macro] (elements from the
+// start of the block area), then every W_K (FP64, column-major, 9P x 9P).
+struct BoundaryLayout { size_t off, W, total; int64_t nW; };
+static BoundaryLayout boundary_layout(const mhdg_mesh* M) {
+  BoundaryLayout B{};
+  size_t o = 0;
+  B.off = o;   o = align_up(o + size_t(M->n_macro) * 8);
+  B.W = o;
+  int64_t nW = 0;
+  for (auto& mi : M->macros) { const int64_t nb = 9 * int64_t(mi.P); nW += nb * nb; }
+  B.nW = nW;
+  B.total = align_up(o + size_t(nW) * 8);
+  return B;
+}
 
 // Block table of the assembled trace matrix: for every macro, every ordered
 // pair of its interior faces gives a block (F, F') fed by that macro's T_K
@@ -2021,6 +2042,7 @@ mhdg_status mhdg_set_instances(mhdg_mesh* M, int32_t n_inst) {
   M->have_rhs = false;
   M->folded = false;
   M->assembled = false;
+  M->bcond = false;
   M->ws = nullptr;
   M->drop_graphs();
   M->n_inst = n_inst;
@@ -2223,6 +2245,7 @@ mhdg_status mhdg_factor_local_batched(mhdg_mesh* M, const double* kappa, const d
   M->have_rhs = false;
   M->folded = false;
   M->assembled = false;
+  M->bcond = false;
   M->drop_graphs();
   M->precision = precision;
   M->tau = tau;
@@ -2431,6 +2454,50 @@ mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* M, void* ws, size_t ws_bytes, 
   return MHDG_OK;
 }
 
+size_t mhdg_boundary_ws_bytes(const mhdg_mesh* M) {
+  if (!M) return 0;
+  return boundary_layout(M).total;
+}
+
+mhdg_status mhdg_condense_boundary(mhdg_mesh* M, void* ws, size_t ws_bytes, void* stream) {
+  if (!M) return MHDG_ERR_INVALID_ARG;
+  if (!M->factored || M->precision != MHDG_FP64)
+    return fail(M, MHDG_ERR_STATE, "condense_boundary: needs MHDG_FP64 factors (call factor_local first)");
+  const BoundaryLayout B = boundary_layout(M);
+  if (!ws || ws_bytes < B.total)
+    return fail(M, MHDG_ERR_WORKSPACE, "condense_boundary: workspace smaller than mhdg_boundary_ws_bytes");
+  std::vector<int64_t> off(M->n_macro);
+  int64_t o = 0;
+  int maxP = 0;
+  for (int64_t e = 0; e < M->n_macro; ++e) {
+    off[e] = o;
+    const int P = M->macros[e].P;
+    maxP = std::max(maxP, P);
+    o += 81 * int64_t(P) * P;
+  }
+  if (9 * maxP > 512)
+    return fail(M, MHDG_ERR_INVALID_ARG, "condense_boundary: macro boundary larger than 512 unknowns");
+  hipStream_t s = (hipStream_t)stream;
+  char* bw = (char*)ws;
+  HIP_TRY(M, hipMemcpyAsync(bw + B.off, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
+  FactorLayout& L = M->L;
+  char* w = M->ws;
+  double* W = (double*)(bw + B.W);
+  if (M->n_macro > 0)
+    HIP_TRY(M, launch_bc_build((const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
+                               (const int32_t*)(w + L.order), M->classes.data(),
+                               (int)M->classes.size(), (const int32_t*)(w + L.perm),
+                               (const double*)(w + L.tmpl), M->T, (const int64_t*)(bw + B.off), W,
+                               s));
+  HIP_TRY(M, hipStreamSynchronize(s));   // the host offset table is freed on return
+  M->bc_off = (const int64_t*)(bw + B.off);
+  M->bc_W = W;
+  M->bc_maxP = maxP;
+  M->bcond = true;
+  M->drop_graphs();
+  return MHDG_OK;
+}
+
 mhdg_status mhdg_set_supg(mhdg_mesh* M, int32_t on) {
   if (!M) return MHDG_ERR_INVALID_ARG;
   if (on != 0 && on != 1) return fail(M, MHDG_ERR_INVALID_ARG, "set_supg: on must be 0 or 1");
@@ -2447,6 +2514,7 @@ mhdg_status mhdg_set_supg(mhdg_mesh* M, int32_t on) {
   M->have_rhs = false;
   M->folded = false;
   M->assembled = false;
+  M->bcond = false;
   M->drop_graphs();
   return MHDG_OK;
 }
@@ -2624,6 +2692,8 @@ static mhdg_status run_macro_solve(mhdg_mesh* M, int mode, int transpose, const 
 namespace {
 mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t flags,
                            const int32_t* skip, hipStream_t s);
+// applies that run through stored condensed operators (timed under index 5)
+constexpr int32_t kCondensed = MHDG_FOLDED | MHDG_ASSEMBLED | MHDG_BOUNDARY;
 
 // The trace operator with an optional per-instance mask (see gmres).  With
 // MHDG_GRAPH the launches (one per size class, each covering every
@@ -2635,7 +2705,7 @@ mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags
   const int32_t f = flags & ~MHDG_GRAPH;
   for (auto& a : M->graphs)
     if (a.lam == lam && a.out == out && a.flags == f && a.skip == skip) {
-      ProfScope ps(M, (f & MHDG_FOLDED) ? 5 : 2, s);   // the whole replayed apply
+      ProfScope ps(M, (f & kCondensed) ? 5 : 2, s);   // the whole replayed apply
       HIP_TRY(M, hipGraphLaunch(a.x, s));
       return MHDG_OK;
     }
@@ -2662,7 +2732,7 @@ mhdg_status apply_op(mhdg_mesh* M, const double* lam, double* out, int32_t flags
     return fail(M, MHDG_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
   }
   M->graphs.push_back({lam, out, f, skip, g, x});
-  ProfScope ps(M, (f & MHDG_FOLDED) ? 5 : 2, s);
+  ProfScope ps(M, (f & kCondensed) ? 5 : 2, s);
   HIP_TRY(M, hipGraphLaunch(x, s));
   return MHDG_OK;
 }
@@ -2678,6 +2748,21 @@ mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t
                                          M->tm_values, (const double*)(M->ws + L.tmpl), M->T,
                                          M->tau, (flags & MHDG_PRECONDITION) ? 1 : 0, skip, lam,
                                          out, s));
+    return MHDG_OK;
+  }
+  if (flags & MHDG_BOUNDARY) {
+    FactorLayout& L = M->L;
+    {
+      ProfScope ps(M, 5, s);
+      HIP_TRY(M, launch_bc_apply((const MacroInfo*)(M->ws + L.meta), M->n_macro, M->bc_off,
+                                 M->bc_W, M->bc_maxP, (const double*)(M->ws + L.tmpl), M->T,
+                                 M->tau, skip, tr, lam, (double*)(M->ws + L.slots), s));
+    }
+    ProfScope ps(M, 3, s);
+    HIP_TRY(M, launch_face_combine((flags & MHDG_PRECONDITION) ? FACE_PREC_S : FACE_S,
+                                   (const FaceInfo*)(M->ws + L.faces), M->n_int,
+                                   (const double*)(M->ws + L.tmpl), M->T, M->tau, lam,
+                                   (const double*)(M->ws + L.slots), out, s, skip));
     return MHDG_OK;
   }
   if (flags & MHDG_FOLDED) {
@@ -2724,6 +2809,13 @@ mhdg_status mhdg_apply_trace_operator(mhdg_mesh* M, const double* lam, double* o
     if (tr || (flags & MHDG_FOLDED))
       return fail(M, MHDG_ERR_INVALID_ARG,
                   "apply: MHDG_ASSEMBLED takes no MHDG_TRANSPOSE or MHDG_FOLDED");
+  }
+  if (flags & MHDG_BOUNDARY) {
+    if (!M->bcond)
+      return fail(M, MHDG_ERR_STATE, "apply: the boundary-condensed blocks need mhdg_condense_boundary");
+    if (flags & (MHDG_FOLDED | MHDG_ASSEMBLED))
+      return fail(M, MHDG_ERR_INVALID_ARG,
+                  "apply: MHDG_BOUNDARY takes no MHDG_FOLDED or MHDG_ASSEMBLED");
   }
   if (M->n_trace == 0) return MHDG_OK;
   return apply_op(M, lam, out, flags, nullptr, (hipStream_t)stream);
@@ -3008,6 +3100,14 @@ mhdg_status mhdg_solve(mhdg_mesh* M, const double* f_nodes, const double* g_bnd,
       return fail(M, MHDG_ERR_INVALID_ARG, "solve: folded and assembled are exclusive");
     G.op_flags |= MHDG_ASSEMBLED;
   }
+  if (o->boundary) {
+    if (!M->bcond)
+      return fail(M, MHDG_ERR_STATE, "solve: boundary-condensed applies need mhdg_condense_boundary");
+    if (o->folded || o->assembled)
+      return fail(M, MHDG_ERR_INVALID_ARG,
+                  "solve: boundary-condensed, folded and assembled applies are exclusive");
+    G.op_flags |= MHDG_BOUNDARY;
+  }
   const bool stop_true = o->stop_norm == MHDG_NORM_TRUE;
   if (stop_true && !(M->precision == MHDG_FP64 || M->precision == MHDG_QELIM))
     return fail(M, MHDG_ERR_INVALID_ARG,
@@ -3208,6 +3308,13 @@ mhdg_status mhdg_adjoint(mhdg_mesh* M, const double* lam, const double* qu, cons
   if (o->folded) {
     if (!M->folded) return fail(M, MHDG_ERR_STATE, "adjoint: folded applies need mhdg_fold_operator");
     G.op_flags |= MHDG_FOLDED;
+  }
+  if (o->boundary) {
+    if (!M->bcond)
+      return fail(M, MHDG_ERR_STATE, "adjoint: boundary-condensed applies need mhdg_condense_boundary");
+    if (o->folded)
+      return fail(M, MHDG_ERR_INVALID_ARG, "adjoint: boundary-condensed and folded are exclusive");
+    G.op_flags |= MHDG_BOUNDARY;
   }
   FactorLayout& L = M->L;
   char* fw = M->ws;

@@ -249,6 +249,17 @@ hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* to
                              int p, int max_L, const int32_t* skip, int transpose,
                              const double* lam, double* slots, hipStream_t s);
 
+// boundary-condensed blocks W_K = (A_K^-1)_bb (boundary.hip): the build from
+// the FP64 factors, then steps 1-3 through W_K (W_K^T when transposed)
+hipError_t launch_bc_build(const double* fac, const MacroInfo* info, const int32_t* order,
+                           const SizeClass* classes, int n_classes, const int32_t* perm,
+                           const double* tmpl, const Templates& T, const int64_t* woff,
+                           double* W, hipStream_t s);
+hipError_t launch_bc_apply(const MacroInfo* info, int64_t n, const int64_t* woff, const double* W,
+                           int max_P, const double* tmpl, const Templates& T, double tau,
+                           const int32_t* skip, int transpose, const double* lam, double* slots,
+                           hipStream_t s);
+
 // steps 1-3 for n_rhs trace vectors at once (many.hip): vector v reads
 // lam + v * ld_lam and writes its slots at slots + v * ld_slots
 hipError_t launch_apply_many(const double* fac, const MacroInfo* info, const int32_t* order,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmhdg.so")
 
 MHDG_FP64, MHDG_FP32, MHDG_BF16, MHDG_QELIM = 0, 1, 2, 3
 MHDG_PRECONDITION, MHDG_TRANSPOSE, MHDG_GRAPH, MHDG_FOLDED = 1, 2, 4, 8
-MHDG_ASSEMBLED = 16
+MHDG_ASSEMBLED, MHDG_BOUNDARY = 16, 32
 MHDG_DRIVER_DEVICE, MHDG_DRIVER_HOST = 0, 1
 MHDG_NORM_PRECONDITIONED, MHDG_NORM_TRUE = 0, 1
 
@@ -33,7 +33,7 @@ ABI_SYMBOLS = [
     "mhdg_set_kernel_variant", "mhdg_fold_operator", "mhdg_apply_many_ws_bytes",
     "mhdg_apply_trace_operator_many", "mhdg_flux_balance", "mhdg_set_supg",
     "mhdg_apply_trace_operator_many_noalloc", "mhdg_trace_matrix_ws_bytes",
-    "mhdg_assemble_trace_matrix",
+    "mhdg_assemble_trace_matrix", "mhdg_boundary_ws_bytes", "mhdg_condense_boundary",
 ]
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 MHDG_TUNE_LU, MHDG_TUNE_SOLVE = 1, 2
@@ -62,7 +62,8 @@ class SolveOpts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
                 ("graph", ctypes.c_int32), ("folded", ctypes.c_int32),
                 ("classic_gs", ctypes.c_int32), ("driver", ctypes.c_int32),
-                ("stop_norm", ctypes.c_int32), ("assembled", ctypes.c_int32)]
+                ("stop_norm", ctypes.c_int32), ("assembled", ctypes.c_int32),
+                ("boundary", ctypes.c_int32)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -131,6 +132,7 @@ def load_library(path: str = LIB_PATH):
         "mhdg_set_supg": [P, I32],
         "mhdg_fold_operator": [P, P, SZ, P],
         "mhdg_assemble_trace_matrix": [P, P, SZ, P],
+        "mhdg_condense_boundary": [P, P, SZ, P],
         "mhdg_local_matrix": [P, I64, P, P],
         "mhdg_apply_trace_operator": [P, P, P, I32, P],
         "mhdg_apply_trace_operator_many": [P, I32, P, P, I32, P, SZ, P],
@@ -153,6 +155,8 @@ def load_library(path: str = LIB_PATH):
     lib.mhdg_apply_many_ws_bytes.restype = SZ
     lib.mhdg_trace_matrix_ws_bytes.argtypes = [P]
     lib.mhdg_trace_matrix_ws_bytes.restype = SZ
+    lib.mhdg_boundary_ws_bytes.argtypes = [P]
+    lib.mhdg_boundary_ws_bytes.restype = SZ
     lib.mhdg_destroy.argtypes = [P]
     lib.mhdg_destroy.restype = None
     lib.mhdg_last_error.argtypes = [P]
@@ -199,6 +203,9 @@ class MacroMesh:
         if st != 0:
             raise MhdgError(st, "setup_macro_mesh rejected the mesh")
         self.h = h
+        self._level = (np.full(tri.shape[0], uniform, dtype=np.int64) if lev_arr is None
+                       else lev_arr.astype(np.int64))
+        self._p = int(p)
         self.factor_ws = None
         self.solve_ws = None
         self.precision = MHDG_FP64
@@ -216,6 +223,7 @@ class MacroMesh:
             self._lib.mhdg_destroy(h)
         self.h = None
         self.factor_ws = self.solve_ws = self.fold_ws = self.many_ws = None
+        self.matrix_ws = self.boundary_ws = None
 
     def __del__(self):
         self.close()
@@ -242,6 +250,10 @@ class MacroMesh:
     @property
     def n_instances(self) -> int:
         return int(self.sizes.n_instances)
+
+    def macro_P(self):
+        """P = 2^r_K p of every macro (all instances, instance-major)."""
+        return np.tile((2 ** self._level) * self._p, self.n_instances)
 
     def sample_points(self):
         s = self.sizes
@@ -326,7 +338,7 @@ class MacroMesh:
 
     def solve(self, f_nodes, g_bnd, lam, rtol=1e-10, restart=30, max_iter=10000, zero_guess=True,
               stream=None, check=True, inner_rtol=0.0, max_outer=0, graph=True, folded=False,
-              classic_gs=False, driver=None, stop_norm=None, assembled=False):
+              classic_gs=False, driver=None, stop_norm=None, assembled=False, boundary=False):
         import torch
         self.state_gen += 1
         s = self.query(self.precision, restart)
@@ -338,7 +350,7 @@ class MacroMesh:
                          1 if folded else 0, 1 if classic_gs else 0,
                          MHDG_DRIVER_DEVICE if driver is None else int(driver),
                          MHDG_NORM_PRECONDITIONED if stop_norm is None else int(stop_norm),
-                         1 if assembled else 0)
+                         1 if assembled else 0, 1 if boundary else 0)
         infos = (SolveInfo * max(1, s.n_instances))()
         st = self._lib.mhdg_solve(self.h, _ptr(f_nodes), _ptr(g_bnd), ctypes.byref(opts), _ptr(lam),
                                   _ptr(self.solve_ws), self.solve_ws.numel(),
@@ -355,7 +367,7 @@ class MacroMesh:
 
     def adjoint(self, lam, qu, dJ_dU, psi_lam, psi_U, dJ_dkappa, dJ_dbeta, rtol=1e-12,
                 restart=300, max_iter=20000, stream=None, graph=True, folded=False,
-                classic_gs=False, driver=None):
+                classic_gs=False, driver=None, boundary=False):
         import torch
         s = self.query(self.precision, restart)
         if self.solve_ws is None or self.solve_ws.numel() < s.solve_ws_bytes:
@@ -364,7 +376,7 @@ class MacroMesh:
         opts = SolveOpts(float(rtol), int(restart), int(max_iter), 1, 0, 0.0, 1 if graph else 0,
                          1 if folded else 0, 1 if classic_gs else 0,
                          MHDG_DRIVER_DEVICE if driver is None else int(driver),
-                         MHDG_NORM_PRECONDITIONED, 0)
+                         MHDG_NORM_PRECONDITIONED, 0, 1 if boundary else 0)
         info = SolveInfo()
         self._check(self._lib.mhdg_adjoint(self.h, _ptr(lam), _ptr(qu), _ptr(dJ_dU),
                                            ctypes.byref(opts), _ptr(psi_lam), _ptr(psi_U),
@@ -408,6 +420,36 @@ class MacroMesh:
         self._check(self._lib.mhdg_assemble_trace_matrix(self.h, _ptr(self.matrix_ws),
                                                          self.matrix_ws.numel(), _stream(stream)),
                     "assemble_trace_matrix")
+
+    def condense_boundary(self, stream=None):
+        """Boundary-condensed blocks W_K = (A_K^-1)_bb of every macro from the
+        FP64 factors (call factor_local first); then apply/solve/adjoint can
+        use them (MHDG_BOUNDARY / boundary=True)."""
+        self.state_gen += 1
+        import torch
+        need = int(self._lib.mhdg_boundary_ws_bytes(self.h))
+        if getattr(self, "boundary_ws", None) is None or self.boundary_ws.numel() < need:
+            self.boundary_ws = None
+            self.boundary_ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+        self._check(self._lib.mhdg_condense_boundary(self.h, _ptr(self.boundary_ws),
+                                                     self.boundary_ws.numel(), _stream(stream)),
+                    "condense_boundary")
+
+    def boundary_blocks(self):
+        """The blocks of condense_boundary as a list of FP64 (9P x 9P) device
+        views, W_K[row, col] (the workspace layout of mhdg_condense_boundary)."""
+        import torch
+        n = int(self.sizes.n_macro)
+        ws = self.boundary_ws
+        off = ws[:8 * n].view(torch.int64).cpu()
+        base = (8 * n + 255) // 256 * 256
+        W = ws[base:].view(torch.float64)
+        out = []
+        for e, P in enumerate(self.macro_P()):
+            nb = 9 * int(P)
+            o = int(off[e])
+            out.append(W[o:o + nb * nb].view(nb, nb).t())
+        return out
 
     def set_supg(self, on: bool):
         """SUPG stabilisation inside the macros (section 3.4) on or off; the

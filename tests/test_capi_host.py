@@ -212,3 +212,25 @@ def test_trace_matrix_size_counts_the_face_pair_blocks():
         got = lib.mhdg_trace_matrix_ws_bytes(m.h)
         assert blocks * nF * nF * 8 <= got <= blocks * nF * nF * 8 + blocks * 128 + 4 * 4096 + \
             4 * (int(topo.interior.sum()) + 1), (n, got)
+
+
+def test_boundary_workspace_holds_the_offsets_and_every_block():
+    """mhdg_boundary_ws_bytes: the int64 offset table (padded to 256 bytes)
+    and one (9P)^2 FP64 block per macro, P = 2^r_K p, over every instance;
+    condensing before factor_local is a state error."""
+    lib = _lib()
+    xy, tri = inputs.structured_mesh(3)
+    lev = inputs.random_levels(len(tri), (0, 1, 2, 3), seed=2)
+    m = mhdg.MacroMesh(xy, tri, lev, 2)
+    for n_inst in (1, 3):
+        m.set_instances(n_inst)
+        P = m.macro_P()
+        assert P.size == n_inst * len(tri)
+        base = (8 * P.size + 255) // 256 * 256
+        need = base + 8 * int(np.sum((9 * P) ** 2))
+        got = lib.mhdg_boundary_ws_bytes(m.h)
+        assert need <= got < need + 256, (n_inst, got, need)
+    assert lib.mhdg_boundary_ws_bytes(None) == 0
+    assert lib.mhdg_condense_boundary(m.h, None, 0, None) == 7
+    assert b"factor_local" in lib.mhdg_last_error(m.h)
+    assert lib.mhdg_apply_trace_operator(m.h, None, None, mhdg.MHDG_BOUNDARY, None) == 7

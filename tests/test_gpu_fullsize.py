@@ -398,6 +398,47 @@ def test_c2_apply_sampled(c2):
     apply_sampled(c2["m"], orc, c2["faces"], lam, folded=True)
 
 
+def test_c2_boundary_condensed_sampled(c2):
+    """The boundary-condensed form at full size: W_K = (A_K^-1)_bb of the
+    sampled macros against the oracle's (relative 1e-10); applies through
+    W_K, direct and graph-captured, forward and transposed, on the sampled
+    faces to the FP64 bar; its GMRES solve within the global residual bound
+    and recovery on the sampled macros to 1e-10."""
+    m, orc, faces, macros = c2["m"], c2["orc"], c2["faces"], c2["macros"]
+    topo = orc.topo
+    m.condense_boundary()
+    Ws = m.boundary_blocks()
+    for K in macros[:8]:
+        Wo = orc.boundary_block(K)
+        err = np.linalg.norm(host(Ws[K]) - Wo) / np.linalg.norm(Wo)
+        print(f"  W_{K}: {err:.2e}", flush=True)
+        assert err <= TOL, (K, err)
+    lam_r = inputs.random_vector(topo.n_trace, seed=1)
+    out = torch.empty(topo.n_trace, dtype=torch.float64, device=DEV)
+    for transpose in (False, True):
+        ref = gather(orc.apply(lam_r, precondition=True, faces=faces, transpose=transpose),
+                     topo, faces)
+        for extra in (0, mhdg.MHDG_GRAPH):
+            flags = mhdg.MHDG_PRECONDITION | mhdg.MHDG_BOUNDARY | extra
+            if transpose:
+                flags |= mhdg.MHDG_TRANSPOSE
+            m.apply_trace_operator(gpu(lam_r), out, flags)
+            err = P.blocks(gather(host(out), topo, faces), ref, sizes_of(topo, faces))
+            print(f"  boundary apply transpose={transpose} graph={extra}: {err:.2e}", flush=True)
+            assert err <= TOL, (transpose, extra, err)
+    lam = torch.zeros(topo.n_trace, dtype=torch.float64, device=DEV)
+    info = m.solve(c2["f"], c2["g"], lam, rtol=RTOL, restart=2000, max_iter=20000, boundary=True)
+    print(f"  boundary solve: {info.iterations} it, rel {info.rel_res_prec:.2e}", flush=True)
+    assert info.status == 0
+    lam_h = host(lam)
+    Y, U = sampled_local(orc, macros, lam_h, c2["fo"], c2["lamD"])
+    res_o, _ = sampled_residual(orc, faces, lam_h, Y, U)
+    check_residual(res_o, c2["fhat_norm"])
+    qu = torch.empty(m.sizes.n_local, dtype=torch.float64, device=DEV)
+    m.recover_local(lam, qu)
+    check_recovery(host(qu), U, topo, macros)
+
+
 def test_c2_apply_many_sampled(c2):
     """The many-vector apply at full size: 9 vectors in one call (groups of
     4, 4 and 1 per macro), each against the oracle on the sampled faces and
