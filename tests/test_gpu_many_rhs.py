@@ -5,9 +5,10 @@ local solve; per vector it is the same operator as the single apply (steps
 1-4 of section 3.3.2).  Every output vector must equal the oracle's S lambda
 (D^-1 S lambda) to the FP64 bound (relative 1e-10) and the single-vector GPU
 apply to 1e-12, for vector counts that leave ragged groups in every size
-class (8, 4, 2 and 1 vectors per wavefront), on uniform and mixed-level
-meshes and with coefficient instances.  Error paths are checked through the
-C-ABI.
+class (8, 4, 2 and 1 vectors per wavefront, and from 12 vectors on macros of
+up to 1024 unknowns 16 vectors per workgroup, whose sweeps run on MFMA), on
+uniform and mixed-level meshes and with coefficient instances.  Error paths
+are checked through the C-ABI.
 """
 
 import numpy as np
@@ -40,7 +41,8 @@ def host(t):
 
 # (mesh n, levels, p): local sizes 24..180 (8 vectors per wavefront), 273 (8),
 # 975 (4), 1683 (2) and the uneven levels 1..4 with 84, 273, 975 and 3675
-# (8, 8, 4, 1); 11 vectors leave a partial last group in every class.
+# (8, 8, 4, 1); 11 vectors leave a partial last group in every class, and 19
+# a partial second group of the 16-vector workgroups (N_K <= 1024).
 CASES = {"mixed_p2": (3, "mixed", 2), "uniform_r2_p3": (3, 2, 3), "r3_p3": (2, 3, 3),
          "r3_p4": (2, 3, 4), "mixed_r1to4_p3": (2, "mixed4", 3)}
 
@@ -66,7 +68,11 @@ def test_many_matches_oracle_and_single(name):
     m = mhdg.MacroMesh(xy, tri, r, p)
     m.factor_local(gpu(kap), beta, 1.0)
     n = orc.topo.n_trace
-    n_rhs = 11   # 8+3, 4+4+3, 2*5+1 and 11*1 vectors per size class
+    for n_rhs in (11, 19):   # 8+3, 4+4+3, 2*5+1, 11*1; 16+3 (MFMA sweeps), 8+8+3, ...
+        _many_against_single_and_oracle(orc, m, n, n_rhs)
+
+
+def _many_against_single_and_oracle(orc, m, n, n_rhs):
     lam_h = np.stack([inputs.random_vector(n, seed=20 + v) for v in range(n_rhs)])
     lam = gpu(lam_h)
     out = torch.full((n_rhs, n), np.nan, dtype=torch.float64, device=DEV)
@@ -85,8 +91,8 @@ def test_many_matches_oracle_and_single(name):
 
 @pytest.mark.parametrize("n_rhs", [1, 3, 16, 40])
 def test_many_vector_counts(n_rhs):
-    """One vector, fewer than a group, two full groups, and five groups (the
-    last one partial) of the 8-vector kernels, against single applies."""
+    """One vector, fewer than a group, one full group and three groups (the
+    last one partial) of the 16-vector workgroups, against single applies."""
     xy, tri, r, p, kap, beta = _case("mixed_p2")
     m = mhdg.MacroMesh(xy, tri, r, p)
     m.factor_local(gpu(kap), beta, 1.0)
