@@ -95,7 +95,7 @@ __global__ __launch_bounds__(64 * NW, 2) void apply_many_mfma_kernel(
     int64_t ld_slots) {
   constexpr int NR = 16 * NH, NT = 64 * NW;
   extern __shared__ double sm[];
-  double* vec = sm + MrhsLds<NH>::doubles;   // NR compact boundary vectors of 3 NBD entries
+  double* vec = sm + mrhs_lds_doubles(NW, NH);   // NR compact boundary vectors of 3 NBD entries
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int64_t m = int64_t(seq / nch) * 8 + xcd;
   const int chunk = seq % nch;
@@ -201,9 +201,9 @@ static int apply_many_group(int N) {
 // The MFMA sweeps for groups of 16 vectors on macros of up to 1024 unknowns
 // (8 tiles of 16 rows per wavefront at most), from 12 vectors per call: below
 // that the per-wavefront sweeps (up to 4 or 8 vectors per factor pass) are as
-// fast, since the workgroup sweeps are bound by one barrier and one factor
-// load latency per 16-column block (at 8192 macros with N_K = 975: 27.4 ms
-// per group of 16 against 36 ms for four groups of 4).
+// fast, since the workgroup sweeps are bound by one barrier per 16-column
+// block (at 8192 macros with N_K = 975: 23.8 ms per group of 16 against
+// 36 ms for four groups of 4).
 static bool use_mfma_sweeps(int N, int n_rhs) { return n_rhs >= 12 && N <= 1024; }
 
 hipError_t launch_apply_many(const double* fac, const MacroInfo* info, const int32_t* order,
@@ -221,7 +221,7 @@ hipError_t launch_apply_many(const double* fac, const MacroInfo* info, const int
       const int nch = (n_rhs + 15) / 16;
       const int64_t nblk = (sc.count + 7) / 8 * 8 * int64_t(nch);
       if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-      const size_t lds = (size_t(MrhsLds<1>::doubles) + size_t(16) * 9 * sc.P) * sizeof(double);
+      const size_t lds = (size_t(mrhs_lds_doubles(nw, 1)) + size_t(16) * 9 * sc.P) * sizeof(double);
       const dim3 g((unsigned)nblk), b(64 * nw);
 #define MHDG_APPLY_MANY_MFMA(NW_)                                                               \
   hipLaunchKernelGGL((apply_many_mfma_kernel<NW_, 8, 1>), g, b, lds, s, fac, info, order,       \
