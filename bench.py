@@ -1012,7 +1012,9 @@ def bench_many_rhs(args, w):
         "roofline": {"bound": "hbm", "achieved": nbytes / (k_ms * 1e-3) / 1e9, "peak": 8000.0,
                      "unit": "GB/s", "frac": nbytes / (k_ms * 1e-3) / 1e9 / 8000.0,
                      "traffic": None,
-                     "kernel": "apply_many_kernel<16, 4>",
+                     "kernel": ("apply_many_mfma_kernel<8, 8, 1> (16 vectors per workgroup, "
+                                "sweeps on MFMA)" if n_rhs >= 12 and s.max_local <= 1024 else
+                                "apply_many_kernel (per-wavefront sweeps)"),
                      "algorithmic_bytes_per_launch": nbytes,
                      "kernel_ms": k_ms},
         "single_vector_applies_per_s": single,
