@@ -39,18 +39,23 @@ __global__ __launch_bounds__(256) void trace_matrix_build_kernel(
 // wavefront.  The row's blocks are stored one after another, so the row is
 // one column-major n_F x K array (K = the sum of its blocks' column counts)
 // whose columns k multiply the gathered trace values xs[k].  The wavefront
-// splits into G groups of 64 / G lanes (G = 4, 2, 1 for n_F <= 16, 32,
-// more); group g takes the columns k = g mod G, lane i of a group rows i,
-// i + 64 / G, ..., and the G partial sums meet by lane exchanges, so most
-// lanes load and every column is read once, coalesced.  Faces of a masked
-// coefficient instance write zeros (as the matrix-free apply does).
+// splits into G groups of 64 / G lanes; group g takes the columns
+// k = g mod G, lane i of a group rows i, i + 64 / G, ... (TR of them), and the
+// G partial sums meet by lane exchanges, so every column is read once,
+// coalesced.  U columns per group are loaded before any is used (a row of 125
+// columns at n_F = 25 is read in four round trips), and the last partial
+// batch is loaded the same way under a mask.  G and TR are chosen for the
+// largest face of the mesh.  Faces of a masked coefficient instance write
+// zeros (as the matrix-free apply does).
 constexpr int kMaxTraceNF = (1 << kMaxLevel) * 4 + 1;
 constexpr int kMaxRowCols = 5 * kMaxTraceNF;   // a face couples with at most 5 faces
+template <int G, int TR>
 __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
     const int32_t* __restrict__ row_ptr, const TraceBlock* __restrict__ blk,
     const FaceInfo* __restrict__ faces, const double* __restrict__ S,
     const double* __restrict__ tm, Templates Tp, double tau, int precondition,
     const int32_t* __restrict__ skip, const double* __restrict__ lam, double* __restrict__ out) {
+  constexpr int W = 64 / G, U = TR == 1 ? 16 : (TR == 2 ? 8 : 4);
   __shared__ double xs[kMaxRowCols];
   __shared__ double ys[kMaxTraceNF];
   const int fr = blockIdx.x, lane = threadIdx.x;
@@ -60,52 +65,66 @@ __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
     for (int i = lane; i < nF; i += 64) out[f.tr_off + i] = 0.0;
     return;
   }
-  const int b0 = row_ptr[fr], b1 = row_ptr[fr + 1];
-  int K = 0;
-  for (int bi = b0; bi < b1; ++bi) {
-    const TraceBlock& b = blk[bi];
-    const int c_off = faces[b.col_face].tr_off;
-    for (int j = lane; j < b.nC; j += 64) xs[K + j] = lam[c_off + j];
-    K += b.nC;
+  // the row's (at most 5) blocks are looked up by one lane each, so the gather
+  // of the trace values takes three memory round trips whatever the block count
+  const int b0 = row_ptr[fr], nblk = row_ptr[fr + 1] - b0;
+  int my_nC = 0, my_off = 0;
+  if (lane < nblk) {
+    const TraceBlock& b = blk[b0 + lane];
+    my_nC = b.nC;
+    my_off = faces[b.col_face].tr_off;
+  }
+  int incl = my_nC;   // inclusive prefix sum of the blocks' column counts
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  const int K = __shfl(incl, nblk - 1, 64);
+  int bend[5], boff[5];   // every lane: end column and trace offset of each block
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    bend[q] = __shfl(incl, q, 64);
+    boff[q] = __shfl(my_off, q, 64) - (bend[q] - __shfl(my_nC, q, 64));
+  }
+  for (int x = lane; x < K; x += 64) {
+    int o = boff[0];
+#pragma unroll
+    for (int q = 1; q < 5; ++q)
+      if (q < nblk && x >= bend[q - 1]) o = boff[q];
+    xs[x] = lam[o + x];
   }
   __syncthreads();
   const double* Sr = S + blk[b0].voff;
-  const int G = nF <= 16 ? 4 : (nF <= 32 ? 2 : 1);
-  const int W = 64 / G, g = lane / W, i0 = lane % W;
-  double acc[3] = {0.0, 0.0, 0.0};
-  int k = g;
-  for (; k + 3 * G < K; k += 4 * G) {
-    double v[4][3];
+  const int g = lane / W, i0 = lane % W;
+  double acc[TR];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+  for (int t = 0; t < TR; ++t) acc[t] = 0.0;
+  for (int k = g; k < K; k += U * G) {
+    double v[U][TR];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int i = i0 + W * t;
-        v[u][t] = i < nF ? Sr[int64_t(k + u * G) * nF + i] : 0.0;
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int i = i0 + W * t, kk = k + u * G;
+        v[u][t] = (i < nF && kk < K) ? Sr[int64_t(kk) * nF + i] : 0.0;
       }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double x = xs[k + u * G];
+    for (int u = 0; u < U; ++u) {
+      const int kk = k + u * G;
+      const double x = kk < K ? xs[kk] : 0.0;
 #pragma unroll
-      for (int t = 0; t < 3; ++t) acc[t] += v[u][t] * x;
-    }
-  }
-  for (; k < K; k += G) {
-    const double x = xs[k];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int i = i0 + W * t;
-      if (i < nF) acc[t] += Sr[int64_t(k) * nF + i] * x;
+      for (int t = 0; t < TR; ++t) acc[t] += v[u][t] * x;
     }
   }
   // the groups' partial sums: lane i0 of group 0 ends with the row sums
   for (int o = W; o < 64; o <<= 1)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) acc[t] += __shfl_xor(acc[t], o, 64);
+    for (int t = 0; t < TR; ++t) acc[t] += __shfl_xor(acc[t], o, 64);
   if (!precondition) {
     if (g == 0)
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
+      for (int t = 0; t < TR; ++t) {
         const int i = i0 + W * t;
         if (i < nF) out[f.tr_off + i] = acc[t];
       }
@@ -114,7 +133,7 @@ __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
   // D_F^-1 y = -M_F^-1 y / (2 tau |F|)
   if (g == 0)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < TR; ++t) {
       const int i = i0 + W * t;
       if (i < nF) ys[i] = acc[t];
     }
@@ -138,13 +157,22 @@ hipError_t launch_trace_matrix_build(const TraceBlock* blk, int64_t n_blocks, co
 }
 
 hipError_t launch_trace_matrix_apply(const int32_t* row_ptr, const TraceBlock* blk,
-                                     const FaceInfo* faces, int64_t n_faces, const double* S,
-                                     const double* tmpl, const Templates& T, double tau,
-                                     int precondition, const int32_t* skip, const double* lam,
-                                     double* out, hipStream_t s) {
+                                     const FaceInfo* faces, int64_t n_faces, int max_nF,
+                                     const double* S, const double* tmpl, const Templates& T,
+                                     double tau, int precondition, const int32_t* skip,
+                                     const double* lam, double* out, hipStream_t s) {
   if (n_faces == 0) return hipSuccess;
-  hipLaunchKernelGGL(trace_matrix_apply_kernel, dim3((unsigned)n_faces), dim3(64), 0, s, row_ptr,
-                     blk, faces, S, tmpl, T, tau, precondition, skip, lam, out);
+  const dim3 g((unsigned)n_faces), b(64);
+#define MHDG_TM_APPLY(G_, TR_)                                                               \
+  hipLaunchKernelGGL((trace_matrix_apply_kernel<G_, TR_>), g, b, 0, s, row_ptr, blk, faces, S, \
+                     tmpl, T, tau, precondition, skip, lam, out)
+  if (max_nF <= 16) MHDG_TM_APPLY(4, 1);
+  else if (max_nF <= 32) MHDG_TM_APPLY(2, 1);
+  else if (max_nF <= 64) MHDG_TM_APPLY(1, 1);
+  else if (max_nF <= 128) MHDG_TM_APPLY(1, 2);
+  else if (max_nF <= 192) MHDG_TM_APPLY(1, 3);
+  else return hipErrorInvalidValue;
+#undef MHDG_TM_APPLY
   return hipGetLastError();
 }
 

@@ -67,6 +67,7 @@ struct mhdg_mesh {
   const TraceBlock* tm_blocks = nullptr;  // device: block table
   const double* tm_values = nullptr;      // device: block values
   int64_t tm_n_blocks = 0, tm_n_values = 0;
+  int tm_max_nF = 0;                      // largest interior face trace
   // boundary-condensed blocks W_K (mhdg_condense_boundary): valid until the
   // next factor_local
   bool bcond = false;
@@ -2429,6 +2430,9 @@ mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* M, void* ws, size_t ws_bytes, 
       if (f.nF > (1 << kMaxLevel) * 4 + 1)
         return fail(M, MHDG_ERR_INVALID_ARG, "assemble_trace_matrix: face trace too large");
   const TracePlan P = trace_plan(M);
+  for (size_t r = 0; r + 1 < P.row_ptr.size(); ++r)
+    if (P.row_ptr[r + 1] - P.row_ptr[r] > 5)   // the product kernel gathers at most 5 blocks
+      return fail(M, MHDG_ERR_INVALID_ARG, "assemble_trace_matrix: a face row with more than 5 blocks");
   if (!ws || ws_bytes < P.total)
     return fail(M, MHDG_ERR_WORKSPACE,
                 "assemble_trace_matrix: workspace smaller than mhdg_trace_matrix_ws_bytes");
@@ -2449,6 +2453,8 @@ mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* M, void* ws, size_t ws_bytes, 
   M->tm_values = (const double*)(w + P.off_val);
   M->tm_n_blocks = int64_t(P.blocks.size());
   M->tm_n_values = P.n_values;
+  M->tm_max_nF = 0;
+  for (int64_t fi = 0; fi < M->n_int; ++fi) M->tm_max_nF = std::max(M->tm_max_nF, M->faces[fi].nF);
   M->assembled = true;
   M->drop_graphs();
   return MHDG_OK;
@@ -2745,7 +2751,8 @@ mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t
     ProfScope ps(M, 5, s);
     HIP_TRY(M, launch_trace_matrix_apply(M->tm_row_ptr, M->tm_blocks,
                                          (const FaceInfo*)(M->ws + L.faces), M->n_int,
-                                         M->tm_values, (const double*)(M->ws + L.tmpl), M->T,
+                                         M->tm_max_nF, M->tm_values,
+                                         (const double*)(M->ws + L.tmpl), M->T,
                                          M->tau, (flags & MHDG_PRECONDITION) ? 1 : 0, skip, lam,
                                          out, s));
     return MHDG_OK;

@@ -314,11 +314,12 @@ struct TraceBlock {
 hipError_t launch_trace_matrix_build(const TraceBlock* blk, int64_t n_blocks, const FaceInfo* faces,
                                      const double* tmpl, const Templates& T, double tau,
                                      const double* Tk, double* S, hipStream_t s);
+// max_nF: the largest face trace (picks the lane split of the product kernel)
 hipError_t launch_trace_matrix_apply(const int32_t* row_ptr, const TraceBlock* blk,
-                                     const FaceInfo* faces, int64_t n_faces, const double* S,
-                                     const double* tmpl, const Templates& T, double tau,
-                                     int precondition, const int32_t* skip, const double* lam,
-                                     double* out, hipStream_t s);
+                                     const FaceInfo* faces, int64_t n_faces, int max_nF,
+                                     const double* S, const double* tmpl, const Templates& T,
+                                     double tau, int precondition, const int32_t* skip,
+                                     const double* lam, double* out, hipStream_t s);
 
 // Device state of the GMRES whose per-segment recurrences run on the device
 // (gmres_dev.hip); every pointer is into the solve workspace.  Per segment
