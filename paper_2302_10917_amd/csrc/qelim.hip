@@ -13,6 +13,7 @@
 // Only the LU of S_u (Q x Q, Q = N_K / 3) is stored per macro; the templates are
 // shared by every macro of a level and are read from cache.
 #include "macro_solve.h"
+#include "mrhs.h"
 
 namespace mhdg {
 
@@ -575,6 +576,195 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
   }
 }
 
+// The same build for large Schur blocks with 16 columns of B_K per workgroup
+// of NW wavefronts, the factor read once per 16 columns: the right-hand
+// sides are formed in the MFMA tile layout of mrhs.h (lane (li, lk) of
+// wavefront w: column col0 + li, rows 16 (w + NW i) + lk + 4 v of the permuted
+// order), z = x_u - kappa sum_a P_a w_a summed over the P + 1 boundary
+// positions of the column's own edge (the only nonzero entries of its lift);
+// the sweeps run on MFMA; the boundary values
+//   q_d(b) = sum_j c_d(j, b) u_j + Mbb x_d / |det J|,  c_0 = G0 PB0 + G2 PB1,
+//   c_1 = G1 PB0 + G3 PB1,
+// are formed per wavefront as MFMA products of the PB tiles with its own
+// solution tiles, summed across the wavefronts by LDS atomics; u on the
+// boundary nodes comes from the wavefront that holds it.  The restriction
+// with C_K then writes the 16 columns of T_K.
+template <int NW, int TPW>
+__global__ __launch_bounds__(64 * NW, 2) void qelim_fold_build_mfma_kernel(
+    const double* __restrict__ fac, const MacroInfo* __restrict__ info,
+    const int32_t* __restrict__ order, int64_t base, int64_t count, int nch,
+    const int32_t* __restrict__ perm_all, const double* __restrict__ tm, Templates Tp,
+    const double* __restrict__ qt, QTemplates QT, double tau, const int64_t* __restrict__ toff,
+    double* __restrict__ T) {
+  extern __shared__ double sm[];   // the sweeps' LDS, later the 16 boundary vectors zc
+  const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
+  const int64_t m = int64_t(seq / nch) * 8 + xcd;
+  const int chunk = seq % nch;
+  if (m >= count) return;
+  const int e = order[base + m];
+  const MacroInfo& mi = info[e];
+  const int Q = mi.Q, P = mi.P, NBD = 3 * P, p = Tp.p, tid = threadIdx.x;
+  const int lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: branches around MFMAs
+  int lo[3], nk[3], L = 0;
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = L;
+    nk[k] = mi.tr_off[k] >= 0 ? (1 << mi.flevel[k]) * p + 1 : 0;
+    L += nk[k];
+  }
+  const int col0 = chunk * 16;
+  if (col0 >= L) return;
+  const int ncol = min(16, L - col0);
+  const LevelTemplates& LT = Tp.lev[mi.level];
+  const QLevel& QL = QT.lev[mi.level];
+  const int32_t* enode = ints_(tm, LT.edge_node);
+  const int32_t* bidx = ints_(tm, LT.bnd_index);
+  const double* PT0 = qt + QL.PT0;
+  const double* PT1 = qt + QL.PT1;
+  const double G0 = mi.G[0], G1 = mi.G[1], G2 = mi.G[2], G3 = mi.G[3];
+  const double idJ = 1.0 / mi.dJ, kap = mi.kappa;
+  // this lane's column: its edge kr, trace node ir, coefficients of B_K
+  const int col = col0 + min(li, ncol - 1);
+  const bool live = li < ncol;
+  const int kr = col < lo[1] ? 0 : (col < lo[2] ? 1 : 2);
+  const int ir = col - lo[kr], nFr = nk[kr];
+  const double* T1r = tm + LT.T1[mi.flevel[kr]];
+  const EdgeCoef cr = coef_B(mi, kr, tau);
+  const int orr = mi.orient[kr];
+  const double lenr = mi.len[kr];
+  // lift value of this column at position s of its edge
+  auto gval = [&](int s) -> double {
+    const int sc = orr > 0 ? s : P - s;
+    return live ? T1r[size_t(sc) * nFr + ir] * lenr : 0.0;
+  };
+  // ---- permuted right-hand sides z[perm[row]] in the tile layout
+  const int32_t* perm = perm_all + mi.sperm_off;
+  d4 x[TPW][1];
+  int rp[TPW][4];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * (wid + NW * i) + lk + 4 * v;
+      const int r2 = row < Q ? perm[row] : -1;
+      rp[i][v] = r2;
+      double z = 0.0;
+      if (r2 >= 0) {
+        const int b = bidx[r2];   // x_u on the column's own edge
+        int sp = -1;
+        if (b >= 0) {
+          if (b >= kr * P && b < kr * P + P) sp = b - kr * P;
+          else if (b == ((kr + 1) % 3) * P) sp = P;
+        }
+        if (sp >= 0) z = cr.c2 * gval(sp);
+      }
+      x[i][0][v] = z;
+    }
+  for (int sp = 0; sp <= P; ++sp) {
+    const double g = gval(sp);
+    const double x0 = cr.c0 * g, x1 = cr.c1 * g;
+    const double a0 = kap * (G0 * x0 + G1 * x1), a1 = kap * (G2 * x0 + G3 * x1);
+    const int nb = enode[kr * (P + 1) + sp];
+    const double* r0 = PT0 + size_t(nb) * Q;
+    const double* r1 = PT1 + size_t(nb) * Q;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r2 = rp[i][v];
+        const int rr = r2 >= 0 ? r2 : 0;
+        const double pv = r0[rr] * a0 + r1[rr] * a1;
+        if (r2 >= 0) x[i][0][v] -= pv;
+      }
+  }
+  // ---- Schur-block solves (end with a workgroup barrier)
+  mrhs_sweeps<NW, TPW, 1, 2>(x, fac + mi.sfac_off, Q, mi.sld, sm, wid, lane);
+  // ---- boundary values: zc[r][b] = Mbb terms, then += the PB products, and u
+  double* zc = sm;   // 16 x 3 NBD
+  const double* Mbb = qt + QL.Mbb;
+  for (int w = tid; w < 16 * NBD; w += 64 * NW) {
+    const int r = w / NBD, b = w - r * NBD;
+    double s0 = 0.0, s1 = 0.0;
+    if (r < ncol) {
+      const int cc = col0 + r;
+      const int k = cc < lo[1] ? 0 : (cc < lo[2] ? 1 : 2);
+      const int i = cc - lo[k], nF = nk[k];
+      const double* T1 = tm + LT.T1[mi.flevel[k]];
+      const EdgeCoef c = coef_B(mi, k, tau);
+      for (int sp = 0; sp <= P; ++sp) {
+        const int sc = mi.orient[k] > 0 ? sp : P - sp;
+        const double g = T1[size_t(sc) * nF + i] * mi.len[k];
+        const double mv = Mbb[size_t(bpos(k, sp, P)) * NBD + b] * idJ;   // Mbb is symmetric
+        s0 += mv * c.c0 * g;
+        s1 += mv * c.c1 * g;
+      }
+    }
+    zc[r * 3 * NBD + b] = s0;
+    zc[r * 3 * NBD + NBD + b] = s1;
+    zc[r * 3 * NBD + 2 * NBD + b] = 0.0;
+  }
+  __syncthreads();
+  const double* PB0 = qt + QL.PB0;
+  const double* PB1 = qt + QL.PB1;
+  const int nbc = (NBD + 15) / 16;
+  for (int bc = 0; bc < nbc; ++bc) {
+    d4 q0 = {0.0, 0.0, 0.0, 0.0}, q1 = {0.0, 0.0, 0.0, 0.0};
+    const int bA = min(16 * bc + li, NBD - 1);   // A row: boundary position
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = wid + NW * i;
+      if (16 * t >= Q) continue;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int j = 16 * t + 4 * s + lk;   // A column: solution row
+        const int jj = min(j, Q - 1);
+        const double p0 = PB0[size_t(jj) * NBD + bA], p1 = PB1[size_t(jj) * NBD + bA];
+        const double c0 = j < Q ? G0 * p0 + G2 * p1 : 0.0;
+        const double c1 = j < Q ? G1 * p0 + G3 * p1 : 0.0;
+        q0 = Mfma<double>::run(c0, x[i][0][s], q0);
+        q1 = Mfma<double>::run(c1, x[i][0][s], q1);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = 16 * bc + lk + 4 * v;
+      if (b < NBD) {
+        atomicAdd(&zc[li * 3 * NBD + b], q0[v]);
+        atomicAdd(&zc[li * 3 * NBD + NBD + b], q1[v]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * (wid + NW * i) + lk + 4 * v;
+      if (row < Q) {
+        const int b = bidx[row];
+        if (b >= 0) zc[li * 3 * NBD + 2 * NBD + b] = x[i][0][v];
+      }
+    }
+  __syncthreads();
+  // ---- restriction with C_K into the 16 columns of T_K
+  double* Tm = T + toff[e];
+  for (int k = 0; k < 3; ++k) {
+    if (nk[k] == 0) continue;
+    const int fl = mi.flevel[k], nF = nk[k];
+    const double* T1 = tm + LT.T1[fl];
+    const EdgeCoef c = coef_C(mi, k, tau);
+    for (int w = tid; w < ncol * nF; w += 64 * NW) {
+      const int r = w / nF, l = w - r * nF;
+      const double* z = zc + r * 3 * NBD;
+      double acc = 0.0;
+      for (int sc = 0; sc <= P; ++sc) {
+        const int b = bpos(k, mi.orient[k] > 0 ? sc : P - sc, P);
+        acc += T1[size_t(sc) * nF + l] * (c.c0 * z[b] + c.c1 * z[NBD + b] + c.c2 * z[2 * NBD + b]);
+      }
+      Tm[int64_t(col0 + r) * L + lo[k] + l] = mi.len[k] * acc;
+    }
+  }
+}
+
 hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, const int32_t* order,
                                    const SizeClass* classes, int n_classes, const int32_t* perm,
                                    const double* tmpl, const Templates& T, const double* qtm,
@@ -585,6 +775,20 @@ hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, con
     if (sc.count == 0) continue;
     const int Q = sc.N / 3;
     const int nq = (Q + 63) / 64;
+    if (Q > 1024 && Q <= 1280) {
+      // 16 columns per workgroup of 8 wavefronts, the Schur factor read once per 16
+      const int nch = (max_L + 15) / 16;
+      const int64_t nblk = (sc.count + 7) / 8 * 8 * int64_t(nch);
+      if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+      const size_t lds = size_t(std::max(mrhs_lds_doubles(8, 1), 16 * 9 * sc.P)) * sizeof(double);
+      if (lds > 65536) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((qelim_fold_build_mfma_kernel<8, 10>), dim3((unsigned)nblk), dim3(512),
+                         lds, s, fac, info, order, sc.start, sc.count, nch, perm, tmpl, T, qtm,
+                         QT, tau, toff, out);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      continue;
+    }
     const int nr = nq <= 4 ? 4 : (nq <= 14 ? 2 : 1);
     const int nch = (max_L + nr - 1) / nr;
     const int64_t nblk = (sc.count + 7) / 8 * 8 * int64_t(nch);
