@@ -146,36 +146,41 @@ hipError_t launch_fold_build(const double* fac, const MacroInfo* info, const int
 
 // Steps 1-3 with the folded operators: slots of macro K = T_K lambda_K, or
 // T_K^T lambda_K for the transposed operator S^T (adjoint solves).  One
-// wavefront per macro with lambda_K gathered into LDS; lane l owns rows
-// l + 64 t (t < NT, L_K <= 64 NT).  T_K is read column by column, coalesced
-// across the lanes, in batches of CB columns whose loads are all issued
-// before any of them is used (a macro's T_K is read in ceil(L_K / CB) memory
-// round trips).  Forward: row r accumulates T[r][c] lambda_c.  Transposed:
-// column c's dot product with lambda is summed across the wavefront and kept
-// by the lane that owns row c.
-template <int NT>
-__global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restrict__ info,
-                                                        const int64_t* __restrict__ toff,
-                                                        const double* __restrict__ T, int p,
-                                                        const int32_t* __restrict__ skip,
-                                                        int transpose,
-                                                        const double* __restrict__ lam,
-                                                        double* __restrict__ slots) {
+// workgroup of NW wavefronts per macro with lambda_K gathered into LDS; lane
+// l owns rows l + 64 t (t < NT, L_K <= 64 NT).  Wavefront w takes the w-th of
+// NW consecutive column ranges of T_K and reads it column by column,
+// coalesced across the lanes, in batches of CB columns whose loads are all
+// issued before any of them is used, so a macro's T_K is read in about
+// ceil(L_K / (NW CB)) memory round trips.  Forward: row r accumulates
+// T[r][c] lambda_c, and the wavefronts' partial sums meet in LDS.
+// Transposed: column c's dot product with lambda is summed across the
+// wavefront that holds the column and stored for row c.
+template <int NT, int NW>
+__global__ __launch_bounds__(64 * NW) void fold_apply_kernel(const MacroInfo* __restrict__ info,
+                                                             const int64_t* __restrict__ toff,
+                                                             const double* __restrict__ T, int p,
+                                                             const int32_t* __restrict__ skip,
+                                                             int transpose,
+                                                             const double* __restrict__ lam,
+                                                             double* __restrict__ slots) {
   constexpr int CB = NT == 3 ? 8 : 16;
   __shared__ double xl[64 * NT];
+  __shared__ double red[NW][64 * NT];
   const MacroInfo& mi = info[blockIdx.x];
   if (skip && skip[mi.inst]) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   int L = 0;
   for (int k = 0; k < 3; ++k) {
     if (mi.tr_off[k] < 0) continue;
     const int nF = face_nodes(mi, k, p);
-    for (int l = lane; l < nF; l += 64) xl[L + l] = lam[mi.tr_off[k] + l];
+    for (int l = tid; l < nF; l += 64 * NW) xl[L + l] = lam[mi.tr_off[k] + l];
     L += nF;
   }
   if (L == 0) return;
   __syncthreads();
   const double* Tm = T + toff[blockIdx.x];
+  const int span = (L + NW - 1) / NW;
+  const int cbeg = wid * span, cend = min(L, cbeg + span);
   double xr[NT], acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -183,19 +188,19 @@ __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restr
     xr[t] = r < L ? xl[r] : 0.0;
     acc[t] = 0.0;
   }
-  for (int c0 = 0; c0 < L; c0 += CB) {
+  for (int c0 = cbeg; c0 < cend; c0 += CB) {
     double a[CB][NT];
 #pragma unroll
     for (int cc = 0; cc < CB; ++cc)
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int c = c0 + cc, r = lane + 64 * t;
-        a[cc][t] = (c < L && r < L) ? Tm[int64_t(c) * L + r] : 0.0;
+        a[cc][t] = (c < cend && r < L) ? Tm[int64_t(c) * L + r] : 0.0;
       }
     if (!transpose) {
 #pragma unroll
       for (int cc = 0; cc < CB; ++cc) {
-        const double x = c0 + cc < L ? xl[c0 + cc] : 0.0;
+        const double x = c0 + cc < cend ? xl[c0 + cc] : 0.0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] += a[cc][t] * x;
       }
@@ -207,20 +212,25 @@ __global__ __launch_bounds__(64) void fold_apply_kernel(const MacroInfo* __restr
         for (int t = 0; t < NT; ++t) v += a[cc][t] * xr[t];
         v = wave_sum_(v);
         const int c = c0 + cc;
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (c == lane + 64 * t) acc[t] = v;
+        if (lane == 0 && c < cend) red[0][c] = v;   // row c of T_K^T lambda
       }
     }
   }
+  if (!transpose) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) red[wid][lane + 64 * t] = acc[t];
+  }
+  __syncthreads();
   int r0 = 0;
   for (int k = 0; k < 3; ++k) {
     if (mi.tr_off[k] < 0) continue;
     const int nF = face_nodes(mi, k, p);
+    for (int l = tid; l < nF; l += 64 * NW) {
+      double v = red[0][r0 + l];
+      if (!transpose)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int r = lane + 64 * t;
-      if (r >= r0 && r < r0 + nF) slots[mi.slot_off[k] + (r - r0)] = acc[t];
+        for (int w = 1; w < NW; ++w) v += red[w][r0 + l];
+      slots[mi.slot_off[k] + l] = v;
     }
     r0 += nF;
   }
@@ -319,13 +329,17 @@ hipError_t launch_fold_apply_many(const MacroInfo* info, int64_t n, const int64_
 hipError_t launch_fold_apply(const MacroInfo* info, int64_t n, const int64_t* toff, const double* T,
                              int p, int max_L, const int32_t* skip, int transpose,
                              const double* lam, double* slots, hipStream_t s) {
-  const dim3 g((unsigned)n), b(64);
+#ifndef MHDG_FOLD_APPLY_WAVES
+#define MHDG_FOLD_APPLY_WAVES 2
+#endif
+  constexpr int NW = MHDG_FOLD_APPLY_WAVES;
+  const dim3 g((unsigned)n), b(64 * NW);
   if (max_L <= 64)
-    hipLaunchKernelGGL(fold_apply_kernel<1>, g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
+    hipLaunchKernelGGL((fold_apply_kernel<1, NW>), g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
   else if (max_L <= 128)
-    hipLaunchKernelGGL(fold_apply_kernel<2>, g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
+    hipLaunchKernelGGL((fold_apply_kernel<2, NW>), g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
   else if (max_L <= kFoldMaxL)
-    hipLaunchKernelGGL(fold_apply_kernel<3>, g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
+    hipLaunchKernelGGL((fold_apply_kernel<3, NW>), g, b, 0, s, info, toff, T, p, skip, transpose, lam, slots);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
