@@ -946,57 +946,55 @@ __global__ __launch_bounds__(256) void dots_partial_kernel(const double* __restr
 
 // Two inner products per column in one read of V: for column c and segment
 // seg, partial[((2c + 0) nseg + seg) nblk + blk] = <V_c, x> and
-// partial[((2c + 1) nseg + seg) nblk + blk] = <V_c, y> over one chunk.  Each
-// wavefront takes two columns (c and c + 4 of its block's eight), so every
-// load of x and y serves two columns.
+// partial[((2c + 1) nseg + seg) nblk + blk] = <V_c, y> over one chunk.  A
+// workgroup takes eight columns over one chunk; its 256 threads stride the
+// chunk together, each loading x and y once for all eight columns (ten
+// independent loads per element), and the four wavefronts' sums meet in LDS.
 __global__ __launch_bounds__(256) void dots2_partial_kernel(const double* __restrict__ V, int64_t ld,
                                                             int ncols, const double* __restrict__ x,
                                                             const double* __restrict__ y, int64_t n,
                                                             double* __restrict__ partial,
                                                             const int32_t* __restrict__ skip) {
+  __shared__ double red[4][16];
   const int nblk = n > kDotChunk ? (int)((n + kDotChunk - 1) / kDotChunk) : 1;
   const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
   const int nseg = gridDim.x / nblk;
-  const int c0 = blockIdx.y * 8 + (threadIdx.x >> 6), c1 = c0 + 4;
-  const int lane = threadIdx.x & 63;
-  if (c0 >= ncols || (skip && skip[seg])) return;
-  const bool two = c1 < ncols;
-  const double* v0p = V + c0 * ld + int64_t(seg) * n;
-  const double* v1p = V + (two ? c1 : c0) * ld + int64_t(seg) * n;
+  const int cb = blockIdx.y * 8;
+  const int nc = min(8, ncols - cb);
+  if (skip && skip[seg]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const double* Vb = V + int64_t(cb) * ld + int64_t(seg) * n;
   x += int64_t(seg) * n;
   y += int64_t(seg) * n;
   const int64_t i0 = int64_t(blk) * kDotChunk;
   const int64_t i1 = i0 + kDotChunk < n ? i0 + kDotChunk : n;
-  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, e0 = 0.0, e1 = 0.0, f0 = 0.0, f1 = 0.0;
-  int64_t i = i0 + lane;
-  for (; i + 64 < i1; i += 128) {
-    const double x0 = x[i], x1 = x[i + 64], y0 = y[i], y1 = y[i + 64];
-    const double p0 = v0p[i], p1 = v0p[i + 64], q0 = v1p[i], q1 = v1p[i + 64];
-    a0 += p0 * x0;
-    a1 += p1 * x1;
-    b0 += p0 * y0;
-    b1 += p1 * y1;
-    e0 += q0 * x0;
-    e1 += q1 * x1;
-    f0 += q0 * y0;
-    f1 += q1 * y1;
-  }
-  for (; i < i1; i += 64) {
-    const double x0 = x[i], y0 = y[i], p0 = v0p[i], q0 = v1p[i];
-    a0 += p0 * x0;
-    b0 += p0 * y0;
-    e0 += q0 * x0;
-    f0 += q0 * y0;
-  }
-  const double sa = wave_sum(a0 + a1), sb = wave_sum(b0 + b1);
-  const double se = wave_sum(e0 + e1), sf = wave_sum(f0 + f1);
-  if (lane == 0) {
-    partial[(int64_t(2 * c0) * nseg + seg) * nblk + blk] = sa;
-    partial[(int64_t(2 * c0 + 1) * nseg + seg) * nblk + blk] = sb;
-    if (two) {
-      partial[(int64_t(2 * c1) * nseg + seg) * nblk + blk] = se;
-      partial[(int64_t(2 * c1 + 1) * nseg + seg) * nblk + blk] = sf;
+  double ax[8], ay[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) ax[c] = ay[c] = 0.0;
+  for (int64_t i = i0 + tid; i < i1; i += 256) {
+    const double xv = x[i], yv = y[i];
+    double v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = Vb[int64_t(c < nc ? c : 0) * ld + i];   // every load issued
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      ax[c] += v[c] * xv;
+      ay[c] += v[c] * yv;
     }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const double sx = wave_sum(ax[c]), sy = wave_sum(ay[c]);
+    if (lane == 0) {
+      red[wid][2 * c] = sx;
+      red[wid][2 * c + 1] = sy;
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * nc) {
+    const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    const int c = cb + (tid >> 1), w = tid & 1;
+    partial[(int64_t(2 * c + w) * nseg + seg) * nblk + blk] = v;
   }
 }
 
