@@ -43,6 +43,8 @@ for n, r, p, jit in ((2, 1, 2, 0.0), (3, "mixed", 3, 0.12), (4, 0, 1, 0.05), (5,
     assert np.all(np.isfinite(node)) and np.all(np.isfinite(bnd))
     m.set_instances(3)
     m.sample_points()
+    assert lib.mhdg_boundary_ws_bytes(m.h) > 0 and lib.mhdg_trace_matrix_ws_bytes(m.h) > 0
+    assert lib.mhdg_condense_boundary(m.h, None, 0, None) == 7   # before factor_local
     m.set_instances(1)
     N = m.sizes.max_local
     for lu, sv in ((0, 0), (5, 1), (9, 1), (1, 9)):
