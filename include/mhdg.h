@@ -536,8 +536,10 @@ mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* mesh, void* ws, size_t ws_byte
  * the boundary nodes of all three fields.  Where the interior block A_ii is
  * invertible, W_K is the inverse of the boundary Schur complement
  * A_bb - A_bi A_ii^-1 A_ib (the interior unknowns condensed out); W_K is
- * formed from the stored LU of A_K (9P solves with unit right-hand sides),
- * which also covers a macro whose A_ii is singular.
+ * formed from the stored factors by 9P solves with unit right-hand sides (the
+ * LU of A_K with MHDG_FP64 factors; with MHDG_QELIM the flux elimination and
+ * the Schur-block LU, the same solves), which also covers a macro whose A_ii
+ * is singular.
  * Layout of ws (device memory of at least mhdg_boundary_ws_bytes bytes, owned
  * by the caller and read by every later MHDG_BOUNDARY apply until the next
  * factor_local, set_instances or set_supg): int64 offsets[n_macro], then from
@@ -548,8 +550,8 @@ mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* mesh, void* ws, size_t ws_byte
  * At 8192 macros, r = 3, p = 3 the blocks take 3.06 GB (216 x 216 each).
  * Applies with MHDG_BOUNDARY (and solves or adjoints with opts->boundary)
  * then read W_K once per macro.  Synchronises the stream once.
- * Errors: STATE (before factor_local, or factors other than MHDG_FP64),
- * WORKSPACE, INVALID_ARG (9P > 512), HIP. */
+ * Errors: STATE (before factor_local, or factors other than MHDG_FP64 and
+ * MHDG_QELIM), WORKSPACE, INVALID_ARG (9P > 512), HIP. */
 size_t mhdg_boundary_ws_bytes(const mhdg_mesh* mesh);
 mhdg_status mhdg_condense_boundary(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void* stream);
 

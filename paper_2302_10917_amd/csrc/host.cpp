@@ -2467,8 +2467,9 @@ size_t mhdg_boundary_ws_bytes(const mhdg_mesh* M) {
 
 mhdg_status mhdg_condense_boundary(mhdg_mesh* M, void* ws, size_t ws_bytes, void* stream) {
   if (!M) return MHDG_ERR_INVALID_ARG;
-  if (!M->factored || M->precision != MHDG_FP64)
-    return fail(M, MHDG_ERR_STATE, "condense_boundary: needs MHDG_FP64 factors (call factor_local first)");
+  if (!M->factored || (M->precision != MHDG_FP64 && M->precision != MHDG_QELIM))
+    return fail(M, MHDG_ERR_STATE,
+                "condense_boundary: needs MHDG_FP64 or MHDG_QELIM factors (call factor_local first)");
   const BoundaryLayout B = boundary_layout(M);
   if (!ws || ws_bytes < B.total)
     return fail(M, MHDG_ERR_WORKSPACE, "condense_boundary: workspace smaller than mhdg_boundary_ws_bytes");
@@ -2489,7 +2490,14 @@ mhdg_status mhdg_condense_boundary(mhdg_mesh* M, void* ws, size_t ws_bytes, void
   FactorLayout& L = M->L;
   char* w = M->ws;
   double* W = (double*)(bw + B.W);
-  if (M->n_macro > 0)
+  if (M->n_macro > 0 && M->precision == MHDG_QELIM)
+    HIP_TRY(M, launch_qelim_bc_build((const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
+                                     (const int32_t*)(w + L.order), M->classes.data(),
+                                     (int)M->classes.size(), (const int32_t*)(w + L.perm),
+                                     (const double*)(w + L.tmpl), M->T,
+                                     (const double*)(w + L.qtmpl), M->QT, M->tau,
+                                     (const int64_t*)(bw + B.off), W, s));
+  else if (M->n_macro > 0)
     HIP_TRY(M, launch_bc_build((const double*)(w + L.factors), (const MacroInfo*)(w + L.meta),
                                (const int32_t*)(w + L.order), M->classes.data(),
                                (int)M->classes.size(), (const int32_t*)(w + L.perm),

@@ -240,6 +240,14 @@ hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, con
                                    const QTemplates& QT, double tau, int max_L,
                                    const int64_t* toff, double* out, hipStream_t s);
 
+// W_K = (A_K^-1)_bb for every macro from the Schur-block factors (boundary.hip
+// layout: offsets woff, blocks W)
+hipError_t launch_qelim_bc_build(const double* fac, const MacroInfo* info, const int32_t* order,
+                                 const SizeClass* classes, int n_classes, const int32_t* perm,
+                                 const double* tmpl, const Templates& T, const double* qtm,
+                                 const QTemplates& QT, double tau, const int64_t* woff, double* W,
+                                 hipStream_t s);
+
 // T_K for every macro, from the FP64 factors (max_L: the largest L_K)
 hipError_t launch_fold_build(const double* fac, const MacroInfo* info, const int32_t* order,
                              const SizeClass* classes, int n_classes, const int32_t* perm,

@@ -312,7 +312,13 @@ __global__ __launch_bounds__(64) void qelim_solve_kernel(
 // rows of PT_a, u read from LDS) and u are restricted with C_K into NR columns
 // of T_K.  The wavefronts of a macro are consecutive in one XCD's dispatch
 // (block b runs on XCD b mod 8).
-template <int NQ, int NR>
+// BC: the boundary-condensed blocks W_K = (A_K^-1)_bb instead.  Column c of
+// W_K (c < 9P, compact boundary order) is the solution for the unit vector at
+// compact index c, which is a boundary vector like a lift of B_K, so the
+// same steps apply; its boundary values (q_x, q_y, u at the 3P boundary
+// positions) are written as column c of W_K (toff / T: W_K's offsets and
+// storage) instead of being restricted with C_K.
+template <int NQ, int NR, bool BC>
 __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
     const double* __restrict__ fac, const MacroInfo* __restrict__ info,
     const int32_t* __restrict__ order, int64_t base, int64_t count, int nch,
@@ -333,8 +339,9 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
     nk[k] = mi.tr_off[k] >= 0 ? (1 << mi.flevel[k]) * p + 1 : 0;
     L += nk[k];
   }
+  const int ncols = BC ? 3 * NBD : L;
   const int col0 = chunk * NR;
-  if (col0 >= L) return;
+  if (col0 >= ncols) return;
   // LDS: the columns of B_K (later the boundary values of the solutions),
   // then the unpermuted right-hand sides (later the solutions)
   double* xc = sm;                    // NR x 3 NBD: columns of B_K (boundary rows)
@@ -351,7 +358,9 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
   const double idJ = 1.0 / mi.dJ, kap = mi.kappa;
   for (int t = lane; t < NR * 3 * NBD; t += 64) xc[t] = 0.0;
   __syncthreads();
-  for (int r = 0; r < NR && col0 + r < L; ++r) {
+  if (BC) {
+    if (lane < NR && col0 + lane < ncols) xc[lane * 3 * NBD + col0 + lane] = 1.0;
+  } else for (int r = 0; r < NR && col0 + r < L; ++r) {
     const int col = col0 + r;
     const int k = col < lo[1] ? 0 : (col < lo[2] ? 1 : 2);
     const int i = col - lo[k], nF = nk[k];
@@ -569,6 +578,12 @@ __global__ __launch_bounds__(64) void qelim_fold_build_kernel(
   }
   __syncthreads();
   double* Tm = T + toff[e];
+  if (BC) {
+    for (int r = 0; r < NR && col0 + r < ncols; ++r)
+      for (int t = lane; t < 3 * NBD; t += 64)
+        Tm[int64_t(col0 + r) * (3 * NBD) + t] = zc[r * 3 * NBD + t];
+    return;
+  }
   for (int r = 0; r < NR && col0 + r < L; ++r) {
     double* Tc = Tm + int64_t(col0 + r) * L;
     for (int k = 0; k < 3; ++k)
@@ -765,17 +780,18 @@ __global__ __launch_bounds__(64 * NW, 2) void qelim_fold_build_mfma_kernel(
   }
 }
 
-hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, const int32_t* order,
-                                   const SizeClass* classes, int n_classes, const int32_t* perm,
-                                   const double* tmpl, const Templates& T, const double* qtm,
-                                   const QTemplates& QT, double tau, int max_L,
-                                   const int64_t* toff, double* out, hipStream_t s) {
+// T_K (bc = false, max_L the largest L_K) or W_K (bc = true) for every macro
+static hipError_t qelim_build(bool bc, const double* fac, const MacroInfo* info,
+                              const int32_t* order, const SizeClass* classes, int n_classes,
+                              const int32_t* perm, const double* tmpl, const Templates& T,
+                              const double* qtm, const QTemplates& QT, double tau, int max_L,
+                              const int64_t* toff, double* out, hipStream_t s) {
   for (int c = 0; c < n_classes; ++c) {
     const SizeClass& sc = classes[c];
     if (sc.count == 0) continue;
     const int Q = sc.N / 3;
     const int nq = (Q + 63) / 64;
-    if (Q > 1024 && Q <= 1280) {
+    if (!bc && Q > 1024 && Q <= 1280) {
       // 16 columns per workgroup of 8 wavefronts, the Schur factor read once per 16
       const int nch = (max_L + 15) / 16;
       const int64_t nblk = (sc.count + 7) / 8 * 8 * int64_t(nch);
@@ -790,27 +806,50 @@ hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, con
       continue;
     }
     const int nr = nq <= 4 ? 4 : (nq <= 14 ? 2 : 1);
-    const int nch = (max_L + nr - 1) / nr;
+    const int cols = bc ? 9 * sc.P : max_L;
+    const int nch = (cols + nr - 1) / nr;
     const int64_t nblk = (sc.count + 7) / 8 * 8 * int64_t(nch);
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
     const size_t lds = (size_t(nr) * (9 * sc.P + Q)) * sizeof(double);
     if (lds > 65536) return hipErrorInvalidValue;
     const dim3 g((unsigned)nblk), b(64);
 #define MHDG_QFOLD(NQ_, NR_)                                                                   \
-  hipLaunchKernelGGL((qelim_fold_build_kernel<NQ_, NR_>), g, b, lds, s, fac, info, order,      \
-                     sc.start, sc.count, nch, perm, tmpl, T, qtm, QT, tau, toff, out)
-    if (nq <= 2) MHDG_QFOLD(2, 4);
-    else if (nq <= 4) MHDG_QFOLD(4, 4);
-    else if (nq <= 6) MHDG_QFOLD(6, 2);
-    else if (nq <= 9) MHDG_QFOLD(9, 2);
-    else if (nq <= 14) MHDG_QFOLD(14, 2);
-    else if (nq <= 20) MHDG_QFOLD(20, 1);
+  if (bc)                                                                                      \
+    hipLaunchKernelGGL((qelim_fold_build_kernel<NQ_, NR_, true>), g, b, lds, s, fac, info,     \
+                       order, sc.start, sc.count, nch, perm, tmpl, T, qtm, QT, tau, toff, out); \
+  else                                                                                         \
+    hipLaunchKernelGGL((qelim_fold_build_kernel<NQ_, NR_, false>), g, b, lds, s, fac, info,    \
+                       order, sc.start, sc.count, nch, perm, tmpl, T, qtm, QT, tau, toff, out)
+    if (nq <= 2) { MHDG_QFOLD(2, 4); }
+    else if (nq <= 4) { MHDG_QFOLD(4, 4); }
+    else if (nq <= 6) { MHDG_QFOLD(6, 2); }
+    else if (nq <= 9) { MHDG_QFOLD(9, 2); }
+    else if (nq <= 14) { MHDG_QFOLD(14, 2); }
+    else if (nq <= 20) { MHDG_QFOLD(20, 1); }
     else return hipErrorInvalidValue;
 #undef MHDG_QFOLD
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_qelim_fold_build(const double* fac, const MacroInfo* info, const int32_t* order,
+                                   const SizeClass* classes, int n_classes, const int32_t* perm,
+                                   const double* tmpl, const Templates& T, const double* qtm,
+                                   const QTemplates& QT, double tau, int max_L,
+                                   const int64_t* toff, double* out, hipStream_t s) {
+  return qelim_build(false, fac, info, order, classes, n_classes, perm, tmpl, T, qtm, QT, tau,
+                     max_L, toff, out, s);
+}
+
+hipError_t launch_qelim_bc_build(const double* fac, const MacroInfo* info, const int32_t* order,
+                                 const SizeClass* classes, int n_classes, const int32_t* perm,
+                                 const double* tmpl, const Templates& T, const double* qtm,
+                                 const QTemplates& QT, double tau, const int64_t* woff, double* W,
+                                 hipStream_t s) {
+  return qelim_build(true, fac, info, order, classes, n_classes, perm, tmpl, T, qtm, QT, tau, 0,
+                     woff, W, s);
 }
 
 hipError_t launch_qelim_solve(int mode, const double* fac, const MacroInfo* info,

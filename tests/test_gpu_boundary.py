@@ -8,7 +8,9 @@ the stored LU) must equal the oracle's, per macro, to the FP64 bound
 (and D^-1 S lambda, S^T lambda) to 1e-10 and the plain GPU apply to 1e-12;
 GMRES solves and adjoint solves on them must match the oracle and the plain
 ones.  The lone cubic bubble (r = 0, p = 3), whose interior block A_ii is
-singular, is one of the cases: W_K does not need A_ii's inverse.
+singular, is one of the cases: W_K does not need A_ii's inverse.  W_K is
+built from the LU of A_K (FP64 factors) and from the flux elimination's
+Schur-block factors (QELIM); both must meet the same bars.
 """
 import numpy as np
 import pytest
@@ -55,19 +57,23 @@ def _case(name):
     return xy, tri, r, p, kap, (1.0, -0.4)
 
 
-def _built(name):
+PRECISIONS = {"fp64": mhdg.MHDG_FP64, "qelim": mhdg.MHDG_QELIM}
+
+
+def _built(name, prec="fp64"):
     xy, tri, r, p, kap, beta = _case(name)
     orc = hdg.Oracle(xy, tri, r, p, kap, beta, 1.0)
     m = mhdg.MacroMesh(xy, tri, r, p)
-    m.factor_local(gpu(kap), beta, 1.0)
+    m.factor_local(gpu(kap), beta, 1.0, precision=PRECISIONS[prec])
     m.condense_boundary()
     return orc, m
 
 
+@pytest.mark.parametrize("prec", list(PRECISIONS))
 @pytest.mark.parametrize("name", list(CASES))
-def test_boundary_blocks_match_oracle(name):
-    print(f"\n[boundary blocks {name}]", flush=True)
-    orc, m = _built(name)
+def test_boundary_blocks_match_oracle(name, prec):
+    print(f"\n[boundary blocks {name} {prec}]", flush=True)
+    orc, m = _built(name, prec)
     Ws = m.boundary_blocks()
     assert len(Ws) == orc.topo.n_macro
     worst = 0.0
@@ -106,9 +112,26 @@ def test_boundary_apply_matches_oracle_and_plain(name):
         assert P.faces(host(a), host(b), orc.topo) <= 1e-12
 
 
-def test_boundary_solve_matches_oracle():
+@pytest.mark.parametrize("name", ["uniform_r2_p3", "bubble_r0_p3", "mixed_r1to4_p3"])
+def test_boundary_apply_from_schur_factors(name):
+    """W_K from the Schur-block factors: applies against the oracle (1e-10)
+    and against the flux-eliminated factor apply (1e-12)."""
+    orc, m = _built(name, "qelim")
+    n = orc.topo.n_trace
+    lam = inputs.random_vector(n, seed=3)
+    a = torch.empty(n, dtype=torch.float64, device=DEV)
+    b = torch.empty(n, dtype=torch.float64, device=DEV)
+    for flags, prec in ((0, False), (mhdg.MHDG_PRECONDITION, True)):
+        m.apply_trace_operator(gpu(lam), a, flags | mhdg.MHDG_BOUNDARY)
+        m.apply_trace_operator(gpu(lam), b, flags)
+        assert P.faces(host(a), orc.apply(lam, precondition=prec), orc.topo) <= 1e-10
+        assert P.faces(host(a), host(b), orc.topo) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", list(PRECISIONS))
+def test_boundary_solve_matches_oracle(prec):
     xy, tri, r, p, kap, beta = _case("mixed_p2")
-    orc, m = _built("mixed_p2")
+    orc, m = _built("mixed_p2", prec)
     ex = inputs.exp_sin(1.0, beta)
     node, bnd = m.sample_points()
     f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
@@ -170,8 +193,8 @@ def test_boundary_state_rules():
     m.factor_local(gpu(kap), beta, 1.0)           # new factors drop the blocks
     with pytest.raises(mhdg.MhdgError):
         m.apply_trace_operator(x, y, mhdg.MHDG_BOUNDARY)
-    m.factor_local(gpu(kap), beta, 1.0, precision=mhdg.MHDG_QELIM)
-    with pytest.raises(mhdg.MhdgError) as e:      # the blocks need the full FP64 factors
+    m.factor_local(gpu(kap), beta, 1.0, precision=mhdg.MHDG_FP32)
+    with pytest.raises(mhdg.MhdgError) as e:      # the blocks need FP64 or QELIM factors
         m.condense_boundary()
     assert e.value.status == 7
 
