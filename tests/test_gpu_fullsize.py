@@ -580,8 +580,9 @@ def test_c2_folded_flux_eliminated_sampled(c2):
     """The tuned form of the benchmark at full size: flux eliminated,
     operators folded from the Schur factors, GMRES(40) to 1e-10.  Folded
     applies, direct and graph-captured, on the sampled faces to the FP64 bar;
-    the solve within the global residual bound; recovery on the sampled
-    macros to 1e-10."""
+    the boundary-condensed blocks from the same factors (sampled W_K and
+    applies); the solve within the global residual bound; recovery on the
+    sampled macros to 1e-10."""
     orc, faces, macros = c2["orc"], c2["faces"], c2["macros"]
     topo = orc.topo
     xy, tri = inputs.structured_mesh(C2["n"])
@@ -598,6 +599,20 @@ def test_c2_folded_flux_eliminated_sampled(c2):
                                    mhdg.MHDG_PRECONDITION | mhdg.MHDG_FOLDED | extra)
             err = P.blocks(gather(host(out), topo, faces), ref, sizes_of(topo, faces))
             print(f"  folded flux-eliminated apply graph={extra}: {err:.2e}", flush=True)
+            assert err <= TOL, extra
+        # the boundary-condensed blocks from the same Schur factors
+        m.condense_boundary()
+        Ws = m.boundary_blocks()
+        for K in macros[:4]:
+            Wo = orc.boundary_block(K)
+            errw = np.linalg.norm(host(Ws[K]) - Wo) / np.linalg.norm(Wo)
+            print(f"  W_{K} from the Schur factors: {errw:.2e}", flush=True)
+            assert errw <= TOL, (K, errw)
+        for extra in (0, mhdg.MHDG_GRAPH):
+            m.apply_trace_operator(gpu(lam_r), out,
+                                   mhdg.MHDG_PRECONDITION | mhdg.MHDG_BOUNDARY | extra)
+            err = P.blocks(gather(host(out), topo, faces), ref, sizes_of(topo, faces))
+            print(f"  boundary apply from the Schur factors graph={extra}: {err:.2e}", flush=True)
             assert err <= TOL, extra
         lam = torch.zeros(topo.n_trace, dtype=torch.float64, device=DEV)
         info = m.solve(c2["f"], c2["g"], lam, rtol=RTOL, restart=40, max_iter=20000,
