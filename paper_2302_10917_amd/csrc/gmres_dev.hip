@@ -96,14 +96,21 @@ __global__ __launch_bounds__(256) void gm_start_kernel(GmDev d, int R) {
 // 1) ns + i ns + q], columns < j - 1, for j >= 2).  In the closing mode
 // (last) only the single products p of the projection pass are present, in
 // hy[c ns + q], and no next direction is prepared.  LDS: the finished column
-// and the rotations, 3 (R + 2) doubles.
-__global__ __launch_bounds__(64) void gm_step_kernel(GmDev d, int R, int j, int last) {
-  extern __shared__ double lds[];
-  __shared__ int act_s;
+// and the rotations, 3 (R + 2) doubles.  The step runs on one wavefront
+// (lanes 0..63 of its workgroup), so its LDS hand-offs need only a
+// wavefront-scope fence.
+__device__ __forceinline__ void gm_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ void gm_step_wave(const GmDev& d, int R, int j, int last, double* lds, int* act_sp) {
+  int& act_s = *act_sp;
   double* col = lds;                 // unrotated column j-1, rows 0..j
   double* csl = lds + (R + 2);       // rotations 0..j-2
   double* snl = csl + (R + 2);
-  const int q = blockIdx.x, lane = threadIdx.x, ns = d.ns;
+  const int q = blockIdx.x, lane = threadIdx.x & 63, ns = d.ns;
   const int hld = R + 1;
   const int max_iter = (int)d.prm[1];
   double* ca = d.coef;
@@ -145,7 +152,7 @@ __global__ __launch_bounds__(64) void gm_step_kernel(GmDev d, int R, int j, int 
       snl[i] = d.sn[int64_t(q) * R + i];
     }
     if (lane == 0) col[j] = bt;
-    __syncthreads();
+    gm_wave_sync();
     for (int i = lane; i <= j; i += 64) d.Hb[(int64_t(jj) * hld + i) * ns + q] = col[i];
     double* Hc = d.H + (int64_t(q) * R + jj) * hld;   // rotated column jj
     if (lane == 0) {
@@ -179,7 +186,7 @@ __global__ __launch_bounds__(64) void gm_step_kernel(GmDev d, int R, int j, int 
       }
     }
     if (lane == 0) act_s = d.active[q];
-    __syncthreads();
+    gm_wave_sync();
     act = act_s != 0;
   } else if (bt == 0.0) {
     if (lane == 0) {
@@ -222,6 +229,76 @@ __global__ __launch_bounds__(64) void gm_step_kernel(GmDev d, int R, int j, int 
   }
 }
 
+
+__global__ __launch_bounds__(64) void gm_step_kernel(GmDev d, int R, int j, int last) {
+  extern __shared__ double lds[];
+  __shared__ int act_s;
+  gm_step_wave(d, R, j, last, lds, &act_s);
+}
+
+// Column j's scalar work in one launch per segment, for j + 1 <= kGmColumnMax:
+// the sums of the chunk partials of dots2 (the 2 (j + 1) dual products), the
+// Hbar correction (j >= 2), then the step on wavefront 0.  Every sum keeps the
+// order of the separate kernels (dots_final: chunks strided over the 64 lanes,
+// then the wavefront sum; hbar_gemv: k strided by 8 in eight groups, the groups
+// added in order), so the results equal the three-launch sequence bit for bit.
+// 16 wavefronts: four products per wavefront in flight, 128 rows x 8 groups of
+// the correction.  LDS: the step's 3 (R + 2) doubles plus the group sums.
+constexpr int kGmColWaves = 16;
+__global__ __launch_bounds__(64 * kGmColWaves) void gm_column_kernel(GmDev d,
+                                                                    const double* __restrict__ partial,
+                                                                    int nblk, int R, int j) {
+  extern __shared__ double lds[];
+  __shared__ int act_s;
+  __shared__ double red[8][128];
+  const int q = blockIdx.x, ns = d.ns, tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int np = 2 * (j + 1);
+  if (!d.skip[q]) {   // a skipped segment has no partial sums (as in dots_final)
+    for (int c0 = 4 * wid; c0 < np; c0 += 4 * kGmColWaves) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int b = lane; b < nblk; b += 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u < np ? c0 + u : np - 1;
+          acc[u] += partial[(int64_t(c) * ns + q) * nblk + b];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double v = gm_wave_sum(acc[u]);
+        if (lane == 0 && c0 + u < np) d.pq[int64_t(c0 + u) * ns + q] = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (j >= 2) {   // Hbar a over the finished columns k < j - 1, rows i < j
+    const int hld = R + 1, kmax = j - 1;
+    const int g = tid & 7, r = tid >> 3;
+    double* out = d.pq + 2 * int64_t(j + 1) * ns;
+    for (int i0 = 0; i0 < j; i0 += 128) {
+      const int i = i0 + r;
+      double acc = 0.0;
+      if (i < j) {
+        const int k0 = i > 0 ? i - 1 : 0;
+        for (int kk = k0 + g; kk < kmax; kk += 8)
+          acc += d.pq[int64_t(2 * kk) * ns + q] * d.Hb[(int64_t(kk) * hld + i) * ns + q];
+      }
+      red[g][r] = acc;
+      __syncthreads();
+      if (g == 0 && i < j) {
+        double sum = 0.0;
+#pragma unroll
+        for (int g2 = 0; g2 < 8; ++g2) sum += red[g2][r];
+        out[int64_t(i) * ns + q] = sum;
+      }
+      __syncthreads();
+    }
+  }
+  if (wid != 0) return;
+  gm_step_wave(d, R, j, 0, lds, &act_s);
+}
+
 // y = R^-1 g over the jc[q] finished columns of segment q (upper triangular,
 // column-oriented back substitution; g is consumed), then skip[q] = done[q]
 // for the residual apply of the next cycle start.
@@ -254,6 +331,15 @@ hipError_t launch_gm_start(const GmDev& d, int R, hipStream_t s) {
 hipError_t launch_gm_step(const GmDev& d, int R, int j, int last, hipStream_t s) {
   const size_t lds = 3 * size_t(R + 2) * sizeof(double);
   hipLaunchKernelGGL(gm_step_kernel, dim3(d.ns), dim3(64), lds, s, d, R, j, last);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_column(const GmDev& d, const double* partial, int nblk, int R, int j,
+                            hipStream_t s) {
+  if (j + 1 > kGmColumnMax) return hipErrorInvalidValue;
+  const size_t lds = 3 * size_t(R + 2) * sizeof(double);
+  hipLaunchKernelGGL(gm_column_kernel, dim3(d.ns), dim3(64 * kGmColWaves), lds, s, d, partial,
+                     nblk, R, j);
   return hipGetLastError();
 }
 

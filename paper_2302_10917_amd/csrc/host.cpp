@@ -1451,6 +1451,11 @@ mhdg_status gmres_device(mhdg_mesh* M, Gm& G, const double* b, const double* bre
   const int32_t aflags = G.op_flags & ~MHDG_GRAPH;
   const bool true_norm = G.fh_true != nullptr;
   if (!true_norm) d.nrm_true = nullptr;   // gm_start tests the preconditioned residual
+  // the first kGmColumnMax columns of a cycle finish in one launch after the
+  // products (MHDG_GM_COLUMN_LAUNCHES=3 keeps the three separate launches;
+  // both give the same bits)
+  const char* cl_env = std::getenv("MHDG_GM_COLUMN_LAUNCHES");
+  const bool fused_column = !(cl_env && std::atoi(cl_env) == 3);
   mhdg_status st;
   // ---- initial state: parameters, reference norms, flags
   const size_t nd_in = 2 + 2 * size_t(ns);   // prm, bref, fref
@@ -1511,10 +1516,16 @@ mhdg_status gmres_device(mhdg_mesh* M, Gm& G, const double* b, const double* bre
     double* u = G.V + j * ld;
     mhdg_status e;
     if ((e = apply_launches(M, u, G.wv, aflags, d.skip, t))) return e;   // z = D^-1 S u_j
-    HIP_TRY(M, launch_dots2(G.V, ld, j + 1, u, G.wv, n, G.partial, G.nblk, d.pq, t, ns, d.skip));
-    if (j >= 2)
-      HIP_TRY(M, launch_hbar_gemv(G.Hb, hld, ns, j - 1, j, d.pq, d.pq + 2 * size_t(j + 1) * ns, t));
-    HIP_TRY(M, launch_gm_step(d, R, j, 0, t));
+    if (fused_column && j + 1 <= kGmColumnMax) {   // the same sums in one launch
+      HIP_TRY(M, launch_dots2_partial(G.V, ld, j + 1, u, G.wv, n, G.partial, G.nblk, t, ns,
+                                      d.skip));
+      HIP_TRY(M, launch_gm_column(d, G.partial, G.nblk, R, j, t));
+    } else {
+      HIP_TRY(M, launch_dots2(G.V, ld, j + 1, u, G.wv, n, G.partial, G.nblk, d.pq, t, ns, d.skip));
+      if (j >= 2)
+        HIP_TRY(M, launch_hbar_gemv(G.Hb, hld, ns, j - 1, j, d.pq, d.pq + 2 * size_t(j + 1) * ns, t));
+      HIP_TRY(M, launch_gm_step(d, R, j, 0, t));
+    }
     HIP_TRY(M, launch_dual_update(G.V, ld, j, n, ns, d.coef, d.coef + size_t(j) * ns,
                                   d.coef + 2 * size_t(j) * ns, G.wv, nullptr, t, d.skip));
     return MHDG_OK;

@@ -302,6 +302,10 @@ hipError_t launch_seg_scale_copy(const double* alpha, const double* x, double* y
 hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x, const double* y,
                         int64_t n, double* partial, int nblk, double* out, hipStream_t s,
                         int nseg, const int32_t* skip = nullptr);
+// the chunk partial sums of launch_dots2 only (their sums left to the caller)
+hipError_t launch_dots2_partial(const double* V, int64_t ld, int ncols, const double* x,
+                                const double* y, int64_t n, double* partial, int nblk,
+                                hipStream_t s, int nseg, const int32_t* skip = nullptr);
 hipError_t launch_hbar_gemv(const double* Hb, int64_t ld, int nseg, int kmax, int rows,
                             const double* pq, double* out, hipStream_t s);
 hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg, const double* ca,
@@ -347,6 +351,11 @@ struct GmDev {
 };
 hipError_t launch_gm_start(const GmDev& d, int R, hipStream_t s);
 hipError_t launch_gm_step(const GmDev& d, int R, int j, int last, hipStream_t s);
+// dots2's final sums, the Hbar correction and gm_step of column j in one
+// launch (the partial sums of launch_dots2_partial in; j + 1 <= kGmColumnMax)
+constexpr int kGmColumnMax = 64;
+hipError_t launch_gm_column(const GmDev& d, const double* partial, int nblk, int R, int j,
+                            hipStream_t s);
 hipError_t launch_gm_lsq(const GmDev& d, int R, hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);

@@ -1571,9 +1571,9 @@ hipError_t launch_gemv_sub(const double* V, int64_t ld, int ncols, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x, const double* y,
-                        int64_t n, double* partial, int nblk, double* out, hipStream_t s,
-                        int nseg, const int32_t* skip) {
+hipError_t launch_dots2_partial(const double* V, int64_t ld, int ncols, const double* x,
+                                const double* y, int64_t n, double* partial, int nblk,
+                                hipStream_t s, int nseg, const int32_t* skip) {
   // eight columns per workgroup either way; past 48 columns the workgroup
   // shares x and y across its eight (measured: 18.2 against 15.9 us per call
   // at 20 columns on 304,000 rows, faster on the long bases of GMRES(1000))
@@ -1583,6 +1583,14 @@ hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x,
   else
     hipLaunchKernelGGL(dots2_partial_narrow_kernel, dim3(nblk * nseg, (ncols + 7) / 8), dim3(256),
                        0, s, V, ld, ncols, x, y, n, partial, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots2(const double* V, int64_t ld, int ncols, const double* x, const double* y,
+                        int64_t n, double* partial, int nblk, double* out, hipStream_t s,
+                        int nseg, const int32_t* skip) {
+  const hipError_t e = launch_dots2_partial(V, ld, ncols, x, y, n, partial, nblk, s, nseg, skip);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(dots_final_kernel, dim3(2 * ncols * nseg), dim3(64), 0, s, partial, nblk, out,
                      nseg, skip);
   return hipGetLastError();

@@ -175,3 +175,47 @@ def test_device_driver_iteration_cap():
     info = m.solve(f, g, lam, rtol=1e-15, restart=5, max_iter=7, check=False)
     assert info.status == 4 and info.iterations == 7
     assert np.all(np.isfinite(host(lam)))
+
+
+@pytest.mark.parametrize("case", ["restart9", "restart300", "folded_qelim", "instances"])
+def test_one_launch_column_equals_the_three_launches_bitwise(case, monkeypatch):
+    """The first 64 columns of a cycle finish in one launch after the dual
+    products (their chunk sums, the Hbar correction, the step); it keeps the
+    order of every sum of the three separate launches, so the solves are the
+    same bits.  restart 300 runs 81 columns in one cycle: one launch up to
+    column 63, three launches after."""
+    if case == "instances":
+        xy, tri = inputs.structured_mesh(3, jitter=0.1, seed=7)
+        r = inputs.random_levels(len(tri), (1, 2), seed=3)
+        m = mhdg.MacroMesh(xy, tri, r, 2)
+        nn, nb = m.sizes.n_nodes, m.sizes.n_bnd_points
+        m.set_instances(3)
+        m.factor_local(gpu(np.repeat([1e-2, 0.3, 1.0], len(tri))),
+                       np.array([[1.0, 0.5], [-0.5, 1.0], [0.2, 0.1]]), 1.0)
+        node, bnd = m.sample_points()
+        ex = inputs.exp_sin(1e-2, (1.0, 0.5))
+        f, g = gpu(ex.f(node[:, 0], node[:, 1])), gpu(ex.u(bnd[:, 0], bnd[:, 1]))
+        assert f.numel() == 3 * nn and g.numel() == 3 * nb
+        kw = dict(restart=11)
+    else:
+        folded = case == "folded_qelim"
+        _, m, f, g, _, _ = _case(precision=mhdg.MHDG_QELIM if folded else None)
+        if folded:
+            m.fold_operator()
+        kw = dict(restart=300 if case == "restart300" else 9, folded=folded)
+    n = m.sizes.n_trace
+    out = {}
+    for launches in ("1", "3"):
+        monkeypatch.setenv("MHDG_GM_COLUMN_LAUNCHES", launches)
+        for graph in (False, True):
+            lam = torch.zeros(n, dtype=torch.float64, device=DEV)
+            info = m.solve(f, g, lam, rtol=1e-13, max_iter=5000, graph=graph, **kw)
+            assert info.status == 0, (launches, graph)
+            out[launches, graph] = (info.iterations, host(lam))
+    it0, ref = out["3", False]
+    print(f"  {case}: {it0} iterations", flush=True)
+    if case == "restart300":
+        assert it0 > 64   # the cycle runs past the one-launch columns
+    for key, (it, lam) in out.items():
+        assert it == it0, key
+        assert np.array_equal(lam, ref), key
