@@ -856,7 +856,14 @@ def main():
     if assembled:
         # assembled product: every stored block once (and its table), the trace read and
         # the result written once
-        nbytes = float(mhdg.load_library().mhdg_trace_matrix_ws_bytes(m.h)) + 16.0 * s.n_trace
+        # (S and D^-1 S are stored side by side, a product reads one of them: the
+        # workspace holds row_ptr, the 72-byte block table, then the two value arrays)
+        ws = float(mhdg.load_library().mhdg_trace_matrix_ws_bytes(m.h))
+        n_int = s.n_interior_faces
+        n_blk = int(m.matrix_ws[:4 * (n_int + 1)].view(torch.int32)[n_int].item())
+        a256 = lambda b: (b + 255) // 256 * 256
+        tables = a256(4 * (n_int + 1)) + a256(72 * n_blk)
+        nbytes = tables + (ws - tables) / 2 + 16.0 * s.n_trace
     if boundary:
         nbytes = boundary_bytes(m, s.n_trace)
     if n_inst > 1:

@@ -518,12 +518,19 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* mesh, void* ws, size_t ws_bytes, void*
  * mhdg_fold_operator.  Storage is block-sparse: one block per pair of
  * interior faces that share a macro (rows and columns in the faces'
  * canonical trace order), S_FF' = delta_FF' D_F - sum_{K holds F, F'}
- * T_K[F, F'], each block column-major; at 8192 macros, r = 3, p = 3 this
- * holds 304 MB against the 369 MB of the T_K.  Applies with MHDG_ASSEMBLED
- * (and solves with opts->assembled) then run one block-sparse product per
- * face row.  ws: device workspace of at least mhdg_trace_matrix_ws_bytes
+ * T_K[F, F'], each block column-major.  The left-preconditioned matrix
+ * D^-1 S (block (F, F') times D_F^-1) is stored beside it in the same layout,
+ * so that preconditioned products need no D_F^-1 step.  Applies with
+ * MHDG_ASSEMBLED (and solves with opts->assembled) then run one block-sparse
+ * product per face row, over D^-1 S with MHDG_PRECONDITION and over S
+ * without.  ws: device workspace of at least mhdg_trace_matrix_ws_bytes
  * bytes, owned by the caller and used until the next factor_local or
- * fold_operator.  Synchronises the stream once.
+ * fold_operator.  Layout: int32 row_ptr[n_interior_faces + 1] (the blocks of
+ * face row f are row_ptr[f] .. row_ptr[f + 1] - 1); from the next 256-byte
+ * boundary the block table (72 bytes per block); from the next 256-byte
+ * boundary the values of S; from the next the values of D^-1 S (the same
+ * size).  At 8192 macros, r = 3, p = 3: 60,292 blocks, 301 MB of values
+ * each, 607 MB in all (the T_K take 369 MB).  Synchronises the stream once.
  * Errors: STATE (before mhdg_fold_operator), WORKSPACE, INVALID_ARG (face
  * traces over 129 values), HIP. */
 size_t mhdg_trace_matrix_ws_bytes(const mhdg_mesh* mesh);

@@ -10,7 +10,10 @@
 // with D_F = -2 tau |F| M_F (M_F the face's 1D trace mass), rows and columns in
 // the faces' canonical trace order.  Each block is stored column-major
 // (n_F rows, n_F' columns), so one column is contiguous across the lanes of
-// the product kernel.
+// the product kernel.  Beside S the left-preconditioned matrix D^-1 S is stored
+// in the same layout (block (F, F') multiplied by D_F^-1 = -M_F^-1 / (2 tau
+// |F|)), so that GMRES's preconditioned products are plain block-sparse
+// products as well.
 #include "internal.h"
 
 namespace mhdg {
@@ -35,7 +38,28 @@ __global__ __launch_bounds__(256) void trace_matrix_build_kernel(
   }
 }
 
-// y = S lam (or D^-1 S lam with precondition) for one face row per
+// The blocks of D^-1 S from those of S: one workgroup per block,
+// P[i, j] = -1 / (2 tau |F|) sum_k (M_F^-1)[i, k] S[k, j], the sum in k order.
+__global__ __launch_bounds__(256) void trace_matrix_precondition_kernel(
+    const TraceBlock* __restrict__ blk, const FaceInfo* __restrict__ faces,
+    const double* __restrict__ tm, Templates Tp, double tau, const double* __restrict__ S,
+    double* __restrict__ Pm) {
+  const TraceBlock& b = blk[blockIdx.x];
+  const int nF = b.nF, nC = b.nC;
+  const FaceInfo& f = faces[b.row_face];
+  const double* Mi = tm + Tp.lev[f.level].M1inv;
+  const double sc = -1.0 / (2.0 * tau * f.len);
+  const double* Sb = S + b.voff;
+  double* out = Pm + b.voff;
+  for (int x = threadIdx.x; x < nF * nC; x += blockDim.x) {
+    const int j = x / nF, i = x % nF;
+    double d = 0.0;
+    for (int k = 0; k < nF; ++k) d += Mi[size_t(i) * nF + k] * Sb[size_t(j) * nF + k];
+    out[x] = sc * d;
+  }
+}
+
+// y = S lam (or D^-1 S lam from the stored D^-1 S) for one face row per
 // wavefront.  The row's blocks are stored one after another, so the row is
 // one column-major n_F x K array (K = the sum of its blocks' column counts)
 // whose columns k multiply the gathered trace values xs[k].  The wavefront
@@ -53,20 +77,13 @@ template <int G, int TR>
 __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
     const int32_t* __restrict__ row_ptr, const TraceBlock* __restrict__ blk,
     const FaceInfo* __restrict__ faces, const double* __restrict__ S,
-    const double* __restrict__ tm, Templates Tp, double tau, int precondition,
     const int32_t* __restrict__ skip, const double* __restrict__ lam, double* __restrict__ out) {
   constexpr int W = 64 / G, U = TR == 1 ? 16 : (TR == 2 ? 8 : 4);
   __shared__ double xs[kMaxRowCols];
-  __shared__ double ys[kMaxTraceNF];
   const int fr = blockIdx.x, lane = threadIdx.x;
-  const FaceInfo& f = faces[fr];
-  const int nF = f.nF;
-  if (skip && skip[f.inst]) {
-    for (int i = lane; i < nF; i += 64) out[f.tr_off + i] = 0.0;
-    return;
-  }
   // the row's (at most 5) blocks are looked up by one lane each, so the gather
-  // of the trace values takes three memory round trips whatever the block count
+  // of the trace values takes three memory round trips whatever the block
+  // count; these loads are issued before the instance's mask is known
   const int b0 = row_ptr[fr], nblk = row_ptr[fr + 1] - b0;
   int my_nC = 0, my_off = 0;
   if (lane < nblk) {
@@ -74,18 +91,26 @@ __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
     my_nC = b.nC;
     my_off = faces[b.col_face].tr_off;
   }
+  const FaceInfo& f = faces[fr];
+  const int nF = f.nF;
+  if (skip && skip[f.inst]) {
+    for (int i = lane; i < nF; i += 64) out[f.tr_off + i] = 0.0;
+    return;
+  }
   int incl = my_nC;   // inclusive prefix sum of the blocks' column counts
 #pragma unroll
   for (int o = 1; o < 8; o <<= 1) {
     const int t = __shfl_up(incl, o, 64);
     if (lane >= o) incl += t;
   }
-  const int K = __shfl(incl, nblk - 1, 64);
-  int bend[5], boff[5];   // every lane: end column and trace offset of each block
+  // wavefront-uniform (read from one lane into scalar registers): K, and the
+  // end column and trace offset of each block
+  const int K = __builtin_amdgcn_readlane(incl, nblk - 1);
+  int bend[5], boff[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    bend[q] = __shfl(incl, q, 64);
-    boff[q] = __shfl(my_off, q, 64) - (bend[q] - __shfl(my_nC, q, 64));
+    bend[q] = __builtin_amdgcn_readlane(incl, q);
+    boff[q] = __builtin_amdgcn_readlane(my_off, q) - (bend[q] - __builtin_amdgcn_readlane(my_nC, q));
   }
   for (int x = lane; x < K; x += 64) {
     int o = boff[0];
@@ -95,7 +120,10 @@ __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
     xs[x] = lam[o + x];
   }
   __syncthreads();
-  const double* Sr = S + blk[b0].voff;
+  // the row's base is uniform across the wavefront and its blocks span far
+  // less than 4 GiB, so each load takes a 32-bit byte offset from a scalar base
+  // (one address register per load instead of two)
+  const char* Sr = reinterpret_cast<const char*>(S + blk[b0].voff);
   const int g = lane / W, i0 = lane % W;
   double acc[TR];
 #pragma unroll
@@ -107,7 +135,9 @@ __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
 #pragma unroll
       for (int t = 0; t < TR; ++t) {
         const int i = i0 + W * t, kk = k + u * G;
-        v[u][t] = (i < nF && kk < K) ? Sr[int64_t(kk) * nF + i] : 0.0;
+        v[u][t] = (i < nF && kk < K)
+                      ? *reinterpret_cast<const double*>(Sr + uint32_t(kk * nF + i) * 8u)
+                      : 0.0;
       }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -121,51 +151,34 @@ __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
   for (int o = W; o < 64; o <<= 1)
 #pragma unroll
     for (int t = 0; t < TR; ++t) acc[t] += __shfl_xor(acc[t], o, 64);
-  if (!precondition) {
-    if (g == 0)
-#pragma unroll
-      for (int t = 0; t < TR; ++t) {
-        const int i = i0 + W * t;
-        if (i < nF) out[f.tr_off + i] = acc[t];
-      }
-    return;
-  }
-  // D_F^-1 y = -M_F^-1 y / (2 tau |F|)
   if (g == 0)
 #pragma unroll
     for (int t = 0; t < TR; ++t) {
       const int i = i0 + W * t;
-      if (i < nF) ys[i] = acc[t];
+      if (i < nF) out[f.tr_off + i] = acc[t];
     }
-  __syncthreads();
-  const double* Mi = tm + Tp.lev[f.level].M1inv;
-  const double sc = -1.0 / (2.0 * tau * f.len);
-  for (int i = lane; i < nF; i += 64) {
-    double d = 0.0;
-    for (int kk = 0; kk < nF; ++kk) d += Mi[size_t(i) * nF + kk] * ys[kk];
-    out[f.tr_off + i] = sc * d;
-  }
 }
 
 hipError_t launch_trace_matrix_build(const TraceBlock* blk, int64_t n_blocks, const FaceInfo* faces,
                                      const double* tmpl, const Templates& T, double tau,
-                                     const double* Tk, double* S, hipStream_t s) {
+                                     const double* Tk, double* S, double* Pm, hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(trace_matrix_build_kernel, dim3((unsigned)n_blocks), dim3(256), 0, s, blk,
                      faces, tmpl, T, tau, Tk, S);
+  hipLaunchKernelGGL(trace_matrix_precondition_kernel, dim3((unsigned)n_blocks), dim3(256), 0, s,
+                     blk, faces, tmpl, T, tau, S, Pm);
   return hipGetLastError();
 }
 
 hipError_t launch_trace_matrix_apply(const int32_t* row_ptr, const TraceBlock* blk,
                                      const FaceInfo* faces, int64_t n_faces, int max_nF,
-                                     const double* S, const double* tmpl, const Templates& T,
-                                     double tau, int precondition, const int32_t* skip,
-                                     const double* lam, double* out, hipStream_t s) {
+                                     const double* S, const int32_t* skip, const double* lam,
+                                     double* out, hipStream_t s) {
   if (n_faces == 0) return hipSuccess;
   const dim3 g((unsigned)n_faces), b(64);
 #define MHDG_TM_APPLY(G_, TR_)                                                               \
   hipLaunchKernelGGL((trace_matrix_apply_kernel<G_, TR_>), g, b, 0, s, row_ptr, blk, faces, S, \
-                     tmpl, T, tau, precondition, skip, lam, out)
+                     skip, lam, out)
   if (max_nF <= 16) MHDG_TM_APPLY(4, 1);
   else if (max_nF <= 32) MHDG_TM_APPLY(2, 1);
   else if (max_nF <= 64) MHDG_TM_APPLY(1, 1);

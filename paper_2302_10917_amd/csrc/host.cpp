@@ -65,7 +65,8 @@ struct mhdg_mesh {
   bool assembled = false;
   const int32_t* tm_row_ptr = nullptr;    // device: block rows per interior face
   const TraceBlock* tm_blocks = nullptr;  // device: block table
-  const double* tm_values = nullptr;      // device: block values
+  const double* tm_values = nullptr;      // device: block values of S
+  const double* tm_pvalues = nullptr;     // device: block values of D^-1 S
   int64_t tm_n_blocks = 0, tm_n_values = 0;
   int tm_max_nF = 0;                      // largest interior face trace
   // boundary-condensed blocks W_K (mhdg_condense_boundary): valid until the
@@ -849,7 +850,7 @@ struct TracePlan {
   std::vector<int32_t> row_ptr;
   std::vector<TraceBlock> blocks;
   int64_t n_values = 0;
-  size_t off_row = 0, off_blk = 0, off_val = 0, total = 0;
+  size_t off_row = 0, off_blk = 0, off_val = 0, off_pval = 0, total = 0;
 };
 static TracePlan trace_plan(const mhdg_mesh* M) {
   TracePlan P;
@@ -912,6 +913,7 @@ static TracePlan trace_plan(const mhdg_mesh* M) {
   P.off_row = o;  o = align_up(o + P.row_ptr.size() * sizeof(int32_t));
   P.off_blk = o;  o = align_up(o + P.blocks.size() * sizeof(TraceBlock));
   P.off_val = o;  o = align_up(o + size_t(P.n_values) * sizeof(double));
+  P.off_pval = o; o = align_up(o + size_t(P.n_values) * sizeof(double));
   P.total = o;
   return P;
 }
@@ -2457,11 +2459,12 @@ mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* M, void* ws, size_t ws_bytes, 
   HIP_TRY(M, launch_trace_matrix_build((const TraceBlock*)(w + P.off_blk), int64_t(P.blocks.size()),
                                        (const FaceInfo*)(M->ws + L.faces),
                                        (const double*)(M->ws + L.tmpl), M->T, M->tau, M->fold_T,
-                                       (double*)(w + P.off_val), s));
+                                       (double*)(w + P.off_val), (double*)(w + P.off_pval), s));
   HIP_TRY(M, hipStreamSynchronize(s));   // the host tables above are freed on return
   M->tm_row_ptr = (const int32_t*)(w + P.off_row);
   M->tm_blocks = (const TraceBlock*)(w + P.off_blk);
   M->tm_values = (const double*)(w + P.off_val);
+  M->tm_pvalues = (const double*)(w + P.off_pval);
   M->tm_n_blocks = int64_t(P.blocks.size());
   M->tm_n_values = P.n_values;
   M->tm_max_nF = 0;
@@ -2770,10 +2773,10 @@ mhdg_status apply_launches(mhdg_mesh* M, const double* lam, double* out, int32_t
     ProfScope ps(M, 5, s);
     HIP_TRY(M, launch_trace_matrix_apply(M->tm_row_ptr, M->tm_blocks,
                                          (const FaceInfo*)(M->ws + L.faces), M->n_int,
-                                         M->tm_max_nF, M->tm_values,
-                                         (const double*)(M->ws + L.tmpl), M->T,
-                                         M->tau, (flags & MHDG_PRECONDITION) ? 1 : 0, skip, lam,
-                                         out, s));
+                                         M->tm_max_nF,
+                                         (flags & MHDG_PRECONDITION) ? M->tm_pvalues
+                                                                     : M->tm_values,
+                                         skip, lam, out, s));
     return MHDG_OK;
   }
   if (flags & MHDG_BOUNDARY) {

@@ -323,15 +323,16 @@ struct TraceBlock {
   int32_t row_face, col_face, nF, nC, ncontrib, diag;
   int32_t L[2], r0[2], c0[2];
 };
+// S's blocks, then those of D^-1 S (Pm, the same layout)
 hipError_t launch_trace_matrix_build(const TraceBlock* blk, int64_t n_blocks, const FaceInfo* faces,
                                      const double* tmpl, const Templates& T, double tau,
-                                     const double* Tk, double* S, hipStream_t s);
-// max_nF: the largest face trace (picks the lane split of the product kernel)
+                                     const double* Tk, double* S, double* Pm, hipStream_t s);
+// out = S lam over the block rows (S: the values of S or of D^-1 S); max_nF:
+// the largest face trace (picks the lane split of the product kernel)
 hipError_t launch_trace_matrix_apply(const int32_t* row_ptr, const TraceBlock* blk,
                                      const FaceInfo* faces, int64_t n_faces, int max_nF,
-                                     const double* S, const double* tmpl, const Templates& T,
-                                     double tau, int precondition, const int32_t* skip,
-                                     const double* lam, double* out, hipStream_t s);
+                                     const double* S, const int32_t* skip, const double* lam,
+                                     double* out, hipStream_t s);
 
 // Device state of the GMRES whose per-segment recurrences run on the device
 // (gmres_dev.hip); every pointer is into the solve workspace.  Per segment

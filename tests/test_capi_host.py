@@ -199,7 +199,8 @@ def test_kernel_variant_validation():
 def test_trace_matrix_size_counts_the_face_pair_blocks():
     """The assembled trace matrix holds one block per pair of interior faces
     that share a macro: each interior face's diagonal block and, per macro,
-    every ordered pair of distinct interior faces (computed on the host)."""
+    every ordered pair of distinct interior faces (computed on the host),
+    twice (S and D^-1 S), plus the row pointers and the block table."""
     lib = _lib()
     for n, r in ((3, 1), (64, 3)):
         xy, tri = inputs.structured_mesh(n)
@@ -210,8 +211,10 @@ def test_trace_matrix_size_counts_the_face_pair_blocks():
         blocks = int(topo.interior.sum()) + int(np.sum(c * (c - 1)))
         nF = 2 ** r * 3 + 1
         got = lib.mhdg_trace_matrix_ws_bytes(m.h)
-        assert blocks * nF * nF * 8 <= got <= blocks * nF * nF * 8 + blocks * 128 + 4 * 4096 + \
-            4 * (int(topo.interior.sum()) + 1), (n, got)
+        n_int = int(topo.interior.sum())
+        a256 = lambda b: (b + 255) // 256 * 256
+        need = a256(4 * (n_int + 1)) + a256(72 * blocks) + 2 * a256(blocks * nF * nF * 8)
+        assert got == need, (n, got, need)
 
 
 def test_boundary_workspace_holds_the_offsets_and_every_block():
