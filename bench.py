@@ -919,7 +919,7 @@ def main():
                                      "copy-kernel calibrated; see profiles/)",
                      "traffic_vs_algorithmic": traffic["traffic_bytes_per_launch"] / nbytes
                      if traffic else None,
-                     "kernel": ("trace_matrix_apply_kernel (assembled S)" if assembled else
+                     "kernel": ("trace_matrix_apply_kernel (assembled D^-1 S, the preconditioned product)" if assembled else
                                 "bc_apply_kernel (boundary-condensed steps 1-3)" if boundary else
                                 "fold_apply_kernel (folded steps 1-3)" if folded else
                                 "qelim_solve_kernel (apply steps 1-3, flux eliminated)"

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void trace_matrix_build_kernel(
   double* out = S + b.voff;
   for (int x = threadIdx.x; x < nF * nC; x += blockDim.x) {
     const int j = x / nF, i = x % nF;
-    double v = b.diag ? -2.0 * tau * f.len * M1[size_t(i) * nF + j] : 0.0;
+    double v = b.row_face == b.col_face ? -2.0 * tau * f.len * M1[size_t(i) * nF + j] : 0.0;
     for (int c = 0; c < b.ncontrib; ++c)
       v -= T[b.toff[c] + int64_t(b.c0[c] + j) * b.L[c] + (b.r0[c] + i)];
     out[x] = v;
@@ -81,15 +81,16 @@ __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
   constexpr int W = 64 / G, U = TR == 1 ? 16 : (TR == 2 ? 8 : 4);
   __shared__ double xs[kMaxRowCols];
   const int fr = blockIdx.x, lane = threadIdx.x;
-  // the row's (at most 5) blocks are looked up by one lane each, so the gather
-  // of the trace values takes three memory round trips whatever the block
-  // count; these loads are issued before the instance's mask is known
+  // the row's (at most 5) blocks are looked up by one lane each (the table
+  // holds each block's column trace offset), so the gather of the trace values
+  // takes two memory round trips whatever the block count; these loads are
+  // issued before the instance's mask is known
   const int b0 = row_ptr[fr], nblk = row_ptr[fr + 1] - b0;
   int my_nC = 0, my_off = 0;
   if (lane < nblk) {
     const TraceBlock& b = blk[b0 + lane];
     my_nC = b.nC;
-    my_off = faces[b.col_face].tr_off;
+    my_off = b.col_off;
   }
   const FaceInfo& f = faces[fr];
   const int nF = f.nF;

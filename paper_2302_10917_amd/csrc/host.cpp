@@ -883,7 +883,7 @@ static TracePlan trace_plan(const mhdg_mesh* M) {
           tb.col_face = face[b];
           tb.nF = nF[a];
           tb.nC = nF[b];
-          tb.diag = face[a] == face[b];
+          tb.col_off = int32_t(M->faces[face[b]].tr_off);
           tmp.push_back(tb);
           rowmap[face[a]][face[b]] = bi;
           rows[face[a]].push_back(bi);

@@ -320,9 +320,11 @@ hipError_t launch_dual_update(double* V, int64_t ld, int j, int64_t n, int nseg,
 struct TraceBlock {
   int64_t voff;
   int64_t toff[2];
-  int32_t row_face, col_face, nF, nC, ncontrib, diag;
+  int32_t row_face, col_face, nF, nC, ncontrib;
+  int32_t col_off;   // trace offset of the column face (diagonal: col_face == row_face)
   int32_t L[2], r0[2], c0[2];
 };
+static_assert(sizeof(TraceBlock) == 72, "the block table's documented entry size");
 // S's blocks, then those of D^-1 S (Pm, the same layout)
 hipError_t launch_trace_matrix_build(const TraceBlock* blk, int64_t n_blocks, const FaceInfo* faces,
                                      const double* tmpl, const Templates& T, double tau,
