@@ -123,7 +123,8 @@ enum {
                                  T_K of mhdg_fold_operator (T_K^T with
                                  MHDG_TRANSPOSE)                              */
   MHDG_ASSEMBLED = 16,        /* apply: the assembled matrix S of
-                                 mhdg_assemble_trace_matrix (no TRANSPOSE)   */
+                                 mhdg_assemble_trace_matrix (its stored
+                                 D^-1 S with PRECONDITION; no TRANSPOSE)     */
   MHDG_BOUNDARY = 32          /* apply: steps 1-3 through the boundary blocks
                                  W_K of mhdg_condense_boundary (W_K^T with
                                  MHDG_TRANSPOSE); excludes FOLDED, ASSEMBLED */
