@@ -71,6 +71,9 @@ __global__ __launch_bounds__(256) void trace_matrix_precondition_kernel(
 // batch is loaded the same way under a mask.  G and TR are chosen for the
 // largest face of the mesh.  Faces of a masked coefficient instance write
 // zeros (as the matrix-free apply does).
+#ifndef MHDG_TM_COLS
+#define MHDG_TM_COLS 16   // columns per lane group loaded before use (one face row per lane)
+#endif
 constexpr int kMaxTraceNF = (1 << kMaxLevel) * 4 + 1;
 constexpr int kMaxRowCols = 5 * kMaxTraceNF;   // a face couples with at most 5 faces
 template <int G, int TR>
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(64) void trace_matrix_apply_kernel(
     const int32_t* __restrict__ row_ptr, const TraceBlock* __restrict__ blk,
     const FaceInfo* __restrict__ faces, const double* __restrict__ S,
     const int32_t* __restrict__ skip, const double* __restrict__ lam, double* __restrict__ out) {
-  constexpr int W = 64 / G, U = TR == 1 ? 16 : (TR == 2 ? 8 : 4);
+  constexpr int W = 64 / G, U = TR == 1 ? MHDG_TM_COLS : (TR == 2 ? 8 : 4);
   __shared__ double xs[kMaxRowCols];
   const int fr = blockIdx.x, lane = threadIdx.x;
   // the row's (at most 5) blocks are looked up by one lane each (the table
