@@ -257,6 +257,19 @@ def cpu_baseline(xy, tri, w, lam_seed=1, n_sample=16, budget_s=15.0):
             "condensation": o7}
 
 
+def oracle_solve_estimate(cb, applies_per_solve, gpu_time_to_solve_s):
+    """The oracle's time to solve the job, added to the cpu_baseline record cb:
+    its assembly + LU of every macro (factor_s_whole_mesh, from the sample), then
+    the job's GMRES applies (the mean over the timed solves) at the sampled rate;
+    the oracle's Krylov vector work is not counted."""
+    n_app = float(np.mean(applies_per_solve))
+    cb["time_to_solve_s_estimate"] = cb["factor_s_whole_mesh"] + n_app / cb["value"]
+    cb["time_to_solve_estimate"] = (
+        f"factor_s_whole_mesh + {n_app:.0f} applies / value; the GPU solve of the "
+        f"same job: {gpu_time_to_solve_s:.2f} s")
+    return cb
+
+
 def oracle_condensation_time(orc, sample):
     """The oracle's per-macro condensation (assembly of A_K, B_K, C_K, lu_factor,
     S_K = -C_K A_K^-1 B_K on the interior faces and f^_K; the step before its sparse
@@ -961,13 +974,7 @@ def main():
             wc["kappa"], wc["beta"] = float(kap_inst[0]), tuple(beta_inst[0])
         cb = cpu_baseline(xy, tri, wc)
         if result.get("applies_per_solve"):
-            # the oracle's time to solve: its assembly + LU of every macro, then this
-            # job's GMRES applies at the sampled rate (its Krylov vector work excluded)
-            n_app = float(np.mean(result["applies_per_solve"]))
-            cb["time_to_solve_s_estimate"] = cb["factor_s_whole_mesh"] + n_app / cb["value"]
-            cb["time_to_solve_estimate"] = (
-                f"factor_s_whole_mesh + {n_app:.0f} applies / value; the GPU solve of the "
-                f"same job: {result['time_to_solve_s']:.2f} s")
+            oracle_solve_estimate(cb, result["applies_per_solve"], result["time_to_solve_s"])
         result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 

@@ -51,3 +51,17 @@ def test_bench_refuses_several_gpus():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stderr
+
+
+def test_cpu_baseline_reports_the_oracle_time_to_solve():
+    """The CPU baseline on a small mesh (a bounded sample of macros): the apply
+    rate, the whole-mesh factorisation time scaled from the sample, and the
+    estimated time to solve = factorisation + applies / rate."""
+    xy, tri = inputs.structured_mesh(3)
+    w = {"r": 1, "p": 2, "kappa": 0.05, "beta": (1.0, 0.5)}
+    cb = bench.cpu_baseline(xy, tri, w, n_sample=3, budget_s=0.2)
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["factor_s_whole_mesh"] > 0
+    bench.oracle_solve_estimate(cb, [100, 104], 0.5)
+    expect = cb["factor_s_whole_mesh"] + 102.0 / cb["value"]
+    assert abs(cb["time_to_solve_s_estimate"] - expect) <= 1e-12 * expect
+    assert "102 applies" in cb["time_to_solve_estimate"]
