@@ -14,12 +14,15 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
 
 using namespace mhdg;
+
+struct TracePlan;
 
 struct mhdg_mesh {
   int32_t p = 1;
@@ -69,6 +72,9 @@ struct mhdg_mesh {
   const double* tm_pvalues = nullptr;     // device: block values of D^-1 S
   int64_t tm_n_blocks = 0, tm_n_values = 0;
   int tm_max_nF = 0;                      // largest interior face trace
+  // host block plan of the assembled matrix: fixed by the mesh topology and the
+  // instance count, so built once (cleared by set_instances)
+  mutable std::shared_ptr<const TracePlan> tm_plan;
   // boundary-condensed blocks W_K (mhdg_condense_boundary): valid until the
   // next factor_local
   bool bcond = false;
@@ -916,6 +922,10 @@ static TracePlan trace_plan(const mhdg_mesh* M) {
   P.off_pval = o; o = align_up(o + size_t(P.n_values) * sizeof(double));
   P.total = o;
   return P;
+}
+static const TracePlan& trace_plan_cached(const mhdg_mesh* M) {
+  if (!M->tm_plan) M->tm_plan = std::make_shared<const TracePlan>(trace_plan(M));
+  return *M->tm_plan;
 }
 
 // ---------------------------------------------------------------- GMRES
@@ -2054,6 +2064,7 @@ mhdg_status mhdg_set_instances(mhdg_mesh* M, int32_t n_inst) {
     return fail(M, MHDG_ERR_INVALID_ARG, "set_instances: instance count out of range");
   M->factored = false;
   M->have_rhs = false;
+  M->tm_plan.reset();
   M->folded = false;
   M->assembled = false;
   M->bcond = false;
@@ -2431,7 +2442,7 @@ mhdg_status mhdg_fold_operator(mhdg_mesh* M, void* ws, size_t ws_bytes, void* st
 
 size_t mhdg_trace_matrix_ws_bytes(const mhdg_mesh* M) {
   if (!M) return 0;
-  return trace_plan(M).total;
+  return trace_plan_cached(M).total;
 }
 
 mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* M, void* ws, size_t ws_bytes, void* stream) {
@@ -2442,7 +2453,7 @@ mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* M, void* ws, size_t ws_bytes, 
     for (const FaceInfo& f : M->faces)
       if (f.nF > (1 << kMaxLevel) * 4 + 1)
         return fail(M, MHDG_ERR_INVALID_ARG, "assemble_trace_matrix: face trace too large");
-  const TracePlan P = trace_plan(M);
+  const TracePlan& P = trace_plan_cached(M);
   for (size_t r = 0; r + 1 < P.row_ptr.size(); ++r)
     if (P.row_ptr[r + 1] - P.row_ptr[r] > 5)   // the product kernel gathers at most 5 blocks
       return fail(M, MHDG_ERR_INVALID_ARG, "assemble_trace_matrix: a face row with more than 5 blocks");
@@ -2460,7 +2471,7 @@ mhdg_status mhdg_assemble_trace_matrix(mhdg_mesh* M, void* ws, size_t ws_bytes, 
                                        (const FaceInfo*)(M->ws + L.faces),
                                        (const double*)(M->ws + L.tmpl), M->T, M->tau, M->fold_T,
                                        (double*)(w + P.off_val), (double*)(w + P.off_pval), s));
-  HIP_TRY(M, hipStreamSynchronize(s));   // the host tables above are freed on return
+  HIP_TRY(M, hipStreamSynchronize(s));   // the one documented synchronisation
   M->tm_row_ptr = (const int32_t*)(w + P.off_row);
   M->tm_blocks = (const TraceBlock*)(w + P.off_blk);
   M->tm_values = (const double*)(w + P.off_val);
